@@ -1,0 +1,411 @@
+"""ctypes wrapper of the plain FP64 CPU oracle (``oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by ``__graft_entry__.smoke()``
+and by the CPU-baseline leg of ``bench.py``.  The product path never imports
+this package.  Arrays are numpy float64, row-major (n, dim).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+_lp = C.POINTER(C.c_int64)
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (plain C, FP64, no FMA contraction)."""
+    if force or not os.path.exists(LIB_PATH):
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+               "-Wall", "-o", LIB_PATH, os.path.join(_HERE, "oracle.c"), "-lm"]
+        subprocess.run(cmd, check=True)
+    return LIB_PATH
+
+
+class _Field(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n_coef", C.c_int32), ("coef", _dp),
+                ("param", C.c_double * 8)]
+
+
+class _WalkParams(C.Structure):
+    _fields_ = [("eps", C.c_double), ("max_steps", C.c_int32), ("n_walks", C.c_int32),
+                ("seed", C.c_uint64), ("batch", C.c_uint32), ("control_variate", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = C.CDLL(LIB_PATH)
+        L.orc_scene_new.restype = C.c_void_p
+        L.orc_scene_new.argtypes = [C.c_int, _dp, C.c_int64, _ip, C.c_int64]
+        L.orc_scene_free.argtypes = [C.c_void_p]
+        L.orc_philox4x32_10.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
+                                        C.POINTER(C.c_uint32)]
+        L.orc_uniform_pair.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
+                                       C.c_uint32, _dp, _dp]
+        L.orc_closest_batch.argtypes = [C.c_void_p, C.c_int64, _dp, C.c_int, _dp, _dp, _ip]
+        L.orc_inside.argtypes = [C.c_void_p, _dp]
+        L.orc_inside.restype = C.c_int
+        L.orc_classify.argtypes = [C.c_void_p, C.c_int64, _dp, C.c_double, _ip]
+        L.orc_field_eval_batch.argtypes = [C.POINTER(_Field), C.c_int, C.c_int64, _dp, _dp]
+        L.orc_basis_eval.argtypes = [C.POINTER(_Field), C.c_int, C.c_int, _dp]
+        L.orc_basis_eval.restype = C.c_double
+        L.orc_ein.argtypes = [C.c_double]
+        L.orc_ein.restype = C.c_double
+        L.orc_greens.argtypes = [C.c_int, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.orc_sample_cache.argtypes = [C.c_void_p, C.c_int64, C.c_double, C.c_int, C.c_uint64,
+                                       C.c_uint32, _dp, _dp, _dp, _dp, _dp, _ip]
+        L.orc_sample_cache.restype = C.c_int64
+        L.orc_candidate_measure.argtypes = [C.c_void_p, C.c_double, C.c_int]
+        L.orc_candidate_measure.restype = C.c_double
+        L.orc_sample_sources.argtypes = [C.c_void_p, C.POINTER(_Field), C.c_int64, _dp, _dp,
+                                         C.c_double, C.c_uint64, C.c_uint32, _dp, _dp]
+        L.orc_walk.argtypes = [C.c_void_p, C.POINTER(_Field), C.POINTER(_Field),
+                               C.POINTER(_WalkParams), C.c_int, _dp, _dp, C.c_double, _dp,
+                               C.c_uint32, _dp, _dp, _dp, _dp, _ip, _ip]
+        L.orc_cache_walks.argtypes = [C.c_void_p, C.POINTER(_Field), C.POINTER(_Field),
+                                      C.POINTER(_WalkParams), C.c_int64, _dp, _dp, _dp, _dp,
+                                      _dp, _dp, _dp, _dp, _ip]
+        L.orc_cache_walks_subset.argtypes = [C.c_void_p, C.POINTER(_Field), C.POINTER(_Field),
+                                             C.POINTER(_WalkParams), C.c_int64, _lp, _dp, _dp,
+                                             _dp, _dp, _dp, _dp, _ip]
+        L.orc_reduce.argtypes = [C.c_int64, C.c_int32, _dp, _dp, _dp, _dp]
+        L.orc_pointwise.argtypes = [C.c_void_p, C.POINTER(_Field), C.POINTER(_Field),
+                                    C.POINTER(_WalkParams), C.c_int64, _dp, _dp, _dp, _lp]
+        L.orc_gather.argtypes = [C.c_int, C.c_int64, _dp, C.c_int64, _dp, _dp, _dp, _dp,
+                                 C.c_int64, _dp, _dp, _dp, _dp, _dp]
+        L.orc_gather_backward.argtypes = [C.c_int, C.c_int64, _dp, _dp, C.c_int64, _dp, _dp, _dp,
+                                          _dp, C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.orc_basis_means.argtypes = [C.POINTER(_Field), C.c_int, C.c_int64, C.c_int32, _dp, _dp,
+                                      _dp, C.c_int, _dp, _dp]
+        L.orc_num_threads.restype = C.c_int
+        L.orc_sample_direction.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
+                                           C.c_uint32, C.c_int, _dp]
+        L.orc_sample_ball_source.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
+                                             C.c_uint32, C.c_int, _dp, C.c_double, _dp]
+        L.orc_grad_radius.argtypes = [C.c_double]
+        L.orc_grad_radius.restype = C.c_double
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_dp)
+
+
+def _i(a):
+    if a is None:
+        return None
+    assert a.dtype == np.int32 and a.flags.c_contiguous
+    return a.ctypes.data_as(_ip)
+
+
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _field(fld) -> _Field:
+    F = _Field()
+    if fld is None:
+        F.kind = 0
+        F.n_coef = 0
+        F.coef = None
+        return F
+    F.kind = int(fld.kind)
+    coef = _f64(fld.coef)
+    F._keep = coef
+    F.n_coef = int(coef.size)
+    F.coef = coef.ctypes.data_as(_dp) if coef.size else None
+    for i in range(8):
+        F.param[i] = float(fld.param[i])
+    return F
+
+
+def num_threads() -> int:
+    return lib().orc_num_threads()
+
+
+def philox(ctr, key):
+    c = (C.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
+    k = (C.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    o = (C.c_uint32 * 4)()
+    lib().orc_philox4x32_10(c, k, o)
+    return list(o)
+
+
+def uniform_pair(seed, block, id_, batch, tag):
+    a = C.c_double()
+    b = C.c_double()
+    lib().orc_uniform_pair(seed, block, id_, batch, tag, C.byref(a), C.byref(b))
+    return a.value, b.value
+
+
+def ein(z: float) -> float:
+    return lib().orc_ein(float(z))
+
+
+def greens(dim, x, y, ny=None):
+    x = _f64(x)
+    y = _f64(y)
+    ny = _f64(ny) if ny is not None else np.zeros(dim)
+    G = np.zeros(1)
+    dGdx = np.zeros(dim)
+    dGdn = np.zeros(1)
+    d2 = np.zeros(dim)
+    lib().orc_greens(dim, _d(x), _d(y), _d(ny), _d(G), _d(dGdx), _d(dGdn), _d(d2))
+    return G[0], dGdx, dGdn[0], d2
+
+
+def field_eval(fld, x):
+    x = _f64(x)
+    out = np.zeros(x.shape[0])
+    F = _field(fld)
+    lib().orc_field_eval_batch(C.byref(F), x.shape[1], x.shape[0], _d(x), _d(out))
+    return out
+
+
+def basis_eval(fld, dim, m, x):
+    x = _f64(x)
+    F = _field(fld)
+    return np.array([lib().orc_basis_eval(C.byref(F), dim, m, _d(np.ascontiguousarray(xi)))
+                     for xi in x])
+
+
+class Scene:
+    """Oracle-side scene: copies the geometry and builds its own BVH."""
+
+    def __init__(self, scene):
+        self.dim = scene.dim
+        v = _f64(scene.verts)
+        p = np.ascontiguousarray(scene.prims, dtype=np.int32)
+        self.h = lib().orc_scene_new(self.dim, _d(v), v.shape[0], _i(p), p.shape[0])
+
+    def __del__(self):
+        try:
+            if self.h:
+                lib().orc_scene_free(self.h)
+        except Exception:
+            pass
+
+    def closest(self, x, brute=False):
+        x = _f64(x).reshape(-1, self.dim)
+        n = x.shape[0]
+        d = np.zeros(n)
+        xb = np.zeros((n, self.dim))
+        pr = np.zeros(n, np.int32)
+        lib().orc_closest_batch(self.h, n, _d(x), int(brute), _d(d), _d(xb), _i(pr))
+        return d, xb, pr
+
+    def inside(self, x):
+        x = _f64(x).reshape(-1, self.dim)
+        return np.array([lib().orc_inside(self.h, _d(np.ascontiguousarray(xi))) for xi in x])
+
+    def classify(self, x, l):
+        x = _f64(x).reshape(-1, self.dim)
+        cls = np.zeros(x.shape[0], np.int32)
+        lib().orc_classify(self.h, x.shape[0], _d(x), float(l), _i(cls))
+        return cls
+
+    def candidate_measure(self, l, sides):
+        return lib().orc_candidate_measure(self.h, float(l), int(sides))
+
+    def sample_cache(self, n, l, sides, seed, batch=0):
+        d = self.dim
+        x = np.zeros((n, d))
+        nrm = np.zeros((n, d))
+        w = np.zeros(n)
+        xb = np.zeros((n, d))
+        R0 = np.zeros(n)
+        acc = np.zeros(n, np.int32)
+        na = lib().orc_sample_cache(self.h, n, float(l), int(sides), int(seed), int(batch), _d(x),
+                                    _d(nrm), _d(w), _d(xb), _d(R0), _i(acc))
+        return dict(x=x, n=nrm, w=w, xbar=xb, R0=R0, accept=acc.astype(bool), n_accepted=na)
+
+    def sample_sources(self, f, m, lo, hi, l, seed, batch=0):
+        d = self.dim
+        M = m**d
+        y = np.zeros((M, d))
+        sw = np.zeros(M)
+        F = _field(f)
+        lo = _f64(lo)
+        hi = _f64(hi)
+        lib().orc_sample_sources(self.h, C.byref(F), m, _d(lo), _d(hi), float(l), int(seed),
+                                 int(batch), _d(y), _d(sw))
+        return y, sw
+
+
+def walk_params(eps, n_walks, seed, batch=0, max_steps=1024, control_variate=True):
+    P = _WalkParams()
+    P.eps = float(eps)
+    P.max_steps = int(max_steps)
+    P.n_walks = int(n_walks)
+    P.seed = int(seed)
+    P.batch = int(batch)
+    P.control_variate = int(bool(control_variate))
+    return P
+
+
+def walk(scene: Scene, g, f, params, mode, x, n, R0, xbar, id_):
+    d = scene.dim
+    x = _f64(x)
+    n = _f64(n) if n is not None else None
+    xbar = _f64(xbar)
+    U = np.zeros(1)
+    gr = np.zeros(d)
+    ex = np.zeros(d)
+    w1 = np.zeros(1)
+    st = np.zeros(1, np.int32)
+    cap = np.zeros(1, np.int32)
+    G, Fv = _field(g), _field(f)
+    lib().orc_walk(scene.h, C.byref(G), C.byref(Fv), C.byref(params), mode, _d(x), _d(n),
+                   float(R0), _d(xbar), id_, _d(U), _d(gr), _d(ex), _d(w1), _i(st), _i(cap))
+    return dict(U=U[0], grad=gr, exit=ex, w1=w1[0], steps=int(st[0]), capped=bool(cap[0]))
+
+
+def cache_walks(scene: Scene, g, f, params, cache, records=False):
+    d = scene.dim
+    x = _f64(cache["x"])
+    n = x.shape[0]
+    W = params.n_walks
+    U = np.zeros(n * W)
+    D = np.zeros(n * W)
+    ex = np.zeros((n * W, d)) if records else None
+    w1 = np.zeros(n * W) if records else None
+    st = np.zeros(n * W, np.int32)
+    G, Fv = _field(g), _field(f)
+    lib().orc_cache_walks(scene.h, C.byref(G), C.byref(Fv), C.byref(params), n, _d(x),
+                          _d(_f64(cache["n"])), _d(_f64(cache["R0"])), _d(_f64(cache["xbar"])),
+                          _d(U), _d(D), _d(ex), _d(w1), _i(st))
+    out = dict(U=U, D=D, steps=st)
+    if records:
+        out.update(exit=ex, w1=w1)
+    return out
+
+
+def cache_walks_subset(scene: Scene, g, f, params, cache, ids):
+    ids = np.ascontiguousarray(ids, dtype=np.int64)
+    m = ids.size
+    U = np.zeros(m)
+    D = np.zeros(m)
+    st = np.zeros(m, np.int32)
+    G, Fv = _field(g), _field(f)
+    lib().orc_cache_walks_subset(scene.h, C.byref(G), C.byref(Fv), C.byref(params), m,
+                                 ids.ctypes.data_as(_lp), _d(_f64(cache["x"])),
+                                 _d(_f64(cache["n"])), _d(_f64(cache["R0"])),
+                                 _d(_f64(cache["xbar"])), _d(U), _d(D), _i(st))
+    return dict(U=U, D=D, steps=st)
+
+
+def reduce(U, D, W):
+    U = _f64(U)
+    D = _f64(D)
+    n = U.size // W
+    uh = np.zeros(n)
+    dh = np.zeros(n)
+    lib().orc_reduce(n, W, _d(U), _d(D), _d(uh), _d(dh))
+    return uh, dh
+
+
+def pointwise(scene: Scene, g, f, params, x, with_grad=True):
+    x = _f64(x).reshape(-1, scene.dim)
+    n = x.shape[0]
+    u = np.zeros(n)
+    gr = np.zeros((n, scene.dim)) if with_grad else None
+    tot = C.c_int64()
+    G, Fv = _field(g), _field(f)
+    lib().orc_pointwise(scene.h, C.byref(G), C.byref(Fv), C.byref(params), n, _d(x), _d(u),
+                        _d(gr), C.byref(tot))
+    return u, gr, tot.value
+
+
+def gather(dim, ex, cy, cn, a, b, sy=None, sw=None, with_grad=True, with_cond=False):
+    ex = _f64(ex).reshape(-1, dim)
+    cy = _f64(cy).reshape(-1, dim)
+    cn = _f64(cn).reshape(-1, dim)
+    a = _f64(a)
+    b = _f64(b)
+    K, N = ex.shape[0], cy.shape[0]
+    if sy is None:
+        sy = np.zeros((0, dim))
+        sw = np.zeros(0)
+    sy = _f64(sy).reshape(-1, dim)
+    sw = _f64(sw)
+    u = np.zeros(K)
+    g = np.zeros((K, dim)) if with_grad else None
+    c = np.zeros(K) if with_cond else None
+    lib().orc_gather(dim, K, _d(ex), N, _d(cy), _d(cn), _d(a), _d(b), sy.shape[0], _d(sy),
+                     _d(sw), _d(u), _d(g), _d(c))
+    out = [u]
+    if with_grad:
+        out.append(g)
+    if with_cond:
+        out.append(c)
+    return out[0] if len(out) == 1 else tuple(out)
+
+
+def gather_backward(dim, ex, r, cy, cn, a, b, sy=None, sw=None):
+    ex = _f64(ex).reshape(-1, dim)
+    cy = _f64(cy).reshape(-1, dim)
+    cn = _f64(cn).reshape(-1, dim)
+    r = _f64(r)
+    a = _f64(a)
+    b = _f64(b)
+    K, N = ex.shape[0], cy.shape[0]
+    if sy is None:
+        sy = np.zeros((0, dim))
+        sw = np.zeros(0)
+    sy = _f64(sy).reshape(-1, dim)
+    sw = _f64(sw)
+    M = sy.shape[0]
+    da = np.zeros(N)
+    db = np.zeros(N)
+    ds = np.zeros(M)
+    dx = np.zeros((K, dim))
+    lib().orc_gather_backward(dim, K, _d(ex), _d(r), N, _d(cy), _d(cn), _d(a), _d(b), M, _d(sy),
+                              _d(sw), _d(da), _d(db), _d(ds), _d(dx))
+    return da, db, ds, dx
+
+
+def basis_means(basis, dim, exit_pt, w1, xbar, W, cv=True):
+    exit_pt = _f64(exit_pt).reshape(-1, dim)
+    w1 = _f64(w1)
+    xbar = _f64(xbar).reshape(-1, dim)
+    n = xbar.shape[0]
+    F = _field(basis)
+    nb = F.n_coef if basis.kind != 3 else F.n_coef // (1 + dim)
+    E = np.zeros((n, nb))
+    Fm = np.zeros((n, nb))
+    lib().orc_basis_means(C.byref(F), dim, n, W, _d(exit_pt), _d(w1), _d(xbar), int(cv), _d(E),
+                          _d(Fm))
+    return E, Fm
+
+
+def sample_direction(seed, k, id_, batch, tag, dim):
+    nu = np.zeros(dim)
+    lib().orc_sample_direction(seed, k, id_, batch, tag, dim, _d(nu))
+    return nu
+
+
+def sample_ball_source(seed, k, id_, batch, tag, dim, c, R):
+    y = np.zeros(dim)
+    lib().orc_sample_ball_source(seed, k, id_, batch, tag, dim, _d(_f64(c)), float(R), _d(y))
+    return y
+
+
+def grad_radius(u):
+    return lib().orc_grad_radius(float(u))

@@ -1,0 +1,1246 @@
+/*
+ * Plain FP64 CPU oracle for Boundary Value Caching with walk on spheres.
+ * TEST INFRASTRUCTURE ONLY (see oracle.h): loaded by the tests, the smoke
+ * check and the CPU-baseline leg of the benchmark, never by the product path.
+ *
+ * Everything here is written for checkability, not speed: plain loops in the
+ * order the paper states them, FP64 throughout, no blocking or fusion.  The
+ * only acceleration is a simple median-split BVH for closest points, checked
+ * against the brute-force scan it replaces.  OpenMP splits independent outer
+ * loops (cache points, evaluation points); it never reorders a sum.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_PI 3.14159265358979323846
+
+/* ======================================================================== */
+/* Philox-4x32-10 (Salmon et al., "Parallel random numbers: as easy as 1, 2,  */
+/* 3", SC'11): ten rounds of two 32x32->64 multiplies with a Weyl key update. */
+/* ======================================================================== */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  const uint32_t mul_a = 0xD2511F53u, mul_b = 0xCD9E8D57u;
+  const uint32_t weyl_a = 0x9E3779B9u, weyl_b = 0xBB67AE85u;
+  uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    uint64_t prod_a = (uint64_t)mul_a * (uint64_t)x0;
+    uint64_t prod_b = (uint64_t)mul_b * (uint64_t)x2;
+    uint32_t y0 = (uint32_t)(prod_b >> 32) ^ x1 ^ k0;
+    uint32_t y1 = (uint32_t)prod_b;
+    uint32_t y2 = (uint32_t)(prod_a >> 32) ^ x3 ^ k1;
+    uint32_t y3 = (uint32_t)prod_a;
+    x0 = y0;
+    x1 = y1;
+    x2 = y2;
+    x3 = y3;
+    k0 += weyl_a;
+    k1 += weyl_b;
+  }
+  out[0] = x0;
+  out[1] = x1;
+  out[2] = x2;
+  out[3] = x3;
+}
+
+static double u53(uint32_t hi, uint32_t lo) {
+  uint64_t bits = ((uint64_t)hi << 21) | (uint64_t)(lo >> 11);
+  return (double)bits * (1.0 / 9007199254740992.0); /* 2^-53 */
+}
+
+void orc_uniform_pair(uint64_t seed, uint32_t block, uint32_t id, uint32_t batch,
+                      uint32_t tag, double* ua, double* ub) {
+  uint32_t ctr[4] = {block, id, batch, tag};
+  uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+  uint32_t w[4];
+  orc_philox4x32_10(ctr, key, w);
+  *ua = u53(w[0], w[1]);
+  *ub = u53(w[2], w[3]);
+}
+
+/* ======================================================================== */
+/* Scene, BVH and closest points                                             */
+/* ======================================================================== */
+typedef struct {
+  double lo[3], hi[3];
+  int64_t left, right; /* children (internal) or -1 */
+  int64_t start, count; /* primitive range in perm (leaf) */
+} onode;
+
+struct orc_scene {
+  int dim;
+  int64_t nv, np;
+  double* V;
+  int32_t* P;
+  int64_t n_nodes;
+  onode* nodes;
+  int32_t* perm;
+  /* 3D only */
+  double* fnorm;    /* unit face normals (np x 3) */
+  double* vpn;      /* angle-weighted vertex pseudonormals (nv x 3) */
+  double* epn;      /* per-triangle edge pseudonormals (np x 3 edges x 3) */
+  int64_t ne;
+  int32_t* edges;   /* unique edges (ne x 2) */
+};
+
+static double dot3(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+static void cross3(const double* a, const double* b, double* c) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+static void prim_bounds(const orc_scene* s, int64_t p, double* lo, double* hi, double* cen) {
+  int d = s->dim;
+  for (int a = 0; a < d; ++a) {
+    lo[a] = INFINITY;
+    hi[a] = -INFINITY;
+    cen[a] = 0;
+  }
+  for (int c = 0; c < d; ++c) {
+    const double* v = s->V + (int64_t)s->P[p * d + c] * d;
+    for (int a = 0; a < d; ++a) {
+      if (v[a] < lo[a]) lo[a] = v[a];
+      if (v[a] > hi[a]) hi[a] = v[a];
+      cen[a] += v[a] / d;
+    }
+  }
+}
+
+typedef struct {
+  const double* cen;
+  int axis;
+  int dim;
+} sort_ctx;
+static sort_ctx g_sort; /* build is single-threaded */
+static int cmp_prim(const void* pa, const void* pb) {
+  int32_t a = *(const int32_t*)pa, b = *(const int32_t*)pb;
+  double ca = g_sort.cen[(int64_t)a * g_sort.dim + g_sort.axis];
+  double cb = g_sort.cen[(int64_t)b * g_sort.dim + g_sort.axis];
+  if (ca < cb) return -1;
+  if (ca > cb) return 1;
+  return (a < b) ? -1 : (a > b);
+}
+
+static int64_t build_node(orc_scene* s, const double* plo, const double* phi, const double* cen,
+                          int64_t start, int64_t count) {
+  int d = s->dim;
+  int64_t id = s->n_nodes++;
+  onode* nd = &s->nodes[id];
+  double clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int a = 0; a < 3; ++a) {
+    nd->lo[a] = (a < d) ? INFINITY : 0;
+    nd->hi[a] = (a < d) ? -INFINITY : 0;
+  }
+  for (int64_t i = start; i < start + count; ++i) {
+    int32_t p = s->perm[i];
+    for (int a = 0; a < d; ++a) {
+      if (plo[(int64_t)p * d + a] < nd->lo[a]) nd->lo[a] = plo[(int64_t)p * d + a];
+      if (phi[(int64_t)p * d + a] > nd->hi[a]) nd->hi[a] = phi[(int64_t)p * d + a];
+      if (cen[(int64_t)p * d + a] < clo[a]) clo[a] = cen[(int64_t)p * d + a];
+      if (cen[(int64_t)p * d + a] > chi[a]) chi[a] = cen[(int64_t)p * d + a];
+    }
+  }
+  nd->start = start;
+  nd->count = count;
+  nd->left = nd->right = -1;
+  if (count <= 4) return id;
+  int axis = 0;
+  for (int a = 1; a < d; ++a)
+    if (chi[a] - clo[a] > chi[axis] - clo[axis]) axis = a;
+  g_sort.cen = cen;
+  g_sort.axis = axis;
+  g_sort.dim = d;
+  qsort(s->perm + start, (size_t)count, sizeof(int32_t), cmp_prim);
+  int64_t half = count / 2;
+  int64_t l = build_node(s, plo, phi, cen, start, half);
+  int64_t r = build_node(s, plo, phi, cen, start + half, count - half);
+  s->nodes[id].left = l;
+  s->nodes[id].right = r;
+  s->nodes[id].count = 0;
+  return id;
+}
+
+static int cmp_edge(const void* pa, const void* pb) {
+  const int64_t* a = (const int64_t*)pa;
+  const int64_t* b = (const int64_t*)pb;
+  return (a[0] < b[0]) ? -1 : (a[0] > b[0]);
+}
+
+static void build_pseudonormals(orc_scene* s) {
+  int64_t np = s->np, nv = s->nv;
+  s->fnorm = (double*)calloc((size_t)np * 3, sizeof(double));
+  s->vpn = (double*)calloc((size_t)nv * 3, sizeof(double));
+  s->epn = (double*)calloc((size_t)np * 9, sizeof(double));
+  for (int64_t t = 0; t < np; ++t) {
+    const double* A = s->V + 3 * (int64_t)s->P[3 * t];
+    const double* B = s->V + 3 * (int64_t)s->P[3 * t + 1];
+    const double* C = s->V + 3 * (int64_t)s->P[3 * t + 2];
+    double ab[3], ac[3], n[3];
+    for (int a = 0; a < 3; ++a) {
+      ab[a] = B[a] - A[a];
+      ac[a] = C[a] - A[a];
+    }
+    cross3(ab, ac, n);
+    double len = sqrt(dot3(n, n));
+    for (int a = 0; a < 3; ++a) s->fnorm[3 * t + a] = n[a] / len;
+    /* interior angle at each corner weights the vertex pseudonormal */
+    const double* corner[3] = {A, B, C};
+    for (int c = 0; c < 3; ++c) {
+      const double* o = corner[c];
+      const double* p1 = corner[(c + 1) % 3];
+      const double* p2 = corner[(c + 2) % 3];
+      double u[3], v[3];
+      for (int a = 0; a < 3; ++a) {
+        u[a] = p1[a] - o[a];
+        v[a] = p2[a] - o[a];
+      }
+      double cang = dot3(u, v) / sqrt(dot3(u, u) * dot3(v, v));
+      if (cang > 1) cang = 1;
+      if (cang < -1) cang = -1;
+      double ang = acos(cang);
+      int64_t vi = s->P[3 * t + c];
+      for (int a = 0; a < 3; ++a) s->vpn[3 * vi + a] += ang * s->fnorm[3 * t + a];
+    }
+  }
+  /* unique edges: key = min*nv + max, with the triangle and local edge */
+  int64_t m = 3 * np;
+  int64_t* rec = (int64_t*)malloc((size_t)m * 3 * sizeof(int64_t));
+  for (int64_t t = 0; t < np; ++t)
+    for (int e = 0; e < 3; ++e) {
+      int64_t a = s->P[3 * t + e], b = s->P[3 * t + (e + 1) % 3];
+      int64_t lo = a < b ? a : b, hi = a < b ? b : a;
+      rec[3 * (3 * t + e)] = lo * nv + hi;
+      rec[3 * (3 * t + e) + 1] = t;
+      rec[3 * (3 * t + e) + 2] = e;
+    }
+  qsort(rec, (size_t)m, 3 * sizeof(int64_t), cmp_edge);
+  s->edges = (int32_t*)malloc((size_t)m * 2 * sizeof(int32_t));
+  s->ne = 0;
+  for (int64_t i = 0; i < m;) {
+    int64_t j = i;
+    double sum[3] = {0, 0, 0};
+    while (j < m && rec[3 * j] == rec[3 * i]) {
+      int64_t t = rec[3 * j + 1];
+      for (int a = 0; a < 3; ++a) sum[a] += s->fnorm[3 * t + a];
+      ++j;
+    }
+    for (int64_t q = i; q < j; ++q) {
+      int64_t t = rec[3 * q + 1], e = rec[3 * q + 2];
+      for (int a = 0; a < 3; ++a) s->epn[9 * t + 3 * e + a] = sum[a];
+    }
+    s->edges[2 * s->ne] = (int32_t)(rec[3 * i] / nv);
+    s->edges[2 * s->ne + 1] = (int32_t)(rec[3 * i] % nv);
+    s->ne++;
+    i = j;
+  }
+  free(rec);
+}
+
+orc_scene* orc_scene_new(int dim, const double* verts, int64_t nv, const int32_t* prims,
+                         int64_t np) {
+  orc_scene* s = (orc_scene*)calloc(1, sizeof(orc_scene));
+  s->dim = dim;
+  s->nv = nv;
+  s->np = np;
+  s->V = (double*)malloc((size_t)nv * dim * sizeof(double));
+  memcpy(s->V, verts, (size_t)nv * dim * sizeof(double));
+  s->P = (int32_t*)malloc((size_t)np * dim * sizeof(int32_t));
+  memcpy(s->P, prims, (size_t)np * dim * sizeof(int32_t));
+  double* plo = (double*)malloc((size_t)np * dim * sizeof(double));
+  double* phi = (double*)malloc((size_t)np * dim * sizeof(double));
+  double* cen = (double*)malloc((size_t)np * dim * sizeof(double));
+  for (int64_t p = 0; p < np; ++p) {
+    double lo[3], hi[3], c[3];
+    prim_bounds(s, p, lo, hi, c);
+    for (int a = 0; a < dim; ++a) {
+      plo[p * dim + a] = lo[a];
+      phi[p * dim + a] = hi[a];
+      cen[p * dim + a] = c[a];
+    }
+  }
+  s->perm = (int32_t*)malloc((size_t)np * sizeof(int32_t));
+  for (int64_t p = 0; p < np; ++p) s->perm[p] = (int32_t)p;
+  s->nodes = (onode*)malloc((size_t)(2 * np + 1) * sizeof(onode));
+  s->n_nodes = 0;
+  build_node(s, plo, phi, cen, 0, np);
+  free(plo);
+  free(phi);
+  free(cen);
+  if (dim == 3) build_pseudonormals(s);
+  return s;
+}
+
+void orc_scene_free(orc_scene* s) {
+  if (!s) return;
+  free(s->V);
+  free(s->P);
+  free(s->nodes);
+  free(s->perm);
+  free(s->fnorm);
+  free(s->vpn);
+  free(s->epn);
+  free(s->edges);
+  free(s);
+}
+
+/* Closest point on segment [a, b]; exact endpoints when the projection clamps. */
+static double closest_segment(const double* x, const double* a, const double* b, double* c) {
+  double e0 = b[0] - a[0], e1 = b[1] - a[1];
+  double t = ((x[0] - a[0]) * e0 + (x[1] - a[1]) * e1) / (e0 * e0 + e1 * e1);
+  if (t <= 0) {
+    c[0] = a[0];
+    c[1] = a[1];
+  } else if (t >= 1) {
+    c[0] = b[0];
+    c[1] = b[1];
+  } else {
+    c[0] = a[0] + t * e0;
+    c[1] = a[1] + t * e1;
+  }
+  double d0 = x[0] - c[0], d1 = x[1] - c[1];
+  return d0 * d0 + d1 * d1;
+}
+
+/* Closest point on triangle (a, b, c) by Voronoi-region classification
+ * (Ericson, Real-Time Collision Detection, Sec. 5.1.5).  region: 0 face,
+ * 1/2/3 vertex a/b/c, 4/5/6 edge ab/bc/ca. */
+static double closest_triangle(const double* p, const double* a, const double* b,
+                               const double* c, double* q, int* region) {
+  double ab[3], ac[3], ap[3], bp[3], cp[3];
+  for (int i = 0; i < 3; ++i) {
+    ab[i] = b[i] - a[i];
+    ac[i] = c[i] - a[i];
+    ap[i] = p[i] - a[i];
+    bp[i] = p[i] - b[i];
+    cp[i] = p[i] - c[i];
+  }
+  double d1 = dot3(ab, ap), d2 = dot3(ac, ap);
+  double d3 = dot3(ab, bp), d4 = dot3(ac, bp);
+  double d5 = dot3(ab, cp), d6 = dot3(ac, cp);
+  double vc = d1 * d4 - d3 * d2;
+  double vb = d5 * d2 - d1 * d6;
+  double va = d3 * d6 - d5 * d4;
+  if (d1 <= 0 && d2 <= 0) {
+    for (int i = 0; i < 3; ++i) q[i] = a[i];
+    *region = 1;
+  } else if (d3 >= 0 && d4 <= d3) {
+    for (int i = 0; i < 3; ++i) q[i] = b[i];
+    *region = 2;
+  } else if (vc <= 0 && d1 >= 0 && d3 <= 0) {
+    double v = d1 / (d1 - d3);
+    for (int i = 0; i < 3; ++i) q[i] = a[i] + v * ab[i];
+    *region = 4;
+  } else if (d6 >= 0 && d5 <= d6) {
+    for (int i = 0; i < 3; ++i) q[i] = c[i];
+    *region = 3;
+  } else if (vb <= 0 && d2 >= 0 && d6 <= 0) {
+    double w = d2 / (d2 - d6);
+    for (int i = 0; i < 3; ++i) q[i] = a[i] + w * ac[i];
+    *region = 6;
+  } else if (va <= 0 && (d4 - d3) >= 0 && (d5 - d6) >= 0) {
+    double w = (d4 - d3) / ((d4 - d3) + (d5 - d6));
+    for (int i = 0; i < 3; ++i) q[i] = b[i] + w * (c[i] - b[i]);
+    *region = 5;
+  } else {
+    double den = 1.0 / (va + vb + vc);
+    double v = vb * den, w = vc * den;
+    for (int i = 0; i < 3; ++i) q[i] = a[i] + ab[i] * v + ac[i] * w;
+    *region = 0;
+  }
+  double dd[3] = {p[0] - q[0], p[1] - q[1], p[2] - q[2]};
+  return dot3(dd, dd);
+}
+
+static double prim_dist2(const orc_scene* s, int64_t p, const double* x, double* c, int* region) {
+  if (s->dim == 2) {
+    *region = 0;
+    return closest_segment(x, s->V + 2 * (int64_t)s->P[2 * p], s->V + 2 * (int64_t)s->P[2 * p + 1], c);
+  }
+  return closest_triangle(x, s->V + 3 * (int64_t)s->P[3 * p], s->V + 3 * (int64_t)s->P[3 * p + 1],
+                          s->V + 3 * (int64_t)s->P[3 * p + 2], c, region);
+}
+
+static double box_dist2(const onode* n, const double* x, int dim) {
+  double d2 = 0;
+  for (int a = 0; a < dim; ++a) {
+    double e = 0;
+    if (x[a] < n->lo[a]) e = n->lo[a] - x[a];
+    else if (x[a] > n->hi[a]) e = x[a] - n->hi[a];
+    d2 += e * e;
+  }
+  return d2;
+}
+
+/* Update the best candidate with lexicographic (d^2, primitive id) order. */
+static void consider(const orc_scene* s, int64_t p, const double* x, double* best, int64_t* bp,
+                     double* bc, int* breg) {
+  double c[3];
+  int reg;
+  double d2 = prim_dist2(s, p, x, c, &reg);
+  if (d2 < *best || (d2 == *best && p < *bp)) {
+    *best = d2;
+    *bp = p;
+    *breg = reg;
+    for (int a = 0; a < s->dim; ++a) bc[a] = c[a];
+  }
+}
+
+static void closest_full(const orc_scene* s, const double* x, int brute, double* d2out,
+                         double* xbar, int64_t* prim, int* region) {
+  double best = INFINITY;
+  int64_t bp = -1;
+  int breg = 0;
+  double bc[3] = {0, 0, 0};
+  if (brute) {
+    for (int64_t p = 0; p < s->np; ++p) consider(s, p, x, &best, &bp, bc, &breg);
+  } else {
+    int64_t stack[128];
+    double sd[128];
+    int top = 0;
+    stack[top] = 0;
+    sd[top++] = box_dist2(&s->nodes[0], x, s->dim);
+    while (top > 0) {
+      --top;
+      int64_t ni = stack[top];
+      if (sd[top] > best) continue;
+      const onode* nd = &s->nodes[ni];
+      if (nd->left < 0) {
+        for (int64_t i = nd->start; i < nd->start + nd->count; ++i)
+          consider(s, s->perm[i], x, &best, &bp, bc, &breg);
+        continue;
+      }
+      double dl = box_dist2(&s->nodes[nd->left], x, s->dim);
+      double dr = box_dist2(&s->nodes[nd->right], x, s->dim);
+      /* push the farther child first so the nearer one is visited next */
+      if (dl <= dr) {
+        stack[top] = nd->right;
+        sd[top++] = dr;
+        stack[top] = nd->left;
+        sd[top++] = dl;
+      } else {
+        stack[top] = nd->left;
+        sd[top++] = dl;
+        stack[top] = nd->right;
+        sd[top++] = dr;
+      }
+    }
+  }
+  *d2out = best;
+  for (int a = 0; a < s->dim; ++a) xbar[a] = bc[a];
+  *prim = bp;
+  *region = breg;
+}
+
+void orc_closest(const orc_scene* s, const double* x, int brute, double* dist, double* xbar,
+                 int32_t* prim) {
+  double d2;
+  int64_t p;
+  int reg;
+  closest_full(s, x, brute, &d2, xbar, &p, &reg);
+  *dist = sqrt(d2);
+  if (prim) *prim = (int32_t)p;
+}
+
+void orc_closest_batch(const orc_scene* s, int64_t n, const double* x, int brute, double* dist,
+                       double* xbar, int32_t* prim) {
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t i = 0; i < n; ++i)
+    orc_closest(s, x + i * s->dim, brute, dist + i, xbar + i * s->dim, prim ? prim + i : NULL);
+}
+
+/* Winding number of a closed polygon around x (edge-crossing rule). */
+static int winding2d(const orc_scene* s, const double* x) {
+  int wn = 0;
+  for (int64_t p = 0; p < s->np; ++p) {
+    const double* a = s->V + 2 * (int64_t)s->P[2 * p];
+    const double* b = s->V + 2 * (int64_t)s->P[2 * p + 1];
+    double side = (b[0] - a[0]) * (x[1] - a[1]) - (x[0] - a[0]) * (b[1] - a[1]);
+    if (a[1] <= x[1]) {
+      if (b[1] > x[1] && side > 0) ++wn;
+    } else {
+      if (b[1] <= x[1] && side < 0) --wn;
+    }
+  }
+  return wn;
+}
+
+int orc_inside(const orc_scene* s, const double* x) {
+  if (s->dim == 2) return winding2d(s, x);
+  double d2, xb[3];
+  int64_t p;
+  int reg;
+  closest_full(s, x, 0, &d2, xb, &p, &reg);
+  const double* N;
+  if (reg == 0) N = s->fnorm + 3 * p;
+  else if (reg <= 3) N = s->vpn + 3 * (int64_t)s->P[3 * p + (reg - 1)];
+  else N = s->epn + 9 * p + 3 * (reg - 4);
+  double v[3] = {x[0] - xb[0], x[1] - xb[1], x[2] - xb[2]};
+  return dot3(v, N) < 0 ? 1 : 0;
+}
+
+void orc_classify(const orc_scene* s, int64_t n, const double* x, double l, int32_t* cls) {
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t i = 0; i < n; ++i) {
+    const double* xi = x + i * s->dim;
+    if (orc_inside(s, xi) == 0) {
+      cls[i] = 0;
+      continue;
+    }
+    double d, xb[3];
+    orc_closest(s, xi, 0, &d, xb, NULL);
+    cls[i] = (d > l) ? 1 : 2;
+  }
+}
+
+/* ======================================================================== */
+/* Fields                                                                   */
+/* ======================================================================== */
+/* Ein(z) = int_0^z (1 - e^-t)/t dt.  Power series for small z; for larger z
+ * Ein = E1(z) + ln z + gamma with E1 from its continued fraction evaluated by
+ * the modified Lentz method (Abramowitz & Stegun 5.1.11 and 5.1.22). */
+double orc_ein(double z) {
+  const double euler_gamma = 0.57721566490153286061;
+  if (z <= 0) return 0;
+  if (z < 2.0) {
+    double sum = 0, pw = 1, fact = 1;
+    for (int k = 1; k < 60; ++k) {
+      pw *= z;
+      fact *= k;
+      double term = pw / (k * fact);
+      sum += (k % 2 == 1) ? term : -term;
+      if (term < 1e-18 * fabs(sum)) break;
+    }
+    return sum;
+  }
+  const double tiny = 1e-300;
+  double bcoef = z + 1.0;
+  double cf = 1.0 / tiny;
+  double df = 1.0 / bcoef;
+  double h = df;
+  for (int i = 1; i < 500; ++i) {
+    double acoef = -(double)i * (double)i;
+    bcoef += 2.0;
+    df = 1.0 / (acoef * df + bcoef);
+    cf = bcoef + acoef / cf;
+    double delta = cf * df;
+    h *= delta;
+    if (fabs(delta - 1.0) < 1e-16) break;
+  }
+  return h * exp(-z) + log(z) + euler_gamma;
+}
+
+static double harmonic2d(double k, double alpha, double beta, const double* x) {
+  int kk = (int)k;
+  double re = 1, im = 0;
+  for (int i = 0; i < kk; ++i) {
+    double nre = re * x[0] - im * x[1];
+    double nim = re * x[1] + im * x[0];
+    re = nre;
+    im = nim;
+  }
+  return alpha * re + beta * exp(x[0]) * cos(x[1]);
+}
+
+/* Orthonormal real solid harmonic r^l Y_lm (no Condon-Shortley phase), via
+ * the associated Legendre recurrences in cos(theta). */
+static double solid_harmonic(int l, int m, const double* x) {
+  double r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+  int am = m < 0 ? -m : m;
+  if (r == 0) return (l == 0) ? 0.5 / sqrt(ORC_PI) : 0.0;
+  double ct = x[2] / r;
+  double st = sqrt(fmax(0.0, 1 - ct * ct));
+  double phi = atan2(x[1], x[0]);
+  double pmm = 1;
+  for (int i = 1; i <= am; ++i) pmm *= (2 * i - 1) * st;
+  double plm = pmm, p1 = 0, p2 = 0;
+  for (int ll = am; ll <= l; ++ll) {
+    if (ll == am) plm = pmm;
+    else if (ll == am + 1) plm = ct * (2 * am + 1) * pmm;
+    else plm = (ct * (2 * ll - 1) * p1 - (ll + am - 1) * p2) / (ll - am);
+    p2 = p1;
+    p1 = plm;
+  }
+  double ratio = 1; /* (l-|m|)! / (l+|m|)! */
+  for (int i = l - am + 1; i <= l + am; ++i) ratio /= i;
+  double nrm = sqrt((2 * l + 1) / (4 * ORC_PI) * ratio);
+  double ang = 1;
+  if (m > 0) ang = sqrt(2.0) * cos(m * phi);
+  if (m < 0) ang = sqrt(2.0) * sin(am * phi);
+  return pow(r, l) * nrm * plm * ang;
+}
+
+static double fourier_phi(int b, double th) {
+  if (b == 0) return 1.0;
+  int j = (b + 1) / 2;
+  return (b % 2 == 1) ? cos(j * th) : sin(j * th);
+}
+
+double orc_basis_eval(const orc_field* F, int dim, int m, const double* x) {
+  switch (F->kind) {
+    case ORC_FIELD_FOURIER_2D:
+      return fourier_phi(m, atan2(x[1] - F->param[1], x[0] - F->param[0]));
+    case ORC_FIELD_SOLID_HARMONICS_3D: {
+      int l = 0;
+      while ((l + 1) * (l + 1) <= m) ++l;
+      return solid_harmonic(l, m - l * l - l, x);
+    }
+    case ORC_FIELD_GAUSS_SUM: {
+      const double* c = F->coef + m * (1 + dim);
+      double r2 = 0;
+      for (int a = 0; a < dim; ++a) r2 += (x[a] - c[1 + a]) * (x[a] - c[1 + a]);
+      return exp(-r2 / (2 * F->param[0] * F->param[0]));
+    }
+    default:
+      return 0.0;
+  }
+}
+
+double orc_field_eval(const orc_field* F, int dim, const double* x) {
+  if (!F) return 0.0;
+  const double* p = F->param;
+  switch (F->kind) {
+    case ORC_FIELD_ZERO:
+      return 0.0;
+    case ORC_FIELD_CONST:
+      return p[0];
+    case ORC_FIELD_HARMONIC_2D:
+      return harmonic2d(p[0], p[1], p[2], x);
+    case ORC_FIELD_GAUSS_SUM: {
+      int ng = F->n_coef / (1 + dim);
+      double sum = 0;
+      for (int k = 0; k < ng; ++k) sum += F->coef[k * (1 + dim)] * orc_basis_eval(F, dim, k, x);
+      return sum;
+    }
+    case ORC_FIELD_GAUSS_POTENTIAL_2D: {
+      int ng = F->n_coef / 3;
+      double s = p[0], sum = 0;
+      for (int k = 0; k < ng; ++k) {
+        const double* c = F->coef + 3 * k;
+        double r2 = (x[0] - c[1]) * (x[0] - c[1]) + (x[1] - c[2]) * (x[1] - c[2]);
+        sum += c[0] * s * s / 2 * orc_ein(r2 / (2 * s * s));
+      }
+      return sum + harmonic2d(p[1], p[2], p[3], x);
+    }
+    case ORC_FIELD_SOLID_HARMONICS_3D:
+    case ORC_FIELD_FOURIER_2D: {
+      double sum = 0;
+      for (int m = 0; m < F->n_coef; ++m) sum += F->coef[m] * orc_basis_eval(F, dim, m, x);
+      return sum;
+    }
+    case ORC_FIELD_POINT_SOURCE: {
+      double r2 = 0;
+      for (int a = 0; a < dim; ++a) r2 += (x[a] - p[1 + a]) * (x[a] - p[1 + a]);
+      return dim == 2 ? p[0] * 0.5 * log(r2) : p[0] / sqrt(r2);
+    }
+  }
+  return 0.0;
+}
+
+void orc_field_eval_batch(const orc_field* F, int dim, int64_t n, const double* x, double* out) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) out[i] = orc_field_eval(F, dim, x + i * dim);
+}
+
+/* ======================================================================== */
+/* Green's functions of the Laplacian (Appendix A.1, with G_3D = -1/(4 pi r)) */
+/* ======================================================================== */
+void orc_greens(int dim, const double* x, const double* y, const double* ny, double* G,
+                double* dGdx, double* dGdn, double* d2Gdxdn) {
+  double yx[3] = {0, 0, 0}; /* y - x */
+  double r2 = 0;
+  for (int a = 0; a < dim; ++a) {
+    yx[a] = y[a] - x[a];
+    r2 += yx[a] * yx[a];
+  }
+  double r = sqrt(r2);
+  double ndot = 0;
+  if (ny)
+    for (int a = 0; a < dim; ++a) ndot += ny[a] * yx[a];
+  if (dim == 2) {
+    double c = 1.0 / (2 * ORC_PI);
+    if (G) *G = c * log(r);
+    if (dGdx)
+      for (int a = 0; a < 2; ++a) dGdx[a] = c * (-yx[a]) / r2;
+    if (dGdn) *dGdn = c * ndot / r2;
+    if (d2Gdxdn)
+      for (int a = 0; a < 2; ++a) d2Gdxdn[a] = c * (2 * ndot * yx[a] / (r2 * r2) - ny[a] / r2);
+  } else {
+    double c = 1.0 / (4 * ORC_PI);
+    double r3 = r2 * r;
+    if (G) *G = -c / r;
+    if (dGdx)
+      for (int a = 0; a < 3; ++a) dGdx[a] = c * (-yx[a]) / r3;
+    if (dGdn) *dGdn = c * ndot / r3;
+    if (d2Gdxdn)
+      for (int a = 0; a < 3; ++a) d2Gdxdn[a] = c * (3 * ndot * yx[a] / (r3 * r2) - ny[a] / r3);
+  }
+}
+
+/* ======================================================================== */
+/* Cache sampling on the offset boundary                                    */
+/* ======================================================================== */
+typedef struct {
+  int64_t n_el;
+  int32_t* kind;  /* 0 segment/face offset, 1 vertex circle/sphere, 2 edge cylinder */
+  int32_t* idx;   /* primitive, vertex or edge index */
+  int32_t* side;  /* +1 inward (left of a CCW segment, against the face normal), -1 outward */
+  double* meas;
+  double* cdf;    /* n_el + 1 */
+} elem_table;
+
+static void make_elements(const orc_scene* s, double l, int sides, elem_table* T) {
+  int d = s->dim;
+  int64_t n = (d == 2) ? s->np * sides + s->nv : s->np + s->ne + s->nv;
+  T->n_el = n;
+  T->kind = (int32_t*)malloc((size_t)n * sizeof(int32_t));
+  T->idx = (int32_t*)malloc((size_t)n * sizeof(int32_t));
+  T->side = (int32_t*)malloc((size_t)n * sizeof(int32_t));
+  T->meas = (double*)malloc((size_t)n * sizeof(double));
+  T->cdf = (double*)malloc((size_t)(n + 1) * sizeof(double));
+  int64_t e = 0;
+  if (d == 2) {
+    for (int64_t p = 0; p < s->np; ++p) {
+      const double* a = s->V + 2 * (int64_t)s->P[2 * p];
+      const double* b = s->V + 2 * (int64_t)s->P[2 * p + 1];
+      double len = sqrt((b[0] - a[0]) * (b[0] - a[0]) + (b[1] - a[1]) * (b[1] - a[1]));
+      for (int sd = 0; sd < sides; ++sd) {
+        T->kind[e] = 0;
+        T->idx[e] = (int32_t)p;
+        T->side[e] = sd == 0 ? 1 : -1;
+        T->meas[e] = len;
+        ++e;
+      }
+    }
+    for (int64_t v = 0; v < s->nv; ++v) {
+      T->kind[e] = 1;
+      T->idx[e] = (int32_t)v;
+      T->side[e] = 0;
+      T->meas[e] = 2 * ORC_PI * l;
+      ++e;
+    }
+  } else {
+    for (int64_t p = 0; p < s->np; ++p) {
+      const double* A = s->V + 3 * (int64_t)s->P[3 * p];
+      const double* B = s->V + 3 * (int64_t)s->P[3 * p + 1];
+      const double* C = s->V + 3 * (int64_t)s->P[3 * p + 2];
+      double ab[3], ac[3], c[3];
+      for (int a = 0; a < 3; ++a) {
+        ab[a] = B[a] - A[a];
+        ac[a] = C[a] - A[a];
+      }
+      cross3(ab, ac, c);
+      T->kind[e] = 0;
+      T->idx[e] = (int32_t)p;
+      T->side[e] = 1;
+      T->meas[e] = 0.5 * sqrt(dot3(c, c));
+      ++e;
+    }
+    for (int64_t q = 0; q < s->ne; ++q) {
+      const double* A = s->V + 3 * (int64_t)s->edges[2 * q];
+      const double* B = s->V + 3 * (int64_t)s->edges[2 * q + 1];
+      double ab[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
+      T->kind[e] = 2;
+      T->idx[e] = (int32_t)q;
+      T->side[e] = 0;
+      T->meas[e] = 2 * ORC_PI * l * sqrt(dot3(ab, ab));
+      ++e;
+    }
+    for (int64_t v = 0; v < s->nv; ++v) {
+      T->kind[e] = 1;
+      T->idx[e] = (int32_t)v;
+      T->side[e] = 0;
+      T->meas[e] = 4 * ORC_PI * l * l;
+      ++e;
+    }
+  }
+  T->cdf[0] = 0;
+  for (int64_t i = 0; i < n; ++i) T->cdf[i + 1] = T->cdf[i] + T->meas[i];
+}
+
+static void free_elements(elem_table* T) {
+  free(T->kind);
+  free(T->idx);
+  free(T->side);
+  free(T->meas);
+  free(T->cdf);
+}
+
+double orc_candidate_measure(const orc_scene* s, double l, int sides) {
+  elem_table T;
+  make_elements(s, l, sides, &T);
+  double m = T.cdf[T.n_el];
+  free_elements(&T);
+  return m;
+}
+
+/* Candidate point of element e at stratified residual r and second uniform v. */
+static void candidate_point(const orc_scene* s, const elem_table* T, int64_t e, double r,
+                            double v, double l, double* x) {
+  int d = s->dim;
+  int32_t k = T->kind[e], i = T->idx[e];
+  if (d == 2) {
+    if (k == 0) {
+      const double* a = s->V + 2 * (int64_t)s->P[2 * i];
+      const double* b = s->V + 2 * (int64_t)s->P[2 * i + 1];
+      double t0 = b[0] - a[0], t1 = b[1] - a[1];
+      double len = sqrt(t0 * t0 + t1 * t1);
+      double n0 = t1 / len, n1 = -t0 / len; /* outward normal of a CCW polygon */
+      double q0 = a[0] + r * t0, q1 = a[1] + r * t1;
+      x[0] = q0 - T->side[e] * l * n0;
+      x[1] = q1 - T->side[e] * l * n1;
+    } else {
+      const double* c = s->V + 2 * (int64_t)i;
+      double ang = 2 * ORC_PI * r;
+      x[0] = c[0] + l * cos(ang);
+      x[1] = c[1] + l * sin(ang);
+    }
+    return;
+  }
+  if (k == 0) {
+    const double* A = s->V + 3 * (int64_t)s->P[3 * i];
+    const double* B = s->V + 3 * (int64_t)s->P[3 * i + 1];
+    const double* C = s->V + 3 * (int64_t)s->P[3 * i + 2];
+    double su = sqrt(r);
+    double b0 = 1 - su, b1 = su * (1 - v), b2 = su * v;
+    double ab[3], ac[3], nn[3];
+    for (int a = 0; a < 3; ++a) {
+      ab[a] = B[a] - A[a];
+      ac[a] = C[a] - A[a];
+    }
+    cross3(ab, ac, nn);
+    double len = sqrt(dot3(nn, nn));
+    for (int a = 0; a < 3; ++a) x[a] = b0 * A[a] + b1 * B[a] + b2 * C[a] - l * nn[a] / len;
+  } else if (k == 2) {
+    const double* A = s->V + 3 * (int64_t)s->edges[2 * i];
+    const double* B = s->V + 3 * (int64_t)s->edges[2 * i + 1];
+    double t[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
+    double len = sqrt(dot3(t, t));
+    for (int a = 0; a < 3; ++a) t[a] /= len;
+    /* frame: helper axis with the smallest |t| component (first on ties) */
+    int ax = 0;
+    for (int a = 1; a < 3; ++a)
+      if (fabs(t[a]) < fabs(t[ax])) ax = a;
+    double h[3] = {0, 0, 0};
+    h[ax] = 1;
+    double e1[3], e2[3];
+    cross3(t, h, e1);
+    double l1 = sqrt(dot3(e1, e1));
+    for (int a = 0; a < 3; ++a) e1[a] /= l1;
+    cross3(t, e1, e2);
+    double ang = 2 * ORC_PI * v;
+    double ca = cos(ang), sa = sin(ang);
+    for (int a = 0; a < 3; ++a) x[a] = A[a] + r * (B[a] - A[a]) + l * (ca * e1[a] + sa * e2[a]);
+  } else {
+    const double* c = s->V + 3 * (int64_t)i;
+    double z = 1 - 2 * r;
+    double rho = sqrt(fmax(0.0, 1 - z * z));
+    double ang = 2 * ORC_PI * v;
+    x[0] = c[0] + l * rho * cos(ang);
+    x[1] = c[1] + l * rho * sin(ang);
+    x[2] = c[2] + l * z;
+  }
+}
+
+int64_t orc_sample_cache(const orc_scene* s, int64_t n, double l, int sides, uint64_t seed,
+                         uint32_t batch, double* x, double* nrm, double* w, double* xbar,
+                         double* R0, int32_t* accept) {
+  int d = s->dim;
+  elem_table T;
+  make_elements(s, l, sides, &T);
+  double M = T.cdf[T.n_el];
+  int64_t n_acc = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : n_acc)
+  for (int64_t k = 0; k < n; ++k) {
+    double ua, ub;
+    orc_uniform_pair(seed, 0, (uint32_t)k, batch, 3, &ua, &ub);
+    double target = ((double)k + ua) / (double)n * M;
+    /* largest e with cdf[e] <= target */
+    int64_t lo = 0, hi = T.n_el - 1;
+    while (lo < hi) {
+      int64_t mid = (lo + hi + 1) / 2;
+      if (T.cdf[mid] <= target) lo = mid;
+      else hi = mid - 1;
+    }
+    int64_t e = lo;
+    double r = (target - T.cdf[e]) / T.meas[e];
+    if (r < 0) r = 0;
+    if (r > 1) r = 1;
+    double* xk = x + k * d;
+    candidate_point(s, &T, e, r, ub, l, xk);
+    double dist, xb[3];
+    orc_closest(s, xk, 0, &dist, xb, NULL);
+    int ok = (dist >= l * (1 - 1e-9)) && (orc_inside(s, xk) != 0);
+    accept[k] = ok;
+    n_acc += ok;
+    R0[k] = dist;
+    w[k] = M / (double)n;
+    for (int a = 0; a < d; ++a) {
+      xbar[k * d + a] = xb[a];
+      nrm[k * d + a] = (xb[a] - xk[a]) / dist;
+    }
+  }
+  free_elements(&T);
+  return n_acc;
+}
+
+void orc_sample_sources(const orc_scene* s, const orc_field* f, int64_t m, const double* lo,
+                        const double* hi, double l, uint64_t seed, uint32_t batch, double* y,
+                        double* sw) {
+  int d = s->dim;
+  int64_t M = 1;
+  double vol = 1;
+  for (int a = 0; a < d; ++a) {
+    M *= m;
+    vol *= hi[a] - lo[a];
+  }
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t j = 0; j < M; ++j) {
+    double u[4];
+    orc_uniform_pair(seed, 0, (uint32_t)j, batch, 4, &u[0], &u[1]);
+    orc_uniform_pair(seed, 1, (uint32_t)j, batch, 4, &u[2], &u[3]);
+    int64_t rem = j;
+    double* yj = y + j * d;
+    for (int a = 0; a < d; ++a) {
+      int64_t c = rem % m;
+      rem /= m;
+      yj[a] = lo[a] + ((double)c + u[a]) / (double)m * (hi[a] - lo[a]);
+    }
+    double dist, xb[3];
+    orc_closest(s, yj, 0, &dist, xb, NULL);
+    int in = orc_inside(s, yj) != 0 && dist > l;
+    sw[j] = in ? vol / (double)M * orc_field_eval(f, d, yj) : 0.0;
+  }
+}
+
+/* ======================================================================== */
+/* Walk on spheres with the ball gradient estimator                          */
+/* ======================================================================== */
+/* Uniform direction from step k's block 4k. */
+static void walk_direction(uint64_t seed, uint32_t k, uint32_t id, uint32_t batch, uint32_t tag,
+                           int dim, double* nu) {
+  double ua, ub;
+  orc_uniform_pair(seed, 4 * k, id, batch, tag, &ua, &ub);
+  if (dim == 2) {
+    double th = 2 * ORC_PI * ua;
+    nu[0] = cos(th);
+    nu[1] = sin(th);
+  } else {
+    double z = 1 - 2 * ua;
+    double rho = sqrt(fmax(0.0, 1 - z * z));
+    double ph = 2 * ORC_PI * ub;
+    nu[0] = rho * cos(ph);
+    nu[1] = rho * sin(ph);
+    nu[2] = z;
+  }
+}
+
+/* Point of a ball B(c, R) drawn with density proportional to |G^B(c, .)|:
+ * radius fraction sqrt(U1 U2) in 2D (density 4 s ln(1/s)), median of three
+ * uniforms in 3D (density 6 s (1-s)); direction uniform.  Blocks 4k+1..4k+3. */
+static void ball_source_point(uint64_t seed, uint32_t k, uint32_t id, uint32_t batch,
+                              uint32_t tag, int dim, const double* c, double R, double* y) {
+  double u1, u2, u3, u4, u5, u6;
+  orc_uniform_pair(seed, 4 * k + 1, id, batch, tag, &u1, &u2);
+  orc_uniform_pair(seed, 4 * k + 2, id, batch, tag, &u3, &u4);
+  if (dim == 2) {
+    double s = sqrt(u1 * u2);
+    double th = 2 * ORC_PI * u3;
+    y[0] = c[0] + R * s * cos(th);
+    y[1] = c[1] + R * s * sin(th);
+  } else {
+    double lo = u1 < u2 ? u1 : u2, hi = u1 < u2 ? u2 : u1;
+    double s = u3 < lo ? lo : (u3 > hi ? hi : u3);
+    orc_uniform_pair(seed, 4 * k + 3, id, batch, tag, &u5, &u6);
+    double z = 1 - 2 * u5;
+    double rho = sqrt(fmax(0.0, 1 - z * z));
+    double ph = 2 * ORC_PI * u6;
+    y[0] = c[0] + R * s * rho * cos(ph);
+    y[1] = c[1] + R * s * rho * sin(ph);
+    y[2] = c[2] + R * s * z;
+  }
+}
+
+/* Exported views of the two samplers above, for the density tests. */
+void orc_sample_direction(uint64_t seed, uint32_t k, uint32_t id, uint32_t batch, uint32_t tag,
+                          int dim, double* nu) {
+  walk_direction(seed, k, id, batch, tag, dim, nu);
+}
+void orc_sample_ball_source(uint64_t seed, uint32_t k, uint32_t id, uint32_t batch, uint32_t tag,
+                            int dim, const double* c, double R, double* y) {
+  ball_source_point(seed, k, id, batch, tag, dim, c, R, y);
+}
+/* Radius fraction of the 2D gradient source sample: density (3/2)(1 - s^2). */
+double orc_grad_radius(double u) { return 2 * sin(asin(u) / 3); }
+
+void orc_walk(const orc_scene* s, const orc_field* g, const orc_field* f,
+              const orc_walk_params* p, int mode, const double* x, const double* n, double R0,
+              const double* xbar, uint32_t id, double* U, double* grad, double* exit_pt,
+              double* w1, int32_t* steps, int32_t* capped) {
+  int dim = s->dim;
+  uint32_t tag = mode == 0 ? 1u : 2u;
+  int has_f = f && f->kind != ORC_FIELD_ZERO;
+  *capped = 0;
+  if (mode == 1 && R0 < p->eps) {
+    /* the evaluation point already lies in the epsilon shell */
+    *U = orc_field_eval(g, dim, xbar);
+    for (int a = 0; a < dim; ++a) {
+      grad[a] = 0;
+      exit_pt[a] = xbar[a];
+    }
+    *w1 = 0;
+    *steps = 0;
+    return;
+  }
+  /* First ball B(x, R0): no termination test at x itself. */
+  double nu0[3], pos[3];
+  walk_direction(p->seed, 0, id, p->batch, tag, dim, nu0);
+  for (int a = 0; a < dim; ++a) pos[a] = x[a] + R0 * nu0[a];
+  double f_u = 0, f_g = 0, yhat_g[3] = {0, 0, 0};
+  if (has_f) {
+    double yu[3];
+    ball_source_point(p->seed, 0, id, p->batch, tag, dim, x, R0, yu);
+    f_u = orc_field_eval(f, dim, yu);
+    if (dim == 2) {
+      /* gradient source sample: radius density (3/2)(1 - s^2) */
+      double u1, u2, u3, u4;
+      orc_uniform_pair(p->seed, 2, id, p->batch, tag, &u1, &u2);
+      orc_uniform_pair(p->seed, 3, id, p->batch, tag, &u3, &u4);
+      double sg = 2 * sin(asin(u2) / 3);
+      double th = 2 * ORC_PI * u3;
+      yhat_g[0] = cos(th);
+      yhat_g[1] = sin(th);
+      double yg[2] = {x[0] + R0 * sg * yhat_g[0], x[1] + R0 * sg * yhat_g[1]};
+      f_g = orc_field_eval(f, dim, yg);
+    }
+  }
+  /* Walk on spheres from the first-ball point. */
+  double S = 0, W = 0, pb[3] = {0, 0, 0};
+  int32_t k;
+  for (k = 1;; ++k) {
+    double d;
+    orc_closest(s, pos, 0, &d, pb, NULL);
+    if (d < p->eps) {
+      W = orc_field_eval(g, dim, pb) + S;
+      break;
+    }
+    if (k >= p->max_steps) {
+      W = orc_field_eval(g, dim, pb) + S;
+      *capped = 1;
+      break;
+    }
+    if (has_f) {
+      double y[3];
+      ball_source_point(p->seed, (uint32_t)k, id, p->batch, tag, dim, pos, d, y);
+      S -= d * d / (2.0 * dim) * orc_field_eval(f, dim, y);
+    }
+    double nu[3];
+    walk_direction(p->seed, (uint32_t)k, id, p->batch, tag, dim, nu);
+    for (int a = 0; a < dim; ++a) pos[a] += d * nu[a];
+  }
+  *steps = k;
+  *U = W - R0 * R0 / (2.0 * dim) * f_u;
+  double c = p->control_variate ? orc_field_eval(g, dim, xbar) : 0.0;
+  double wn = 0;
+  for (int a = 0; a < dim; ++a) {
+    grad[a] = dim / R0 * nu0[a] * (W - c);
+    if (has_f && dim == 2) grad[a] -= 2.0 * R0 / 3.0 * yhat_g[a] * f_g;
+    exit_pt[a] = pb[a];
+    if (n) wn += nu0[a] * n[a];
+  }
+  *w1 = dim / R0 * wn;
+}
+
+void orc_cache_walks(const orc_scene* s, const orc_field* g, const orc_field* f,
+                     const orc_walk_params* p, int64_t n_cache, const double* x,
+                     const double* nrm, const double* R0, const double* xbar, double* U,
+                     double* D, double* exit_pt, double* w1, int32_t* steps) {
+  int dim = s->dim;
+  int64_t W = p->n_walks;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t i = 0; i < n_cache; ++i) {
+    for (int64_t j = 0; j < W; ++j) {
+      int64_t id = i * W + j;
+      double u, gr[3], ex[3], ww;
+      int32_t st, cap;
+      orc_walk(s, g, f, p, 0, x + i * dim, nrm + i * dim, R0[i], xbar + i * dim, (uint32_t)id, &u,
+               gr, ex, &ww, &st, &cap);
+      double dn = 0;
+      for (int a = 0; a < dim; ++a) dn += nrm[i * dim + a] * gr[a];
+      U[id] = u;
+      D[id] = dn;
+      if (exit_pt)
+        for (int a = 0; a < dim; ++a) exit_pt[id * dim + a] = ex[a];
+      if (w1) w1[id] = ww;
+      if (steps) steps[id] = st;
+    }
+  }
+}
+
+void orc_cache_walks_subset(const orc_scene* s, const orc_field* g, const orc_field* f,
+                            const orc_walk_params* p, int64_t n_ids, const int64_t* ids,
+                            const double* x, const double* nrm, const double* R0,
+                            const double* xbar, double* U, double* D, int32_t* steps) {
+  int dim = s->dim;
+  int64_t W = p->n_walks;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t q = 0; q < n_ids; ++q) {
+    int64_t id = ids[q];
+    int64_t i = id / W;
+    double u, gr[3], ex[3], ww;
+    int32_t st, cap;
+    orc_walk(s, g, f, p, 0, x + i * dim, nrm + i * dim, R0[i], xbar + i * dim, (uint32_t)id, &u, gr,
+             ex, &ww, &st, &cap);
+    double dn = 0;
+    for (int a = 0; a < dim; ++a) dn += nrm[i * dim + a] * gr[a];
+    U[q] = u;
+    D[q] = dn;
+    if (steps) steps[q] = st;
+  }
+}
+
+void orc_reduce(int64_t n_cache, int32_t W, const double* U, const double* D, double* uhat,
+                double* dudn) {
+  for (int64_t i = 0; i < n_cache; ++i) {
+    double su = 0, sd = 0;
+    for (int32_t j = 0; j < W; ++j) {
+      su += U[i * W + j];
+      sd += D[i * W + j];
+    }
+    uhat[i] = su / W;
+    dudn[i] = sd / W;
+  }
+}
+
+void orc_pointwise(const orc_scene* s, const orc_field* g, const orc_field* f,
+                   const orc_walk_params* p, int64_t n, const double* x, double* u,
+                   double* grad, int64_t* total_steps) {
+  int dim = s->dim;
+  int64_t W = p->n_walks;
+  int64_t tot = 0;
+#pragma omp parallel for schedule(dynamic, 4) reduction(+ : tot)
+  for (int64_t k = 0; k < n; ++k) {
+    double R0, xb[3];
+    orc_closest(s, x + k * dim, 0, &R0, xb, NULL);
+    double su = 0, sg[3] = {0, 0, 0};
+    for (int64_t j = 0; j < W; ++j) {
+      double uu, gr[3], ex[3], ww;
+      int32_t st, cap;
+      orc_walk(s, g, f, p, 1, x + k * dim, NULL, R0, xb, (uint32_t)(k * W + j), &uu, gr, ex, &ww,
+               &st, &cap);
+      su += uu;
+      for (int a = 0; a < dim; ++a) sg[a] += gr[a];
+      tot += st;
+    }
+    u[k] = su / W;
+    if (grad)
+      for (int a = 0; a < dim; ++a) grad[k * dim + a] = sg[a] / W;
+  }
+  if (total_steps) *total_steps = tot;
+}
+
+/* ======================================================================== */
+/* Gather: Monte Carlo estimators of the boundary integral equation          */
+/* ======================================================================== */
+void orc_gather(int dim, int64_t K, const double* ex, int64_t N, const double* cy,
+                const double* cn, const double* a, const double* b, int64_t M,
+                const double* sy, const double* sw, double* u, double* grad, double* cond) {
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t k = 0; k < K; ++k) {
+    const double* x = ex + k * dim;
+    double uk = 0, ck = 0, gk[3] = {0, 0, 0};
+    for (int64_t i = 0; i < N; ++i) {
+      double G, dGdx[3], dGdn, d2[3];
+      orc_greens(dim, x, cy + i * dim, cn + i * dim, &G, dGdx, &dGdn, d2);
+      uk += dGdn * a[i] - G * b[i];
+      ck += fabs(dGdn * a[i]) + fabs(G * b[i]);
+      for (int q = 0; q < dim; ++q) gk[q] += d2[q] * a[i] - dGdx[q] * b[i];
+    }
+    for (int64_t j = 0; j < M; ++j) {
+      double G, dGdx[3];
+      orc_greens(dim, x, sy + j * dim, NULL, &G, dGdx, NULL, NULL);
+      uk += G * sw[j];
+      ck += fabs(G * sw[j]);
+      for (int q = 0; q < dim; ++q) gk[q] += dGdx[q] * sw[j];
+    }
+    u[k] = uk;
+    if (cond) cond[k] = ck;
+    if (grad)
+      for (int q = 0; q < dim; ++q) grad[k * dim + q] = gk[q];
+  }
+}
+
+void orc_gather_backward(int dim, int64_t K, const double* ex, const double* r, int64_t N,
+                         const double* cy, const double* cn, const double* a, const double* b,
+                         int64_t M, const double* sy, const double* sw, double* dLda,
+                         double* dLdb, double* dLds, double* dLdx) {
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t i = 0; i < N; ++i) {
+    double sa = 0, sb = 0;
+    for (int64_t k = 0; k < K; ++k) {
+      double G, dGdn;
+      orc_greens(dim, ex + k * dim, cy + i * dim, cn + i * dim, &G, NULL, &dGdn, NULL);
+      sa += r[k] * dGdn;
+      sb -= r[k] * G;
+    }
+    dLda[i] = sa;
+    dLdb[i] = sb;
+  }
+  if (dLds) {
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t j = 0; j < M; ++j) {
+      double ss = 0;
+      for (int64_t k = 0; k < K; ++k) {
+        double G;
+        orc_greens(dim, ex + k * dim, sy + j * dim, NULL, &G, NULL, NULL, NULL);
+        ss += r[k] * G;
+      }
+      dLds[j] = ss;
+    }
+  }
+  if (dLdx) {
+    double* u = (double*)malloc((size_t)K * sizeof(double));
+    double* g = (double*)malloc((size_t)K * dim * sizeof(double));
+    orc_gather(dim, K, ex, N, cy, cn, a, b, M, sy, sw, u, g, NULL);
+    for (int64_t k = 0; k < K; ++k)
+      for (int q = 0; q < dim; ++q) dLdx[k * dim + q] = r[k] * g[k * dim + q];
+    free(u);
+    free(g);
+  }
+}
+
+void orc_basis_means(const orc_field* basis, int dim, int64_t n_cache, int32_t W,
+                     const double* exit_pt, const double* w1, const double* xbar, int cv,
+                     double* E, double* F) {
+  int nb = basis->n_coef;
+  if (basis->kind == ORC_FIELD_GAUSS_SUM) nb = basis->n_coef / (1 + dim);
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t i = 0; i < n_cache; ++i) {
+    for (int m = 0; m < nb; ++m) {
+      double base = cv ? orc_basis_eval(basis, dim, m, xbar + i * dim) : 0.0;
+      double se = 0, sf = 0;
+      for (int32_t j = 0; j < W; ++j) {
+        int64_t id = i * W + j;
+        double phi = orc_basis_eval(basis, dim, m, exit_pt + id * dim);
+        se += phi;
+        sf += w1[id] * (phi - base);
+      }
+      E[i * nb + m] = se / W;
+      F[i * nb + m] = sf / W;
+    }
+  }
+}
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}

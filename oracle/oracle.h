@@ -1,0 +1,184 @@
+/*
+ * Plain FP64 CPU oracle for Boundary Value Caching (BVC) with walk on spheres.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  It shares no code,
+ * header, table or helper with the HIP library; the two agree only through the
+ * problem definition (the paper) and the random-number convention below, which
+ * each side implements on its own.
+ *
+ * What is computed (paper: Miller, Sawhney, Crane, Gkioulekas, "Boundary Value
+ * Caching for Walk on Spheres", ACM TOG 42(4), 2023):
+ *   - the PDE  Lap u = f in Omega, u = g on the boundary (Eq. 1, sigma = 0,
+ *     Dirichlet only);
+ *   - the boundary integral equation (Eq. 2) and its Monte Carlo estimators
+ *     (Eqs. 3-6), with the free-space kernels of Appendix A.1;
+ *   - walk on spheres with an epsilon shell (Section 3.1), the ball-based
+ *     gradient estimator (Eq. 7) for du/dn at cache points;
+ *   - cache points on the offset Dirichlet boundary at distance l (Section 3.2)
+ *     drawn with a CDF table and stratified uniforms (Section 4, Sampling);
+ *   - Algorithm 1 (UpdateSolution): cache walks, splat of boundary and source
+ *     samples into evaluation points.
+ *
+ * Conventions (fixed readings of the paper, listed in the design notes):
+ *   G_2D = ln r / (2 pi),  G_3D = -1 / (4 pi r)   (Lap G = delta; Appendix A.1
+ *   prints +1/(4 pi r) for 3D, which contradicts its own derivative formulas).
+ *   Arrays are row-major AoS: point k of a (n, dim) array is x[k*dim + a].
+ *
+ * Random numbers: Philox-4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).
+ *   key     = (seed & 0xffffffff, seed >> 32)
+ *   counter = (block, id, batch, tag)
+ *   FP64 uniform from words (w0, w1): ((w0 << 21) | (w1 >> 11)) * 2^-53.
+ *   Each block yields two uniforms: ua from (w0, w1), ub from (w2, w3).
+ *   Walk step k uses blocks 4k + s, s = 0..3 (see orc_walk for the map).
+ *   Tags: 1 cache walk, 2 pointwise walk, 3 cache sampling, 4 source sampling.
+ */
+#ifndef BVC_ORACLE_H
+#define BVC_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Field kinds (same numbering as the problem descriptors). */
+enum {
+  ORC_FIELD_ZERO = 0,
+  ORC_FIELD_CONST = 1,
+  ORC_FIELD_HARMONIC_2D = 2,
+  ORC_FIELD_GAUSS_SUM = 3,
+  ORC_FIELD_GAUSS_POTENTIAL_2D = 4,
+  ORC_FIELD_SOLID_HARMONICS_3D = 5,
+  ORC_FIELD_FOURIER_2D = 6,
+  ORC_FIELD_POINT_SOURCE = 7
+};
+
+typedef struct {
+  int32_t kind;
+  int32_t n_coef;
+  const double* coef; /* host */
+  double param[8];
+} orc_field;
+
+typedef struct orc_scene orc_scene;
+
+/* --- Philox and uniforms ------------------------------------------------ */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+void orc_uniform_pair(uint64_t seed, uint32_t block, uint32_t id, uint32_t batch,
+                      uint32_t tag, double* ua, double* ub);
+
+/* --- Scene and closest point ------------------------------------------- */
+orc_scene* orc_scene_new(int dim, const double* verts, int64_t nv, const int32_t* prims,
+                         int64_t np);
+void orc_scene_free(orc_scene* s);
+/* Closest point on the boundary; ties broken by the smallest primitive id.
+ * brute != 0 scans every primitive, otherwise the oracle's own BVH is used. */
+void orc_closest(const orc_scene* s, const double* x, int brute, double* dist,
+                 double* xbar, int32_t* prim);
+void orc_closest_batch(const orc_scene* s, int64_t n, const double* x, int brute,
+                       double* dist, double* xbar, int32_t* prim);
+/* Inside test: 2D nonzero winding number, 3D pseudonormal sign at the closest
+ * feature.  Returns the winding number (2D) or 1/0 (3D). */
+int orc_inside(const orc_scene* s, const double* x);
+/* Classify points: 0 outside, 1 interior (d > l), 2 band (d <= l). */
+void orc_classify(const orc_scene* s, int64_t n, const double* x, double l, int32_t* cls);
+
+/* --- Fields --------------------------------------------------------------- */
+double orc_field_eval(const orc_field* fld, int dim, const double* x);
+void orc_field_eval_batch(const orc_field* fld, int dim, int64_t n, const double* x,
+                          double* out);
+/* Basis function m of an expandable field (Fourier / solid harmonics). */
+double orc_basis_eval(const orc_field* fld, int dim, int m, const double* x);
+double orc_ein(double z);
+
+/* --- Green's functions (Appendix A.1, Lap G = delta) ---------------------- */
+/* Outputs: G, dG/dx (dim), dG/dn_y, d2G/dxdn_y (dim); any pointer may be NULL. */
+void orc_greens(int dim, const double* x, const double* y, const double* ny, double* G,
+                double* dGdx, double* dGdn, double* d2Gdxdn);
+
+/* --- Cache sampling (Section 3.2 offset boundary, Section 4 CDF sampling) -- */
+/* Draws n candidates on the offset boundary at distance l; writes per
+ * candidate the point, unit outward normal of the region {d > l}, weight
+ * (total candidate measure / n), closest boundary point, distance and an
+ * accept flag.  sides: 1 = inward offsets only, 2 = both sides (2D).
+ * Returns the number accepted. */
+int64_t orc_sample_cache(const orc_scene* s, int64_t n, double l, int sides, uint64_t seed,
+                         uint32_t batch, double* x, double* nrm, double* w, double* xbar,
+                         double* R0, int32_t* accept);
+double orc_candidate_measure(const orc_scene* s, double l, int sides);
+
+/* Source cache: m*m jittered grid over [lo, hi] (2D); s_j = |box|/M f(y)
+ * 1[y in R]. */
+void orc_sample_sources(const orc_scene* s, const orc_field* f, int64_t m, const double* lo,
+                        const double* hi, double l, uint64_t seed, uint32_t batch, double* y,
+                        double* sw);
+
+/* --- Walks (Section 3.1, Eq. 7) ---------------------------------------- */
+typedef struct {
+  double eps;
+  int32_t max_steps;
+  int32_t n_walks;
+  uint64_t seed;
+  uint32_t batch;
+  int32_t control_variate; /* subtract g(xbar) in the gradient estimate */
+} orc_walk_params;
+
+/* One walk.  mode 0: cache walk (tag 1, first ball without termination test);
+ * mode 1: pointwise walk (tag 2, returns g(xbar) when R0 < eps).
+ * Outputs U (solution sample), grad (dim; gradient sample), exit point,
+ * first-step weight (dim/R0)*(nu . n) (cache mode), steps, capped flag. */
+void orc_walk(const orc_scene* s, const orc_field* g, const orc_field* f,
+              const orc_walk_params* p, int mode, const double* x, const double* n, double R0,
+              const double* xbar, uint32_t id, double* U, double* grad, double* exit_pt,
+              double* w1, int32_t* steps, int32_t* capped);
+
+void orc_sample_direction(uint64_t seed, uint32_t k, uint32_t id, uint32_t batch, uint32_t tag,
+                          int dim, double* nu);
+void orc_sample_ball_source(uint64_t seed, uint32_t k, uint32_t id, uint32_t batch, uint32_t tag,
+                            int dim, const double* c, double R, double* y);
+double orc_grad_radius(double u);
+
+/* All walks of n_cache cache points: U[i*W + j], D[i*W + j] = n_i . grad. */
+void orc_cache_walks(const orc_scene* s, const orc_field* g, const orc_field* f,
+                     const orc_walk_params* p, int64_t n_cache, const double* x,
+                     const double* nrm, const double* R0, const double* xbar, double* U,
+                     double* D, double* exit_pt, double* w1, int32_t* steps);
+/* Selected walks only (global walk ids). */
+void orc_cache_walks_subset(const orc_scene* s, const orc_field* g, const orc_field* f,
+                            const orc_walk_params* p, int64_t n_ids, const int64_t* ids,
+                            const double* x, const double* nrm, const double* R0,
+                            const double* xbar, double* U, double* D, int32_t* steps);
+/* Means over walks (in index order): uhat_i, dudn_i. */
+void orc_reduce(int64_t n_cache, int32_t W, const double* U, const double* D, double* uhat,
+                double* dudn);
+/* Pointwise WoS means at n points (W walks each; u and optional gradient). */
+void orc_pointwise(const orc_scene* s, const orc_field* g, const orc_field* f,
+                   const orc_walk_params* p, int64_t n, const double* x, double* u,
+                   double* grad, int64_t* total_steps);
+
+/* --- Gather (Eqs. 3-6) ------------------------------------------------- */
+/* u_k = sum_i [dG/dn(x_k,y_i) a_i - G(x_k,y_i) b_i] + sum_j G(x_k,z_j) s_j,
+ * grad_k likewise with the x-derivatives.  cond (optional) = sum of |terms|. */
+void orc_gather(int dim, int64_t K, const double* ex, int64_t N, const double* cy,
+                const double* cn, const double* a, const double* b, int64_t M,
+                const double* sy, const double* sw, double* u, double* grad, double* cond);
+/* Transposed gather: given r_k = dL/du_k: dL/da_i, dL/db_i, dL/ds_j, and
+ * dL/dx_k = r_k grad u(x_k). */
+void orc_gather_backward(int dim, int64_t K, const double* ex, const double* r, int64_t N,
+                         const double* cy, const double* cn, const double* a, const double* b,
+                         int64_t M, const double* sy, const double* sw, double* dLda,
+                         double* dLdb, double* dLds, double* dLdx);
+
+/* --- Basis expansion from exit records (linearity in the boundary data) --- */
+/* E[i*nb + m] = (1/W) sum_j phi_m(exit_ij),
+ * F[i*nb + m] = (1/W) sum_j w1_ij (phi_m(exit_ij) - cv * phi_m(xbar_i)). */
+void orc_basis_means(const orc_field* basis, int dim, int64_t n_cache, int32_t W,
+                     const double* exit_pt, const double* w1, const double* xbar, int cv,
+                     double* E, double* F);
+
+int orc_num_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
