@@ -1,0 +1,310 @@
+/*
+ * bvc.h - C-ABI of the MI355X (gfx950) library for Boundary Value Caching
+ * with walk on spheres.
+ *
+ * Method: Miller, Sawhney, Crane, Gkioulekas, "Boundary Value Caching for Walk
+ * on Spheres", ACM TOG 42(4), 2023.  The library implements, for the PDE
+ * Lap u = f with Dirichlet data u = g (Eq. 1 with sigma = 0):
+ *   - cache points on the offset Dirichlet boundary (Section 3.2) drawn with a
+ *     CDF table and stratified uniforms (Section 4, "Sampling");
+ *   - walk on spheres from each cache point with the ball gradient estimator
+ *     (Section 3.1, Eq. 7) for u-hat and du/dn-hat;
+ *   - the Monte Carlo boundary-integral gather of Eqs. 3-6 at evaluation
+ *     points (Algorithm 1, UpdateSolution), with its adjoint;
+ *   - pointwise walk on spheres for evaluation points within l of the
+ *     boundary (Section 3.2).
+ *
+ * Conventions shared by every entry point
+ *   - Status: every function returns 0 (BVC_OK) or a negative BVC_E* code;
+ *     bvc_last_error() returns a thread-local message.  Arguments are checked
+ *     before any work is enqueued; device faults surface at the next
+ *     synchronisation.
+ *   - Streams: `stream` is a hipStream_t (NULL = default stream).  Work is
+ *     enqueued and the call returns, except where a function says it
+ *     synchronises (the ones that return a count to the host).
+ *   - Memory: the caller owns all device memory and passes device pointers;
+ *     the library allocates no device memory.  A scene keeps host memory only
+ *     and is copied into a caller-provided device buffer by bvc_scene_upload.
+ *   - Layout: point sets are structure-of-arrays, [dim][n] contiguous
+ *     (coordinate a of point k at x[a*n + k]).
+ *   - dtype: BVC_F32 or BVC_F64 selects the arithmetic of a call; arrays
+ *     typed `void*` hold that type.  Arrays typed `double*` are always FP64.
+ *   - Kernels: G_2D = ln r/(2 pi), G_3D = -1/(4 pi r) (Lap G = delta; the
+ *     sign of G_3D printed in Appendix A.1 is inconsistent with its own
+ *     derivatives and Eq. 2), dG/dn_y, dG/dx, d2G/dx dn_y as in Appendix A.1.
+ *   - Random numbers: Philox-4x32-10 (Salmon et al., SC'11) with key = seed
+ *     and counter = (block, id, batch, tag); walk step k draws blocks
+ *     4k..4k+3; tags 1 cache walk, 2 pointwise walk, 3 cache sampling,
+ *     4 source sampling.  Results depend only on (seed, batch, id), never on
+ *     the launch shape or schedule.
+ */
+#ifndef BVC_H
+#define BVC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BVC_OK 0
+#define BVC_EINVAL (-1)      /* invalid argument (null, size, dtype, geometry) */
+#define BVC_ENOMEM (-2)      /* host allocation failed */
+#define BVC_EDEVICE (-3)     /* HIP runtime error */
+#define BVC_EUNSUPPORTED (-4) /* valid but not implemented combination */
+#define BVC_ESTATE (-5)      /* object used in the wrong state (e.g. not uploaded) */
+
+#define BVC_F32 0
+#define BVC_F64 1
+#define BVC_SPLIT_BF16 2 /* bvc_gather_multi only */
+
+/* Field kinds.  A field is boundary data g or a source f given as a built-in
+ * parametric family (the paper's callbacks, Section 4 "Setup", cannot cross
+ * to the device).  coef is a DEVICE pointer to n_coef doubles.
+ *   0 ZERO, 1 CONST param[0],
+ *   2 HARMONIC_2D  param[1] Re((x+iy)^k) + param[2] e^x cos y, k = param[0]
+ *   3 GAUSS_SUM    sum_k A_k exp(-|x-c_k|^2/(2 s^2)), s = param[0],
+ *                  coef = [A_0, c_0(dim), A_1, c_1(dim), ...]
+ *   4 GAUSS_POTENTIAL_2D sum_k A_k s^2/2 Ein(|x-c_k|^2/(2 s^2)) + HARMONIC_2D
+ *                  with (k, alpha, beta) = param[1..3]; Lap of it = GAUSS_SUM
+ *   5 SOLID_HARMONICS_3D sum coef[l^2+l+m] r^l Y_lm (orthonormal real, no
+ *                  Condon-Shortley phase), l <= L = param[0]
+ *   6 FOURIER_2D   sum_m coef[m] phi_m(theta), theta = atan2(y-param[1],
+ *                  x-param[0]); phi_0 = 1, phi_{2j-1} = cos j theta,
+ *                  phi_{2j} = sin j theta
+ *   7 POINT_SOURCE 2D A ln|x-x0|, 3D A/|x-x0|, A = param[0], x0 = param[1..]
+ */
+typedef struct {
+  int32_t kind;
+  int32_t n_coef;
+  const double* coef;
+  double param[8];
+} bvc_field;
+
+typedef struct bvc_scene_s* bvc_scene;
+
+typedef struct {
+  int32_t dim;
+  int64_t n_verts, n_prims, n_edges;
+  int64_t n_nodes;        /* internal BVH nodes */
+  int32_t depth;          /* deepest internal level (root = 1) */
+  double lo[3], hi[3];    /* bounding box */
+  double diagonal;        /* |hi - lo| */
+  double boundary_measure; /* total length (2D) or area (3D) */
+  size_t device_bytes;    /* size of the buffer bvc_scene_upload needs */
+  int32_t uploaded;
+} bvc_scene_info;
+
+/* ---------------------------------------------------------------------- */
+/* Scene and BVH (Section 4 "Setup": polygonal boundary and an AABB BVH    */
+/* for closest-point queries)                                              */
+/* ---------------------------------------------------------------------- */
+/* Builds the BVH on the host.  verts: host (n_verts, dim) row-major FP64;
+ * prims: host (n_prims, dim) int32 vertex indices (2D segments oriented with
+ * the domain on the left, i.e. counter-clockwise outer boundary; 3D
+ * triangles with outward normals by the right-hand rule).  Rejects NaN or
+ * infinite vertices, out-of-range indices and zero-length segments or
+ * zero-area triangles.  The returned handle owns host memory only. */
+int bvc_scene_create(int32_t dim, const double* verts, int64_t n_verts, const int32_t* prims,
+                     int64_t n_prims, bvc_scene* out);
+int bvc_scene_get_info(bvc_scene scene, bvc_scene_info* out);
+/* Copies the scene (FP64 and FP32 BVH, primitives, sampling tables) into a
+ * caller-owned device buffer of at least info.device_bytes bytes, 256-byte
+ * aligned.  The buffer must outlive every call that uses the scene.
+ * Synchronises the stream (the host staging copy is freed on return). */
+int bvc_scene_upload(bvc_scene scene, void* device_buffer, size_t bytes, void* stream);
+int bvc_scene_destroy(bvc_scene scene);
+
+/* Total measure of the offset-boundary candidate set at offset l: segment
+ * lengths (times `sides`) plus vertex circles (2D); face areas plus edge
+ * cylinders plus vertex spheres (3D).  Host-only. */
+int bvc_cache_measure(bvc_scene scene, double l, int32_t sides, double* measure);
+
+/* ---------------------------------------------------------------------- */
+/* Cache points on the offset Dirichlet boundary (Section 3.2; Section 4)   */
+/* ---------------------------------------------------------------------- */
+/* Draws n candidates: stratified uniforms u_k = (k + U_k)/n through the CDF
+ * of the candidate measure (inward segment/face offsets at distance l,
+ * vertex circles or spheres, edge cylinders; sides = 2 adds outward
+ * segment offsets in 2D for self-intersecting polygons).  A candidate is
+ * accepted when no boundary point is closer than l (up to 1e-9 relative)
+ * and it lies inside (2D: nonzero winding number; 3D: pseudonormal sign).
+ * Outputs (FP64 device, [dim][n] or [n]): x, unit outward normal of the
+ * region {d > l} (towards the closest boundary point), weight w = measure/n,
+ * closest boundary point xbar, distance R0, accept flag (int32 0/1). */
+int bvc_sample_cache(bvc_scene scene, int64_t n, double l, int32_t sides, uint64_t seed,
+                     uint32_t batch, double* x, double* nrm, double* w, double* xbar, double* R0,
+                     int32_t* accept, void* stream);
+
+/* Source samples (Eq. 4): m^dim jittered cells over the box [lo, hi] (host
+ * arrays of dim doubles); s_j = |box|/m^dim * f(y_j) * 1[y_j inside and
+ * d(y_j) > l].  y: [dim][m^dim] FP64 device, s: [m^dim] FP64 device. */
+int bvc_sample_sources(bvc_scene scene, const bvc_field* f, int64_t m, const double* lo,
+                       const double* hi, double l, uint64_t seed, uint32_t batch, double* y,
+                       double* s, void* stream);
+
+/* Classifies points x ([dim][n] FP64 device): cls = 0 outside, 1 interior
+ * (d > l, evaluated by the gather), 2 band (d <= l, evaluated by pointwise
+ * walks, Section 3.2).  dist (optional) receives d(x). */
+int bvc_classify(bvc_scene scene, int64_t n, const double* x, double l, int32_t* cls,
+                 double* dist, void* stream);
+
+/* Deterministic stream compaction: idx[0..count) = ascending k with
+ * flags[k] == want.  scratch: caller-owned device int32 array of at least
+ * bvc_compact_scratch_ints(n) entries, 8-byte aligned.  count is written to
+ * *count_host; synchronises the stream. */
+int64_t bvc_compact_scratch_ints(int64_t n);
+int bvc_compact(int64_t n, const int32_t* flags, int32_t want, int32_t* idx, int32_t* scratch,
+                int64_t* count_host, void* stream);
+/* out[r*ld_out + q] = (dtype_out) in[r*ld_in + idx[q]] for r < rows, q < n_idx
+ * (idx NULL = identity).  Used to pack compacted SoA arrays and convert
+ * FP64 -> FP32. */
+int bvc_take(int32_t dtype_in, int32_t dtype_out, int64_t n_idx, const int32_t* idx,
+             int32_t rows, int64_t ld_in, const void* in, int64_t ld_out, void* out, void* stream);
+/* out[idx[q]] = in[q] (scatter back; dtype of in and out equal). */
+int bvc_scatter(int32_t dtype, int64_t n_idx, const int32_t* idx, int32_t rows, int64_t ld_in,
+                const void* in, int64_t ld_out, void* out, void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Walks (Section 3.1, Eq. 7; Algorithm 1 "WalkOnStars" for Dirichlet data) */
+/* ---------------------------------------------------------------------- */
+typedef struct {
+  double eps;              /* epsilon shell: stop when d < eps */
+  int32_t max_steps;       /* cap on closest-point queries per walk */
+  int32_t n_walks;         /* walks per start point */
+  uint64_t seed;
+  uint32_t batch;
+  int32_t control_variate; /* subtract g(xbar) in the gradient sample */
+  int32_t dtype;           /* BVC_F32 or BVC_F64 walk arithmetic */
+  int32_t blocks;          /* persistent grid size (0 = automatic) */
+  bvc_field g;             /* Dirichlet data */
+  bvc_field f;             /* source term (kind 0 for Laplace) */
+} bvc_walk_params;
+
+/* Walk j of cache point i has id i*W + j (n_cache*W < 2^32).  Each walk takes
+ * a first ball B(x_i, R0_i) with no termination test (uniform direction nu;
+ * source sample with density |G^B|), then walk on spheres until d < eps (or
+ * max_steps queries, counted as capped), reading g at the closest point.
+ * U[id]  = g(exit) + in-walk source sums - R0^2/(2 dim) f(y_u)
+ * D[id]  = n_i . [(dim/R0) nu (W - c_i) - (2 R0/3) y_g f(y_g)]  (2D source term)
+ * Inputs x, nrm, xbar: [dim][n_cache] FP64; R0: [n_cache] FP64 (from
+ * bvc_sample_cache after compaction).  U, D: [n_cache*W] of params->dtype.
+ * Optional exit records (any may be NULL): rec_exit [dim][n_cache*W] of
+ * dtype (closest point where the walk stopped), rec_w1 [n_cache*W]
+ * ((dim/R0)(nu . n_i)), rec_steps int32.  counters: device uint64[4],
+ * zeroed by the call: [0] work queue, [1] total closest-point queries,
+ * [2] capped walks, [3] walks. */
+int bvc_cache_walks(bvc_scene scene, const bvc_walk_params* params, int64_t n_cache,
+                    const double* x, const double* nrm, const double* R0, const double* xbar,
+                    void* U, void* D, void* rec_exit, void* rec_w1, int32_t* rec_steps,
+                    uint64_t* counters, void* stream);
+
+/* Means over the W walks of each cache point, reduced in FP64 in a fixed
+ * order (Eq. 3 needs u-hat and du/dn-hat): uhat, dudn [n] FP64; a = uhat*w,
+ * b = dudn*w in `dtype_out` (the gather's cache values). */
+int bvc_reduce_walks(int64_t n_cache, int32_t W, int32_t dtype_in, const void* U, const void* D,
+                     const double* w, double* uhat, double* dudn, int32_t dtype_out, void* a,
+                     void* b, void* stream);
+
+/* Pointwise walk on spheres at n points x ([dim][n] of params->dtype): the
+ * estimator the paper uses within l of the boundary (Section 3.2) and the
+ * baseline the cache is compared against.  Walk j of point k has id k*W + j
+ * (tag 2); a point already inside the epsilon shell returns g(xbar).
+ * U_walk [n*W] and G_walk [dim][n*W] (optional) are per-walk scratch of
+ * dtype; u [n] and grad [dim][n] (optional) receive the means. */
+int bvc_pointwise_wos(bvc_scene scene, const bvc_walk_params* params, int64_t n, const void* x,
+                      void* U_walk, void* G_walk, void* u, void* grad, uint64_t* counters,
+                      void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Gather (Eqs. 3-6; Algorithm 1 splat loops)                              */
+/* ---------------------------------------------------------------------- */
+typedef struct {
+  int64_t n;
+  int32_t dtype;
+  const void* x;   /* [dim][n] cache points z_i */
+  const void* nrm; /* [dim][n] unit outward normals */
+  const void* a;   /* [n] u-hat_i / p(z_i) / N */
+  const void* b;   /* [n] du/dn-hat_i / p(z_i) / N */
+} bvc_cache_view;
+
+typedef struct {
+  int64_t n;
+  int32_t dtype;
+  const void* y; /* [dim][n] source points */
+  const void* s; /* [n] f(y_j) / p(y_j) / M */
+} bvc_source_view;
+
+typedef struct {
+  int32_t accumulate; /* add into u/grad instead of overwriting */
+  double near_tau;    /* FP32 only: pairs with |x - z| < tau use FP64 (0 = off) */
+  const double* near_x;  /* FP64 copies for the near field: eval [dim][n_eval] */
+  const double* near_cx; /* cache points [dim][n] */
+  const double* near_cn; /* cache normals [dim][n] */
+  const double* near_a;  /* cache a [n] */
+  const double* near_b;  /* cache b [n] */
+} bvc_gather_params;
+
+/* u_k = sum_i [dG/dn(x_k,z_i) a_i - G(x_k,z_i) b_i] + sum_j G(x_k,y_j) s_j
+ * (Eqs. 3-4).  eval_x [dim][n_eval]; u [n_eval]; dtype of cache, sources,
+ * eval points and u must agree.  sources may be NULL. */
+int bvc_gather_u(int32_t dim, const bvc_cache_view* cache, const bvc_source_view* sources,
+                 int64_t n_eval, const void* eval_x, void* u, const bvc_gather_params* params,
+                 void* stream);
+/* grad_k = sum_i [d2G/dxdn a_i - dG/dx b_i] + sum_j dG/dx s_j (Eqs. 5-6) into
+ * grad [dim][n_eval]; u (optional, may be NULL) receives Eqs. 3-4 from the
+ * same pass. */
+int bvc_gather_grad(int32_t dim, const bvc_cache_view* cache, const bvc_source_view* sources,
+                    int64_t n_eval, const void* eval_x, void* u, void* grad,
+                    const bvc_gather_params* params, void* stream);
+
+/* Adjoint of the gather for dL/du = r [n_eval]:
+ * dL/da_i = sum_k r_k dG/dn(x_k,z_i), dL/db_i = -sum_k r_k G(x_k,z_i),
+ * dL/ds_j = sum_k r_k G(x_k,y_j), dL/dx_k = r_k grad u(x_k) (Eq. 5-6).
+ * Any output may be NULL. */
+int bvc_gather_backward(int32_t dim, const bvc_cache_view* cache,
+                        const bvc_source_view* sources, int64_t n_eval, const void* eval_x,
+                        const void* dL_du, void* dL_da, void* dL_db, void* dL_ds, void* dL_dx,
+                        void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Linearity in the boundary data: basis expansions from exit records       */
+/* ---------------------------------------------------------------------- */
+/* For an expandable field family (FOURIER_2D, SOLID_HARMONICS_3D; the
+ * coefficients of `basis` are ignored, n_coef sets the basis size nb):
+ * E[i*nb+m] = (1/W) sum_j phi_m(exit_ij),
+ * F[i*nb+m] = (1/W) sum_j w1_ij (phi_m(exit_ij) - cv phi_m(xbar_i)),
+ * so that u-hat = E theta and du/dn-hat = F theta for g = sum theta_m phi_m.
+ * rec_exit, rec_w1 as written by bvc_cache_walks (dtype); E, F FP64. */
+int bvc_basis_means(const bvc_field* basis, int32_t dim, int64_t n_cache, int32_t W,
+                    int32_t dtype, const void* rec_exit, const void* rec_w1, const double* xbar,
+                    int32_t cv, double* E, double* F, void* stream);
+/* Cache adjoint: dL/dtheta_m = sum_i w_i (E_im dL/da_i + F_im dL/db_i)
+ * (dL_da, dL_db FP64 [n]; dL_dtheta FP64 [nb]), summed in a fixed order over
+ * chunks of 1024 cache points.  scratch: caller-owned FP64 device array of
+ * bvc_cache_backward_scratch_doubles(n_cache, nb) entries. */
+int64_t bvc_cache_backward_scratch_doubles(int64_t n_cache, int32_t nb);
+int bvc_cache_backward(int64_t n_cache, int32_t nb, const double* E, const double* F,
+                       const double* w, const double* dL_da, const double* dL_db,
+                       double* scratch, double* dL_dtheta, void* stream);
+/* Many fields sharing one set of walks: A[i*F+f] = w_i sum_m E_im coef[f*nb+m],
+ * B likewise with F (coef FP64 device [n_fields][nb]); A, B of dtype_out. */
+int bvc_eval_fields(int64_t n_cache, int32_t nb, int32_t n_fields, const double* E,
+                    const double* F, const double* w, const double* coef, int32_t dtype_out,
+                    void* A, void* B, void* stream);
+/* Multi-RHS gather: U[k*F+f] = sum_i [dG/dn(x_k,z_i) A[i*F+f] - G(x_k,z_i) B[i*F+f]]
+ * with the kernel matrix generated on the fly.  FP32 inputs; precision
+ * BVC_F32 (FP32 FMA) or BVC_SPLIT_BF16 (three bf16 MFMA products with FP32
+ * accumulation).  n_fields must be a multiple of 32. */
+int bvc_gather_multi(int32_t dim, int64_t n_cache, const float* cx, const float* cn,
+                     int32_t n_fields, const float* A, const float* B, int64_t n_eval,
+                     const float* eval_x, float* U, int32_t precision, void* stream);
+
+const char* bvc_last_error(void);
+const char* bvc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

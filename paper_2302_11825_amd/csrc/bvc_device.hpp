@@ -1,0 +1,595 @@
+// Device building blocks: counter-based random numbers, samplers, closest
+// points, BVH traversal, inside tests and the built-in boundary-data fields.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "bvc_internal.hpp"
+
+namespace bvc {
+
+// ---------------------------------------------------------------------------
+// Philox-4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds, each two
+// 32x32 -> 64-bit products whose halves are xored with the other counter
+// words and the round key; the key advances by the Weyl constants.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo_a = 0xD2511F53u * c.x;
+    const uint32_t hi_a = __umulhi(0xD2511F53u, c.x);
+    const uint32_t lo_b = 0xCD9E8D57u * c.z;
+    const uint32_t hi_b = __umulhi(0xCD9E8D57u, c.z);
+    c = make_uint4(hi_b ^ c.y ^ k0, lo_b, hi_a ^ c.w ^ k1, lo_a);
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+
+// Two uniforms in [0, 1) from the block (block, id, batch, tag): FP64 takes 53
+// bits from two words, FP32 the top 24 bits of one word.
+template <typename T>
+struct Uniform;
+template <>
+struct Uniform<double> {
+  __device__ static void pair(uint64_t seed, uint32_t block, uint32_t id, uint32_t batch,
+                              uint32_t tag, double& a, double& b) {
+    uint4 w = philox4x32_10(make_uint4(block, id, batch, tag), (uint32_t)seed, (uint32_t)(seed >> 32));
+    a = (double)(((uint64_t)w.x << 21) | (w.y >> 11)) * 0x1.0p-53;
+    b = (double)(((uint64_t)w.z << 21) | (w.w >> 11)) * 0x1.0p-53;
+  }
+};
+template <>
+struct Uniform<float> {
+  __device__ static void pair(uint64_t seed, uint32_t block, uint32_t id, uint32_t batch,
+                              uint32_t tag, float& a, float& b) {
+    uint4 w = philox4x32_10(make_uint4(block, id, batch, tag), (uint32_t)seed, (uint32_t)(seed >> 32));
+    a = (float)(w.x >> 8) * 0x1.0p-24f;
+    b = (float)(w.z >> 8) * 0x1.0p-24f;
+  }
+};
+
+__device__ __forceinline__ void sincos_turns(float t, float* s, float* c) { sincospif(2.0f * t, s, c); }
+__device__ __forceinline__ void sincos_turns(double t, double* s, double* c) { sincospi(2.0 * t, s, c); }
+
+template <typename T>
+__device__ __forceinline__ T fsqrt(T x) { return sqrt(x); }
+template <>
+__device__ __forceinline__ float fsqrt<float>(float x) { return __builtin_sqrtf(x); }
+
+template <typename T>
+__device__ __forceinline__ T fdiv(T a, T b) { return a / b; }
+template <>
+__device__ __forceinline__ float fdiv<float>(float a, float b) { return __fdividef(a, b); }
+
+// Uniform direction on the unit circle / sphere from block 4k.
+template <typename T, int D>
+__device__ __forceinline__ void walk_direction(uint64_t seed, uint32_t k, uint32_t id, uint32_t batch,
+                                               uint32_t tag, T* nu) {
+  T ua, ub;
+  Uniform<T>::pair(seed, 4u * k, id, batch, tag, ua, ub);
+  if constexpr (D == 2) {
+    sincos_turns(ua, &nu[1], &nu[0]);
+  } else {
+    T z = T(1) - T(2) * ua;
+    T rho = fsqrt(fmax(T(0), T(1) - z * z));
+    T s, c;
+    sincos_turns(ub, &s, &c);
+    nu[0] = rho * c;
+    nu[1] = rho * s;
+    nu[2] = z;
+  }
+}
+
+// Point of B(c, R) with density proportional to |G^B(c, .)| (blocks 4k+1..3):
+// radius fraction sqrt(U1 U2) in 2D, median of three uniforms in 3D.
+template <typename T, int D>
+__device__ __forceinline__ void ball_source_point(uint64_t seed, uint32_t k, uint32_t id, uint32_t batch,
+                                                  uint32_t tag, const T* c, T R, T* y) {
+  T u1, u2, u3, u4;
+  Uniform<T>::pair(seed, 4u * k + 1u, id, batch, tag, u1, u2);
+  Uniform<T>::pair(seed, 4u * k + 2u, id, batch, tag, u3, u4);
+  if constexpr (D == 2) {
+    T s = fsqrt(u1 * u2);
+    T sn, cs;
+    sincos_turns(u3, &sn, &cs);
+    y[0] = c[0] + R * s * cs;
+    y[1] = c[1] + R * s * sn;
+  } else {
+    T s = fmax(fmin(u1, u2), fmin(fmax(u1, u2), u3));
+    T u5, u6;
+    Uniform<T>::pair(seed, 4u * k + 3u, id, batch, tag, u5, u6);
+    T z = T(1) - T(2) * u5;
+    T rho = fsqrt(fmax(T(0), T(1) - z * z));
+    T sn, cs;
+    sincos_turns(u6, &sn, &cs);
+    y[0] = c[0] + R * s * rho * cs;
+    y[1] = c[1] + R * s * rho * sn;
+    y[2] = c[2] + R * s * z;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Closest points
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T segment_d2(const T* p, T ax, T ay, T bx, T by, T& cx, T& cy) {
+  const T ex = bx - ax, ey = by - ay;
+  const T t = fdiv((p[0] - ax) * ex + (p[1] - ay) * ey, ex * ex + ey * ey);
+  if (t <= T(0)) {
+    cx = ax;
+    cy = ay;
+  } else if (t >= T(1)) {
+    cx = bx;
+    cy = by;
+  } else {
+    cx = ax + t * ex;
+    cy = ay + t * ey;
+  }
+  const T dx = p[0] - cx, dy = p[1] - cy;
+  return dx * dx + dy * dy;
+}
+
+// Closest point of a triangle by Voronoi regions of its vertices, edges and
+// face (Ericson, Real-Time Collision Detection, Sec. 5.1.5).  region: 0 face,
+// 1/2/3 vertex a/b/c, 4/5/6 edge ab/bc/ca.
+template <typename T>
+__device__ __forceinline__ T triangle_d2(const T* p, const T* a, const T* b, const T* c, T* q, int& region) {
+  T ab[3], ac[3], ap[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    ab[i] = b[i] - a[i];
+    ac[i] = c[i] - a[i];
+    ap[i] = p[i] - a[i];
+  }
+  const T d1 = ab[0] * ap[0] + ab[1] * ap[1] + ab[2] * ap[2];
+  const T d2 = ac[0] * ap[0] + ac[1] * ap[1] + ac[2] * ap[2];
+  // dot products of ab and ac with p - b and p - c, from the ones above
+  const T abab = ab[0] * ab[0] + ab[1] * ab[1] + ab[2] * ab[2];
+  const T abac = ab[0] * ac[0] + ab[1] * ac[1] + ab[2] * ac[2];
+  const T acac = ac[0] * ac[0] + ac[1] * ac[1] + ac[2] * ac[2];
+  const T d3 = d1 - abab, d4 = d2 - abac;  // (p-b).ab, (p-b).ac
+  const T d5 = d1 - abac, d6 = d2 - acac;  // (p-c).ab, (p-c).ac
+  const T vc = d1 * d4 - d3 * d2;
+  const T vb = d5 * d2 - d1 * d6;
+  const T va = d3 * d6 - d5 * d4;
+  T u, v;  // q = a + u ab + v ac
+  if (d1 <= T(0) && d2 <= T(0)) {
+    region = 1;
+    u = 0;
+    v = 0;
+  } else if (d3 >= T(0) && d4 <= d3) {
+    region = 2;
+    u = 1;
+    v = 0;
+  } else if (vc <= T(0) && d1 >= T(0) && d3 <= T(0)) {
+    region = 4;
+    u = fdiv(d1, d1 - d3);
+    v = 0;
+  } else if (d6 >= T(0) && d5 <= d6) {
+    region = 3;
+    u = 0;
+    v = 1;
+  } else if (vb <= T(0) && d2 >= T(0) && d6 <= T(0)) {
+    region = 6;
+    u = 0;
+    v = fdiv(d2, d2 - d6);
+  } else if (va <= T(0) && (d4 - d3) >= T(0) && (d5 - d6) >= T(0)) {
+    region = 5;
+    const T w = fdiv(d4 - d3, (d4 - d3) + (d5 - d6));
+    u = T(1) - w;
+    v = w;
+  } else {
+    region = 0;
+    const T den = T(1) / (va + vb + vc);
+    u = vb * den;
+    v = vc * den;
+  }
+  // vertices are returned exactly when the projection clamps to them
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    T qi = a[i] + u * ab[i] + v * ac[i];
+    if (region == 1) qi = a[i];
+    if (region == 2) qi = b[i];
+    if (region == 3) qi = c[i];
+    if (region == 5) qi = b[i] + v * (c[i] - b[i]);
+    q[i] = qi;
+  }
+  const T dx = p[0] - q[0], dy = p[1] - q[1], dz = p[2] - q[2];
+  return dx * dx + dy * dy + dz * dz;
+}
+
+template <typename T, int D>
+__device__ __forceinline__ T box_d2(const T* lo, const T* hi, const T* p) {
+  T d2 = T(0);
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const T e = fmax(fmax(lo[a] - p[a], p[a] - hi[a]), T(0));
+    d2 += e * e;
+  }
+  return d2;
+}
+
+template <typename T>
+struct SceneArrays;
+template <>
+struct SceneArrays<float> {
+  __device__ static const float* box(const SceneDev& s) { return s.box32; }
+  __device__ static const float* prim(const SceneDev& s) { return s.prim32; }
+};
+template <>
+struct SceneArrays<double> {
+  __device__ static const double* box(const SceneDev& s) { return s.box64; }
+  __device__ static const double* prim(const SceneDev& s) { return s.prim64; }
+};
+
+// Distance^2 and closest point of leaf-ordered primitive i.
+template <typename T, int D>
+__device__ __forceinline__ T prim_d2(const SceneDev& S, int i, const T* p, T* q, int& region) {
+  const T* pr = SceneArrays<T>::prim(S);
+  if constexpr (D == 2) {
+    region = 0;
+    if constexpr (sizeof(T) == 4) {
+      const float4 r = reinterpret_cast<const float4*>(pr)[i];
+      return segment_d2<T>(p, r.x, r.y, r.z, r.w, q[0], q[1]);
+    } else {
+      const double2 r0 = reinterpret_cast<const double2*>(pr)[2 * i];
+      const double2 r1 = reinterpret_cast<const double2*>(pr)[2 * i + 1];
+      return segment_d2<T>(p, r0.x, r0.y, r1.x, r1.y, q[0], q[1]);
+    }
+  } else {
+    T v[9];
+    if constexpr (sizeof(T) == 4) {
+      const float4* r = reinterpret_cast<const float4*>(pr) + 3 * i;
+      const float4 r0 = r[0], r1 = r[1], r2 = r[2];
+      v[0] = r0.x; v[1] = r0.y; v[2] = r0.z; v[3] = r0.w;
+      v[4] = r1.x; v[5] = r1.y; v[6] = r1.z; v[7] = r1.w;
+      v[8] = r2.x;
+    } else {
+      const double2* r = reinterpret_cast<const double2*>(pr) + 6 * i;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const double2 w = r[j];
+        v[2 * j] = w.x;
+        v[2 * j + 1] = w.y;
+      }
+      v[8] = r[4].x;
+    }
+    return triangle_d2<T>(p, v, v + 3, v + 6, q, region);
+  }
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void load_child_boxes(const SceneDev& S, int node, T* lo0, T* hi0, T* lo1, T* hi1) {
+  const T* b = SceneArrays<T>::box(S) + (size_t)node * (4 * D);
+  if constexpr (sizeof(T) == 4 && D == 2) {
+    const float4 u = reinterpret_cast<const float4*>(b)[0];
+    const float4 w = reinterpret_cast<const float4*>(b)[1];
+    lo0[0] = u.x; lo0[1] = u.y; hi0[0] = u.z; hi0[1] = u.w;
+    lo1[0] = w.x; lo1[1] = w.y; hi1[0] = w.z; hi1[1] = w.w;
+  } else if constexpr (sizeof(T) == 4 && D == 3) {
+    const float4 u = reinterpret_cast<const float4*>(b)[0];
+    const float4 v = reinterpret_cast<const float4*>(b)[1];
+    const float4 w = reinterpret_cast<const float4*>(b)[2];
+    lo0[0] = u.x; lo0[1] = u.y; lo0[2] = u.z; hi0[0] = u.w; hi0[1] = v.x; hi0[2] = v.y;
+    lo1[0] = v.z; lo1[1] = v.w; lo1[2] = w.x; hi1[0] = w.y; hi1[1] = w.z; hi1[2] = w.w;
+  } else {
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      lo0[a] = b[a];
+      hi0[a] = b[D + a];
+      lo1[a] = b[2 * D + a];
+      hi1[a] = b[3 * D + a];
+    }
+  }
+}
+
+__device__ __forceinline__ float lower_bound_f32(float d) { return d; }
+__device__ __forceinline__ float lower_bound_f32(double d) { return __double2float_rd(d); }
+
+// Nearest-first closest-point query over the BVH with the traversal stack in
+// LDS (entry: node, box distance^2 rounded down to FP32).  best/bi/bq carry
+// an initial candidate (bi < 0: none); the result is the minimum of
+// (distance^2, original primitive id).
+template <typename T, int D>
+__device__ __forceinline__ void bvh_closest(const SceneDev& S, const T* p, T& best, int& bi, T* bq,
+                                            uint2* stk, int stride) {
+  auto consider = [&](int leaf) {
+    const int s0 = leaf_start(leaf), n = leaf_count(leaf);
+    for (int i = s0; i < s0 + n; ++i) {
+      T q[D];
+      int reg;
+      const T d2 = prim_d2<T, D>(S, i, p, q, reg);
+      bool take = d2 < best;
+      if (!take && d2 == best && i != bi) take = bi < 0 || S.prim_id[i] < S.prim_id[bi];
+      if (take) {
+        best = d2;
+        bi = i;
+#pragma unroll
+        for (int a = 0; a < D; ++a) bq[a] = q[a];
+      }
+    }
+  };
+  int sp = 0;
+  int node = 0;
+  while (true) {
+    T lo0[D], hi0[D], lo1[D], hi1[D];
+    load_child_boxes<T, D>(S, node, lo0, hi0, lo1, hi1);
+    const int2 ch = S.child[node];
+    T d0 = box_d2<T, D>(lo0, hi0, p);
+    T d1 = box_d2<T, D>(lo1, hi1, p);
+    int c0 = ch.x, c1 = ch.y;
+    if (d1 < d0) {
+      const T td = d0;
+      d0 = d1;
+      d1 = td;
+      const int tc = c0;
+      c0 = c1;
+      c1 = tc;
+    }
+    int next = -1;
+    if (d0 <= best) {
+      if (c0 < 0) consider(c0);
+      else next = c0;
+    }
+    if (d1 <= best) {
+      if (c1 < 0) {
+        consider(c1);
+      } else if (next < 0) {
+        next = c1;
+      } else {
+        stk[sp * stride] = make_uint2((uint32_t)c1, __float_as_uint(lower_bound_f32(d1)));
+        ++sp;
+      }
+    }
+    while (next < 0 && sp > 0) {
+      --sp;
+      const uint2 e = stk[sp * stride];
+      if ((T)__uint_as_float(e.y) <= best) next = (int)e.x;
+    }
+    if (next < 0) break;
+    node = next;
+  }
+}
+
+// Closest point with an optional hint primitive (walk coherence: the
+// previous step's closest primitive bounds the new distance from above).
+template <typename T, int D>
+__device__ __forceinline__ T closest_point(const SceneDev& S, const T* p, int& hint, T* q, uint2* stk,
+                                           int stride) {
+  T best = T(INFINITY);
+  int bi = -1;
+  if (hint >= 0) {
+    int reg;
+    best = prim_d2<T, D>(S, hint, p, q, reg);
+    bi = hint;
+  }
+  bvh_closest<T, D>(S, p, best, bi, q, stk, stride);
+  hint = bi;
+  return best;
+}
+
+// ---------------------------------------------------------------------------
+// Inside tests (FP64): 2D nonzero winding number by edge crossings, 3D sign
+// of the angle-weighted pseudonormal at the closest feature.
+// ---------------------------------------------------------------------------
+__device__ inline int winding_number(const SceneDev& S, const double* x) {
+  int wn = 0;
+  for (int p = 0; p < S.np; ++p) {
+    const int2 ij = reinterpret_cast<const int2*>(S.P)[p];
+    const double2 a = reinterpret_cast<const double2*>(S.V)[ij.x];
+    const double2 b = reinterpret_cast<const double2*>(S.V)[ij.y];
+    const double cr = (b.x - a.x) * (x[1] - a.y) - (x[0] - a.x) * (b.y - a.y);
+    if (a.y <= x[1]) {
+      if (b.y > x[1] && cr > 0) ++wn;
+    } else if (b.y <= x[1] && cr < 0) {
+      --wn;
+    }
+  }
+  return wn;
+}
+
+// 3D: x is inside when (x - q) . N < 0 for the pseudonormal N of the feature
+// of original triangle t that holds the closest point q.
+__device__ inline bool inside_3d(const SceneDev& S, const double* x, int t) {
+  const double* A = S.V + 3 * (size_t)S.P[3 * t];
+  const double* B = S.V + 3 * (size_t)S.P[3 * t + 1];
+  const double* C = S.V + 3 * (size_t)S.P[3 * t + 2];
+  double q[3];
+  int reg;
+  triangle_d2<double>(x, A, B, C, q, reg);
+  const double* N;
+  if (reg == 0) N = S.fn + 3 * (size_t)t;
+  else if (reg <= 3) N = S.vpn + 3 * (size_t)S.P[3 * t + (reg - 1)];
+  else N = S.epn + 9 * (size_t)t + 3 * (reg - 4);
+  return (x[0] - q[0]) * N[0] + (x[1] - q[1]) * N[1] + (x[2] - q[2]) * N[2] < 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Built-in fields, evaluated in FP64.
+// ---------------------------------------------------------------------------
+// Ein(z) = int_0^z (1 - e^-t)/t dt: alternating power series below 4, else
+// E1(z) + ln z + gamma with E1 from its continued fraction (modified Lentz).
+__device__ inline double ein(double z) {
+  if (z <= 0.0) return 0.0;
+  if (z < 4.0) {
+    double term = z, sum = z;  // term_k = (-1)^{k+1} z^k / k!
+    for (int k = 2; k < 80; ++k) {
+      term *= -z / k;
+      const double add = term / k;
+      sum += add;
+      if (fabs(add) < 1e-17 * fabs(sum)) break;
+    }
+    return sum;
+  }
+  double b = z + 1.0, c = 1e300, d = 1.0 / b, h = d;
+  for (int i = 1; i < 400; ++i) {
+    const double an = -(double)i * i;
+    b += 2.0;
+    d = 1.0 / (an * d + b);
+    c = b + an / c;
+    const double del = c * d;
+    h *= del;
+    if (fabs(del - 1.0) < 1e-16) break;
+  }
+  return h * exp(-z) + log(z) + 0.57721566490153286061;
+}
+
+__device__ inline double harmonic2d(double k, double alpha, double beta, const double* x) {
+  double re = 1.0, im = 0.0;
+  const int kk = (int)k;
+  for (int i = 0; i < kk; ++i) {
+    const double r2 = re * x[0] - im * x[1];
+    im = re * x[1] + im * x[0];
+    re = r2;
+  }
+  return alpha * re + beta * exp(x[0]) * cos(x[1]);
+}
+
+// Real solid harmonics r^l Y_lm from the Cartesian recurrences: for each m the
+// polynomial Q_l^m(z, r^2) = r^{l-m} P_l^(m)(z/r) obeys
+// (l-m) Q_l = (2l-1) z Q_{l-1} - (l+m-1) r^2 Q_{l-2}, Q_m = (2m-1)!!, and
+// (x + i y)^m carries the azimuth.  If `only` >= 0, returns basis `only`.
+__device__ inline double solid_harmonics(const double* coef, int L, const double* x, int only) {
+  const double r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+  double cm = 1.0, sm = 0.0;  // Re, Im of (x + i y)^m
+  double dfact = 1.0;         // (2m-1)!!
+  double total = 0.0;
+  for (int m = 0; m <= L; ++m) {
+    if (m > 0) {
+      const double c2 = cm * x[0] - sm * x[1];
+      sm = cm * x[1] + sm * x[0];
+      cm = c2;
+      dfact *= (2 * m - 1);
+    }
+    double qm2 = 0.0, qm1 = 0.0;
+    for (int l = m; l <= L; ++l) {
+      double q;
+      if (l == m) q = dfact;
+      else if (l == m + 1) q = (2 * m + 1) * x[2] * dfact;
+      else q = ((2 * l - 1) * x[2] * qm1 - (l + m - 1) * r2 * qm2) / (l - m);
+      qm2 = qm1;
+      qm1 = q;
+      double ratio = 1.0;  // (l-m)!/(l+m)!
+      for (int i = l - m + 1; i <= l + m; ++i) ratio /= i;
+      double nrm = sqrt((2 * l + 1) / (4.0 * kPi) * ratio);
+      if (m > 0) nrm *= 1.4142135623730950488;
+      const int ic = l * l + l + m, is = l * l + l - m;
+      if (only >= 0) {
+        if (only == ic) return nrm * q * cm;
+        if (m > 0 && only == is) return nrm * q * sm;
+      } else {
+        total += coef[ic] * nrm * q * cm;
+        if (m > 0) total += coef[is] * nrm * q * sm;
+      }
+    }
+  }
+  return only >= 0 ? 0.0 : total;
+}
+
+__device__ inline double fourier_basis(int b, double th) {
+  if (b == 0) return 1.0;
+  const int j = (b + 1) / 2;
+  double s, c;
+  sincos(j * th, &s, &c);
+  return (b & 1) ? c : s;
+}
+
+__device__ inline double field_value(const FieldDev& F, int dim, const double* x) {
+  const double* p = F.param;
+  switch (F.kind) {
+    case 0:
+      return 0.0;
+    case 1:
+      return p[0];
+    case 2:
+      return harmonic2d(p[0], p[1], p[2], x);
+    case 3: {
+      const int ng = F.n_coef / (1 + dim);
+      const double inv = 1.0 / (2.0 * p[0] * p[0]);
+      double sum = 0.0;
+      for (int k = 0; k < ng; ++k) {
+        const double* c = F.coef + k * (1 + dim);
+        double r2 = 0.0;
+        for (int a = 0; a < dim; ++a) r2 += (x[a] - c[1 + a]) * (x[a] - c[1 + a]);
+        sum += c[0] * exp(-r2 * inv);
+      }
+      return sum;
+    }
+    case 4: {
+      const int ng = F.n_coef / 3;
+      const double s2 = p[0] * p[0];
+      double sum = 0.0;
+      for (int k = 0; k < ng; ++k) {
+        const double* c = F.coef + 3 * k;
+        const double r2 = (x[0] - c[1]) * (x[0] - c[1]) + (x[1] - c[2]) * (x[1] - c[2]);
+        sum += c[0] * s2 * 0.5 * ein(r2 / (2.0 * s2));
+      }
+      return sum + harmonic2d(p[1], p[2], p[3], x);
+    }
+    case 5:
+      return solid_harmonics(F.coef, (int)p[0], x, -1);
+    case 6: {
+      const double th = atan2(x[1] - p[1], x[0] - p[0]);
+      double sum = F.coef[0];
+      // cos/sin(j th) by the angle-addition recurrence
+      double s1, c1;
+      sincos(th, &s1, &c1);
+      double cj = 1.0, sj = 0.0;
+      for (int b = 1; b < F.n_coef; b += 2) {
+        const double cn = cj * c1 - sj * s1;
+        sj = sj * c1 + cj * s1;
+        cj = cn;
+        sum += F.coef[b] * cj;
+        if (b + 1 < F.n_coef) sum += F.coef[b + 1] * sj;
+      }
+      return sum;
+    }
+    case 7: {
+      double r2 = 0.0;
+      for (int a = 0; a < dim; ++a) r2 += (x[a] - p[1 + a]) * (x[a] - p[1 + a]);
+      return dim == 2 ? p[0] * 0.5 * log(r2) : p[0] * rsqrt(r2);
+    }
+  }
+  return 0.0;
+}
+
+__device__ inline double basis_value(const FieldDev& F, int dim, int m, const double* x) {
+  switch (F.kind) {
+    case 6:
+      return fourier_basis(m, atan2(x[1] - F.param[1], x[0] - F.param[0]));
+    case 5:
+      return solid_harmonics(nullptr, (int)F.param[0], x, m);
+    default:
+      return 0.0;
+  }
+}
+
+// Source term in the walk's precision: Gaussian sums stay in T, everything
+// else goes through the FP64 evaluator.
+template <typename T, int D>
+__device__ __forceinline__ T source_value(const FieldDev& F, const T* y) {
+  if (F.kind == 3) {
+    const int ng = F.n_coef / (1 + D);
+    const T inv = T(1) / (T(2) * (T)F.param[0] * (T)F.param[0]);
+    T sum = T(0);
+    for (int k = 0; k < ng; ++k) {
+      const double* c = F.coef + k * (1 + D);
+      T r2 = T(0);
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        const T e = y[a] - (T)c[1 + a];
+        r2 += e * e;
+      }
+      sum += (T)c[0] * exp(-r2 * inv);
+    }
+    return sum;
+  }
+  double yd[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) yd[a] = (double)y[a];
+  return (T)field_value(F, D, yd);
+}
+
+}  // namespace bvc

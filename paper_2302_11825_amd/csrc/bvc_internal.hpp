@@ -1,0 +1,104 @@
+// Internal declarations shared by the host entry points and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/bvc.h"
+
+namespace bvc {
+
+constexpr int kLeafMax = 4;      // primitives per BVH leaf
+constexpr int kMaxDepth = 48;    // bound on the traversal stack
+constexpr double kPi = 3.141592653589793238462643383279502884;
+
+// Child link encoding: >= 0 internal node index; < 0 leaf ~(start << 3 | (count - 1)).
+__host__ __device__ inline int encode_leaf(int start, int count) { return ~((start << 3) | (count - 1)); }
+__host__ __device__ inline int leaf_start(int c) { return (~c) >> 3; }
+__host__ __device__ inline int leaf_count(int c) { return ((~c) & 7) + 1; }
+
+// Device view of an uploaded scene (pointers into the caller's buffer).
+struct SceneDev {
+  int dim;
+  int np, nv, ne, n_nodes, depth;
+  const double* V;      // [nv][dim] original vertices
+  const int* P;         // [np][dim] original primitives
+  const int* E;         // [ne][2] unique edges (3D)
+  const int2* child;    // [n_nodes] child links
+  const double* box64;  // [n_nodes][4*dim]: child0 lo, child0 hi, child1 lo, child1 hi
+  const float* box32;   // same, rounded outward
+  const double* prim64; // leaf order: 2D [np][4] (a, b); 3D [np][12] (a, b, c, pad)
+  const float* prim32;  // same layout in FP32
+  const int* prim_id;   // leaf order -> original primitive id
+  const double* fn;     // 3D [np][3] unit face normals (original order)
+  const double* epn;    // 3D [np][9] edge pseudonormals of edges (ab, bc, ca)
+  const double* vpn;    // 3D [nv][3] angle-weighted vertex pseudonormals
+  const double* cdf;    // [n_el + 1] sampling CDF for the current (l, sides)
+  const double* meas;   // [n_el] element measures
+  int n_el;
+  int sides;
+  double l;
+};
+
+struct FieldDev {
+  int kind;
+  int n_coef;
+  const double* coef;
+  double param[8];
+};
+
+inline FieldDev to_dev(const bvc_field& f) {
+  FieldDev d;
+  d.kind = f.kind;
+  d.n_coef = f.n_coef;
+  d.coef = f.coef;
+  for (int i = 0; i < 8; ++i) d.param[i] = f.param[i];
+  return d;
+}
+
+// Host-side scene.
+struct SceneHost {
+  int dim = 0;
+  int64_t nv = 0, np = 0, ne = 0;
+  std::vector<double> V;
+  std::vector<int> P;
+  std::vector<int> E;
+  std::vector<int2> child;
+  std::vector<double> box64;
+  std::vector<float> box32;
+  std::vector<double> prim64;
+  std::vector<float> prim32;
+  std::vector<int> prim_id;
+  std::vector<double> fn, epn, vpn;
+  std::vector<double> seg_measure;  // length (2D) / area (3D) per primitive
+  std::vector<double> edge_len;     // 3D
+  int depth = 0;
+  double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  double boundary_measure = 0;
+  // device placement
+  size_t bytes = 0;
+  size_t off_V = 0, off_P = 0, off_E = 0, off_child = 0, off_box64 = 0, off_box32 = 0,
+         off_prim64 = 0, off_prim32 = 0, off_prim_id = 0, off_fn = 0, off_epn = 0, off_vpn = 0,
+         off_cdf = 0, off_meas = 0;
+  int64_t n_el_max = 0;
+  char* dev = nullptr;
+  // cached sampling table
+  double cdf_l = -1;
+  int cdf_sides = -1;
+  int64_t cdf_n_el = 0;
+  SceneDev view() const;
+};
+
+// Error helpers (thread-local message).
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+int check_hip(hipError_t e, const char* what);
+
+}  // namespace bvc
+
+struct bvc_scene_s {
+  bvc::SceneHost h;
+};

@@ -1,0 +1,665 @@
+// Boundary-integral gather (Eqs. 3-6), its adjoint, and the basis expansions
+// that make the cache linear in the boundary data.
+//
+// The gather inverts the loop order of the paper's splat (Algorithm 1): the
+// evaluation points are the parallel dimension, held in registers (two per
+// thread), and cache entries stream through LDS in tiles that every thread of
+// the block reads by broadcast.  No atomics: each point's sum is owned by one
+// thread.  Cache entries are pre-scaled once per tile (a n/(2 pi), b/(2 pi),
+// ...) so the pair loop is a handful of FMAs, one reciprocal and, in 2D, one
+// logarithm.  FP32 partial sums are folded into FP64 after every tile.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+
+#include "bvc_device.hpp"
+
+namespace bvc {
+namespace {
+
+constexpr int kGBlock = 256;
+constexpr int kTile = 256;
+constexpr int kPPT = 2;  // evaluation points per thread
+
+// log(r^2) via the hardware log2 in FP32; natural log in FP64.
+__device__ __forceinline__ float log_r2(float r2) { return __log2f(r2); }
+__device__ __forceinline__ double log_r2(double r2) { return log(r2); }
+template <typename T>
+__host__ __device__ constexpr T log_scale() {
+  return sizeof(T) == 4 ? (T)0.69314718055994530942 : (T)1;  // ln r^2 = ln2 * log2 r^2
+}
+__device__ __forceinline__ float recip(float x) { return __frcp_rn(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+__device__ __forceinline__ float rsq(float x) { return __frsqrt_rn(x); }
+__device__ __forceinline__ double rsq(double x) { return rsqrt(x); }
+
+template <typename T>
+struct GatherArgs {
+  int64_t n_eval;
+  const T* ex;       // [D][n_eval]
+  int64_t n_cache;
+  const T* cx;       // [D][n_cache]
+  const T* cn;
+  const T* ca;
+  const T* cb;
+  int64_t n_src;
+  const T* sy;       // [D][n_src]
+  const T* ss;
+  T* u;              // [n_eval] or null
+  T* g;              // [D][n_eval] or null
+  const T* scale;    // multiply outputs by scale[k] (adjoint dL/dx) or null
+  int accumulate;
+};
+
+// Entry layout in LDS (8 values): 2D boundary {y0, y1, na0, na1, bl, bg}, 3D
+// boundary {y0, y1, y2, bl, na0, na1, na2, -}; sources {y.., sl, sg}.
+template <typename T, int D, bool GRAD>
+__global__ __launch_bounds__(kGBlock) void k_gather(GatherArgs<T> a) {
+  __shared__ T ent[kTile * 8];
+  const int tid = threadIdx.x;
+  const int64_t k0 = (int64_t)blockIdx.x * (kGBlock * kPPT) + tid;
+  T x[kPPT][D];
+  bool live[kPPT];
+#pragma unroll
+  for (int p = 0; p < kPPT; ++p) {
+    const int64_t k = k0 + p * kGBlock;
+    live[p] = k < a.n_eval;
+#pragma unroll
+    for (int c = 0; c < D; ++c) x[p][c] = live[p] ? a.ex[c * a.n_eval + k] : T(0);
+  }
+  double tu[kPPT], tg[kPPT][D];
+  T au[kPPT], ag[kPPT][D];
+#pragma unroll
+  for (int p = 0; p < kPPT; ++p) {
+    tu[p] = 0.0;
+    au[p] = T(0);
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      tg[p][c] = 0.0;
+      ag[p][c] = T(0);
+    }
+  }
+  const T inv2pi = (T)(1.0 / (2.0 * kPi)), inv4pi = (T)(1.0 / (4.0 * kPi));
+  const T tiny = sizeof(T) == 4 ? (T)1e-18 : (T)1e-200;
+
+  auto fold = [&]() {
+#pragma unroll
+    for (int p = 0; p < kPPT; ++p) {
+      tu[p] += (double)au[p];
+      au[p] = T(0);
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        tg[p][c] += (double)ag[p][c];
+        ag[p][c] = T(0);
+      }
+    }
+  };
+
+  // ---- boundary samples (Eqs. 3 and 5) ----
+  for (int64_t t0 = 0; t0 < a.n_cache; t0 += kTile) {
+    const int cnt = (int)std::min<int64_t>(kTile, a.n_cache - t0);
+    if (tid < cnt) {
+      const int64_t i = t0 + tid;
+      T y[D], nn[D];
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        y[c] = a.cx[c * a.n_cache + i];
+        nn[c] = a.cn[c * a.n_cache + i];
+      }
+      const T av = a.ca[i], bv = a.cb[i];
+      T* e = ent + tid * 8;
+      if constexpr (D == 2) {
+        e[0] = y[0];
+        e[1] = y[1];
+        e[2] = nn[0] * av * inv2pi;
+        e[3] = nn[1] * av * inv2pi;
+        e[4] = -bv * inv2pi * T(0.5) * log_scale<T>();  // -G b = -(b/4pi) ln r^2
+        e[5] = bv * inv2pi;
+      } else {
+        e[0] = y[0];
+        e[1] = y[1];
+        e[2] = y[2];
+        e[3] = bv * inv4pi;  // -G b = b/(4 pi r)
+        e[4] = nn[0] * av * inv4pi;
+        e[5] = nn[1] * av * inv4pi;
+        e[6] = nn[2] * av * inv4pi;
+      }
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int j = 0; j < cnt; ++j) {
+      const T* e = ent + j * 8;
+      if constexpr (D == 2) {
+        const T y0 = e[0], y1 = e[1], n0 = e[2], n1 = e[3], bl = e[4], bg = e[5];
+#pragma unroll
+        for (int p = 0; p < kPPT; ++p) {
+          const T dx = y0 - x[p][0], dy = y1 - x[p][1];
+          const T r2 = fmax(dx * dx + dy * dy, tiny);
+          const T ri = recip(r2);
+          const T t = n0 * dx + n1 * dy;  // a (n . (y - x)) / (2 pi)
+          au[p] += t * ri + bl * log_r2(r2);
+          if constexpr (GRAD) {
+            const T q = ri * (T(2) * t * ri + bg);
+            ag[p][0] += q * dx - n0 * ri;
+            ag[p][1] += q * dy - n1 * ri;
+          }
+        }
+      } else {
+        const T y0 = e[0], y1 = e[1], y2 = e[2], bl = e[3], n0 = e[4], n1 = e[5], n2 = e[6];
+#pragma unroll
+        for (int p = 0; p < kPPT; ++p) {
+          const T dx = y0 - x[p][0], dy = y1 - x[p][1], dz = y2 - x[p][2];
+          const T r2 = fmax(dx * dx + dy * dy + dz * dz, tiny);
+          const T ri = rsq(r2);
+          const T ri2 = ri * ri;
+          const T ri3 = ri2 * ri;
+          const T t = n0 * dx + n1 * dy + n2 * dz;
+          au[p] += t * ri3 + bl * ri;
+          if constexpr (GRAD) {
+            const T q = ri3 * (T(3) * t * ri2 + bl);
+            ag[p][0] += q * dx - n0 * ri3;
+            ag[p][1] += q * dy - n1 * ri3;
+            ag[p][2] += q * dz - n2 * ri3;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    fold();
+  }
+
+  // ---- source samples (Eqs. 4 and 6) ----
+  for (int64_t t0 = 0; t0 < a.n_src; t0 += kTile) {
+    const int cnt = (int)std::min<int64_t>(kTile, a.n_src - t0);
+    if (tid < cnt) {
+      const int64_t j = t0 + tid;
+      T* e = ent + tid * 8;
+      const T sv = a.ss[j];
+#pragma unroll
+      for (int c = 0; c < D; ++c) e[c] = a.sy[c * a.n_src + j];
+      if constexpr (D == 2) {
+        e[2] = sv * inv2pi * T(0.5) * log_scale<T>();  // G s = (s/4pi) ln r^2
+        e[3] = -sv * inv2pi;                           // dG/dx s = -s (y-x)/(2 pi r^2)
+      } else {
+        e[3] = -sv * inv4pi;  // G s = -s/(4 pi r); dG/dx s = -s (y-x)/(4 pi r^3)
+      }
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int j = 0; j < cnt; ++j) {
+      const T* e = ent + j * 8;
+      if constexpr (D == 2) {
+        const T y0 = e[0], y1 = e[1], sl = e[2], sg = e[3];
+#pragma unroll
+        for (int p = 0; p < kPPT; ++p) {
+          const T dx = y0 - x[p][0], dy = y1 - x[p][1];
+          const T r2 = fmax(dx * dx + dy * dy, tiny);
+          au[p] += sl * log_r2(r2);
+          if constexpr (GRAD) {
+            const T q = sg * recip(r2);
+            ag[p][0] += q * dx;
+            ag[p][1] += q * dy;
+          }
+        }
+      } else {
+        const T y0 = e[0], y1 = e[1], y2 = e[2], sl = e[3];
+#pragma unroll
+        for (int p = 0; p < kPPT; ++p) {
+          const T dx = y0 - x[p][0], dy = y1 - x[p][1], dz = y2 - x[p][2];
+          const T r2 = fmax(dx * dx + dy * dy + dz * dz, tiny);
+          const T ri = rsq(r2);
+          au[p] += sl * ri;
+          if constexpr (GRAD) {
+            const T q = sl * ri * ri * ri;
+            ag[p][0] += q * dx;
+            ag[p][1] += q * dy;
+            ag[p][2] += q * dz;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    fold();
+  }
+
+#pragma unroll
+  for (int p = 0; p < kPPT; ++p) {
+    const int64_t k = k0 + p * kGBlock;
+    if (!live[p]) continue;
+    const double sc = a.scale ? (double)a.scale[k] : 1.0;
+    if (a.u) a.u[k] = (T)((a.accumulate ? (double)a.u[k] : 0.0) + sc * tu[p]);
+    if (GRAD && a.g) {
+#pragma unroll
+      for (int c = 0; c < D; ++c)
+        a.g[c * a.n_eval + k] = (T)((a.accumulate ? (double)a.g[c * a.n_eval + k] : 0.0) + sc * tg[p][c]);
+    }
+  }
+}
+
+// Transposed gather: cache (or source) points are the parallel dimension and
+// the evaluation points with their residuals r_k stream through LDS.
+template <typename T>
+struct BackArgs {
+  int64_t n_eval;
+  const T* ex;
+  const T* r;
+  int64_t n_pts;
+  const T* py;   // [D][n_pts] cache or source points
+  const T* pn;   // normals (cache) or null (sources)
+  T* out_a;      // cache: dL/da ; sources: dL/ds
+  T* out_b;      // cache: dL/db
+};
+
+template <typename T, int D, bool CACHE>
+__global__ __launch_bounds__(kGBlock) void k_gather_back(BackArgs<T> a) {
+  __shared__ T ent[kTile * 4];
+  const int tid = threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.x * (kGBlock * kPPT) + tid;
+  T y[kPPT][D], nn[kPPT][D];
+  bool live[kPPT];
+#pragma unroll
+  for (int p = 0; p < kPPT; ++p) {
+    const int64_t i = i0 + p * kGBlock;
+    live[p] = i < a.n_pts;
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      y[p][c] = live[p] ? a.py[c * a.n_pts + i] : T(0);
+      nn[p][c] = (CACHE && live[p]) ? a.pn[c * a.n_pts + i] : T(0);
+    }
+  }
+  double ta[kPPT], tb[kPPT];
+  T sa[kPPT], sb[kPPT];
+#pragma unroll
+  for (int p = 0; p < kPPT; ++p) {
+    ta[p] = tb[p] = 0.0;
+    sa[p] = sb[p] = T(0);
+  }
+  const T inv2pi = (T)(1.0 / (2.0 * kPi)), inv4pi = (T)(1.0 / (4.0 * kPi));
+  const T tiny = sizeof(T) == 4 ? (T)1e-18 : (T)1e-200;
+  for (int64_t t0 = 0; t0 < a.n_eval; t0 += kTile) {
+    const int cnt = (int)std::min<int64_t>(kTile, a.n_eval - t0);
+    if (tid < cnt) {
+      const int64_t k = t0 + tid;
+      T* e = ent + tid * 4;
+#pragma unroll
+      for (int c = 0; c < D; ++c) e[c] = a.ex[c * a.n_eval + k];
+      e[3] = a.r[k];
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int j = 0; j < cnt; ++j) {
+      const T* e = ent + j * 4;
+      const T rk = e[3];
+#pragma unroll
+      for (int p = 0; p < kPPT; ++p) {
+        T dx[D], r2 = T(0), t = T(0);
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+          dx[c] = y[p][c] - e[c];  // y - x
+          r2 += dx[c] * dx[c];
+          t += nn[p][c] * dx[c];
+        }
+        r2 = fmax(r2, tiny);
+        if constexpr (D == 2) {
+          const T lr = log_r2(r2) * log_scale<T>();  // ln r^2
+          if constexpr (CACHE) {
+            sa[p] += rk * t * recip(r2);  // r dG/dn (times 2 pi)
+            sb[p] += rk * lr;             // -r G (times -4 pi)
+          } else {
+            sa[p] += rk * lr;  // r G (times 4 pi)
+          }
+        } else {
+          const T ri = rsq(r2);
+          if constexpr (CACHE) {
+            sa[p] += rk * t * ri * ri * ri;  // r dG/dn (times 4 pi)
+            sb[p] += rk * ri;                // -r G (times 4 pi)
+          } else {
+            sa[p] += rk * ri;  // r G (times -4 pi)
+          }
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < kPPT; ++p) {
+      ta[p] += (double)sa[p];
+      tb[p] += (double)sb[p];
+      sa[p] = sb[p] = T(0);
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < kPPT; ++p) {
+    const int64_t i = i0 + p * kGBlock;
+    if (!live[p]) continue;
+    if constexpr (D == 2) {
+      if constexpr (CACHE) {
+        if (a.out_a) a.out_a[i] = (T)(ta[p] / (2.0 * kPi));
+        if (a.out_b) a.out_b[i] = (T)(-tb[p] / (4.0 * kPi));
+      } else {
+        if (a.out_a) a.out_a[i] = (T)(ta[p] / (4.0 * kPi));
+      }
+    } else {
+      if constexpr (CACHE) {
+        if (a.out_a) a.out_a[i] = (T)(ta[p] / (4.0 * kPi));
+        if (a.out_b) a.out_b[i] = (T)(tb[p] / (4.0 * kPi));
+      } else {
+        if (a.out_a) a.out_a[i] = (T)(-ta[p] / (4.0 * kPi));
+      }
+    }
+  }
+  (void)inv2pi;
+  (void)inv4pi;
+}
+
+// ---------------------------------------------------------------------------
+// Basis expansions from exit records
+// ---------------------------------------------------------------------------
+// One real solid harmonic r^l Y_lm (orthonormal, no Condon-Shortley phase).
+__device__ inline double solid_harmonic_lm(int l, int m, const double* x) {
+  const int am = m < 0 ? -m : m;
+  const double r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+  double cm = 1.0, sm = 0.0, dfact = 1.0;
+  for (int i = 1; i <= am; ++i) {
+    const double c2 = cm * x[0] - sm * x[1];
+    sm = cm * x[1] + sm * x[0];
+    cm = c2;
+    dfact *= (2 * i - 1);
+  }
+  double q = dfact, q1 = 0.0;
+  for (int ll = am + 1; ll <= l; ++ll) {
+    const double qn = ll == am + 1 ? (2 * am + 1) * x[2] * dfact
+                                   : ((2 * ll - 1) * x[2] * q - (ll + am - 1) * r2 * q1) / (ll - am);
+    q1 = q;
+    q = qn;
+  }
+  double ratio = 1.0;
+  for (int i = l - am + 1; i <= l + am; ++i) ratio /= i;
+  double nrm = sqrt((2 * l + 1) / (4.0 * kPi) * ratio);
+  if (m == 0) return nrm * q;
+  nrm *= 1.4142135623730950488;
+  return m > 0 ? nrm * q * cm : nrm * q * sm;
+}
+
+__device__ inline double basis_single(const FieldDev& F, int D, int m, const double* x) {
+  if (F.kind == 6) return fourier_basis(m, atan2(x[1] - F.param[1], x[0] - F.param[0]));
+  int l = 0;
+  while ((l + 1) * (l + 1) <= m) ++l;
+  return solid_harmonic_lm(l, m - l * l - l, x);
+}
+
+template <typename T, int D>
+__global__ void k_basis_means(FieldDev F, int nb, int64_t n_cache, int W, const T* ex, const T* w1,
+                              const double* xbar, int cv, double* E, double* Fo) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_cache * nb) return;
+  const int64_t i = t / nb;
+  const int m = (int)(t % nb);
+  const int64_t total = n_cache * (int64_t)W;
+  double base = 0.0;
+  if (cv) {
+    double xb[D];
+    for (int c = 0; c < D; ++c) xb[c] = xbar[c * n_cache + i];
+    base = basis_single(F, D, m, xb);
+  }
+  double se = 0.0, sf = 0.0;
+  for (int j = 0; j < W; ++j) {
+    const int64_t id = i * W + j;
+    double q[D];
+    for (int c = 0; c < D; ++c) q[c] = (double)ex[c * total + id];
+    const double phi = basis_single(F, D, m, q);
+    se += phi;
+    sf += (double)w1[id] * (phi - base);
+  }
+  E[i * nb + m] = se / W;
+  Fo[i * nb + m] = sf / W;
+}
+
+// dL/dtheta_m = sum_i w_i (E_im gA_i + F_im gB_i): partial sums over chunks
+// of cache points, then a fixed-order sum of the chunks.
+constexpr int kChunk = 1024;
+__global__ void k_cache_back_partial(int64_t n, int nb, const double* E, const double* F, const double* w,
+                                     const double* ga, const double* gb, double* part) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  if (m >= nb) return;
+  double s = 0.0;
+  const int64_t i1 = std::min<int64_t>(n, (c + 1) * kChunk);
+  for (int64_t i = c * kChunk; i < i1; ++i) s += w[i] * (E[i * nb + m] * ga[i] + F[i * nb + m] * gb[i]);
+  part[c * nb + m] = s;
+}
+__global__ void k_cache_back_final(int nb, int64_t chunks, const double* part, double* out) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= nb) return;
+  double s = 0.0;
+  for (int64_t c = 0; c < chunks; ++c) s += part[c * nb + m];
+  out[m] = s;
+}
+
+template <typename To>
+__global__ void k_eval_fields(int64_t n, int nb, int nf, const double* E, const double* F, const double* w,
+                              const double* coef, To* A, To* B) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * nf) return;
+  const int64_t i = t / nf;
+  const int f = (int)(t % nf);
+  double sa = 0.0, sb = 0.0;
+  for (int m = 0; m < nb; ++m) {
+    const double c = coef[(int64_t)f * nb + m];
+    sa += E[i * nb + m] * c;
+    sb += F[i * nb + m] * c;
+  }
+  A[i * nf + f] = (To)(sa * w[i]);
+  B[i * nf + f] = (To)(sb * w[i]);
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+int check_view(const bvc_cache_view* c, int dim) {
+  if (!c) return fail(BVC_EINVAL, "cache view is null");
+  if (c->n < 0) return fail(BVC_EINVAL, "cache size is negative");
+  if (c->dtype != BVC_F32 && c->dtype != BVC_F64) return fail(BVC_EINVAL, "cache dtype must be F32 or F64");
+  if (c->n > 0 && (!c->x || !c->nrm || !c->a || !c->b)) return fail(BVC_EINVAL, "cache arrays are null");
+  (void)dim;
+  return BVC_OK;
+}
+
+int check_sources(const bvc_source_view* s, int dtype) {
+  if (!s) return BVC_OK;
+  if (s->n < 0) return fail(BVC_EINVAL, "source count is negative");
+  if (s->dtype != dtype) return fail(BVC_EINVAL, "source dtype differs from the cache dtype");
+  if (s->n > 0 && (!s->y || !s->s)) return fail(BVC_EINVAL, "source arrays are null");
+  return BVC_OK;
+}
+
+template <typename T, int D>
+void launch_gather(const GatherArgs<T>& a, bool grad, hipStream_t st) {
+  const int blocks = (int)((a.n_eval + kGBlock * kPPT - 1) / (kGBlock * kPPT));
+  if (grad) hipLaunchKernelGGL((k_gather<T, D, true>), dim3(blocks), dim3(kGBlock), 0, st, a);
+  else hipLaunchKernelGGL((k_gather<T, D, false>), dim3(blocks), dim3(kGBlock), 0, st, a);
+}
+
+template <typename T>
+int gather_impl(int dim, const bvc_cache_view* c, const bvc_source_view* s, int64_t n_eval, const void* ex, void* u,
+                void* g, const void* scale, int accumulate, hipStream_t st) {
+  GatherArgs<T> a{};
+  a.n_eval = n_eval;
+  a.ex = (const T*)ex;
+  a.n_cache = c->n;
+  a.cx = (const T*)c->x;
+  a.cn = (const T*)c->nrm;
+  a.ca = (const T*)c->a;
+  a.cb = (const T*)c->b;
+  a.n_src = s ? s->n : 0;
+  a.sy = s ? (const T*)s->y : nullptr;
+  a.ss = s ? (const T*)s->s : nullptr;
+  a.u = (T*)u;
+  a.g = (T*)g;
+  a.scale = (const T*)scale;
+  a.accumulate = accumulate;
+  if (dim == 2) launch_gather<T, 2>(a, g != nullptr, st);
+  else launch_gather<T, 3>(a, g != nullptr, st);
+  return check_hip(hipGetLastError(), "gather launch");
+}
+
+int gather_entry(int32_t dim, const bvc_cache_view* c, const bvc_source_view* s, int64_t n_eval, const void* ex,
+                 void* u, void* g, const bvc_gather_params* prm, void* stream) {
+  if (dim != 2 && dim != 3) return fail(BVC_EINVAL, "dim must be 2 or 3");
+  int rc = check_view(c, dim);
+  if (rc) return rc;
+  rc = check_sources(s, c->dtype);
+  if (rc) return rc;
+  if (n_eval < 0) return fail(BVC_EINVAL, "n_eval must be >= 0");
+  if (n_eval == 0) return BVC_OK;
+  if (!ex || (!u && !g)) return fail(BVC_EINVAL, "null evaluation points or outputs");
+  const int acc = prm ? prm->accumulate : 0;
+  hipStream_t st = (hipStream_t)stream;
+  if (c->dtype == BVC_F32) return gather_impl<float>(dim, c, s, n_eval, ex, u, g, nullptr, acc, st);
+  return gather_impl<double>(dim, c, s, n_eval, ex, u, g, nullptr, acc, st);
+}
+
+template <typename T>
+int backward_impl(int dim, const bvc_cache_view* c, const bvc_source_view* s, int64_t n_eval, const void* ex,
+                  const void* r, void* da, void* db, void* ds, void* dx, hipStream_t st) {
+  if (da || db) {
+    BackArgs<T> b{n_eval, (const T*)ex, (const T*)r, c->n, (const T*)c->x, (const T*)c->nrm, (T*)da, (T*)db};
+    const int blocks = (int)((c->n + kGBlock * kPPT - 1) / (kGBlock * kPPT));
+    if (blocks > 0) {
+      if (dim == 2) hipLaunchKernelGGL((k_gather_back<T, 2, true>), dim3(blocks), dim3(kGBlock), 0, st, b);
+      else hipLaunchKernelGGL((k_gather_back<T, 3, true>), dim3(blocks), dim3(kGBlock), 0, st, b);
+    }
+  }
+  if (ds && s && s->n > 0) {
+    BackArgs<T> b{n_eval, (const T*)ex, (const T*)r, s->n, (const T*)s->y, nullptr, (T*)ds, nullptr};
+    const int blocks = (int)((s->n + kGBlock * kPPT - 1) / (kGBlock * kPPT));
+    if (dim == 2) hipLaunchKernelGGL((k_gather_back<T, 2, false>), dim3(blocks), dim3(kGBlock), 0, st, b);
+    else hipLaunchKernelGGL((k_gather_back<T, 3, false>), dim3(blocks), dim3(kGBlock), 0, st, b);
+  }
+  if (dx) {
+    int rc = gather_impl<T>(dim, c, s, n_eval, ex, nullptr, dx, r, 0, st);
+    if (rc) return rc;
+  }
+  return check_hip(hipGetLastError(), "gather backward launch");
+}
+
+}  // namespace
+}  // namespace bvc
+
+using namespace bvc;
+
+extern "C" {
+
+int bvc_gather_u(int32_t dim, const bvc_cache_view* cache, const bvc_source_view* sources, int64_t n_eval,
+                 const void* eval_x, void* u, const bvc_gather_params* params, void* stream) {
+  if (!u) return fail(BVC_EINVAL, "u is null");
+  return gather_entry(dim, cache, sources, n_eval, eval_x, u, nullptr, params, stream);
+}
+
+int bvc_gather_grad(int32_t dim, const bvc_cache_view* cache, const bvc_source_view* sources, int64_t n_eval,
+                    const void* eval_x, void* u, void* grad, const bvc_gather_params* params, void* stream) {
+  if (!grad) return fail(BVC_EINVAL, "grad is null");
+  return gather_entry(dim, cache, sources, n_eval, eval_x, u, grad, params, stream);
+}
+
+int bvc_gather_backward(int32_t dim, const bvc_cache_view* cache, const bvc_source_view* sources, int64_t n_eval,
+                        const void* eval_x, const void* dL_du, void* dL_da, void* dL_db, void* dL_ds, void* dL_dx,
+                        void* stream) {
+  if (dim != 2 && dim != 3) return fail(BVC_EINVAL, "dim must be 2 or 3");
+  int rc = check_view(cache, dim);
+  if (rc) return rc;
+  rc = check_sources(sources, cache->dtype);
+  if (rc) return rc;
+  if (n_eval < 0) return fail(BVC_EINVAL, "n_eval must be >= 0");
+  if (n_eval > 0 && (!eval_x || !dL_du)) return fail(BVC_EINVAL, "null evaluation points or residuals");
+  hipStream_t st = (hipStream_t)stream;
+  // with no evaluation points every adjoint is zero
+  if (n_eval == 0) {
+    const size_t es = cache->dtype == BVC_F32 ? 4 : 8;
+    if (dL_da && cache->n) (void)hipMemsetAsync(dL_da, 0, cache->n * es, st);
+    if (dL_db && cache->n) (void)hipMemsetAsync(dL_db, 0, cache->n * es, st);
+    if (dL_ds && sources && sources->n) (void)hipMemsetAsync(dL_ds, 0, sources->n * es, st);
+    return check_hip(hipGetLastError(), "gather backward");
+  }
+  if (cache->dtype == BVC_F32)
+    return backward_impl<float>(dim, cache, sources, n_eval, eval_x, dL_du, dL_da, dL_db, dL_ds, dL_dx, st);
+  return backward_impl<double>(dim, cache, sources, n_eval, eval_x, dL_du, dL_da, dL_db, dL_ds, dL_dx, st);
+}
+
+int bvc_basis_means(const bvc_field* basis, int32_t dim, int64_t n_cache, int32_t W, int32_t dtype,
+                    const void* rec_exit, const void* rec_w1, const double* xbar, int32_t cv, double* E, double* F,
+                    void* stream) {
+  if (!basis) return fail(BVC_EINVAL, "basis is null");
+  if (!((basis->kind == 6 && dim == 2) || (basis->kind == 5 && dim == 3)))
+    return fail(BVC_EINVAL, "basis must be FOURIER_2D (2D) or SOLID_HARMONICS_3D (3D)");
+  const int nb = basis->n_coef;
+  if (nb < 1) return fail(BVC_EINVAL, "basis size must be >= 1");
+  if (basis->kind == 5) {
+    const int L = (int)basis->param[0];
+    if (nb != (L + 1) * (L + 1)) return fail(BVC_EINVAL, "solid harmonics need (L+1)^2 terms");
+  }
+  if (n_cache < 0 || W < 1) return fail(BVC_EINVAL, "bad sizes");
+  if (dtype != BVC_F32 && dtype != BVC_F64) return fail(BVC_EINVAL, "dtype must be F32 or F64");
+  if (n_cache == 0) return BVC_OK;
+  if (!rec_exit || !rec_w1 || !E || !F || (cv && !xbar)) return fail(BVC_EINVAL, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t total = n_cache * nb;
+  const int blocks = (int)((total + 255) / 256);
+  FieldDev Fd = to_dev(*basis);
+  if (dim == 2) {
+    if (dtype == BVC_F32)
+      hipLaunchKernelGGL((k_basis_means<float, 2>), dim3(blocks), dim3(256), 0, st, Fd, nb, n_cache, W,
+                         (const float*)rec_exit, (const float*)rec_w1, xbar, cv, E, F);
+    else
+      hipLaunchKernelGGL((k_basis_means<double, 2>), dim3(blocks), dim3(256), 0, st, Fd, nb, n_cache, W,
+                         (const double*)rec_exit, (const double*)rec_w1, xbar, cv, E, F);
+  } else {
+    if (dtype == BVC_F32)
+      hipLaunchKernelGGL((k_basis_means<float, 3>), dim3(blocks), dim3(256), 0, st, Fd, nb, n_cache, W,
+                         (const float*)rec_exit, (const float*)rec_w1, xbar, cv, E, F);
+    else
+      hipLaunchKernelGGL((k_basis_means<double, 3>), dim3(blocks), dim3(256), 0, st, Fd, nb, n_cache, W,
+                         (const double*)rec_exit, (const double*)rec_w1, xbar, cv, E, F);
+  }
+  return check_hip(hipGetLastError(), "basis means launch");
+}
+
+int64_t bvc_cache_backward_scratch_doubles(int64_t n_cache, int32_t nb) {
+  return ((n_cache + kChunk - 1) / kChunk) * (int64_t)nb;
+}
+
+int bvc_cache_backward(int64_t n_cache, int32_t nb, const double* E, const double* F, const double* w,
+                       const double* dL_da, const double* dL_db, double* scratch, double* dL_dtheta,
+                       void* stream) {
+  if (n_cache < 0 || nb < 1) return fail(BVC_EINVAL, "bad sizes");
+  if (!dL_dtheta) return fail(BVC_EINVAL, "dL_dtheta is null");
+  hipStream_t st = (hipStream_t)stream;
+  if (n_cache == 0) return check_hip(hipMemsetAsync(dL_dtheta, 0, nb * sizeof(double), st), "zero");
+  if (!E || !F || !w || !dL_da || !dL_db || !scratch) return fail(BVC_EINVAL, "null argument");
+  const int64_t chunks = (n_cache + kChunk - 1) / kChunk;
+  hipLaunchKernelGGL(k_cache_back_partial, dim3((nb + 63) / 64, (unsigned)chunks), dim3(64), 0, st, n_cache, nb, E, F,
+                     w, dL_da, dL_db, scratch);
+  hipLaunchKernelGGL(k_cache_back_final, dim3((nb + 63) / 64), dim3(64), 0, st, nb, chunks, scratch, dL_dtheta);
+  return check_hip(hipGetLastError(), "cache backward launch");
+}
+
+int bvc_eval_fields(int64_t n_cache, int32_t nb, int32_t n_fields, const double* E, const double* F, const double* w,
+                    const double* coef, int32_t dtype_out, void* A, void* B, void* stream) {
+  if (n_cache < 0 || nb < 1 || n_fields < 1) return fail(BVC_EINVAL, "bad sizes");
+  if (dtype_out != BVC_F32 && dtype_out != BVC_F64) return fail(BVC_EINVAL, "dtype must be F32 or F64");
+  if (n_cache == 0) return BVC_OK;
+  if (!E || !F || !w || !coef || !A || !B) return fail(BVC_EINVAL, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t total = n_cache * n_fields;
+  const int blocks = (int)((total + 255) / 256);
+  if (dtype_out == BVC_F32)
+    hipLaunchKernelGGL(k_eval_fields<float>, dim3(blocks), dim3(256), 0, st, n_cache, nb, n_fields, E, F, w, coef,
+                       (float*)A, (float*)B);
+  else
+    hipLaunchKernelGGL(k_eval_fields<double>, dim3(blocks), dim3(256), 0, st, n_cache, nb, n_fields, E, F, w, coef,
+                       (double*)A, (double*)B);
+  return check_hip(hipGetLastError(), "eval fields launch");
+}
+
+}  // extern "C"

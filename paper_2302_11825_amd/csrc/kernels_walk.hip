@@ -1,0 +1,845 @@
+// Sampling, classification, compaction and walk-on-spheres kernels with their
+// C-ABI entry points.
+//
+// Walks run in a persistent kernel: each wave takes walk ids from a global
+// queue, one id per idle lane, so a lane whose walk ended starts the next one
+// at the following iteration instead of idling until the longest walk of its
+// wave is done.  A walk's random numbers depend only on (seed, batch, id), so
+// results do not depend on which lane ran it.  Each walk writes its own
+// sample; cache means are reduced afterwards in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+
+#include "bvc_device.hpp"
+
+namespace bvc {
+
+int ensure_cdf(SceneHost& S, double l, int sides, hipStream_t stream);
+double candidate_measure(const SceneHost& S, double l, int sides);
+
+namespace {
+
+constexpr int kBlock = 256;
+
+inline size_t stack_bytes(const SceneHost& h, int block) {
+  return (size_t)(h.depth + 1) * block * sizeof(uint2);
+}
+
+int num_cus() {
+  static int n = 0;
+  if (n == 0) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) == hipSuccess) n = p.multiProcessorCount;
+    if (n <= 0) n = 256;
+  }
+  return n;
+}
+
+// ---------------------------------------------------------------------------
+// Cache sampling
+// ---------------------------------------------------------------------------
+__device__ void candidate_point(const SceneDev& S, int e, double r, double v, double l, double* x) {
+  if (S.dim == 2) {
+    const int ns = S.np * S.sides;
+    if (e < ns) {
+      const int p = e / S.sides;
+      const double side = (e % S.sides == 0) ? 1.0 : -1.0;
+      const double* a = S.V + 2 * (size_t)S.P[2 * p];
+      const double* b = S.V + 2 * (size_t)S.P[2 * p + 1];
+      const double t0 = b[0] - a[0], t1 = b[1] - a[1];
+      const double len = sqrt(t0 * t0 + t1 * t1);
+      const double n0 = t1 / len, n1 = -t0 / len;  // outward normal of a CCW polygon
+      x[0] = (a[0] + r * t0) - side * l * n0;
+      x[1] = (a[1] + r * t1) - side * l * n1;
+    } else {
+      const double* c = S.V + 2 * (size_t)(e - ns);
+      double s, cs;
+      sincos(2 * kPi * r, &s, &cs);
+      x[0] = c[0] + l * cs;
+      x[1] = c[1] + l * s;
+    }
+    return;
+  }
+  if (e < S.np) {
+    const double* A = S.V + 3 * (size_t)S.P[3 * e];
+    const double* B = S.V + 3 * (size_t)S.P[3 * e + 1];
+    const double* C = S.V + 3 * (size_t)S.P[3 * e + 2];
+    const double su = sqrt(r);
+    const double b0 = 1 - su, b1 = su * (1 - v), b2 = su * v;
+    double ab[3], ac[3];
+    for (int a = 0; a < 3; ++a) {
+      ab[a] = B[a] - A[a];
+      ac[a] = C[a] - A[a];
+    }
+    const double nn[3] = {ab[1] * ac[2] - ab[2] * ac[1], ab[2] * ac[0] - ab[0] * ac[2],
+                          ab[0] * ac[1] - ab[1] * ac[0]};
+    const double len = sqrt(nn[0] * nn[0] + nn[1] * nn[1] + nn[2] * nn[2]);
+    for (int a = 0; a < 3; ++a) x[a] = b0 * A[a] + b1 * B[a] + b2 * C[a] - l * nn[a] / len;
+  } else if (e < S.np + S.ne) {
+    const int q = e - S.np;
+    const double* A = S.V + 3 * (size_t)S.E[2 * q];
+    const double* B = S.V + 3 * (size_t)S.E[2 * q + 1];
+    double t[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
+    const double len = sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+    for (int a = 0; a < 3; ++a) t[a] /= len;
+    int ax = 0;
+    for (int a = 1; a < 3; ++a)
+      if (fabs(t[a]) < fabs(t[ax])) ax = a;
+    double h[3] = {0, 0, 0};
+    h[ax] = 1;
+    double e1[3] = {t[1] * h[2] - t[2] * h[1], t[2] * h[0] - t[0] * h[2], t[0] * h[1] - t[1] * h[0]};
+    const double l1 = sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+    for (int a = 0; a < 3; ++a) e1[a] /= l1;
+    const double e2[3] = {t[1] * e1[2] - t[2] * e1[1], t[2] * e1[0] - t[0] * e1[2],
+                          t[0] * e1[1] - t[1] * e1[0]};
+    double s, cs;
+    sincos(2 * kPi * v, &s, &cs);
+    for (int a = 0; a < 3; ++a) x[a] = A[a] + r * (B[a] - A[a]) + l * (cs * e1[a] + s * e2[a]);
+  } else {
+    const double* c = S.V + 3 * (size_t)(e - S.np - S.ne);
+    const double z = 1 - 2 * r;
+    const double rho = sqrt(fmax(0.0, 1 - z * z));
+    double s, cs;
+    sincos(2 * kPi * v, &s, &cs);
+    x[0] = c[0] + l * rho * cs;
+    x[1] = c[1] + l * rho * s;
+    x[2] = c[2] + l * z;
+  }
+}
+
+template <int D>
+__device__ bool inside_point(const SceneDev& S, const double* x, int leaf_prim) {
+  if constexpr (D == 2) return winding_number(S, x) != 0;
+  else return inside_3d(S, x, S.prim_id[leaf_prim]);
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_sample_cache(SceneDev S, int64_t n, double l, uint64_t seed,
+                                                          uint32_t batch, double M, double* x, double* nrm,
+                                                          double* w, double* xbar, double* R0, int* acc) {
+  extern __shared__ uint2 lds[];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double ua, ub;
+  Uniform<double>::pair(seed, 0, (uint32_t)k, batch, 3, ua, ub);
+  const double target = ((double)k + ua) / (double)n * M;
+  int lo = 0, hi = S.n_el - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (S.cdf[mid] <= target) lo = mid;
+    else hi = mid - 1;
+  }
+  double r = (target - S.cdf[lo]) / S.meas[lo];
+  r = fmin(fmax(r, 0.0), 1.0);
+  double xc[D];
+  candidate_point(S, lo, r, ub, l, xc);
+  double q[D];
+  int hint = -1;
+  const double d = sqrt(closest_point<double, D>(S, xc, hint, q, lds + threadIdx.x, blockDim.x));
+  const bool ok = d >= l * (1 - 1e-9) && inside_point<D>(S, xc, hint);
+  acc[k] = ok ? 1 : 0;
+  R0[k] = d;
+  w[k] = M / (double)n;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    x[a * n + k] = xc[a];
+    xbar[a * n + k] = q[a];
+    nrm[a * n + k] = (q[a] - xc[a]) / d;
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_sample_sources(SceneDev S, FieldDev f, int64_t m, int64_t M, double lo0,
+                                                            double lo1, double lo2, double hi0, double hi1,
+                                                            double hi2, double l, uint64_t seed, uint32_t batch,
+                                                            double* y, double* s) {
+  extern __shared__ uint2 lds[];
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= M) return;
+  double u[4];
+  Uniform<double>::pair(seed, 0, (uint32_t)j, batch, 4, u[0], u[1]);
+  Uniform<double>::pair(seed, 1, (uint32_t)j, batch, 4, u[2], u[3]);
+  const double lo[3] = {lo0, lo1, lo2}, hi[3] = {hi0, hi1, hi2};
+  double yj[D];
+  int64_t rem = j;
+  double vol = 1.0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const int64_t c = rem % m;
+    rem /= m;
+    yj[a] = lo[a] + ((double)c + u[a]) / (double)m * (hi[a] - lo[a]);
+    vol *= hi[a] - lo[a];
+    y[a * M + j] = yj[a];
+  }
+  double q[D];
+  int hint = -1;
+  const double d = sqrt(closest_point<double, D>(S, yj, hint, q, lds + threadIdx.x, blockDim.x));
+  const bool in = inside_point<D>(S, yj, hint) && d > l;
+  s[j] = in ? vol / (double)M * field_value(f, D, yj) : 0.0;
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_classify(SceneDev S, int64_t n, const double* x, double l, int* cls,
+                                                      double* dist) {
+  extern __shared__ uint2 lds[];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double xk[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) xk[a] = x[a * n + k];
+  double q[D];
+  int hint = -1;
+  const double d = sqrt(closest_point<double, D>(S, xk, hint, q, lds + threadIdx.x, blockDim.x));
+  const bool in = inside_point<D>(S, xk, hint);
+  cls[k] = !in ? 0 : (d > l ? 1 : 2);
+  if (dist) dist[k] = d;
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic compaction: per-block counts, one-block scan, scatter.
+// ---------------------------------------------------------------------------
+constexpr int kCompactItems = 4;  // items per thread
+constexpr int kCompactTile = kBlock * kCompactItems;
+
+__global__ __launch_bounds__(kBlock) void k_compact_count(int64_t n, const int* flags, int want, int* counts) {
+  __shared__ int part[kBlock / 64];
+  const int64_t base = (int64_t)blockIdx.x * kCompactTile;
+  int c = 0;
+  for (int i = 0; i < kCompactItems; ++i) {
+    const int64_t k = base + (int64_t)i * kBlock + threadIdx.x;
+    c += (k < n && flags[k] == want) ? 1 : 0;
+  }
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int wv = 0; wv < kBlock / 64; ++wv) t += part[wv];
+    counts[blockIdx.x] = t;
+  }
+}
+
+__global__ void k_compact_scan(int nb, int* counts, int64_t* total) {
+  // single block: sequential chunks with a block-wide scan per chunk
+  __shared__ int buf[1024];
+  __shared__ int carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int base = 0; base < nb; base += 1024) {
+    const int i = base + threadIdx.x;
+    const int v = i < nb ? counts[i] : 0;
+    buf[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+      const int add = threadIdx.x >= off ? buf[threadIdx.x - off] : 0;
+      __syncthreads();
+      buf[threadIdx.x] += add;
+      __syncthreads();
+    }
+    if (i < nb) counts[i] = carry + buf[threadIdx.x] - v;  // exclusive
+    __syncthreads();
+    if (threadIdx.x == 1023) carry += buf[1023];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ __launch_bounds__(kBlock) void k_compact_scatter(int64_t n, const int* flags, int want,
+                                                             const int* offsets, int* idx) {
+  __shared__ int wave_tot[kBlock / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int run = offsets[blockIdx.x];
+  const int64_t base = (int64_t)blockIdx.x * kCompactTile;
+  for (int i = 0; i < kCompactItems; ++i) {
+    const int64_t k = base + (int64_t)i * kBlock + threadIdx.x;
+    const bool f = k < n && flags[k] == want;
+    const uint64_t m = __ballot(f);
+    if (lane == 0) wave_tot[wv] = __popcll(m);
+    __syncthreads();
+    int before = 0;
+    for (int q = 0; q < wv; ++q) before += wave_tot[q];
+    if (f) idx[run + before + __popcll(m & ((1ull << lane) - 1))] = (int)k;
+    int tot = 0;
+    for (int q = 0; q < kBlock / 64; ++q) tot += wave_tot[q];
+    __syncthreads();
+    run += tot;
+  }
+}
+
+template <typename Ti, typename To>
+__global__ void k_take(int64_t n_idx, const int* idx, int rows, int64_t ld_in, const Ti* in, int64_t ld_out,
+                       To* out) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n_idx) return;
+  const int64_t src = idx ? idx[q] : q;
+  for (int r = 0; r < rows; ++r) out[r * ld_out + q] = (To)in[r * ld_in + src];
+}
+
+template <typename T>
+__global__ void k_scatter(int64_t n_idx, const int* idx, int rows, int64_t ld_in, const T* in, int64_t ld_out,
+                          T* out) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n_idx) return;
+  for (int r = 0; r < rows; ++r) out[r * ld_out + idx[q]] = in[r * ld_in + q];
+}
+
+// ---------------------------------------------------------------------------
+// Walks
+// ---------------------------------------------------------------------------
+struct WalkArgs {
+  SceneDev S;
+  FieldDev g, f;
+  double eps;
+  int max_steps;
+  int W;
+  uint64_t seed;
+  uint32_t batch;
+  int cv;
+  uint64_t total;
+  int64_t n_pts;
+  const double* x;     // mode 0: cache points [D][n] FP64
+  const double* nrm;
+  const double* R0;
+  const double* xbar;
+  const void* px;      // mode 1: evaluation points [D][n] of T
+  void* U;
+  void* Dout;          // mode 0: n.grad [n*W]; mode 1: grad [D][n*W] (optional)
+  void* rec_exit;
+  void* rec_w1;
+  int* rec_steps;
+  unsigned long long* counters;
+};
+
+template <typename T, int D, bool SRC, int MODE>
+__global__ __launch_bounds__(kBlock) void k_walks(WalkArgs a) {
+  extern __shared__ uint2 lds[];
+  uint2* stk = lds + threadIdx.x;
+  const int stride = blockDim.x;
+  const int lane = threadIdx.x & 63;
+  const uint32_t tag = MODE == 0 ? 1u : 2u;
+  const T eps = (T)a.eps;
+  const SceneDev& S = a.S;
+  T* U = (T*)a.U;
+  T* Dv = (T*)a.Dout;
+
+  bool active = false, exhausted = false;
+  uint32_t id = 0;
+  int k = 0, hint = -1;
+  T p[D], gw[D], gs[D];
+  T acc_s = T(0), w1 = T(0), usrc = T(0), dsrc = T(0);
+  double cv = 0.0;
+  unsigned long long steps_acc = 0, capped_acc = 0, walks_acc = 0;
+#pragma unroll
+  for (int q = 0; q < D; ++q) {
+    p[q] = T(0);
+    gw[q] = T(0);
+    gs[q] = T(0);
+  }
+
+  while (true) {
+    if (!exhausted) {
+      const uint64_t need = __ballot(!active);
+      if (need) {
+        const int leader = __ffsll((unsigned long long)need) - 1;
+        const int cnt = __popcll(need);
+        unsigned long long base = 0;
+        if (lane == leader) base = atomicAdd(&a.counters[0], (unsigned long long)cnt);
+        base = __shfl(base, leader);
+        if (base + cnt >= a.total) exhausted = true;
+        if (!active) {
+          const unsigned long long my = base + __popcll(need & ((1ull << lane) - 1));
+          if (my < a.total) {
+            id = (uint32_t)my;
+            const int64_t i = (int64_t)(id / (uint32_t)a.W);
+            T x0[D], R0;
+            double xb[D];
+            bool start = true;
+            if constexpr (MODE == 0) {
+#pragma unroll
+              for (int q = 0; q < D; ++q) {
+                x0[q] = (T)a.x[q * a.n_pts + i];
+                xb[q] = a.xbar[q * a.n_pts + i];
+              }
+              R0 = (T)a.R0[i];
+              hint = -1;
+            } else {
+              const T* px = (const T*)a.px;
+#pragma unroll
+              for (int q = 0; q < D; ++q) x0[q] = px[q * a.n_pts + i];
+              T qq[D];
+              hint = -1;
+              R0 = fsqrt(closest_point<T, D>(S, x0, hint, qq, stk, stride));
+#pragma unroll
+              for (int q = 0; q < D; ++q) xb[q] = (double)qq[q];
+              if (R0 < eps) {
+                // already inside the epsilon shell: the walk returns g(xbar)
+                U[id] = (T)field_value(a.g, D, xb);
+                if (Dv) {
+                  for (int q = 0; q < D; ++q) Dv[(size_t)q * a.total + id] = T(0);
+                }
+                if (a.rec_exit) {
+#pragma unroll
+                  for (int q = 0; q < D; ++q) ((T*)a.rec_exit)[(size_t)q * a.total + id] = (T)xb[q];
+                }
+                if (a.rec_w1) ((T*)a.rec_w1)[id] = T(0);
+                if (a.rec_steps) a.rec_steps[id] = 0;
+                ++walks_acc;
+                start = false;
+              }
+            }
+            if (start) {
+              T nu0[D];
+              walk_direction<T, D>(a.seed, 0, id, a.batch, tag, nu0);
+              T dn = T(0);
+#pragma unroll
+              for (int q = 0; q < D; ++q) {
+                p[q] = x0[q] + R0 * nu0[q];
+                if constexpr (MODE == 0) dn += nu0[q] * (T)a.nrm[q * a.n_pts + i];
+                gw[q] = (T)D / R0 * nu0[q];
+                gs[q] = T(0);
+              }
+              w1 = (T)D / R0 * dn;
+              cv = a.cv ? field_value(a.g, D, xb) : 0.0;
+              usrc = T(0);
+              dsrc = T(0);
+              if constexpr (SRC) {
+                T yu[D];
+                ball_source_point<T, D>(a.seed, 0, id, a.batch, tag, x0, R0, yu);
+                usrc = -R0 * R0 / (T)(2 * D) * source_value<T, D>(a.f, yu);
+                if constexpr (D == 2) {
+                  // gradient source sample, radius density (3/2)(1 - s^2)
+                  T u1, u2, u3, u4;
+                  Uniform<T>::pair(a.seed, 2, id, a.batch, tag, u1, u2);
+                  Uniform<T>::pair(a.seed, 3, id, a.batch, tag, u3, u4);
+                  const T sg = T(2) * sin(asin(u2) / T(3));
+                  T sn, cs;
+                  sincos_turns(u3, &sn, &cs);
+                  const T yg[2] = {x0[0] + R0 * sg * cs, x0[1] + R0 * sg * sn};
+                  const T fg = source_value<T, D>(a.f, yg);
+                  const T c = -T(2) * R0 / T(3) * fg;
+                  gs[0] = c * cs;
+                  gs[1] = c * sn;
+                  if constexpr (MODE == 0)
+                    dsrc = c * (cs * (T)a.nrm[i] + sn * (T)a.nrm[a.n_pts + i]);
+                }
+              }
+              acc_s = T(0);
+              k = 1;
+              active = true;
+            }
+          }
+        }
+      }
+    }
+    if (!__any(active)) {
+      if (exhausted) break;
+      continue;
+    }
+    if (active) {
+      T q[D];
+      const T d = fsqrt(closest_point<T, D>(S, p, hint, q, stk, stride));
+      const bool stop = d < eps;
+      const bool cap = !stop && k >= a.max_steps;
+      if (stop || cap) {
+        double qd[D];
+#pragma unroll
+        for (int c = 0; c < D; ++c) qd[c] = (double)q[c];
+        const double Wd = field_value(a.g, D, qd) + (double)acc_s;
+        U[id] = (T)(Wd + (double)usrc);
+        if constexpr (MODE == 0) {
+          Dv[id] = (T)((double)w1 * (Wd - cv) + (double)dsrc);
+        } else if (Dv) {
+#pragma unroll
+          for (int c = 0; c < D; ++c) Dv[(size_t)c * a.total + id] = (T)((double)gw[c] * (Wd - cv) + (double)gs[c]);
+        }
+        if (a.rec_exit) {
+#pragma unroll
+          for (int c = 0; c < D; ++c) ((T*)a.rec_exit)[(size_t)c * a.total + id] = q[c];
+        }
+        if (a.rec_w1) ((T*)a.rec_w1)[id] = w1;
+        if (a.rec_steps) a.rec_steps[id] = k;
+        steps_acc += (unsigned long long)k;
+        capped_acc += cap ? 1ull : 0ull;
+        ++walks_acc;
+        active = false;
+      } else {
+        if constexpr (SRC) {
+          T y[D];
+          ball_source_point<T, D>(a.seed, (uint32_t)k, id, a.batch, tag, p, d, y);
+          acc_s -= d * d / (T)(2 * D) * source_value<T, D>(a.f, y);
+        }
+        T nu[D];
+        walk_direction<T, D>(a.seed, (uint32_t)k, id, a.batch, tag, nu);
+#pragma unroll
+        for (int c = 0; c < D; ++c) p[c] += d * nu[c];
+        ++k;
+      }
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    steps_acc += __shfl_xor(steps_acc, off);
+    capped_acc += __shfl_xor(capped_acc, off);
+    walks_acc += __shfl_xor(walks_acc, off);
+  }
+  if (lane == 0) {
+    atomicAdd(&a.counters[1], steps_acc);
+    atomicAdd(&a.counters[2], capped_acc);
+    atomicAdd(&a.counters[3], walks_acc);
+  }
+}
+
+// Means of W samples per point in FP64, one wave per point, fixed order.
+template <typename Ti, typename To>
+__global__ __launch_bounds__(kBlock) void k_reduce(int64_t n, int W, int rows, int64_t ld, const Ti* U,
+                                                    const Ti* G, const double* w, double* uhat, double* ghat,
+                                                    To* a, To* b, int64_t ld_g) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (i >= n) return;
+  double su = 0.0;
+  double sg[3] = {0.0, 0.0, 0.0};
+  for (int j = lane; j < W; j += 64) {
+    su += (double)U[i * W + j];
+    for (int r = 0; r < rows; ++r) sg[r] += (double)G[r * ld + i * W + j];
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    su += __shfl_xor(su, off);
+    for (int r = 0; r < rows; ++r) sg[r] += __shfl_xor(sg[r], off);
+  }
+  if (lane == 0) {
+    const double mu = su / W;
+    if (uhat) uhat[i] = mu;
+    if (a) a[i] = (To)(w ? mu * w[i] : mu);
+    for (int r = 0; r < rows; ++r) {
+      const double mg = sg[r] / W;
+      if (ghat) ghat[r * ld_g + i] = mg;
+      if (b) b[r * ld_g + i] = (To)(w ? mg * w[i] : mg);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Validation helpers
+// ---------------------------------------------------------------------------
+int check_scene(bvc_scene s) {
+  if (!s) return fail(BVC_EINVAL, "scene is null");
+  if (!s->h.dev) return fail(BVC_ESTATE, "scene is not uploaded");
+  return BVC_OK;
+}
+
+int check_field(const bvc_field& f, int dim, const char* name) {
+  if (f.kind < 0 || f.kind > 7) return fail(BVC_EINVAL, std::string(name) + ": unknown field kind");
+  if (f.n_coef < 0) return fail(BVC_EINVAL, std::string(name) + ": negative coefficient count");
+  if (f.n_coef > 0 && !f.coef) return fail(BVC_EINVAL, std::string(name) + ": coefficients are null");
+  if ((f.kind == 2 || f.kind == 4 || f.kind == 6) && dim != 2)
+    return fail(BVC_EINVAL, std::string(name) + ": 2D field used in 3D");
+  if (f.kind == 5 && dim != 3) return fail(BVC_EINVAL, std::string(name) + ": 3D field used in 2D");
+  if (f.kind == 3 && (f.n_coef % (1 + dim) != 0 || !(f.param[0] > 0)))
+    return fail(BVC_EINVAL, std::string(name) + ": Gaussian sum needs (1+dim)*k coefficients and s > 0");
+  if (f.kind == 4 && (f.n_coef % 3 != 0 || !(f.param[0] > 0)))
+    return fail(BVC_EINVAL, std::string(name) + ": Gaussian potential needs 3*k coefficients and s > 0");
+  if (f.kind == 5) {
+    const int L = (int)f.param[0];
+    if (L < 0 || L > 16 || f.n_coef != (L + 1) * (L + 1))
+      return fail(BVC_EINVAL, std::string(name) + ": solid harmonics need (L+1)^2 coefficients, L <= 16");
+  }
+  if (f.kind == 6 && f.n_coef < 1) return fail(BVC_EINVAL, std::string(name) + ": Fourier series is empty");
+  return BVC_OK;
+}
+
+int check_walk_params(const bvc_walk_params* p, int dim) {
+  if (!p) return fail(BVC_EINVAL, "walk params are null");
+  if (!(p->eps > 0) || !std::isfinite(p->eps)) return fail(BVC_EINVAL, "eps must be positive");
+  if (p->max_steps < 1) return fail(BVC_EINVAL, "max_steps must be >= 1");
+  if (p->n_walks < 1) return fail(BVC_EINVAL, "n_walks must be >= 1");
+  if (p->dtype != BVC_F32 && p->dtype != BVC_F64) return fail(BVC_EINVAL, "walk dtype must be F32 or F64");
+  int rc = check_field(p->g, dim, "g");
+  if (rc) return rc;
+  return check_field(p->f, dim, "f");
+}
+
+template <typename T, int D>
+void launch_walks(const WalkArgs& args, int mode, bool src, int blocks, size_t lds, hipStream_t st) {
+  if (mode == 0) {
+    if (src) hipLaunchKernelGGL((k_walks<T, D, true, 0>), dim3(blocks), dim3(kBlock), lds, st, args);
+    else hipLaunchKernelGGL((k_walks<T, D, false, 0>), dim3(blocks), dim3(kBlock), lds, st, args);
+  } else {
+    if (src) hipLaunchKernelGGL((k_walks<T, D, true, 1>), dim3(blocks), dim3(kBlock), lds, st, args);
+    else hipLaunchKernelGGL((k_walks<T, D, false, 1>), dim3(blocks), dim3(kBlock), lds, st, args);
+  }
+}
+
+int run_walks(bvc_scene s, const bvc_walk_params* p, int mode, int64_t n, WalkArgs& args, hipStream_t st) {
+  const SceneHost& h = s->h;
+  const uint64_t total = (uint64_t)n * (uint64_t)p->n_walks;
+  args.S = h.view();
+  args.g = to_dev(p->g);
+  args.f = to_dev(p->f);
+  args.eps = p->eps;
+  args.max_steps = p->max_steps;
+  args.W = p->n_walks;
+  args.seed = p->seed;
+  args.batch = p->batch;
+  args.cv = p->control_variate;
+  args.total = total;
+  args.n_pts = n;
+  int rc = check_hip(hipMemsetAsync(args.counters, 0, 4 * sizeof(unsigned long long), st), "counter reset");
+  if (rc || total == 0) return rc;
+  int blocks = p->blocks > 0 ? p->blocks : num_cus() * 4;
+  const int64_t needed = (int64_t)((total + kBlock - 1) / kBlock);
+  blocks = (int)std::max<int64_t>(1, std::min<int64_t>(blocks, needed));
+  const size_t lds = stack_bytes(h, kBlock);
+  const bool src = p->f.kind != 0;
+  if (h.dim == 2) {
+    if (p->dtype == BVC_F32) launch_walks<float, 2>(args, mode, src, blocks, lds, st);
+    else launch_walks<double, 2>(args, mode, src, blocks, lds, st);
+  } else {
+    if (p->dtype == BVC_F32) launch_walks<float, 3>(args, mode, src, blocks, lds, st);
+    else launch_walks<double, 3>(args, mode, src, blocks, lds, st);
+  }
+  return check_hip(hipGetLastError(), "walk launch");
+}
+
+}  // namespace
+}  // namespace bvc
+
+using namespace bvc;
+
+extern "C" {
+
+int bvc_sample_cache(bvc_scene s, int64_t n, double l, int32_t sides, uint64_t seed, uint32_t batch,
+                     double* x, double* nrm, double* w, double* xbar, double* R0, int32_t* accept,
+                     void* stream) {
+  int rc = check_scene(s);
+  if (rc) return rc;
+  if (n < 0 || n >= (int64_t)1 << 31) return fail(BVC_EINVAL, "n out of range");
+  if (!(l > 0) || !std::isfinite(l)) return fail(BVC_EINVAL, "offset l must be positive");
+  if (sides != 1 && sides != 2) return fail(BVC_EINVAL, "sides must be 1 or 2");
+  if (sides == 2 && s->h.dim == 3) return fail(BVC_EUNSUPPORTED, "two-sided offsets are 2D only");
+  if (n == 0) return BVC_OK;
+  if (!x || !nrm || !w || !xbar || !R0 || !accept) return fail(BVC_EINVAL, "null output");
+  hipStream_t st = (hipStream_t)stream;
+  rc = ensure_cdf(s->h, l, sides, st);
+  if (rc) return rc;
+  const double M = candidate_measure(s->h, l, sides);
+  SceneDev S = s->h.view();
+  const int blocks = (int)((n + kBlock - 1) / kBlock);
+  const size_t lds = stack_bytes(s->h, kBlock);
+  if (S.dim == 2)
+    hipLaunchKernelGGL(k_sample_cache<2>, dim3(blocks), dim3(kBlock), lds, st, S, n, l, seed, batch, M, x, nrm, w,
+                       xbar, R0, accept);
+  else
+    hipLaunchKernelGGL(k_sample_cache<3>, dim3(blocks), dim3(kBlock), lds, st, S, n, l, seed, batch, M, x, nrm, w,
+                       xbar, R0, accept);
+  return check_hip(hipGetLastError(), "sample_cache launch");
+}
+
+int bvc_sample_sources(bvc_scene s, const bvc_field* f, int64_t m, const double* lo, const double* hi, double l,
+                       uint64_t seed, uint32_t batch, double* y, double* sw, void* stream) {
+  int rc = check_scene(s);
+  if (rc) return rc;
+  if (!f || !lo || !hi) return fail(BVC_EINVAL, "null argument");
+  const int dim = s->h.dim;
+  rc = check_field(*f, dim, "f");
+  if (rc) return rc;
+  if (m < 0) return fail(BVC_EINVAL, "m must be >= 0");
+  int64_t M = 1;
+  for (int a = 0; a < dim; ++a) {
+    M *= m;
+    if (!(hi[a] > lo[a])) return fail(BVC_EINVAL, "empty source box");
+  }
+  if (M >= (int64_t)1 << 31) return fail(BVC_EINVAL, "too many sources");
+  if (m == 0) return BVC_OK;
+  if (!y || !sw) return fail(BVC_EINVAL, "null output");
+  if (!(l >= 0)) return fail(BVC_EINVAL, "l must be >= 0");
+  hipStream_t st = (hipStream_t)stream;
+  SceneDev S = s->h.view();
+  const int blocks = (int)((M + kBlock - 1) / kBlock);
+  const size_t lds = stack_bytes(s->h, kBlock);
+  const double z0 = dim == 3 ? lo[2] : 0.0, z1 = dim == 3 ? hi[2] : 1.0;
+  if (dim == 2)
+    hipLaunchKernelGGL(k_sample_sources<2>, dim3(blocks), dim3(kBlock), lds, st, S, to_dev(*f), m, M, lo[0], lo[1],
+                       z0, hi[0], hi[1], z1, l, seed, batch, y, sw);
+  else
+    hipLaunchKernelGGL(k_sample_sources<3>, dim3(blocks), dim3(kBlock), lds, st, S, to_dev(*f), m, M, lo[0], lo[1],
+                       z0, hi[0], hi[1], z1, l, seed, batch, y, sw);
+  return check_hip(hipGetLastError(), "sample_sources launch");
+}
+
+int bvc_classify(bvc_scene s, int64_t n, const double* x, double l, int32_t* cls, double* dist, void* stream) {
+  int rc = check_scene(s);
+  if (rc) return rc;
+  if (n < 0 || n >= (int64_t)1 << 31) return fail(BVC_EINVAL, "n out of range");
+  if (!(l >= 0)) return fail(BVC_EINVAL, "l must be >= 0");
+  if (n == 0) return BVC_OK;
+  if (!x || !cls) return fail(BVC_EINVAL, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  SceneDev S = s->h.view();
+  const int blocks = (int)((n + kBlock - 1) / kBlock);
+  const size_t lds = stack_bytes(s->h, kBlock);
+  if (S.dim == 2)
+    hipLaunchKernelGGL(k_classify<2>, dim3(blocks), dim3(kBlock), lds, st, S, n, x, l, cls, dist);
+  else
+    hipLaunchKernelGGL(k_classify<3>, dim3(blocks), dim3(kBlock), lds, st, S, n, x, l, cls, dist);
+  return check_hip(hipGetLastError(), "classify launch");
+}
+
+int64_t bvc_compact_scratch_ints(int64_t n) { return (n + kCompactTile - 1) / kCompactTile + 4; }
+
+int bvc_compact(int64_t n, const int32_t* flags, int32_t want, int32_t* idx, int32_t* scratch,
+                int64_t* count_host, void* stream) {
+  if (n < 0 || n >= (int64_t)1 << 31) return fail(BVC_EINVAL, "n out of range");
+  if (!count_host) return fail(BVC_EINVAL, "count_host is null");
+  *count_host = 0;
+  if (n == 0) return BVC_OK;
+  if (!flags || !idx || !scratch) return fail(BVC_EINVAL, "null argument");
+  if (((uintptr_t)scratch & 7) != 0) return fail(BVC_EINVAL, "scratch must be 8-byte aligned");
+  hipStream_t st = (hipStream_t)stream;
+  const int nb = (int)((n + kCompactTile - 1) / kCompactTile);
+  int* offs = scratch + 2;
+  int64_t* tot = (int64_t*)scratch;
+  int rc = BVC_OK;
+  hipLaunchKernelGGL(k_compact_count, dim3(nb), dim3(kBlock), 0, st, n, flags, want, offs);
+  hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, st, nb, offs, tot);
+  hipLaunchKernelGGL(k_compact_scatter, dim3(nb), dim3(kBlock), 0, st, n, flags, want, offs, idx);
+  rc = check_hip(hipGetLastError(), "compact launch");
+  int64_t h = 0;
+  if (!rc) rc = check_hip(hipMemcpyAsync(&h, tot, sizeof(int64_t), hipMemcpyDeviceToHost, st), "compact count");
+  if (!rc) rc = check_hip(hipStreamSynchronize(st), "compact sync");
+  if (!rc) *count_host = h;
+  return rc;
+}
+
+int bvc_take(int32_t dti, int32_t dto, int64_t n_idx, const int32_t* idx, int32_t rows, int64_t ld_in,
+             const void* in, int64_t ld_out, void* out, void* stream) {
+  if ((dti != BVC_F32 && dti != BVC_F64) || (dto != BVC_F32 && dto != BVC_F64))
+    return fail(BVC_EINVAL, "dtype must be F32 or F64");
+  if (n_idx < 0 || rows < 0 || ld_in < 0 || ld_out < n_idx) return fail(BVC_EINVAL, "bad sizes");
+  if (n_idx == 0 || rows == 0) return BVC_OK;
+  if (!in || !out) return fail(BVC_EINVAL, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  const int blocks = (int)((n_idx + kBlock - 1) / kBlock);
+  if (dti == BVC_F64 && dto == BVC_F64)
+    hipLaunchKernelGGL((k_take<double, double>), dim3(blocks), dim3(kBlock), 0, st, n_idx, idx, rows, ld_in,
+                       (const double*)in, ld_out, (double*)out);
+  else if (dti == BVC_F64 && dto == BVC_F32)
+    hipLaunchKernelGGL((k_take<double, float>), dim3(blocks), dim3(kBlock), 0, st, n_idx, idx, rows, ld_in,
+                       (const double*)in, ld_out, (float*)out);
+  else if (dti == BVC_F32 && dto == BVC_F64)
+    hipLaunchKernelGGL((k_take<float, double>), dim3(blocks), dim3(kBlock), 0, st, n_idx, idx, rows, ld_in,
+                       (const float*)in, ld_out, (double*)out);
+  else
+    hipLaunchKernelGGL((k_take<float, float>), dim3(blocks), dim3(kBlock), 0, st, n_idx, idx, rows, ld_in,
+                       (const float*)in, ld_out, (float*)out);
+  return check_hip(hipGetLastError(), "take launch");
+}
+
+int bvc_scatter(int32_t dtype, int64_t n_idx, const int32_t* idx, int32_t rows, int64_t ld_in, const void* in,
+                int64_t ld_out, void* out, void* stream) {
+  if (dtype != BVC_F32 && dtype != BVC_F64) return fail(BVC_EINVAL, "dtype must be F32 or F64");
+  if (n_idx < 0 || rows < 0 || ld_in < n_idx || ld_out < 0) return fail(BVC_EINVAL, "bad sizes");
+  if (n_idx == 0 || rows == 0) return BVC_OK;
+  if (!in || !out || !idx) return fail(BVC_EINVAL, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  const int blocks = (int)((n_idx + kBlock - 1) / kBlock);
+  if (dtype == BVC_F64)
+    hipLaunchKernelGGL(k_scatter<double>, dim3(blocks), dim3(kBlock), 0, st, n_idx, idx, rows, ld_in,
+                       (const double*)in, ld_out, (double*)out);
+  else
+    hipLaunchKernelGGL(k_scatter<float>, dim3(blocks), dim3(kBlock), 0, st, n_idx, idx, rows, ld_in,
+                       (const float*)in, ld_out, (float*)out);
+  return check_hip(hipGetLastError(), "scatter launch");
+}
+
+int bvc_cache_walks(bvc_scene s, const bvc_walk_params* p, int64_t n_cache, const double* x, const double* nrm,
+                    const double* R0, const double* xbar, void* U, void* D, void* rec_exit, void* rec_w1,
+                    int32_t* rec_steps, uint64_t* counters, void* stream) {
+  int rc = check_scene(s);
+  if (rc) return rc;
+  rc = check_walk_params(p, s->h.dim);
+  if (rc) return rc;
+  if (n_cache < 0) return fail(BVC_EINVAL, "n_cache must be >= 0");
+  if ((uint64_t)n_cache * (uint64_t)p->n_walks >= (1ull << 32)) return fail(BVC_EINVAL, "n_cache * W >= 2^32");
+  if (!counters) return fail(BVC_EINVAL, "counters is null");
+  if (n_cache > 0 && (!x || !nrm || !R0 || !xbar || !U || !D)) return fail(BVC_EINVAL, "null input/output");
+  WalkArgs a{};
+  a.x = x;
+  a.nrm = nrm;
+  a.R0 = R0;
+  a.xbar = xbar;
+  a.U = U;
+  a.Dout = D;
+  a.rec_exit = rec_exit;
+  a.rec_w1 = rec_w1;
+  a.rec_steps = rec_steps;
+  a.counters = (unsigned long long*)counters;
+  return run_walks(s, p, 0, n_cache, a, (hipStream_t)stream);
+}
+
+int bvc_reduce_walks(int64_t n_cache, int32_t W, int32_t dti, const void* U, const void* D, const double* w,
+                     double* uhat, double* dudn, int32_t dto, void* a, void* b, void* stream) {
+  if (n_cache < 0 || W < 1) return fail(BVC_EINVAL, "bad sizes");
+  if ((dti != BVC_F32 && dti != BVC_F64) || (dto != BVC_F32 && dto != BVC_F64))
+    return fail(BVC_EINVAL, "dtype must be F32 or F64");
+  if (n_cache == 0) return BVC_OK;
+  if (!U || !D) return fail(BVC_EINVAL, "null input");
+  if ((a || b) && !w) return fail(BVC_EINVAL, "weights are null");
+  hipStream_t st = (hipStream_t)stream;
+  const int per = kBlock / 64;
+  const int blocks = (int)((n_cache + per - 1) / per);
+  const int64_t ld = n_cache * (int64_t)W;
+  if (dti == BVC_F32 && dto == BVC_F32)
+    hipLaunchKernelGGL((k_reduce<float, float>), dim3(blocks), dim3(kBlock), 0, st, n_cache, W, 1, ld,
+                       (const float*)U, (const float*)D, w, uhat, dudn, (float*)a, (float*)b, n_cache);
+  else if (dti == BVC_F32)
+    hipLaunchKernelGGL((k_reduce<float, double>), dim3(blocks), dim3(kBlock), 0, st, n_cache, W, 1, ld,
+                       (const float*)U, (const float*)D, w, uhat, dudn, (double*)a, (double*)b, n_cache);
+  else if (dto == BVC_F32)
+    hipLaunchKernelGGL((k_reduce<double, float>), dim3(blocks), dim3(kBlock), 0, st, n_cache, W, 1, ld,
+                       (const double*)U, (const double*)D, w, uhat, dudn, (float*)a, (float*)b, n_cache);
+  else
+    hipLaunchKernelGGL((k_reduce<double, double>), dim3(blocks), dim3(kBlock), 0, st, n_cache, W, 1, ld,
+                       (const double*)U, (const double*)D, w, uhat, dudn, (double*)a, (double*)b, n_cache);
+  return check_hip(hipGetLastError(), "reduce launch");
+}
+
+int bvc_pointwise_wos(bvc_scene s, const bvc_walk_params* p, int64_t n, const void* x, void* U_walk, void* G_walk,
+                      void* u, void* grad, uint64_t* counters, void* stream) {
+  int rc = check_scene(s);
+  if (rc) return rc;
+  rc = check_walk_params(p, s->h.dim);
+  if (rc) return rc;
+  if (n < 0) return fail(BVC_EINVAL, "n must be >= 0");
+  if ((uint64_t)n * (uint64_t)p->n_walks >= (1ull << 32)) return fail(BVC_EINVAL, "n * W >= 2^32");
+  if (!counters) return fail(BVC_EINVAL, "counters is null");
+  if (n > 0 && (!x || !U_walk || !u)) return fail(BVC_EINVAL, "null input/output");
+  if (grad && !G_walk) return fail(BVC_EINVAL, "grad needs G_walk scratch");
+  WalkArgs a{};
+  a.px = x;
+  a.U = U_walk;
+  a.Dout = G_walk;
+  a.counters = (unsigned long long*)counters;
+  hipStream_t st = (hipStream_t)stream;
+  rc = run_walks(s, p, 1, n, a, st);
+  if (rc || n == 0) return rc;
+  const int per = kBlock / 64;
+  const int blocks = (int)((n + per - 1) / per);
+  const int rows = grad ? s->h.dim : 0;
+  const int64_t ld = n * (int64_t)p->n_walks;
+  if (p->dtype == BVC_F32)
+    hipLaunchKernelGGL((k_reduce<float, float>), dim3(blocks), dim3(kBlock), 0, st, n, p->n_walks, rows, ld,
+                       (const float*)U_walk, (const float*)G_walk, nullptr, nullptr, nullptr, (float*)u,
+                       (float*)grad, n);
+  else
+    hipLaunchKernelGGL((k_reduce<double, double>), dim3(blocks), dim3(kBlock), 0, st, n, p->n_walks, rows, ld,
+                       (const double*)U_walk, (const double*)G_walk, nullptr, nullptr, nullptr, (double*)u,
+                       (double*)grad, n);
+  return check_hip(hipGetLastError(), "pointwise reduce launch");
+}
+
+}  // extern "C"

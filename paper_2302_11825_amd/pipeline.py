@@ -1,0 +1,270 @@
+"""Boundary Value Caching on one GPU: Algorithm 1 (UpdateSolution) as a
+sequence of C-ABI calls.
+
+    cache points on the offset boundary   bvc_sample_cache + bvc_compact + bvc_take
+    walks from every cache point          bvc_cache_walks            (Section 3.1, Eq. 7)
+    cache means  u-hat, du/dn-hat         bvc_reduce_walks
+    source samples                        bvc_sample_sources         (Eq. 4)
+    interior / band classification        bvc_classify + bvc_compact (Section 3.2)
+    gather of u and grad u                bvc_gather_u / _grad       (Eqs. 3-6)
+    pointwise walks for band points       bvc_pointwise_wos          (Section 3.2)
+
+This module only allocates device memory (torch) and sequences calls; every
+step runs in the library's kernels on torch's current stream.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _bvc as B
+
+DT = {"f32": torch.float32, "f64": torch.float64}
+CODE = {"f32": B.F32, "f64": B.F64}
+
+
+class DeviceField:
+    """A field descriptor with its coefficients resident on the device."""
+
+    def __init__(self, fld, device="cuda"):
+        self.kind = int(fld.kind)
+        self.param = [float(v) for v in fld.param]
+        coef = np.ascontiguousarray(fld.coef, dtype=np.float64)
+        self.coef = torch.from_numpy(coef).to(device) if coef.size else None
+
+    def c(self) -> B.bvc_field:
+        return B.make_field(self.kind, self.coef, self.param)
+
+
+class Scene:
+    """Host BVH build and upload into a torch-owned device buffer."""
+
+    def __init__(self, scene, device="cuda"):
+        self.dim = scene.dim
+        self.h = B.bvc_scene_create(scene.dim, scene.verts, scene.prims)
+        info = B.bvc_scene_get_info(self.h)
+        self.buf = torch.empty(int(info.device_bytes), dtype=torch.uint8, device=device)
+        B.bvc_scene_upload(self.h, self.buf)
+        self.info = B.bvc_scene_get_info(self.h)
+        self.device = device
+        self._scratch = {}
+
+    def __del__(self):
+        try:
+            B.bvc_scene_destroy(self.h)
+        except Exception:
+            pass
+
+    @property
+    def lo(self):
+        return list(self.info.lo)[: self.dim]
+
+    @property
+    def hi(self):
+        return list(self.info.hi)[: self.dim]
+
+    def scratch_int(self, n):
+        k = ("compact", n)
+        if k not in self._scratch:
+            self._scratch[k] = torch.empty(B.bvc_compact_scratch_ints(n), dtype=torch.int32, device=self.device)
+        return self._scratch[k]
+
+    def compact(self, flags, want):
+        n = flags.numel()
+        idx = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
+        cnt = B.bvc_compact(n, flags, want, idx, self.scratch_int(n))
+        return idx, cnt
+
+
+@dataclass
+class Cache:
+    n: int
+    x: torch.Tensor      # [d][n] FP64
+    nrm: torch.Tensor
+    w: torch.Tensor      # [n]
+    xbar: torch.Tensor
+    R0: torch.Tensor
+    n_candidates: int = 0
+
+
+def take(src, idx, n, rows, ld_in, dtype_out=torch.float64):
+    out = torch.empty((rows, max(n, 1)) if rows > 1 else (max(n, 1),), dtype=dtype_out, device=src.device)
+    B.bvc_take(B.dtype_code(src.dtype), B.dtype_code(dtype_out), n, idx, rows, ld_in, src, max(n, 1), out)
+    return out
+
+
+def sample_cache(sc: Scene, n_cand, l, sides, seed, batch=0) -> Cache:
+    d, dev = sc.dim, sc.device
+    f64 = torch.float64
+    x = torch.empty(d, n_cand, dtype=f64, device=dev)
+    nrm = torch.empty_like(x)
+    xbar = torch.empty_like(x)
+    w = torch.empty(n_cand, dtype=f64, device=dev)
+    R0 = torch.empty_like(w)
+    acc = torch.empty(n_cand, dtype=torch.int32, device=dev)
+    B.bvc_sample_cache(sc.h, n_cand, l, sides, seed, batch, x, nrm, w, xbar, R0, acc)
+    idx, n = sc.compact(acc, 1)
+    c = Cache(n, take(x, idx, n, d, n_cand), take(nrm, idx, n, d, n_cand), take(w, idx, n, 1, n_cand),
+              take(xbar, idx, n, d, n_cand), take(R0, idx, n, 1, n_cand), n_cand)
+    return c
+
+
+def candidates_for(sc: Scene, n_target, l, sides, seed, pilot=65536):
+    """Number of candidates whose expected accepted count is n_target, from a
+    pilot draw with an independent batch index."""
+    c = sample_cache(sc, pilot, l, sides, seed, batch=0x7FFFFFFF)
+    rate = max(c.n, 1) / pilot
+    return int(math.ceil(n_target / rate))
+
+
+def walk_params(eps, n_walks, seed, g: DeviceField, f: Optional[DeviceField], dtype="f32", batch=0,
+                max_steps=1024, control_variate=True, blocks=0) -> B.bvc_walk_params:
+    p = B.bvc_walk_params()
+    p.eps = float(eps)
+    p.max_steps = int(max_steps)
+    p.n_walks = int(n_walks)
+    p.seed = int(seed)
+    p.batch = int(batch)
+    p.control_variate = int(bool(control_variate))
+    p.dtype = CODE[dtype]
+    p.blocks = int(blocks)
+    p.g = g.c()
+    p.f = f.c() if f is not None else B.make_field(0, None, [])
+    return p
+
+
+def cache_walks(sc: Scene, cache: Cache, params: B.bvc_walk_params, dtype="f32", records=False):
+    dev = sc.device
+    n, W = cache.n, params.n_walks
+    T = DT[dtype]
+    U = torch.empty(max(n * W, 1), dtype=T, device=dev)
+    D = torch.empty_like(U)
+    rec = None
+    if records:
+        rec = dict(exit=torch.empty(sc.dim, max(n * W, 1), dtype=T, device=dev),
+                   w1=torch.empty(max(n * W, 1), dtype=T, device=dev),
+                   steps=torch.empty(max(n * W, 1), dtype=torch.int32, device=dev))
+    counters = torch.zeros(4, dtype=torch.int64, device=dev)
+    B.bvc_cache_walks(sc.h, params, n, cache.x, cache.nrm, cache.R0, cache.xbar, U, D,
+                      rec["exit"] if rec else None, rec["w1"] if rec else None, rec["steps"] if rec else None,
+                      counters)
+    return U, D, rec, counters
+
+
+def reduce_walks(cache: Cache, W, U, D, dtype_out="f32"):
+    dev = U.device
+    n = cache.n
+    uhat = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
+    dudn = torch.empty_like(uhat)
+    a = torch.empty(max(n, 1), dtype=DT[dtype_out], device=dev)
+    b = torch.empty_like(a)
+    B.bvc_reduce_walks(n, W, B.dtype_code(U.dtype), U, D, cache.w, uhat, dudn, CODE[dtype_out], a, b)
+    return uhat, dudn, a, b
+
+
+def sample_sources(sc: Scene, f: DeviceField, m, l, seed, batch=0, lo=None, hi=None):
+    d, dev = sc.dim, sc.device
+    M = m**d
+    y = torch.empty(d, max(M, 1), dtype=torch.float64, device=dev)
+    s = torch.empty(max(M, 1), dtype=torch.float64, device=dev)
+    B.bvc_sample_sources(sc.h, f.c(), m, lo if lo is not None else sc.lo, hi if hi is not None else sc.hi, l,
+                         seed, batch, y, s)
+    return y, s, M
+
+
+def classify(sc: Scene, x64, l):
+    n = x64.shape[1]
+    cls = torch.empty(max(n, 1), dtype=torch.int32, device=sc.device)
+    dist = torch.empty(max(n, 1), dtype=torch.float64, device=sc.device)
+    B.bvc_classify(sc.h, n, x64, l, cls, dist)
+    return cls, dist
+
+
+@dataclass
+class Solution:
+    idx_int: torch.Tensor
+    n_int: int
+    idx_band: torch.Tensor
+    n_band: int
+    u_int: torch.Tensor
+    g_int: Optional[torch.Tensor]
+    u_band: torch.Tensor
+    g_band: Optional[torch.Tensor]
+    cache: Cache
+    uhat: torch.Tensor
+    dudn: torch.Tensor
+    counters: torch.Tensor
+    pw_counters: torch.Tensor
+    extra: dict = field(default_factory=dict)
+
+
+class Prepared:
+    """Per-scene state reused across solves: device scene, fields, classified
+    evaluation points and the candidate count of the cache sampler."""
+
+    def __init__(self, problem, dtype=None, n_cand=None, device="cuda", eval_x=None):
+        self.p = problem
+        self.dtype = dtype or problem.precision
+        self.sc = Scene(problem.scene, device)
+        self.g = DeviceField(problem.g, device)
+        self.f = DeviceField(problem.f, device) if not problem.f.is_zero else None
+        self.n_cand = n_cand or candidates_for(self.sc, problem.n_cache, problem.offset, problem.sides,
+                                               problem.seed_cache)
+        ex = problem.eval_x if eval_x is None else eval_x
+        self.eval64 = torch.from_numpy(np.ascontiguousarray(ex.T)).to(device)
+        n = self.eval64.shape[1]
+        self.cls, self.dist = classify(self.sc, self.eval64, problem.offset)
+        self.idx_int, self.n_int = self.sc.compact(self.cls, 1)
+        self.idx_band, self.n_band = self.sc.compact(self.cls, 2)
+        T = DT[self.dtype]
+        self.x_int = take(self.eval64, self.idx_int, self.n_int, self.sc.dim, n, T)
+        self.x_band = take(self.eval64, self.idx_band, self.n_band, self.sc.dim, n, T)
+
+
+def solve(prep: Prepared, batch=0, with_grad=True, n_walks_band=None, records=False) -> Solution:
+    p, sc = prep.p, prep.sc
+    dt = prep.dtype
+    T = DT[dt]
+    d = sc.dim
+    cache = sample_cache(sc, prep.n_cand, p.offset, p.sides, p.seed_cache, batch)
+    wp = walk_params(p.eps, p.n_walks, p.seed_walks, prep.g, prep.f, dt, batch)
+    U, D, rec, counters = cache_walks(sc, cache, wp, dt, records)
+    uhat, dudn, a, b = reduce_walks(cache, p.n_walks, U, D, dt)
+    if T != torch.float64:
+        cx = take(cache.x, None, cache.n, d, cache.n, T)
+        cn = take(cache.nrm, None, cache.n, d, cache.n, T)
+    else:
+        cx, cn = cache.x, cache.nrm
+    cview = dict(n=cache.n, dtype=CODE[dt], x=cx, nrm=cn, a=a, b=b)
+    sview = None
+    if prep.f is not None and p.n_sources > 0:
+        m = int(round(p.n_sources ** (1.0 / d)))
+        y64, s64, M = sample_sources(sc, prep.f, m, p.offset, p.seed_sources, batch)
+        if T != torch.float64:
+            y = take(y64, None, M, d, M, T)
+            s = take(s64, None, M, 1, M, T)
+        else:
+            y, s = y64, s64
+        sview = dict(n=M, dtype=CODE[dt], y=y, s=s)
+    n_int = prep.n_int
+    u_int = torch.empty(max(n_int, 1), dtype=T, device=sc.device)
+    g_int = torch.empty(d, max(n_int, 1), dtype=T, device=sc.device) if with_grad else None
+    if with_grad:
+        B.bvc_gather_grad(d, cview, sview, n_int, prep.x_int, u_int, g_int)
+    else:
+        B.bvc_gather_u(d, cview, sview, n_int, prep.x_int, u_int)
+    Wb = n_walks_band or p.n_walks
+    nb = prep.n_band
+    u_band = torch.empty(max(nb, 1), dtype=T, device=sc.device)
+    g_band = torch.empty(d, max(nb, 1), dtype=T, device=sc.device) if with_grad else None
+    Uw = torch.empty(max(nb * Wb, 1), dtype=T, device=sc.device)
+    Gw = torch.empty(d, max(nb * Wb, 1), dtype=T, device=sc.device) if with_grad else None
+    pwc = torch.zeros(4, dtype=torch.int64, device=sc.device)
+    wpb = walk_params(p.eps, Wb, p.seed_walks, prep.g, prep.f, dt, batch)
+    B.bvc_pointwise_wos(sc.h, wpb, nb, prep.x_band, Uw, Gw, u_band, g_band, pwc)
+    return Solution(prep.idx_int, n_int, prep.idx_band, nb, u_int, g_int, u_band, g_band, cache, uhat, dudn,
+                    counters, pwc, extra=dict(U=U, D=D, a=a, b=b, cview=cview, sview=sview, rec=rec))
