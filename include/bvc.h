@@ -190,11 +190,13 @@ typedef struct {
  * D[id]  = n_i . [(dim/R0) nu (W - c_i) - (2 R0/3) y_g f(y_g)]  (2D source term)
  * Inputs x, nrm, xbar: [dim][n_cache] FP64; R0: [n_cache] FP64 (from
  * bvc_sample_cache after compaction).  U, D: [n_cache*W] of params->dtype.
- * Optional exit records (any may be NULL): rec_exit [dim][n_cache*W] of
- * dtype (closest point where the walk stopped), rec_w1 [n_cache*W]
- * ((dim/R0)(nu . n_i)), rec_steps int32.  counters: device uint64[4],
- * zeroed by the call: [0] work queue, [1] total closest-point queries,
- * [2] capped walks, [3] walks. */
+ * Exit records (required; they are also the checkpoint the cache adjoint
+ * reads instead of re-walking): rec_exit [dim][n_cache*W] of dtype (the
+ * closest boundary point where the walk stopped), rec_w1 [n_cache*W]
+ * ((dim/R0)(nu . n_i)); rec_steps int32 [n_cache*W] is optional.  The source
+ * term f must be ZERO, CONST or GAUSS_SUM; g is evaluated in FP64 at the
+ * exit points.  counters: device uint64[4], zeroed by the call: [0] work
+ * queue, [1] total closest-point queries, [2] capped walks, [3] walks. */
 int bvc_cache_walks(bvc_scene scene, const bvc_walk_params* params, int64_t n_cache,
                     const double* x, const double* nrm, const double* R0, const double* xbar,
                     void* U, void* D, void* rec_exit, void* rec_w1, int32_t* rec_steps,
@@ -212,10 +214,15 @@ int bvc_reduce_walks(int64_t n_cache, int32_t W, int32_t dtype_in, const void* U
  * baseline the cache is compared against.  Walk j of point k has id k*W + j
  * (tag 2); a point already inside the epsilon shell returns g(xbar).
  * U_walk [n*W] and G_walk [dim][n*W] (optional) are per-walk scratch of
- * dtype; u [n] and grad [dim][n] (optional) receive the means. */
+ * dtype; u [n] and grad [dim][n] (optional) receive the means.  work: a
+ * caller-owned, 256-byte aligned device buffer of at least
+ * bvc_pointwise_workspace_bytes(dim, n, W, dtype, grad != NULL) bytes
+ * (closest points and exit records). */
+size_t bvc_pointwise_workspace_bytes(int32_t dim, int64_t n, int32_t W, int32_t dtype,
+                                     int32_t with_grad);
 int bvc_pointwise_wos(bvc_scene scene, const bvc_walk_params* params, int64_t n, const void* x,
-                      void* U_walk, void* G_walk, void* u, void* grad, uint64_t* counters,
-                      void* stream);
+                      void* U_walk, void* G_walk, void* work, size_t work_bytes, void* u, void* grad,
+                      uint64_t* counters, void* stream);
 
 /* ---------------------------------------------------------------------- */
 /* Gather (Eqs. 3-6; Algorithm 1 splat loops)                              */

@@ -87,7 +87,8 @@ _SIGS = {
     "bvc_cache_walks": [_vp, _P(bvc_walk_params), C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                         _vp, _vp],
     "bvc_reduce_walks": [C.c_int64, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp, _vp, C.c_int32, _vp, _vp, _vp],
-    "bvc_pointwise_wos": [_vp, _P(bvc_walk_params), C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
+    "bvc_pointwise_wos": [_vp, _P(bvc_walk_params), C.c_int64, _vp, _vp, _vp, _vp, C.c_size_t, _vp, _vp, _vp,
+                          _vp],
     "bvc_gather_u": [C.c_int32, _P(bvc_cache_view), _P(bvc_source_view), C.c_int64, _vp, _vp,
                      _P(bvc_gather_params), _vp],
     "bvc_gather_grad": [C.c_int32, _P(bvc_cache_view), _P(bvc_source_view), C.c_int64, _vp, _vp, _vp,
@@ -111,9 +112,11 @@ _L.bvc_compact_scratch_ints.argtypes = [C.c_int64]
 _L.bvc_compact_scratch_ints.restype = C.c_int64
 _L.bvc_cache_backward_scratch_doubles.argtypes = [C.c_int64, C.c_int32]
 _L.bvc_cache_backward_scratch_doubles.restype = C.c_int64
+_L.bvc_pointwise_workspace_bytes.argtypes = [C.c_int32, C.c_int64, C.c_int32, C.c_int32, C.c_int32]
+_L.bvc_pointwise_workspace_bytes.restype = C.c_size_t
 
 EXPORTED = sorted(list(_SIGS) + ["bvc_last_error", "bvc_version", "bvc_compact_scratch_ints",
-                                 "bvc_cache_backward_scratch_doubles"])
+                                 "bvc_cache_backward_scratch_doubles", "bvc_pointwise_workspace_bytes"])
 
 
 def _check(rc, name):
@@ -249,9 +252,15 @@ def bvc_reduce_walks(n_cache, W, dtype_in, U, D, w, uhat, dudn, dtype_out, a, b,
                                ptr(a), ptr(b), stream_ptr(stream)), "bvc_reduce_walks")
 
 
-def bvc_pointwise_wos(scene, params: bvc_walk_params, n, x, U_walk, G_walk, u, grad, counters, stream=None):
-    _check(_L.bvc_pointwise_wos(scene, C.byref(params), n, ptr(x), ptr(U_walk), ptr(G_walk), ptr(u), ptr(grad),
-                                ptr(counters), stream_ptr(stream)), "bvc_pointwise_wos")
+def bvc_pointwise_workspace_bytes(dim, n, W, dtype, with_grad) -> int:
+    return int(_L.bvc_pointwise_workspace_bytes(dim, n, W, dtype, int(bool(with_grad))))
+
+
+def bvc_pointwise_wos(scene, params: bvc_walk_params, n, x, U_walk, G_walk, work, u, grad, counters,
+                      stream=None):
+    nbytes = 0 if work is None else work.numel() * work.element_size()
+    _check(_L.bvc_pointwise_wos(scene, C.byref(params), n, ptr(x), ptr(U_walk), ptr(G_walk), ptr(work), nbytes,
+                                ptr(u), ptr(grad), ptr(counters), stream_ptr(stream)), "bvc_pointwise_wos")
 
 
 def _views(cache, sources):

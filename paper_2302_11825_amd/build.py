@@ -19,7 +19,8 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libbvc.so")
 
-SOURCES = ["scene.cpp", "kernels_walk.hip", "kernels_gather.hip", "kernels_multi.hip", "kernels_mfma.hip"]
+SOURCES = ["scene.cpp", "kernels_walk.hip", "walks.hip", "kernels_gather.hip", "kernels_multi.hip",
+           "kernels_mfma.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -53,15 +53,17 @@ struct Uniform<float> {
 __device__ __forceinline__ void sincos_turns(float t, float* s, float* c) { sincospif(2.0f * t, s, c); }
 __device__ __forceinline__ void sincos_turns(double t, double* s, double* c) { sincospi(2.0 * t, s, c); }
 
+// FP32 helpers use the hardware square root and reciprocal (1 ulp), not the
+// correctly rounded sequences; FP64 keeps IEEE operations.
 template <typename T>
 __device__ __forceinline__ T fsqrt(T x) { return sqrt(x); }
 template <>
-__device__ __forceinline__ float fsqrt<float>(float x) { return __builtin_sqrtf(x); }
+__device__ __forceinline__ float fsqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 template <typename T>
 __device__ __forceinline__ T fdiv(T a, T b) { return a / b; }
 template <>
-__device__ __forceinline__ float fdiv<float>(float a, float b) { return __fdividef(a, b); }
+__device__ __forceinline__ float fdiv<float>(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 
 // Uniform direction on the unit circle / sphere from block 4k.
 template <typename T, int D>
@@ -413,6 +415,8 @@ __device__ inline bool inside_3d(const SceneDev& S, const double* x, int t) {
 // E1(z) + ln z + gamma with E1 from its continued fraction (modified Lentz).
 __device__ inline double ein(double z) {
   if (z <= 0.0) return 0.0;
+  // beyond 40, E1(z) < e^-40/40 is below half an ulp of ln z + gamma
+  if (z > 40.0) return log(z) + 0.57721566490153286061;
   if (z < 4.0) {
     double term = z, sum = z;  // term_k = (-1)^{k+1} z^k / k!
     for (int k = 2; k < 80; ++k) {

@@ -96,6 +96,9 @@ struct SceneHost {
 void set_error(const std::string& msg);
 int fail(int code, const std::string& msg);
 int check_hip(hipError_t e, const char* what);
+int check_scene(bvc_scene s);
+int check_field(const bvc_field& f, int dim, const char* name);
+int num_cus();
 
 }  // namespace bvc
 

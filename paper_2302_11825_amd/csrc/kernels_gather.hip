@@ -30,9 +30,11 @@ template <typename T>
 __host__ __device__ constexpr T log_scale() {
   return sizeof(T) == 4 ? (T)0.69314718055994530942 : (T)1;  // ln r^2 = ln2 * log2 r^2
 }
-__device__ __forceinline__ float recip(float x) { return __frcp_rn(x); }
+// FP32: the hardware reciprocal and reciprocal square root (1 ulp), not the
+// correctly rounded division sequence.
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
-__device__ __forceinline__ float rsq(float x) { return __frsqrt_rn(x); }
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsq(double x) { return rsqrt(x); }
 
 template <typename T>
@@ -136,14 +138,15 @@ __global__ __launch_bounds__(kGBlock) void k_gather(GatherArgs<T> a) {
 #pragma unroll
         for (int p = 0; p < kPPT; ++p) {
           const T dx = y0 - x[p][0], dy = y1 - x[p][1];
-          const T r2 = fmax(dx * dx + dy * dy, tiny);
+          const T r2 = fmax(fma(dx, dx, dy * dy), tiny);
           const T ri = recip(r2);
-          const T t = n0 * dx + n1 * dy;  // a (n . (y - x)) / (2 pi)
-          au[p] += t * ri + bl * log_r2(r2);
+          const T t = fma(n0, dx, n1 * dy);  // a (n . (y - x)) / (2 pi)
+          const T tr = t * ri;               // a dG/dn
+          au[p] = fma(bl, log_r2(r2), au[p] + tr);
           if constexpr (GRAD) {
-            const T q = ri * (T(2) * t * ri + bg);
-            ag[p][0] += q * dx - n0 * ri;
-            ag[p][1] += q * dy - n1 * ri;
+            const T q = fma(T(2), tr, bg) * ri;  // (2 a n.(y-x)/r^2 + b)/(2 pi r^2)
+            ag[p][0] = fma(-n0, ri, fma(q, dx, ag[p][0]));
+            ag[p][1] = fma(-n1, ri, fma(q, dy, ag[p][1]));
           }
         }
       } else {
@@ -151,17 +154,17 @@ __global__ __launch_bounds__(kGBlock) void k_gather(GatherArgs<T> a) {
 #pragma unroll
         for (int p = 0; p < kPPT; ++p) {
           const T dx = y0 - x[p][0], dy = y1 - x[p][1], dz = y2 - x[p][2];
-          const T r2 = fmax(dx * dx + dy * dy + dz * dz, tiny);
+          const T r2 = fmax(fma(dx, dx, fma(dy, dy, dz * dz)), tiny);
           const T ri = rsq(r2);
           const T ri2 = ri * ri;
           const T ri3 = ri2 * ri;
-          const T t = n0 * dx + n1 * dy + n2 * dz;
-          au[p] += t * ri3 + bl * ri;
+          const T t = fma(n0, dx, fma(n1, dy, n2 * dz));
+          au[p] = fma(t, ri3, fma(bl, ri, au[p]));
           if constexpr (GRAD) {
-            const T q = ri3 * (T(3) * t * ri2 + bl);
-            ag[p][0] += q * dx - n0 * ri3;
-            ag[p][1] += q * dy - n1 * ri3;
-            ag[p][2] += q * dz - n2 * ri3;
+            const T q = ri3 * fma(T(3) * t, ri2, bl);
+            ag[p][0] = fma(-n0, ri3, fma(q, dx, ag[p][0]));
+            ag[p][1] = fma(-n1, ri3, fma(q, dy, ag[p][1]));
+            ag[p][2] = fma(-n2, ri3, fma(q, dz, ag[p][2]));
           }
         }
       }

@@ -28,6 +28,8 @@ inline size_t stack_bytes(const SceneHost& h, int block) {
   return (size_t)(h.depth + 1) * block * sizeof(uint2);
 }
 
+}  // namespace
+
 int num_cus() {
   static int n = 0;
   if (n == 0) {
@@ -39,6 +41,8 @@ int num_cus() {
   }
   return n;
 }
+
+namespace {
 
 // ---------------------------------------------------------------------------
 // Cache sampling
@@ -288,243 +292,10 @@ __global__ void k_scatter(int64_t n_idx, const int* idx, int rows, int64_t ld_in
   for (int r = 0; r < rows; ++r) out[r * ld_out + idx[q]] = in[r * ld_in + q];
 }
 
-// ---------------------------------------------------------------------------
-// Walks
-// ---------------------------------------------------------------------------
-struct WalkArgs {
-  SceneDev S;
-  FieldDev g, f;
-  double eps;
-  int max_steps;
-  int W;
-  uint64_t seed;
-  uint32_t batch;
-  int cv;
-  uint64_t total;
-  int64_t n_pts;
-  const double* x;     // mode 0: cache points [D][n] FP64
-  const double* nrm;
-  const double* R0;
-  const double* xbar;
-  const void* px;      // mode 1: evaluation points [D][n] of T
-  void* U;
-  void* Dout;          // mode 0: n.grad [n*W]; mode 1: grad [D][n*W] (optional)
-  void* rec_exit;
-  void* rec_w1;
-  int* rec_steps;
-  unsigned long long* counters;
-};
-
-template <typename T, int D, bool SRC, int MODE>
-__global__ __launch_bounds__(kBlock) void k_walks(WalkArgs a) {
-  extern __shared__ uint2 lds[];
-  uint2* stk = lds + threadIdx.x;
-  const int stride = blockDim.x;
-  const int lane = threadIdx.x & 63;
-  const uint32_t tag = MODE == 0 ? 1u : 2u;
-  const T eps = (T)a.eps;
-  const SceneDev& S = a.S;
-  T* U = (T*)a.U;
-  T* Dv = (T*)a.Dout;
-
-  bool active = false, exhausted = false;
-  uint32_t id = 0;
-  int k = 0, hint = -1;
-  T p[D], gw[D], gs[D];
-  T acc_s = T(0), w1 = T(0), usrc = T(0), dsrc = T(0);
-  double cv = 0.0;
-  unsigned long long steps_acc = 0, capped_acc = 0, walks_acc = 0;
-#pragma unroll
-  for (int q = 0; q < D; ++q) {
-    p[q] = T(0);
-    gw[q] = T(0);
-    gs[q] = T(0);
-  }
-
-  while (true) {
-    if (!exhausted) {
-      const uint64_t need = __ballot(!active);
-      if (need) {
-        const int leader = __ffsll((unsigned long long)need) - 1;
-        const int cnt = __popcll(need);
-        unsigned long long base = 0;
-        if (lane == leader) base = atomicAdd(&a.counters[0], (unsigned long long)cnt);
-        base = __shfl(base, leader);
-        if (base + cnt >= a.total) exhausted = true;
-        if (!active) {
-          const unsigned long long my = base + __popcll(need & ((1ull << lane) - 1));
-          if (my < a.total) {
-            id = (uint32_t)my;
-            const int64_t i = (int64_t)(id / (uint32_t)a.W);
-            T x0[D], R0;
-            double xb[D];
-            bool start = true;
-            if constexpr (MODE == 0) {
-#pragma unroll
-              for (int q = 0; q < D; ++q) {
-                x0[q] = (T)a.x[q * a.n_pts + i];
-                xb[q] = a.xbar[q * a.n_pts + i];
-              }
-              R0 = (T)a.R0[i];
-              hint = -1;
-            } else {
-              const T* px = (const T*)a.px;
-#pragma unroll
-              for (int q = 0; q < D; ++q) x0[q] = px[q * a.n_pts + i];
-              T qq[D];
-              hint = -1;
-              R0 = fsqrt(closest_point<T, D>(S, x0, hint, qq, stk, stride));
-#pragma unroll
-              for (int q = 0; q < D; ++q) xb[q] = (double)qq[q];
-              if (R0 < eps) {
-                // already inside the epsilon shell: the walk returns g(xbar)
-                U[id] = (T)field_value(a.g, D, xb);
-                if (Dv) {
-                  for (int q = 0; q < D; ++q) Dv[(size_t)q * a.total + id] = T(0);
-                }
-                if (a.rec_exit) {
-#pragma unroll
-                  for (int q = 0; q < D; ++q) ((T*)a.rec_exit)[(size_t)q * a.total + id] = (T)xb[q];
-                }
-                if (a.rec_w1) ((T*)a.rec_w1)[id] = T(0);
-                if (a.rec_steps) a.rec_steps[id] = 0;
-                ++walks_acc;
-                start = false;
-              }
-            }
-            if (start) {
-              T nu0[D];
-              walk_direction<T, D>(a.seed, 0, id, a.batch, tag, nu0);
-              T dn = T(0);
-#pragma unroll
-              for (int q = 0; q < D; ++q) {
-                p[q] = x0[q] + R0 * nu0[q];
-                if constexpr (MODE == 0) dn += nu0[q] * (T)a.nrm[q * a.n_pts + i];
-                gw[q] = (T)D / R0 * nu0[q];
-                gs[q] = T(0);
-              }
-              w1 = (T)D / R0 * dn;
-              cv = a.cv ? field_value(a.g, D, xb) : 0.0;
-              usrc = T(0);
-              dsrc = T(0);
-              if constexpr (SRC) {
-                T yu[D];
-                ball_source_point<T, D>(a.seed, 0, id, a.batch, tag, x0, R0, yu);
-                usrc = -R0 * R0 / (T)(2 * D) * source_value<T, D>(a.f, yu);
-                if constexpr (D == 2) {
-                  // gradient source sample, radius density (3/2)(1 - s^2)
-                  T u1, u2, u3, u4;
-                  Uniform<T>::pair(a.seed, 2, id, a.batch, tag, u1, u2);
-                  Uniform<T>::pair(a.seed, 3, id, a.batch, tag, u3, u4);
-                  const T sg = T(2) * sin(asin(u2) / T(3));
-                  T sn, cs;
-                  sincos_turns(u3, &sn, &cs);
-                  const T yg[2] = {x0[0] + R0 * sg * cs, x0[1] + R0 * sg * sn};
-                  const T fg = source_value<T, D>(a.f, yg);
-                  const T c = -T(2) * R0 / T(3) * fg;
-                  gs[0] = c * cs;
-                  gs[1] = c * sn;
-                  if constexpr (MODE == 0)
-                    dsrc = c * (cs * (T)a.nrm[i] + sn * (T)a.nrm[a.n_pts + i]);
-                }
-              }
-              acc_s = T(0);
-              k = 1;
-              active = true;
-            }
-          }
-        }
-      }
-    }
-    if (!__any(active)) {
-      if (exhausted) break;
-      continue;
-    }
-    if (active) {
-      T q[D];
-      const T d = fsqrt(closest_point<T, D>(S, p, hint, q, stk, stride));
-      const bool stop = d < eps;
-      const bool cap = !stop && k >= a.max_steps;
-      if (stop || cap) {
-        double qd[D];
-#pragma unroll
-        for (int c = 0; c < D; ++c) qd[c] = (double)q[c];
-        const double Wd = field_value(a.g, D, qd) + (double)acc_s;
-        U[id] = (T)(Wd + (double)usrc);
-        if constexpr (MODE == 0) {
-          Dv[id] = (T)((double)w1 * (Wd - cv) + (double)dsrc);
-        } else if (Dv) {
-#pragma unroll
-          for (int c = 0; c < D; ++c) Dv[(size_t)c * a.total + id] = (T)((double)gw[c] * (Wd - cv) + (double)gs[c]);
-        }
-        if (a.rec_exit) {
-#pragma unroll
-          for (int c = 0; c < D; ++c) ((T*)a.rec_exit)[(size_t)c * a.total + id] = q[c];
-        }
-        if (a.rec_w1) ((T*)a.rec_w1)[id] = w1;
-        if (a.rec_steps) a.rec_steps[id] = k;
-        steps_acc += (unsigned long long)k;
-        capped_acc += cap ? 1ull : 0ull;
-        ++walks_acc;
-        active = false;
-      } else {
-        if constexpr (SRC) {
-          T y[D];
-          ball_source_point<T, D>(a.seed, (uint32_t)k, id, a.batch, tag, p, d, y);
-          acc_s -= d * d / (T)(2 * D) * source_value<T, D>(a.f, y);
-        }
-        T nu[D];
-        walk_direction<T, D>(a.seed, (uint32_t)k, id, a.batch, tag, nu);
-#pragma unroll
-        for (int c = 0; c < D; ++c) p[c] += d * nu[c];
-        ++k;
-      }
-    }
-  }
-  for (int off = 32; off > 0; off >>= 1) {
-    steps_acc += __shfl_xor(steps_acc, off);
-    capped_acc += __shfl_xor(capped_acc, off);
-    walks_acc += __shfl_xor(walks_acc, off);
-  }
-  if (lane == 0) {
-    atomicAdd(&a.counters[1], steps_acc);
-    atomicAdd(&a.counters[2], capped_acc);
-    atomicAdd(&a.counters[3], walks_acc);
-  }
-}
-
-// Means of W samples per point in FP64, one wave per point, fixed order.
-template <typename Ti, typename To>
-__global__ __launch_bounds__(kBlock) void k_reduce(int64_t n, int W, int rows, int64_t ld, const Ti* U,
-                                                    const Ti* G, const double* w, double* uhat, double* ghat,
-                                                    To* a, To* b, int64_t ld_g) {
-  const int lane = threadIdx.x & 63;
-  const int64_t i = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-  if (i >= n) return;
-  double su = 0.0;
-  double sg[3] = {0.0, 0.0, 0.0};
-  for (int j = lane; j < W; j += 64) {
-    su += (double)U[i * W + j];
-    for (int r = 0; r < rows; ++r) sg[r] += (double)G[r * ld + i * W + j];
-  }
-  for (int off = 32; off > 0; off >>= 1) {
-    su += __shfl_xor(su, off);
-    for (int r = 0; r < rows; ++r) sg[r] += __shfl_xor(sg[r], off);
-  }
-  if (lane == 0) {
-    const double mu = su / W;
-    if (uhat) uhat[i] = mu;
-    if (a) a[i] = (To)(w ? mu * w[i] : mu);
-    for (int r = 0; r < rows; ++r) {
-      const double mg = sg[r] / W;
-      if (ghat) ghat[r * ld_g + i] = mg;
-      if (b) b[r * ld_g + i] = (To)(w ? mg * w[i] : mg);
-    }
-  }
-}
+}  // namespace
 
 // ---------------------------------------------------------------------------
-// Validation helpers
+// Validation helpers (shared with the walk entry points)
 // ---------------------------------------------------------------------------
 int check_scene(bvc_scene s) {
   if (!s) return fail(BVC_EINVAL, "scene is null");
@@ -552,60 +323,6 @@ int check_field(const bvc_field& f, int dim, const char* name) {
   return BVC_OK;
 }
 
-int check_walk_params(const bvc_walk_params* p, int dim) {
-  if (!p) return fail(BVC_EINVAL, "walk params are null");
-  if (!(p->eps > 0) || !std::isfinite(p->eps)) return fail(BVC_EINVAL, "eps must be positive");
-  if (p->max_steps < 1) return fail(BVC_EINVAL, "max_steps must be >= 1");
-  if (p->n_walks < 1) return fail(BVC_EINVAL, "n_walks must be >= 1");
-  if (p->dtype != BVC_F32 && p->dtype != BVC_F64) return fail(BVC_EINVAL, "walk dtype must be F32 or F64");
-  int rc = check_field(p->g, dim, "g");
-  if (rc) return rc;
-  return check_field(p->f, dim, "f");
-}
-
-template <typename T, int D>
-void launch_walks(const WalkArgs& args, int mode, bool src, int blocks, size_t lds, hipStream_t st) {
-  if (mode == 0) {
-    if (src) hipLaunchKernelGGL((k_walks<T, D, true, 0>), dim3(blocks), dim3(kBlock), lds, st, args);
-    else hipLaunchKernelGGL((k_walks<T, D, false, 0>), dim3(blocks), dim3(kBlock), lds, st, args);
-  } else {
-    if (src) hipLaunchKernelGGL((k_walks<T, D, true, 1>), dim3(blocks), dim3(kBlock), lds, st, args);
-    else hipLaunchKernelGGL((k_walks<T, D, false, 1>), dim3(blocks), dim3(kBlock), lds, st, args);
-  }
-}
-
-int run_walks(bvc_scene s, const bvc_walk_params* p, int mode, int64_t n, WalkArgs& args, hipStream_t st) {
-  const SceneHost& h = s->h;
-  const uint64_t total = (uint64_t)n * (uint64_t)p->n_walks;
-  args.S = h.view();
-  args.g = to_dev(p->g);
-  args.f = to_dev(p->f);
-  args.eps = p->eps;
-  args.max_steps = p->max_steps;
-  args.W = p->n_walks;
-  args.seed = p->seed;
-  args.batch = p->batch;
-  args.cv = p->control_variate;
-  args.total = total;
-  args.n_pts = n;
-  int rc = check_hip(hipMemsetAsync(args.counters, 0, 4 * sizeof(unsigned long long), st), "counter reset");
-  if (rc || total == 0) return rc;
-  int blocks = p->blocks > 0 ? p->blocks : num_cus() * 4;
-  const int64_t needed = (int64_t)((total + kBlock - 1) / kBlock);
-  blocks = (int)std::max<int64_t>(1, std::min<int64_t>(blocks, needed));
-  const size_t lds = stack_bytes(h, kBlock);
-  const bool src = p->f.kind != 0;
-  if (h.dim == 2) {
-    if (p->dtype == BVC_F32) launch_walks<float, 2>(args, mode, src, blocks, lds, st);
-    else launch_walks<double, 2>(args, mode, src, blocks, lds, st);
-  } else {
-    if (p->dtype == BVC_F32) launch_walks<float, 3>(args, mode, src, blocks, lds, st);
-    else launch_walks<double, 3>(args, mode, src, blocks, lds, st);
-  }
-  return check_hip(hipGetLastError(), "walk launch");
-}
-
-}  // namespace
 }  // namespace bvc
 
 using namespace bvc;
@@ -754,92 +471,6 @@ int bvc_scatter(int32_t dtype, int64_t n_idx, const int32_t* idx, int32_t rows, 
     hipLaunchKernelGGL(k_scatter<float>, dim3(blocks), dim3(kBlock), 0, st, n_idx, idx, rows, ld_in,
                        (const float*)in, ld_out, (float*)out);
   return check_hip(hipGetLastError(), "scatter launch");
-}
-
-int bvc_cache_walks(bvc_scene s, const bvc_walk_params* p, int64_t n_cache, const double* x, const double* nrm,
-                    const double* R0, const double* xbar, void* U, void* D, void* rec_exit, void* rec_w1,
-                    int32_t* rec_steps, uint64_t* counters, void* stream) {
-  int rc = check_scene(s);
-  if (rc) return rc;
-  rc = check_walk_params(p, s->h.dim);
-  if (rc) return rc;
-  if (n_cache < 0) return fail(BVC_EINVAL, "n_cache must be >= 0");
-  if ((uint64_t)n_cache * (uint64_t)p->n_walks >= (1ull << 32)) return fail(BVC_EINVAL, "n_cache * W >= 2^32");
-  if (!counters) return fail(BVC_EINVAL, "counters is null");
-  if (n_cache > 0 && (!x || !nrm || !R0 || !xbar || !U || !D)) return fail(BVC_EINVAL, "null input/output");
-  WalkArgs a{};
-  a.x = x;
-  a.nrm = nrm;
-  a.R0 = R0;
-  a.xbar = xbar;
-  a.U = U;
-  a.Dout = D;
-  a.rec_exit = rec_exit;
-  a.rec_w1 = rec_w1;
-  a.rec_steps = rec_steps;
-  a.counters = (unsigned long long*)counters;
-  return run_walks(s, p, 0, n_cache, a, (hipStream_t)stream);
-}
-
-int bvc_reduce_walks(int64_t n_cache, int32_t W, int32_t dti, const void* U, const void* D, const double* w,
-                     double* uhat, double* dudn, int32_t dto, void* a, void* b, void* stream) {
-  if (n_cache < 0 || W < 1) return fail(BVC_EINVAL, "bad sizes");
-  if ((dti != BVC_F32 && dti != BVC_F64) || (dto != BVC_F32 && dto != BVC_F64))
-    return fail(BVC_EINVAL, "dtype must be F32 or F64");
-  if (n_cache == 0) return BVC_OK;
-  if (!U || !D) return fail(BVC_EINVAL, "null input");
-  if ((a || b) && !w) return fail(BVC_EINVAL, "weights are null");
-  hipStream_t st = (hipStream_t)stream;
-  const int per = kBlock / 64;
-  const int blocks = (int)((n_cache + per - 1) / per);
-  const int64_t ld = n_cache * (int64_t)W;
-  if (dti == BVC_F32 && dto == BVC_F32)
-    hipLaunchKernelGGL((k_reduce<float, float>), dim3(blocks), dim3(kBlock), 0, st, n_cache, W, 1, ld,
-                       (const float*)U, (const float*)D, w, uhat, dudn, (float*)a, (float*)b, n_cache);
-  else if (dti == BVC_F32)
-    hipLaunchKernelGGL((k_reduce<float, double>), dim3(blocks), dim3(kBlock), 0, st, n_cache, W, 1, ld,
-                       (const float*)U, (const float*)D, w, uhat, dudn, (double*)a, (double*)b, n_cache);
-  else if (dto == BVC_F32)
-    hipLaunchKernelGGL((k_reduce<double, float>), dim3(blocks), dim3(kBlock), 0, st, n_cache, W, 1, ld,
-                       (const double*)U, (const double*)D, w, uhat, dudn, (float*)a, (float*)b, n_cache);
-  else
-    hipLaunchKernelGGL((k_reduce<double, double>), dim3(blocks), dim3(kBlock), 0, st, n_cache, W, 1, ld,
-                       (const double*)U, (const double*)D, w, uhat, dudn, (double*)a, (double*)b, n_cache);
-  return check_hip(hipGetLastError(), "reduce launch");
-}
-
-int bvc_pointwise_wos(bvc_scene s, const bvc_walk_params* p, int64_t n, const void* x, void* U_walk, void* G_walk,
-                      void* u, void* grad, uint64_t* counters, void* stream) {
-  int rc = check_scene(s);
-  if (rc) return rc;
-  rc = check_walk_params(p, s->h.dim);
-  if (rc) return rc;
-  if (n < 0) return fail(BVC_EINVAL, "n must be >= 0");
-  if ((uint64_t)n * (uint64_t)p->n_walks >= (1ull << 32)) return fail(BVC_EINVAL, "n * W >= 2^32");
-  if (!counters) return fail(BVC_EINVAL, "counters is null");
-  if (n > 0 && (!x || !U_walk || !u)) return fail(BVC_EINVAL, "null input/output");
-  if (grad && !G_walk) return fail(BVC_EINVAL, "grad needs G_walk scratch");
-  WalkArgs a{};
-  a.px = x;
-  a.U = U_walk;
-  a.Dout = G_walk;
-  a.counters = (unsigned long long*)counters;
-  hipStream_t st = (hipStream_t)stream;
-  rc = run_walks(s, p, 1, n, a, st);
-  if (rc || n == 0) return rc;
-  const int per = kBlock / 64;
-  const int blocks = (int)((n + per - 1) / per);
-  const int rows = grad ? s->h.dim : 0;
-  const int64_t ld = n * (int64_t)p->n_walks;
-  if (p->dtype == BVC_F32)
-    hipLaunchKernelGGL((k_reduce<float, float>), dim3(blocks), dim3(kBlock), 0, st, n, p->n_walks, rows, ld,
-                       (const float*)U_walk, (const float*)G_walk, nullptr, nullptr, nullptr, (float*)u,
-                       (float*)grad, n);
-  else
-    hipLaunchKernelGGL((k_reduce<double, double>), dim3(blocks), dim3(kBlock), 0, st, n, p->n_walks, rows, ld,
-                       (const double*)U_walk, (const double*)G_walk, nullptr, nullptr, nullptr, (double*)u,
-                       (double*)grad, n);
-  return check_hip(hipGetLastError(), "pointwise reduce launch");
 }
 
 }  // extern "C"

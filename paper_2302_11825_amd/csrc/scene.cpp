@@ -58,6 +58,78 @@ struct Builder {
   std::vector<int>& perm;
   std::vector<TmpNode> nodes;
 
+  // Half perimeter (2D) or half surface area (3D) of a box.
+  double box_cost(const double* lo, const double* hi) const {
+    double e[3] = {0, 0, 0};
+    for (int a = 0; a < dim; ++a) e[a] = std::max(0.0, hi[a] - lo[a]);
+    return dim == 2 ? e[0] + e[1] : e[0] * e[1] + e[1] * e[2] + e[2] * e[0];
+  }
+
+  // Binned surface-area split: minimise n_L cost(L) + n_R cost(R) over 16
+  // centroid bins per axis.  Returns the size of the left part after
+  // partitioning perm[start, start+count), or -1 when no split separates.
+  int sah_split(int start, int count, const double* clo, const double* chi) {
+    constexpr int kBins = 16;
+    double best = INFINITY;
+    int best_axis = -1, best_bin = -1;
+    for (int a = 0; a < dim; ++a) {
+      const double ext = chi[a] - clo[a];
+      if (!(ext > 0)) continue;
+      int cnt[kBins] = {0};
+      double blo[kBins][3], bhi[kBins][3];
+      for (int b = 0; b < kBins; ++b)
+        for (int q = 0; q < 3; ++q) {
+          blo[b][q] = INFINITY;
+          bhi[b][q] = -INFINITY;
+        }
+      for (int i = start; i < start + count; ++i) {
+        const int p = perm[i];
+        int b = (int)(kBins * (cen[(size_t)p * dim + a] - clo[a]) / ext);
+        b = std::min(kBins - 1, std::max(0, b));
+        ++cnt[b];
+        for (int q = 0; q < dim; ++q) {
+          blo[b][q] = std::min(blo[b][q], plo[(size_t)p * dim + q]);
+          bhi[b][q] = std::max(bhi[b][q], phi[(size_t)p * dim + q]);
+        }
+      }
+      // suffix boxes
+      double rlo[kBins][3], rhi[kBins][3];
+      int rcnt[kBins];
+      for (int b = kBins - 1; b >= 0; --b) {
+        rcnt[b] = cnt[b] + (b + 1 < kBins ? rcnt[b + 1] : 0);
+        for (int q = 0; q < 3; ++q) {
+          rlo[b][q] = std::min(blo[b][q], b + 1 < kBins ? rlo[b + 1][q] : INFINITY);
+          rhi[b][q] = std::max(bhi[b][q], b + 1 < kBins ? rhi[b + 1][q] : -INFINITY);
+        }
+      }
+      double llo[3] = {INFINITY, INFINITY, INFINITY}, lhi[3] = {-INFINITY, -INFINITY, -INFINITY};
+      int lcnt = 0;
+      for (int b = 0; b + 1 < kBins; ++b) {
+        lcnt += cnt[b];
+        for (int q = 0; q < 3; ++q) {
+          llo[q] = std::min(llo[q], blo[b][q]);
+          lhi[q] = std::max(lhi[q], bhi[b][q]);
+        }
+        const int rc = rcnt[b + 1];
+        if (lcnt == 0 || rc == 0) continue;
+        const double cost = lcnt * box_cost(llo, lhi) + rc * box_cost(rlo[b + 1], rhi[b + 1]);
+        if (cost < best) {
+          best = cost;
+          best_axis = a;
+          best_bin = b;
+        }
+      }
+    }
+    if (best_axis < 0) return -1;
+    const double ext = chi[best_axis] - clo[best_axis];
+    auto mid = std::stable_partition(perm.begin() + start, perm.begin() + start + count, [&](int p) {
+      int b = (int)(kBins * (cen[(size_t)p * dim + best_axis] - clo[best_axis]) / ext);
+      b = std::min(kBins - 1, std::max(0, b));
+      return b <= best_bin;
+    });
+    return (int)(mid - (perm.begin() + start));
+  }
+
   int build(int start, int count, int depth) {
     int id = (int)nodes.size();
     nodes.emplace_back();
@@ -84,17 +156,22 @@ struct Builder {
       nodes[id] = nd;
       return id;
     }
-    int axis = 0;
-    for (int a = 1; a < dim; ++a)
-      if (chi[a] - clo[a] > chi[axis] - clo[axis]) axis = a;
-    int half = count / 2;
     const std::vector<double>& c = cen;
     int d = dim;
-    std::nth_element(perm.begin() + start, perm.begin() + start + half, perm.begin() + start + count,
-                     [&](int x, int y) {
-                       double cx = c[(size_t)x * d + axis], cy = c[(size_t)y * d + axis];
-                       return cx < cy || (cx == cy && x < y);
-                     });
+    int half = -1;
+    if (depth < 32) half = sah_split(start, count, clo, chi);
+    if (half <= 0 || half >= count) {
+      // median split along the widest centroid axis (also bounds the depth)
+      int axis = 0;
+      for (int a = 1; a < dim; ++a)
+        if (chi[a] - clo[a] > chi[axis] - clo[axis]) axis = a;
+      half = count / 2;
+      std::nth_element(perm.begin() + start, perm.begin() + start + half, perm.begin() + start + count,
+                       [&](int x, int y) {
+                         double cx = c[(size_t)x * d + axis], cy = c[(size_t)y * d + axis];
+                         return cx < cy || (cx == cy && x < y);
+                       });
+    }
     nodes[id] = nd;
     int l = build(start, half, depth + 1);
     int r = build(start + half, count - half, depth + 1);

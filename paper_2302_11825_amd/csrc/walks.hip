@@ -1,0 +1,538 @@
+// Walk on spheres from cache points and from evaluation points (Section 3.1,
+// Eq. 7), the FP64 evaluation of the boundary data at the walks' exit points,
+// and the fixed-order reduction of walk samples into means.
+//
+// The walk kernel is persistent: each wave takes walk ids from a global queue,
+// one id per idle lane, so a lane whose walk ended starts the next one at the
+// following iteration instead of idling until the longest walk of its wave is
+// done.  A walk's random numbers depend only on (seed, batch, id), so results
+// do not depend on which lane ran it.  The kernel only traces: it records the
+// exit point, the in-walk source sum and the first ball's weights, and a
+// second kernel evaluates g in FP64 at the exit points.  Keeping the boundary
+// data out of the traversal loop keeps its register footprint small.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+
+#include "bvc_device.hpp"
+
+namespace bvc {
+namespace {
+
+constexpr int kBlock = 256;
+
+struct WalkArgs {
+  SceneDev S;
+  FieldDev f;      // source term: kinds 0, 1, 3
+  double eps;
+  int max_steps;
+  int W;
+  uint64_t seed;
+  uint32_t batch;
+  uint64_t total;
+  int64_t n_pts;
+  const double* x;     // mode 0 start points [D][n] FP64
+  const void* px;      // mode 1 start points [D][n] of T
+  const double* nrm;   // mode 0 normals [D][n]
+  const double* R0;    // [n] distance of each start point to the boundary
+  const double* xbar;  // [D][n] closest boundary points (mode 1 shell exit)
+  void* U;             // [total] in-walk source sums plus the first-ball term
+  void* Dof;           // mode 0 [total] D offset; mode 1 [D][total] gradient offset
+  void* exit;          // [D][total] exit points
+  void* w1;            // mode 0 [total] (dim/R0) nu.n; mode 1 [D][total] (dim/R0) nu
+  int* steps;          // [total] or null
+  unsigned long long* counters;
+};
+
+// In-walk source term in the walk's precision (constants and Gaussian sums).
+template <typename T, int D>
+__device__ __forceinline__ T walk_source(const FieldDev& F, const T* y) {
+  if (F.kind == 1) return (T)F.param[0];
+  const int ng = F.n_coef / (1 + D);
+  const T inv = T(1) / (T(2) * (T)F.param[0] * (T)F.param[0]);
+  T sum = T(0);
+  for (int k = 0; k < ng; ++k) {
+    const double* c = F.coef + k * (1 + D);
+    T r2 = T(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const T e = y[a] - (T)c[1 + a];
+      r2 = fma(e, e, r2);
+    }
+    sum = fma((T)c[0], exp(-r2 * inv), sum);
+  }
+  return sum;
+}
+
+template <typename T, int D, bool SRC, int MODE>
+__global__ __launch_bounds__(kBlock) void k_walks(WalkArgs a) {
+  extern __shared__ uint2 lds[];
+  uint2* stk = lds + threadIdx.x;
+  const int stride = blockDim.x;
+  const int lane = threadIdx.x & 63;
+  const uint32_t tag = MODE == 0 ? 1u : 2u;
+  const T eps = (T)a.eps;
+  const SceneDev& S = a.S;
+  T* U = (T*)a.U;
+  T* Dof = (T*)a.Dof;
+  T* EX = (T*)a.exit;
+  T* W1 = (T*)a.w1;
+
+  bool active = false, exhausted = false;
+  uint32_t id = 0;
+  int k = 0, hint = -1;
+  T p[D];
+  T acc_s = T(0), usrc = T(0);
+  unsigned long long steps_acc = 0, capped_acc = 0, walks_acc = 0;
+#pragma unroll
+  for (int q = 0; q < D; ++q) p[q] = T(0);
+
+  while (true) {
+    if (!exhausted) {
+      const uint64_t need = __ballot(!active);
+      if (need) {
+        const int leader = __ffsll((unsigned long long)need) - 1;
+        const int cnt = __popcll(need);
+        unsigned long long base = 0;
+        if (lane == leader) base = atomicAdd(&a.counters[0], (unsigned long long)cnt);
+        base = __shfl(base, leader);
+        if (base + cnt >= a.total) exhausted = true;
+        if (!active) {
+          const unsigned long long my = base + __popcll(need & ((1ull << lane) - 1));
+          if (my < a.total) {
+            id = (uint32_t)my;
+            const int64_t i = (int64_t)(id / (uint32_t)a.W);
+            const T R0 = (T)a.R0[i];
+            if (MODE == 1 && R0 < eps) {
+              // the evaluation point already lies in the epsilon shell: its
+              // walk returns g at the closest boundary point
+#pragma unroll
+              for (int q = 0; q < D; ++q) EX[(size_t)q * a.total + id] = (T)a.xbar[q * a.n_pts + i];
+              U[id] = T(0);
+              if (Dof) {
+#pragma unroll
+                for (int q = 0; q < D; ++q) {
+                  Dof[(size_t)q * a.total + id] = T(0);
+                  W1[(size_t)q * a.total + id] = T(0);
+                }
+              }
+              if (a.steps) a.steps[id] = 0;
+              ++walks_acc;
+            } else {
+              T x0[D], nu0[D];
+#pragma unroll
+              for (int q = 0; q < D; ++q)
+                x0[q] = MODE == 0 ? (T)a.x[q * a.n_pts + i] : ((const T*)a.px)[q * a.n_pts + i];
+              walk_direction<T, D>(a.seed, 0, id, a.batch, tag, nu0);
+              T dn = T(0);
+#pragma unroll
+              for (int q = 0; q < D; ++q) {
+                p[q] = fma(R0, nu0[q], x0[q]);
+                if constexpr (MODE == 0) dn = fma(nu0[q], (T)a.nrm[q * a.n_pts + i], dn);
+              }
+              const T wgt = (T)D / R0;
+              usrc = T(0);
+              T gs[D];
+#pragma unroll
+              for (int q = 0; q < D; ++q) gs[q] = T(0);
+              if constexpr (SRC) {
+                T yu[D];
+                ball_source_point<T, D>(a.seed, 0, id, a.batch, tag, x0, R0, yu);
+                usrc = -R0 * R0 / (T)(2 * D) * walk_source<T, D>(a.f, yu);
+                if constexpr (D == 2) {
+                  // gradient source sample, radius density (3/2)(1 - s^2)
+                  T u1, u2, u3, u4;
+                  Uniform<T>::pair(a.seed, 2, id, a.batch, tag, u1, u2);
+                  Uniform<T>::pair(a.seed, 3, id, a.batch, tag, u3, u4);
+                  const T sg = T(2) * sin(asin(u2) / T(3));
+                  T sn, cs;
+                  sincos_turns(u3, &sn, &cs);
+                  const T yg[2] = {fma(R0 * sg, cs, x0[0]), fma(R0 * sg, sn, x0[1])};
+                  const T c = -T(2) * R0 / T(3) * walk_source<T, D>(a.f, yg);
+                  gs[0] = c * cs;
+                  gs[1] = c * sn;
+                }
+              }
+              if constexpr (MODE == 0) {
+                const T w1 = wgt * dn;
+                T ds = T(0);
+#pragma unroll
+                for (int q = 0; q < D; ++q) ds = fma(gs[q], (T)a.nrm[q * a.n_pts + i], ds);
+                W1[id] = w1;
+                Dof[id] = ds - w1 * usrc;
+              } else if (Dof) {
+#pragma unroll
+                for (int q = 0; q < D; ++q) {
+                  const T gw = wgt * nu0[q];
+                  W1[(size_t)q * a.total + id] = gw;
+                  Dof[(size_t)q * a.total + id] = gs[q] - gw * usrc;
+                }
+              }
+              acc_s = T(0);
+              k = 1;
+              hint = -1;
+              active = true;
+            }
+          }
+        }
+      }
+    }
+    if (!__any(active)) {
+      if (exhausted) break;
+      continue;
+    }
+    if (active) {
+      T q[D];
+      const T d = fsqrt(closest_point<T, D>(S, p, hint, q, stk, stride));
+      const bool stop = d < eps;
+      const bool cap = !stop && k >= a.max_steps;
+      if (stop || cap) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) EX[(size_t)c * a.total + id] = q[c];
+        U[id] = acc_s + usrc;
+        if (a.steps) a.steps[id] = k;
+        steps_acc += (unsigned long long)k;
+        capped_acc += cap ? 1ull : 0ull;
+        ++walks_acc;
+        active = false;
+      } else {
+        if constexpr (SRC) {
+          T y[D];
+          ball_source_point<T, D>(a.seed, (uint32_t)k, id, a.batch, tag, p, d, y);
+          acc_s = fma(-d * d / (T)(2 * D), walk_source<T, D>(a.f, y), acc_s);
+        }
+        T nu[D];
+        walk_direction<T, D>(a.seed, (uint32_t)k, id, a.batch, tag, nu);
+#pragma unroll
+        for (int c = 0; c < D; ++c) p[c] = fma(d, nu[c], p[c]);
+        ++k;
+      }
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    steps_acc += __shfl_xor(steps_acc, off);
+    capped_acc += __shfl_xor(capped_acc, off);
+    walks_acc += __shfl_xor(walks_acc, off);
+  }
+  if (lane == 0) {
+    atomicAdd(&a.counters[1], steps_acc);
+    atomicAdd(&a.counters[2], capped_acc);
+    atomicAdd(&a.counters[3], walks_acc);
+  }
+}
+
+// Boundary data at the exit points, in FP64.  With W = g(exit) + S:
+// U = W + u_src,  mode 0: D = w1 (W - c) + d_src,  mode 1: grad = gw (W - c) + g_src,
+// where c = g(xbar) is the control variate (0 when disabled).
+// Each thread finishes kFinishRun consecutive walks, so the control variate of
+// a start point is evaluated once per run rather than once per walk.
+constexpr int kFinishRun = 8;
+
+template <typename T, int D, int MODE>
+__global__ __launch_bounds__(kBlock) void k_finish(FieldDev g, int cv, uint64_t total, int W, int64_t n_pts,
+                                                    const double* xbar, const T* EX, T* U, T* Dof, const T* W1) {
+  const uint64_t id0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * kFinishRun;
+  if (id0 >= total) return;
+  int64_t i_cv = -1;
+  double c = 0.0;
+  for (int r = 0; r < kFinishRun; ++r) {
+    const uint64_t id = id0 + r;
+    if (id >= total) break;
+    const int64_t i = (int64_t)(id / (uint64_t)W);
+    if (cv && i != i_cv) {
+      double xb[D];
+#pragma unroll
+      for (int a = 0; a < D; ++a) xb[a] = xbar[a * n_pts + i];
+      c = field_value(g, D, xb);
+      i_cv = i;
+    }
+    double q[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) q[a] = (double)EX[(size_t)a * total + id];
+    const double gq = field_value(g, D, q);
+    const double su = (double)U[id];
+    U[id] = (T)(gq + su);
+    if constexpr (MODE == 0) {
+      Dof[id] = (T)((double)W1[id] * (gq + su - c) + (double)Dof[id]);
+    } else if (Dof) {
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+        Dof[(size_t)a * total + id] =
+            (T)((double)W1[(size_t)a * total + id] * (gq + su - c) + (double)Dof[(size_t)a * total + id]);
+    }
+  }
+}
+
+// Distance and closest point of each evaluation point (pointwise walks).
+template <typename T, int D>
+__global__ __launch_bounds__(kBlock) void k_closest_points(SceneDev S, int64_t n, const T* x, double* R0,
+                                                            double* xbar) {
+  extern __shared__ uint2 lds[];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  T p[D], q[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) p[a] = x[a * n + k];
+  int hint = -1;
+  const T d2 = closest_point<T, D>(S, p, hint, q, lds + threadIdx.x, blockDim.x);
+  R0[k] = (double)fsqrt(d2);
+#pragma unroll
+  for (int a = 0; a < D; ++a) xbar[a * n + k] = (double)q[a];
+}
+
+// Means of W samples per point in FP64, one wave per point, fixed order.
+template <typename Ti, typename To>
+__global__ __launch_bounds__(kBlock) void k_reduce(int64_t n, int W, int rows, int64_t ld, const Ti* U,
+                                                    const Ti* G, const double* w, double* uhat, double* ghat,
+                                                    To* a, To* b, int64_t ld_g) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (i >= n) return;
+  double su = 0.0;
+  double sg[3] = {0.0, 0.0, 0.0};
+  for (int j = lane; j < W; j += 64) {
+    su += (double)U[i * W + j];
+    for (int r = 0; r < rows; ++r) sg[r] += (double)G[r * ld + i * W + j];
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    su += __shfl_xor(su, off);
+    for (int r = 0; r < rows; ++r) sg[r] += __shfl_xor(sg[r], off);
+  }
+  if (lane == 0) {
+    const double mu = su / W;
+    if (uhat) uhat[i] = mu;
+    if (a) a[i] = (To)(w ? mu * w[i] : mu);
+    for (int r = 0; r < rows; ++r) {
+      const double mg = sg[r] / W;
+      if (ghat) ghat[r * ld_g + i] = mg;
+      if (b) b[r * ld_g + i] = (To)(w ? mg * w[i] : mg);
+    }
+  }
+}
+
+int check_walk_params(const bvc_walk_params* p, int dim) {
+  if (!p) return fail(BVC_EINVAL, "walk params are null");
+  if (!(p->eps > 0) || !std::isfinite(p->eps)) return fail(BVC_EINVAL, "eps must be positive");
+  if (p->max_steps < 1) return fail(BVC_EINVAL, "max_steps must be >= 1");
+  if (p->n_walks < 1) return fail(BVC_EINVAL, "n_walks must be >= 1");
+  if (p->dtype != BVC_F32 && p->dtype != BVC_F64) return fail(BVC_EINVAL, "walk dtype must be F32 or F64");
+  int rc = check_field(p->g, dim, "g");
+  if (rc) return rc;
+  rc = check_field(p->f, dim, "f");
+  if (rc) return rc;
+  if (p->f.kind != 0 && p->f.kind != 1 && p->f.kind != 3)
+    return fail(BVC_EUNSUPPORTED, "walk source terms are constants or Gaussian sums");
+  return BVC_OK;
+}
+
+template <typename T, int D>
+void launch_walks(const WalkArgs& args, int mode, bool src, int blocks, size_t lds, hipStream_t st) {
+  if (mode == 0) {
+    if (src) hipLaunchKernelGGL((k_walks<T, D, true, 0>), dim3(blocks), dim3(kBlock), lds, st, args);
+    else hipLaunchKernelGGL((k_walks<T, D, false, 0>), dim3(blocks), dim3(kBlock), lds, st, args);
+  } else {
+    if (src) hipLaunchKernelGGL((k_walks<T, D, true, 1>), dim3(blocks), dim3(kBlock), lds, st, args);
+    else hipLaunchKernelGGL((k_walks<T, D, false, 1>), dim3(blocks), dim3(kBlock), lds, st, args);
+  }
+}
+
+template <typename T, int D>
+void launch_finish(const bvc_walk_params* p, int mode, const WalkArgs& a, hipStream_t st) {
+  const uint64_t threads = (a.total + kFinishRun - 1) / kFinishRun;
+  const int blocks = (int)((threads + kBlock - 1) / kBlock);
+  FieldDev g = to_dev(p->g);
+  if (mode == 0)
+    hipLaunchKernelGGL((k_finish<T, D, 0>), dim3(blocks), dim3(kBlock), 0, st, g, p->control_variate, a.total,
+                       a.W, a.n_pts, a.xbar, (const T*)a.exit, (T*)a.U, (T*)a.Dof, (const T*)a.w1);
+  else
+    hipLaunchKernelGGL((k_finish<T, D, 1>), dim3(blocks), dim3(kBlock), 0, st, g, p->control_variate, a.total,
+                       a.W, a.n_pts, a.xbar, (const T*)a.exit, (T*)a.U, (T*)a.Dof, (const T*)a.w1);
+}
+
+size_t stack_bytes(const SceneHost& h) { return (size_t)(h.depth + 1) * kBlock * sizeof(uint2); }
+
+int run_walks(bvc_scene s, const bvc_walk_params* p, int mode, int64_t n, WalkArgs& a, hipStream_t st) {
+  const SceneHost& h = s->h;
+  const uint64_t total = (uint64_t)n * (uint64_t)p->n_walks;
+  a.S = h.view();
+  a.f = to_dev(p->f);
+  a.eps = p->eps;
+  a.max_steps = p->max_steps;
+  a.W = p->n_walks;
+  a.seed = p->seed;
+  a.batch = p->batch;
+  a.total = total;
+  a.n_pts = n;
+  int rc = check_hip(hipMemsetAsync(a.counters, 0, 4 * sizeof(unsigned long long), st), "counter reset");
+  if (rc || total == 0) return rc;
+  int blocks = p->blocks > 0 ? p->blocks : num_cus() * 8;
+  const int64_t needed = (int64_t)((total + kBlock - 1) / kBlock);
+  blocks = (int)std::max<int64_t>(1, std::min<int64_t>(blocks, needed));
+  const size_t lds = stack_bytes(h);
+  const bool src = p->f.kind != 0;
+  const bool f32 = p->dtype == BVC_F32;
+  if (h.dim == 2) {
+    if (f32) launch_walks<float, 2>(a, mode, src, blocks, lds, st);
+    else launch_walks<double, 2>(a, mode, src, blocks, lds, st);
+  } else {
+    if (f32) launch_walks<float, 3>(a, mode, src, blocks, lds, st);
+    else launch_walks<double, 3>(a, mode, src, blocks, lds, st);
+  }
+  rc = check_hip(hipGetLastError(), "walk launch");
+  if (rc) return rc;
+  if (h.dim == 2) {
+    if (f32) launch_finish<float, 2>(p, mode, a, st);
+    else launch_finish<double, 2>(p, mode, a, st);
+  } else {
+    if (f32) launch_finish<float, 3>(p, mode, a, st);
+    else launch_finish<double, 3>(p, mode, a, st);
+  }
+  return check_hip(hipGetLastError(), "walk finish launch");
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+}  // namespace bvc
+
+using namespace bvc;
+
+extern "C" {
+
+int bvc_cache_walks(bvc_scene s, const bvc_walk_params* p, int64_t n_cache, const double* x, const double* nrm,
+                    const double* R0, const double* xbar, void* U, void* D, void* rec_exit, void* rec_w1,
+                    int32_t* rec_steps, uint64_t* counters, void* stream) {
+  int rc = check_scene(s);
+  if (rc) return rc;
+  rc = check_walk_params(p, s->h.dim);
+  if (rc) return rc;
+  if (n_cache < 0) return fail(BVC_EINVAL, "n_cache must be >= 0");
+  if ((uint64_t)n_cache * (uint64_t)p->n_walks >= (1ull << 32)) return fail(BVC_EINVAL, "n_cache * W >= 2^32");
+  if (!counters) return fail(BVC_EINVAL, "counters is null");
+  if (n_cache > 0 && (!x || !nrm || !R0 || !xbar || !U || !D || !rec_exit || !rec_w1))
+    return fail(BVC_EINVAL, "null input, output or exit record");
+  WalkArgs a{};
+  a.x = x;
+  a.nrm = nrm;
+  a.R0 = R0;
+  a.xbar = xbar;
+  a.U = U;
+  a.Dof = D;
+  a.exit = rec_exit;
+  a.w1 = rec_w1;
+  a.steps = rec_steps;
+  a.counters = (unsigned long long*)counters;
+  return run_walks(s, p, 0, n_cache, a, (hipStream_t)stream);
+}
+
+size_t bvc_pointwise_workspace_bytes(int32_t dim, int64_t n, int32_t W, int32_t dtype, int32_t with_grad) {
+  if (n < 0 || W < 1 || (dim != 2 && dim != 3)) return 0;
+  const size_t es = dtype == BVC_F64 ? 8 : 4;
+  const size_t nw = (size_t)n * (size_t)W;
+  size_t b = align256((size_t)n * 8) + align256((size_t)dim * n * 8) + align256((size_t)dim * nw * es);
+  if (with_grad) b += align256((size_t)dim * nw * es);
+  return b;
+}
+
+int bvc_pointwise_wos(bvc_scene s, const bvc_walk_params* p, int64_t n, const void* x, void* U_walk, void* G_walk,
+                      void* work, size_t work_bytes, void* u, void* grad, uint64_t* counters, void* stream) {
+  int rc = check_scene(s);
+  if (rc) return rc;
+  const int dim = s->h.dim;
+  rc = check_walk_params(p, dim);
+  if (rc) return rc;
+  if (n < 0) return fail(BVC_EINVAL, "n must be >= 0");
+  if ((uint64_t)n * (uint64_t)p->n_walks >= (1ull << 32)) return fail(BVC_EINVAL, "n * W >= 2^32");
+  if (!counters) return fail(BVC_EINVAL, "counters is null");
+  if (n > 0 && (!x || !U_walk || !u || !work)) return fail(BVC_EINVAL, "null input/output/workspace");
+  if (grad && !G_walk) return fail(BVC_EINVAL, "grad needs G_walk scratch");
+  const size_t need = bvc_pointwise_workspace_bytes(dim, n, p->n_walks, p->dtype, grad != nullptr);
+  if (n > 0 && work_bytes < need) return fail(BVC_EINVAL, "pointwise workspace too small");
+  if (((uintptr_t)work & 255) != 0) return fail(BVC_EINVAL, "workspace must be 256-byte aligned");
+  hipStream_t st = (hipStream_t)stream;
+  const size_t es = p->dtype == BVC_F64 ? 8 : 4;
+  const size_t nw = (size_t)n * (size_t)p->n_walks;
+  char* w = (char*)work;
+  double* R0 = (double*)w;
+  w += align256((size_t)n * 8);
+  double* xbar = (double*)w;
+  w += align256((size_t)dim * n * 8);
+  void* ex = w;
+  w += align256((size_t)dim * nw * es);
+  void* gw = grad ? (void*)w : nullptr;
+  if (n > 0) {
+    const int blocks = (int)((n + kBlock - 1) / kBlock);
+    const size_t lds = stack_bytes(s->h);
+    SceneDev S = s->h.view();
+    if (dim == 2) {
+      if (p->dtype == BVC_F32)
+        hipLaunchKernelGGL((k_closest_points<float, 2>), dim3(blocks), dim3(kBlock), lds, st, S, n, (const float*)x,
+                           R0, xbar);
+      else
+        hipLaunchKernelGGL((k_closest_points<double, 2>), dim3(blocks), dim3(kBlock), lds, st, S, n,
+                           (const double*)x, R0, xbar);
+    } else {
+      if (p->dtype == BVC_F32)
+        hipLaunchKernelGGL((k_closest_points<float, 3>), dim3(blocks), dim3(kBlock), lds, st, S, n, (const float*)x,
+                           R0, xbar);
+      else
+        hipLaunchKernelGGL((k_closest_points<double, 3>), dim3(blocks), dim3(kBlock), lds, st, S, n,
+                           (const double*)x, R0, xbar);
+    }
+  }
+  WalkArgs a{};
+  a.px = x;
+  a.R0 = R0;
+  a.xbar = xbar;
+  a.U = U_walk;
+  a.Dof = grad ? G_walk : nullptr;
+  a.exit = ex;
+  a.w1 = gw;
+  a.counters = (unsigned long long*)counters;
+  rc = run_walks(s, p, 1, n, a, st);
+  if (rc || n == 0) return rc;
+  const int per = kBlock / 64;
+  const int blocks = (int)((n + per - 1) / per);
+  const int rows = grad ? dim : 0;
+  const int64_t ld = n * (int64_t)p->n_walks;
+  if (p->dtype == BVC_F32)
+    hipLaunchKernelGGL((k_reduce<float, float>), dim3(blocks), dim3(kBlock), 0, st, n, p->n_walks, rows, ld,
+                       (const float*)U_walk, (const float*)G_walk, nullptr, nullptr, nullptr, (float*)u,
+                       (float*)grad, n);
+  else
+    hipLaunchKernelGGL((k_reduce<double, double>), dim3(blocks), dim3(kBlock), 0, st, n, p->n_walks, rows, ld,
+                       (const double*)U_walk, (const double*)G_walk, nullptr, nullptr, nullptr, (double*)u,
+                       (double*)grad, n);
+  return check_hip(hipGetLastError(), "pointwise reduce launch");
+}
+
+int bvc_reduce_walks(int64_t n_cache, int32_t W, int32_t dti, const void* U, const void* D, const double* w,
+                     double* uhat, double* dudn, int32_t dto, void* a, void* b, void* stream) {
+  if (n_cache < 0 || W < 1) return fail(BVC_EINVAL, "bad sizes");
+  if ((dti != BVC_F32 && dti != BVC_F64) || (dto != BVC_F32 && dto != BVC_F64))
+    return fail(BVC_EINVAL, "dtype must be F32 or F64");
+  if (n_cache == 0) return BVC_OK;
+  if (!U || !D) return fail(BVC_EINVAL, "null input");
+  if ((a || b) && !w) return fail(BVC_EINVAL, "weights are null");
+  hipStream_t st = (hipStream_t)stream;
+  const int per = kBlock / 64;
+  const int blocks = (int)((n_cache + per - 1) / per);
+  const int64_t ld = n_cache * (int64_t)W;
+  if (dti == BVC_F32 && dto == BVC_F32)
+    hipLaunchKernelGGL((k_reduce<float, float>), dim3(blocks), dim3(kBlock), 0, st, n_cache, W, 1, ld,
+                       (const float*)U, (const float*)D, w, uhat, dudn, (float*)a, (float*)b, n_cache);
+  else if (dti == BVC_F32)
+    hipLaunchKernelGGL((k_reduce<float, double>), dim3(blocks), dim3(kBlock), 0, st, n_cache, W, 1, ld,
+                       (const float*)U, (const float*)D, w, uhat, dudn, (double*)a, (double*)b, n_cache);
+  else if (dto == BVC_F32)
+    hipLaunchKernelGGL((k_reduce<double, float>), dim3(blocks), dim3(kBlock), 0, st, n_cache, W, 1, ld,
+                       (const double*)U, (const double*)D, w, uhat, dudn, (float*)a, (float*)b, n_cache);
+  else
+    hipLaunchKernelGGL((k_reduce<double, double>), dim3(blocks), dim3(kBlock), 0, st, n_cache, W, 1, ld,
+                       (const double*)U, (const double*)D, w, uhat, dudn, (double*)a, (double*)b, n_cache);
+  return check_hip(hipGetLastError(), "reduce launch");
+}
+
+}  // extern "C"

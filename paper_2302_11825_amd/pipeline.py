@@ -143,16 +143,31 @@ def cache_walks(sc: Scene, cache: Cache, params: B.bvc_walk_params, dtype="f32",
     T = DT[dtype]
     U = torch.empty(max(n * W, 1), dtype=T, device=dev)
     D = torch.empty_like(U)
-    rec = None
-    if records:
-        rec = dict(exit=torch.empty(sc.dim, max(n * W, 1), dtype=T, device=dev),
-                   w1=torch.empty(max(n * W, 1), dtype=T, device=dev),
-                   steps=torch.empty(max(n * W, 1), dtype=torch.int32, device=dev))
+    rec = dict(exit=torch.empty(sc.dim, max(n * W, 1), dtype=T, device=dev),
+               w1=torch.empty(max(n * W, 1), dtype=T, device=dev),
+               steps=torch.empty(max(n * W, 1), dtype=torch.int32, device=dev) if records else None)
     counters = torch.zeros(4, dtype=torch.int64, device=dev)
-    B.bvc_cache_walks(sc.h, params, n, cache.x, cache.nrm, cache.R0, cache.xbar, U, D,
-                      rec["exit"] if rec else None, rec["w1"] if rec else None, rec["steps"] if rec else None,
-                      counters)
+    B.bvc_cache_walks(sc.h, params, n, cache.x, cache.nrm, cache.R0, cache.xbar, U, D, rec["exit"], rec["w1"],
+                      rec["steps"], counters)
     return U, D, rec, counters
+
+
+def pointwise(sc: Scene, params: B.bvc_walk_params, x, with_grad=True):
+    """Pointwise walk on spheres at points x ([dim][n] of the walk dtype):
+    returns (u [n], grad [dim][n] or None, counters)."""
+    dev, d = sc.device, sc.dim
+    n = x.shape[1] if x.dim() == 2 else 0
+    W = params.n_walks
+    T = x.dtype
+    Uw = torch.empty(max(n * W, 1), dtype=T, device=dev)
+    Gw = torch.empty(d, max(n * W, 1), dtype=T, device=dev) if with_grad else None
+    nbytes = B.bvc_pointwise_workspace_bytes(d, max(n, 1), W, B.dtype_code(T), with_grad)
+    work = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    u = torch.empty(max(n, 1), dtype=T, device=dev)
+    g = torch.empty(d, max(n, 1), dtype=T, device=dev) if with_grad else None
+    cnt = torch.zeros(4, dtype=torch.int64, device=dev)
+    B.bvc_pointwise_wos(sc.h, params, n, x, Uw, Gw, work, u, g, cnt)
+    return u, g, cnt
 
 
 def reduce_walks(cache: Cache, W, U, D, dtype_out="f32"):
@@ -225,15 +240,62 @@ class Prepared:
         self.x_band = take(self.eval64, self.idx_band, self.n_band, self.sc.dim, n, T)
 
 
-def solve(prep: Prepared, batch=0, with_grad=True, n_walks_band=None, records=False) -> Solution:
+class Stopwatch:
+    """HIP events around named stages on torch's current stream (the stream
+    every library call is enqueued on)."""
+
+    def __init__(self):
+        self.marks = []
+
+    def stage(self, name):
+        sw = self
+
+        class _Ctx:
+            def __enter__(self):
+                self.e0 = torch.cuda.Event(enable_timing=True)
+                self.e1 = torch.cuda.Event(enable_timing=True)
+                self.e0.record()
+                return self
+
+            def __exit__(self, *exc):
+                self.e1.record()
+                sw.marks.append((name, self.e0, self.e1))
+                return False
+
+        return _Ctx()
+
+    def totals_ms(self):
+        out = {}
+        for name, e0, e1 in self.marks:
+            out.setdefault(name, []).append(e0.elapsed_time(e1))
+        return out
+
+
+class _NoWatch:
+    class _N:
+        def __enter__(self):
+            return self
+
+        def __exit__(self, *exc):
+            return False
+
+    def stage(self, name):
+        return self._N()
+
+
+def solve(prep: Prepared, batch=0, with_grad=True, n_walks_band=None, records=False, watch=None) -> Solution:
     p, sc = prep.p, prep.sc
     dt = prep.dtype
     T = DT[dt]
     d = sc.dim
-    cache = sample_cache(sc, prep.n_cand, p.offset, p.sides, p.seed_cache, batch)
+    watch = watch or _NoWatch()
+    with watch.stage("sample_cache"):
+        cache = sample_cache(sc, prep.n_cand, p.offset, p.sides, p.seed_cache, batch)
     wp = walk_params(p.eps, p.n_walks, p.seed_walks, prep.g, prep.f, dt, batch)
-    U, D, rec, counters = cache_walks(sc, cache, wp, dt, records)
-    uhat, dudn, a, b = reduce_walks(cache, p.n_walks, U, D, dt)
+    with watch.stage("cache_walks"):
+        U, D, rec, counters = cache_walks(sc, cache, wp, dt, records)
+    with watch.stage("reduce_walks"):
+        uhat, dudn, a, b = reduce_walks(cache, p.n_walks, U, D, dt)
     if T != torch.float64:
         cx = take(cache.x, None, cache.n, d, cache.n, T)
         cn = take(cache.nrm, None, cache.n, d, cache.n, T)
@@ -243,28 +305,26 @@ def solve(prep: Prepared, batch=0, with_grad=True, n_walks_band=None, records=Fa
     sview = None
     if prep.f is not None and p.n_sources > 0:
         m = int(round(p.n_sources ** (1.0 / d)))
-        y64, s64, M = sample_sources(sc, prep.f, m, p.offset, p.seed_sources, batch)
-        if T != torch.float64:
-            y = take(y64, None, M, d, M, T)
-            s = take(s64, None, M, 1, M, T)
-        else:
-            y, s = y64, s64
+        with watch.stage("sample_sources"):
+            y64, s64, M = sample_sources(sc, prep.f, m, p.offset, p.seed_sources, batch)
+            if T != torch.float64:
+                y = take(y64, None, M, d, M, T)
+                s = take(s64, None, M, 1, M, T)
+            else:
+                y, s = y64, s64
         sview = dict(n=M, dtype=CODE[dt], y=y, s=s)
     n_int = prep.n_int
     u_int = torch.empty(max(n_int, 1), dtype=T, device=sc.device)
     g_int = torch.empty(d, max(n_int, 1), dtype=T, device=sc.device) if with_grad else None
-    if with_grad:
-        B.bvc_gather_grad(d, cview, sview, n_int, prep.x_int, u_int, g_int)
-    else:
-        B.bvc_gather_u(d, cview, sview, n_int, prep.x_int, u_int)
+    with watch.stage("gather"):
+        if with_grad:
+            B.bvc_gather_grad(d, cview, sview, n_int, prep.x_int, u_int, g_int)
+        else:
+            B.bvc_gather_u(d, cview, sview, n_int, prep.x_int, u_int)
     Wb = n_walks_band or p.n_walks
     nb = prep.n_band
-    u_band = torch.empty(max(nb, 1), dtype=T, device=sc.device)
-    g_band = torch.empty(d, max(nb, 1), dtype=T, device=sc.device) if with_grad else None
-    Uw = torch.empty(max(nb * Wb, 1), dtype=T, device=sc.device)
-    Gw = torch.empty(d, max(nb * Wb, 1), dtype=T, device=sc.device) if with_grad else None
-    pwc = torch.zeros(4, dtype=torch.int64, device=sc.device)
     wpb = walk_params(p.eps, Wb, p.seed_walks, prep.g, prep.f, dt, batch)
-    B.bvc_pointwise_wos(sc.h, wpb, nb, prep.x_band, Uw, Gw, u_band, g_band, pwc)
+    with watch.stage("band_walks"):
+        u_band, g_band, pwc = pointwise(sc, wpb, prep.x_band[:, :nb] if nb else prep.x_band[:, :0], with_grad)
     return Solution(prep.idx_int, n_int, prep.idx_band, nb, u_int, g_int, u_band, g_band, cache, uhat, dudn,
                     counters, pwc, extra=dict(U=U, D=D, a=a, b=b, cview=cview, sview=sview, rec=rec))

@@ -84,8 +84,9 @@ def test_bvh_depth_bounds_stack():
     for scene in (wl.star_polygon(4096), wl.displaced_icosphere(5, 1)):
         h = _bvc.bvc_scene_create(scene.dim, scene.verts, scene.prims)
         info = _bvc.bvc_scene_get_info(h)
-        # median splits: depth = ceil(log2(np / leaf)) + 1
-        assert info.depth <= int(np.ceil(np.log2(scene.prims.shape[0] / 4))) + 2
+        # surface-area splits down to level 32, median splits below it
+        assert info.depth <= 32 + int(np.ceil(np.log2(scene.prims.shape[0] / 4)))
+        assert info.depth >= int(np.ceil(np.log2(scene.prims.shape[0] / 4)))
         assert info.n_nodes >= scene.prims.shape[0] // 4 - 1  # internal nodes = leaves - 1
         _bvc.bvc_scene_destroy(h)
 

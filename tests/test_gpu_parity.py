@@ -139,14 +139,8 @@ def test_pointwise_fp64_per_walk(B, orc, case):
     pts = pts[os_.inside(pts) != 0][:200]
     x = torch.from_numpy(np.ascontiguousarray(pts.T)).cuda()
     Wp = 16
-    k = pts.shape[0]
-    Uw = torch.empty(k * Wp, dtype=torch.float64, device="cuda")
-    Gw = torch.empty(scene.dim, k * Wp, dtype=torch.float64, device="cuda")
-    u = torch.empty(k, dtype=torch.float64, device="cuda")
-    gr = torch.empty(scene.dim, k, dtype=torch.float64, device="cuda")
-    cnt = torch.zeros(4, dtype=torch.int64, device="cuda")
     params = pl.walk_params(eps, Wp, 99, gd, fd, "f64")
-    _bvc.bvc_pointwise_wos(sc.h, params, k, x, Uw, Gw, u, gr, cnt)
+    u, gr, cnt = pl.pointwise(sc, params, x, with_grad=True)
     torch.cuda.synchronize()
     uo, go, tot = orc.pointwise(os_, g, f, orc.walk_params(eps, Wp, 99), pts)
     okp = per_walk_match(u.cpu().numpy(), uo, 1e-9)
