@@ -303,10 +303,16 @@ int bvc_eval_fields(int64_t n_cache, int32_t nb, int32_t n_fields, const double*
 /* Multi-RHS gather: U[k*F+f] = sum_i [dG/dn(x_k,z_i) A[i*F+f] - G(x_k,z_i) B[i*F+f]]
  * with the kernel matrix generated on the fly.  FP32 inputs; precision
  * BVC_F32 (FP32 FMA) or BVC_SPLIT_BF16 (three bf16 MFMA products with FP32
- * accumulation).  n_fields must be a multiple of 32. */
+ * accumulation).  n_fields is 32 or 64.  cx, cn: [dim][n_cache]; A, B:
+ * [n_cache][n_fields]; eval_x: [dim][n_eval]; U: [n_eval][n_fields].
+ * workspace: caller-owned, 256-byte aligned device buffer of
+ * bvc_gather_multi_workspace_bytes(n_cache, precision) bytes (the split
+ * coefficients in the MFMA operand layout; 0 bytes for BVC_F32). */
+size_t bvc_gather_multi_workspace_bytes(int64_t n_cache, int32_t precision);
 int bvc_gather_multi(int32_t dim, int64_t n_cache, const float* cx, const float* cn,
                      int32_t n_fields, const float* A, const float* B, int64_t n_eval,
-                     const float* eval_x, float* U, int32_t precision, void* stream);
+                     const float* eval_x, float* U, int32_t precision, void* workspace,
+                     size_t ws_bytes, void* stream);
 
 const char* bvc_last_error(void);
 const char* bvc_version(void);

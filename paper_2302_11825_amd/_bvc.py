@@ -100,7 +100,7 @@ _SIGS = {
     "bvc_cache_backward": [C.c_int64, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
     "bvc_eval_fields": [C.c_int64, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp, C.c_int32, _vp, _vp, _vp],
     "bvc_gather_multi": [C.c_int32, C.c_int64, _vp, _vp, C.c_int32, _vp, _vp, C.c_int64, _vp, _vp,
-                         C.c_int32, _vp],
+                         C.c_int32, _vp, C.c_size_t, _vp],
 }
 for _name, _args in _SIGS.items():
     _fn = getattr(_L, _name)
@@ -114,9 +114,12 @@ _L.bvc_cache_backward_scratch_doubles.argtypes = [C.c_int64, C.c_int32]
 _L.bvc_cache_backward_scratch_doubles.restype = C.c_int64
 _L.bvc_pointwise_workspace_bytes.argtypes = [C.c_int32, C.c_int64, C.c_int32, C.c_int32, C.c_int32]
 _L.bvc_pointwise_workspace_bytes.restype = C.c_size_t
+_L.bvc_gather_multi_workspace_bytes.argtypes = [C.c_int64, C.c_int32]
+_L.bvc_gather_multi_workspace_bytes.restype = C.c_size_t
 
 EXPORTED = sorted(list(_SIGS) + ["bvc_last_error", "bvc_version", "bvc_compact_scratch_ints",
-                                 "bvc_cache_backward_scratch_doubles", "bvc_pointwise_workspace_bytes"])
+                                 "bvc_cache_backward_scratch_doubles", "bvc_pointwise_workspace_bytes",
+                                 "bvc_gather_multi_workspace_bytes"])
 
 
 def _check(rc, name):
@@ -316,6 +319,12 @@ def bvc_eval_fields(n_cache, nb, n_fields, E, F, w, coef, dtype_out, A, B, strea
                               ptr(B), stream_ptr(stream)), "bvc_eval_fields")
 
 
-def bvc_gather_multi(dim, n_cache, cx, cn, n_fields, A, B, n_eval, eval_x, U, precision, stream=None):
+def bvc_gather_multi_workspace_bytes(n_cache, precision) -> int:
+    return int(_L.bvc_gather_multi_workspace_bytes(n_cache, precision))
+
+
+def bvc_gather_multi(dim, n_cache, cx, cn, n_fields, A, B, n_eval, eval_x, U, precision, workspace=None,
+                     stream=None):
+    nbytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
     _check(_L.bvc_gather_multi(dim, n_cache, ptr(cx), ptr(cn), n_fields, ptr(A), ptr(B), n_eval, ptr(eval_x),
-                               ptr(U), precision, stream_ptr(stream)), "bvc_gather_multi")
+                               ptr(U), precision, ptr(workspace), nbytes, stream_ptr(stream)), "bvc_gather_multi")

@@ -12,7 +12,8 @@
 namespace bvc {
 
 int gather_multi_mfma(int dim, int64_t n_cache, const float* cx, const float* cn, int nf, const float* A,
-                      const float* B, int64_t n_eval, const float* ex, float* U, hipStream_t st);
+                      const float* B, int64_t n_eval, const float* ex, float* U, void* pack, hipStream_t st);
+int64_t gather_multi_pack_bytes(int64_t n_cache);
 
 namespace {
 
@@ -60,10 +61,10 @@ __global__ __launch_bounds__(kMBlock) void k_gather_multi_f32(int64_t n_cache, c
       r2 = fmaxf(r2, 1e-18f);
       float kd, kg;  // dG/dn and -G
       if constexpr (D == 2) {
-        kd = c2 * t * __frcp_rn(r2);
+        kd = c2 * t * __builtin_amdgcn_rcpf(r2);
         kg = -c2 * 0.5f * 0.69314718f * __log2f(r2);
       } else {
-        const float ri = __frsqrt_rn(r2);
+        const float ri = __builtin_amdgcn_rsqf(r2);
         kd = c4 * t * ri * ri * ri;
         kg = c4 * ri;
       }
@@ -83,9 +84,14 @@ __global__ __launch_bounds__(kMBlock) void k_gather_multi_f32(int64_t n_cache, c
 
 using namespace bvc;
 
+extern "C" size_t bvc_gather_multi_workspace_bytes(int64_t n_cache, int32_t precision) {
+  if (n_cache < 0) return 0;
+  return precision == BVC_SPLIT_BF16 ? (size_t)gather_multi_pack_bytes(n_cache) : 0;
+}
+
 extern "C" int bvc_gather_multi(int32_t dim, int64_t n_cache, const float* cx, const float* cn, int32_t n_fields,
                                 const float* A, const float* B, int64_t n_eval, const float* eval_x, float* U,
-                                int32_t precision, void* stream) {
+                                int32_t precision, void* workspace, size_t ws_bytes, void* stream) {
   if (dim != 2 && dim != 3) return fail(BVC_EINVAL, "dim must be 2 or 3");
   if (n_cache < 0 || n_eval < 0) return fail(BVC_EINVAL, "sizes must be >= 0");
   if (n_fields != 32 && n_fields != 64) return fail(BVC_EUNSUPPORTED, "n_fields must be 32 or 64");
@@ -93,7 +99,12 @@ extern "C" int bvc_gather_multi(int32_t dim, int64_t n_cache, const float* cx, c
   if (n_eval == 0) return BVC_OK;
   if (!eval_x || !U || (n_cache > 0 && (!cx || !cn || !A || !B))) return fail(BVC_EINVAL, "null argument");
   hipStream_t st = (hipStream_t)stream;
-  if (precision == BVC_SPLIT_BF16) return gather_multi_mfma(dim, n_cache, cx, cn, n_fields, A, B, n_eval, eval_x, U, st);
+  if (precision == BVC_SPLIT_BF16) {
+    if (!workspace || ws_bytes < (size_t)gather_multi_pack_bytes(n_cache))
+      return fail(BVC_EINVAL, "split-BF16 workspace too small");
+    if (((uintptr_t)workspace & 255) != 0) return fail(BVC_EINVAL, "workspace must be 256-byte aligned");
+    return gather_multi_mfma(dim, n_cache, cx, cn, n_fields, A, B, n_eval, eval_x, U, workspace, st);
+  }
   const int blocks = (int)((n_eval + kMBlock - 1) / kMBlock);
   if (dim == 2) {
     if (n_fields == 32)

@@ -98,7 +98,7 @@ def test_argument_validation_without_gpu():
     assert L.bvc_compact(-1, None, 1, None, None, C.byref(C.c_int64()), None) == -1
     assert L.bvc_take(7, 0, 1, None, 1, 1, None, 1, None, None) == -1
     assert L.bvc_gather_u(4, None, None, 1, None, None, None, None) == -1
-    assert L.bvc_gather_multi(3, 1, None, None, 48, None, None, 1, None, None, 0, None) == -4
+    assert L.bvc_gather_multi(3, 1, None, None, 48, None, None, 1, None, None, 0, None, 0, None) == -4
     assert L.bvc_reduce_walks(1, 0, 0, None, None, None, None, None, 0, None, None, None) == -1
     assert L.bvc_cache_walks(None, None, 0, None, None, None, None, None, None, None, None, None, None,
                              None) == -1
