@@ -314,6 +314,52 @@ int bvc_gather_multi(int32_t dim, int64_t n_cache, const float* cx, const float*
                      const float* eval_x, float* U, int32_t precision, void* workspace,
                      size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------------- */
+/* Many uneven scenes in one launch sequence                                */
+/* ---------------------------------------------------------------------- */
+/* One scene of a batch: its uploaded scene, FP32 walk parameters, its
+ * compacted cache (FP64 arrays as bvc_cache_walks takes them, plus FP32
+ * copies of positions and normals for the gather), and its interior
+ * evaluation points (FP32 [dim][n_eval]) with the output u [n_eval].  All
+ * scenes share dim and either all have a source term or none has. */
+typedef struct {
+  bvc_scene scene;
+  bvc_walk_params walk;
+  int64_t n_cache;
+  const double* x;
+  const double* nrm;
+  const double* R0;
+  const double* xbar;
+  const double* w;
+  const float* cx;
+  const float* cn;
+  int64_t n_eval;
+  const float* eval_x;
+  float* u;
+} bvc_batch_item;
+
+typedef struct bvc_batch_s* bvc_batch;
+
+/* Workspace for a batch: the scene table, per-walk samples and exit records
+ * of every scene, cache values, counters (0 on invalid items). */
+size_t bvc_batch_workspace_bytes(const bvc_batch_item* items, int32_t n_items);
+/* Validates the items and uploads the scene table into the caller's
+ * 256-byte aligned workspace (synchronises the stream once).  The handle
+ * owns host memory only; the workspace and every array an item points to
+ * must outlive it. */
+int bvc_batch_plan(const bvc_batch_item* items, int32_t n_items, void* workspace, size_t ws_bytes,
+                   void* stream, bvc_batch* out);
+/* Enqueues, over the concatenated work of all scenes: counter reset, cache
+ * walks (walk j of cache point i of a scene keeps id i*W + j and that
+ * scene's seed, so every walk equals the single-scene one), FP64 boundary
+ * data at the exits, FP64 cache means, and the gather of u (Eq. 3) at each
+ * scene's evaluation points.  Only kernels are enqueued: the call can be
+ * captured in a HIP graph and replayed. */
+int bvc_batch_launch(bvc_batch batch, void* stream);
+/* Device pointer to the batch's uint64[4] counters (as bvc_cache_walks). */
+int bvc_batch_counters(bvc_batch batch, uint64_t** dev_counters);
+int bvc_batch_destroy(bvc_batch batch);
+
 const char* bvc_last_error(void);
 const char* bvc_version(void);
 

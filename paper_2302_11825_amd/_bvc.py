@@ -63,6 +63,13 @@ class bvc_gather_params(C.Structure):
                 ("near_b", C.c_void_p)]
 
 
+class bvc_batch_item(C.Structure):
+    _fields_ = [("scene", C.c_void_p), ("walk", bvc_walk_params), ("n_cache", C.c_int64), ("x", C.c_void_p),
+                ("nrm", C.c_void_p), ("R0", C.c_void_p), ("xbar", C.c_void_p), ("w", C.c_void_p),
+                ("cx", C.c_void_p), ("cn", C.c_void_p), ("n_eval", C.c_int64), ("eval_x", C.c_void_p),
+                ("u", C.c_void_p)]
+
+
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with python -m paper_2302_11825_amd.build")
 
@@ -101,6 +108,10 @@ _SIGS = {
     "bvc_eval_fields": [C.c_int64, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp, C.c_int32, _vp, _vp, _vp],
     "bvc_gather_multi": [C.c_int32, C.c_int64, _vp, _vp, C.c_int32, _vp, _vp, C.c_int64, _vp, _vp,
                          C.c_int32, _vp, C.c_size_t, _vp],
+    "bvc_batch_plan": [_P(bvc_batch_item), C.c_int32, _vp, C.c_size_t, _vp, _P(_vp)],
+    "bvc_batch_launch": [_vp, _vp],
+    "bvc_batch_counters": [_vp, _P(_vp)],
+    "bvc_batch_destroy": [_vp],
 }
 for _name, _args in _SIGS.items():
     _fn = getattr(_L, _name)
@@ -116,10 +127,12 @@ _L.bvc_pointwise_workspace_bytes.argtypes = [C.c_int32, C.c_int64, C.c_int32, C.
 _L.bvc_pointwise_workspace_bytes.restype = C.c_size_t
 _L.bvc_gather_multi_workspace_bytes.argtypes = [C.c_int64, C.c_int32]
 _L.bvc_gather_multi_workspace_bytes.restype = C.c_size_t
+_L.bvc_batch_workspace_bytes.argtypes = [_P(bvc_batch_item), C.c_int32]
+_L.bvc_batch_workspace_bytes.restype = C.c_size_t
 
 EXPORTED = sorted(list(_SIGS) + ["bvc_last_error", "bvc_version", "bvc_compact_scratch_ints",
                                  "bvc_cache_backward_scratch_doubles", "bvc_pointwise_workspace_bytes",
-                                 "bvc_gather_multi_workspace_bytes"])
+                                 "bvc_gather_multi_workspace_bytes", "bvc_batch_workspace_bytes"])
 
 
 def _check(rc, name):
@@ -317,6 +330,33 @@ def bvc_cache_backward(n_cache, nb, E, F, w, dL_da, dL_db, scratch, dL_dtheta, s
 def bvc_eval_fields(n_cache, nb, n_fields, E, F, w, coef, dtype_out, A, B, stream=None):
     _check(_L.bvc_eval_fields(n_cache, nb, n_fields, ptr(E), ptr(F), ptr(w), ptr(coef), dtype_out, ptr(A),
                               ptr(B), stream_ptr(stream)), "bvc_eval_fields")
+
+
+def bvc_batch_workspace_bytes(items) -> int:
+    arr = (bvc_batch_item * len(items))(*items)
+    return int(_L.bvc_batch_workspace_bytes(arr, len(items)))
+
+
+def bvc_batch_plan(items, workspace, stream=None):
+    arr = (bvc_batch_item * len(items))(*items)
+    h = C.c_void_p()
+    _check(_L.bvc_batch_plan(arr, len(items), ptr(workspace), workspace.numel() * workspace.element_size(),
+                             stream_ptr(stream), C.byref(h)), "bvc_batch_plan")
+    return h
+
+
+def bvc_batch_launch(batch, stream=None):
+    _check(_L.bvc_batch_launch(batch, stream_ptr(stream)), "bvc_batch_launch")
+
+
+def bvc_batch_counters(batch) -> int:
+    p = C.c_void_p()
+    _check(_L.bvc_batch_counters(batch, C.byref(p)), "bvc_batch_counters")
+    return p.value
+
+
+def bvc_batch_destroy(batch):
+    _check(_L.bvc_batch_destroy(batch), "bvc_batch_destroy")
 
 
 def bvc_gather_multi_workspace_bytes(n_cache, precision) -> int:

@@ -92,6 +92,51 @@ struct SceneHost {
   SceneDev view() const;
 };
 
+// One scene of a multi-scene batch (device table entry).
+struct BatchSceneDev {
+  SceneDev S;
+  FieldDev g, f;
+  double eps;
+  int max_steps, W;
+  uint64_t seed;
+  uint32_t batch;
+  int cv;
+  int64_t n_cache, n_eval;
+  const double* x;     // cache [dim][n_cache] FP64
+  const double* nrm;
+  const double* R0;
+  const double* xbar;
+  const double* w;
+  const float* cx;     // cache [dim][n_cache] FP32
+  const float* cn;
+  const float* ex;     // evaluation points [dim][n_eval] FP32
+  float* u;            // [n_eval]
+  uint64_t walk_off;   // first walk of this scene in the batch's walk space
+  int64_t cache_off;   // first cache point in the batch's concatenated arrays
+  int64_t tile_off;    // first gather tile (512 evaluation points each)
+};
+
+struct BatchDev {
+  const BatchSceneDev* scenes;
+  int n_scenes;
+  int dim;
+  int has_src;
+  uint64_t total_walks;
+  int64_t total_cache;
+  int64_t total_tiles;
+  float* U;       // [total_walks]
+  float* D;       // [total_walks]
+  float* exit;    // [dim][total_walks]
+  float* w1;      // [total_walks]
+  float* a;       // [total_cache]
+  float* b;       // [total_cache]
+  unsigned long long* counters;  // [4]
+};
+
+// Batch launchers (walks.hip, kernels_gather.hip).
+int launch_batch_walks(const BatchDev& b, int max_depth, int blocks, hipStream_t st);
+int launch_batch_gather(const BatchDev& b, hipStream_t st);
+
 // Error helpers (thread-local message).
 void set_error(const std::string& msg);
 int fail(int code, const std::string& msg);

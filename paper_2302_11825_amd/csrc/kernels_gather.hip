@@ -58,10 +58,19 @@ struct GatherArgs {
 // Entry layout in LDS (8 values): 2D boundary {y0, y1, na0, na1, bl, bg}, 3D
 // boundary {y0, y1, y2, bl, na0, na1, na2, -}; sources {y.., sl, sg}.
 template <typename T, int D, bool GRAD>
+__device__ __forceinline__ void gather_block(const GatherArgs<T>& a, int64_t block, T* ent);
+
+template <typename T, int D, bool GRAD>
 __global__ __launch_bounds__(kGBlock) void k_gather(GatherArgs<T> a) {
   __shared__ T ent[kTile * 8];
+  gather_block<T, D, GRAD>(a, blockIdx.x, ent);
+}
+
+// One block's share of the gather: evaluation points [block*512, block*512+512).
+template <typename T, int D, bool GRAD>
+__device__ __forceinline__ void gather_block(const GatherArgs<T>& a, int64_t block, T* ent) {
   const int tid = threadIdx.x;
-  const int64_t k0 = (int64_t)blockIdx.x * (kGBlock * kPPT) + tid;
+  const int64_t k0 = block * (kGBlock * kPPT) + tid;
   T x[kPPT][D];
   bool live[kPPT];
 #pragma unroll
@@ -547,7 +556,46 @@ int backward_impl(int dim, const bvc_cache_view* c, const bvc_source_view* s, in
   return check_hip(hipGetLastError(), "gather backward launch");
 }
 
+// Many scenes in one launch: block t takes tile t of the batch's
+// concatenated tile list and gathers it against its own scene's cache.
+template <int D>
+__global__ __launch_bounds__(kGBlock) void k_batch_gather(BatchDev b) {
+  __shared__ float ent[kTile * 8];
+  const int64_t tile = blockIdx.x;
+  int lo = 0, hi = b.n_scenes - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (b.scenes[mid].tile_off <= tile) lo = mid;
+    else hi = mid - 1;
+  }
+  const BatchSceneDev& s = b.scenes[lo];
+  GatherArgs<float> a{};
+  a.n_eval = s.n_eval;
+  a.ex = s.ex;
+  a.n_cache = s.n_cache;
+  a.cx = s.cx;
+  a.cn = s.cn;
+  a.ca = b.a + s.cache_off;
+  a.cb = b.b + s.cache_off;
+  a.n_src = 0;
+  a.u = s.u;
+  a.g = nullptr;
+  a.scale = nullptr;
+  a.accumulate = 0;
+  gather_block<float, D, false>(a, tile - s.tile_off, ent);
+}
+
 }  // namespace
+
+int launch_batch_gather(const BatchDev& b, hipStream_t st) {
+  if (b.total_tiles <= 0) return BVC_OK;
+  if (b.dim == 2)
+    hipLaunchKernelGGL(k_batch_gather<2>, dim3((unsigned)b.total_tiles), dim3(kGBlock), 0, st, b);
+  else
+    hipLaunchKernelGGL(k_batch_gather<3>, dim3((unsigned)b.total_tiles), dim3(kGBlock), 0, st, b);
+  return check_hip(hipGetLastError(), "batch gather launch");
+}
+
 }  // namespace bvc
 
 using namespace bvc;

@@ -394,6 +394,231 @@ int run_walks(bvc_scene s, const bvc_walk_params* p, int mode, int64_t n, WalkAr
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// ---------------------------------------------------------------------------
+// Many scenes in one launch: the walk space of the batch is the
+// concatenation of every scene's walk ids; a lane maps its global id to
+// (scene, local id) by binary search over the scenes' offsets and then runs
+// exactly the walk of the single-scene kernel (same counters, same stream).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int batch_scene_of_walk(const BatchDev& b, uint64_t g) {
+  int lo = 0, hi = b.n_scenes - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (b.scenes[mid].walk_off <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void k_batch_zero(unsigned long long* c) {
+  if (threadIdx.x < 4) c[threadIdx.x] = 0ull;
+}
+
+template <int D, bool SRC>
+__global__ __launch_bounds__(kBlock) void k_batch_walks(BatchDev b) {
+  extern __shared__ uint2 lds[];
+  uint2* stk = lds + threadIdx.x;
+  const int stride = blockDim.x;
+  const int lane = threadIdx.x & 63;
+  bool active = false, exhausted = false;
+  uint64_t gid = 0;
+  uint32_t id = 0;
+  int k = 0, hint = -1, sc = 0;
+  float p[D];
+  float acc_s = 0.f, usrc = 0.f, eps = 0.f;
+  unsigned long long steps_acc = 0, capped_acc = 0, walks_acc = 0;
+#pragma unroll
+  for (int q = 0; q < D; ++q) p[q] = 0.f;
+  while (true) {
+    if (!exhausted) {
+      const uint64_t need = __ballot(!active);
+      if (need) {
+        const int leader = __ffsll((unsigned long long)need) - 1;
+        const int cnt = __popcll(need);
+        unsigned long long base = 0;
+        if (lane == leader) base = atomicAdd(&b.counters[0], (unsigned long long)cnt);
+        base = __shfl(base, leader);
+        if (base + cnt >= b.total_walks) exhausted = true;
+        if (!active) {
+          const unsigned long long my = base + __popcll(need & ((1ull << lane) - 1));
+          if (my < b.total_walks) {
+            gid = my;
+            sc = batch_scene_of_walk(b, gid);
+            const BatchSceneDev& s = b.scenes[sc];
+            id = (uint32_t)(gid - s.walk_off);
+            eps = (float)s.eps;
+            const int64_t i = (int64_t)(id / (uint32_t)s.W);
+            const float R0 = (float)s.R0[i];
+            float x0[D], nu0[D];
+#pragma unroll
+            for (int q = 0; q < D; ++q) x0[q] = (float)s.x[q * s.n_cache + i];
+            walk_direction<float, D>(s.seed, 0, id, s.batch, 1u, nu0);
+            float dn = 0.f;
+#pragma unroll
+            for (int q = 0; q < D; ++q) {
+              p[q] = fmaf(R0, nu0[q], x0[q]);
+              dn = fmaf(nu0[q], (float)s.nrm[q * s.n_cache + i], dn);
+            }
+            const float w1 = (float)D / R0 * dn;
+            usrc = 0.f;
+            float ds = 0.f;
+            if constexpr (SRC) {
+              float yu[D];
+              ball_source_point<float, D>(s.seed, 0, id, s.batch, 1u, x0, R0, yu);
+              usrc = -R0 * R0 / (float)(2 * D) * walk_source<float, D>(s.f, yu);
+              if constexpr (D == 2) {
+                float u1, u2, u3, u4;
+                Uniform<float>::pair(s.seed, 2, id, s.batch, 1u, u1, u2);
+                Uniform<float>::pair(s.seed, 3, id, s.batch, 1u, u3, u4);
+                const float sg = 2.f * sinf(asinf(u2) / 3.f);
+                float sn, cs;
+                sincos_turns(u3, &sn, &cs);
+                const float yg[2] = {fmaf(R0 * sg, cs, x0[0]), fmaf(R0 * sg, sn, x0[1])};
+                const float c = -2.f * R0 / 3.f * walk_source<float, D>(s.f, yg);
+                ds = c * (cs * (float)s.nrm[i] + sn * (float)s.nrm[s.n_cache + i]);
+              }
+            }
+            b.w1[gid] = w1;
+            b.D[gid] = ds - w1 * usrc;
+            acc_s = 0.f;
+            k = 1;
+            hint = -1;
+            active = true;
+          }
+        }
+      }
+    }
+    if (!__any(active)) {
+      if (exhausted) break;
+      continue;
+    }
+    if (active) {
+      const BatchSceneDev& s = b.scenes[sc];
+      float q[D];
+      const float d = fsqrt(closest_point<float, D>(s.S, p, hint, q, stk, stride));
+      const bool stop = d < eps;
+      const bool cap = !stop && k >= s.max_steps;
+      if (stop || cap) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) b.exit[(size_t)c * b.total_walks + gid] = q[c];
+        b.U[gid] = acc_s + usrc;
+        steps_acc += (unsigned long long)k;
+        capped_acc += cap ? 1ull : 0ull;
+        ++walks_acc;
+        active = false;
+      } else {
+        if constexpr (SRC) {
+          float y[D];
+          ball_source_point<float, D>(s.seed, (uint32_t)k, id, s.batch, 1u, p, d, y);
+          acc_s = fmaf(-d * d / (float)(2 * D), walk_source<float, D>(s.f, y), acc_s);
+        }
+        float nu[D];
+        walk_direction<float, D>(s.seed, (uint32_t)k, id, s.batch, 1u, nu);
+#pragma unroll
+        for (int c = 0; c < D; ++c) p[c] = fmaf(d, nu[c], p[c]);
+        ++k;
+      }
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    steps_acc += __shfl_xor(steps_acc, off);
+    capped_acc += __shfl_xor(capped_acc, off);
+    walks_acc += __shfl_xor(walks_acc, off);
+  }
+  if (lane == 0) {
+    atomicAdd(&b.counters[1], steps_acc);
+    atomicAdd(&b.counters[2], capped_acc);
+    atomicAdd(&b.counters[3], walks_acc);
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_batch_finish(BatchDev b) {
+  const uint64_t id0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * kFinishRun;
+  if (id0 >= b.total_walks) return;
+  int64_t i_cv = -1;
+  int sc_cv = -1;
+  double c = 0.0;
+  for (int r = 0; r < kFinishRun; ++r) {
+    const uint64_t gid = id0 + r;
+    if (gid >= b.total_walks) break;
+    const int sc = batch_scene_of_walk(b, gid);
+    const BatchSceneDev& s = b.scenes[sc];
+    const int64_t i = (int64_t)((gid - s.walk_off) / (uint64_t)s.W);
+    if (s.cv && (i != i_cv || sc != sc_cv)) {
+      double xb[D];
+#pragma unroll
+      for (int a = 0; a < D; ++a) xb[a] = s.xbar[a * s.n_cache + i];
+      c = field_value(s.g, D, xb);
+      i_cv = i;
+      sc_cv = sc;
+    }
+    if (!s.cv) c = 0.0;
+    double q[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) q[a] = (double)b.exit[(size_t)a * b.total_walks + gid];
+    const double gq = field_value(s.g, D, q);
+    const double su = (double)b.U[gid];
+    b.U[gid] = (float)(gq + su);
+    b.D[gid] = (float)((double)b.w1[gid] * (gq + su - c) + (double)b.D[gid]);
+  }
+}
+
+// Cache means per point of the batch (one wave per cache point, FP64).
+__global__ __launch_bounds__(kBlock) void k_batch_reduce(BatchDev b) {
+  const int lane = threadIdx.x & 63;
+  const int64_t gi = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (gi >= b.total_cache) return;
+  int lo = 0, hi = b.n_scenes - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (b.scenes[mid].cache_off <= gi) lo = mid;
+    else hi = mid - 1;
+  }
+  const BatchSceneDev& s = b.scenes[lo];
+  const int64_t i = gi - s.cache_off;
+  const uint64_t base = s.walk_off + (uint64_t)i * s.W;
+  double su = 0.0, sd = 0.0;
+  for (int j = lane; j < s.W; j += 64) {
+    su += (double)b.U[base + j];
+    sd += (double)b.D[base + j];
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    su += __shfl_xor(su, off);
+    sd += __shfl_xor(sd, off);
+  }
+  if (lane == 0) {
+    b.a[gi] = (float)(su / s.W * s.w[i]);
+    b.b[gi] = (float)(sd / s.W * s.w[i]);
+  }
+}
+
+}  // namespace
+
+int launch_batch_walks(const BatchDev& b, int max_depth, int blocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_zero, dim3(1), dim3(64), 0, st, b.counters);
+  if (b.total_walks == 0) return check_hip(hipGetLastError(), "batch walks");
+  const size_t lds = (size_t)(max_depth + 1) * kBlock * sizeof(uint2);
+  const int64_t needed = (int64_t)((b.total_walks + kBlock - 1) / kBlock);
+  blocks = (int)std::max<int64_t>(1, std::min<int64_t>(blocks > 0 ? blocks : num_cus() * 8, needed));
+  if (b.dim == 2) {
+    if (b.has_src) hipLaunchKernelGGL((k_batch_walks<2, true>), dim3(blocks), dim3(kBlock), lds, st, b);
+    else hipLaunchKernelGGL((k_batch_walks<2, false>), dim3(blocks), dim3(kBlock), lds, st, b);
+  } else {
+    if (b.has_src) hipLaunchKernelGGL((k_batch_walks<3, true>), dim3(blocks), dim3(kBlock), lds, st, b);
+    else hipLaunchKernelGGL((k_batch_walks<3, false>), dim3(blocks), dim3(kBlock), lds, st, b);
+  }
+  const uint64_t threads = (b.total_walks + kFinishRun - 1) / kFinishRun;
+  const int fblocks = (int)((threads + kBlock - 1) / kBlock);
+  if (b.dim == 2) hipLaunchKernelGGL(k_batch_finish<2>, dim3(fblocks), dim3(kBlock), 0, st, b);
+  else hipLaunchKernelGGL(k_batch_finish<3>, dim3(fblocks), dim3(kBlock), 0, st, b);
+  const int per = kBlock / 64;
+  const int rblocks = (int)((b.total_cache + per - 1) / per);
+  if (rblocks > 0) hipLaunchKernelGGL(k_batch_reduce, dim3(rblocks), dim3(kBlock), 0, st, b);
+  return check_hip(hipGetLastError(), "batch walk launch");
+}
+
+namespace {
 }  // namespace
 }  // namespace bvc
 

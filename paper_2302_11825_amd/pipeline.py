@@ -240,6 +240,79 @@ class Prepared:
         self.x_band = take(self.eval64, self.idx_band, self.n_band, self.sc.dim, n, T)
 
 
+class SceneBatch:
+    """Many scenes sharing one launch sequence (bvc_batch_plan / _launch).
+
+    Each entry is (problem, n_eval_candidates) with a Laplace or Poisson
+    problem in FP32; caches are drawn once here, evaluation points classified,
+    and bvc_batch_launch then runs walks, boundary data, means and the gather
+    of every scene with five kernels, which a caller may capture in a graph.
+    """
+
+    def __init__(self, problems, device="cuda", cache_batch=0):
+        self.entries = []
+        items = []
+        for p in problems:
+            sc = Scene(p.scene, device)
+            g = DeviceField(p.g, device)
+            f = DeviceField(p.f, device) if not p.f.is_zero else None
+            n_cand = candidates_for(sc, p.n_cache, p.offset, p.sides, p.seed_cache)
+            cache = sample_cache(sc, n_cand, p.offset, p.sides, p.seed_cache, cache_batch)
+            d = sc.dim
+            cx = take(cache.x, None, cache.n, d, max(cache.n, 1), torch.float32)
+            cn = take(cache.nrm, None, cache.n, d, max(cache.n, 1), torch.float32)
+            ex64 = torch.from_numpy(np.ascontiguousarray(p.eval_x.T)).to(device)
+            cls, _ = classify(sc, ex64, p.offset)
+            idx, n_int = sc.compact(cls, 1)
+            x_int = take(ex64, idx, n_int, d, ex64.shape[1], torch.float32)
+            u = torch.empty(max(n_int, 1), dtype=torch.float32, device=device)
+            wp = walk_params(p.eps, p.n_walks, p.seed_walks, g, f, "f32", cache_batch)
+            it = B.bvc_batch_item()
+            it.scene = sc.h
+            it.walk = wp
+            it.n_cache = cache.n
+            it.x, it.nrm, it.R0, it.xbar, it.w = (t.data_ptr() for t in (cache.x, cache.nrm, cache.R0, cache.xbar,
+                                                                          cache.w))
+            it.cx, it.cn = cx.data_ptr(), cn.data_ptr()
+            it.n_eval = n_int
+            it.eval_x = x_int.data_ptr()
+            it.u = u.data_ptr()
+            items.append(it)
+            self.entries.append(dict(problem=p, scene=sc, g=g, f=f, cache=cache, cx=cx, cn=cn, x=x_int, n_int=n_int,
+                                     idx=idx, u=u, params=wp))
+        self.items = items
+        nbytes = B.bvc_batch_workspace_bytes(items)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.h = B.bvc_batch_plan(items, self.ws)
+
+    def __del__(self):
+        try:
+            B.bvc_batch_destroy(self.h)
+        except Exception:
+            pass
+
+    def launch(self):
+        B.bvc_batch_launch(self.h)
+
+    def counters(self):
+        """The batch's uint64[4] counters (work queue, queries, capped, walks)."""
+        off = B.bvc_batch_counters(self.h) - self.ws.data_ptr()
+        return self.ws[off:off + 32].view(torch.int64).cpu().numpy()
+
+    def run_sequential(self):
+        """The same work with one call sequence per scene (walks, means, gather)."""
+        outs = []
+        for e in self.entries:
+            p, sc, cache = e["problem"], e["scene"], e["cache"]
+            U, D, rec, _ = cache_walks(sc, cache, e["params"], "f32")
+            uhat, dudn, a, b = reduce_walks(cache, p.n_walks, U, D, "f32")
+            u = torch.empty(max(e["n_int"], 1), dtype=torch.float32, device=sc.device)
+            cview = dict(n=cache.n, dtype=B.F32, x=e["cx"], nrm=e["cn"], a=a, b=b)
+            B.bvc_gather_u(sc.dim, cview, None, e["n_int"], e["x"], u)
+            outs.append(u)
+        return outs
+
+
 class Stopwatch:
     """HIP events around named stages on torch's current stream (the stream
     every library call is enqueued on)."""
