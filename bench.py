@@ -49,6 +49,10 @@ def parse():
     ap.add_argument("--no-pointwise", action="store_true", help="skip the pointwise-WoS comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4a", "c4b"],
+                    help="c2 prints the benchmark line; the others print their own measurement lines")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="copy this many MiB device-to-device before timing (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -69,6 +73,11 @@ def main():
     from paper_2302_11825_amd import pipeline as pl
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload != "c2":
+        from paper_2302_11825_amd import measure
+
+        measure.run(args)
+        return
     t_setup = time.time()
     prob = wl.problem_c2(grid=args.grid)
     prep = pl.Prepared(prob, dtype=args.dtype)
@@ -77,6 +86,13 @@ def main():
     print(f"[bench] setup {setup_s:.1f}s: candidates {prep.n_cand}, interior {prep.n_int}, band {prep.n_band}",
           file=sys.stderr, flush=True)
 
+    if args.calib_copy_mib > 0:
+        # a plain copy of known size: the reference that scales HBM counters
+        src = torch.empty(args.calib_copy_mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for w in range(args.warmup):
         pl.solve(prep, batch=1000 + w)
     torch.cuda.synchronize()

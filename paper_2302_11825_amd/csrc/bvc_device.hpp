@@ -226,6 +226,28 @@ struct SceneArrays<double> {
   __device__ static const double* prim(const SceneDev& s) { return s.prim64; }
 };
 
+// Vertices (a, b, c) of leaf-ordered triangle i.
+template <typename T>
+__device__ __forceinline__ void load_triangle(const SceneDev& S, int i, T* v) {
+  const T* pr = SceneArrays<T>::prim(S);
+  if constexpr (sizeof(T) == 4) {
+    const float4* r = reinterpret_cast<const float4*>(pr) + 3 * i;
+    const float4 r0 = r[0], r1 = r[1], r2 = r[2];
+    v[0] = r0.x; v[1] = r0.y; v[2] = r0.z; v[3] = r0.w;
+    v[4] = r1.x; v[5] = r1.y; v[6] = r1.z; v[7] = r1.w;
+    v[8] = r2.x;
+  } else {
+    const double2* r = reinterpret_cast<const double2*>(pr) + 6 * i;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const double2 w = r[j];
+      v[2 * j] = w.x;
+      v[2 * j + 1] = w.y;
+    }
+    v[8] = r[4].x;
+  }
+}
+
 // Distance^2 and closest point of leaf-ordered primitive i.
 template <typename T, int D>
 __device__ __forceinline__ T prim_d2(const SceneDev& S, int i, const T* p, T* q, int& region) {
@@ -242,22 +264,7 @@ __device__ __forceinline__ T prim_d2(const SceneDev& S, int i, const T* p, T* q,
     }
   } else {
     T v[9];
-    if constexpr (sizeof(T) == 4) {
-      const float4* r = reinterpret_cast<const float4*>(pr) + 3 * i;
-      const float4 r0 = r[0], r1 = r[1], r2 = r[2];
-      v[0] = r0.x; v[1] = r0.y; v[2] = r0.z; v[3] = r0.w;
-      v[4] = r1.x; v[5] = r1.y; v[6] = r1.z; v[7] = r1.w;
-      v[8] = r2.x;
-    } else {
-      const double2* r = reinterpret_cast<const double2*>(pr) + 6 * i;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const double2 w = r[j];
-        v[2 * j] = w.x;
-        v[2 * j + 1] = w.y;
-      }
-      v[8] = r[4].x;
-    }
+    load_triangle<T>(S, i, v);
     return triangle_d2<T>(p, v, v + 3, v + 6, q, region);
   }
 }
@@ -290,19 +297,64 @@ __device__ __forceinline__ void load_child_boxes(const SceneDev& S, int node, T*
 __device__ __forceinline__ float lower_bound_f32(float d) { return d; }
 __device__ __forceinline__ float lower_bound_f32(double d) { return __double2float_rd(d); }
 
+// Traversal stack entry, 32 bits: node index (17 bits) and a lower bound of
+// the node's box distance^2 as the 15 non-sign bits of an FP16 number,
+// obtained by truncating the FP32 mantissa (round toward zero, which for a
+// non-negative value rounds down).  Values below the smallest normal FP16
+// become 0 and values beyond the largest become the largest: both still
+// bound the true distance from below, so pruning stays exact.
+__device__ __forceinline__ uint32_t stack_entry(int node, float d2) {
+  const uint32_t bits = __float_as_uint(d2);
+  const int e = (int)(bits >> 23) - 127 + 15;
+  uint32_t h;
+  if (!(d2 > 0.0f) || e <= 0) h = 0;
+  else if (e >= 31) h = 0x7BFF;
+  else h = ((uint32_t)e << 10) | ((bits >> 13) & 0x3FF);
+  return ((uint32_t)node << 15) | h;
+}
+__device__ __forceinline__ int stack_node(uint32_t s) { return (int)(s >> 15); }
+__device__ __forceinline__ float stack_bound(uint32_t s) {
+  const uint32_t h = s & 0x7FFF;
+  if (h == 0) return 0.0f;
+  return __uint_as_float(((((h >> 10) & 0x1F) - 15 + 127) << 23) | ((h & 0x3FF) << 13));
+}
+
+// Lower bound of the distance^2 from p to a triangle: distance to its box.
+template <typename T>
+__device__ __forceinline__ T triangle_box_d2(const T* p, const T* v) {
+  T d2 = T(0);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const T lo = fmin(fmin(v[a], v[3 + a]), v[6 + a]);
+    const T hi = fmax(fmax(v[a], v[3 + a]), v[6 + a]);
+    const T e = fmax(fmax(lo - p[a], p[a] - hi), T(0));
+    d2 += e * e;
+  }
+  return d2;
+}
+
 // Nearest-first closest-point query over the BVH with the traversal stack in
-// LDS (entry: node, box distance^2 rounded down to FP32).  best/bi/bq carry
-// an initial candidate (bi < 0: none); the result is the minimum of
+// LDS (one 32-bit entry per level, see stack_entry).  best/bi/bq carry an
+// initial candidate (bi < 0: none); the result is the minimum of
 // (distance^2, original primitive id).
 template <typename T, int D>
 __device__ __forceinline__ void bvh_closest(const SceneDev& S, const T* p, T& best, int& bi, T* bq,
-                                            uint2* stk, int stride) {
+                                            uint32_t* stk, int stride) {
   auto consider = [&](int leaf) {
     const int s0 = leaf_start(leaf), n = leaf_count(leaf);
     for (int i = s0; i < s0 + n; ++i) {
       T q[D];
       int reg;
-      const T d2 = prim_d2<T, D>(S, i, p, q, reg);
+      T d2;
+      if constexpr (D == 3) {
+        // skip the exact test when the triangle's box is already farther
+        T v[9];
+        load_triangle<T>(S, i, v);
+        if (triangle_box_d2<T>(p, v) > best) continue;
+        d2 = triangle_d2<T>(p, v, v + 3, v + 6, q, reg);
+      } else {
+        d2 = prim_d2<T, D>(S, i, p, q, reg);
+      }
       bool take = d2 < best;
       if (!take && d2 == best && i != bi) take = bi < 0 || S.prim_id[i] < S.prim_id[bi];
       if (take) {
@@ -341,24 +393,114 @@ __device__ __forceinline__ void bvh_closest(const SceneDev& S, const T* p, T& be
       } else if (next < 0) {
         next = c1;
       } else {
-        stk[sp * stride] = make_uint2((uint32_t)c1, __float_as_uint(lower_bound_f32(d1)));
+        stk[sp * stride] = stack_entry(c1, lower_bound_f32(d1));
         ++sp;
       }
     }
     while (next < 0 && sp > 0) {
       --sp;
-      const uint2 e = stk[sp * stride];
-      if ((T)__uint_as_float(e.y) <= best) next = (int)e.x;
+      const uint32_t e = stk[sp * stride];
+      if ((T)stack_bound(e) <= best) next = stack_node(e);
     }
     if (next < 0) break;
     node = next;
   }
 }
 
+// Resumable form of the same nearest-first query: query_begin seeds it (with
+// the hint primitive as the initial candidate) and each query_step expands one
+// node, so a wave can interleave queries of different lengths.  node < 0
+// marks a finished query; best/bi/bq then hold the result.
+template <typename T, int D>
+struct Query {
+  int node;
+  int sp;
+  int bi;
+  T best;
+  T bq[D];
+};
+
+template <typename T, int D>
+__device__ __forceinline__ void query_begin(const SceneDev& S, const T* p, int hint, Query<T, D>& q) {
+  q.node = 0;
+  q.sp = 0;
+  q.best = T(INFINITY);
+  q.bi = -1;
+  if (hint >= 0) {
+    int reg;
+    q.best = prim_d2<T, D>(S, hint, p, q.bq, reg);
+    q.bi = hint;
+  }
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void query_step(const SceneDev& S, const T* p, Query<T, D>& q, uint32_t* stk,
+                                           int stride) {
+  auto consider = [&](int leaf) {
+    const int s0 = leaf_start(leaf), n = leaf_count(leaf);
+    for (int i = s0; i < s0 + n; ++i) {
+      T qq[D];
+      int reg;
+      T d2;
+      if constexpr (D == 3) {
+        T v[9];
+        load_triangle<T>(S, i, v);
+        if (triangle_box_d2<T>(p, v) > q.best) continue;
+        d2 = triangle_d2<T>(p, v, v + 3, v + 6, qq, reg);
+      } else {
+        d2 = prim_d2<T, D>(S, i, p, qq, reg);
+      }
+      bool take = d2 < q.best;
+      if (!take && d2 == q.best && i != q.bi) take = q.bi < 0 || S.prim_id[i] < S.prim_id[q.bi];
+      if (take) {
+        q.best = d2;
+        q.bi = i;
+#pragma unroll
+        for (int a = 0; a < D; ++a) q.bq[a] = qq[a];
+      }
+    }
+  };
+  T lo0[D], hi0[D], lo1[D], hi1[D];
+  load_child_boxes<T, D>(S, q.node, lo0, hi0, lo1, hi1);
+  const int2 ch = S.child[q.node];
+  T d0 = box_d2<T, D>(lo0, hi0, p);
+  T d1 = box_d2<T, D>(lo1, hi1, p);
+  int c0 = ch.x, c1 = ch.y;
+  if (d1 < d0) {
+    const T td = d0;
+    d0 = d1;
+    d1 = td;
+    const int tc = c0;
+    c0 = c1;
+    c1 = tc;
+  }
+  int next = -1;
+  if (d0 <= q.best) {
+    if (c0 < 0) consider(c0);
+    else next = c0;
+  }
+  if (d1 <= q.best) {
+    if (c1 < 0) {
+      consider(c1);
+    } else if (next < 0) {
+      next = c1;
+    } else {
+      stk[q.sp * stride] = stack_entry(c1, lower_bound_f32(d1));
+      ++q.sp;
+    }
+  }
+  while (next < 0 && q.sp > 0) {
+    --q.sp;
+    const uint32_t e = stk[q.sp * stride];
+    if ((T)stack_bound(e) <= q.best) next = stack_node(e);
+  }
+  q.node = next;
+}
+
 // Closest point with an optional hint primitive (walk coherence: the
 // previous step's closest primitive bounds the new distance from above).
 template <typename T, int D>
-__device__ __forceinline__ T closest_point(const SceneDev& S, const T* p, int& hint, T* q, uint2* stk,
+__device__ __forceinline__ T closest_point(const SceneDev& S, const T* p, int& hint, T* q, uint32_t* stk,
                                            int stride) {
   T best = T(INFINITY);
   int bi = -1;

@@ -25,7 +25,7 @@ namespace {
 constexpr int kBlock = 256;
 
 inline size_t stack_bytes(const SceneHost& h, int block) {
-  return (size_t)(h.depth + 1) * block * sizeof(uint2);
+  return (size_t)(h.depth + 1) * block * sizeof(uint32_t);
 }
 
 }  // namespace
@@ -126,7 +126,7 @@ template <int D>
 __global__ __launch_bounds__(kBlock) void k_sample_cache(SceneDev S, int64_t n, double l, uint64_t seed,
                                                           uint32_t batch, double M, double* x, double* nrm,
                                                           double* w, double* xbar, double* R0, int* acc) {
-  extern __shared__ uint2 lds[];
+  extern __shared__ uint32_t lds[];
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   double ua, ub;
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(kBlock) void k_sample_sources(SceneDev S, FieldDev 
                                                             double lo1, double lo2, double hi0, double hi1,
                                                             double hi2, double l, uint64_t seed, uint32_t batch,
                                                             double* y, double* s) {
-  extern __shared__ uint2 lds[];
+  extern __shared__ uint32_t lds[];
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= M) return;
   double u[4];
@@ -190,7 +190,7 @@ __global__ __launch_bounds__(kBlock) void k_sample_sources(SceneDev S, FieldDev 
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_classify(SceneDev S, int64_t n, const double* x, double l, int* cls,
                                                       double* dist) {
-  extern __shared__ uint2 lds[];
+  extern __shared__ uint32_t lds[];
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   double xk[D];

@@ -321,6 +321,7 @@ static int build_scene(SceneHost& S, int dim, const double* verts, int64_t nv, c
     q.push(T[t].right);
   }
   int nn = (int)order.size();
+  if (nn >= (1 << 17)) return fail(BVC_EUNSUPPORTED, "scene needs more than 2^17 BVH nodes");
   int bw = 4 * dim;  // doubles per node: two children x (lo, hi)
   S.child.resize(nn);
   S.box64.assign((size_t)nn * bw, 0.0);

@@ -66,10 +66,19 @@ __device__ __forceinline__ T walk_source(const FieldDev& F, const T* y) {
   return sum;
 }
 
+// A walk alternates closest-point queries and sphere jumps.  Queries differ in
+// length by orders of magnitude (a point near a curved boundary touches few
+// nodes, one deep inside a near-spherical domain touches hundreds), so the
+// query is resumable: each iteration expands one BVH node for every lane whose
+// query is open, and the jump of the lanes whose query closed runs only once
+// at most kOpenLanes lanes of the wave are still querying.  A long query no
+// longer holds the other 63 lanes back.
+constexpr int kOpenLanes = 8;
+
 template <typename T, int D, bool SRC, int MODE>
 __global__ __launch_bounds__(kBlock) void k_walks(WalkArgs a) {
-  extern __shared__ uint2 lds[];
-  uint2* stk = lds + threadIdx.x;
+  extern __shared__ uint32_t lds[];
+  uint32_t* stk = lds + threadIdx.x;
   const int stride = blockDim.x;
   const int lane = threadIdx.x & 63;
   const uint32_t tag = MODE == 0 ? 1u : 2u;
@@ -82,14 +91,17 @@ __global__ __launch_bounds__(kBlock) void k_walks(WalkArgs a) {
 
   bool active = false, exhausted = false;
   uint32_t id = 0;
-  int k = 0, hint = -1;
+  int k = 0;
   T p[D];
   T acc_s = T(0), usrc = T(0);
+  Query<T, D> qs;
+  qs.node = -1;
   unsigned long long steps_acc = 0, capped_acc = 0, walks_acc = 0;
 #pragma unroll
   for (int q = 0; q < D; ++q) p[q] = T(0);
 
   while (true) {
+    // ---- refill idle lanes with new walks (their first ball starts a query)
     if (!exhausted) {
       const uint64_t need = __ballot(!active);
       if (need) {
@@ -172,7 +184,7 @@ __global__ __launch_bounds__(kBlock) void k_walks(WalkArgs a) {
               }
               acc_s = T(0);
               k = 1;
-              hint = -1;
+              query_begin<T, D>(S, p, -1, qs);
               active = true;
             }
           }
@@ -183,14 +195,20 @@ __global__ __launch_bounds__(kBlock) void k_walks(WalkArgs a) {
       if (exhausted) break;
       continue;
     }
-    if (active) {
-      T q[D];
-      const T d = fsqrt(closest_point<T, D>(S, p, hint, q, stk, stride));
+    // ---- expand one node per open query until few queries remain open
+    while (true) {
+      const bool open = active && qs.node >= 0;
+      if (open) query_step<T, D>(S, p, qs, stk, stride);
+      if (__popcll(__ballot(active && qs.node >= 0)) <= kOpenLanes) break;
+    }
+    // ---- lanes whose query closed: stop in the shell, or jump
+    if (active && qs.node < 0) {
+      const T d = fsqrt(qs.best);
       const bool stop = d < eps;
       const bool cap = !stop && k >= a.max_steps;
       if (stop || cap) {
 #pragma unroll
-        for (int c = 0; c < D; ++c) EX[(size_t)c * a.total + id] = q[c];
+        for (int c = 0; c < D; ++c) EX[(size_t)c * a.total + id] = qs.bq[c];
         U[id] = acc_s + usrc;
         if (a.steps) a.steps[id] = k;
         steps_acc += (unsigned long long)k;
@@ -208,6 +226,7 @@ __global__ __launch_bounds__(kBlock) void k_walks(WalkArgs a) {
 #pragma unroll
         for (int c = 0; c < D; ++c) p[c] = fma(d, nu[c], p[c]);
         ++k;
+        query_begin<T, D>(S, p, qs.bi, qs);
       }
     }
   }
@@ -269,7 +288,7 @@ __global__ __launch_bounds__(kBlock) void k_finish(FieldDev g, int cv, uint64_t 
 template <typename T, int D>
 __global__ __launch_bounds__(kBlock) void k_closest_points(SceneDev S, int64_t n, const T* x, double* R0,
                                                             double* xbar) {
-  extern __shared__ uint2 lds[];
+  extern __shared__ uint32_t lds[];
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   T p[D], q[D];
@@ -351,7 +370,7 @@ void launch_finish(const bvc_walk_params* p, int mode, const WalkArgs& a, hipStr
                        a.W, a.n_pts, a.xbar, (const T*)a.exit, (T*)a.U, (T*)a.Dof, (const T*)a.w1);
 }
 
-size_t stack_bytes(const SceneHost& h) { return (size_t)(h.depth + 1) * kBlock * sizeof(uint2); }
+size_t stack_bytes(const SceneHost& h) { return (size_t)(h.depth + 1) * kBlock * sizeof(uint32_t); }
 
 int run_walks(bvc_scene s, const bvc_walk_params* p, int mode, int64_t n, WalkArgs& a, hipStream_t st) {
   const SceneHost& h = s->h;
@@ -416,8 +435,8 @@ __global__ void k_batch_zero(unsigned long long* c) {
 
 template <int D, bool SRC>
 __global__ __launch_bounds__(kBlock) void k_batch_walks(BatchDev b) {
-  extern __shared__ uint2 lds[];
-  uint2* stk = lds + threadIdx.x;
+  extern __shared__ uint32_t lds[];
+  uint32_t* stk = lds + threadIdx.x;
   const int stride = blockDim.x;
   const int lane = threadIdx.x & 63;
   bool active = false, exhausted = false;
@@ -598,7 +617,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_reduce(BatchDev b) {
 int launch_batch_walks(const BatchDev& b, int max_depth, int blocks, hipStream_t st) {
   hipLaunchKernelGGL(k_batch_zero, dim3(1), dim3(64), 0, st, b.counters);
   if (b.total_walks == 0) return check_hip(hipGetLastError(), "batch walks");
-  const size_t lds = (size_t)(max_depth + 1) * kBlock * sizeof(uint2);
+  const size_t lds = (size_t)(max_depth + 1) * kBlock * sizeof(uint32_t);
   const int64_t needed = (int64_t)((b.total_walks + kBlock - 1) / kBlock);
   blocks = (int)std::max<int64_t>(1, std::min<int64_t>(blocks > 0 ? blocks : num_cus() * 8, needed));
   if (b.dim == 2) {

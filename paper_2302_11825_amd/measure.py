@@ -1,0 +1,212 @@
+"""Measurements of the workloads other than the 2D Poisson benchmark line.
+
+    python bench.py --workload c3    3D Laplace, displaced icosphere (81,920 triangles)
+    python bench.py --workload c4a   64 boundary-data fields on the 3D walks:
+                                     split-BF16 MFMA vs FP32 multi-RHS vs 64 plain gathers
+    python bench.py --workload c4b   32 uneven 2D scenes: one graph-replayed launch
+                                     sequence vs per-scene call sequences
+
+Each prints one JSON line.  Inputs are the seeded synthetic workloads.
+"""
+from __future__ import annotations
+
+import json
+import math
+import sys
+import time
+
+import numpy as np
+import torch
+
+import workloads as wl
+
+from . import _bvc as B
+from . import pipeline as pl
+
+
+# Algorithmic FP operations of one 3D boundary pair for u (Eq. 3): difference
+# (3), r^2 (5), rsqrt (1), r^-2 and r^-3 (2), n.(y-x) (5), the two terms and
+# their accumulation (4).
+FLOPS_3D_BOUNDARY_U = 20
+
+
+def _ev():
+    return torch.cuda.Event(enable_timing=True)
+
+
+def _time(fn, reps=1):
+    e0, e1 = _ev(), _ev()
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def _log(msg):
+    print(f"[measure] {msg}", file=sys.stderr, flush=True)
+
+
+def run(args):
+    {"c3": c3, "c4a": c4a, "c4b": c4b}[args.workload](args)
+
+
+def _c3_setup():
+    prob = wl.problem_c3()
+    t = time.time()
+    prep = pl.Prepared(prob, dtype="f32")
+    torch.cuda.synchronize()
+    _log(f"c3 setup {time.time() - t:.1f}s candidates {prep.n_cand} interior {prep.n_int} band {prep.n_band}")
+    return prob, prep
+
+
+def c3(args):
+    prob, prep = _c3_setup()
+    for w in range(args.warmup):
+        pl.solve(prep, batch=100 + w, with_grad=False)
+    torch.cuda.synchronize()
+    watch = pl.Stopwatch()
+    sols = []
+    ms = _time(lambda: sols.append(pl.solve(prep, batch=len(sols), with_grad=False, watch=watch)), args.steps)
+    stages = {k: float(np.mean(v)) for k, v in watch.totals_ms().items()}
+    sol = sols[-1]
+    idx = prep.idx_int[: prep.n_int].cpu().numpy()
+    n_box = prob.extra["n_box"]
+    sub = idx[:: max(1, idx.size // 200000)]
+    u = sol.u_int[: prep.n_int].double().cpu().numpy()[:: max(1, idx.size // 200000)]
+    truth = wl.field_value(prob.truth, prob.eval_x[sub])
+    rmse = float(np.sqrt(np.mean((u - truth) ** 2)))
+    dsub = prep.dist.cpu().numpy()[sub]
+    rmse_far = {f"d>={t}": float(np.sqrt(np.mean((u[dsub >= t] - truth[dsub >= t]) ** 2)))
+                for t in (0.05, 0.2) if (dsub >= t).any()}
+    rms_truth = float(np.sqrt(np.mean(truth**2)))
+    steps = int(sol.counters[1])
+    pairs = prep.n_int * sol.cache.n
+    out = {"workload": prob.name, "dtype": "f32", "ms_per_step": ms,
+           "points_per_s": (prep.n_int + prep.n_band) / (ms / 1e3),
+           "interior_points": prep.n_int, "band_points": prep.n_band, "box_candidates": n_box,
+           "slice_points": prob.extra["n_slice"], "cache_points": sol.cache.n, "walks_per_point": prob.n_walks,
+           "walks": int(sol.counters[3]), "walk_steps": steps,
+           "cache_walk_steps_per_s": steps / (stages["cache_walks"] / 1e3),
+           "gather_pairs_per_s": pairs / (stages["gather"] / 1e3),
+           "gather_tflops_u": pairs * FLOPS_3D_BOUNDARY_U / (stages["gather"] / 1e3) / 1e12,
+           "stage_ms": stages, "rmse_u_sampled": rmse, "rmse_u_far": rmse_far, "rms_u_true": rms_truth,
+           "capped_walks": int(sol.counters[2])}
+    print(json.dumps(out))
+
+
+def c4a(args):
+    prob, prep = _c3_setup()
+    sc = prep.sc
+    cache = pl.sample_cache(sc, prep.n_cand, prob.offset, prob.sides, prob.seed_cache, 0)
+    W = prob.n_walks
+    params = pl.walk_params(prob.eps, W, prob.seed_walks, prep.g, None, "f32")
+    U, D, rec, counters = pl.cache_walks(sc, cache, params, "f32")
+    nb = 81
+    basis = pl.DeviceField(wl.solid_harmonics_3d(np.zeros(nb), 8))
+    n = cache.n
+    E = torch.empty(n, nb, dtype=torch.float64, device="cuda")
+    F = torch.empty_like(E)
+    t_basis = _time(lambda: B.bvc_basis_means(basis.c(), 3, n, W, B.F32, rec["exit"], rec["w1"], cache.xbar, 1,
+                                              E, F))
+    coefs = wl.c4_fields(64)
+    coef_d = torch.from_numpy(np.ascontiguousarray(coefs)).cuda()
+    nf = coefs.shape[0]
+    A = torch.empty(n, nf, dtype=torch.float32, device="cuda")
+    Bm = torch.empty_like(A)
+    t_fields = _time(lambda: B.bvc_eval_fields(n, nb, nf, E, F, cache.w, coef_d, B.F32, A, Bm))
+    cx = pl.take(cache.x, None, n, 3, n, torch.float32)
+    cn = pl.take(cache.nrm, None, n, 3, n, torch.float32)
+    K = prep.n_int
+    xs = prep.x_int
+    res = {}
+    for name, prec in (("split_bf16", B.SPLIT_BF16), ("fp32", B.F32)):
+        Uo = torch.empty(K, nf, dtype=torch.float32, device="cuda")
+        nbytes = B.bvc_gather_multi_workspace_bytes(n, prec)
+        ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device="cuda")
+        fn = lambda: B.bvc_gather_multi(3, n, cx, cn, nf, A, Bm, K, xs, Uo, prec, ws)
+        fn()
+        torch.cuda.synchronize()
+        res[name] = (_time(fn), Uo)
+        _log(f"c4a {name} {res[name][0]:.2f} ms")
+    # one plain FP32 gather of field 0, times 64 fields
+    a0 = A[:, 0].contiguous()
+    b0 = Bm[:, 0].contiguous()
+    u0 = torch.empty(K, dtype=torch.float32, device="cuda")
+    cview = dict(n=n, dtype=B.F32, x=cx, nrm=cn, a=a0, b=b0)
+    t_plain = _time(lambda: B.bvc_gather_u(3, cview, None, K, xs, u0))
+    # error against the closed forms on a subset of points and fields
+    idx = prep.idx_int[:K].cpu().numpy()
+    rng = np.random.default_rng(1)
+    sub = np.sort(rng.choice(K, size=min(20000, K), replace=False))
+    pts = prob.eval_x[idx[sub]]
+    Ybasis = wl.real_sph_harm(8, pts)
+    ls = np.array([l for l in range(9) for _ in range(2 * l + 1)])
+    R = np.linalg.norm(pts, axis=1)
+    basis_vals = Ybasis * R[:, None] ** ls[None, :]
+    truth = basis_vals @ coefs.T  # (sub, nf)
+    errs = {}
+    for name in res:
+        Ug = res[name][1].double().cpu().numpy()[sub]
+        errs[name] = float(np.sqrt(np.mean((Ug - truth) ** 2)))
+    diff = float((res["split_bf16"][1] - res["fp32"][1]).abs().max())
+    pairs = K * n
+    mfma_flops = 3 * 2 * K * (2 * n) * nf
+    t_bf16 = res["split_bf16"][0]
+    out = {"workload": "c4a_dispsphere_64fields", "fields": nf, "eval_points": K, "cache_points": n,
+           "split_bf16_ms": t_bf16, "fp32_multi_ms": res["fp32"][0], "plain_fp32_x64_ms": 64 * t_plain,
+           "plain_fp32_one_field_ms": t_plain,
+           "field_points_per_s": {"split_bf16": K * nf / (t_bf16 / 1e3),
+                                  "fp32_multi": K * nf / (res["fp32"][0] / 1e3),
+                                  "plain_fp32": K * nf / (64 * t_plain / 1e3)},
+           "mfma_tflops": mfma_flops / (t_bf16 / 1e3) / 1e12, "mfma_peak_bf16_tflops": 2500.0,
+           "mfma_frac": mfma_flops / (t_bf16 / 1e3) / 1e12 / 2500.0,
+           "generation_pairs_per_s": pairs / (t_bf16 / 1e3),
+           "rmse_vs_closed_form": errs, "max_abs_split_minus_fp32": diff,
+           "basis_means_ms": t_basis, "eval_fields_ms": t_fields, "walks": int(counters[3])}
+    print(json.dumps(out))
+
+
+def c4b(args):
+    scenes = wl.c4_scenes(32)
+    probs = []
+    for s, (sc, nc, ne) in enumerate(scenes):
+        eps = 1e-3 * sc.diagonal
+        lo, hi = sc.bbox
+        pts = wl.uniform_box(ne, lo, hi, wl.seed(4, 5) * 100 + s)
+        g = wl.harmonic_2d(3, 1.0, 1.0)
+        probs.append(wl.Problem(f"c4b_{s}", sc, g, wl.Field(), nc, 64, eps, 5 * eps, 0, pts, g, sides=2,
+                                seed_walks=wl.seed(4, 4) * 100 + s, seed_cache=wl.seed(4, 3) * 100 + s))
+    t = time.time()
+    batch = pl.SceneBatch(probs)
+    torch.cuda.synchronize()
+    _log(f"c4b setup {time.time() - t:.1f}s")
+    batch.launch()
+    torch.cuda.synchronize()
+    t_eager = _time(batch.launch, max(1, args.steps))
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        batch.launch()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        batch.launch()
+    g.replay()
+    torch.cuda.synchronize()
+    t_graph = _time(g.replay, max(1, args.steps))
+    batch.run_sequential()
+    torch.cuda.synchronize()
+    t_seq = _time(batch.run_sequential, max(1, args.steps))
+    n_pts = sum(e["n_int"] for e in batch.entries)
+    n_cache = sum(e["cache"].n for e in batch.entries)
+    pairs = sum(e["n_int"] * e["cache"].n for e in batch.entries)
+    c = batch.counters()
+    out = {"workload": "c4b_32_uneven_stars", "scenes": len(probs), "eval_points": n_pts, "cache_points": n_cache,
+           "walks": int(c[3]), "gather_pairs": pairs, "graph_ms": t_graph, "eager_batch_ms": t_eager,
+           "sequential_ms": t_seq, "points_per_s_graph": n_pts / (t_graph / 1e3),
+           "points_per_s_sequential": n_pts / (t_seq / 1e3), "speedup_vs_sequential": t_seq / t_graph,
+           "cache_sizes": [e["cache"].n for e in batch.entries], "eval_sizes": [e["n_int"] for e in batch.entries]}
+    print(json.dumps(out))
