@@ -50,7 +50,12 @@ struct Uniform<float> {
   }
 };
 
-__device__ __forceinline__ void sincos_turns(float t, float* s, float* c) { sincospif(2.0f * t, s, c); }
+// Angles in turns.  FP32 uses the hardware sine and cosine, which take their
+// argument in turns (valid for |t| <= 256; t is a uniform in [0, 1) here).
+__device__ __forceinline__ void sincos_turns(float t, float* s, float* c) {
+  *s = __builtin_amdgcn_sinf(t);
+  *c = __builtin_amdgcn_cosf(t);
+}
 __device__ __forceinline__ void sincos_turns(double t, double* s, double* c) { sincospi(2.0 * t, s, c); }
 
 // FP32 helpers use the hardware square root and reciprocal (1 ulp), not the

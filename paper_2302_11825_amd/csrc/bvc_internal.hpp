@@ -144,6 +144,9 @@ int check_hip(hipError_t e, const char* what);
 int check_scene(bvc_scene s);
 int check_field(const bvc_field& f, int dim, const char* name);
 int num_cus();
+// Zero `bytes` (a multiple of 4) of device memory with a kernel rather than a
+// memset node, so the call stays correct inside a captured HIP graph.
+int zero_async(void* p, size_t bytes, hipStream_t st);
 
 }  // namespace bvc
 

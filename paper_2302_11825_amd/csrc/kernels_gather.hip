@@ -628,10 +628,11 @@ int bvc_gather_backward(int32_t dim, const bvc_cache_view* cache, const bvc_sour
   // with no evaluation points every adjoint is zero
   if (n_eval == 0) {
     const size_t es = cache->dtype == BVC_F32 ? 4 : 8;
-    if (dL_da && cache->n) (void)hipMemsetAsync(dL_da, 0, cache->n * es, st);
-    if (dL_db && cache->n) (void)hipMemsetAsync(dL_db, 0, cache->n * es, st);
-    if (dL_ds && sources && sources->n) (void)hipMemsetAsync(dL_ds, 0, sources->n * es, st);
-    return check_hip(hipGetLastError(), "gather backward");
+    int rc = BVC_OK;
+    if (dL_da && cache->n) rc = zero_async(dL_da, cache->n * es, st);
+    if (!rc && dL_db && cache->n) rc = zero_async(dL_db, cache->n * es, st);
+    if (!rc && dL_ds && sources && sources->n) rc = zero_async(dL_ds, sources->n * es, st);
+    return rc;
   }
   if (cache->dtype == BVC_F32)
     return backward_impl<float>(dim, cache, sources, n_eval, eval_x, dL_du, dL_da, dL_db, dL_ds, dL_dx, st);
@@ -686,7 +687,7 @@ int bvc_cache_backward(int64_t n_cache, int32_t nb, const double* E, const doubl
   if (n_cache < 0 || nb < 1) return fail(BVC_EINVAL, "bad sizes");
   if (!dL_dtheta) return fail(BVC_EINVAL, "dL_dtheta is null");
   hipStream_t st = (hipStream_t)stream;
-  if (n_cache == 0) return check_hip(hipMemsetAsync(dL_dtheta, 0, nb * sizeof(double), st), "zero");
+  if (n_cache == 0) return zero_async(dL_dtheta, nb * sizeof(double), st);
   if (!E || !F || !w || !dL_da || !dL_db || !scratch) return fail(BVC_EINVAL, "null argument");
   const int64_t chunks = (n_cache + kChunk - 1) / kChunk;
   hipLaunchKernelGGL(k_cache_back_partial, dim3((nb + 63) / 64, (unsigned)chunks), dim3(64), 0, st, n_cache, nb, E, F,

@@ -43,6 +43,21 @@ int num_cus() {
 }
 
 namespace {
+__global__ void k_zero_words(uint32_t* p, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0u;
+}
+}  // namespace
+
+int zero_async(void* p, size_t bytes, hipStream_t st) {
+  if (bytes == 0) return BVC_OK;
+  if (!p || bytes % 4) return fail(BVC_EINVAL, "zero_async needs a non-null pointer and a multiple of 4 bytes");
+  const size_t n = bytes / 4;
+  const int blocks = (int)std::min<size_t>((n + kBlock - 1) / kBlock, 4096);
+  hipLaunchKernelGGL(k_zero_words, dim3(blocks), dim3(kBlock), 0, st, (uint32_t*)p, n);
+  return check_hip(hipGetLastError(), "zero launch");
+}
+
+namespace {
 
 // ---------------------------------------------------------------------------
 // Cache sampling

@@ -57,6 +57,7 @@ struct Builder {
   const std::vector<double>& cen;
   std::vector<int>& perm;
   std::vector<TmpNode> nodes;
+  int leaf_max;
 
   // Half perimeter (2D) or half surface area (3D) of a box.
   double box_cost(const double* lo, const double* hi) const {
@@ -149,7 +150,7 @@ struct Builder {
       }
     }
     nd.depth = depth;
-    if (count <= kLeafMax) {
+    if (count <= leaf_max) {
       nd.leaf = true;
       nd.start = start;
       nd.count = count;
@@ -281,7 +282,12 @@ static int build_scene(SceneHost& S, int dim, const double* verts, int64_t nv, c
     }
   std::vector<int> perm(np);
   std::iota(perm.begin(), perm.end(), 0);
-  Builder B{dim, plo, phi, cen, perm, {}};
+  // One primitive per leaf while the node indices fit: a node expansion then
+  // tests at most two primitives, which keeps the 64 lanes of a wave doing
+  // the same amount of work per traversal step.  Larger scenes use leaves of
+  // up to kLeafMax primitives.
+  const int leaf_max = np < (1 << 17) ? 1 : kLeafMax;
+  Builder B{dim, plo, phi, cen, perm, {}, leaf_max};
   B.nodes.reserve(2 * np + 2);
   int root = B.build(0, (int)np, 1);
   std::vector<TmpNode>& T = B.nodes;

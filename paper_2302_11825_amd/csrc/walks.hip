@@ -22,6 +22,10 @@ namespace bvc {
 namespace {
 
 constexpr int kBlock = 256;
+// Walk ids a wave claims from the global queue at a time: one atomic per
+// chunk rather than one per refill keeps the queue counter, which every XCD
+// shares, off the critical path.
+constexpr int kChunk = 256;
 
 struct WalkArgs {
   SceneDev S;
@@ -47,11 +51,18 @@ struct WalkArgs {
 };
 
 // In-walk source term in the walk's precision (constants and Gaussian sums).
+// `scale` is 1/(2 sigma^2), times log2(e) in FP32, where the Gaussian factor
+// is taken as a power of two on the hardware exp2.
+template <typename T>
+__device__ __forceinline__ T source_scale(const FieldDev& F) {
+  const double inv = 1.0 / (2.0 * F.param[0] * F.param[0]);
+  return sizeof(T) == 4 ? (T)(inv * 1.4426950408889634) : (T)inv;
+}
+
 template <typename T, int D>
-__device__ __forceinline__ T walk_source(const FieldDev& F, const T* y) {
+__device__ __forceinline__ T walk_source(const FieldDev& F, T scale, const T* y) {
   if (F.kind == 1) return (T)F.param[0];
   const int ng = F.n_coef / (1 + D);
-  const T inv = T(1) / (T(2) * (T)F.param[0] * (T)F.param[0]);
   T sum = T(0);
   for (int k = 0; k < ng; ++k) {
     const double* c = F.coef + k * (1 + D);
@@ -61,7 +72,8 @@ __device__ __forceinline__ T walk_source(const FieldDev& F, const T* y) {
       const T e = y[a] - (T)c[1 + a];
       r2 = fma(e, e, r2);
     }
-    sum = fma((T)c[0], exp(-r2 * inv), sum);
+    if constexpr (sizeof(T) == 4) sum = fmaf((float)c[0], __builtin_amdgcn_exp2f(-r2 * scale), sum);
+    else sum = fma(c[0], exp(-r2 * scale), sum);
   }
   return sum;
 }
@@ -70,10 +82,16 @@ __device__ __forceinline__ T walk_source(const FieldDev& F, const T* y) {
 // length by orders of magnitude (a point near a curved boundary touches few
 // nodes, one deep inside a near-spherical domain touches hundreds), so the
 // query is resumable: each iteration expands one BVH node for every lane whose
-// query is open, and the jump of the lanes whose query closed runs only once
-// at most kOpenLanes lanes of the wave are still querying.  A long query no
-// longer holds the other 63 lanes back.
-constexpr int kOpenLanes = 8;
+// query is open, and the jump of the lanes whose query closed runs once at most
+// OpenLanes lanes of the wave are still querying, so that a long query does not
+// hold the other lanes back.  Measured on MI355X: 3D triangle meshes run best
+// with the jump phase entered at 32 open lanes (about 1.7x faster than waiting
+// for all 64); 2D polylines, whose queries are short and even, run best when
+// the wave finishes every query first.
+template <int D>
+struct OpenLanes {
+  static constexpr int value = D == 3 ? 32 : 0;
+};
 
 template <typename T, int D, bool SRC, int MODE>
 __global__ __launch_bounds__(kBlock) void k_walks(WalkArgs a) {
@@ -83,17 +101,26 @@ __global__ __launch_bounds__(kBlock) void k_walks(WalkArgs a) {
   const int lane = threadIdx.x & 63;
   const uint32_t tag = MODE == 0 ? 1u : 2u;
   const T eps = (T)a.eps;
+  const T src_scale = SRC && a.f.kind == 3 ? source_scale<T>(a.f) : T(0);
   const SceneDev& S = a.S;
   T* U = (T*)a.U;
   T* Dof = (T*)a.Dof;
   T* EX = (T*)a.exit;
   T* W1 = (T*)a.w1;
 
-  bool active = false, exhausted = false;
+  // Lane state.  A walk is active from its start to its exit; `jump` marks a
+  // lane whose next action is a sphere jump from p with radius d (the first
+  // ball, k = 0, is centred at the start point with radius R0, so it runs the
+  // same jump code as every later ball).
+  bool active = false, jump = false, exhausted = false;
+  // walk ids [pool_next, pool_end) are claimed by this wave; last_chunk once
+  // the global queue has handed out its final chunk
+  unsigned long long pool_next = 0, pool_end = 0;
+  bool last_chunk = false;
   uint32_t id = 0;
   int k = 0;
   T p[D];
-  T acc_s = T(0), usrc = T(0);
+  T d = T(0), acc_s = T(0), usrc = T(0);
   Query<T, D> qs;
   qs.node = -1;
   unsigned long long steps_acc = 0, capped_acc = 0, walks_acc = 0;
@@ -101,19 +128,37 @@ __global__ __launch_bounds__(kBlock) void k_walks(WalkArgs a) {
   for (int q = 0; q < D; ++q) p[q] = T(0);
 
   while (true) {
-    // ---- refill idle lanes with new walks (their first ball starts a query)
+    // ---- refill idle lanes with new walks from the wave's chunk of ids
     if (!exhausted) {
       const uint64_t need = __ballot(!active);
       if (need) {
-        const int leader = __ffsll((unsigned long long)need) - 1;
-        const int cnt = __popcll(need);
-        unsigned long long base = 0;
-        if (lane == leader) base = atomicAdd(&a.counters[0], (unsigned long long)cnt);
-        base = __shfl(base, leader);
-        if (base + cnt >= a.total) exhausted = true;
+        const unsigned long long cnt = (unsigned long long)__popcll(need);
+        const unsigned long long rank = (unsigned long long)__popcll(need & ((1ull << lane) - 1));
+        const unsigned long long avail = pool_end - pool_next;
+        unsigned long long lo = 0, hi = 0;
+        if (avail < cnt && !last_chunk) {
+          const int leader = __ffsll((unsigned long long)need) - 1;
+          unsigned long long c = 0;
+          if (lane == leader) c = atomicAdd(&a.counters[0], (unsigned long long)kChunk);
+          c = __shfl(c, leader);
+          lo = c;
+          hi = c >= a.total ? c : std::min<unsigned long long>(c + kChunk, a.total);
+          last_chunk = c + kChunk >= a.total;
+        }
+        const unsigned long long used_old = std::min(cnt, avail);
+        const unsigned long long used_new = std::min(cnt - used_old, hi - lo);
+        unsigned long long my = ~0ull;
+        if (rank < avail) my = pool_next + rank;
+        else if (rank - avail < hi - lo) my = lo + (rank - avail);
+        if (hi > lo) {
+          pool_next = lo + used_new;
+          pool_end = hi;
+        } else {
+          pool_next += used_old;
+        }
+        if (last_chunk && pool_next >= pool_end) exhausted = true;
         if (!active) {
-          const unsigned long long my = base + __popcll(need & ((1ull << lane) - 1));
-          if (my < a.total) {
+          if (my != ~0ull) {
             id = (uint32_t)my;
             const int64_t i = (int64_t)(id / (uint32_t)a.W);
             const T R0 = (T)a.R0[i];
@@ -133,63 +178,80 @@ __global__ __launch_bounds__(kBlock) void k_walks(WalkArgs a) {
               if (a.steps) a.steps[id] = 0;
               ++walks_acc;
             } else {
-              T x0[D], nu0[D];
 #pragma unroll
               for (int q = 0; q < D; ++q)
-                x0[q] = MODE == 0 ? (T)a.x[q * a.n_pts + i] : ((const T*)a.px)[q * a.n_pts + i];
-              walk_direction<T, D>(a.seed, 0, id, a.batch, tag, nu0);
-              T dn = T(0);
-#pragma unroll
-              for (int q = 0; q < D; ++q) {
-                p[q] = fma(R0, nu0[q], x0[q]);
-                if constexpr (MODE == 0) dn = fma(nu0[q], (T)a.nrm[q * a.n_pts + i], dn);
-              }
-              const T wgt = (T)D / R0;
-              usrc = T(0);
-              T gs[D];
-#pragma unroll
-              for (int q = 0; q < D; ++q) gs[q] = T(0);
-              if constexpr (SRC) {
-                T yu[D];
-                ball_source_point<T, D>(a.seed, 0, id, a.batch, tag, x0, R0, yu);
-                usrc = -R0 * R0 / (T)(2 * D) * walk_source<T, D>(a.f, yu);
-                if constexpr (D == 2) {
-                  // gradient source sample, radius density (3/2)(1 - s^2)
-                  T u1, u2, u3, u4;
-                  Uniform<T>::pair(a.seed, 2, id, a.batch, tag, u1, u2);
-                  Uniform<T>::pair(a.seed, 3, id, a.batch, tag, u3, u4);
-                  const T sg = T(2) * sin(asin(u2) / T(3));
-                  T sn, cs;
-                  sincos_turns(u3, &sn, &cs);
-                  const T yg[2] = {fma(R0 * sg, cs, x0[0]), fma(R0 * sg, sn, x0[1])};
-                  const T c = -T(2) * R0 / T(3) * walk_source<T, D>(a.f, yg);
-                  gs[0] = c * cs;
-                  gs[1] = c * sn;
-                }
-              }
-              if constexpr (MODE == 0) {
-                const T w1 = wgt * dn;
-                T ds = T(0);
-#pragma unroll
-                for (int q = 0; q < D; ++q) ds = fma(gs[q], (T)a.nrm[q * a.n_pts + i], ds);
-                W1[id] = w1;
-                Dof[id] = ds - w1 * usrc;
-              } else if (Dof) {
-#pragma unroll
-                for (int q = 0; q < D; ++q) {
-                  const T gw = wgt * nu0[q];
-                  W1[(size_t)q * a.total + id] = gw;
-                  Dof[(size_t)q * a.total + id] = gs[q] - gw * usrc;
-                }
-              }
+                p[q] = MODE == 0 ? (T)a.x[q * a.n_pts + i] : ((const T*)a.px)[q * a.n_pts + i];
+              d = R0;
+              k = 0;
               acc_s = T(0);
-              k = 1;
-              query_begin<T, D>(S, p, -1, qs);
+              usrc = T(0);
               active = true;
+              jump = true;
             }
           }
         }
       }
+    }
+    // ---- sphere jump: source sample in the ball, direction, next query
+    if (jump) {
+      T srcv = T(0);
+      const T coef = -d * d / (T)(2 * D);
+      if constexpr (SRC) {
+        T y[D];
+        ball_source_point<T, D>(a.seed, (uint32_t)k, id, a.batch, tag, p, d, y);
+        srcv = walk_source<T, D>(a.f, src_scale, y);
+      }
+      T nu[D];
+      walk_direction<T, D>(a.seed, (uint32_t)k, id, a.batch, tag, nu);
+      if (k == 0) {
+        // first ball: its source term and the weights of the gradient and
+        // normal-derivative estimators (Eq. 7 with the control variate)
+        usrc = SRC ? coef * srcv : T(0);
+        const int64_t i = (int64_t)(id / (uint32_t)a.W);
+        const T wgt = (T)D / d;
+        T gs[D];
+#pragma unroll
+        for (int q = 0; q < D; ++q) gs[q] = T(0);
+        if constexpr (SRC && D == 2) {
+          // gradient source sample, radius density (3/2)(1 - s^2)
+          T u1, u2, u3, u4;
+          Uniform<T>::pair(a.seed, 2, id, a.batch, tag, u1, u2);
+          Uniform<T>::pair(a.seed, 3, id, a.batch, tag, u3, u4);
+          const T sg = T(2) * sin(asin(u2) / T(3));
+          T sn, cs;
+          sincos_turns(u3, &sn, &cs);
+          const T yg[2] = {fma(d * sg, cs, p[0]), fma(d * sg, sn, p[1])};
+          const T c = -T(2) * d / T(3) * walk_source<T, D>(a.f, src_scale, yg);
+          gs[0] = c * cs;
+          gs[1] = c * sn;
+        }
+        if constexpr (MODE == 0) {
+          T dn = T(0), ds = T(0);
+#pragma unroll
+          for (int q = 0; q < D; ++q) {
+            const T nq = (T)a.nrm[q * a.n_pts + i];
+            dn = fma(nu[q], nq, dn);
+            ds = fma(gs[q], nq, ds);
+          }
+          const T w1 = wgt * dn;
+          W1[id] = w1;
+          Dof[id] = ds - w1 * usrc;
+        } else if (Dof) {
+#pragma unroll
+          for (int q = 0; q < D; ++q) {
+            const T gw = wgt * nu[q];
+            W1[(size_t)q * a.total + id] = gw;
+            Dof[(size_t)q * a.total + id] = gs[q] - gw * usrc;
+          }
+        }
+      } else if constexpr (SRC) {
+        acc_s = fma(coef, srcv, acc_s);
+      }
+#pragma unroll
+      for (int c = 0; c < D; ++c) p[c] = fma(d, nu[c], p[c]);
+      query_begin<T, D>(S, p, k == 0 ? -1 : qs.bi, qs);
+      ++k;
+      jump = false;
     }
     if (!__any(active)) {
       if (exhausted) break;
@@ -199,11 +261,11 @@ __global__ __launch_bounds__(kBlock) void k_walks(WalkArgs a) {
     while (true) {
       const bool open = active && qs.node >= 0;
       if (open) query_step<T, D>(S, p, qs, stk, stride);
-      if (__popcll(__ballot(active && qs.node >= 0)) <= kOpenLanes) break;
+      if (__popcll(__ballot(active && qs.node >= 0)) <= OpenLanes<D>::value) break;
     }
-    // ---- lanes whose query closed: stop in the shell, or jump
-    if (active && qs.node < 0) {
-      const T d = fsqrt(qs.best);
+    // ---- lanes whose query closed: stop in the shell, or jump next
+    if (active && !jump && qs.node < 0) {
+      d = fsqrt(qs.best);
       const bool stop = d < eps;
       const bool cap = !stop && k >= a.max_steps;
       if (stop || cap) {
@@ -216,17 +278,7 @@ __global__ __launch_bounds__(kBlock) void k_walks(WalkArgs a) {
         ++walks_acc;
         active = false;
       } else {
-        if constexpr (SRC) {
-          T y[D];
-          ball_source_point<T, D>(a.seed, (uint32_t)k, id, a.batch, tag, p, d, y);
-          acc_s = fma(-d * d / (T)(2 * D), walk_source<T, D>(a.f, y), acc_s);
-        }
-        T nu[D];
-        walk_direction<T, D>(a.seed, (uint32_t)k, id, a.batch, tag, nu);
-#pragma unroll
-        for (int c = 0; c < D; ++c) p[c] = fma(d, nu[c], p[c]);
-        ++k;
-        query_begin<T, D>(S, p, qs.bi, qs);
+        jump = true;
       }
     }
   }
@@ -245,31 +297,32 @@ __global__ __launch_bounds__(kBlock) void k_walks(WalkArgs a) {
 // Boundary data at the exit points, in FP64.  With W = g(exit) + S:
 // U = W + u_src,  mode 0: D = w1 (W - c) + d_src,  mode 1: grad = gw (W - c) + g_src,
 // where c = g(xbar) is the control variate (0 when disabled).
-// Each thread finishes kFinishRun consecutive walks, so the control variate of
-// a start point is evaluated once per run rather than once per walk.
+// A wave finishes kFinishRun runs of 64 consecutive walks, lane l taking walk
+// l of each run, so that every load and store is coalesced; a lane evaluates
+// the control variate only when its start point changes.
 constexpr int kFinishRun = 8;
 
 template <typename T, int D, int MODE>
 __global__ __launch_bounds__(kBlock) void k_finish(FieldDev g, int cv, uint64_t total, int W, int64_t n_pts,
                                                     const double* xbar, const T* EX, T* U, T* Dof, const T* W1) {
-  const uint64_t id0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * kFinishRun;
-  if (id0 >= total) return;
+  const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint64_t id0 = wave * (64 * kFinishRun) + (threadIdx.x & 63);
   int64_t i_cv = -1;
   double c = 0.0;
   for (int r = 0; r < kFinishRun; ++r) {
-    const uint64_t id = id0 + r;
+    const uint64_t id = id0 + (uint64_t)r * 64;
     if (id >= total) break;
     const int64_t i = (int64_t)(id / (uint64_t)W);
     if (cv && i != i_cv) {
       double xb[D];
 #pragma unroll
-      for (int a = 0; a < D; ++a) xb[a] = xbar[a * n_pts + i];
+      for (int q = 0; q < D; ++q) xb[q] = xbar[q * n_pts + i];
       c = field_value(g, D, xb);
       i_cv = i;
     }
     double q[D];
 #pragma unroll
-    for (int a = 0; a < D; ++a) q[a] = (double)EX[(size_t)a * total + id];
+    for (int e = 0; e < D; ++e) q[e] = (double)EX[(size_t)e * total + id];
     const double gq = field_value(g, D, q);
     const double su = (double)U[id];
     U[id] = (T)(gq + su);
@@ -277,9 +330,9 @@ __global__ __launch_bounds__(kBlock) void k_finish(FieldDev g, int cv, uint64_t 
       Dof[id] = (T)((double)W1[id] * (gq + su - c) + (double)Dof[id]);
     } else if (Dof) {
 #pragma unroll
-      for (int a = 0; a < D; ++a)
-        Dof[(size_t)a * total + id] =
-            (T)((double)W1[(size_t)a * total + id] * (gq + su - c) + (double)Dof[(size_t)a * total + id]);
+      for (int e = 0; e < D; ++e)
+        Dof[(size_t)e * total + id] =
+            (T)((double)W1[(size_t)e * total + id] * (gq + su - c) + (double)Dof[(size_t)e * total + id]);
     }
   }
 }
@@ -359,8 +412,8 @@ void launch_walks(const WalkArgs& args, int mode, bool src, int blocks, size_t l
 
 template <typename T, int D>
 void launch_finish(const bvc_walk_params* p, int mode, const WalkArgs& a, hipStream_t st) {
-  const uint64_t threads = (a.total + kFinishRun - 1) / kFinishRun;
-  const int blocks = (int)((threads + kBlock - 1) / kBlock);
+  const uint64_t waves = (a.total + 64 * kFinishRun - 1) / (64 * kFinishRun);
+  const int blocks = (int)((waves * 64 + kBlock - 1) / kBlock);
   FieldDev g = to_dev(p->g);
   if (mode == 0)
     hipLaunchKernelGGL((k_finish<T, D, 0>), dim3(blocks), dim3(kBlock), 0, st, g, p->control_variate, a.total,
@@ -384,7 +437,7 @@ int run_walks(bvc_scene s, const bvc_walk_params* p, int mode, int64_t n, WalkAr
   a.batch = p->batch;
   a.total = total;
   a.n_pts = n;
-  int rc = check_hip(hipMemsetAsync(a.counters, 0, 4 * sizeof(unsigned long long), st), "counter reset");
+  int rc = zero_async(a.counters, 4 * sizeof(unsigned long long), st);
   if (rc || total == 0) return rc;
   int blocks = p->blocks > 0 ? p->blocks : num_cus() * 8;
   const int64_t needed = (int64_t)((total + kBlock - 1) / kBlock);
@@ -444,7 +497,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_walks(BatchDev b) {
   uint32_t id = 0;
   int k = 0, hint = -1, sc = 0;
   float p[D];
-  float acc_s = 0.f, usrc = 0.f, eps = 0.f;
+  float acc_s = 0.f, usrc = 0.f, eps = 0.f, sscale = 0.f;
   unsigned long long steps_acc = 0, capped_acc = 0, walks_acc = 0;
 #pragma unroll
   for (int q = 0; q < D; ++q) p[q] = 0.f;
@@ -466,6 +519,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_walks(BatchDev b) {
             const BatchSceneDev& s = b.scenes[sc];
             id = (uint32_t)(gid - s.walk_off);
             eps = (float)s.eps;
+            sscale = SRC && s.f.kind == 3 ? source_scale<float>(s.f) : 0.f;
             const int64_t i = (int64_t)(id / (uint32_t)s.W);
             const float R0 = (float)s.R0[i];
             float x0[D], nu0[D];
@@ -484,7 +538,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_walks(BatchDev b) {
             if constexpr (SRC) {
               float yu[D];
               ball_source_point<float, D>(s.seed, 0, id, s.batch, 1u, x0, R0, yu);
-              usrc = -R0 * R0 / (float)(2 * D) * walk_source<float, D>(s.f, yu);
+              usrc = -R0 * R0 / (float)(2 * D) * walk_source<float, D>(s.f, sscale, yu);
               if constexpr (D == 2) {
                 float u1, u2, u3, u4;
                 Uniform<float>::pair(s.seed, 2, id, s.batch, 1u, u1, u2);
@@ -493,7 +547,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_walks(BatchDev b) {
                 float sn, cs;
                 sincos_turns(u3, &sn, &cs);
                 const float yg[2] = {fmaf(R0 * sg, cs, x0[0]), fmaf(R0 * sg, sn, x0[1])};
-                const float c = -2.f * R0 / 3.f * walk_source<float, D>(s.f, yg);
+                const float c = -2.f * R0 / 3.f * walk_source<float, D>(s.f, sscale, yg);
                 ds = c * (cs * (float)s.nrm[i] + sn * (float)s.nrm[s.n_cache + i]);
               }
             }
@@ -529,7 +583,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_walks(BatchDev b) {
         if constexpr (SRC) {
           float y[D];
           ball_source_point<float, D>(s.seed, (uint32_t)k, id, s.batch, 1u, p, d, y);
-          acc_s = fmaf(-d * d / (float)(2 * D), walk_source<float, D>(s.f, y), acc_s);
+          acc_s = fmaf(-d * d / (float)(2 * D), walk_source<float, D>(s.f, sscale, y), acc_s);
         }
         float nu[D];
         walk_direction<float, D>(s.seed, (uint32_t)k, id, s.batch, 1u, nu);
