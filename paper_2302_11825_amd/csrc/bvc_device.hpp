@@ -412,23 +412,34 @@ __device__ __forceinline__ void bvh_closest(const SceneDev& S, const T* p, T& be
   }
 }
 
-// Resumable form of the same nearest-first query: query_begin seeds it (with
-// the hint primitive as the initial candidate) and each query_step expands one
-// node, so a wave can interleave queries of different lengths.  node < 0
-// marks a finished query; best/bi/bq then hold the result.
+// Resumable form of the same nearest-first query, for wave-interleaved
+// traversal.  A step tests at most one primitive and expands at most one node,
+// so every lane of a wave runs the same instructions per step whatever mix of
+// nodes and leaves its query meets.  Leaves reached by an expansion wait in
+// two pending slots (leaf encodings, 0 = empty) and are consumed one primitive
+// per step; a node is expanded only when no leaf is pending, so the slots
+// never overflow.  The query is finished when no node and no leaf remain.
 template <typename T, int D>
 struct Query {
-  int node;
+  int node;   // next internal node to expand, -1 when the stack is empty
   int sp;
   int bi;
+  int pa, pb; // pending leaves (pa first)
   T best;
   T bq[D];
 };
 
 template <typename T, int D>
+__device__ __forceinline__ bool query_open(const Query<T, D>& q) {
+  return q.node >= 0 || q.pa != 0;
+}
+
+template <typename T, int D>
 __device__ __forceinline__ void query_begin(const SceneDev& S, const T* p, int hint, Query<T, D>& q) {
   q.node = 0;
   q.sp = 0;
+  q.pa = 0;
+  q.pb = 0;
   q.best = T(INFINITY);
   q.bi = -1;
   if (hint >= 0) {
@@ -441,20 +452,24 @@ __device__ __forceinline__ void query_begin(const SceneDev& S, const T* p, int h
 template <typename T, int D>
 __device__ __forceinline__ void query_step(const SceneDev& S, const T* p, Query<T, D>& q, uint32_t* stk,
                                            int stride) {
-  auto consider = [&](int leaf) {
-    const int s0 = leaf_start(leaf), n = leaf_count(leaf);
-    for (int i = s0; i < s0 + n; ++i) {
-      T qq[D];
-      int reg;
-      T d2;
-      if constexpr (D == 3) {
-        T v[9];
-        load_triangle<T>(S, i, v);
-        if (triangle_box_d2<T>(p, v) > q.best) continue;
-        d2 = triangle_d2<T>(p, v, v + 3, v + 6, qq, reg);
-      } else {
-        d2 = prim_d2<T, D>(S, i, p, qq, reg);
-      }
+  // ---- one primitive of the first pending leaf
+  if (q.pa != 0) {
+    const int i = leaf_start(q.pa), n = leaf_count(q.pa);
+    bool test = true;
+    T qq[D];
+    int reg;
+    T d2 = T(INFINITY);
+    if constexpr (D == 3) {
+      T v[9];
+      load_triangle<T>(S, i, v);
+      // a single-primitive leaf already passed its own box; in longer
+      // leaves the triangle's box is a cheap lower bound
+      if (n > 1 && triangle_box_d2<T>(p, v) > q.best) test = false;
+      if (test) d2 = triangle_d2<T>(p, v, v + 3, v + 6, qq, reg);
+    } else {
+      d2 = prim_d2<T, D>(S, i, p, qq, reg);
+    }
+    if (test) {
       bool take = d2 < q.best;
       if (!take && d2 == q.best && i != q.bi) take = q.bi < 0 || S.prim_id[i] < S.prim_id[q.bi];
       if (take) {
@@ -464,7 +479,16 @@ __device__ __forceinline__ void query_step(const SceneDev& S, const T* p, Query<
         for (int a = 0; a < D; ++a) q.bq[a] = qq[a];
       }
     }
-  };
+    if (n > 1) {
+      q.pa = encode_leaf(i + 1, n - 1);
+    } else {
+      q.pa = q.pb;
+      q.pb = 0;
+    }
+  }
+  if (q.pa != 0 || q.node < 0) return;
+  // ---- expand one node: leaves go to the pending slots, the nearer inner
+  // child is expanded next and the farther one is pushed with its bound
   T lo0[D], hi0[D], lo1[D], hi1[D];
   load_child_boxes<T, D>(S, q.node, lo0, hi0, lo1, hi1);
   const int2 ch = S.child[q.node];
@@ -481,12 +505,13 @@ __device__ __forceinline__ void query_step(const SceneDev& S, const T* p, Query<
   }
   int next = -1;
   if (d0 <= q.best) {
-    if (c0 < 0) consider(c0);
+    if (c0 < 0) q.pa = c0;
     else next = c0;
   }
   if (d1 <= q.best) {
     if (c1 < 0) {
-      consider(c1);
+      if (q.pa == 0) q.pa = c1;
+      else q.pb = c1;
     } else if (next < 0) {
       next = c1;
     } else {

@@ -123,6 +123,7 @@ __global__ __launch_bounds__(kBlock) void k_walks(WalkArgs a) {
   T d = T(0), acc_s = T(0), usrc = T(0);
   Query<T, D> qs;
   qs.node = -1;
+  qs.pa = qs.pb = 0;
   unsigned long long steps_acc = 0, capped_acc = 0, walks_acc = 0;
 #pragma unroll
   for (int q = 0; q < D; ++q) p[q] = T(0);
@@ -259,12 +260,11 @@ __global__ __launch_bounds__(kBlock) void k_walks(WalkArgs a) {
     }
     // ---- expand one node per open query until few queries remain open
     while (true) {
-      const bool open = active && qs.node >= 0;
-      if (open) query_step<T, D>(S, p, qs, stk, stride);
-      if (__popcll(__ballot(active && qs.node >= 0)) <= OpenLanes<D>::value) break;
+      if (active && query_open(qs)) query_step<T, D>(S, p, qs, stk, stride);
+      if (__popcll(__ballot(active && query_open(qs))) <= OpenLanes<D>::value) break;
     }
     // ---- lanes whose query closed: stop in the shell, or jump next
-    if (active && !jump && qs.node < 0) {
+    if (active && !jump && !query_open(qs)) {
       d = fsqrt(qs.best);
       const bool stop = d < eps;
       const bool cap = !stop && k >= a.max_steps;
