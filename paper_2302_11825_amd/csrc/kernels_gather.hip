@@ -95,10 +95,13 @@ __device__ __forceinline__ void gather_block(const GatherArgs<T>& a, int64_t blo
   const T inv2pi = (T)(1.0 / (2.0 * kPi)), inv4pi = (T)(1.0 / (4.0 * kPi));
   const T tiny = sizeof(T) == 4 ? (T)1e-18 : (T)1e-200;
 
+  // In 2D the FP32 u accumulators hold twice the potential (the entries carry
+  // the factor 2 that the gradient needs), halved when folded into FP64.
+  constexpr double kUnfold = D == 2 ? 0.5 : 1.0;
   auto fold = [&]() {
 #pragma unroll
     for (int p = 0; p < kPPT; ++p) {
-      tu[p] += (double)au[p];
+      tu[p] += kUnfold * (double)au[p];
       au[p] = T(0);
 #pragma unroll
       for (int c = 0; c < D; ++c) {
@@ -122,12 +125,15 @@ __device__ __forceinline__ void gather_block(const GatherArgs<T>& a, int64_t blo
       const T av = a.ca[i], bv = a.cb[i];
       T* e = ent + tid * 8;
       if constexpr (D == 2) {
+        // twice the potential terms (see kUnfold), the gradient terms as is
         e[0] = y[0];
         e[1] = y[1];
-        e[2] = nn[0] * av * inv2pi;
-        e[3] = nn[1] * av * inv2pi;
-        e[4] = -bv * inv2pi * T(0.5) * log_scale<T>();  // -G b = -(b/4pi) ln r^2
+        e[2] = T(2) * nn[0] * av * inv2pi;
+        e[3] = T(2) * nn[1] * av * inv2pi;
+        e[4] = -bv * inv2pi * log_scale<T>();  // 2 (-G b) = -(b/2pi) ln r^2
         e[5] = bv * inv2pi;
+        e[6] = nn[0] * av * inv2pi;
+        e[7] = nn[1] * av * inv2pi;
       } else {
         e[0] = y[0];
         e[1] = y[1];
@@ -143,19 +149,20 @@ __device__ __forceinline__ void gather_block(const GatherArgs<T>& a, int64_t blo
     for (int j = 0; j < cnt; ++j) {
       const T* e = ent + j * 8;
       if constexpr (D == 2) {
-        const T y0 = e[0], y1 = e[1], n0 = e[2], n1 = e[3], bl = e[4], bg = e[5];
+        const T y0 = e[0], y1 = e[1], m0 = e[2], m1 = e[3], bl = e[4], bg = e[5];
 #pragma unroll
         for (int p = 0; p < kPPT; ++p) {
           const T dx = y0 - x[p][0], dy = y1 - x[p][1];
-          const T r2 = fmax(fma(dx, dx, dy * dy), tiny);
+          // r^2 + tiny keeps coincident points finite at no extra instruction
+          const T r2 = fma(dx, dx, fma(dy, dy, tiny));
           const T ri = recip(r2);
-          const T t = fma(n0, dx, n1 * dy);  // a (n . (y - x)) / (2 pi)
-          const T tr = t * ri;               // a dG/dn
-          au[p] = fma(bl, log_r2(r2), au[p] + tr);
+          const T t2 = fma(m0, dx, m1 * dy);  // 2 a (n . (y - x)) / (2 pi)
+          au[p] = fma(bl, log_r2(r2), fma(t2, ri, au[p]));
           if constexpr (GRAD) {
-            const T q = fma(T(2), tr, bg) * ri;  // (2 a n.(y-x)/r^2 + b)/(2 pi r^2)
-            ag[p][0] = fma(-n0, ri, fma(q, dx, ag[p][0]));
-            ag[p][1] = fma(-n1, ri, fma(q, dy, ag[p][1]));
+            // grad = (q (y - x) - a n / (2 pi)) / r^2,  q = (2 a n.(y-x)/r^2 + b)/(2 pi)
+            const T q = fma(t2, ri, bg);
+            ag[p][0] = fma(ri, fma(q, dx, -e[6]), ag[p][0]);
+            ag[p][1] = fma(ri, fma(q, dy, -e[7]), ag[p][1]);
           }
         }
       } else {
@@ -163,13 +170,14 @@ __device__ __forceinline__ void gather_block(const GatherArgs<T>& a, int64_t blo
 #pragma unroll
         for (int p = 0; p < kPPT; ++p) {
           const T dx = y0 - x[p][0], dy = y1 - x[p][1], dz = y2 - x[p][2];
-          const T r2 = fmax(fma(dx, dx, fma(dy, dy, dz * dz)), tiny);
+          const T r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, tiny)));
           const T ri = rsq(r2);
           const T ri2 = ri * ri;
-          const T ri3 = ri2 * ri;
           const T t = fma(n0, dx, fma(n1, dy, n2 * dz));
-          au[p] = fma(t, ri3, fma(bl, ri, au[p]));
+          // b/r + t/r^3 = (b + t/r^2)/r
+          au[p] = fma(ri, fma(t, ri2, bl), au[p]);
           if constexpr (GRAD) {
+            const T ri3 = ri2 * ri;
             const T q = ri3 * fma(T(3) * t, ri2, bl);
             ag[p][0] = fma(-n0, ri3, fma(q, dx, ag[p][0]));
             ag[p][1] = fma(-n1, ri3, fma(q, dy, ag[p][1]));
@@ -192,8 +200,8 @@ __device__ __forceinline__ void gather_block(const GatherArgs<T>& a, int64_t blo
 #pragma unroll
       for (int c = 0; c < D; ++c) e[c] = a.sy[c * a.n_src + j];
       if constexpr (D == 2) {
-        e[2] = sv * inv2pi * T(0.5) * log_scale<T>();  // G s = (s/4pi) ln r^2
-        e[3] = -sv * inv2pi;                           // dG/dx s = -s (y-x)/(2 pi r^2)
+        e[2] = sv * inv2pi * log_scale<T>();  // 2 G s = (s/2pi) ln r^2
+        e[3] = -sv * inv2pi;                  // dG/dx s = -s (y-x)/(2 pi r^2)
       } else {
         e[3] = -sv * inv4pi;  // G s = -s/(4 pi r); dG/dx s = -s (y-x)/(4 pi r^3)
       }
@@ -207,8 +215,8 @@ __device__ __forceinline__ void gather_block(const GatherArgs<T>& a, int64_t blo
 #pragma unroll
         for (int p = 0; p < kPPT; ++p) {
           const T dx = y0 - x[p][0], dy = y1 - x[p][1];
-          const T r2 = fmax(dx * dx + dy * dy, tiny);
-          au[p] += sl * log_r2(r2);
+          const T r2 = fma(dx, dx, fma(dy, dy, tiny));
+          au[p] = fma(sl, log_r2(r2), au[p]);
           if constexpr (GRAD) {
             const T q = sg * recip(r2);
             ag[p][0] += q * dx;
@@ -220,9 +228,9 @@ __device__ __forceinline__ void gather_block(const GatherArgs<T>& a, int64_t blo
 #pragma unroll
         for (int p = 0; p < kPPT; ++p) {
           const T dx = y0 - x[p][0], dy = y1 - x[p][1], dz = y2 - x[p][2];
-          const T r2 = fmax(dx * dx + dy * dy + dz * dz, tiny);
+          const T r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, tiny)));
           const T ri = rsq(r2);
-          au[p] += sl * ri;
+          au[p] = fma(sl, ri, au[p]);
           if constexpr (GRAD) {
             const T q = sl * ri * ri * ri;
             ag[p][0] += q * dx;
