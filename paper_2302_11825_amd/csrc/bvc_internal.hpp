@@ -131,6 +131,7 @@ struct BatchDev {
   float* a;       // [total_cache]
   float* b;       // [total_cache]
   unsigned long long* counters;  // [4]
+  unsigned long long chunk;      // walk ids per queue claim (set at launch)
 };
 
 // Batch launchers (walks.hip, kernels_gather.hip).

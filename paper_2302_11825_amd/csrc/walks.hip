@@ -22,10 +22,11 @@ namespace bvc {
 namespace {
 
 constexpr int kBlock = 256;
-// Walk ids a wave claims from the global queue at a time: one atomic per
-// chunk rather than one per refill keeps the queue counter, which every XCD
-// shares, off the critical path.
-constexpr int kChunk = 256;
+// Walk ids a wave claims from the global queue at a time (at most): one
+// atomic per chunk rather than one per refill keeps the queue counter, which
+// every XCD shares, off the critical path.  Small launches use smaller chunks
+// so that every wave still gets work.
+constexpr int kChunkMax = 256;
 
 struct WalkArgs {
   SceneDev S;
@@ -48,6 +49,7 @@ struct WalkArgs {
   void* w1;            // mode 0 [total] (dim/R0) nu.n; mode 1 [D][total] (dim/R0) nu
   int* steps;          // [total] or null
   unsigned long long* counters;
+  unsigned long long chunk;  // walk ids per claim, 1..kChunkMax
 };
 
 // In-walk source term in the walk's precision (constants and Gaussian sums).
@@ -76,6 +78,52 @@ __device__ __forceinline__ T walk_source(const FieldDev& F, T scale, const T* y)
     else sum = fma(c[0], exp(-r2 * scale), sum);
   }
   return sum;
+}
+
+// Wave-private pool of walk ids [next, end) claimed from a global queue in
+// chunks.  All lanes of a wave hold the same pool (every update is computed
+// from wave-uniform values), so the pool lives in scalar registers.
+struct IdPool {
+  unsigned long long next = 0, end = 0;
+  bool last = false;  // the queue has handed out its final chunk
+
+  // Gives each lane of `need` the next id (~0 when none is left) and sets
+  // `exhausted` once the pool and the queue are both empty.
+  __device__ unsigned long long take(uint64_t need, int lane, unsigned long long* queue, unsigned long long chunk,
+                                     unsigned long long total, bool& exhausted) {
+    const unsigned long long cnt = (unsigned long long)__popcll(need);
+    const unsigned long long rank = (unsigned long long)__popcll(need & ((1ull << lane) - 1));
+    const unsigned long long avail = end - next;
+    unsigned long long lo = 0, hi = 0;
+    if (avail < cnt && !last) {
+      const int leader = __ffsll((unsigned long long)need) - 1;
+      unsigned long long c = 0;
+      if (lane == leader) c = atomicAdd(queue, chunk);
+      c = __shfl(c, leader);
+      lo = c;
+      hi = c >= total ? c : std::min<unsigned long long>(c + chunk, total);
+      last = c + chunk >= total;
+    }
+    const unsigned long long used_old = std::min(cnt, avail);
+    const unsigned long long used_new = std::min(cnt - used_old, hi - lo);
+    unsigned long long my = ~0ull;
+    if (rank < avail) my = next + rank;
+    else if (rank - avail < hi - lo) my = lo + (rank - avail);
+    if (hi > lo) {
+      next = lo + used_new;
+      end = hi;
+    } else {
+      next += used_old;
+    }
+    if (last && next >= end) exhausted = true;
+    return my;
+  }
+};
+
+__host__ __device__ inline unsigned long long chunk_for(uint64_t total, int blocks) {
+  const uint64_t waves = (uint64_t)blocks * (kBlock / 64);
+  const uint64_t c = total / (2 * waves);  // about two chunks per wave
+  return c < 1 ? 1 : (c > (uint64_t)kChunkMax ? (uint64_t)kChunkMax : c);
 }
 
 // A walk alternates closest-point queries and sphere jumps.  Queries differ in
@@ -113,10 +161,7 @@ __global__ __launch_bounds__(kBlock) void k_walks(WalkArgs a) {
   // ball, k = 0, is centred at the start point with radius R0, so it runs the
   // same jump code as every later ball).
   bool active = false, jump = false, exhausted = false;
-  // walk ids [pool_next, pool_end) are claimed by this wave; last_chunk once
-  // the global queue has handed out its final chunk
-  unsigned long long pool_next = 0, pool_end = 0;
-  bool last_chunk = false;
+  IdPool pool;
   uint32_t id = 0;
   int k = 0;
   T p[D];
@@ -133,31 +178,7 @@ __global__ __launch_bounds__(kBlock) void k_walks(WalkArgs a) {
     if (!exhausted) {
       const uint64_t need = __ballot(!active);
       if (need) {
-        const unsigned long long cnt = (unsigned long long)__popcll(need);
-        const unsigned long long rank = (unsigned long long)__popcll(need & ((1ull << lane) - 1));
-        const unsigned long long avail = pool_end - pool_next;
-        unsigned long long lo = 0, hi = 0;
-        if (avail < cnt && !last_chunk) {
-          const int leader = __ffsll((unsigned long long)need) - 1;
-          unsigned long long c = 0;
-          if (lane == leader) c = atomicAdd(&a.counters[0], (unsigned long long)kChunk);
-          c = __shfl(c, leader);
-          lo = c;
-          hi = c >= a.total ? c : std::min<unsigned long long>(c + kChunk, a.total);
-          last_chunk = c + kChunk >= a.total;
-        }
-        const unsigned long long used_old = std::min(cnt, avail);
-        const unsigned long long used_new = std::min(cnt - used_old, hi - lo);
-        unsigned long long my = ~0ull;
-        if (rank < avail) my = pool_next + rank;
-        else if (rank - avail < hi - lo) my = lo + (rank - avail);
-        if (hi > lo) {
-          pool_next = lo + used_new;
-          pool_end = hi;
-        } else {
-          pool_next += used_old;
-        }
-        if (last_chunk && pool_next >= pool_end) exhausted = true;
+        const unsigned long long my = pool.take(need, lane, &a.counters[0], a.chunk, a.total, exhausted);
         if (!active) {
           if (my != ~0ull) {
             id = (uint32_t)my;
@@ -443,6 +464,7 @@ int run_walks(bvc_scene s, const bvc_walk_params* p, int mode, int64_t n, WalkAr
   const int64_t needed = (int64_t)((total + kBlock - 1) / kBlock);
   blocks = (int)std::max<int64_t>(1, std::min<int64_t>(blocks, needed));
   const size_t lds = stack_bytes(h);
+  a.chunk = chunk_for(total, blocks);
   const bool src = p->f.kind != 0;
   const bool f32 = p->dtype == BVC_F32;
   if (h.dim == 2) {
@@ -501,19 +523,14 @@ __global__ __launch_bounds__(kBlock) void k_batch_walks(BatchDev b) {
   unsigned long long steps_acc = 0, capped_acc = 0, walks_acc = 0;
 #pragma unroll
   for (int q = 0; q < D; ++q) p[q] = 0.f;
+  IdPool pool;
   while (true) {
     if (!exhausted) {
       const uint64_t need = __ballot(!active);
       if (need) {
-        const int leader = __ffsll((unsigned long long)need) - 1;
-        const int cnt = __popcll(need);
-        unsigned long long base = 0;
-        if (lane == leader) base = atomicAdd(&b.counters[0], (unsigned long long)cnt);
-        base = __shfl(base, leader);
-        if (base + cnt >= b.total_walks) exhausted = true;
+        const unsigned long long my = pool.take(need, lane, &b.counters[0], b.chunk, b.total_walks, exhausted);
         if (!active) {
-          const unsigned long long my = base + __popcll(need & ((1ull << lane) - 1));
-          if (my < b.total_walks) {
+          if (my != ~0ull) {
             gid = my;
             sc = batch_scene_of_walk(b, gid);
             const BatchSceneDev& s = b.scenes[sc];
@@ -607,13 +624,14 @@ __global__ __launch_bounds__(kBlock) void k_batch_walks(BatchDev b) {
 
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_batch_finish(BatchDev b) {
-  const uint64_t id0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * kFinishRun;
-  if (id0 >= b.total_walks) return;
+  // same coalesced layout as k_finish
+  const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint64_t id0 = wave * (64 * kFinishRun) + (threadIdx.x & 63);
   int64_t i_cv = -1;
   int sc_cv = -1;
   double c = 0.0;
   for (int r = 0; r < kFinishRun; ++r) {
-    const uint64_t gid = id0 + r;
+    const uint64_t gid = id0 + (uint64_t)r * 64;
     if (gid >= b.total_walks) break;
     const int sc = batch_scene_of_walk(b, gid);
     const BatchSceneDev& s = b.scenes[sc];
@@ -668,12 +686,14 @@ __global__ __launch_bounds__(kBlock) void k_batch_reduce(BatchDev b) {
 
 }  // namespace
 
-int launch_batch_walks(const BatchDev& b, int max_depth, int blocks, hipStream_t st) {
-  hipLaunchKernelGGL(k_batch_zero, dim3(1), dim3(64), 0, st, b.counters);
-  if (b.total_walks == 0) return check_hip(hipGetLastError(), "batch walks");
+int launch_batch_walks(const BatchDev& batch, int max_depth, int blocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_zero, dim3(1), dim3(64), 0, st, batch.counters);
+  if (batch.total_walks == 0) return check_hip(hipGetLastError(), "batch walks");
   const size_t lds = (size_t)(max_depth + 1) * kBlock * sizeof(uint32_t);
-  const int64_t needed = (int64_t)((b.total_walks + kBlock - 1) / kBlock);
+  const int64_t needed = (int64_t)((batch.total_walks + kBlock - 1) / kBlock);
   blocks = (int)std::max<int64_t>(1, std::min<int64_t>(blocks > 0 ? blocks : num_cus() * 8, needed));
+  BatchDev b = batch;
+  b.chunk = chunk_for(b.total_walks, blocks);
   if (b.dim == 2) {
     if (b.has_src) hipLaunchKernelGGL((k_batch_walks<2, true>), dim3(blocks), dim3(kBlock), lds, st, b);
     else hipLaunchKernelGGL((k_batch_walks<2, false>), dim3(blocks), dim3(kBlock), lds, st, b);
@@ -681,8 +701,8 @@ int launch_batch_walks(const BatchDev& b, int max_depth, int blocks, hipStream_t
     if (b.has_src) hipLaunchKernelGGL((k_batch_walks<3, true>), dim3(blocks), dim3(kBlock), lds, st, b);
     else hipLaunchKernelGGL((k_batch_walks<3, false>), dim3(blocks), dim3(kBlock), lds, st, b);
   }
-  const uint64_t threads = (b.total_walks + kFinishRun - 1) / kFinishRun;
-  const int fblocks = (int)((threads + kBlock - 1) / kBlock);
+  const uint64_t fwaves = (b.total_walks + 64 * kFinishRun - 1) / (64 * kFinishRun);
+  const int fblocks = (int)((fwaves * 64 + kBlock - 1) / kBlock);
   if (b.dim == 2) hipLaunchKernelGGL(k_batch_finish<2>, dim3(fblocks), dim3(kBlock), 0, st, b);
   else hipLaunchKernelGGL(k_batch_finish<3>, dim3(fblocks), dim3(kBlock), 0, st, b);
   const int per = kBlock / 64;
