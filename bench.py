@@ -60,6 +60,28 @@ def rmse(a, b):
     return float(np.sqrt(np.mean((a - b) ** 2)))
 
 
+def measured_traffic():
+    """HBM bytes per launch of the gather from the committed FETCH_SIZE /
+    WRITE_SIZE summary, or None when the kernel sources have changed since
+    those counters were taken (their SHA-256 is recorded beside the figure)."""
+    import hashlib
+    import re
+
+    path = os.path.join(ROOT, "profiles", "k_gather_c2_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_hash = re.search(r"source_sha256: ([0-9a-f]{64})", text)
+    m_bytes = re.search(r"traffic_bytes_per_launch: (\d+)", text)
+    if not m_hash or not m_bytes:
+        return None
+    h = hashlib.sha256()
+    for f in ("kernels_gather.hip", "bvc_device.hpp", "bvc_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2302_11825_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return int(m_bytes.group(1)) if h.hexdigest() == m_hash.group(1) else None
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -155,7 +177,7 @@ def main():
     flops = pairs_b * FLOPS_2D_BOUNDARY_UG + pairs_s * FLOPS_2D_SOURCE_UG
     achieved = flops / (gather_ms / 1e3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": measured_traffic(),
                 "kernel": "k_gather<float,2,true>", "pairs_per_launch": pairs_b + pairs_s,
                 "flops_per_pair": {"boundary": FLOPS_2D_BOUNDARY_UG, "source": FLOPS_2D_SOURCE_UG},
                 "avg_launch_ms": round(gather_ms, 4),

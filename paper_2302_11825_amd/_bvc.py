@@ -293,18 +293,28 @@ def _views(cache, sources):
     return cv, sv
 
 
-def bvc_gather_u(dim, cache, sources, n_eval, eval_x, u, accumulate=0, stream=None):
-    cv, sv = _views(cache, sources)
+def _gparams(accumulate, near):
+    """near: None, or dict(tau, x, cx, cn, a, b) with FP64 device tensors
+    (evaluation points [dim][n_eval], cache points and normals [dim][n], a, b)."""
     gp = bvc_gather_params()
     gp.accumulate = accumulate
+    if near is not None:
+        gp.near_tau = float(near["tau"])
+        gp.near_x, gp.near_cx, gp.near_cn, gp.near_a, gp.near_b = (
+            ptr(near[k]) for k in ("x", "cx", "cn", "a", "b"))
+    return gp
+
+
+def bvc_gather_u(dim, cache, sources, n_eval, eval_x, u, accumulate=0, stream=None, near=None):
+    cv, sv = _views(cache, sources)
+    gp = _gparams(accumulate, near)
     _check(_L.bvc_gather_u(dim, C.byref(cv), C.byref(sv) if sv is not None else None, n_eval, ptr(eval_x),
                            ptr(u), C.byref(gp), stream_ptr(stream)), "bvc_gather_u")
 
 
-def bvc_gather_grad(dim, cache, sources, n_eval, eval_x, u, grad, accumulate=0, stream=None):
+def bvc_gather_grad(dim, cache, sources, n_eval, eval_x, u, grad, accumulate=0, stream=None, near=None):
     cv, sv = _views(cache, sources)
-    gp = bvc_gather_params()
-    gp.accumulate = accumulate
+    gp = _gparams(accumulate, near)
     _check(_L.bvc_gather_grad(dim, C.byref(cv), C.byref(sv) if sv is not None else None, n_eval, ptr(eval_x),
                               ptr(u), ptr(grad), C.byref(gp), stream_ptr(stream)), "bvc_gather_grad")
 

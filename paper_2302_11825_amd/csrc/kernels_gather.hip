@@ -53,22 +53,66 @@ struct GatherArgs {
   T* g;              // [D][n_eval] or null
   const T* scale;    // multiply outputs by scale[k] (adjoint dL/dx) or null
   int accumulate;
+  // FP64 near field (FP32 kernels only): boundary pairs with r^2 < tau2 in
+  // FP32 are left out of the FP32 sums and added in FP64 from these copies.
+  T tau2;
+  const double* nx;   // evaluation points [D][n_eval]
+  const double* ncx;  // cache points [D][n_cache]
+  const double* ncn;  // cache normals [D][n_cache]
+  const double* na;   // [n_cache]
+  const double* nb;   // [n_cache]
 };
 
-// Entry layout in LDS (8 values): 2D boundary {y0, y1, na0, na1, bl, bg}, 3D
-// boundary {y0, y1, y2, bl, na0, na1, na2, -}; sources {y.., sl, sg}.
-template <typename T, int D, bool GRAD>
+// Entry layout in LDS (8 values): 2D boundary {y0, y1, 2 na0, 2 na1, 2 bl, bg,
+// na0, na1}, 3D boundary {y0, y1, y2, bl, na0, na1, na2, -}; sources
+// {y.., sl, sg} (2D sl doubled like bl).
+template <typename T, int D, bool GRAD, bool NEAR = false>
 __device__ __forceinline__ void gather_block(const GatherArgs<T>& a, int64_t block, T* ent);
 
-template <typename T, int D, bool GRAD>
+template <typename T, int D, bool GRAD, bool NEAR>
 __global__ __launch_bounds__(kGBlock) void k_gather(GatherArgs<T> a) {
   __shared__ T ent[kTile * 8];
-  gather_block<T, D, GRAD>(a, blockIdx.x, ent);
+  gather_block<T, D, GRAD, NEAR>(a, blockIdx.x, ent);
+}
+
+// FP64 contribution of cache point i to u (and grad u) at evaluation point k,
+// from the FP64 copies: u += a dG/dn - b G (Eq. 3), grad from Eq. 5.
+template <int D, bool GRAD>
+__device__ __forceinline__ void near_pair(const GatherArgs<float>& a, int64_t k, int64_t i, double& tu, double* tg) {
+  double d[D];
+  double r2 = 0.0, nd = 0.0;
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    d[c] = a.ncx[c * a.n_cache + i] - a.nx[c * a.n_eval + k];
+    r2 += d[c] * d[c];
+    nd += a.ncn[c * a.n_cache + i] * d[c];
+  }
+  if (!(r2 > 0.0)) return;  // coincident points carry no finite contribution
+  const double av = a.na[i], bv = a.nb[i];
+  if constexpr (D == 2) {
+    const double k2 = 1.0 / (2.0 * kPi * r2);
+    tu += av * nd * k2 - bv * log(r2) / (4.0 * kPi);
+    if constexpr (GRAD) {
+      const double q = (2.0 * av * nd / r2 + bv) * k2;
+#pragma unroll
+      for (int c = 0; c < D; ++c) tg[c] += q * d[c] - av * a.ncn[c * a.n_cache + i] * k2;
+    }
+  } else {
+    const double r = sqrt(r2);
+    const double k3 = 1.0 / (4.0 * kPi * r2 * r);
+    tu += bv / (4.0 * kPi * r) + av * nd * k3;
+    if constexpr (GRAD) {
+      const double q = (3.0 * av * nd / r2 + bv) * k3;
+#pragma unroll
+      for (int c = 0; c < D; ++c) tg[c] += q * d[c] - av * a.ncn[c * a.n_cache + i] * k3;
+    }
+  }
 }
 
 // One block's share of the gather: evaluation points [block*512, block*512+512).
-template <typename T, int D, bool GRAD>
+template <typename T, int D, bool GRAD, bool NEAR>
 __device__ __forceinline__ void gather_block(const GatherArgs<T>& a, int64_t block, T* ent) {
+  static_assert(!NEAR || sizeof(T) == 4, "the near field applies to FP32 gathers");
   const int tid = threadIdx.x;
   const int64_t k0 = block * (kGBlock * kPPT) + tid;
   T x[kPPT][D];
@@ -145,6 +189,9 @@ __device__ __forceinline__ void gather_block(const GatherArgs<T>& a, int64_t blo
       }
     }
     __syncthreads();
+    bool hit[kPPT];
+#pragma unroll
+    for (int p = 0; p < kPPT; ++p) hit[p] = false;
 #pragma unroll 4
     for (int j = 0; j < cnt; ++j) {
       const T* e = ent + j * 8;
@@ -155,9 +202,19 @@ __device__ __forceinline__ void gather_block(const GatherArgs<T>& a, int64_t blo
           const T dx = y0 - x[p][0], dy = y1 - x[p][1];
           // r^2 + tiny keeps coincident points finite at no extra instruction
           const T r2 = fma(dx, dx, fma(dy, dy, tiny));
-          const T ri = recip(r2);
+          T ri, lr;
+          if constexpr (NEAR) {
+            // near pairs contribute nothing here; near_sweep adds them in FP64
+            const bool nr = r2 < a.tau2;
+            hit[p] = hit[p] || nr;
+            ri = nr ? T(0) : recip(r2);
+            lr = nr ? T(0) : log_r2(r2);
+          } else {
+            ri = recip(r2);
+            lr = log_r2(r2);
+          }
           const T t2 = fma(m0, dx, m1 * dy);  // 2 a (n . (y - x)) / (2 pi)
-          au[p] = fma(bl, log_r2(r2), fma(t2, ri, au[p]));
+          au[p] = fma(bl, lr, fma(t2, ri, au[p]));
           if constexpr (GRAD) {
             // grad = (q (y - x) - a n / (2 pi)) / r^2,  q = (2 a n.(y-x)/r^2 + b)/(2 pi)
             const T q = fma(t2, ri, bg);
@@ -171,7 +228,14 @@ __device__ __forceinline__ void gather_block(const GatherArgs<T>& a, int64_t blo
         for (int p = 0; p < kPPT; ++p) {
           const T dx = y0 - x[p][0], dy = y1 - x[p][1], dz = y2 - x[p][2];
           const T r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, tiny)));
-          const T ri = rsq(r2);
+          T ri;
+          if constexpr (NEAR) {
+            const bool nr = r2 < a.tau2;
+            hit[p] = hit[p] || nr;
+            ri = nr ? T(0) : rsq(r2);
+          } else {
+            ri = rsq(r2);
+          }
           const T ri2 = ri * ri;
           const T t = fma(n0, dx, fma(n1, dy, n2 * dz));
           // b/r + t/r^3 = (b + t/r^2)/r
@@ -182,6 +246,31 @@ __device__ __forceinline__ void gather_block(const GatherArgs<T>& a, int64_t blo
             ag[p][0] = fma(-n0, ri3, fma(q, dx, ag[p][0]));
             ag[p][1] = fma(-n1, ri3, fma(q, dy, ag[p][1]));
             ag[p][2] = fma(-n2, ri3, fma(q, dz, ag[p][2]));
+          }
+        }
+      }
+    }
+    if constexpr (NEAR) {
+      // FP64 sweep of the tile for lanes that met a near pair: the same FP32
+      // test as above picks exactly the pairs left out of the FP32 sums
+      bool any = false;
+#pragma unroll
+      for (int p = 0; p < kPPT; ++p) any = any || (hit[p] && live[p]);
+      if (__any(any)) {
+        for (int j = 0; j < cnt; ++j) {
+          const T* e = ent + j * 8;
+#pragma unroll
+          for (int p = 0; p < kPPT; ++p) {
+            if (!(hit[p] && live[p])) continue;
+            T r2;
+            if constexpr (D == 2) {
+              const T dx = e[0] - x[p][0], dy = e[1] - x[p][1];
+              r2 = fma(dx, dx, fma(dy, dy, tiny));
+            } else {
+              const T dx = e[0] - x[p][0], dy = e[1] - x[p][1], dz = e[2] - x[p][2];
+              r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, tiny)));
+            }
+            if (r2 < a.tau2) near_pair<D, GRAD>(a, k0 + p * kGBlock, t0 + j, tu[p], tg[p]);
           }
         }
       }
@@ -495,15 +584,22 @@ int check_sources(const bvc_source_view* s, int dtype) {
 }
 
 template <typename T, int D>
-void launch_gather(const GatherArgs<T>& a, bool grad, hipStream_t st) {
+void launch_gather(const GatherArgs<T>& a, bool grad, bool near, hipStream_t st) {
   const int blocks = (int)((a.n_eval + kGBlock * kPPT - 1) / (kGBlock * kPPT));
-  if (grad) hipLaunchKernelGGL((k_gather<T, D, true>), dim3(blocks), dim3(kGBlock), 0, st, a);
-  else hipLaunchKernelGGL((k_gather<T, D, false>), dim3(blocks), dim3(kGBlock), 0, st, a);
+  if constexpr (sizeof(T) == 4) {
+    if (near) {
+      if (grad) hipLaunchKernelGGL((k_gather<T, D, true, true>), dim3(blocks), dim3(kGBlock), 0, st, a);
+      else hipLaunchKernelGGL((k_gather<T, D, false, true>), dim3(blocks), dim3(kGBlock), 0, st, a);
+      return;
+    }
+  }
+  if (grad) hipLaunchKernelGGL((k_gather<T, D, true, false>), dim3(blocks), dim3(kGBlock), 0, st, a);
+  else hipLaunchKernelGGL((k_gather<T, D, false, false>), dim3(blocks), dim3(kGBlock), 0, st, a);
 }
 
 template <typename T>
 int gather_impl(int dim, const bvc_cache_view* c, const bvc_source_view* s, int64_t n_eval, const void* ex, void* u,
-                void* g, const void* scale, int accumulate, hipStream_t st) {
+                void* g, const void* scale, int accumulate, hipStream_t st, const bvc_gather_params* near = nullptr) {
   GatherArgs<T> a{};
   a.n_eval = n_eval;
   a.ex = (const T*)ex;
@@ -519,8 +615,19 @@ int gather_impl(int dim, const bvc_cache_view* c, const bvc_source_view* s, int6
   a.g = (T*)g;
   a.scale = (const T*)scale;
   a.accumulate = accumulate;
-  if (dim == 2) launch_gather<T, 2>(a, g != nullptr, st);
-  else launch_gather<T, 3>(a, g != nullptr, st);
+  if (near) {
+    // tau^2 rounded up to FP32 so that every pair closer than tau in FP32 is near
+    float t2 = (float)(near->near_tau * near->near_tau);
+    if ((double)t2 < near->near_tau * near->near_tau) t2 = nextafterf(t2, INFINITY);
+    a.tau2 = (T)t2;
+    a.nx = near->near_x;
+    a.ncx = near->near_cx;
+    a.ncn = near->near_cn;
+    a.na = near->near_a;
+    a.nb = near->near_b;
+  }
+  if (dim == 2) launch_gather<T, 2>(a, g != nullptr, near != nullptr, st);
+  else launch_gather<T, 3>(a, g != nullptr, near != nullptr, st);
   return check_hip(hipGetLastError(), "gather launch");
 }
 
@@ -536,7 +643,11 @@ int gather_entry(int32_t dim, const bvc_cache_view* c, const bvc_source_view* s,
   if (!ex || (!u && !g)) return fail(BVC_EINVAL, "null evaluation points or outputs");
   const int acc = prm ? prm->accumulate : 0;
   hipStream_t st = (hipStream_t)stream;
-  if (c->dtype == BVC_F32) return gather_impl<float>(dim, c, s, n_eval, ex, u, g, nullptr, acc, st);
+  const bool near = prm && prm->near_tau > 0.0 && c->dtype == BVC_F32 && c->n > 0;
+  if (prm && !(prm->near_tau >= 0.0)) return fail(BVC_EINVAL, "near_tau must be >= 0");
+  if (near && (!prm->near_x || !prm->near_cx || !prm->near_cn || !prm->near_a || !prm->near_b))
+    return fail(BVC_EINVAL, "near_tau > 0 needs the FP64 copies near_x, near_cx, near_cn, near_a, near_b");
+  if (c->dtype == BVC_F32) return gather_impl<float>(dim, c, s, n_eval, ex, u, g, nullptr, acc, st, near ? prm : nullptr);
   return gather_impl<double>(dim, c, s, n_eval, ex, u, g, nullptr, acc, st);
 }
 

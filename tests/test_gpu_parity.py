@@ -217,6 +217,77 @@ def test_gather_matches_oracle(B, orc, dim, dtype):
         assert np.all(np.abs(gg - go).max(1) <= gtol + 1e-30)
 
 
+def _abs_terms(dim, ex, cy, cn, a, b, sy, sw, tau):
+    """Sums of |terms| of u and of grad u per evaluation point, split into the
+    pairs at r >= tau (FP32 in the kernel) and r < tau (FP64 near field)."""
+    d = cy[None, :, :] - ex[:, None, :]
+    r = np.linalg.norm(d, axis=2)
+    nd = np.abs(np.einsum("kid,id->ki", d, cn))
+    c = 2 * np.pi if dim == 2 else 4 * np.pi
+    g_abs = np.abs(np.log(r)) / (2 * np.pi) if dim == 2 else 1 / (4 * np.pi * r)
+    tu = np.abs(a)[None] * nd / (c * r**dim) + np.abs(b)[None] * g_abs
+    tg = (4 * np.abs(a)[None] / r**dim + np.abs(b)[None] / r ** (dim - 1)) / c
+    far = r >= tau * (1 - 1e-4)  # margin for the FP32 test in the kernel
+    ds_ = np.linalg.norm(sy[None] - ex[:, None], axis=2)
+    su = np.abs(sw)[None] * (np.abs(np.log(ds_)) / (2 * np.pi) if dim == 2 else 1 / (4 * np.pi * ds_))
+    sg = np.abs(sw)[None] / (c * ds_ ** (dim - 1))
+    rmin = np.minimum(np.where(far, r, np.inf).min(1), ds_.min(1))
+    return ((tu * far).sum(1) + su.sum(1), (tu * ~far).sum(1), (tg * far).sum(1) + sg.sum(1),
+            (tg * ~far).sum(1), rmin)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_gather_fp32_near_field(B, orc, dim):
+    """FP32 gather with the FP64 near field (pairs closer than tau evaluated
+    from FP64 copies): matches the FP64 oracle to the FP32 bound of the far
+    pairs plus FP64 rounding of the near ones, at evaluation points 1e-6 to
+    1e-3 from cache points where the plain FP32 gather is far off."""
+    _bvc, pl = B
+    say(f"gather fp32 near field dim={dim}")
+    ex, cy, cn, a, b, sy, sw = _gather_case(dim, "f32")
+    f32 = lambda v: v.astype(np.float32).astype(np.float64)
+    cy, cn, a, b, sy, sw = (f32(v) for v in (cy, cn, a, b, sy, sw))  # cache data exact in both precisions
+    rng = np.random.default_rng(40 + dim)
+    pick = rng.choice(cy.shape[0], 200)
+    v = rng.normal(0, 1, (200, dim))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    ex = np.concatenate([ex[:300], cy[pick] + v * (10 ** rng.uniform(-6, -3, 200))[:, None]])
+    K = ex.shape[0]
+    tau = 1e-2
+    dev = lambda x, T: torch.from_numpy(np.ascontiguousarray(x.T if x.ndim == 2 else x)).to("cuda", T)
+    F, D = torch.float32, torch.float64
+    cache = dict(n=cy.shape[0], dtype=_bvc.F32, x=dev(cy, F), nrm=dev(cn, F), a=dev(a, F), b=dev(b, F))
+    src = dict(n=sy.shape[0], dtype=_bvc.F32, y=dev(sy, F), s=dev(sw, F))
+    near = dict(tau=tau, x=dev(ex, D), cx=dev(cy, D), cn=dev(cn, D), a=dev(a, D), b=dev(b, D))
+    u_n = torch.empty(K, dtype=F, device="cuda")
+    g_n = torch.empty(dim, K, dtype=F, device="cuda")
+    u_p = torch.empty(K, dtype=F, device="cuda")
+    _bvc.bvc_gather_grad(dim, cache, src, K, dev(ex, F), u_n, g_n, near=near)
+    _bvc.bvc_gather_u(dim, cache, src, K, dev(ex, F), u_p)
+    torch.cuda.synchronize()
+    uo, go = orc.gather(dim, ex, cy, cn, a, b, sy, sw, with_grad=True)
+    su_far, su_near, sg_far, sg_near, rmin = _abs_terms(dim, ex, cy, cn, a, b, sy, sw, tau)
+    x32 = f32(ex)
+    uu = 2.0**-24
+    zmax = np.linalg.norm(np.concatenate([cy, sy]), axis=1).max()
+    # far pairs: the FP32 bound of the plain test, with the FP32 rounding of
+    # the evaluation point itself (|x - x32| / r relative per term) added
+    shift = np.linalg.norm(ex - x32, axis=1) / rmin
+    rel = uu * (300 + 4 * (np.linalg.norm(ex, axis=1) + zmax) / rmin) + 4 * shift
+    # plus the FP32 rounding of the result itself (u |value|)
+    tol = su_far * rel + 1e-10 * su_near + uu * np.abs(uo)
+    err = np.abs(u_n.double().cpu().numpy() - uo)
+    assert np.all(err <= tol), np.max(err / tol)
+    gtol = sg_far * (rel + 2 * shift) + 1e-10 * sg_near + uu * np.abs(go).max(1)
+    gerr = np.abs(to_np_aos(g_n) - go).max(1)
+    assert np.all(gerr <= gtol + 1e-30), np.max(gerr / gtol)
+    # the points that sit close to a cache point are where the plain FP32
+    # gather loses digits and the near field recovers them
+    close = np.arange(300, K)[np.linalg.norm(ex[300:] - cy[pick], axis=1) < 1e-4]
+    err_p = np.abs(u_p.double().cpu().numpy() - uo)
+    assert np.median(err_p[close]) > 10 * np.median(err[close] + 1e-300)
+
+
 @pytest.mark.parametrize("dim", [2, 3])
 def test_gather_backward_fp64(B, orc, dim):
     _bvc, pl = B
