@@ -11,7 +11,9 @@ method); the scene is built and uploaded once before timing.
 Prints one JSON line: interior points per second of the BVC step, walk steps
 per second, the error of the BVC result against the manufactured closed form
 next to pointwise walk on spheres at matching error, the roofline of the
-dominant kernel (the gather), and the FP64 oracle timed on the host cores.
+longest kernel of the step (the band-point walks, memory roofline on
+algorithmic traversal bytes) and of the gather (VALU roofline), and the FP64
+oracle timed on the host cores.
 """
 from __future__ import annotations
 
@@ -60,26 +62,44 @@ def rmse(a, b):
     return float(np.sqrt(np.mean((a - b) ** 2)))
 
 
-def measured_traffic():
-    """HBM bytes per launch of the gather from the committed FETCH_SIZE /
-    WRITE_SIZE summary, or None when the kernel sources have changed since
+def measured_traffic(kernel, sources):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE /
+    WRITE_SIZE summary, or None when the kernel's sources have changed since
     those counters were taken (their SHA-256 is recorded beside the figure)."""
     import hashlib
     import re
 
-    path = os.path.join(ROOT, "profiles", "k_gather_c2_hbm_traffic.md")
+    path = os.path.join(ROOT, "profiles", "c2_hbm_traffic.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
-    m_hash = re.search(r"source_sha256: ([0-9a-f]{64})", text)
-    m_bytes = re.search(r"traffic_bytes_per_launch: (\d+)", text)
-    if not m_hash or not m_bytes:
+    m = re.search(r"kernel: " + re.escape(kernel) + r"\s+source_sha256: ([0-9a-f]{64})\s+"
+                  r"traffic_bytes_per_launch: (\d+)", text)
+    if not m:
         return None
     h = hashlib.sha256()
-    for f in ("kernels_gather.hip", "bvc_device.hpp", "bvc_internal.hpp"):
+    for f in sources:
         with open(os.path.join(ROOT, "paper_2302_11825_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    return int(m_bytes.group(1)) if h.hexdigest() == m_hash.group(1) else None
+    return int(m.group(2)) if h.hexdigest() == m.group(1) else None
+
+
+GATHER_SOURCES = ("kernels_gather.hip", "bvc_device.hpp", "bvc_internal.hpp")
+WALK_SOURCES = ("walks.hip", "bvc_device.hpp", "bvc_internal.hpp")
+
+
+def walk_bytes(dim, es, mode, with_grad):
+    """Algorithmic bytes of the walk kernel: per BVH node expanded (two child
+    boxes in the walk precision plus the int2 child links), per primitive
+    tested (segment: 4 values; triangle: 3 x 4 values), and per walk (inputs
+    read and records written; mode 0 cache walk, mode 1 pointwise walk)."""
+    node = 2 * 2 * dim * es + 8
+    prim = (4 if dim == 2 else 12) * es
+    if mode == 0:
+        io = 8 + 2 * dim * 8 + dim * es + 3 * es          # R0, x, n (FP64); exit, U, D, w1
+    else:
+        io = 8 + dim * es + dim * es + es + (2 * dim * es if with_grad else 0)  # R0, x; exit, U, grad, w1
+    return node, prim, io
 
 
 def main():
@@ -133,7 +153,9 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_step = e0.elapsed_time(e1) / args.steps
-    stages = {k: float(np.mean(v)) for k, v in watch.totals_ms().items()}
+    timers = {k: float(np.mean(v)) for k, v in watch.totals_ms().items()}
+    kernels = {k: v for k, v in timers.items() if k.startswith("k_")}
+    stages = {k: v for k, v in timers.items() if not k.startswith("k_")}
     print(f"[bench] timed {args.steps} steps: {ms_step:.2f} ms/step (wall {wall:.2f}s) {stages}",
           file=sys.stderr, flush=True)
 
@@ -143,7 +165,7 @@ def main():
     steps_total = sum(int(s.counters[1]) + int(s.pw_counters[1]) for s in sols)
     walks_total = sum(int(s.counters[3]) + int(s.pw_counters[3]) for s in sols)
     capped = sum(int(s.counters[2]) + int(s.pw_counters[2]) for s in sols)
-    walk_ms = stages.get("cache_walks", 0.0)
+    walk_ms = kernels.get("k_walks_cache", stages.get("cache_walks", 0.0))
     cache_steps = sum(int(s.counters[1]) for s in sols) / args.steps
     cache_walk_rate = cache_steps / (walk_ms / 1e3) if walk_ms > 0 else 0.0
 
@@ -169,19 +191,20 @@ def main():
     rmse_grad_far = float(np.sqrt(np.mean(gerr[far16]))) if far16.any() else float("nan")
     band_rmse = rmse(u_b, truth_b) if prep.n_band else float("nan")
 
-    # dominant kernel roofline (the gather: one launch per step)
+    # VALU roofline of the gather (one launch per step)
     gather_ms = stages["gather"]
     n_src = int(sol.extra["sview"]["n"]) if sol.extra["sview"] else 0
     pairs_b = prep.n_int * sol.cache.n
     pairs_s = prep.n_int * n_src
     flops = pairs_b * FLOPS_2D_BOUNDARY_UG + pairs_s * FLOPS_2D_SOURCE_UG
     achieved = flops / (gather_ms / 1e3) / 1e12
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": measured_traffic(),
-                "kernel": "k_gather<float,2,true>", "pairs_per_launch": pairs_b + pairs_s,
-                "flops_per_pair": {"boundary": FLOPS_2D_BOUNDARY_UG, "source": FLOPS_2D_SOURCE_UG},
-                "avg_launch_ms": round(gather_ms, 4),
-                "pairs_per_s": (pairs_b + pairs_s) / (gather_ms / 1e3)}
+    roofline_gather = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+                       "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                       "traffic": measured_traffic("k_gather<float,2,true>", GATHER_SOURCES),
+                       "kernel": "k_gather<float,2,true>", "pairs_per_launch": pairs_b + pairs_s,
+                       "flops_per_pair": {"boundary": FLOPS_2D_BOUNDARY_UG, "source": FLOPS_2D_SOURCE_UG},
+                       "avg_launch_ms": round(gather_ms, 4),
+                       "pairs_per_s": (pairs_b + pairs_s) / (gather_ms / 1e3)}
 
     # pointwise walk on spheres at matching error, on a subset of interior points
     pointwise = None
@@ -227,10 +250,42 @@ def main():
         print(f"[bench] pointwise {pointwise['walks_for_equal_rmse']} walks for equal RMSE", file=sys.stderr,
               flush=True)
 
-    cpu = None
+    cpu, work = None, None
     if not args.no_cpu:
-        cpu = cpu_baseline(prob, prep, sol, args.cpu_seconds, n_pts)
+        cpu, work = oracle_leg(prob, prep, sol, args.cpu_seconds, n_pts)
         print(f"[bench] cpu baseline {cpu}", file=sys.stderr, flush=True)
+
+    # memory roofline of the band-point walk kernel, the longest launch of the
+    # step, on algorithmic traversal bytes: nodes and primitives a
+    # nearest-first query visits (counted by the oracle on this BVH) times
+    # their record sizes, plus each walk's inputs and records
+    es = 4 if args.dtype == "f32" else 8
+    band_ms = kernels.get("k_walks_band", 0.0)
+    q_band, w_band = int(sol.pw_counters[1]), int(sol.pw_counters[3])
+    node_b, prim_b, io_b = walk_bytes(2, es, 1, True)
+    roofline = {"bound": "hbm", "achieved": None, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": None,
+                "traffic": measured_traffic("k_walks<float,2,true,1>", WALK_SOURCES) if es == 4 else None,
+                "kernel": "k_walks<float,2,true,1> (band-point walks)", "avg_launch_ms": round(band_ms, 4),
+                "queries_per_launch": q_band, "walks_per_launch": w_band,
+                "bytes": {"node": node_b, "primitive": prim_b, "walk_io": io_b}}
+    walk_rates = {}
+    if work is not None and band_ms > 0:
+        vn, vp = work["band"]["nodes_per_query"], work["band"]["prims_per_query"]
+        per_query = vn * node_b + vp * prim_b
+        alg = q_band * per_query + w_band * io_b
+        gbs = alg / (band_ms / 1e3) / 1e9
+        roofline.update(achieved=round(gbs, 1), frac=round(gbs / PEAK_HBM_GBS, 4), nodes_per_query=vn,
+                        prims_per_query=vp, bytes_per_query=round(per_query, 1), bytes_per_launch=alg)
+        vn_c, vp_c = work["cache"]["nodes_per_query"], work["cache"]["prims_per_query"]
+        node_c, prim_c, io_c = walk_bytes(2, es, 0, False)
+        q_c, w_c = int(sol.counters[1]), int(sol.counters[3])
+        cache_ms = kernels.get("k_walks_cache", 0.0)
+        alg_c = q_c * (vn_c * node_c + vp_c * prim_c) + w_c * io_c
+        walk_rates = {"cache_walk_kernel": {"avg_launch_ms": round(cache_ms, 4), "queries": q_c,
+                                            "nodes_per_query": vn_c, "prims_per_query": vp_c,
+                                            "GB_per_s": round(alg_c / (cache_ms / 1e3) / 1e9, 1),
+                                            "frac_hbm": round(alg_c / (cache_ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4)},
+                      "counted_on": work["counted_on"]}
 
     out = {
         "metric": "interior pts/sec at fixed RMSE (BVC vs pointwise WoS); walk steps/sec",
@@ -259,16 +314,23 @@ def main():
                  "grad": rmse_grad, "grad_d_ge_0.05": rmse_grad_far},
         "pointwise_wos": pointwise,
         "roofline": roofline,
+        "roofline_gather": roofline_gather,
+        "walk_kernels": walk_rates,
+        "kernel_ms": {k: round(v, 4) for k, v in kernels.items()},
         "cpu_baseline": cpu,
         "setup_s": setup_s,
     }
     print(json.dumps(out))
 
 
-def cpu_baseline(prob, prep, sol, budget_s, n_pts):
-    """The FP64 oracle on a bounded sample of the same step, extrapolated to
-    the step's full work: walks of the first cache points, the gather at the
-    first interior points, pointwise walks at the first band points."""
+def oracle_leg(prob, prep, sol, budget_s, n_pts):
+    """The host oracle leg.  (1) cpu_baseline: the FP64 oracle on a bounded
+    sample of the same step, extrapolated to the step's full work: walks of
+    the first cache points, the gather at the first interior points,
+    pointwise walks at the first band points.  (2) The traversal work per
+    closest-point query: the oracle replays walks with the library's walk ids
+    and counts the nodes and primitives a nearest-first query visits on the
+    library's own BVH (exported through the C-ABI)."""
     import oracle
     import workloads as wl
 
@@ -318,12 +380,46 @@ def cpu_baseline(prob, prep, sol, budget_s, n_pts):
         tb = time.perf_counter() - t
     band_pts_s = nbp / tb if tb > 0 else float("inf")
     step_s = n_cache * W / walks_per_s + prep.n_int / gather_pts_s + (prep.n_band / band_pts_s if nbp else 0.0)
+    work = traversal_work(oracle, osc, prob, prep, cn, idx_b, W)
     return {"value": n_pts / step_s, "unit": "points/s", "cores": oracle.num_threads(), "kind": "oracle",
             "sample": (f"FP64 oracle: {nw} cache points x {W} walks ({walks_per_s:.3g} walks/s), gather at "
                        f"{ng} interior points against {n_cache} cache + {0 if sw is None else sw.size} sources "
                        f"({gather_pts_s:.3g} points/s), pointwise walks at {nbp} band points; extrapolated to "
                        f"the full step ({step_s:.1f} s)"),
-            "step_s_extrapolated": step_s}
+            "step_s_extrapolated": step_s}, work
+
+
+def traversal_work(oracle, osc, prob, prep, cn, idx_b, W, n_cache_pts=256, n_band_pts=1024, walks_each=8):
+    """Mean nodes expanded and primitives tested per query, counted by the
+    oracle on the library's exported BVH, over the queries of `walks_each`
+    walks (ids i*W + j, as the library numbers them) of cache points and band
+    points taken evenly across their sets (cache walks and pointwise walks)."""
+    from paper_2302_11825_amd import _bvc as B
+
+    child, boxes, order = B.bvc_scene_export_bvh(prep.sc.h)
+    P = oracle.walk_params(prob.eps, W, prob.seed_walks)
+    out = {}
+    n_all = cn["x"].shape[0]
+    ci = np.linspace(0, n_all - 1, min(n_cache_pts, n_all)).astype(np.int64)
+    nc = ci.size
+    ids = [int(i) * W + j for i in ci for j in range(walks_each)]
+    q, h, _ = oracle.walk_queries(osc, P, 0, np.repeat(cn["x"][ci], walks_each, 0),
+                                  np.repeat(cn["R0"][ci], walks_each), ids)
+    vn, vp = oracle.bvh_visits(osc, child, boxes, order, q, h)
+    out["cache"] = {"nodes_per_query": float(vn.mean()), "prims_per_query": float(vp.mean()),
+                    "queries_counted": int(q.shape[0])}
+    bi = np.linspace(0, idx_b.size - 1, min(n_band_pts, idx_b.size)).astype(np.int64)
+    nb = bi.size
+    pts = prob.eval_x[idx_b[bi]]
+    d, _, _ = osc.closest(pts)
+    ids = [int(k) * W + j for k in bi for j in range(walks_each)]
+    q, h, _ = oracle.walk_queries(osc, P, 1, np.repeat(pts, walks_each, 0), np.repeat(d, walks_each), ids)
+    vn, vp = oracle.bvh_visits(osc, child, boxes, order, q, h)
+    out["band"] = {"nodes_per_query": float(vn.mean()), "prims_per_query": float(vp.mean()),
+                   "queries_counted": int(q.shape[0])}
+    out["counted_on"] = (f"{out['cache']['queries_counted']} cache-walk and {out['band']['queries_counted']} "
+                         f"band-walk queries of oracle walks ({walks_each} walks x {nc} cache / {nb} band points)")
+    return out
 
 
 if __name__ == "__main__":

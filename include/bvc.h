@@ -115,6 +115,14 @@ int bvc_scene_get_info(bvc_scene scene, bvc_scene_info* out);
  * Synchronises the stream (the host staging copy is freed on return). */
 int bvc_scene_upload(bvc_scene scene, void* device_buffer, size_t bytes, void* stream);
 int bvc_scene_destroy(bvc_scene scene);
+/* Host copy of the BVH topology, for tools that count the traversal work a
+ * closest-point query needs on this exact tree.  child [n_nodes][2]: >= 0 an
+ * internal node, < 0 a leaf ~((start << 3) | (count - 1)) over the leaf-ordered
+ * primitives; boxes [n_nodes][4*dim] FP64 child boxes stored in the parent
+ * (child 0 lo, child 0 hi, child 1 lo, child 1 hi); order [n_prims]: the
+ * original primitive id of each leaf-ordered primitive.  Node 0 is the root.
+ * Host pointers, caller-owned, sized from bvc_scene_info; any may be NULL. */
+int bvc_scene_export_bvh(bvc_scene scene, int32_t* child, double* boxes, int32_t* order);
 
 /* Total measure of the offset-boundary candidate set at offset l: segment
  * lengths (times `sides`) plus vertex circles (2D); face areas plus edge
@@ -180,6 +188,9 @@ typedef struct {
   int32_t blocks;          /* persistent grid size (0 = automatic) */
   bvc_field g;             /* Dirichlet data */
   bvc_field f;             /* source term (kind 0 for Laplace) */
+  void* ev_begin;          /* optional hipEvent_t recorded on the stream right before */
+  void* ev_end;            /* and right after the walk kernel (NULL = none), to time
+                              the traversal alone; ignored by the batch calls */
 } bvc_walk_params;
 
 /* Walk j of cache point i has id i*W + j (n_cache*W < 2^32).  Each walk takes

@@ -97,6 +97,10 @@ def lib():
                                              C.c_uint32, C.c_int, _dp, C.c_double, _dp]
         L.orc_grad_radius.argtypes = [C.c_double]
         L.orc_grad_radius.restype = C.c_double
+        L.orc_walk_queries.argtypes = [C.c_void_p, C.POINTER(_WalkParams), C.c_int, _dp, C.c_double,
+                                       C.c_uint32, C.c_int32, _dp, _ip]
+        L.orc_walk_queries.restype = C.c_int32
+        L.orc_bvh_visits.argtypes = [C.c_void_p, C.c_int64, _ip, _dp, _ip, C.c_int64, _dp, _ip, _dp, _dp]
         _lib = L
     return _lib
 
@@ -275,6 +279,41 @@ def walk(scene: Scene, g, f, params, mode, x, n, R0, xbar, id_):
     lib().orc_walk(scene.h, C.byref(G), C.byref(Fv), C.byref(params), mode, _d(x), _d(n),
                    float(R0), _d(xbar), id_, _d(U), _d(gr), _d(ex), _d(w1), _i(st), _i(cap))
     return dict(U=U[0], grad=gr, exit=ex, w1=w1[0], steps=int(st[0]), capped=bool(cap[0]))
+
+
+def walk_queries(scene: Scene, params, mode, x, R0, ids, max_q=None):
+    """Query points (and hints: the previous query's closest primitive) of the
+    walks `ids` started from x[i] with first radius R0[i], ids[i] the walk id
+    (Section 3.1).  Returns (points [n, dim], hints [n], walk index [n])."""
+    d = scene.dim
+    max_q = int(max_q or params.max_steps)
+    pts, hints, owner = [], [], []
+    x = _f64(x).reshape(-1, d)
+    for i, wid in enumerate(ids):
+        q = np.zeros((max_q, d))
+        h = np.zeros(max_q, np.int32)
+        n = lib().orc_walk_queries(scene.h, C.byref(params), int(mode), _d(np.ascontiguousarray(x[i])),
+                                   float(R0[i]), int(wid), max_q, _d(q), _i(h))
+        pts.append(q[:n])
+        hints.append(h[:n])
+        owner.append(np.full(n, i))
+    return np.concatenate(pts), np.concatenate(hints), np.concatenate(owner)
+
+
+def bvh_visits(scene: Scene, child, boxes, order, q, hints):
+    """Nodes expanded and primitive distances evaluated by a nearest-first
+    query at each point q on the given BVH (child links, FP64 child boxes in
+    the parent, leaf order), seeded with the hint primitive."""
+    child = np.ascontiguousarray(child, dtype=np.int32)
+    order = np.ascontiguousarray(order, dtype=np.int32)
+    boxes = _f64(boxes)
+    q = _f64(q).reshape(-1, scene.dim)
+    hints = np.ascontiguousarray(hints, dtype=np.int32)
+    nodes = np.zeros(q.shape[0])
+    prims = np.zeros(q.shape[0])
+    lib().orc_bvh_visits(scene.h, child.shape[0], _i(child), _d(boxes), _i(order), q.shape[0], _d(q),
+                         _i(hints), _d(nodes), _d(prims))
+    return nodes, prims
 
 
 def cache_walks(scene: Scene, g, f, params, cache, records=False):

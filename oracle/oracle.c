@@ -1057,6 +1057,88 @@ void orc_walk(const orc_scene* s, const orc_field* g, const orc_field* f,
   *w1 = dim / R0 * wn;
 }
 
+int32_t orc_walk_queries(const orc_scene* s, const orc_walk_params* p, int mode, const double* x,
+                         double R0, uint32_t id, int32_t max_q, double* q, int32_t* hint) {
+  int dim = s->dim;
+  uint32_t tag = mode == 0 ? 1u : 2u;
+  if (mode == 1 && R0 < p->eps) return 0;
+  double nu[3], pos[3], pb[3];
+  walk_direction(p->seed, 0, id, p->batch, tag, dim, nu);
+  for (int a = 0; a < dim; ++a) pos[a] = x[a] + R0 * nu[a];
+  int32_t prev = -1, n = 0;
+  for (int32_t k = 1; n < max_q; ++k) {
+    for (int a = 0; a < dim; ++a) q[n * dim + a] = pos[a];
+    hint[n++] = prev;
+    double d;
+    int32_t prim;
+    orc_closest(s, pos, 0, &d, pb, &prim);
+    if (d < p->eps || k >= p->max_steps) break;
+    walk_direction(p->seed, (uint32_t)k, id, p->batch, tag, dim, nu);
+    for (int a = 0; a < dim; ++a) pos[a] += d * nu[a];
+    prev = prim;
+  }
+  return n;
+}
+
+void orc_bvh_visits(const orc_scene* s, int64_t n_nodes, const int32_t* child, const double* boxes,
+                    const int32_t* order, int64_t n_q, const double* q, const int32_t* hint,
+                    double* nodes, double* prims) {
+  int dim = s->dim;
+  (void)n_nodes;
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t i = 0; i < n_q; ++i) {
+    const double* x = q + i * dim;
+    double best = INFINITY, c[3];
+    int reg;
+    int64_t nn = 0, np = 0;
+    if (hint[i] >= 0) {
+      best = prim_dist2(s, hint[i], x, c, &reg);
+      ++np;
+    }
+    int32_t stack[256];
+    double bound[256];
+    int top = 0;
+    stack[top] = 0;
+    bound[top++] = 0.0;
+    while (top > 0) {
+      --top;
+      int32_t link = stack[top];
+      if (bound[top] > best) continue;
+      if (link < 0) {
+        int32_t start = (~link) >> 3, cnt = ((~link) & 7) + 1;
+        for (int32_t j = start; j < start + cnt; ++j) {
+          double d2 = prim_dist2(s, order[j], x, c, &reg);
+          ++np;
+          if (d2 < best) best = d2;
+        }
+        continue;
+      }
+      ++nn;
+      double db[2];
+      for (int ch = 0; ch < 2; ++ch) {
+        const double* lo = boxes + (int64_t)link * 4 * dim + ch * 2 * dim;
+        const double* hi = lo + dim;
+        double d2 = 0;
+        for (int a = 0; a < dim; ++a) {
+          double e = 0;
+          if (x[a] < lo[a]) e = lo[a] - x[a];
+          else if (x[a] > hi[a]) e = x[a] - hi[a];
+          d2 += e * e;
+        }
+        db[ch] = d2;
+      }
+      /* the farther child goes below the nearer one */
+      int near = db[1] < db[0] ? 1 : 0;
+      stack[top] = child[2 * link + (1 - near)];
+      bound[top++] = db[1 - near];
+      stack[top] = child[2 * link + near];
+      bound[top++] = db[near];
+    }
+    nodes[i] = (double)nn;
+    prims[i] = (double)np;
+  }
+}
+
 void orc_cache_walks(const orc_scene* s, const orc_field* g, const orc_field* f,
                      const orc_walk_params* p, int64_t n_cache, const double* x,
                      const double* nrm, const double* R0, const double* xbar, double* U,

@@ -138,6 +138,24 @@ void orc_sample_ball_source(uint64_t seed, uint32_t k, uint32_t id, uint32_t bat
                             int dim, const double* c, double R, double* y);
 double orc_grad_radius(double u);
 
+/* Query points of one walk, in the order the walk makes them (Section 3.1):
+ * the first-ball point, then every point a jump reaches, up to the query that
+ * stops the walk (d < eps or the step cap).  hint[k] is the closest primitive
+ * (original id) of query k-1, -1 for the first.  Returns the number written
+ * (at most max_q; 0 for a pointwise start inside the epsilon shell). */
+int32_t orc_walk_queries(const orc_scene* s, const orc_walk_params* p, int mode, const double* x,
+                         double R0, uint32_t id, int32_t max_q, double* q, int32_t* hint);
+
+/* Work of a nearest-first closest-point query on a given BVH (child links and
+ * FP64 child boxes stored in the parent, leaves ~((start << 3) | (count - 1))
+ * over primitives order[start..]; node 0 is the root): internal nodes expanded
+ * and primitive distances evaluated, per query point, with the hint primitive
+ * (original id, or -1) evaluated first.  A popped entry whose box is farther
+ * than the best distance so far is skipped. */
+void orc_bvh_visits(const orc_scene* s, int64_t n_nodes, const int32_t* child, const double* boxes,
+                    const int32_t* order, int64_t n_q, const double* q, const int32_t* hint,
+                    double* nodes, double* prims);
+
 /* All walks of n_cache cache points: U[i*W + j], D[i*W + j] = n_i . grad. */
 void orc_cache_walks(const orc_scene* s, const orc_field* g, const orc_field* f,
                      const orc_walk_params* p, int64_t n_cache, const double* x,

@@ -45,7 +45,8 @@ class bvc_scene_info(C.Structure):
 class bvc_walk_params(C.Structure):
     _fields_ = [("eps", C.c_double), ("max_steps", C.c_int32), ("n_walks", C.c_int32),
                 ("seed", C.c_uint64), ("batch", C.c_uint32), ("control_variate", C.c_int32),
-                ("dtype", C.c_int32), ("blocks", C.c_int32), ("g", bvc_field), ("f", bvc_field)]
+                ("dtype", C.c_int32), ("blocks", C.c_int32), ("g", bvc_field), ("f", bvc_field),
+                ("ev_begin", C.c_void_p), ("ev_end", C.c_void_p)]
 
 
 class bvc_cache_view(C.Structure):
@@ -82,6 +83,7 @@ _SIGS = {
     "bvc_scene_get_info": [_vp, _P(bvc_scene_info)],
     "bvc_scene_upload": [_vp, _vp, C.c_size_t, _vp],
     "bvc_scene_destroy": [_vp],
+    "bvc_scene_export_bvh": [_vp, _vp, _vp, _vp],
     "bvc_cache_measure": [_vp, C.c_double, C.c_int32, _P(C.c_double)],
     "bvc_sample_cache": [_vp, C.c_int64, C.c_double, C.c_int32, C.c_uint64, C.c_uint32, _vp, _vp, _vp,
                          _vp, _vp, _vp, _vp],
@@ -206,6 +208,20 @@ def bvc_scene_get_info(scene) -> bvc_scene_info:
     info = bvc_scene_info()
     _check(_L.bvc_scene_get_info(scene, C.byref(info)), "bvc_scene_get_info")
     return info
+
+
+def bvc_scene_export_bvh(scene):
+    """Host copy of the BVH topology: (child int32 [n_nodes, 2], boxes float64
+    [n_nodes, 4*dim], order int32 [n_prims])."""
+    import numpy as np
+
+    info = bvc_scene_get_info(scene)
+    child = np.empty((info.n_nodes, 2), dtype=np.int32)
+    boxes = np.empty((info.n_nodes, 4 * info.dim), dtype=np.float64)
+    order = np.empty(info.n_prims, dtype=np.int32)
+    _check(_L.bvc_scene_export_bvh(scene, child.ctypes.data, boxes.ctypes.data, order.ctypes.data),
+           "bvc_scene_export_bvh")
+    return child, boxes, order
 
 
 def bvc_scene_upload(scene, buf, stream=None):

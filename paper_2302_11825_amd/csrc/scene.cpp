@@ -559,6 +559,19 @@ int bvc_scene_get_info(bvc_scene s, bvc_scene_info* out) {
   return BVC_OK;
 }
 
+int bvc_scene_export_bvh(bvc_scene s, int32_t* child, double* boxes, int32_t* order) {
+  if (!s) return fail(BVC_EINVAL, "null scene");
+  const SceneHost& h = s->h;
+  if (child)
+    for (size_t i = 0; i < h.child.size(); ++i) {
+      child[2 * i] = h.child[i].x;
+      child[2 * i + 1] = h.child[i].y;
+    }
+  if (boxes) std::copy(h.box64.begin(), h.box64.end(), boxes);
+  if (order) std::copy(h.prim_id.begin(), h.prim_id.end(), order);
+  return BVC_OK;
+}
+
 int bvc_scene_upload(bvc_scene s, void* buf, size_t bytes, void* stream) {
   if (!s || !buf) return fail(BVC_EINVAL, "null argument");
   SceneHost& h = s->h;

@@ -467,6 +467,10 @@ int run_walks(bvc_scene s, const bvc_walk_params* p, int mode, int64_t n, WalkAr
   a.chunk = chunk_for(total, blocks);
   const bool src = p->f.kind != 0;
   const bool f32 = p->dtype == BVC_F32;
+  if (p->ev_begin) {
+    rc = check_hip(hipEventRecord((hipEvent_t)p->ev_begin, st), "walk begin event");
+    if (rc) return rc;
+  }
   if (h.dim == 2) {
     if (f32) launch_walks<float, 2>(a, mode, src, blocks, lds, st);
     else launch_walks<double, 2>(a, mode, src, blocks, lds, st);
@@ -476,6 +480,10 @@ int run_walks(bvc_scene s, const bvc_walk_params* p, int mode, int64_t n, WalkAr
   }
   rc = check_hip(hipGetLastError(), "walk launch");
   if (rc) return rc;
+  if (p->ev_end) {
+    rc = check_hip(hipEventRecord((hipEvent_t)p->ev_end, st), "walk end event");
+    if (rc) return rc;
+  }
   if (h.dim == 2) {
     if (f32) launch_finish<float, 2>(p, mode, a, st);
     else launch_finish<double, 2>(p, mode, a, st);

@@ -69,7 +69,9 @@ def c3(args):
     watch = pl.Stopwatch()
     sols = []
     ms = _time(lambda: sols.append(pl.solve(prep, batch=len(sols), with_grad=False, watch=watch)), args.steps)
-    stages = {k: float(np.mean(v)) for k, v in watch.totals_ms().items()}
+    timers = {k: float(np.mean(v)) for k, v in watch.totals_ms().items()}
+    stages = {k: v for k, v in timers.items() if not k.startswith("k_")}
+    kernels = {k: v for k, v in timers.items() if k.startswith("k_")}
     sol = sols[-1]
     idx = prep.idx_int[: prep.n_int].cpu().numpy()
     n_box = prob.extra["n_box"]
@@ -88,7 +90,8 @@ def c3(args):
            "interior_points": prep.n_int, "band_points": prep.n_band, "box_candidates": n_box,
            "slice_points": prob.extra["n_slice"], "cache_points": sol.cache.n, "walks_per_point": prob.n_walks,
            "walks": int(sol.counters[3]), "walk_steps": steps,
-           "cache_walk_steps_per_s": steps / (stages["cache_walks"] / 1e3),
+           "cache_walk_steps_per_s": steps / (kernels["k_walks_cache"] / 1e3),
+           "kernel_ms": kernels,
            "gather_pairs_per_s": pairs / (stages["gather"] / 1e3),
            "gather_tflops_u": pairs * FLOPS_3D_BOUNDARY_U / (stages["gather"] / 1e3) / 1e12,
            "stage_ms": stages, "rmse_u_sampled": rmse, "rmse_u_far": rmse_far, "rms_u_true": rms_truth,

@@ -337,6 +337,17 @@ class Stopwatch:
 
         return _Ctx()
 
+    def kernel(self, name, params: B.bvc_walk_params):
+        """Times the walk kernel of the call that takes `params` alone: the
+        library records the two events right around its launch."""
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()  # creates the events; the library records them again
+        e1.record()
+        params.ev_begin = e0.cuda_event
+        params.ev_end = e1.cuda_event
+        self.marks.append((name, e0, e1))
+
     def totals_ms(self):
         out = {}
         for name, e0, e1 in self.marks:
@@ -355,6 +366,9 @@ class _NoWatch:
     def stage(self, name):
         return self._N()
 
+    def kernel(self, name, params):
+        pass
+
 
 def solve(prep: Prepared, batch=0, with_grad=True, n_walks_band=None, records=False, watch=None) -> Solution:
     p, sc = prep.p, prep.sc
@@ -365,6 +379,7 @@ def solve(prep: Prepared, batch=0, with_grad=True, n_walks_band=None, records=Fa
     with watch.stage("sample_cache"):
         cache = sample_cache(sc, prep.n_cand, p.offset, p.sides, p.seed_cache, batch)
     wp = walk_params(p.eps, p.n_walks, p.seed_walks, prep.g, prep.f, dt, batch)
+    watch.kernel("k_walks_cache", wp)
     with watch.stage("cache_walks"):
         U, D, rec, counters = cache_walks(sc, cache, wp, dt, records)
     with watch.stage("reduce_walks"):
@@ -397,6 +412,7 @@ def solve(prep: Prepared, batch=0, with_grad=True, n_walks_band=None, records=Fa
     Wb = n_walks_band or p.n_walks
     nb = prep.n_band
     wpb = walk_params(p.eps, Wb, p.seed_walks, prep.g, prep.f, dt, batch)
+    watch.kernel("k_walks_band", wpb)
     with watch.stage("band_walks"):
         u_band, g_band, pwc = pointwise(sc, wpb, prep.x_band[:, :nb] if nb else prep.x_band[:, :0], with_grad)
     return Solution(prep.idx_int, n_int, prep.idx_band, nb, u_int, g_int, u_band, g_band, cache, uhat, dudn,
