@@ -53,6 +53,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4a", "c4b"],
                     help="c2 prints the benchmark line; the others print their own measurement lines")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes (no autotuning)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="copy this many MiB device-to-device before timing (HBM counter calibration)")
     return ap.parse_args()
@@ -123,6 +124,7 @@ def main():
     t_setup = time.time()
     prob = wl.problem_c2(grid=args.grid)
     prep = pl.Prepared(prob, dtype=args.dtype)
+    tuned = None if args.no_tune else pl.tune(prep, with_grad=True)
     torch.cuda.synchronize()
     setup_s = time.time() - t_setup
     print(f"[bench] setup {setup_s:.1f}s: candidates {prep.n_cand}, interior {prep.n_int}, band {prep.n_band}",
@@ -319,6 +321,7 @@ def main():
         "kernel_ms": {k: round(v, 4) for k, v in kernels.items()},
         "cpu_baseline": cpu,
         "setup_s": setup_s,
+        "tuned_shapes": tuned,
     }
     print(json.dumps(out))
 

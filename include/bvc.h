@@ -277,6 +277,36 @@ int bvc_gather_grad(int32_t dim, const bvc_cache_view* cache, const bvc_source_v
                     int64_t n_eval, const void* eval_x, void* u, void* grad,
                     const bvc_gather_params* params, void* stream);
 
+/* ---------------------------------------------------------------------- */
+/* Autotuning of launch shapes (no passage of the paper: a performance aid) */
+/* ---------------------------------------------------------------------- */
+/* Times the gather of this problem with 1, 2 and 4 evaluation points per
+ * thread (one warm-up and `reps` timed launches each, HIP events on the
+ * stream) and keeps the fastest for every later gather of the same class:
+ * dim, dtype, gradient or not, near field or not, floor(log2) of n_eval and
+ * of the cache size.  The choice is process-wide (guarded by a mutex) and
+ * does not change any result: each point's sum runs in the same order for
+ * every shape.  Arguments as bvc_gather_grad (grad may be NULL for u only);
+ * params->accumulate must be 0.  On return u/grad hold the gather's result
+ * and *ppt the choice.  Synchronises the stream. */
+int bvc_tune_gather(int32_t dim, const bvc_cache_view* cache, const bvc_source_view* sources,
+                    int64_t n_eval, const void* eval_x, void* u, void* grad,
+                    const bvc_gather_params* params, int32_t reps, int32_t* ppt, void* stream);
+
+/* Times the cache walks of this problem over persistent grids of 4, 8 and 16
+ * blocks per compute unit and traversal-loop exit thresholds of 0, 8, 16, 32
+ * and 48 open lanes (the default shape first; another is kept only when at
+ * least 3% faster) and keeps the choice for every later cache-walk launch of
+ * the same class (dim, walk dtype, source term or not) whose params->blocks
+ * is 0; pointwise walks keep their default shape.  Every shape gives the same
+ * walk results (a walk's random numbers depend on its id only).  Arguments as
+ * bvc_cache_walks; the outputs hold the walks' results on return.
+ * Synchronises the stream. */
+int bvc_tune_walks(bvc_scene scene, const bvc_walk_params* params, int64_t n_cache, const double* x,
+                   const double* nrm, const double* R0, const double* xbar, void* U, void* D,
+                   void* rec_exit, void* rec_w1, uint64_t* counters, int32_t reps,
+                   int32_t* blocks_per_cu, int32_t* open_lanes, void* stream);
+
 /* Adjoint of the gather for dL/du = r [n_eval]:
  * dL/da_i = sum_k r_k dG/dn(x_k,z_i), dL/db_i = -sum_k r_k G(x_k,z_i),
  * dL/ds_j = sum_k r_k G(x_k,y_j), dL/dx_k = r_k grad u(x_k) (Eq. 5-6).

@@ -102,6 +102,10 @@ _SIGS = {
                      _P(bvc_gather_params), _vp],
     "bvc_gather_grad": [C.c_int32, _P(bvc_cache_view), _P(bvc_source_view), C.c_int64, _vp, _vp, _vp,
                         _P(bvc_gather_params), _vp],
+    "bvc_tune_gather": [C.c_int32, _P(bvc_cache_view), _P(bvc_source_view), C.c_int64, _vp, _vp, _vp,
+                        _P(bvc_gather_params), C.c_int32, _P(C.c_int32), _vp],
+    "bvc_tune_walks": [_vp, _P(bvc_walk_params), C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                       C.c_int32, _P(C.c_int32), _P(C.c_int32), _vp],
     "bvc_gather_backward": [C.c_int32, _P(bvc_cache_view), _P(bvc_source_view), C.c_int64, _vp, _vp, _vp,
                             _vp, _vp, _vp, _vp],
     "bvc_basis_means": [_P(bvc_field), C.c_int32, C.c_int64, C.c_int32, C.c_int32, _vp, _vp, _vp, C.c_int32,
@@ -333,6 +337,27 @@ def bvc_gather_grad(dim, cache, sources, n_eval, eval_x, u, grad, accumulate=0, 
     gp = _gparams(accumulate, near)
     _check(_L.bvc_gather_grad(dim, C.byref(cv), C.byref(sv) if sv is not None else None, n_eval, ptr(eval_x),
                               ptr(u), ptr(grad), C.byref(gp), stream_ptr(stream)), "bvc_gather_grad")
+
+
+def bvc_tune_gather(dim, cache, sources, n_eval, eval_x, u, grad=None, reps=3, stream=None, near=None):
+    """Returns the points-per-thread the library keeps for this gather class."""
+    cv, sv = _views(cache, sources)
+    gp = _gparams(0, near)
+    out = C.c_int32()
+    _check(_L.bvc_tune_gather(dim, C.byref(cv), C.byref(sv) if sv is not None else None, n_eval, ptr(eval_x),
+                              ptr(u), ptr(grad), C.byref(gp), reps, C.byref(out), stream_ptr(stream)),
+           "bvc_tune_gather")
+    return out.value
+
+
+def bvc_tune_walks(scene, params: bvc_walk_params, n_cache, x, nrm, R0, xbar, U, D, rec_exit, rec_w1, counters,
+                   reps=2, stream=None):
+    """Returns (blocks per compute unit, open lanes) the library keeps for this walk class."""
+    bpc, lanes = C.c_int32(), C.c_int32()
+    _check(_L.bvc_tune_walks(scene, C.byref(params), n_cache, ptr(x), ptr(nrm), ptr(R0), ptr(xbar), ptr(U), ptr(D),
+                             ptr(rec_exit), ptr(rec_w1), ptr(counters), reps, C.byref(bpc), C.byref(lanes),
+                             stream_ptr(stream)), "bvc_tune_walks")
+    return bpc.value, lanes.value
 
 
 def bvc_gather_backward(dim, cache, sources, n_eval, eval_x, dL_du, dL_da, dL_db, dL_ds=None, dL_dx=None,

@@ -12,7 +12,10 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 
 #include "bvc_device.hpp"
 
@@ -66,13 +69,13 @@ struct GatherArgs {
 // Entry layout in LDS (8 values): 2D boundary {y0, y1, 2 na0, 2 na1, 2 bl, bg,
 // na0, na1}, 3D boundary {y0, y1, y2, bl, na0, na1, na2, -}; sources
 // {y.., sl, sg} (2D sl doubled like bl).
-template <typename T, int D, bool GRAD, bool NEAR = false>
+template <typename T, int D, bool GRAD, bool NEAR = false, int PPT = kPPT>
 __device__ __forceinline__ void gather_block(const GatherArgs<T>& a, int64_t block, T* ent);
 
-template <typename T, int D, bool GRAD, bool NEAR>
+template <typename T, int D, bool GRAD, bool NEAR, int PPT>
 __global__ __launch_bounds__(kGBlock) void k_gather(GatherArgs<T> a) {
   __shared__ T ent[kTile * 8];
-  gather_block<T, D, GRAD, NEAR>(a, blockIdx.x, ent);
+  gather_block<T, D, GRAD, NEAR, PPT>(a, blockIdx.x, ent);
 }
 
 // FP64 contribution of cache point i to u (and grad u) at evaluation point k,
@@ -109,25 +112,28 @@ __device__ __forceinline__ void near_pair(const GatherArgs<float>& a, int64_t k,
   }
 }
 
-// One block's share of the gather: evaluation points [block*512, block*512+512).
-template <typename T, int D, bool GRAD, bool NEAR>
+// One block's share of the gather: evaluation points
+// [block*256*PPT, (block+1)*256*PPT), PPT per thread.  The sum of each point
+// runs over the cache in the same order whatever PPT is, so every PPT gives
+// bit-identical results and PPT is a pure tuning choice.
+template <typename T, int D, bool GRAD, bool NEAR, int PPT>
 __device__ __forceinline__ void gather_block(const GatherArgs<T>& a, int64_t block, T* ent) {
   static_assert(!NEAR || sizeof(T) == 4, "the near field applies to FP32 gathers");
   const int tid = threadIdx.x;
-  const int64_t k0 = block * (kGBlock * kPPT) + tid;
-  T x[kPPT][D];
-  bool live[kPPT];
+  const int64_t k0 = block * (kGBlock * PPT) + tid;
+  T x[PPT][D];
+  bool live[PPT];
 #pragma unroll
-  for (int p = 0; p < kPPT; ++p) {
+  for (int p = 0; p < PPT; ++p) {
     const int64_t k = k0 + p * kGBlock;
     live[p] = k < a.n_eval;
 #pragma unroll
     for (int c = 0; c < D; ++c) x[p][c] = live[p] ? a.ex[c * a.n_eval + k] : T(0);
   }
-  double tu[kPPT], tg[kPPT][D];
-  T au[kPPT], ag[kPPT][D];
+  double tu[PPT], tg[PPT][D];
+  T au[PPT], ag[PPT][D];
 #pragma unroll
-  for (int p = 0; p < kPPT; ++p) {
+  for (int p = 0; p < PPT; ++p) {
     tu[p] = 0.0;
     au[p] = T(0);
 #pragma unroll
@@ -144,7 +150,7 @@ __device__ __forceinline__ void gather_block(const GatherArgs<T>& a, int64_t blo
   constexpr double kUnfold = D == 2 ? 0.5 : 1.0;
   auto fold = [&]() {
 #pragma unroll
-    for (int p = 0; p < kPPT; ++p) {
+    for (int p = 0; p < PPT; ++p) {
       tu[p] += kUnfold * (double)au[p];
       au[p] = T(0);
 #pragma unroll
@@ -189,16 +195,16 @@ __device__ __forceinline__ void gather_block(const GatherArgs<T>& a, int64_t blo
       }
     }
     __syncthreads();
-    bool hit[kPPT];
+    bool hit[PPT];
 #pragma unroll
-    for (int p = 0; p < kPPT; ++p) hit[p] = false;
+    for (int p = 0; p < PPT; ++p) hit[p] = false;
 #pragma unroll 4
     for (int j = 0; j < cnt; ++j) {
       const T* e = ent + j * 8;
       if constexpr (D == 2) {
         const T y0 = e[0], y1 = e[1], m0 = e[2], m1 = e[3], bl = e[4], bg = e[5];
 #pragma unroll
-        for (int p = 0; p < kPPT; ++p) {
+        for (int p = 0; p < PPT; ++p) {
           const T dx = y0 - x[p][0], dy = y1 - x[p][1];
           // r^2 + tiny keeps coincident points finite at no extra instruction
           const T r2 = fma(dx, dx, fma(dy, dy, tiny));
@@ -225,7 +231,7 @@ __device__ __forceinline__ void gather_block(const GatherArgs<T>& a, int64_t blo
       } else {
         const T y0 = e[0], y1 = e[1], y2 = e[2], bl = e[3], n0 = e[4], n1 = e[5], n2 = e[6];
 #pragma unroll
-        for (int p = 0; p < kPPT; ++p) {
+        for (int p = 0; p < PPT; ++p) {
           const T dx = y0 - x[p][0], dy = y1 - x[p][1], dz = y2 - x[p][2];
           const T r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, tiny)));
           T ri;
@@ -255,12 +261,12 @@ __device__ __forceinline__ void gather_block(const GatherArgs<T>& a, int64_t blo
       // test as above picks exactly the pairs left out of the FP32 sums
       bool any = false;
 #pragma unroll
-      for (int p = 0; p < kPPT; ++p) any = any || (hit[p] && live[p]);
+      for (int p = 0; p < PPT; ++p) any = any || (hit[p] && live[p]);
       if (__any(any)) {
         for (int j = 0; j < cnt; ++j) {
           const T* e = ent + j * 8;
 #pragma unroll
-          for (int p = 0; p < kPPT; ++p) {
+          for (int p = 0; p < PPT; ++p) {
             if (!(hit[p] && live[p])) continue;
             T r2;
             if constexpr (D == 2) {
@@ -302,7 +308,7 @@ __device__ __forceinline__ void gather_block(const GatherArgs<T>& a, int64_t blo
       if constexpr (D == 2) {
         const T y0 = e[0], y1 = e[1], sl = e[2], sg = e[3];
 #pragma unroll
-        for (int p = 0; p < kPPT; ++p) {
+        for (int p = 0; p < PPT; ++p) {
           const T dx = y0 - x[p][0], dy = y1 - x[p][1];
           const T r2 = fma(dx, dx, fma(dy, dy, tiny));
           au[p] = fma(sl, log_r2(r2), au[p]);
@@ -315,7 +321,7 @@ __device__ __forceinline__ void gather_block(const GatherArgs<T>& a, int64_t blo
       } else {
         const T y0 = e[0], y1 = e[1], y2 = e[2], sl = e[3];
 #pragma unroll
-        for (int p = 0; p < kPPT; ++p) {
+        for (int p = 0; p < PPT; ++p) {
           const T dx = y0 - x[p][0], dy = y1 - x[p][1], dz = y2 - x[p][2];
           const T r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, tiny)));
           const T ri = rsq(r2);
@@ -334,7 +340,7 @@ __device__ __forceinline__ void gather_block(const GatherArgs<T>& a, int64_t blo
   }
 
 #pragma unroll
-  for (int p = 0; p < kPPT; ++p) {
+  for (int p = 0; p < PPT; ++p) {
     const int64_t k = k0 + p * kGBlock;
     if (!live[p]) continue;
     const double sc = a.scale ? (double)a.scale[k] : 1.0;
@@ -584,22 +590,70 @@ int check_sources(const bvc_source_view* s, int dtype) {
 }
 
 template <typename T, int D>
-void launch_gather(const GatherArgs<T>& a, bool grad, bool near, hipStream_t st) {
-  const int blocks = (int)((a.n_eval + kGBlock * kPPT - 1) / (kGBlock * kPPT));
+void launch_gather(const GatherArgs<T>& a, bool grad, bool near, int ppt, hipStream_t st) {
+  const int blocks = (int)((a.n_eval + kGBlock * ppt - 1) / (kGBlock * ppt));
+  auto go = [&](auto kernel) { hipLaunchKernelGGL(kernel, dim3(blocks), dim3(kGBlock), 0, st, a); };
   if constexpr (sizeof(T) == 4) {
     if (near) {
-      if (grad) hipLaunchKernelGGL((k_gather<T, D, true, true>), dim3(blocks), dim3(kGBlock), 0, st, a);
-      else hipLaunchKernelGGL((k_gather<T, D, false, true>), dim3(blocks), dim3(kGBlock), 0, st, a);
+      if (grad) {
+        if (ppt == 1) go(k_gather<T, D, true, true, 1>);
+        else if (ppt == 4) go(k_gather<T, D, true, true, 4>);
+        else go(k_gather<T, D, true, true, 2>);
+      } else {
+        if (ppt == 1) go(k_gather<T, D, false, true, 1>);
+        else if (ppt == 4) go(k_gather<T, D, false, true, 4>);
+        else go(k_gather<T, D, false, true, 2>);
+      }
       return;
     }
   }
-  if (grad) hipLaunchKernelGGL((k_gather<T, D, true, false>), dim3(blocks), dim3(kGBlock), 0, st, a);
-  else hipLaunchKernelGGL((k_gather<T, D, false, false>), dim3(blocks), dim3(kGBlock), 0, st, a);
+  if (grad) {
+    if (ppt == 1) go(k_gather<T, D, true, false, 1>);
+    else if (ppt == 4) go(k_gather<T, D, true, false, 4>);
+    else go(k_gather<T, D, true, false, 2>);
+  } else {
+    if (ppt == 1) go(k_gather<T, D, false, false, 1>);
+    else if (ppt == 4) go(k_gather<T, D, false, false, 4>);
+    else go(k_gather<T, D, false, false, 2>);
+  }
+}
+
+// ---- tile-shape autotuning ------------------------------------------------
+// Evaluation points per thread (PPT) of the gather, chosen per problem class by
+// bvc_tune_gather and used by every later gather of that class in the process.
+struct GatherClass {
+  int dim, dtype, grad, near, log_eval, log_cache;
+  bool operator<(const GatherClass& o) const {
+    return std::tie(dim, dtype, grad, near, log_eval, log_cache) <
+           std::tie(o.dim, o.dtype, o.grad, o.near, o.log_eval, o.log_cache);
+  }
+};
+int ilog2(int64_t n) {
+  int l = 0;
+  while (n > 1) {
+    n >>= 1;
+    ++l;
+  }
+  return l;
+}
+std::mutex g_tune_mu;
+std::map<GatherClass, int> g_gather_ppt;
+
+GatherClass gather_class(int dim, int dtype, bool grad, bool near, int64_t n_eval, int64_t n_cache) {
+  return GatherClass{dim, dtype, grad ? 1 : 0, near ? 1 : 0, ilog2(n_eval), ilog2(n_cache)};
+}
+int tuned_ppt(const GatherClass& k) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  auto it = g_gather_ppt.find(k);
+  return it == g_gather_ppt.end() ? kPPT : it->second;
 }
 
 template <typename T>
 int gather_impl(int dim, const bvc_cache_view* c, const bvc_source_view* s, int64_t n_eval, const void* ex, void* u,
-                void* g, const void* scale, int accumulate, hipStream_t st, const bvc_gather_params* near = nullptr) {
+                void* g, const void* scale, int accumulate, hipStream_t st, const bvc_gather_params* near = nullptr,
+                int ppt = 0) {
+  if (ppt == 0)
+    ppt = tuned_ppt(gather_class(dim, sizeof(T) == 4 ? BVC_F32 : BVC_F64, g != nullptr, near != nullptr, n_eval, c->n));
   GatherArgs<T> a{};
   a.n_eval = n_eval;
   a.ex = (const T*)ex;
@@ -626,13 +680,13 @@ int gather_impl(int dim, const bvc_cache_view* c, const bvc_source_view* s, int6
     a.na = near->near_a;
     a.nb = near->near_b;
   }
-  if (dim == 2) launch_gather<T, 2>(a, g != nullptr, near != nullptr, st);
-  else launch_gather<T, 3>(a, g != nullptr, near != nullptr, st);
+  if (dim == 2) launch_gather<T, 2>(a, g != nullptr, near != nullptr, ppt, st);
+  else launch_gather<T, 3>(a, g != nullptr, near != nullptr, ppt, st);
   return check_hip(hipGetLastError(), "gather launch");
 }
 
 int gather_entry(int32_t dim, const bvc_cache_view* c, const bvc_source_view* s, int64_t n_eval, const void* ex,
-                 void* u, void* g, const bvc_gather_params* prm, void* stream) {
+                 void* u, void* g, const bvc_gather_params* prm, void* stream, int ppt = 0) {
   if (dim != 2 && dim != 3) return fail(BVC_EINVAL, "dim must be 2 or 3");
   int rc = check_view(c, dim);
   if (rc) return rc;
@@ -647,8 +701,9 @@ int gather_entry(int32_t dim, const bvc_cache_view* c, const bvc_source_view* s,
   if (prm && !(prm->near_tau >= 0.0)) return fail(BVC_EINVAL, "near_tau must be >= 0");
   if (near && (!prm->near_x || !prm->near_cx || !prm->near_cn || !prm->near_a || !prm->near_b))
     return fail(BVC_EINVAL, "near_tau > 0 needs the FP64 copies near_x, near_cx, near_cn, near_a, near_b");
-  if (c->dtype == BVC_F32) return gather_impl<float>(dim, c, s, n_eval, ex, u, g, nullptr, acc, st, near ? prm : nullptr);
-  return gather_impl<double>(dim, c, s, n_eval, ex, u, g, nullptr, acc, st);
+  if (c->dtype == BVC_F32)
+    return gather_impl<float>(dim, c, s, n_eval, ex, u, g, nullptr, acc, st, near ? prm : nullptr, ppt);
+  return gather_impl<double>(dim, c, s, n_eval, ex, u, g, nullptr, acc, st, nullptr, ppt);
 }
 
 template <typename T>
@@ -731,6 +786,46 @@ int bvc_gather_grad(int32_t dim, const bvc_cache_view* cache, const bvc_source_v
                     const void* eval_x, void* u, void* grad, const bvc_gather_params* params, void* stream) {
   if (!grad) return fail(BVC_EINVAL, "grad is null");
   return gather_entry(dim, cache, sources, n_eval, eval_x, u, grad, params, stream);
+}
+
+int bvc_tune_gather(int32_t dim, const bvc_cache_view* cache, const bvc_source_view* sources, int64_t n_eval,
+                    const void* eval_x, void* u, void* grad, const bvc_gather_params* params, int32_t reps,
+                    int32_t* ppt_out, void* stream) {
+  if (reps < 1) return fail(BVC_EINVAL, "reps must be >= 1");
+  if (!u && !grad) return fail(BVC_EINVAL, "u and grad are null");
+  if (params && params->accumulate) return fail(BVC_EINVAL, "tuning runs the gather repeatedly: accumulate must be 0");
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = check_hip(hipEventCreate(&e0), "tune event");
+  if (!rc) rc = check_hip(hipEventCreate(&e1), "tune event");
+  const int cand[3] = {1, 2, 4};
+  float best_ms = INFINITY;
+  int best = kPPT;
+  for (int ci = 0; ci < 3 && !rc; ++ci) {
+    rc = gather_entry(dim, cache, sources, n_eval, eval_x, u, grad, params, stream, cand[ci]);  // warm-up
+    if (!rc) rc = check_hip(hipEventRecord(e0, st), "tune event");
+    for (int r = 0; r < reps && !rc; ++r)
+      rc = gather_entry(dim, cache, sources, n_eval, eval_x, u, grad, params, stream, cand[ci]);
+    if (!rc) rc = check_hip(hipEventRecord(e1, st), "tune event");
+    if (!rc) rc = check_hip(hipEventSynchronize(e1), "tune sync");
+    float ms = 0;
+    if (!rc) rc = check_hip(hipEventElapsedTime(&ms, e0, e1), "tune time");
+    if (!rc && ms < best_ms) {
+      best_ms = ms;
+      best = cand[ci];
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  const bool near = params && params->near_tau > 0.0 && cache->dtype == BVC_F32 && cache->n > 0;
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_gather_ppt[gather_class(dim, cache->dtype, grad != nullptr, near, n_eval, cache->n)] = best;
+  }
+  if (ppt_out) *ppt_out = best;
+  // leave the outputs as a gather with the chosen shape writes them
+  return gather_entry(dim, cache, sources, n_eval, eval_x, u, grad, params, stream, best);
 }
 
 int bvc_gather_backward(int32_t dim, const bvc_cache_view* cache, const bvc_source_view* sources, int64_t n_eval,

@@ -14,6 +14,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <string>
 
 #include "bvc_device.hpp"
@@ -50,6 +52,7 @@ struct WalkArgs {
   int* steps;          // [total] or null
   unsigned long long* counters;
   unsigned long long chunk;  // walk ids per claim, 1..kChunkMax
+  int open_lanes;            // leave the traversal loop at this many open queries
 };
 
 // In-walk source term in the walk's precision (constants and Gaussian sums).
@@ -129,17 +132,37 @@ __host__ __device__ inline unsigned long long chunk_for(uint64_t total, int bloc
 // A walk alternates closest-point queries and sphere jumps.  Queries differ in
 // length by orders of magnitude (a point near a curved boundary touches few
 // nodes, one deep inside a near-spherical domain touches hundreds), so the
-// query is resumable: each iteration expands one BVH node for every lane whose
-// query is open, and the jump of the lanes whose query closed runs once at most
-// OpenLanes lanes of the wave are still querying, so that a long query does not
-// hold the other lanes back.  Measured on MI355X: 3D triangle meshes run best
-// with the jump phase entered at 32 open lanes (about 1.7x faster than waiting
-// for all 64); 2D polylines, whose queries are short and even, run best when
-// the wave finishes every query first.
-template <int D>
-struct OpenLanes {
-  static constexpr int value = D == 3 ? 32 : 0;
+// query is resumable: each iteration advances every open query by one step,
+// and the jump of the lanes whose query closed runs once at most `open_lanes`
+// lanes of the wave are still querying, so that a long query does not hold
+// the other lanes back.  Measured on MI355X: 3D triangle meshes run best with
+// the jump phase entered at 32 open lanes (about 1.7x faster than waiting for
+// all 64); 2D polylines, whose queries are short and even, run best when the
+// wave finishes every query first.  bvc_tune_walks can pick another threshold
+// and grid size for a problem class.
+struct WalkShape {
+  int blocks_per_cu;
+  int open_lanes;
 };
+WalkShape default_shape(int dim) { return WalkShape{8, dim == 3 ? 32 : 0}; }
+
+struct WalkClass {
+  int dim, dtype, src, mode;
+  bool operator<(const WalkClass& o) const {
+    if (dim != o.dim) return dim < o.dim;
+    if (dtype != o.dtype) return dtype < o.dtype;
+    if (src != o.src) return src < o.src;
+    return mode < o.mode;
+  }
+};
+std::mutex g_walk_mu;
+std::map<WalkClass, WalkShape> g_walk_shape;
+
+WalkShape tuned_shape(const WalkClass& k) {
+  std::lock_guard<std::mutex> lock(g_walk_mu);
+  auto it = g_walk_shape.find(k);
+  return it == g_walk_shape.end() ? default_shape(k.dim) : it->second;
+}
 
 template <typename T, int D, bool SRC, int MODE>
 __global__ __launch_bounds__(kBlock) void k_walks(WalkArgs a) {
@@ -282,7 +305,7 @@ __global__ __launch_bounds__(kBlock) void k_walks(WalkArgs a) {
     // ---- expand one node per open query until few queries remain open
     while (true) {
       if (active && query_open(qs)) query_step<T, D>(S, p, qs, stk, stride);
-      if (__popcll(__ballot(active && query_open(qs))) <= OpenLanes<D>::value) break;
+      if (__popcll(__ballot(active && query_open(qs))) <= a.open_lanes) break;
     }
     // ---- lanes whose query closed: stop in the shell, or jump next
     if (active && !jump && !query_open(qs)) {
@@ -446,7 +469,8 @@ void launch_finish(const bvc_walk_params* p, int mode, const WalkArgs& a, hipStr
 
 size_t stack_bytes(const SceneHost& h) { return (size_t)(h.depth + 1) * kBlock * sizeof(uint32_t); }
 
-int run_walks(bvc_scene s, const bvc_walk_params* p, int mode, int64_t n, WalkArgs& a, hipStream_t st) {
+int run_walks(bvc_scene s, const bvc_walk_params* p, int mode, int64_t n, WalkArgs& a, hipStream_t st,
+              const WalkShape* force = nullptr) {
   const SceneHost& h = s->h;
   const uint64_t total = (uint64_t)n * (uint64_t)p->n_walks;
   a.S = h.view();
@@ -460,7 +484,9 @@ int run_walks(bvc_scene s, const bvc_walk_params* p, int mode, int64_t n, WalkAr
   a.n_pts = n;
   int rc = zero_async(a.counters, 4 * sizeof(unsigned long long), st);
   if (rc || total == 0) return rc;
-  int blocks = p->blocks > 0 ? p->blocks : num_cus() * 8;
+  const WalkShape shape = force ? *force : tuned_shape(WalkClass{h.dim, p->dtype, p->f.kind != 0 ? 1 : 0, mode});
+  a.open_lanes = shape.open_lanes;
+  int blocks = p->blocks > 0 ? p->blocks : num_cus() * shape.blocks_per_cu;
   const int64_t needed = (int64_t)((total + kBlock - 1) / kBlock);
   blocks = (int)std::max<int64_t>(1, std::min<int64_t>(blocks, needed));
   const size_t lds = stack_bytes(h);
@@ -720,16 +746,9 @@ int launch_batch_walks(const BatchDev& batch, int max_depth, int blocks, hipStre
 }
 
 namespace {
-}  // namespace
-}  // namespace bvc
-
-using namespace bvc;
-
-extern "C" {
-
-int bvc_cache_walks(bvc_scene s, const bvc_walk_params* p, int64_t n_cache, const double* x, const double* nrm,
-                    const double* R0, const double* xbar, void* U, void* D, void* rec_exit, void* rec_w1,
-                    int32_t* rec_steps, uint64_t* counters, void* stream) {
+int cache_walks_entry(bvc_scene s, const bvc_walk_params* p, int64_t n_cache, const double* x, const double* nrm,
+                      const double* R0, const double* xbar, void* U, void* D, void* rec_exit, void* rec_w1,
+                      int32_t* rec_steps, uint64_t* counters, void* stream, const WalkShape* force) {
   int rc = check_scene(s);
   if (rc) return rc;
   rc = check_walk_params(p, s->h.dim);
@@ -750,7 +769,80 @@ int bvc_cache_walks(bvc_scene s, const bvc_walk_params* p, int64_t n_cache, cons
   a.w1 = rec_w1;
   a.steps = rec_steps;
   a.counters = (unsigned long long*)counters;
-  return run_walks(s, p, 0, n_cache, a, (hipStream_t)stream);
+  return run_walks(s, p, 0, n_cache, a, (hipStream_t)stream, force);
+}
+}  // namespace
+}  // namespace bvc
+
+using namespace bvc;
+
+extern "C" {
+
+int bvc_cache_walks(bvc_scene s, const bvc_walk_params* p, int64_t n_cache, const double* x, const double* nrm,
+                    const double* R0, const double* xbar, void* U, void* D, void* rec_exit, void* rec_w1,
+                    int32_t* rec_steps, uint64_t* counters, void* stream) {
+  return cache_walks_entry(s, p, n_cache, x, nrm, R0, xbar, U, D, rec_exit, rec_w1, rec_steps, counters, stream,
+                           nullptr);
+}
+
+int bvc_tune_walks(bvc_scene s, const bvc_walk_params* p, int64_t n_cache, const double* x, const double* nrm,
+                   const double* R0, const double* xbar, void* U, void* D, void* rec_exit, void* rec_w1,
+                   uint64_t* counters, int32_t reps, int32_t* blocks_per_cu, int32_t* open_lanes, void* stream) {
+  int rc = check_scene(s);
+  if (rc) return rc;
+  rc = check_walk_params(p, s->h.dim);
+  if (rc) return rc;
+  if (reps < 1) return fail(BVC_EINVAL, "reps must be >= 1");
+  bvc_walk_params q = *p;
+  q.blocks = 0;
+  q.ev_begin = nullptr;
+  q.ev_end = nullptr;
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  rc = check_hip(hipEventCreate(&e0), "tune event");
+  if (!rc) rc = check_hip(hipEventCreate(&e1), "tune event");
+  // the default shape first: another is kept only when it is at least 3%
+  // faster, so that timing noise does not move the choice
+  const WalkShape def = default_shape(s->h.dim);
+  WalkShape cand[16];
+  int nc = 0;
+  cand[nc++] = def;
+  const int bpc[3] = {4, 8, 16};
+  const int lanes[5] = {0, 8, 16, 32, 48};
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 5; ++j)
+      if (bpc[i] != def.blocks_per_cu || lanes[j] != def.open_lanes) cand[nc++] = WalkShape{bpc[i], lanes[j]};
+  WalkShape best = def;
+  float best_ms = INFINITY, def_ms = INFINITY;
+  for (int c = 0; c < nc && !rc; ++c) {
+    const WalkShape sh = cand[c];
+    rc = cache_walks_entry(s, &q, n_cache, x, nrm, R0, xbar, U, D, rec_exit, rec_w1, nullptr, counters, stream,
+                           &sh);  // warm-up
+    if (!rc) rc = check_hip(hipEventRecord(e0, st), "tune event");
+    for (int r = 0; r < reps && !rc; ++r)
+      rc = cache_walks_entry(s, &q, n_cache, x, nrm, R0, xbar, U, D, rec_exit, rec_w1, nullptr, counters, stream,
+                             &sh);
+    if (!rc) rc = check_hip(hipEventRecord(e1, st), "tune event");
+    if (!rc) rc = check_hip(hipEventSynchronize(e1), "tune sync");
+    float ms = 0;
+    if (!rc) rc = check_hip(hipEventElapsedTime(&ms, e0, e1), "tune time");
+    if (rc) break;
+    if (c == 0) def_ms = ms;
+    if (ms < best_ms && (c == 0 || ms < 0.97f * def_ms)) {
+      best_ms = ms;
+      best = sh;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  {
+    std::lock_guard<std::mutex> lock(g_walk_mu);
+    g_walk_shape[WalkClass{s->h.dim, p->dtype, p->f.kind != 0 ? 1 : 0, 0}] = best;
+  }
+  if (blocks_per_cu) *blocks_per_cu = best.blocks_per_cu;
+  if (open_lanes) *open_lanes = best.open_lanes;
+  return BVC_OK;
 }
 
 size_t bvc_pointwise_workspace_bytes(int32_t dim, int64_t n, int32_t W, int32_t dtype, int32_t with_grad) {

@@ -52,17 +52,19 @@ def run(args):
     {"c3": c3, "c4a": c4a, "c4b": c4b}[args.workload](args)
 
 
-def _c3_setup():
+def _c3_setup(args):
     prob = wl.problem_c3()
     t = time.time()
     prep = pl.Prepared(prob, dtype="f32")
+    tuned = None if getattr(args, "no_tune", False) else pl.tune(prep, with_grad=False, reps=1)
     torch.cuda.synchronize()
-    _log(f"c3 setup {time.time() - t:.1f}s candidates {prep.n_cand} interior {prep.n_int} band {prep.n_band}")
+    _log(f"c3 setup {time.time() - t:.1f}s candidates {prep.n_cand} interior {prep.n_int} band {prep.n_band} "
+         f"tuned {tuned}")
     return prob, prep
 
 
 def c3(args):
-    prob, prep = _c3_setup()
+    prob, prep = _c3_setup(args)
     for w in range(args.warmup):
         pl.solve(prep, batch=100 + w, with_grad=False)
     torch.cuda.synchronize()
@@ -100,7 +102,7 @@ def c3(args):
 
 
 def c4a(args):
-    prob, prep = _c3_setup()
+    prob, prep = _c3_setup(args)
     sc = prep.sc
     cache = pl.sample_cache(sc, prep.n_cand, prob.offset, prob.sides, prob.seed_cache, 0)
     W = prob.n_walks

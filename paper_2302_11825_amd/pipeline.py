@@ -370,20 +370,11 @@ class _NoWatch:
         pass
 
 
-def solve(prep: Prepared, batch=0, with_grad=True, n_walks_band=None, records=False, watch=None) -> Solution:
-    p, sc = prep.p, prep.sc
-    dt = prep.dtype
-    T = DT[dt]
-    d = sc.dim
-    watch = watch or _NoWatch()
-    with watch.stage("sample_cache"):
-        cache = sample_cache(sc, prep.n_cand, p.offset, p.sides, p.seed_cache, batch)
-    wp = walk_params(p.eps, p.n_walks, p.seed_walks, prep.g, prep.f, dt, batch)
-    watch.kernel("k_walks_cache", wp)
-    with watch.stage("cache_walks"):
-        U, D, rec, counters = cache_walks(sc, cache, wp, dt, records)
-    with watch.stage("reduce_walks"):
-        uhat, dudn, a, b = reduce_walks(cache, p.n_walks, U, D, dt)
+def _gather_views(prep: Prepared, cache: Cache, a, b, batch, watch):
+    """Cache view (positions and normals in the gather dtype, a, b) and the
+    source view (jittered source samples, Eq. 4) of one solve."""
+    p, sc, dt = prep.p, prep.sc, prep.dtype
+    T, d = DT[dt], sc.dim
     if T != torch.float64:
         cx = take(cache.x, None, cache.n, d, cache.n, T)
         cn = take(cache.nrm, None, cache.n, d, cache.n, T)
@@ -401,6 +392,49 @@ def solve(prep: Prepared, batch=0, with_grad=True, n_walks_band=None, records=Fa
             else:
                 y, s = y64, s64
         sview = dict(n=M, dtype=CODE[dt], y=y, s=s)
+    return cview, sview
+
+
+def tune(prep: Prepared, with_grad=True, reps=3) -> dict:
+    """Picks the launch shapes of this problem's walks and gather with the
+    library's tuners (bvc_tune_walks, bvc_tune_gather) on one solve's real
+    inputs; later solves of the same problem class use them.  Results do not
+    depend on the shapes."""
+    p, sc, dt = prep.p, prep.sc, prep.dtype
+    T, d = DT[dt], sc.dim
+    cache = sample_cache(sc, prep.n_cand, p.offset, p.sides, p.seed_cache, 0)
+    wp = walk_params(p.eps, p.n_walks, p.seed_walks, prep.g, prep.f, dt, 0)
+    n, W = cache.n, p.n_walks
+    U = torch.empty(max(n * W, 1), dtype=T, device=sc.device)
+    D = torch.empty_like(U)
+    ex = torch.empty(d, max(n * W, 1), dtype=T, device=sc.device)
+    w1 = torch.empty_like(U)
+    counters = torch.zeros(4, dtype=torch.int64, device=sc.device)
+    bpc, lanes = B.bvc_tune_walks(sc.h, wp, n, cache.x, cache.nrm, cache.R0, cache.xbar, U, D, ex, w1, counters,
+                                  reps)
+    _, _, a, b = reduce_walks(cache, W, U, D, dt)
+    cview, sview = _gather_views(prep, cache, a, b, 0, _NoWatch())
+    u = torch.empty(max(prep.n_int, 1), dtype=T, device=sc.device)
+    g = torch.empty(d, max(prep.n_int, 1), dtype=T, device=sc.device) if with_grad else None
+    ppt = B.bvc_tune_gather(d, cview, sview, prep.n_int, prep.x_int, u, g, reps) if prep.n_int else 0
+    return dict(walk_blocks_per_cu=bpc, walk_open_lanes=lanes, gather_points_per_thread=ppt)
+
+
+def solve(prep: Prepared, batch=0, with_grad=True, n_walks_band=None, records=False, watch=None) -> Solution:
+    p, sc = prep.p, prep.sc
+    dt = prep.dtype
+    T = DT[dt]
+    d = sc.dim
+    watch = watch or _NoWatch()
+    with watch.stage("sample_cache"):
+        cache = sample_cache(sc, prep.n_cand, p.offset, p.sides, p.seed_cache, batch)
+    wp = walk_params(p.eps, p.n_walks, p.seed_walks, prep.g, prep.f, dt, batch)
+    watch.kernel("k_walks_cache", wp)
+    with watch.stage("cache_walks"):
+        U, D, rec, counters = cache_walks(sc, cache, wp, dt, records)
+    with watch.stage("reduce_walks"):
+        uhat, dudn, a, b = reduce_walks(cache, p.n_walks, U, D, dt)
+    cview, sview = _gather_views(prep, cache, a, b, batch, watch)
     n_int = prep.n_int
     u_int = torch.empty(max(n_int, 1), dtype=T, device=sc.device)
     g_int = torch.empty(d, max(n_int, 1), dtype=T, device=sc.device) if with_grad else None
