@@ -531,6 +531,189 @@ __global__ void k_basis_means(FieldDev F, int nb, int64_t n_cache, int W, const 
   Fo[i * nb + m] = sf / W;
 }
 
+// Basis means by recurrence chains: one thread per (cache point, chain), and
+// a chain's basis values come out of one recurrence per walk.  Sums run
+// without the basis normalisation, which multiplies the means at the end.
+//
+// Real solid harmonics of degree <= L (L <= kMaxChainL): chain 0 is order
+// m = 0, chain 2m-1 the cosine and chain 2m the sine part of order m; its
+// values are l = m..L, Q_l^m(z, r^2) from the three-term recurrence times
+// Re or Im (x + i y)^m.
+constexpr int kMaxChainL = 8;
+
+__device__ __forceinline__ void sh_chain_values(int m, int part, int L, double dfact, const double* x,
+                                                double* v) {
+  double az = 1.0;
+  if (m > 0) {
+    double cm = 1.0, sm = 0.0;
+    for (int i = 0; i < m; ++i) {
+      const double c2 = cm * x[0] - sm * x[1];
+      sm = cm * x[1] + sm * x[0];
+      cm = c2;
+    }
+    az = part ? sm : cm;
+  }
+  const double r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+  double q1 = 0.0, q2 = 0.0;
+  // guarded rather than broken off, so that every index is a compile-time
+  // constant and the arrays stay in registers
+#pragma unroll
+  for (int k = 0; k <= kMaxChainL; ++k) {
+    double q;
+    if (k == 0) q = dfact;
+    else if (k == 1) q = (2 * m + 1) * x[2] * dfact;
+    else q = ((2 * (m + k) - 1) * x[2] * q1 - (2 * m + k - 1) * r2 * q2) * (1.0 / k);
+    q2 = q1;
+    q1 = q;
+    v[k] = k <= L - m ? q * az : 0.0;
+  }
+}
+
+template <typename T>
+__global__ void k_basis_means_sh(int L, int nb, int64_t n_cache, int W, const T* ex, const T* w1,
+                                 const double* xbar, int cv, double* E, double* Fo) {
+  const int chains = 2 * L + 1;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_cache * chains) return;
+  const int64_t i = t / chains;
+  const int c = (int)(t % chains);
+  const int m = (c + 1) / 2, part = (c > 0 && c % 2 == 0) ? 1 : 0;
+  const int n = L - m + 1;
+  double dfact = 1.0;  // (2m - 1)!!
+  for (int k = 1; k <= m; ++k) dfact *= (2 * k - 1);
+  double base[kMaxChainL + 1], se[kMaxChainL + 1], sf[kMaxChainL + 1], v[kMaxChainL + 1];
+#pragma unroll
+  for (int k = 0; k <= kMaxChainL; ++k) base[k] = se[k] = sf[k] = v[k] = 0.0;
+  if (cv) {
+    const double xb[3] = {xbar[i], xbar[n_cache + i], xbar[2 * n_cache + i]};
+    sh_chain_values(m, part, L, dfact, xb, base);
+  }
+  const int64_t total = n_cache * (int64_t)W;
+  for (int j = 0; j < W; ++j) {
+    const int64_t id = i * W + j;
+    const double q[3] = {(double)ex[id], (double)ex[total + id], (double)ex[2 * total + id]};
+    sh_chain_values(m, part, L, dfact, q, v);
+    const double w = (double)w1[id];
+#pragma unroll
+    for (int k = 0; k <= kMaxChainL; ++k) {
+      se[k] += v[k];
+      sf[k] += w * (v[k] - base[k]);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k <= kMaxChainL; ++k) {
+    if (k >= n) continue;
+    const int l = m + k;
+    double ratio = 1.0;  // (l-m)!/(l+m)!
+    for (int r = l - m + 1; r <= l + m; ++r) ratio /= r;
+    double nrm = sqrt((2 * l + 1) / (4.0 * kPi) * ratio);
+    if (m > 0) nrm *= 1.4142135623730950488;
+    const int idx = part ? l * l + l - m : l * l + l + m;
+    E[i * nb + idx] = nrm * se[k] / W;
+    Fo[i * nb + idx] = nrm * sf[k] / W;
+  }
+}
+
+// Fourier basis in the angle about a centre (2D): basis 0 is 1, basis 2j-1
+// cos(j theta), basis 2j sin(j theta).  Chunk c takes frequencies 8c+1..8c+8
+// (and basis 0 in chunk 0): the first frequency by powering, then rotations
+// by theta.
+constexpr int kFourierChunk = 8;
+
+// cos and sin of theta from the unit direction to x, and of j0 theta as
+// (cos theta + i sin theta)^j0 by binary powering (no transcendental).
+__device__ __forceinline__ void fourier_start(int j0, double cx, double cy, const double* x, double& c1,
+                                              double& s1, double& c, double& s) {
+  const double dx = x[0] - cx, dy = x[1] - cy;
+  const double r2 = dx * dx + dy * dy;
+  if (r2 > 0.0) {
+    const double ri = 1.0 / sqrt(r2);
+    c1 = dx * ri;
+    s1 = dy * ri;
+  } else {
+    c1 = 1.0;  // atan2(0, 0) = 0
+    s1 = 0.0;
+  }
+  double pc = c1, ps = s1;
+  c = 1.0;
+  s = 0.0;
+  for (int e = j0; e > 0; e >>= 1) {
+    if (e & 1) {
+      const double t = c * pc - s * ps;
+      s = s * pc + c * ps;
+      c = t;
+    }
+    const double t = pc * pc - ps * ps;
+    ps = 2.0 * pc * ps;
+    pc = t;
+  }
+}
+
+template <typename T>
+__global__ void k_basis_means_fourier(int nb, double cx, double cy, int64_t n_cache, int W, const T* ex,
+                                      const T* w1, const double* xbar, int cv, double* E, double* Fo) {
+  const int chunks = std::max(1, (nb / 2 + kFourierChunk - 1) / kFourierChunk);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_cache * (int64_t)chunks) return;
+  const int64_t i = t / chunks;
+  const int ch = (int)(t % chunks);
+  const int j0 = ch * kFourierChunk + 1;
+  double bc[kFourierChunk], bs[kFourierChunk];
+  double ec[kFourierChunk], es[kFourierChunk], fc[kFourierChunk], fs[kFourierChunk];
+#pragma unroll
+  for (int k = 0; k < kFourierChunk; ++k) bc[k] = bs[k] = ec[k] = es[k] = fc[k] = fs[k] = 0.0;
+  if (cv) {
+    const double xb[2] = {xbar[i], xbar[n_cache + i]};
+    double c1, s1, c, s;
+    fourier_start(j0, cx, cy, xb, c1, s1, c, s);
+#pragma unroll
+    for (int k = 0; k < kFourierChunk; ++k) {
+      bc[k] = c;
+      bs[k] = s;
+      const double c2 = c * c1 - s * s1;
+      s = s * c1 + c * s1;
+      c = c2;
+    }
+  }
+  double e0 = 0.0, f0 = 0.0;
+  const int64_t total = n_cache * (int64_t)W;
+  for (int j = 0; j < W; ++j) {
+    const int64_t id = i * W + j;
+    const double q[2] = {(double)ex[id], (double)ex[total + id]};
+    const double w = (double)w1[id];
+    e0 += 1.0;
+    f0 += w * (1.0 - (cv ? 1.0 : 0.0));
+    double c1, s1, c, s;
+    fourier_start(j0, cx, cy, q, c1, s1, c, s);
+#pragma unroll
+    for (int k = 0; k < kFourierChunk; ++k) {
+      ec[k] += c;
+      es[k] += s;
+      fc[k] += w * (c - bc[k]);
+      fs[k] += w * (s - bs[k]);
+      const double c2 = c * c1 - s * s1;
+      s = s * c1 + c * s1;
+      c = c2;
+    }
+  }
+  if (ch == 0) {
+    E[i * nb] = e0 / W;
+    Fo[i * nb] = f0 / W;
+  }
+#pragma unroll
+  for (int k = 0; k < kFourierChunk; ++k) {
+    const int jj = j0 + k;
+    if (2 * jj - 1 < nb) {
+      E[i * nb + 2 * jj - 1] = ec[k] / W;
+      Fo[i * nb + 2 * jj - 1] = fc[k] / W;
+    }
+    if (2 * jj < nb) {
+      E[i * nb + 2 * jj] = es[k] / W;
+      Fo[i * nb + 2 * jj] = fs[k] / W;
+    }
+  }
+}
+
 // dL/dtheta_m = sum_i w_i (E_im gA_i + F_im gB_i): partial sums over chunks
 // of cache points, then a fixed-order sum of the chunks.
 constexpr int kChunk = 1024;
@@ -870,18 +1053,34 @@ int bvc_basis_means(const bvc_field* basis, int32_t dim, int64_t n_cache, int32_
   if (n_cache == 0) return BVC_OK;
   if (!rec_exit || !rec_w1 || !E || !F || (cv && !xbar)) return fail(BVC_EINVAL, "null argument");
   hipStream_t st = (hipStream_t)stream;
-  const int64_t total = n_cache * nb;
-  const int blocks = (int)((total + 255) / 256);
-  FieldDev Fd = to_dev(*basis);
-  if (dim == 2) {
-    if (dtype == BVC_F32)
-      hipLaunchKernelGGL((k_basis_means<float, 2>), dim3(blocks), dim3(256), 0, st, Fd, nb, n_cache, W,
+  const bool f32 = dtype == BVC_F32;
+  if (basis->kind == 6) {
+    const int chunks = std::max(1, (nb / 2 + kFourierChunk - 1) / kFourierChunk);
+    const int64_t threads = n_cache * (int64_t)chunks;
+    const int blocks = (int)((threads + 255) / 256);
+    const double cx = basis->param[0], cy = basis->param[1];
+    if (f32)
+      hipLaunchKernelGGL((k_basis_means_fourier<float>), dim3(blocks), dim3(256), 0, st, nb, cx, cy, n_cache, W,
                          (const float*)rec_exit, (const float*)rec_w1, xbar, cv, E, F);
     else
-      hipLaunchKernelGGL((k_basis_means<double, 2>), dim3(blocks), dim3(256), 0, st, Fd, nb, n_cache, W,
+      hipLaunchKernelGGL((k_basis_means_fourier<double>), dim3(blocks), dim3(256), 0, st, nb, cx, cy, n_cache, W,
+                         (const double*)rec_exit, (const double*)rec_w1, xbar, cv, E, F);
+  } else if ((int)basis->param[0] <= kMaxChainL) {
+    const int L = (int)basis->param[0];
+    const int64_t threads = n_cache * (int64_t)(2 * L + 1);
+    const int blocks = (int)((threads + 255) / 256);
+    if (f32)
+      hipLaunchKernelGGL((k_basis_means_sh<float>), dim3(blocks), dim3(256), 0, st, L, nb, n_cache, W,
+                         (const float*)rec_exit, (const float*)rec_w1, xbar, cv, E, F);
+    else
+      hipLaunchKernelGGL((k_basis_means_sh<double>), dim3(blocks), dim3(256), 0, st, L, nb, n_cache, W,
                          (const double*)rec_exit, (const double*)rec_w1, xbar, cv, E, F);
   } else {
-    if (dtype == BVC_F32)
+    // degrees beyond the chain kernel: one thread per (cache point, basis)
+    const int64_t total = n_cache * nb;
+    const int blocks = (int)((total + 255) / 256);
+    FieldDev Fd = to_dev(*basis);
+    if (f32)
       hipLaunchKernelGGL((k_basis_means<float, 3>), dim3(blocks), dim3(256), 0, st, Fd, nb, n_cache, W,
                          (const float*)rec_exit, (const float*)rec_w1, xbar, cv, E, F);
     else

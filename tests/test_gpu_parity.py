@@ -312,7 +312,7 @@ def test_gather_backward_fp64(B, orc, dim):
     assert np.allclose(to_np_aos(dx), rdx, rtol=1e-9, atol=1e-11 * np.abs(rdx).max())
 
 
-@pytest.mark.parametrize("case", ["c5", "sphere"])
+@pytest.mark.parametrize("case", ["c5", "sphere", "fourier_1", "fourier_5", "sphere_L10"])
 def test_basis_means_fp64(B, orc, case):
     _bvc, pl = B
     say(f"basis means {case}")
@@ -321,6 +321,18 @@ def test_basis_means_fp64(B, orc, case):
         scene, eps, l, sides, n, W = p["scene"], p["eps"], p["offset"], 2, 3000, 8
         basis = wl.fourier_2d(np.zeros(256))
         g = wl.fourier_2d(p["theta_true"])
+    elif case.startswith("fourier_"):
+        # the smallest bases: the constant alone, and a ragged last chunk
+        nb = int(case.split("_")[1])
+        p = wl.problem_c5()
+        scene, eps, l, sides, n, W = p["scene"], p["eps"], p["offset"], 2, 1500, 8
+        basis = wl.fourier_2d(np.zeros(nb))
+        g = wl.fourier_2d(np.random.default_rng(9).normal(0, 1, nb))
+    elif case == "sphere_L10":
+        # beyond the chain kernel's degree: one thread per (cache point, basis)
+        scene, eps, l, sides, n, W = wl.displaced_icosphere(2, 3), 4e-3, 2e-2, 1, 200, 4
+        basis = wl.solid_harmonics_3d(np.zeros(121), 10)
+        g = wl.solid_harmonics_3d(np.random.default_rng(5).normal(0, 1, 121), 10)
     else:
         scene, eps, l, sides, n, W = wl.displaced_icosphere(2, 3), 4e-3, 2e-2, 1, 300, 8
         basis = wl.solid_harmonics_3d(np.zeros(81), 8)
