@@ -200,10 +200,14 @@ def main():
     pairs_s = prep.n_int * n_src
     flops = pairs_b * FLOPS_2D_BOUNDARY_UG + pairs_s * FLOPS_2D_SOURCE_UG
     achieved = flops / (gather_ms / 1e3) / 1e12
+    # the gather's template names its evaluation points per thread: the tuned
+    # value, else the library's default of 2
+    ppt = tuned["gather_points_per_thread"] if tuned else 2
+    gather_kernel = f"k_gather<float,2,true,false,{ppt}>"
     roofline_gather = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                        "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                       "traffic": measured_traffic("k_gather<float,2,true>", GATHER_SOURCES),
-                       "kernel": "k_gather<float,2,true>", "pairs_per_launch": pairs_b + pairs_s,
+                       "traffic": measured_traffic(gather_kernel, GATHER_SOURCES),
+                       "kernel": gather_kernel, "pairs_per_launch": pairs_b + pairs_s,
                        "flops_per_pair": {"boundary": FLOPS_2D_BOUNDARY_UG, "source": FLOPS_2D_SOURCE_UG},
                        "avg_launch_ms": round(gather_ms, 4),
                        "pairs_per_s": (pairs_b + pairs_s) / (gather_ms / 1e3)}
