@@ -101,6 +101,17 @@ def lib():
                                        C.c_uint32, C.c_int32, _dp, _ip]
         L.orc_walk_queries.restype = C.c_int32
         L.orc_bvh_visits.argtypes = [C.c_void_p, C.c_int64, _ip, _dp, _ip, C.c_int64, _dp, _ip, _dp, _dp]
+        L.orc_clamp_radius.argtypes = [C.c_int, C.c_double]
+        L.orc_clamp_radius.restype = C.c_double
+        L.orc_gather_clamped.argtypes = [C.c_int, C.c_int64, _dp, C.c_int64, _dp, _dp, _dp, _dp,
+                                         C.c_int64, _dp, _dp, C.c_double, _dp]
+        L.orc_offset_hits.argtypes = [C.c_void_p, C.c_double, C.c_int, _dp, _dp, C.c_double, C.c_int32,
+                                      _dp, _dp, _dp]
+        L.orc_offset_hits.restype = C.c_int32
+        L.orc_ray_direction.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int, _dp]
+        L.orc_clamp_correction.argtypes = [C.c_void_p, C.POINTER(_Field), C.POINTER(_Field),
+                                           C.POINTER(_WalkParams), C.c_double, C.c_int, C.c_double, C.c_int32,
+                                           C.c_int32, C.POINTER(_Field), C.c_int64, _dp, _dp, _lp]
         _lib = L
     return _lib
 
@@ -448,3 +459,64 @@ def sample_ball_source(seed, k, id_, batch, tag, dim, c, R):
 
 def grad_radius(u):
     return lib().orc_grad_radius(float(u))
+
+
+# --- Clamped double-layer kernel and its bias correction (Section 3.4) ------
+def clamp_radius(dim, c):
+    """Distance beyond which |dG/dn| cannot exceed c."""
+    return lib().orc_clamp_radius(int(dim), float(c))
+
+
+def gather_clamped(dim, ex, cy, cn, a, b, c, sy=None, sw=None):
+    """u with dG/dn clamped to [-c, c] in the boundary term (Eq. 9)."""
+    ex = _f64(ex).reshape(-1, dim)
+    cy = _f64(cy).reshape(-1, dim)
+    cn = _f64(cn).reshape(-1, dim)
+    a = _f64(a)
+    b = _f64(b)
+    if sy is None:
+        sy = np.zeros((0, dim))
+        sw = np.zeros(0)
+    sy = _f64(sy).reshape(-1, dim)
+    sw = _f64(sw)
+    u = np.zeros(ex.shape[0])
+    lib().orc_gather_clamped(dim, ex.shape[0], _d(ex), cy.shape[0], _d(cy), _d(cn), _d(a), _d(b), sy.shape[0],
+                             _d(sy), _d(sw), float(c), _d(u))
+    return u
+
+
+def offset_hits(scene: Scene, l, sides, x, w, t_max, max_hits=64):
+    """Crossings of the ray x + t w with the offset boundary, nearest first:
+    (count, t, z, n) with at most max_hits rows."""
+    d = scene.dim
+    x = _f64(x).reshape(d)
+    w = _f64(w).reshape(d)
+    t = np.zeros(max_hits)
+    z = np.zeros((max_hits, d))
+    n = np.zeros((max_hits, d))
+    cnt = lib().orc_offset_hits(scene.h, float(l), int(sides), _d(x), _d(w), float(t_max), int(max_hits), _d(t),
+                                _d(z), _d(n))
+    m = min(cnt, max_hits)
+    return cnt, t[:m], z[:m], n[:m]
+
+
+def ray_direction(seed, j, k, batch, dim):
+    w = np.zeros(dim)
+    lib().orc_ray_direction(int(seed), int(j), int(k), int(batch), int(dim), _d(w))
+    return w
+
+
+def clamp_correction(scene: Scene, g, f, params, l, sides, c, n_rays, max_hits, x, u_at_hits=None):
+    """Second integral of Eq. 8 at the points x (inside the region the cache
+    bounds): returns (corr, stats) with stats = (crossings, walks, rays with
+    more than max_hits crossings)."""
+    x = _f64(x).reshape(-1, scene.dim)
+    n = x.shape[0]
+    corr = np.zeros(n)
+    st = np.zeros(3, np.int64)
+    G, Fv = _field(g), _field(f)
+    Uh = _field(u_at_hits) if u_at_hits is not None else None
+    lib().orc_clamp_correction(scene.h, C.byref(G), C.byref(Fv), C.byref(params), float(l), int(sides), float(c),
+                               int(n_rays), int(max_hits), C.byref(Uh) if Uh is not None else None, n, _d(x),
+                               _d(corr), st.ctypes.data_as(_lp))
+    return corr, st

@@ -1319,6 +1319,297 @@ void orc_basis_means(const orc_field* basis, int dim, int64_t n_cache, int32_t W
   }
 }
 
+/* ======================================================================== */
+/* Clamped double-layer kernel and its bias correction (Section 3.4,         */
+/* Eqs. 8-9)                                                                 */
+/* ======================================================================== */
+/* |dG/dn(x, z)| = |n . (z - x)| / (|S| r^dim) <= 1 / (|S| r^(dim-1)), so no
+ * boundary point farther than this radius has |dG/dn| above c. */
+double orc_clamp_radius(int dim, double c) {
+  if (!(c > 0)) return INFINITY;
+  return dim == 2 ? 1.0 / (2 * ORC_PI * c) : sqrt(1.0 / (4 * ORC_PI * c));
+}
+
+/* Eq. 3 with dG/dn replaced by its clamp to [-c, c] (Eq. 9): the first
+ * integral of Eq. 8 estimated with the cache samples, plus the single-layer
+ * and source terms unchanged. */
+void orc_gather_clamped(int dim, int64_t K, const double* ex, int64_t N, const double* cy,
+                        const double* cn, const double* a, const double* b, int64_t M,
+                        const double* sy, const double* sw, double c, double* u) {
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t k = 0; k < K; ++k) {
+    const double* x = ex + k * dim;
+    double uk = 0;
+    for (int64_t i = 0; i < N; ++i) {
+      double G, dGdn;
+      orc_greens(dim, x, cy + i * dim, cn + i * dim, &G, NULL, &dGdn, NULL);
+      double kc = dGdn > c ? c : (dGdn < -c ? -c : dGdn);
+      uk += kc * a[i] - G * b[i];
+    }
+    for (int64_t j = 0; j < M; ++j) {
+      double G;
+      orc_greens(dim, x, sy + j * dim, NULL, &G, NULL, NULL, NULL);
+      uk += G * sw[j];
+    }
+    u[k] = uk;
+  }
+}
+
+/* Intersections of a ray with the offset boundary dR = {z inside : d(z) = l},
+ * the boundary of the region whose cache the gather uses (Section 3.2).  The
+ * candidates are the ray's crossings with every piece of the candidate set the
+ * cache sampler draws from (segment or face offsets at distance l, vertex
+ * circles or spheres, edge cylinders; both segment sides when sides = 2); a
+ * candidate belongs to dR when no boundary point is closer than l (up to
+ * 1e-9 relative) and it lies inside, the sampler's own acceptance rule. */
+typedef struct {
+  double t;
+  double z[3];
+  double n[3];
+} orc_hit;
+
+typedef struct {
+  orc_hit* h;
+  int64_t n, cap;
+} hit_list;
+
+static void hit_push(hit_list* L, const double* x, const double* w, double t, const double* n, int dim) {
+  if (L->n == L->cap) {
+    L->cap = L->cap ? 2 * L->cap : 16;
+    L->h = (orc_hit*)realloc(L->h, (size_t)L->cap * sizeof(orc_hit));
+  }
+  orc_hit* H = &L->h[L->n++];
+  H->t = t;
+  for (int a = 0; a < 3; ++a) {
+    H->z[a] = a < dim ? x[a] + t * w[a] : 0.0;
+    H->n[a] = a < dim ? n[a] : 0.0;
+  }
+}
+
+static int hit_cmp(const void* p, const void* q) {
+  double a = ((const orc_hit*)p)->t, b = ((const orc_hit*)q)->t;
+  return a < b ? -1 : (a > b ? 1 : 0);
+}
+
+/* Roots of t^2 + 2 qb t + qc = 0 (a unit-speed ray against a circle or
+ * sphere of radius l around c, qb = w.(x - c), qc = |x - c|^2 - l^2). */
+static int unit_quadratic(double qb, double qc, double* t) {
+  double disc = qb * qb - qc;
+  if (disc < 0) return 0;
+  double s = sqrt(disc);
+  t[0] = -qb - s;
+  t[1] = -qb + s;
+  return 2;
+}
+
+static void round_candidates(const double* x, const double* w, const double* c, double l, double t_max, int dim,
+                             hit_list* L) {
+  double qb = 0, qc = -l * l, t[2];
+  for (int a = 0; a < dim; ++a) {
+    qb += w[a] * (x[a] - c[a]);
+    qc += (x[a] - c[a]) * (x[a] - c[a]);
+  }
+  int nr = unit_quadratic(qb, qc, t);
+  for (int r = 0; r < nr; ++r) {
+    if (!(t[r] > 0 && t[r] <= t_max)) continue;
+    double n[3];
+    for (int a = 0; a < dim; ++a) n[a] = (c[a] - (x[a] + t[r] * w[a])) / l;
+    hit_push(L, x, w, t[r], n, dim);
+  }
+}
+
+int32_t orc_offset_hits(const orc_scene* s, double l, int sides, const double* x, const double* w, double t_max,
+                        int32_t max_hits, double* t_out, double* z_out, double* n_out) {
+  int dim = s->dim;
+  hit_list C = {NULL, 0, 0};
+  if (dim == 2) {
+    for (int64_t p = 0; p < s->np; ++p) {
+      const double* a = s->V + 2 * (int64_t)s->P[2 * p];
+      const double* b = s->V + 2 * (int64_t)s->P[2 * p + 1];
+      double e0 = b[0] - a[0], e1 = b[1] - a[1];
+      double len = sqrt(e0 * e0 + e1 * e1);
+      double n0 = e1 / len, n1 = -e0 / len; /* outward normal of a CCW polygon */
+      for (int sd = 0; sd < sides; ++sd) {
+        double side = sd == 0 ? 1.0 : -1.0;
+        /* offset segment a' + u e, a' = a - side l n; solve x + t w = a' + u e */
+        double ap0 = a[0] - side * l * n0, ap1 = a[1] - side * l * n1;
+        double den = w[0] * e1 - w[1] * e0; /* cross(w, e) */
+        if (den == 0) continue;
+        double r0 = ap0 - x[0], r1 = ap1 - x[1];
+        double t = (r0 * e1 - r1 * e0) / den;
+        double u = (r0 * w[1] - r1 * w[0]) / den;
+        if (!(t > 0 && t <= t_max && u >= 0 && u <= 1)) continue;
+        double n[2] = {side * n0, side * n1};
+        hit_push(&C, x, w, t, n, 2);
+      }
+    }
+    for (int64_t v = 0; v < s->nv; ++v) round_candidates(x, w, s->V + 2 * v, l, t_max, 2, &C);
+  } else {
+    for (int64_t p = 0; p < s->np; ++p) {
+      const double* A = s->V + 3 * (int64_t)s->P[3 * p];
+      const double* B = s->V + 3 * (int64_t)s->P[3 * p + 1];
+      const double* Cc = s->V + 3 * (int64_t)s->P[3 * p + 2];
+      double ab[3], ac[3], nn[3];
+      for (int a = 0; a < 3; ++a) {
+        ab[a] = B[a] - A[a];
+        ac[a] = Cc[a] - A[a];
+      }
+      cross3(ab, ac, nn);
+      double len = sqrt(dot3(nn, nn));
+      for (int a = 0; a < 3; ++a) nn[a] /= len;
+      /* inward offset triangle A - l n + beta ab + gamma ac (Moller and
+       * Trumbore's ray-triangle test, solved by Cramer's rule) */
+      double Ap[3], pv[3], tv[3], qv[3];
+      for (int a = 0; a < 3; ++a) Ap[a] = A[a] - l * nn[a];
+      cross3(w, ac, pv);
+      double det = dot3(ab, pv);
+      if (det == 0) continue;
+      for (int a = 0; a < 3; ++a) tv[a] = x[a] - Ap[a];
+      double beta = dot3(tv, pv) / det;
+      cross3(tv, ab, qv);
+      double gam = dot3(w, qv) / det;
+      double t = dot3(ac, qv) / det;
+      if (!(beta >= 0 && gam >= 0 && beta + gam <= 1 && t > 0 && t <= t_max)) continue;
+      hit_push(&C, x, w, t, nn, 3);
+    }
+    for (int64_t q = 0; q < s->ne; ++q) {
+      const double* A = s->V + 3 * (int64_t)s->edges[2 * q];
+      const double* B = s->V + 3 * (int64_t)s->edges[2 * q + 1];
+      double e[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
+      double L2 = dot3(e, e), L = sqrt(L2);
+      double eh[3] = {e[0] / L, e[1] / L, e[2] / L};
+      double w0[3] = {x[0] - A[0], x[1] - A[1], x[2] - A[2]};
+      double we = dot3(w, eh), w0e = dot3(w0, eh);
+      double wp[3], w0p[3];
+      for (int a = 0; a < 3; ++a) {
+        wp[a] = w[a] - we * eh[a];
+        w0p[a] = w0[a] - w0e * eh[a];
+      }
+      double qa = dot3(wp, wp);
+      if (qa == 0) continue;
+      double qb = dot3(w0p, wp), qc = dot3(w0p, w0p) - l * l;
+      double disc = qb * qb - qa * qc;
+      if (disc < 0) continue;
+      double sq = sqrt(disc);
+      double ts[2] = {(-qb - sq) / qa, (-qb + sq) / qa};
+      for (int r = 0; r < 2; ++r) {
+        double t = ts[r];
+        if (!(t > 0 && t <= t_max)) continue;
+        double along = (w0e + t * we) / L; /* axial parameter on the edge */
+        if (!(along >= 0 && along <= 1)) continue;
+        double n[3];
+        for (int a = 0; a < 3; ++a) n[a] = -(w0p[a] + t * wp[a]) / l;
+        hit_push(&C, x, w, t, n, 3);
+      }
+    }
+    for (int64_t v = 0; v < s->nv; ++v) round_candidates(x, w, s->V + 3 * v, l, t_max, 3, &C);
+  }
+  /* keep the candidates on dR, nearest first */
+  hit_list H = {NULL, 0, 0};
+  for (int64_t i = 0; i < C.n; ++i) {
+    double d, xb[3];
+    orc_closest(s, C.h[i].z, 0, &d, xb, NULL);
+    if (d >= l * (1 - 1e-9) && orc_inside(s, C.h[i].z) != 0) {
+      if (H.n == H.cap) {
+        H.cap = H.cap ? 2 * H.cap : 16;
+        H.h = (orc_hit*)realloc(H.h, (size_t)H.cap * sizeof(orc_hit));
+      }
+      H.h[H.n++] = C.h[i];
+    }
+  }
+  if (H.n > 1) qsort(H.h, (size_t)H.n, sizeof(orc_hit), hit_cmp);
+  for (int64_t i = 0; i < H.n && i < max_hits; ++i) {
+    if (t_out) t_out[i] = H.h[i].t;
+    for (int a = 0; a < dim; ++a) {
+      if (z_out) z_out[i * dim + a] = H.h[i].z[a];
+      if (n_out) n_out[i * dim + a] = H.h[i].n[a];
+    }
+  }
+  int32_t count = (int32_t)H.n;
+  free(C.h);
+  free(H.h);
+  return count;
+}
+
+/* Direction of ray j from point k: uniform on the unit circle or sphere from
+ * Philox block j, id k, tag 5. */
+void orc_ray_direction(uint64_t seed, uint32_t j, uint32_t k, uint32_t batch, int dim, double* w) {
+  double ua, ub;
+  orc_uniform_pair(seed, j, k, batch, 5, &ua, &ub);
+  if (dim == 2) {
+    double th = 2 * ORC_PI * ua;
+    w[0] = cos(th);
+    w[1] = sin(th);
+  } else {
+    double z = 1 - 2 * ua;
+    double rho = sqrt(fmax(0.0, 1 - z * z));
+    double ph = 2 * ORC_PI * ub;
+    w[0] = rho * cos(ph);
+    w[1] = rho * sin(ph);
+    w[2] = z;
+  }
+}
+
+/* Second integral of Eq. 8 at n points inside R: with dG/dn(x, z) dz the
+ * signed solid angle that z subtends at x, a uniform ray direction w and the
+ * ray's crossings z_h of dR give the estimate
+ *   sum_h sign(dG/dn) max(0, 1 - c/|dG/dn(x, z_h)|) u(z_h),
+ * averaged over n_rays rays.  u(z_h) is one pointwise walk from z_h (mode 1,
+ * walk id (k n_rays + j) max_hits + h) or, when u_at_hits is not NULL, that
+ * field's value (for checks of the ray sampling alone).  Only crossings
+ * within orc_clamp_radius can contribute; a ray keeps its max_hits nearest.
+ * stats (optional, 3 entries): crossings found, walks run, rays with more
+ * than max_hits crossings. */
+void orc_clamp_correction(const orc_scene* s, const orc_field* g, const orc_field* f, const orc_walk_params* p,
+                          double l, int sides, double c, int32_t n_rays, int32_t max_hits,
+                          const orc_field* u_at_hits, int64_t n, const double* x, double* corr, int64_t* stats) {
+  int dim = s->dim;
+  double t_max = orc_clamp_radius(dim, c);
+  int64_t found = 0, walks = 0, over = 0;
+#pragma omp parallel for schedule(dynamic, 4) reduction(+ : found, walks, over)
+  for (int64_t k = 0; k < n; ++k) {
+    const double* xk = x + k * dim;
+    double* tz = (double*)malloc((size_t)max_hits * (1 + 2 * dim) * sizeof(double));
+    double* zz = tz + max_hits;
+    double* nz = zz + (size_t)max_hits * dim;
+    double sum = 0;
+    for (int32_t j = 0; j < n_rays; ++j) {
+      double w[3];
+      orc_ray_direction(p->seed, (uint32_t)j, (uint32_t)k, p->batch, dim, w);
+      int32_t nh = orc_offset_hits(s, l, sides, xk, w, t_max, max_hits, tz, zz, nz);
+      found += nh;
+      if (nh > max_hits) ++over;
+      for (int32_t h = 0; h < nh && h < max_hits; ++h) {
+        const double* z = zz + (size_t)h * dim;
+        double dGdn;
+        orc_greens(dim, xk, z, nz + (size_t)h * dim, NULL, NULL, &dGdn, NULL);
+        double mag = fabs(dGdn);
+        if (!(mag > c)) continue;
+        double wgt = (dGdn > 0 ? 1.0 : -1.0) * (1 - c / mag);
+        double val;
+        if (u_at_hits) {
+          val = orc_field_eval(u_at_hits, dim, z);
+        } else {
+          double R0, xb[3], gr[3], ex[3], w1;
+          int32_t st, cap;
+          orc_closest(s, z, 0, &R0, xb, NULL);
+          uint32_t id = (uint32_t)(((int64_t)k * n_rays + j) * max_hits + h);
+          orc_walk(s, g, f, p, 1, z, NULL, R0, xb, id, &val, gr, ex, &w1, &st, &cap);
+          ++walks;
+        }
+        sum += wgt * val;
+      }
+    }
+    corr[k] = sum / n_rays;
+    free(tz);
+  }
+  if (stats) {
+    stats[0] = found;
+    stats[1] = walks;
+    stats[2] = over;
+  }
+}
+
 int orc_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

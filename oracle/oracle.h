@@ -18,7 +18,10 @@
  *   - cache points on the offset Dirichlet boundary at distance l (Section 3.2)
  *     drawn with a CDF table and stratified uniforms (Section 4, Sampling);
  *   - Algorithm 1 (UpdateSolution): cache walks, splat of boundary and source
- *     samples into evaluation points.
+ *     samples into evaluation points;
+ *   - the clamped double-layer kernel and its bias correction by ray-cast
+ *     signed-solid-angle sampling with walks at the crossings (Section 3.4,
+ *     Eqs. 8-9).
  *
  * Conventions (fixed readings of the paper, listed in the design notes):
  *   G_2D = ln r / (2 pi),  G_3D = -1 / (4 pi r)   (Lap G = delta; Appendix A.1
@@ -31,7 +34,8 @@
  *   FP64 uniform from words (w0, w1): ((w0 << 21) | (w1 >> 11)) * 2^-53.
  *   Each block yields two uniforms: ua from (w0, w1), ub from (w2, w3).
  *   Walk step k uses blocks 4k + s, s = 0..3 (see orc_walk for the map).
- *   Tags: 1 cache walk, 2 pointwise walk, 3 cache sampling, 4 source sampling.
+ *   Tags: 1 cache walk, 2 pointwise walk, 3 cache sampling, 4 source sampling,
+ *   5 ray directions of the clamping correction.
  */
 #ifndef BVC_ORACLE_H
 #define BVC_ORACLE_H
@@ -186,6 +190,31 @@ void orc_gather_backward(int dim, int64_t K, const double* ex, const double* r, 
                          const double* cy, const double* cn, const double* a, const double* b,
                          int64_t M, const double* sy, const double* sw, double* dLda,
                          double* dLdb, double* dLds, double* dLdx);
+
+/* --- Clamped double-layer kernel and bias correction (Section 3.4) ------ */
+/* Distance beyond which |dG/dn| cannot exceed c (INFINITY for c <= 0). */
+double orc_clamp_radius(int dim, double c);
+/* u only, with dG/dn clamped to [-c, c] (Eq. 9) in the boundary term. */
+void orc_gather_clamped(int dim, int64_t K, const double* ex, int64_t N, const double* cy,
+                        const double* cn, const double* a, const double* b, int64_t M,
+                        const double* sy, const double* sw, double c, double* u);
+/* Crossings of the ray x + t w (0 < t <= t_max, |w| = 1) with the offset
+ * boundary {z inside : d(z) = l}: returns how many there are and writes the
+ * nearest max_hits: t, point z and the unit outward normal of {d > l} at z
+ * (pointing to the closest boundary point). */
+int32_t orc_offset_hits(const orc_scene* s, double l, int sides, const double* x, const double* w,
+                        double t_max, int32_t max_hits, double* t_out, double* z_out, double* n_out);
+/* Ray direction j of point k (Philox block j, id k, tag 5). */
+void orc_ray_direction(uint64_t seed, uint32_t j, uint32_t k, uint32_t batch, int dim, double* w);
+/* Bias correction of the clamped gather (Eq. 8, second integral) at n points:
+ * corr[k] = (1/n_rays) sum_j sum_h sign(K) max(0, 1 - c/|K|) u(z_jh), with
+ * u from one pointwise walk per contributing crossing (id (k n_rays + j)
+ * max_hits + h) or from u_at_hits when not NULL.  stats: crossings, walks,
+ * rays with more than max_hits crossings. */
+void orc_clamp_correction(const orc_scene* s, const orc_field* g, const orc_field* f,
+                          const orc_walk_params* p, double l, int sides, double c, int32_t n_rays,
+                          int32_t max_hits, const orc_field* u_at_hits, int64_t n, const double* x,
+                          double* corr, int64_t* stats);
 
 /* --- Basis expansion from exit records (linearity in the boundary data) --- */
 /* E[i*nb + m] = (1/W) sum_j phi_m(exit_ij),
