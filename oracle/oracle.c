@@ -1552,52 +1552,67 @@ void orc_ray_direction(uint64_t seed, uint32_t j, uint32_t k, uint32_t batch, in
 
 /* Second integral of Eq. 8 at n points inside R: with dG/dn(x, z) dz the
  * signed solid angle that z subtends at x, a uniform ray direction w and the
- * ray's crossings z_h of dR give the estimate
- *   sum_h sign(dG/dn) max(0, 1 - c/|dG/dn(x, z_h)|) u(z_h),
- * averaged over n_rays rays.  u(z_h) is one pointwise walk from z_h (mode 1,
- * walk id (k n_rays + j) max_hits + h) or, when u_at_hits is not NULL, that
- * field's value (for checks of the ray sampling alone).  Only crossings
- * within orc_clamp_radius can contribute; a ray keeps its max_hits nearest.
- * stats (optional, 3 entries): crossings found, walks run, rays with more
- * than max_hits crossings. */
+ * ray's crossings z of dR give the estimate
+ *   sum_z sign(dG/dn) max(0, 1 - c/|dG/dn(x, z)|) u(z),
+ * averaged over n_rays rays.  Only crossings with |dG/dn| > c contribute;
+ * they are ranked h = 0, 1, ... nearest first, a ray keeps max_hits of them,
+ * and u at crossing h of ray j of point k is one pointwise walk from it
+ * (mode 1, walk id (k n_rays + j) max_hits + h) or, when u_at_hits is not
+ * NULL, that field's value (for checks of the ray sampling alone).  Only
+ * crossings within orc_clamp_radius can contribute.  stats (optional, 3
+ * entries): contributing crossings found, walks run, rays with more than
+ * max_hits contributing crossings. */
 void orc_clamp_correction(const orc_scene* s, const orc_field* g, const orc_field* f, const orc_walk_params* p,
                           double l, int sides, double c, int32_t n_rays, int32_t max_hits,
                           const orc_field* u_at_hits, int64_t n, const double* x, double* corr, int64_t* stats) {
   int dim = s->dim;
   double t_max = orc_clamp_radius(dim, c);
+  const int32_t cap = 1024;
   int64_t found = 0, walks = 0, over = 0;
 #pragma omp parallel for schedule(dynamic, 4) reduction(+ : found, walks, over)
   for (int64_t k = 0; k < n; ++k) {
     const double* xk = x + k * dim;
-    double* tz = (double*)malloc((size_t)max_hits * (1 + 2 * dim) * sizeof(double));
-    double* zz = tz + max_hits;
-    double* nz = zz + (size_t)max_hits * dim;
+    double* tz = (double*)malloc((size_t)cap * (1 + 2 * dim) * sizeof(double));
+    double* zz = tz + cap;
+    double* nz = zz + (size_t)cap * dim;
     double sum = 0;
     for (int32_t j = 0; j < n_rays; ++j) {
       double w[3];
       orc_ray_direction(p->seed, (uint32_t)j, (uint32_t)k, p->batch, dim, w);
-      int32_t nh = orc_offset_hits(s, l, sides, xk, w, t_max, max_hits, tz, zz, nz);
-      found += nh;
-      if (nh > max_hits) ++over;
-      for (int32_t h = 0; h < nh && h < max_hits; ++h) {
-        const double* z = zz + (size_t)h * dim;
+      int32_t nh = orc_offset_hits(s, l, sides, xk, w, t_max, cap, tz, zz, nz);
+      int32_t h = 0;
+      for (int32_t i = 0; i < nh && i < cap; ++i) {
+        const double* z = zz + (size_t)i * dim;
         double dGdn;
-        orc_greens(dim, xk, z, nz + (size_t)h * dim, NULL, NULL, &dGdn, NULL);
+        orc_greens(dim, xk, z, nz + (size_t)i * dim, NULL, NULL, &dGdn, NULL);
         double mag = fabs(dGdn);
         if (!(mag > c)) continue;
+        ++found;
+        if (h >= max_hits) continue;
         double wgt = (dGdn > 0 ? 1.0 : -1.0) * (1 - c / mag);
         double val;
         if (u_at_hits) {
           val = orc_field_eval(u_at_hits, dim, z);
         } else {
           double R0, xb[3], gr[3], ex[3], w1;
-          int32_t st, cap;
+          int32_t st, cp;
           orc_closest(s, z, 0, &R0, xb, NULL);
           uint32_t id = (uint32_t)(((int64_t)k * n_rays + j) * max_hits + h);
-          orc_walk(s, g, f, p, 1, z, NULL, R0, xb, id, &val, gr, ex, &w1, &st, &cap);
+          orc_walk(s, g, f, p, 1, z, NULL, R0, xb, id, &val, gr, ex, &w1, &st, &cp);
           ++walks;
         }
         sum += wgt * val;
+        ++h;
+      }
+      if (h >= max_hits && nh > 0) {
+        /* count the ray when contributing crossings were left out */
+        int32_t m = 0;
+        for (int32_t i = 0; i < nh && i < cap; ++i) {
+          double dGdn;
+          orc_greens(dim, xk, zz + (size_t)i * dim, nz + (size_t)i * dim, NULL, NULL, &dGdn, NULL);
+          if (fabs(dGdn) > c) ++m;
+        }
+        if (m > max_hits) ++over;
       }
     }
     corr[k] = sum / n_rays;

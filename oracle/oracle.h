@@ -207,10 +207,11 @@ int32_t orc_offset_hits(const orc_scene* s, double l, int sides, const double* x
 /* Ray direction j of point k (Philox block j, id k, tag 5). */
 void orc_ray_direction(uint64_t seed, uint32_t j, uint32_t k, uint32_t batch, int dim, double* w);
 /* Bias correction of the clamped gather (Eq. 8, second integral) at n points:
- * corr[k] = (1/n_rays) sum_j sum_h sign(K) max(0, 1 - c/|K|) u(z_jh), with
- * u from one pointwise walk per contributing crossing (id (k n_rays + j)
- * max_hits + h) or from u_at_hits when not NULL.  stats: crossings, walks,
- * rays with more than max_hits crossings. */
+ * corr[k] = (1/n_rays) sum_j sum_h sign(K) (1 - c/|K|) u(z_jh) over the
+ * crossings with |K| > c, ranked h nearest first (at most max_hits per ray),
+ * with u from one pointwise walk per crossing (id (k n_rays + j) max_hits + h)
+ * or from u_at_hits when not NULL.  stats: contributing crossings, walks,
+ * rays with more than max_hits contributing crossings. */
 void orc_clamp_correction(const orc_scene* s, const orc_field* g, const orc_field* f,
                           const orc_walk_params* p, double l, int sides, double c, int32_t n_rays,
                           int32_t max_hits, const orc_field* u_at_hits, int64_t n, const double* x,

@@ -295,7 +295,8 @@ def test_eq8_reproduces_the_solution_on_the_l_shape():
 def test_correction_recomposed_from_single_walks():
     """orc_clamp_correction equals its definition assembled from the single
     routines: ray j of point k from the tag-5 direction, its crossings, and
-    one mode-1 walk from each contributing crossing with id (k S + j) H + h."""
+    one mode-1 walk from each contributing crossing (|dG/dn| > c, rank h
+    among them, nearest first) with id (k S + j) H + h."""
     # a jagged self-intersecting star: rays often meet several crossings
     scene = wl.star_polygon(256, 5, jitter="isotropic")
     osc = orc.Scene(scene)
@@ -312,16 +313,18 @@ def test_correction_recomposed_from_single_walks():
         acc = 0.0
         for j in range(S):
             w = orc.ray_direction(4242, j, k, 3, 2)
-            cnt, t, z, n = orc.offset_hits(osc, l, sides, x[k], w, t_max, H)
-            for h in range(min(cnt, H)):
-                K = orc.greens(2, x[k], z[h], n[h])[2]
-                if abs(K) <= c:
+            cnt, t, z, n = orc.offset_hits(osc, l, sides, x[k], w, t_max, 256)
+            h = 0
+            for i in range(cnt):
+                K = orc.greens(2, x[k], z[i], n[i])[2]
+                if abs(K) <= c or h >= H:
                     continue
-                d, xb, _ = osc.closest(z[h])
-                U = orc.walk(osc, g, None, P, 1, z[h], None, d[0], xb[0], (k * S + j) * H + h)["U"]
+                d, xb, _ = osc.closest(z[i])
+                U = orc.walk(osc, g, None, P, 1, z[i], None, d[0], xb[0], (k * S + j) * H + h)["U"]
                 acc += np.sign(K) * (1 - c / abs(K)) * U
                 walks += 1
                 later += h > 0
+                h += 1
         assert corr[k] == pytest.approx(acc / S, rel=1e-12, abs=1e-14)
     assert walks == st[1] and later > 0
 
