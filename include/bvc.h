@@ -262,6 +262,10 @@ typedef struct {
   const double* near_cn; /* cache normals [dim][n] */
   const double* near_a;  /* cache a [n] */
   const double* near_b;  /* cache b [n] */
+  double clamp_c;        /* > 0: dG/dn clamped to [-clamp_c, clamp_c] in the
+                            potential's boundary term (Eq. 9 in the first
+                            integral of Eq. 8); the gradient is not clamped.
+                            0 = off */
 } bvc_gather_params;
 
 /* u_k = sum_i [dG/dn(x_k,z_i) a_i - G(x_k,z_i) b_i] + sum_j G(x_k,y_j) s_j
@@ -276,6 +280,61 @@ int bvc_gather_u(int32_t dim, const bvc_cache_view* cache, const bvc_source_view
 int bvc_gather_grad(int32_t dim, const bvc_cache_view* cache, const bvc_source_view* sources,
                     int64_t n_eval, const void* eval_x, void* u, void* grad,
                     const bvc_gather_params* params, void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Bias correction of the clamped gather (Section 3.4, Eq. 8)              */
+/* ---------------------------------------------------------------------- */
+/* Clamping dG/dn at c (bvc_gather_params.clamp_c) removes the near-boundary
+ * artefacts of the gather and adds a bias equal to the second integral of
+ * Eq. 8.  This call estimates that integral at points inside the region the
+ * cache bounds and adds it to u.  dG/dn(x, z) dz is the signed solid angle
+ * dR subtends at x, so a uniform ray direction from x and the ray's
+ * crossings z of the offset boundary dR = {z inside : d(z) = l} give
+ *   sum_z sign(dG/dn) max(0, 1 - c/|dG/dn(x, z)|) u(z),
+ * averaged over n_rays rays per point, with u(z) from one pointwise walk per
+ * contributing crossing (|dG/dn| > c; only crossings within
+ * bvc_clamp_radius(dim, c) can contribute).  A crossing belongs to dR by the
+ * cache sampler's acceptance rule (no boundary point closer than l up to
+ * 1e-9 relative, and inside).  Random numbers: ray j of point k takes the
+ * Philox pair of block j, id k, batch, tag 5 (2D angle 2 pi ua; 3D
+ * z = 1 - 2 ua, azimuth 2 pi ub); the contributing crossings of a ray are
+ * ranked h = 0, 1, ... nearest first, at most max_hits are kept, and crossing
+ * h walks with id (k n_rays + j) max_hits + h, tag 2 (as bvc_pointwise_wos).
+ * Use a walk seed other than the band walks' so the two sets are independent. */
+typedef struct {
+  double l;          /* offset distance of the cache boundary */
+  int32_t sides;     /* candidate sides, as bvc_sample_cache */
+  double c;          /* clamp bound, > 0 */
+  int32_t n_rays;    /* rays per point, >= 1 */
+  int32_t max_hits;  /* contributing crossings kept per ray, 1..64 */
+} bvc_clamp_params;
+
+/* Distance beyond which |dG/dn| <= c: 1/(2 pi c) in 2D, (4 pi c)^(-1/2) in 3D. */
+double bvc_clamp_radius(int32_t dim, double c);
+
+/* 2D winding numbers of n points ([2][n] FP64 device) into wind [n] int32:
+ * the input bvc_clamp_correction needs to tell inside from outside along a
+ * ray (3D scenes use the pseudonormal test and need none). */
+int bvc_point_winding(bvc_scene scene, int64_t n, const double* x, int32_t* wind, void* stream);
+
+size_t bvc_clamp_workspace_bytes(int32_t dim, int32_t dtype, int64_t n, int32_t n_rays, int32_t max_hits);
+
+/* x: [dim][n] FP64 device points, each inside the region {d > l};
+ * wind: [n] int32 winding numbers (2D; from bvc_point_winding), ignored in
+ * 3D; out_index: [n] int64 or NULL: the correction of point k is added to
+ * u[out_index[k]] (u[k] when NULL); u: params->dtype (walk precision) device
+ * array.  The crossings and weights are computed in FP64, the walks in
+ * params->dtype (params->n_walks is ignored: one walk per crossing).
+ * workspace: caller-owned, 256-byte aligned, >= bvc_clamp_workspace_bytes
+ * bytes.  counters: device uint64[6], zeroed by the call: [0] contributing
+ * crossings, [1] rays with more than max_hits of them or more candidates than
+ * the ray kernel holds (their extra crossings are dropped), [2] walk queue,
+ * [3] closest-point queries of the walks, [4] capped walks, [5] walks.
+ * Synchronises the stream once (the number of walks sizes their launch). */
+int bvc_clamp_correction(bvc_scene scene, const bvc_walk_params* params, const bvc_clamp_params* cp,
+                         int64_t n, const double* x, const int32_t* wind, const int64_t* out_index,
+                         void* u, void* workspace, size_t workspace_bytes, uint64_t* counters,
+                         void* stream);
 
 /* ---------------------------------------------------------------------- */
 /* Autotuning of launch shapes (no passage of the paper: a performance aid) */

@@ -61,7 +61,12 @@ class bvc_source_view(C.Structure):
 class bvc_gather_params(C.Structure):
     _fields_ = [("accumulate", C.c_int32), ("near_tau", C.c_double), ("near_x", C.c_void_p),
                 ("near_cx", C.c_void_p), ("near_cn", C.c_void_p), ("near_a", C.c_void_p),
-                ("near_b", C.c_void_p)]
+                ("near_b", C.c_void_p), ("clamp_c", C.c_double)]
+
+
+class bvc_clamp_params(C.Structure):
+    _fields_ = [("l", C.c_double), ("sides", C.c_int32), ("c", C.c_double), ("n_rays", C.c_int32),
+                ("max_hits", C.c_int32)]
 
 
 class bvc_batch_item(C.Structure):
@@ -118,6 +123,9 @@ _SIGS = {
     "bvc_batch_launch": [_vp, _vp],
     "bvc_batch_counters": [_vp, _P(_vp)],
     "bvc_batch_destroy": [_vp],
+    "bvc_point_winding": [_vp, C.c_int64, _vp, _vp, _vp],
+    "bvc_clamp_correction": [_vp, _P(bvc_walk_params), _P(bvc_clamp_params), C.c_int64, _vp, _vp, _vp, _vp, _vp,
+                             C.c_size_t, _vp, _vp],
 }
 for _name, _args in _SIGS.items():
     _fn = getattr(_L, _name)
@@ -135,10 +143,15 @@ _L.bvc_gather_multi_workspace_bytes.argtypes = [C.c_int64, C.c_int32]
 _L.bvc_gather_multi_workspace_bytes.restype = C.c_size_t
 _L.bvc_batch_workspace_bytes.argtypes = [_P(bvc_batch_item), C.c_int32]
 _L.bvc_batch_workspace_bytes.restype = C.c_size_t
+_L.bvc_clamp_radius.argtypes = [C.c_int32, C.c_double]
+_L.bvc_clamp_radius.restype = C.c_double
+_L.bvc_clamp_workspace_bytes.argtypes = [C.c_int32, C.c_int32, C.c_int64, C.c_int32, C.c_int32]
+_L.bvc_clamp_workspace_bytes.restype = C.c_size_t
 
 EXPORTED = sorted(list(_SIGS) + ["bvc_last_error", "bvc_version", "bvc_compact_scratch_ints",
                                  "bvc_cache_backward_scratch_doubles", "bvc_pointwise_workspace_bytes",
-                                 "bvc_gather_multi_workspace_bytes", "bvc_batch_workspace_bytes"])
+                                 "bvc_gather_multi_workspace_bytes", "bvc_batch_workspace_bytes",
+                                 "bvc_clamp_radius", "bvc_clamp_workspace_bytes"])
 
 
 def _check(rc, name):
@@ -313,11 +326,13 @@ def _views(cache, sources):
     return cv, sv
 
 
-def _gparams(accumulate, near):
+def _gparams(accumulate, near, clamp=0.0):
     """near: None, or dict(tau, x, cx, cn, a, b) with FP64 device tensors
-    (evaluation points [dim][n_eval], cache points and normals [dim][n], a, b)."""
+    (evaluation points [dim][n_eval], cache points and normals [dim][n], a, b).
+    clamp: bound c of dG/dn in the potential (Eq. 9), 0 = off."""
     gp = bvc_gather_params()
     gp.accumulate = accumulate
+    gp.clamp_c = float(clamp)
     if near is not None:
         gp.near_tau = float(near["tau"])
         gp.near_x, gp.near_cx, gp.near_cn, gp.near_a, gp.near_b = (
@@ -325,16 +340,17 @@ def _gparams(accumulate, near):
     return gp
 
 
-def bvc_gather_u(dim, cache, sources, n_eval, eval_x, u, accumulate=0, stream=None, near=None):
+def bvc_gather_u(dim, cache, sources, n_eval, eval_x, u, accumulate=0, stream=None, near=None, clamp=0.0):
     cv, sv = _views(cache, sources)
-    gp = _gparams(accumulate, near)
+    gp = _gparams(accumulate, near, clamp)
     _check(_L.bvc_gather_u(dim, C.byref(cv), C.byref(sv) if sv is not None else None, n_eval, ptr(eval_x),
                            ptr(u), C.byref(gp), stream_ptr(stream)), "bvc_gather_u")
 
 
-def bvc_gather_grad(dim, cache, sources, n_eval, eval_x, u, grad, accumulate=0, stream=None, near=None):
+def bvc_gather_grad(dim, cache, sources, n_eval, eval_x, u, grad, accumulate=0, stream=None, near=None,
+                    clamp=0.0):
     cv, sv = _views(cache, sources)
-    gp = _gparams(accumulate, near)
+    gp = _gparams(accumulate, near, clamp)
     _check(_L.bvc_gather_grad(dim, C.byref(cv), C.byref(sv) if sv is not None else None, n_eval, ptr(eval_x),
                               ptr(u), ptr(grad), C.byref(gp), stream_ptr(stream)), "bvc_gather_grad")
 
@@ -419,3 +435,28 @@ def bvc_gather_multi(dim, n_cache, cx, cn, n_fields, A, B, n_eval, eval_x, U, pr
     nbytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
     _check(_L.bvc_gather_multi(dim, n_cache, ptr(cx), ptr(cn), n_fields, ptr(A), ptr(B), n_eval, ptr(eval_x),
                                ptr(U), precision, ptr(workspace), nbytes, stream_ptr(stream)), "bvc_gather_multi")
+
+
+def bvc_clamp_radius(dim, c):
+    return _L.bvc_clamp_radius(dim, float(c))
+
+
+def bvc_point_winding(scene, n, x, wind, stream=None):
+    _check(_L.bvc_point_winding(scene, n, ptr(x), ptr(wind), stream_ptr(stream)), "bvc_point_winding")
+
+
+def bvc_clamp_workspace_bytes(dim, dtype, n, n_rays, max_hits):
+    return _L.bvc_clamp_workspace_bytes(dim, dtype, n, n_rays, max_hits)
+
+
+def clamp_params(l, sides, c, n_rays, max_hits):
+    cp = bvc_clamp_params()
+    cp.l, cp.sides, cp.c, cp.n_rays, cp.max_hits = float(l), int(sides), float(c), int(n_rays), int(max_hits)
+    return cp
+
+
+def bvc_clamp_correction(scene, params: bvc_walk_params, cp: bvc_clamp_params, n, x, wind, out_index, u, work,
+                         counters, stream=None):
+    nbytes = 0 if work is None else work.numel() * work.element_size()
+    _check(_L.bvc_clamp_correction(scene, C.byref(params), C.byref(cp), n, ptr(x), ptr(wind), ptr(out_index), ptr(u),
+                                   ptr(work), nbytes, ptr(counters), stream_ptr(stream)), "bvc_clamp_correction")

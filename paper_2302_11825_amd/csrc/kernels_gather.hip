@@ -64,23 +64,35 @@ struct GatherArgs {
   const double* ncn;  // cache normals [D][n_cache]
   const double* na;   // [n_cache]
   const double* nb;   // [n_cache]
+  // Clamp of dG/dn in the potential's boundary term (Eq. 9), kernels with
+  // CLAMP only: clampc in the kernel's precision, clamp64 for the FP64 near
+  // field.
+  T clampc;
+  double clamp64;
 };
 
 // Entry layout in LDS (8 values): 2D boundary {y0, y1, 2 na0, 2 na1, 2 bl, bg,
 // na0, na1}, 3D boundary {y0, y1, y2, bl, na0, na1, na2, -}; sources
-// {y.., sl, sg} (2D sl doubled like bl).
-template <typename T, int D, bool GRAD, bool NEAR = false, int PPT = kPPT>
+// {y.., sl, sg} (2D sl doubled like bl).  With CLAMP a ninth array after the
+// tile holds each boundary entry's clamp bound in the same scaling as its
+// dG/dn term: |a| c (3D), 2 |a| c (2D, whose potential runs doubled).
+template <typename T, int D, bool GRAD, bool NEAR = false, int PPT = kPPT, bool CLAMP = false>
 __device__ __forceinline__ void gather_block(const GatherArgs<T>& a, int64_t block, T* ent);
 
-template <typename T, int D, bool GRAD, bool NEAR, int PPT>
+template <typename T, int D, bool GRAD, bool NEAR, int PPT, bool CLAMP = false>
 __global__ __launch_bounds__(kGBlock) void k_gather(GatherArgs<T> a) {
-  __shared__ T ent[kTile * 8];
-  gather_block<T, D, GRAD, NEAR, PPT>(a, blockIdx.x, ent);
+  __shared__ T ent[kTile * (CLAMP ? 9 : 8)];
+  gather_block<T, D, GRAD, NEAR, PPT, CLAMP>(a, blockIdx.x, ent);
 }
 
+// Clamp of t to [-b, b] (b >= 0): one v_med3 in FP32.
+__device__ __forceinline__ float clamp_sym(float t, float b) { return __builtin_amdgcn_fmed3f(t, -b, b); }
+__device__ __forceinline__ double clamp_sym(double t, double b) { return fmin(fmax(t, -b), b); }
+
 // FP64 contribution of cache point i to u (and grad u) at evaluation point k,
-// from the FP64 copies: u += a dG/dn - b G (Eq. 3), grad from Eq. 5.
-template <int D, bool GRAD>
+// from the FP64 copies: u += a dG/dn - b G (Eq. 3), grad from Eq. 5; with
+// CLAMP, dG/dn in u is clamped to [-c, c] (Eq. 9).
+template <int D, bool GRAD, bool CLAMP = false>
 __device__ __forceinline__ void near_pair(const GatherArgs<float>& a, int64_t k, int64_t i, double& tu, double* tg) {
   double d[D];
   double r2 = 0.0, nd = 0.0;
@@ -94,7 +106,8 @@ __device__ __forceinline__ void near_pair(const GatherArgs<float>& a, int64_t k,
   const double av = a.na[i], bv = a.nb[i];
   if constexpr (D == 2) {
     const double k2 = 1.0 / (2.0 * kPi * r2);
-    tu += av * nd * k2 - bv * log(r2) / (4.0 * kPi);
+    const double kn = CLAMP ? clamp_sym(nd * k2, a.clamp64) : nd * k2;
+    tu += av * kn - bv * log(r2) / (4.0 * kPi);
     if constexpr (GRAD) {
       const double q = (2.0 * av * nd / r2 + bv) * k2;
 #pragma unroll
@@ -103,7 +116,8 @@ __device__ __forceinline__ void near_pair(const GatherArgs<float>& a, int64_t k,
   } else {
     const double r = sqrt(r2);
     const double k3 = 1.0 / (4.0 * kPi * r2 * r);
-    tu += bv / (4.0 * kPi * r) + av * nd * k3;
+    const double kn = CLAMP ? clamp_sym(nd * k3, a.clamp64) : nd * k3;
+    tu += bv / (4.0 * kPi * r) + av * kn;
     if constexpr (GRAD) {
       const double q = (3.0 * av * nd / r2 + bv) * k3;
 #pragma unroll
@@ -116,7 +130,7 @@ __device__ __forceinline__ void near_pair(const GatherArgs<float>& a, int64_t k,
 // [block*256*PPT, (block+1)*256*PPT), PPT per thread.  The sum of each point
 // runs over the cache in the same order whatever PPT is, so every PPT gives
 // bit-identical results and PPT is a pure tuning choice.
-template <typename T, int D, bool GRAD, bool NEAR, int PPT>
+template <typename T, int D, bool GRAD, bool NEAR, int PPT, bool CLAMP>
 __device__ __forceinline__ void gather_block(const GatherArgs<T>& a, int64_t block, T* ent) {
   static_assert(!NEAR || sizeof(T) == 4, "the near field applies to FP32 gathers");
   const int tid = threadIdx.x;
@@ -174,6 +188,7 @@ __device__ __forceinline__ void gather_block(const GatherArgs<T>& a, int64_t blo
       }
       const T av = a.ca[i], bv = a.cb[i];
       T* e = ent + tid * 8;
+      if constexpr (CLAMP) ent[kTile * 8 + tid] = (D == 2 ? T(2) : T(1)) * fabs(av) * a.clampc;
       if constexpr (D == 2) {
         // twice the potential terms (see kUnfold), the gradient terms as is
         e[0] = y[0];
@@ -203,6 +218,7 @@ __device__ __forceinline__ void gather_block(const GatherArgs<T>& a, int64_t blo
       const T* e = ent + j * 8;
       if constexpr (D == 2) {
         const T y0 = e[0], y1 = e[1], m0 = e[2], m1 = e[3], bl = e[4], bg = e[5];
+        const T bt = CLAMP ? ent[kTile * 8 + j] : T(0);
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
           const T dx = y0 - x[p][0], dy = y1 - x[p][1];
@@ -220,16 +236,25 @@ __device__ __forceinline__ void gather_block(const GatherArgs<T>& a, int64_t blo
             lr = log_r2(r2);
           }
           const T t2 = fma(m0, dx, m1 * dy);  // 2 a (n . (y - x)) / (2 pi)
-          au[p] = fma(bl, lr, fma(t2, ri, au[p]));
+          T q;
+          if constexpr (CLAMP) {
+            // 2 a clamp(dG/dn) = clamp(2 a dG/dn, -2|a|c, 2|a|c); grad unclamped
+            const T tk = t2 * ri;
+            au[p] = fma(bl, lr, au[p] + clamp_sym(tk, bt));
+            q = tk + bg;
+          } else {
+            au[p] = fma(bl, lr, fma(t2, ri, au[p]));
+            q = fma(t2, ri, bg);
+          }
           if constexpr (GRAD) {
             // grad = (q (y - x) - a n / (2 pi)) / r^2,  q = (2 a n.(y-x)/r^2 + b)/(2 pi)
-            const T q = fma(t2, ri, bg);
             ag[p][0] = fma(ri, fma(q, dx, -e[6]), ag[p][0]);
             ag[p][1] = fma(ri, fma(q, dy, -e[7]), ag[p][1]);
           }
         }
       } else {
         const T y0 = e[0], y1 = e[1], y2 = e[2], bl = e[3], n0 = e[4], n1 = e[5], n2 = e[6];
+        const T bt = CLAMP ? ent[kTile * 8 + j] : T(0);
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
           const T dx = y0 - x[p][0], dy = y1 - x[p][1], dz = y2 - x[p][2];
@@ -244,8 +269,13 @@ __device__ __forceinline__ void gather_block(const GatherArgs<T>& a, int64_t blo
           }
           const T ri2 = ri * ri;
           const T t = fma(n0, dx, fma(n1, dy, n2 * dz));
-          // b/r + t/r^3 = (b + t/r^2)/r
-          au[p] = fma(ri, fma(t, ri2, bl), au[p]);
+          if constexpr (CLAMP) {
+            // b/r + clamp(t/r^3, -|a|c, |a|c)
+            au[p] = fma(ri, bl, au[p] + clamp_sym(t * ri2 * ri, bt));
+          } else {
+            // b/r + t/r^3 = (b + t/r^2)/r
+            au[p] = fma(ri, fma(t, ri2, bl), au[p]);
+          }
           if constexpr (GRAD) {
             const T ri3 = ri2 * ri;
             const T q = ri3 * fma(T(3) * t, ri2, bl);
@@ -276,7 +306,7 @@ __device__ __forceinline__ void gather_block(const GatherArgs<T>& a, int64_t blo
               const T dx = e[0] - x[p][0], dy = e[1] - x[p][1], dz = e[2] - x[p][2];
               r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, tiny)));
             }
-            if (r2 < a.tau2) near_pair<D, GRAD>(a, k0 + p * kGBlock, t0 + j, tu[p], tg[p]);
+            if (r2 < a.tau2) near_pair<D, GRAD, CLAMP>(a, k0 + p * kGBlock, t0 + j, tu[p], tg[p]);
           }
         }
       }
@@ -773,9 +803,22 @@ int check_sources(const bvc_source_view* s, int dtype) {
 }
 
 template <typename T, int D>
-void launch_gather(const GatherArgs<T>& a, bool grad, bool near, int ppt, hipStream_t st) {
+void launch_gather(const GatherArgs<T>& a, bool grad, bool near, int ppt, bool clamp, hipStream_t st) {
+  if (clamp) ppt = kPPT;  // the clamped kernels come in the default shape only
   const int blocks = (int)((a.n_eval + kGBlock * ppt - 1) / (kGBlock * ppt));
   auto go = [&](auto kernel) { hipLaunchKernelGGL(kernel, dim3(blocks), dim3(kGBlock), 0, st, a); };
+  if (clamp) {
+    if constexpr (sizeof(T) == 4) {
+      if (near) {
+        if (grad) go(k_gather<T, D, true, true, kPPT, true>);
+        else go(k_gather<T, D, false, true, kPPT, true>);
+        return;
+      }
+    }
+    if (grad) go(k_gather<T, D, true, false, kPPT, true>);
+    else go(k_gather<T, D, false, false, kPPT, true>);
+    return;
+  }
   if constexpr (sizeof(T) == 4) {
     if (near) {
       if (grad) {
@@ -834,7 +877,7 @@ int tuned_ppt(const GatherClass& k) {
 template <typename T>
 int gather_impl(int dim, const bvc_cache_view* c, const bvc_source_view* s, int64_t n_eval, const void* ex, void* u,
                 void* g, const void* scale, int accumulate, hipStream_t st, const bvc_gather_params* near = nullptr,
-                int ppt = 0) {
+                int ppt = 0, double clamp_c = 0.0) {
   if (ppt == 0)
     ppt = tuned_ppt(gather_class(dim, sizeof(T) == 4 ? BVC_F32 : BVC_F64, g != nullptr, near != nullptr, n_eval, c->n));
   GatherArgs<T> a{};
@@ -863,8 +906,11 @@ int gather_impl(int dim, const bvc_cache_view* c, const bvc_source_view* s, int6
     a.na = near->near_a;
     a.nb = near->near_b;
   }
-  if (dim == 2) launch_gather<T, 2>(a, g != nullptr, near != nullptr, ppt, st);
-  else launch_gather<T, 3>(a, g != nullptr, near != nullptr, ppt, st);
+  a.clampc = (T)clamp_c;
+  a.clamp64 = clamp_c;
+  const bool clamp = clamp_c > 0.0;
+  if (dim == 2) launch_gather<T, 2>(a, g != nullptr, near != nullptr, ppt, clamp, st);
+  else launch_gather<T, 3>(a, g != nullptr, near != nullptr, ppt, clamp, st);
   return check_hip(hipGetLastError(), "gather launch");
 }
 
@@ -884,9 +930,11 @@ int gather_entry(int32_t dim, const bvc_cache_view* c, const bvc_source_view* s,
   if (prm && !(prm->near_tau >= 0.0)) return fail(BVC_EINVAL, "near_tau must be >= 0");
   if (near && (!prm->near_x || !prm->near_cx || !prm->near_cn || !prm->near_a || !prm->near_b))
     return fail(BVC_EINVAL, "near_tau > 0 needs the FP64 copies near_x, near_cx, near_cn, near_a, near_b");
+  const double clamp_c = prm ? prm->clamp_c : 0.0;
+  if (!(clamp_c >= 0.0) || !std::isfinite(clamp_c)) return fail(BVC_EINVAL, "clamp_c must be finite and >= 0");
   if (c->dtype == BVC_F32)
-    return gather_impl<float>(dim, c, s, n_eval, ex, u, g, nullptr, acc, st, near ? prm : nullptr, ppt);
-  return gather_impl<double>(dim, c, s, n_eval, ex, u, g, nullptr, acc, st, nullptr, ppt);
+    return gather_impl<float>(dim, c, s, n_eval, ex, u, g, nullptr, acc, st, near ? prm : nullptr, ppt, clamp_c);
+  return gather_impl<double>(dim, c, s, n_eval, ex, u, g, nullptr, acc, st, nullptr, ppt, clamp_c);
 }
 
 template <typename T>

@@ -40,8 +40,9 @@ struct WalkArgs {
   uint32_t batch;
   uint64_t total;
   int64_t n_pts;
-  const double* x;     // mode 0 start points [D][n] FP64
+  const double* x;     // mode 0 and 2 start points [D][n] FP64
   const void* px;      // mode 1 start points [D][n] of T
+  const uint32_t* ids; // mode 2: queue position -> walk id (the start point's index)
   const double* nrm;   // mode 0 normals [D][n]
   const double* R0;    // [n] distance of each start point to the boundary
   const double* xbar;  // [D][n] closest boundary points (mode 1 shell exit)
@@ -50,6 +51,7 @@ struct WalkArgs {
   void* exit;          // [D][total] exit points
   void* w1;            // mode 0 [total] (dim/R0) nu.n; mode 1 [D][total] (dim/R0) nu
   int* steps;          // [total] or null
+  uint64_t ld;         // stride of the [D][*] records: total (modes 0, 1), the id range (mode 2)
   unsigned long long* counters;
   unsigned long long chunk;  // walk ids per claim, 1..kChunkMax
   int open_lanes;            // leave the traversal loop at this many open queries
@@ -204,20 +206,21 @@ __global__ __launch_bounds__(kBlock) void k_walks(WalkArgs a) {
         const unsigned long long my = pool.take(need, lane, &a.counters[0], a.chunk, a.total, exhausted);
         if (!active) {
           if (my != ~0ull) {
-            id = (uint32_t)my;
-            const int64_t i = (int64_t)(id / (uint32_t)a.W);
+            // mode 2 walks start from the points their ids index (one walk each)
+            id = MODE == 2 ? a.ids[my] : (uint32_t)my;
+            const int64_t i = MODE == 2 ? (int64_t)id : (int64_t)(id / (uint32_t)a.W);
             const T R0 = (T)a.R0[i];
             if (MODE == 1 && R0 < eps) {
               // the evaluation point already lies in the epsilon shell: its
               // walk returns g at the closest boundary point
 #pragma unroll
-              for (int q = 0; q < D; ++q) EX[(size_t)q * a.total + id] = (T)a.xbar[q * a.n_pts + i];
+              for (int q = 0; q < D; ++q) EX[(size_t)q * a.ld + id] = (T)a.xbar[q * a.n_pts + i];
               U[id] = T(0);
               if (Dof) {
 #pragma unroll
                 for (int q = 0; q < D; ++q) {
-                  Dof[(size_t)q * a.total + id] = T(0);
-                  W1[(size_t)q * a.total + id] = T(0);
+                  Dof[(size_t)q * a.ld + id] = T(0);
+                  W1[(size_t)q * a.ld + id] = T(0);
                 }
               }
               if (a.steps) a.steps[id] = 0;
@@ -225,7 +228,7 @@ __global__ __launch_bounds__(kBlock) void k_walks(WalkArgs a) {
             } else {
 #pragma unroll
               for (int q = 0; q < D; ++q)
-                p[q] = MODE == 0 ? (T)a.x[q * a.n_pts + i] : ((const T*)a.px)[q * a.n_pts + i];
+                p[q] = MODE != 1 ? (T)a.x[q * a.n_pts + i] : ((const T*)a.px)[q * a.n_pts + i];
               d = R0;
               k = 0;
               acc_s = T(0);
@@ -281,12 +284,12 @@ __global__ __launch_bounds__(kBlock) void k_walks(WalkArgs a) {
           const T w1 = wgt * dn;
           W1[id] = w1;
           Dof[id] = ds - w1 * usrc;
-        } else if (Dof) {
+        } else if (MODE == 1 && Dof) {
 #pragma unroll
           for (int q = 0; q < D; ++q) {
             const T gw = wgt * nu[q];
-            W1[(size_t)q * a.total + id] = gw;
-            Dof[(size_t)q * a.total + id] = gs[q] - gw * usrc;
+            W1[(size_t)q * a.ld + id] = gw;
+            Dof[(size_t)q * a.ld + id] = gs[q] - gw * usrc;
           }
         }
       } else if constexpr (SRC) {
@@ -314,7 +317,7 @@ __global__ __launch_bounds__(kBlock) void k_walks(WalkArgs a) {
       const bool cap = !stop && k >= a.max_steps;
       if (stop || cap) {
 #pragma unroll
-        for (int c = 0; c < D; ++c) EX[(size_t)c * a.total + id] = qs.bq[c];
+        for (int c = 0; c < D; ++c) EX[(size_t)c * a.ld + id] = qs.bq[c];
         U[id] = acc_s + usrc;
         if (a.steps) a.steps[id] = k;
         steps_acc += (unsigned long long)k;
@@ -448,9 +451,12 @@ void launch_walks(const WalkArgs& args, int mode, bool src, int blocks, size_t l
   if (mode == 0) {
     if (src) hipLaunchKernelGGL((k_walks<T, D, true, 0>), dim3(blocks), dim3(kBlock), lds, st, args);
     else hipLaunchKernelGGL((k_walks<T, D, false, 0>), dim3(blocks), dim3(kBlock), lds, st, args);
-  } else {
+  } else if (mode == 1) {
     if (src) hipLaunchKernelGGL((k_walks<T, D, true, 1>), dim3(blocks), dim3(kBlock), lds, st, args);
     else hipLaunchKernelGGL((k_walks<T, D, false, 1>), dim3(blocks), dim3(kBlock), lds, st, args);
+  } else {
+    if (src) hipLaunchKernelGGL((k_walks<T, D, true, 2>), dim3(blocks), dim3(kBlock), lds, st, args);
+    else hipLaunchKernelGGL((k_walks<T, D, false, 2>), dim3(blocks), dim3(kBlock), lds, st, args);
   }
 }
 
@@ -469,19 +475,27 @@ void launch_finish(const bvc_walk_params* p, int mode, const WalkArgs& a, hipStr
 
 size_t stack_bytes(const SceneHost& h) { return (size_t)(h.depth + 1) * kBlock * sizeof(uint32_t); }
 
+// Modes 0 and 1: n start points, W walks each, records of stride n W, then
+// the FP64 finish.  Mode 2: n walks whose ids (a.ids) index the start points
+// and records (stride a.ld, set by the caller); the caller finishes them.
 int run_walks(bvc_scene s, const bvc_walk_params* p, int mode, int64_t n, WalkArgs& a, hipStream_t st,
               const WalkShape* force = nullptr) {
   const SceneHost& h = s->h;
-  const uint64_t total = (uint64_t)n * (uint64_t)p->n_walks;
+  const uint64_t total = (uint64_t)n * (uint64_t)(mode == 2 ? 1 : p->n_walks);
   a.S = h.view();
   a.f = to_dev(p->f);
   a.eps = p->eps;
   a.max_steps = p->max_steps;
-  a.W = p->n_walks;
+  a.W = mode == 2 ? 1 : p->n_walks;
   a.seed = p->seed;
   a.batch = p->batch;
   a.total = total;
-  a.n_pts = n;
+  if (mode == 2) {
+    a.n_pts = (int64_t)a.ld;
+  } else {
+    a.n_pts = n;
+    a.ld = total;
+  }
   int rc = zero_async(a.counters, 4 * sizeof(unsigned long long), st);
   if (rc || total == 0) return rc;
   const WalkShape shape = force ? *force : tuned_shape(WalkClass{h.dim, p->dtype, p->f.kind != 0 ? 1 : 0, mode});
@@ -510,6 +524,7 @@ int run_walks(bvc_scene s, const bvc_walk_params* p, int mode, int64_t n, WalkAr
     rc = check_hip(hipEventRecord((hipEvent_t)p->ev_end, st), "walk end event");
     if (rc) return rc;
   }
+  if (mode == 2) return BVC_OK;
   if (h.dim == 2) {
     if (f32) launch_finish<float, 2>(p, mode, a, st);
     else launch_finish<double, 2>(p, mode, a, st);
@@ -774,9 +789,124 @@ int cache_walks_entry(bvc_scene s, const bvc_walk_params* p, int64_t n_cache, co
 }  // namespace
 }  // namespace bvc
 
+namespace bvc {
+namespace {
+struct ClampLayout {
+  size_t wind, slot_x, slot_R0, slot_w, flags, ids, scratch, ex, u, total;
+};
+ClampLayout clamp_layout(int dim, int dtype, int64_t n, int n_rays, int max_hits) {
+  const uint64_t slots = (uint64_t)n * n_rays * max_hits;
+  const size_t es = dtype == BVC_F32 ? 4 : 8;
+  ClampLayout L{};
+  size_t o = 0;
+  L.wind = o;
+  o += align256((size_t)n * 4);
+  L.slot_x = o;
+  o += align256((size_t)dim * slots * 8);
+  L.slot_R0 = o;
+  o += align256(slots * 8);
+  L.slot_w = o;
+  o += align256(slots * 8);
+  L.flags = o;
+  o += align256(slots * 4);
+  L.ids = o;
+  o += align256(slots * 4);
+  L.scratch = o;
+  o += align256((size_t)bvc_compact_scratch_ints((int64_t)slots) * 4);
+  L.ex = o;
+  o += align256((size_t)dim * slots * es);
+  L.u = o;
+  o += align256(slots * es);
+  L.total = o;
+  return L;
+}
+}  // namespace
+}  // namespace bvc
+
 using namespace bvc;
 
 extern "C" {
+
+double bvc_clamp_radius(int32_t dim, double c) {
+  if (!(c > 0.0)) return INFINITY;
+  return dim == 2 ? 1.0 / (2.0 * kPi * c) : 1.0 / sqrt(4.0 * kPi * c);
+}
+
+int bvc_point_winding(bvc_scene s, int64_t n, const double* x, int32_t* wind, void* stream) {
+  int rc = check_scene(s);
+  if (rc) return rc;
+  if (s->h.dim != 2) return fail(BVC_EUNSUPPORTED, "winding numbers are for 2D scenes");
+  if (n < 0) return fail(BVC_EINVAL, "n must be >= 0");
+  if (n > 0 && (!x || !wind)) return fail(BVC_EINVAL, "null argument");
+  return launch_point_winding(s->h, n, x, wind, (hipStream_t)stream);
+}
+
+size_t bvc_clamp_workspace_bytes(int32_t dim, int32_t dtype, int64_t n, int32_t n_rays, int32_t max_hits) {
+  if ((dim != 2 && dim != 3) || n < 0 || n_rays < 1 || max_hits < 1) return 0;
+  return clamp_layout(dim, dtype, n, n_rays, max_hits).total;
+}
+
+int bvc_clamp_correction(bvc_scene s, const bvc_walk_params* p, const bvc_clamp_params* cp, int64_t n,
+                         const double* x, const int32_t* wind, const int64_t* out_index, void* u, void* workspace,
+                         size_t workspace_bytes, uint64_t* counters, void* stream) {
+  int rc = check_scene(s);
+  if (rc) return rc;
+  const int dim = s->h.dim;
+  rc = check_walk_params(p, dim);
+  if (rc) return rc;
+  if (!cp) return fail(BVC_EINVAL, "clamp params are null");
+  if (!(cp->l > 0.0) || !std::isfinite(cp->l)) return fail(BVC_EINVAL, "l must be positive");
+  if (cp->sides != 1 && !(cp->sides == 2 && dim == 2)) return fail(BVC_EINVAL, "sides must be 1 (or 2 in 2D)");
+  if (!(cp->c > 0.0) || !std::isfinite(cp->c)) return fail(BVC_EINVAL, "c must be positive");
+  if (cp->n_rays < 1) return fail(BVC_EINVAL, "n_rays must be >= 1");
+  if (cp->max_hits < 1 || cp->max_hits > 64) return fail(BVC_EINVAL, "max_hits must be in 1..64");
+  if (n < 0) return fail(BVC_EINVAL, "n must be >= 0");
+  if (!counters) return fail(BVC_EINVAL, "counters is null");
+  const uint64_t slots = (uint64_t)n * cp->n_rays * cp->max_hits;
+  if (slots >= (1ull << 31)) return fail(BVC_EINVAL, "n * n_rays * max_hits >= 2^31");
+  hipStream_t st = (hipStream_t)stream;
+  rc = zero_async(counters, 6 * sizeof(uint64_t), st);
+  if (rc || n == 0) return rc;
+  if (!x || !u || !workspace) return fail(BVC_EINVAL, "null points, output or workspace");
+  if (((uintptr_t)workspace & 255) != 0) return fail(BVC_EINVAL, "workspace must be 256-byte aligned");
+  const ClampLayout L = clamp_layout(dim, p->dtype, n, cp->n_rays, cp->max_hits);
+  if (workspace_bytes < L.total) return fail(BVC_EINVAL, "workspace too small");
+  char* w = (char*)workspace;
+  int* wn = (int*)(w + L.wind);
+  double* slot_x = (double*)(w + L.slot_x);
+  double* slot_R0 = (double*)(w + L.slot_R0);
+  double* slot_w = (double*)(w + L.slot_w);
+  int* flags = (int*)(w + L.flags);
+  int* ids = (int*)(w + L.ids);
+  int* scratch = (int*)(w + L.scratch);
+  void* EX = w + L.ex;
+  void* U = w + L.u;
+  if (dim == 2 && !wind) {
+    rc = launch_point_winding(s->h, n, x, wn, st);
+    if (rc) return rc;
+    wind = wn;
+  }
+  rc = launch_ray_hits(s->h, n, x, wind, cp->l, cp->sides, cp->c, bvc_clamp_radius(dim, cp->c), cp->n_rays,
+                       cp->max_hits, p->seed, p->batch, slot_x, slot_R0, slot_w, flags,
+                       (unsigned long long*)counters, st);
+  if (rc) return rc;
+  int64_t count = 0;
+  rc = bvc_compact((int64_t)slots, flags, 1, ids, scratch, &count, stream);
+  if (rc) return rc;
+  if (count > 0) {
+    WalkArgs a{};
+    a.x = slot_x;
+    a.R0 = slot_R0;
+    a.ids = (const uint32_t*)ids;
+    a.ld = slots;
+    a.U = U;
+    a.exit = EX;
+    a.counters = (unsigned long long*)(counters + 2);
+    rc = run_walks(s, p, 2, count, a, st);
+    if (rc) return rc;
+  }
+  return launch_corr_sum(p->g, dim, p->dtype, n, cp->n_rays, cp->max_hits, slot_w, EX, U, out_index, u, st);
+}
 
 int bvc_cache_walks(bvc_scene s, const bvc_walk_params* p, int64_t n_cache, const double* x, const double* nrm,
                     const double* R0, const double* xbar, void* U, void* D, void* rec_exit, void* rec_w1,

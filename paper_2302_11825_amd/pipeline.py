@@ -221,7 +221,7 @@ class Prepared:
     """Per-scene state reused across solves: device scene, fields, classified
     evaluation points and the candidate count of the cache sampler."""
 
-    def __init__(self, problem, dtype=None, n_cand=None, device="cuda", eval_x=None):
+    def __init__(self, problem, dtype=None, n_cand=None, device="cuda", eval_x=None, clamp=None):
         self.p = problem
         self.dtype = dtype or problem.precision
         self.sc = Scene(problem.scene, device)
@@ -238,6 +238,42 @@ class Prepared:
         T = DT[self.dtype]
         self.x_int = take(self.eval64, self.idx_int, self.n_int, self.sc.dim, n, T)
         self.x_band = take(self.eval64, self.idx_band, self.n_band, self.sc.dim, n, T)
+        self.clamp = None
+        if clamp is not None:
+            self._prepare_clamp(clamp, device)
+
+    def _prepare_clamp(self, clamp, device):
+        """Clamped gather with bias correction (Section 3.4, Eq. 8).  clamp:
+        dict(c, n_rays, max_hits, seed).  Only gathered points within the
+        clamp radius of the offset boundary can receive a correction; they
+        are found here once (classification against l + radius) with their
+        FP64 coordinates, 2D winding numbers and the correction's workspace."""
+        p, sc, d = self.p, self.sc, self.sc.dim
+        c = float(clamp["c"])
+        r = B.bvc_clamp_radius(d, c)
+        n_int = self.n_int
+        pos = torch.zeros(1, dtype=torch.int64, device=device)
+        n_near = 0
+        if n_int:
+            x64 = take(self.eval64, self.idx_int, n_int, d, self.eval64.shape[1], torch.float64)
+            cls, _ = classify(sc, x64, p.offset + r)
+            near, n_near = sc.compact(cls[:n_int], 2)
+            pos = near[:max(n_near, 1)].to(torch.int64)
+        if n_near:
+            xn = take(self.eval64, self.idx_int[pos].contiguous(), n_near, d, self.eval64.shape[1], torch.float64)
+        else:
+            xn = torch.zeros(d, 1, dtype=torch.float64, device=device)
+        wind = None
+        if d == 2 and n_near:
+            wind = torch.empty(n_near, dtype=torch.int32, device=device)
+            B.bvc_point_winding(sc.h, n_near, xn, wind)
+        n_rays, max_hits = int(clamp.get("n_rays", 16)), int(clamp.get("max_hits", 4))
+        nbytes = B.bvc_clamp_workspace_bytes(d, CODE[self.dtype], n_near, n_rays, max_hits)
+        self.clamp = dict(c=c, radius=r, n_near=n_near, pos=pos, x=xn, wind=wind,
+                          cp=B.clamp_params(p.offset, p.sides, c, n_rays, max_hits),
+                          seed=int(clamp.get("seed", p.seed_walks + 1)),
+                          ws=torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device),
+                          counters=torch.zeros(6, dtype=torch.int64, device=device))
 
 
 class SceneBatch:
@@ -438,11 +474,19 @@ def solve(prep: Prepared, batch=0, with_grad=True, n_walks_band=None, records=Fa
     n_int = prep.n_int
     u_int = torch.empty(max(n_int, 1), dtype=T, device=sc.device)
     g_int = torch.empty(d, max(n_int, 1), dtype=T, device=sc.device) if with_grad else None
+    cl = prep.clamp
+    cc = cl["c"] if cl else 0.0
     with watch.stage("gather"):
         if with_grad:
-            B.bvc_gather_grad(d, cview, sview, n_int, prep.x_int, u_int, g_int)
+            B.bvc_gather_grad(d, cview, sview, n_int, prep.x_int, u_int, g_int, clamp=cc)
         else:
-            B.bvc_gather_u(d, cview, sview, n_int, prep.x_int, u_int)
+            B.bvc_gather_u(d, cview, sview, n_int, prep.x_int, u_int, clamp=cc)
+    if cl:
+        # the second integral of Eq. 8 at the gathered points near the offset boundary
+        wpc = walk_params(p.eps, 1, cl["seed"], prep.g, prep.f, dt, batch)
+        with watch.stage("clamp_correction"):
+            B.bvc_clamp_correction(sc.h, wpc, cl["cp"], cl["n_near"], cl["x"], cl["wind"], cl["pos"], u_int,
+                                   cl["ws"], cl["counters"])
     Wb = n_walks_band or p.n_walks
     nb = prep.n_band
     wpb = walk_params(p.eps, Wb, p.seed_walks, prep.g, prep.f, dt, batch)

@@ -1,0 +1,280 @@
+"""GPU parity of the clamped gather and its bias correction (Section 3.4,
+Eqs. 8-9) against the FP64 oracle, through the C-ABI (marked gpu).
+
+- Clamped gather: u with dG/dn clamped to [-c, c] matches the oracle's
+  clamped sum (FP64: 1e-11 of the sum of |terms|; FP32: the per-term FP32
+  bound of the plain gather test); the gradient stays the unclamped one.
+- Correction, FP64 walks: ray directions, crossings of the offset boundary,
+  weights and walk ids are the oracle's, so each point's correction matches
+  the oracle's to 1e-9 of its scale, point by point, for at least 99% of the
+  points (the rest may differ when an ulp flips a walk's termination or a
+  crossing decision), and the crossing / walk counters agree.
+- Correction, FP32 walks: the mean difference from the FP64 oracle on the
+  same streams is zero within its error (z-test).
+- Edges: no points, points out of reach (nothing added), max_hits = 1 (the
+  rays over capacity are counted as the oracle counts them), out_index
+  scatter into existing values, argument errors.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+from gpu_helpers import lib, to_np_aos
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    return lib()
+
+
+def _case(dim, seed):
+    rng = np.random.default_rng(seed)
+    N, K = 1300, 1537  # several tiles and ragged tails
+    th = rng.normal(0, 1, (N, dim))
+    cy = th / np.linalg.norm(th, axis=1, keepdims=True)
+    cn = cy.copy()
+    a = rng.normal(0, 1, N) / N * 50
+    b = rng.normal(0, 1, N) / N
+    # evaluation points, many close to the cache (where the clamp acts)
+    r = np.concatenate([0.95 * rng.random(K - 600) ** (1.0 / dim), 1 - 10 ** rng.uniform(-3, -1, 600)])
+    v = rng.normal(0, 1, (K, dim))
+    ex = v / np.linalg.norm(v, axis=1, keepdims=True) * r[:, None]
+    return ex, cy, cn, a, b
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_clamped_gather_matches_oracle(B, orc, dim, dtype):
+    _bvc, pl = B
+    say(f"clamped gather dim={dim} {dtype}")
+    ex, cy, cn, a, b = _case(dim, 7 + dim)
+    T = torch.float64 if dtype == "f64" else torch.float32
+    code = _bvc.F64 if dtype == "f64" else _bvc.F32
+    dev = lambda v: torch.from_numpy(np.ascontiguousarray(v.T if v.ndim == 2 else v)).to("cuda", T)
+    cache = dict(n=cy.shape[0], dtype=code, x=dev(cy), nrm=dev(cn), a=dev(a), b=dev(b))
+    K = ex.shape[0]
+    c = 2.0 if dim == 2 else 1.0
+    u = torch.empty(K, dtype=T, device="cuda")
+    g = torch.empty(dim, K, dtype=T, device="cuda")
+    u2 = torch.empty(K, dtype=T, device="cuda")
+    _bvc.bvc_gather_grad(dim, cache, None, K, dev(ex), u, g, clamp=c)
+    _bvc.bvc_gather_u(dim, cache, None, K, dev(ex), u2, clamp=c)
+    torch.cuda.synchronize()
+    r64 = lambda t: t.double().cpu().numpy()
+    cy_r, cn_r, a_r, b_r, ex_r = (to_np_aos(cache["x"]), to_np_aos(cache["nrm"]), r64(cache["a"]), r64(cache["b"]),
+                                  to_np_aos(dev(ex)))
+    uo = orc.gather_clamped(dim, ex_r, cy_r, cn_r, a_r, b_r, c)
+    u_plain, go, cond = orc.gather(dim, ex_r, cy_r, cn_r, a_r, b_r, with_grad=True, with_cond=True)
+    assert np.mean(np.abs(uo - u_plain) > 1e-6 * cond) > 0.2  # the clamp acts at many points
+    ug = u.double().cpu().numpy()
+    if dtype == "f64":
+        tol = 1e-11 * cond
+        assert np.all(np.abs(ug - uo) <= tol)
+        assert np.all(np.abs(u2.cpu().numpy() - uo) <= tol)
+        gs = np.abs(go).max(1) + cond
+        assert np.all(np.abs(to_np_aos(g) - go).max(1) <= 1e-10 * gs)
+    else:
+        uu = 2.0**-24
+        rmin = np.min(np.linalg.norm(ex_r[:, None, :] - cy_r[None], axis=2), axis=1)
+        zmax = np.linalg.norm(cy_r, axis=1).max()
+        tol = uu * cond * (300 + 4 * (np.linalg.norm(ex_r, axis=1) + zmax) / rmin) + uu * np.abs(uo)
+        assert np.all(np.abs(ug - uo) <= tol), np.max(np.abs(ug - uo) / tol)
+        assert np.all(np.abs(u2.double().cpu().numpy() - uo) <= tol)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_clamped_gather_fp32_near_field(B, orc, dim):
+    """FP32 with the FP64 near field: the near pairs are clamped in FP64."""
+    _bvc, pl = B
+    say(f"clamped gather fp32 near field dim={dim}")
+    ex, cy, cn, a, b = _case(dim, 30 + dim)
+    f32 = lambda v: v.astype(np.float32).astype(np.float64)
+    ex, cy, cn, a, b = (f32(v) for v in (ex, cy, cn, a, b))
+    K = ex.shape[0]
+    F, D = torch.float32, torch.float64
+    dev = lambda x, T: torch.from_numpy(np.ascontiguousarray(x.T if x.ndim == 2 else x)).to("cuda", T)
+    cache = dict(n=cy.shape[0], dtype=_bvc.F32, x=dev(cy, F), nrm=dev(cn, F), a=dev(a, F), b=dev(b, F))
+    near = dict(tau=0.05, x=dev(ex, D), cx=dev(cy, D), cn=dev(cn, D), a=dev(a, D), b=dev(b, D))
+    c = 2.0 if dim == 2 else 1.0
+    u = torch.empty(K, dtype=F, device="cuda")
+    _bvc.bvc_gather_u(dim, cache, None, K, dev(ex, F), u, near=near, clamp=c)
+    torch.cuda.synchronize()
+    uo = orc.gather_clamped(dim, ex, cy, cn, a, b, c)
+    _, cond = orc.gather(dim, ex, cy, cn, a, b, with_grad=False, with_cond=True)
+    uu = 2.0**-24
+    rmin = np.maximum(np.min(np.linalg.norm(ex[:, None, :] - cy[None], axis=2), axis=1), 0.05)
+    tol = uu * cond * (300 + 4 * (np.linalg.norm(ex, axis=1) + 1) / rmin) + uu * np.abs(uo)
+    err = np.abs(u.double().cpu().numpy() - uo)
+    assert np.all(err <= tol), np.max(err / tol)
+
+
+def l_shape():
+    verts = np.array([[0.0, 0.0], [2.0, 0.0], [2.0, 1.0], [1.0, 1.0], [1.0, 2.0], [0.0, 2.0]])
+    prims = np.array([[i, (i + 1) % 6] for i in range(6)], dtype=np.int32)
+    return wl.Scene(2, verts, prims, "l_shape")
+
+
+CORR_CASES = {
+    # scene, g, f, l, sides, c, n_rays, max_hits, n points
+    "circle": lambda: (wl.circle_polygon(128), wl.harmonic_2d(3, 1.0, 1.0), None, 0.03, 1, 4.0, 16, 4, 300),
+    "star_selfintersecting": lambda: (wl.star_polygon(512, 11, jitter="isotropic"), wl.harmonic_2d(3, 1.0, 1.0),
+                                      None, 0.01, 2, 2.0, 16, 4, 300),
+    "l_shape_poisson": lambda: (l_shape(), wl.harmonic_2d(3, 1.0, 1.0), wl.Field(1, np.zeros(0), (1.5,)), 0.05, 1,
+                                2.0, 16, 4, 300),
+    "sphere_3d": lambda: (wl.displaced_icosphere(2, 5, amp=0.5), wl.solid_harmonics_3d(
+        np.random.default_rng(1).normal(0, 1, 81), 8), None, 0.03, 1, 4.0, 16, 4, 200),
+}
+
+
+def _near_points(osc, scene, l, r, n, seed):
+    """Points inside {d > l} within l + r of the boundary (all in reach)."""
+    rng = np.random.default_rng(seed)
+    lo, hi = scene.bbox
+    out = []
+    while len(out) < n:
+        x = rng.uniform(lo, hi, (20 * n, scene.dim))
+        d, _, _ = osc.closest(x)
+        ok = (d > l * 1.02) & (d < l + 0.9 * r) & (osc.inside(x) != 0)
+        out.extend(x[ok])
+    return np.array(out[:n])
+
+
+def _run_correction(_bvc, pl, scene, g, f, l, sides, c, n_rays, max_hits, x, dtype, seed=99, u0=None, out=None,
+                    batch=2):
+    sc = pl.Scene(scene)
+    gd = pl.DeviceField(g)
+    fd = pl.DeviceField(f) if f is not None else None
+    d = scene.dim
+    n = x.shape[0]
+    T = torch.float64 if dtype == "f64" else torch.float32
+    x64 = torch.from_numpy(np.ascontiguousarray(x.T)).to("cuda", torch.float64)
+    wind = None
+    if d == 2 and n:
+        wind = torch.empty(n, dtype=torch.int32, device="cuda")
+        _bvc.bvc_point_winding(sc.h, n, x64, wind)
+    m = n if u0 is None else u0.size
+    u = torch.from_numpy(np.zeros(max(m, 1)) if u0 is None else u0.copy()).to("cuda", T)
+    wp = pl.walk_params(1e-4, 1, seed, gd, fd, dtype, batch)
+    cp = _bvc.clamp_params(l, sides, c, n_rays, max_hits)
+    ws = torch.empty(max(_bvc.bvc_clamp_workspace_bytes(d, _bvc.F64 if dtype == "f64" else _bvc.F32, n, n_rays,
+                                                         max_hits), 256), dtype=torch.uint8, device="cuda")
+    cnt = torch.zeros(6, dtype=torch.int64, device="cuda")
+    oi = None if out is None else torch.from_numpy(out.astype(np.int64)).to("cuda")
+    _bvc.bvc_clamp_correction(sc.h, wp, cp, n, x64, wind, oi, u, ws, cnt)
+    torch.cuda.synchronize()
+    return u.double().cpu().numpy()[:m], cnt.cpu().numpy()
+
+
+@pytest.mark.parametrize("case", list(CORR_CASES))
+def test_correction_fp64_matches_oracle(B, orc, case):
+    _bvc, pl = B
+    scene, g, f, l, sides, c, S, H, n = CORR_CASES[case]()
+    say(f"clamp correction fp64 {case}")
+    osc = orc.Scene(scene)
+    r = orc.clamp_radius(scene.dim, c)
+    x = _near_points(osc, scene, l, r, n, 5)
+    u, cnt = _run_correction(_bvc, pl, scene, g, f, l, sides, c, S, H, x, "f64")
+    P = orc.walk_params(1e-4, 1, 99, batch=2)
+    ref, st = orc.clamp_correction(osc, g, f, P, l, sides, c, S, H, x)
+    say(f"  crossings gpu {cnt[0]} oracle {st[0]}, walks gpu {cnt[5]} oracle {st[1]}, over {cnt[1]}/{st[2]}")
+    assert st[1] > 100
+    assert abs(int(cnt[0]) - int(st[0])) <= max(2, 0.002 * st[0])
+    assert abs(int(cnt[5]) - int(st[1])) <= max(2, 0.002 * st[1])
+    assert cnt[4] == 0 and cnt[3] > 0
+    scale = np.sqrt(np.mean(ref**2)) + 1e-300
+    ok = np.abs(u - ref) <= 1e-9 * np.maximum(np.abs(ref), scale)
+    say(f"  point match {ok.mean():.4f}")
+    assert ok.mean() >= 0.99
+    assert np.abs(ref).max() > 1e-3
+
+
+@pytest.mark.parametrize("case", ["circle", "sphere_3d"])
+def test_correction_fp32_statistical(B, orc, case):
+    _bvc, pl = B
+    scene, g, f, l, sides, c, S, H, n = CORR_CASES[case]()
+    say(f"clamp correction fp32 {case}")
+    osc = orc.Scene(scene)
+    x = _near_points(osc, scene, l, orc.clamp_radius(scene.dim, c), n, 6)
+    u, cnt = _run_correction(_bvc, pl, scene, g, f, l, sides, c, S, H, x, "f32")
+    ref, st = orc.clamp_correction(orc.Scene(scene), g, f, orc.walk_params(1e-4, 1, 99, batch=2), l, sides, c, S,
+                                   H, x)
+    diff = u - ref
+    z = diff.mean() / (diff.std(ddof=1) / np.sqrt(diff.size) + 1e-300)
+    say(f"  mean diff z = {z:.2f}, walks gpu {cnt[5]} oracle {st[1]}")
+    assert abs(z) < 4.5
+    # the FP32 path makes the same crossing decisions up to rounding
+    assert abs(int(cnt[5]) - int(st[1])) <= max(4, 0.01 * st[1])
+
+
+def test_correction_edges(B, orc):
+    _bvc, pl = B
+    say("clamp correction edges")
+    scene, g, f, l, sides, c, S, H, n = CORR_CASES["circle"]()
+    osc = orc.Scene(scene)
+    r = orc.clamp_radius(2, c)
+    # no points: counters zeroed, nothing written
+    u, cnt = _run_correction(_bvc, pl, scene, g, f, l, sides, c, S, H, np.zeros((0, 2)), "f64", u0=np.full(3, 7.0))
+    assert np.all(u == 7.0) and np.all(cnt == 0)
+    # points out of reach of every crossing: the values stay as they were
+    far = np.array([[0.0, 0.0], [0.3, -0.2], [-0.5, 0.1]])
+    u, cnt = _run_correction(_bvc, pl, scene, g, f, l, sides, c, S, H, far, "f64", u0=np.array([1.0, 2.0, 3.0]))
+    assert np.array_equal(u, [1.0, 2.0, 3.0]) and cnt[0] == 0 and cnt[5] == 0
+    # max_hits = 1 on the self-intersecting star: the rays over capacity are
+    # the oracle's, and the kept crossing is the nearest contributing one
+    scene2, g2, f2, l2, s2, c2, S2, _, _ = CORR_CASES["star_selfintersecting"]()
+    osc2 = orc.Scene(scene2)
+    x2 = _near_points(osc2, scene2, l2, orc.clamp_radius(2, c2), 200, 8)
+    u1, cnt1 = _run_correction(_bvc, pl, scene2, g2, f2, l2, s2, c2, S2, 1, x2, "f64")
+    ref1, st1 = orc.clamp_correction(osc2, g2, f2, orc.walk_params(1e-4, 1, 99, batch=2), l2, s2, c2, S2, 1, x2)
+    assert st1[2] > 0 and abs(int(cnt1[1]) - int(st1[2])) <= max(2, 0.01 * st1[2])
+    scale = np.sqrt(np.mean(ref1**2)) + 1e-300
+    assert np.mean(np.abs(u1 - ref1) <= 1e-9 * np.maximum(np.abs(ref1), scale)) >= 0.99
+    # out_index: corrections land at the given positions, added to what is there
+    x = _near_points(osc, scene, l, r, 50, 9)
+    perm = np.random.default_rng(3).permutation(80)[:50]
+    base = np.random.default_rng(4).normal(0, 1, 80)
+    u, _ = _run_correction(_bvc, pl, scene, g, f, l, sides, c, S, H, x, "f64", u0=base, out=perm)
+    u_id, _ = _run_correction(_bvc, pl, scene, g, f, l, sides, c, S, H, x, "f64")
+    want = base.copy()
+    want[perm] += u_id
+    assert np.allclose(u, want, rtol=1e-14, atol=1e-14)
+    rest = np.setdiff1d(np.arange(80), perm)
+    assert np.array_equal(u[rest], base[rest])
+
+
+def test_correction_argument_errors(B):
+    _bvc, pl = B
+    say("clamp correction argument errors")
+    sc = pl.Scene(wl.circle_polygon(32))
+    gd = pl.DeviceField(wl.harmonic_2d(3, 1.0, 1.0))
+    wp = pl.walk_params(1e-4, 1, 1, gd, None, "f64")
+    x = torch.zeros(2, 4, dtype=torch.float64, device="cuda")
+    u = torch.zeros(4, dtype=torch.float64, device="cuda")
+    ws = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+    cnt = torch.zeros(6, dtype=torch.int64, device="cuda")
+    for cp in (_bvc.clamp_params(0.05, 1, 0.0, 4, 2), _bvc.clamp_params(0.05, 1, 1.0, 0, 2),
+               _bvc.clamp_params(0.05, 1, 1.0, 4, 65), _bvc.clamp_params(-1.0, 1, 1.0, 4, 2),
+               _bvc.clamp_params(0.05, 3, 1.0, 4, 2)):
+        with pytest.raises(_bvc.BVCError):
+            _bvc.bvc_clamp_correction(sc.h, wp, cp, 4, x, None, None, u, ws, cnt)
+    # a workspace that is too small
+    with pytest.raises(_bvc.BVCError):
+        _bvc.bvc_clamp_correction(sc.h, wp, _bvc.clamp_params(0.05, 1, 1.0, 4, 2), 4, x, None, None, u, ws[:256],
+                                  cnt)
+    sc3 = pl.Scene(wl.icosphere(1))
+    g3 = pl.DeviceField(wl.solid_harmonics_3d(np.ones(4), 1))
+    wp3 = pl.walk_params(1e-4, 1, 1, g3, None, "f64")
+    with pytest.raises(_bvc.BVCError):
+        _bvc.bvc_clamp_correction(sc3.h, wp3, _bvc.clamp_params(0.05, 2, 1.0, 4, 2), 4,
+                                  torch.zeros(3, 4, dtype=torch.float64, device="cuda"), None, None, u, ws, cnt)
