@@ -51,9 +51,12 @@ def parse():
     ap.add_argument("--no-pointwise", action="store_true", help="skip the pointwise-WoS comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4a", "c4b"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4a", "c4b", "c2clamp"],
                     help="c2 prints the benchmark line; the others print their own measurement lines")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes (no autotuning)")
+    ap.add_argument("--clamp-c", type=float, default=20.0, help="c2clamp: bound c of dG/dn (Eq. 9)")
+    ap.add_argument("--clamp-rays", type=int, default=64, help="c2clamp: rays per corrected point")
+    ap.add_argument("--clamp-hits", type=int, default=4, help="c2clamp: contributing crossings kept per ray")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="copy this many MiB device-to-device before timing (HBM counter calibration)")
     return ap.parse_args()

@@ -299,7 +299,9 @@ int bvc_gather_grad(int32_t dim, const bvc_cache_view* cache, const bvc_source_v
  * Philox pair of block j, id k, batch, tag 5 (2D angle 2 pi ua; 3D
  * z = 1 - 2 ua, azimuth 2 pi ub); the contributing crossings of a ray are
  * ranked h = 0, 1, ... nearest first, at most max_hits are kept, and crossing
- * h walks with id (k n_rays + j) max_hits + h, tag 2 (as bvc_pointwise_wos).
+ * h walks with id (k n_rays + j) max_hits + h, tag 2, as bvc_pointwise_wos
+ * walks (a crossing already closer than eps to the boundary returns g at its
+ * closest boundary point).
  * Use a walk seed other than the band walks' so the two sets are independent. */
 typedef struct {
   double l;          /* offset distance of the cache boundary */

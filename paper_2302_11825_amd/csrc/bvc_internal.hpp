@@ -141,7 +141,8 @@ int launch_batch_gather(const BatchDev& b, hipStream_t st);
 // Clamping correction launchers (kernels_clamp.hip).
 int launch_ray_hits(const SceneHost& h, int64_t n, const double* x, const int* wind, double l, int sides, double c,
                     double t_max, int n_rays, int max_hits, uint64_t seed, uint32_t batch, double* slot_x,
-                    double* slot_R0, double* slot_w, int* flags, unsigned long long* counters, hipStream_t st);
+                    double* slot_R0, double* slot_xbar, double* slot_w, int* flags, unsigned long long* counters,
+                    hipStream_t st);
 int launch_point_winding(const SceneHost& h, int64_t n, const double* x, int* wind, hipStream_t st);
 int launch_corr_sum(const bvc_field& g, int dim, int dtype, int64_t n, int n_rays, int max_hits,
                     const double* slot_w, const void* EX, const void* U, const int64_t* out, void* u,

@@ -50,6 +50,7 @@ struct RayArgs {
   uint64_t slots;      // n * n_rays * max_hits
   double* slot_x;      // [D][slots] crossing points
   double* slot_R0;     // [slots] their distance to the boundary
+  double* slot_xbar;   // [D][slots] their closest boundary points
   double* slot_w;      // [slots] weight; 0 marks an empty slot
   int* flags;          // [slots] 1 where a walk is needed
   unsigned long long* counters;  // [0] contributing crossings, [1] rays over capacity
@@ -388,7 +389,10 @@ __global__ __launch_bounds__(kRayBlock) void k_ray_hits(RayArgs a) {
       const double kv = dgdn_at<D>(C.t[i], dotd<D>(C.nrm[i], w));
       const uint64_t s = base + h;
 #pragma unroll
-      for (int q = 0; q < D; ++q) a.slot_x[q * a.slots + s] = z[q];
+      for (int q = 0; q < D; ++q) {
+        a.slot_x[q * a.slots + s] = z[q];
+        a.slot_xbar[q * a.slots + s] = qz[q];
+      }
       a.slot_R0[s] = d;
       a.slot_w[s] = (kv > 0.0 ? 1.0 : -1.0) * (1.0 - a.c / fabs(kv));
       a.flags[s] = 1;
@@ -419,14 +423,17 @@ __global__ __launch_bounds__(256) void k_point_winding(SceneDev S, int64_t n, co
 
 // corr_k = (1/n_rays) sum over the slots of point k of weight * u(z), with
 // u(z) = g(exit) + the walk's source terms, in FP64; added to u[out[k]].
+// One wave per point: lane l reads slots l, l + 64, ... of the point's
+// contiguous run (coalesced), then a shuffle tree sums the lanes.
 template <typename T, int D>
 __global__ __launch_bounds__(256) void k_corr_sum(FieldDev g, int64_t n, int per, int n_rays, uint64_t slots,
                                                   const double* slot_w, const T* EX, const T* U, const int64_t* out,
                                                   T* u) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int64_t k = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
   if (k >= n) return;
   double acc = 0.0;
-  for (int m = 0; m < per; ++m) {
+  for (int m = lane; m < per; m += 64) {
     const uint64_t s = (uint64_t)k * per + m;
     const double wv = slot_w[s];
     if (wv == 0.0) continue;
@@ -435,15 +442,19 @@ __global__ __launch_bounds__(256) void k_corr_sum(FieldDev g, int64_t n, int per
     for (int e = 0; e < D; ++e) q[e] = (double)EX[(size_t)e * slots + s];
     acc += wv * (field_value(g, D, q) + (double)U[s]);
   }
-  const int64_t o = out ? out[k] : k;
-  u[o] = (T)((double)u[o] + acc / n_rays);
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if (lane == 0) {
+    const int64_t o = out ? out[k] : k;
+    u[o] = (T)((double)u[o] + acc / n_rays);
+  }
 }
 
 }  // namespace
 
 int launch_ray_hits(const SceneHost& h, int64_t n, const double* x, const int* wind, double l, int sides, double c,
                     double t_max, int n_rays, int max_hits, uint64_t seed, uint32_t batch, double* slot_x,
-                    double* slot_R0, double* slot_w, int* flags, unsigned long long* counters, hipStream_t st) {
+                    double* slot_R0, double* slot_xbar, double* slot_w, int* flags, unsigned long long* counters,
+                    hipStream_t st) {
   RayArgs a{};
   a.S = h.view();
   a.n = n;
@@ -460,6 +471,7 @@ int launch_ray_hits(const SceneHost& h, int64_t n, const double* x, const int* w
   a.slots = (uint64_t)n * n_rays * max_hits;
   a.slot_x = slot_x;
   a.slot_R0 = slot_R0;
+  a.slot_xbar = slot_xbar;
   a.slot_w = slot_w;
   a.flags = flags;
   a.counters = counters;
@@ -483,7 +495,7 @@ int launch_corr_sum(const bvc_field& g, int dim, int dtype, int64_t n, int n_ray
                     const double* slot_w, const void* EX, const void* U, const int64_t* out, void* u,
                     hipStream_t st) {
   if (n == 0) return BVC_OK;
-  const int blocks = (int)((n + 255) / 256);
+  const int blocks = (int)((n + 3) / 4);  // four waves (points) per block
   const uint64_t slots = (uint64_t)n * n_rays * max_hits;
   const int per = n_rays * max_hits;
   const FieldDev gd = to_dev(g);

@@ -210,13 +210,13 @@ __global__ __launch_bounds__(kBlock) void k_walks(WalkArgs a) {
             id = MODE == 2 ? a.ids[my] : (uint32_t)my;
             const int64_t i = MODE == 2 ? (int64_t)id : (int64_t)(id / (uint32_t)a.W);
             const T R0 = (T)a.R0[i];
-            if (MODE == 1 && R0 < eps) {
-              // the evaluation point already lies in the epsilon shell: its
-              // walk returns g at the closest boundary point
+            if (MODE != 0 && R0 < eps) {
+              // the start point already lies in the epsilon shell: its walk
+              // returns g at the closest boundary point
 #pragma unroll
               for (int q = 0; q < D; ++q) EX[(size_t)q * a.ld + id] = (T)a.xbar[q * a.n_pts + i];
               U[id] = T(0);
-              if (Dof) {
+              if (MODE == 1 && Dof) {
 #pragma unroll
                 for (int q = 0; q < D; ++q) {
                   Dof[(size_t)q * a.ld + id] = T(0);
@@ -792,7 +792,7 @@ int cache_walks_entry(bvc_scene s, const bvc_walk_params* p, int64_t n_cache, co
 namespace bvc {
 namespace {
 struct ClampLayout {
-  size_t wind, slot_x, slot_R0, slot_w, flags, ids, scratch, ex, u, total;
+  size_t wind, slot_x, slot_R0, slot_xbar, slot_w, flags, ids, scratch, ex, u, total;
 };
 ClampLayout clamp_layout(int dim, int dtype, int64_t n, int n_rays, int max_hits) {
   const uint64_t slots = (uint64_t)n * n_rays * max_hits;
@@ -805,6 +805,8 @@ ClampLayout clamp_layout(int dim, int dtype, int64_t n, int n_rays, int max_hits
   o += align256((size_t)dim * slots * 8);
   L.slot_R0 = o;
   o += align256(slots * 8);
+  L.slot_xbar = o;
+  o += align256((size_t)dim * slots * 8);
   L.slot_w = o;
   o += align256(slots * 8);
   L.flags = o;
@@ -875,6 +877,7 @@ int bvc_clamp_correction(bvc_scene s, const bvc_walk_params* p, const bvc_clamp_
   int* wn = (int*)(w + L.wind);
   double* slot_x = (double*)(w + L.slot_x);
   double* slot_R0 = (double*)(w + L.slot_R0);
+  double* slot_xbar = (double*)(w + L.slot_xbar);
   double* slot_w = (double*)(w + L.slot_w);
   int* flags = (int*)(w + L.flags);
   int* ids = (int*)(w + L.ids);
@@ -887,7 +890,7 @@ int bvc_clamp_correction(bvc_scene s, const bvc_walk_params* p, const bvc_clamp_
     wind = wn;
   }
   rc = launch_ray_hits(s->h, n, x, wind, cp->l, cp->sides, cp->c, bvc_clamp_radius(dim, cp->c), cp->n_rays,
-                       cp->max_hits, p->seed, p->batch, slot_x, slot_R0, slot_w, flags,
+                       cp->max_hits, p->seed, p->batch, slot_x, slot_R0, slot_xbar, slot_w, flags,
                        (unsigned long long*)counters, st);
   if (rc) return rc;
   int64_t count = 0;
@@ -897,6 +900,7 @@ int bvc_clamp_correction(bvc_scene s, const bvc_walk_params* p, const bvc_clamp_
     WalkArgs a{};
     a.x = slot_x;
     a.R0 = slot_R0;
+    a.xbar = slot_xbar;
     a.ids = (const uint32_t*)ids;
     a.ld = slots;
     a.U = U;

@@ -5,6 +5,10 @@
                                      split-BF16 MFMA vs FP32 multi-RHS vs 64 plain gathers
     python bench.py --workload c4b   32 uneven 2D scenes: one graph-replayed launch
                                      sequence vs per-scene call sequences
+    python bench.py --workload c2clamp  the 2D Poisson step with the clamped gather
+                                     and its bias correction (Section 3.4): time,
+                                     and the error near the offset boundary of the
+                                     plain, clamped-only and corrected estimates
 
 Each prints one JSON line.  Inputs are the seeded synthetic workloads.
 """
@@ -49,7 +53,7 @@ def _log(msg):
 
 
 def run(args):
-    {"c3": c3, "c4a": c4a, "c4b": c4b}[args.workload](args)
+    {"c3": c3, "c4a": c4a, "c4b": c4b, "c2clamp": c2clamp}[args.workload](args)
 
 
 def _c3_setup(args):
@@ -214,4 +218,66 @@ def c4b(args):
            "sequential_ms": t_seq, "points_per_s_graph": n_pts / (t_graph / 1e3),
            "points_per_s_sequential": n_pts / (t_seq / 1e3), "speedup_vs_sequential": t_seq / t_graph,
            "cache_sizes": [e["cache"].n for e in batch.entries], "eval_sizes": [e["n_int"] for e in batch.entries]}
+    print(json.dumps(out))
+
+
+def c2clamp(args):
+    prob = wl.problem_c2()
+    clamp = dict(c=args.clamp_c, n_rays=args.clamp_rays, max_hits=args.clamp_hits, seed=wl.seed(2, 7))
+    t = time.time()
+    plain = pl.Prepared(prob, dtype="f32")
+    prep = pl.Prepared(prob, dtype="f32", clamp=clamp)
+    cl = prep.clamp
+    torch.cuda.synchronize()
+    _log(f"c2clamp setup {time.time() - t:.1f}s: interior {prep.n_int}, near {cl['n_near']} "
+         f"(radius {cl['radius']:.4f})")
+    for _ in range(max(1, args.warmup)):
+        pl.solve(prep)
+        pl.solve(plain)
+    torch.cuda.synchronize()
+    watch = pl.Stopwatch()
+    e0, e1 = _ev(), _ev()
+    e0.record()
+    for _ in range(args.steps):
+        sol = pl.solve(prep, watch=watch)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    stages = {k: sum(v) / len(v) for k, v in watch.totals_ms().items()}
+    watch_p = pl.Stopwatch()
+    e0.record()
+    for _ in range(args.steps):
+        sol_p = pl.solve(plain, watch=watch_p)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_plain = e0.elapsed_time(e1) / args.steps
+    stages_p = {k: sum(v) / len(v) for k, v in watch_p.totals_ms().items()}
+    # errors at the gathered points within reach of the correction: plain,
+    # clamped only (the clamped gather over the same cache, no correction) and
+    # clamped + corrected; the seeds are shared, so the three use one cache
+    pos = cl["pos"][: cl["n_near"]]
+    idx_i = prep.idx_int[: prep.n_int].cpu().numpy()
+    pts = prob.eval_x[idx_i[pos.cpu().numpy()]]
+    truth = wl.field_value(prob.truth, pts)
+    n = cl["n_near"]
+    xs = prep.x_int[:, pos].contiguous()
+    u_c = torch.empty(max(n, 1), dtype=torch.float32, device="cuda")
+    B.bvc_gather_u(2, sol.extra["cview"], sol.extra["sview"], n, xs, u_c, clamp=cl["c"])
+    torch.cuda.synchronize()
+    est = {"plain": sol_p.u_int[pos].double().cpu().numpy(), "clamped_only": u_c[:n].double().cpu().numpy(),
+           "clamped_corrected": sol.u_int[pos].double().cpu().numpy()}
+    err = {k: {"rmse": float(np.sqrt(np.mean((v - truth) ** 2))), "max": float(np.max(np.abs(v - truth))),
+               "mean": float(np.mean(v - truth))} for k, v in est.items()}
+    far = np.setdiff1d(np.arange(prep.n_int), pos.cpu().numpy())
+    # beyond the clamp radius the clamp never acts: only FP32 rounding differs
+    far_diff = float(np.max(np.abs(sol.u_int[: prep.n_int].double().cpu().numpy()[far]
+                                   - sol_p.u_int[: prep.n_int].double().cpu().numpy()[far]))) if far.size else 0.0
+    c = cl["counters"].cpu().numpy()
+    out = {"workload": "c2clamp_star4096_poisson", "clamp_c": cl["c"], "clamp_radius": cl["radius"],
+           "n_rays": args.clamp_rays, "max_hits": args.clamp_hits, "interior_points": prep.n_int,
+           "corrected_points": n, "rays": n * args.clamp_rays, "contributing_crossings": int(c[0]),
+           "rays_over_capacity": int(c[1]), "correction_walks": int(c[5]), "correction_walk_steps": int(c[3]),
+           "ms_per_step": ms, "ms_per_step_plain": ms_plain, "stage_ms": stages, "stage_ms_plain": stages_p,
+           "error_near_offset_boundary": err, "far_points_max_abs_diff": far_diff,
+           "points_per_s": (prep.n_int + prep.n_band) / (ms / 1e3)}
     print(json.dumps(out))

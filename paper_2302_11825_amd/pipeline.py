@@ -481,17 +481,28 @@ def solve(prep: Prepared, batch=0, with_grad=True, n_walks_band=None, records=Fa
             B.bvc_gather_grad(d, cview, sview, n_int, prep.x_int, u_int, g_int, clamp=cc)
         else:
             B.bvc_gather_u(d, cview, sview, n_int, prep.x_int, u_int, clamp=cc)
+    gathered = None
     if cl:
-        # the second integral of Eq. 8 at the gathered points near the offset boundary
-        wpc = walk_params(p.eps, 1, cl["seed"], prep.g, prep.f, dt, batch)
-        with watch.stage("clamp_correction"):
-            B.bvc_clamp_correction(sc.h, wpc, cl["cp"], cl["n_near"], cl["x"], cl["wind"], cl["pos"], u_int,
-                                   cl["ws"], cl["counters"])
+        gathered = torch.cuda.Event()
+        gathered.record()
     Wb = n_walks_band or p.n_walks
     nb = prep.n_band
     wpb = walk_params(p.eps, Wb, p.seed_walks, prep.g, prep.f, dt, batch)
     watch.kernel("k_walks_band", wpb)
     with watch.stage("band_walks"):
         u_band, g_band, pwc = pointwise(sc, wpb, prep.x_band[:, :nb] if nb else prep.x_band[:, :0], with_grad)
+    if cl:
+        # the second integral of Eq. 8 at the gathered points near the offset
+        # boundary, on a second stream (default priority) so that it overlaps
+        # the band walks it does not depend on; it reads the gather's output
+        main = torch.cuda.current_stream()
+        side = cl.setdefault("stream", torch.cuda.Stream())
+        side.wait_event(gathered)
+        wpc = walk_params(p.eps, 1, cl["seed"], prep.g, prep.f, dt, batch)
+        with torch.cuda.stream(side):
+            with watch.stage("clamp_correction"):
+                B.bvc_clamp_correction(sc.h, wpc, cl["cp"], cl["n_near"], cl["x"], cl["wind"], cl["pos"], u_int,
+                                       cl["ws"], cl["counters"])
+        main.wait_stream(side)
     return Solution(prep.idx_int, n_int, prep.idx_band, nb, u_int, g_int, u_band, g_band, cache, uhat, dudn,
                     counters, pwc, extra=dict(U=U, D=D, a=a, b=b, cview=cview, sview=sview, rec=rec))

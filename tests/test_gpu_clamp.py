@@ -14,6 +14,9 @@ Eqs. 8-9) against the FP64 oracle, through the C-ABI (marked gpu).
 - Edges: no points, points out of reach (nothing added), max_hits = 1 (the
   rays over capacity are counted as the oracle counts them), out_index
   scatter into existing values, argument errors.
+- pipeline.solve with the clamp (FP64): clamped gather everywhere plus the
+  correction at the points within reach, against the oracle on the device's
+  own cache.
 """
 import sys
 
@@ -278,3 +281,50 @@ def test_correction_argument_errors(B):
     with pytest.raises(_bvc.BVCError):
         _bvc.bvc_clamp_correction(sc3.h, wp3, _bvc.clamp_params(0.05, 2, 1.0, 4, 2), 4,
                                   torch.zeros(3, 4, dtype=torch.float64, device="cuda"), None, None, u, ws, cnt)
+
+
+def test_pipeline_solve_with_clamp_fp64(B, orc):
+    """pipeline.solve with the clamp on (FP64): the gathered points within
+    reach receive the clamped gather plus the correction, the others the
+    clamped gather alone; both against the oracle on the device's own cache,
+    sources and walk seeds."""
+    _bvc, pl = B
+    say("pipeline solve with clamp fp64")
+    import dataclasses
+
+    # offset 5 eps as in the 2D Poisson workload: with l = eps every crossing
+    # would sit exactly on the epsilon shell, where the shell test of its walk
+    # is decided by the last ulp of two different closest-point formulas
+    prob = dataclasses.replace(wl.problem_c1(), offset=5e-3)
+    rng = np.random.default_rng(12)
+    ang = rng.uniform(0, 2 * np.pi, 400)
+    rad = np.concatenate([1 - prob.offset - rng.uniform(0.0005, 0.012, 300), rng.uniform(0, 0.9, 100)])
+    ex = np.stack([rad * np.cos(ang), rad * np.sin(ang)], 1)
+    c = 20.0
+    prep = pl.Prepared(prob, dtype="f64", eval_x=ex, clamp=dict(c=c, n_rays=8, max_hits=4, seed=555))
+    cl = prep.clamp
+    sol = pl.solve(prep, with_grad=False)
+    torch.cuda.synchronize()
+    n_int = prep.n_int
+    assert cl["n_near"] > 100 and n_int > cl["n_near"]
+    cv = sol.extra["cview"]
+    n = cv["n"]
+    cy, cn = to_np_aos(cv["x"], n), to_np_aos(cv["nrm"], n)
+    a, b = cv["a"].cpu().numpy()[:n], cv["b"].cpu().numpy()[:n]
+    idx = prep.idx_int[:n_int].cpu().numpy()
+    x = ex[idx]
+    u_ref = orc.gather_clamped(2, x, cy, cn, a, b, c)
+    pos = cl["pos"][: cl["n_near"]].cpu().numpy()
+    P = orc.walk_params(prob.eps, 1, 555)
+    corr, st = orc.clamp_correction(orc.Scene(prob.scene), prob.g, None, P, prob.offset, prob.sides, c, 8, 4, x[pos])
+    u_ref[pos] += corr
+    _, cond = orc.gather(2, x, cy, cn, a, b, with_grad=False, with_cond=True)
+    got = sol.u_int.cpu().numpy()[:n_int]
+    corr_all = np.zeros(n_int)
+    corr_all[pos] = corr
+    scale = np.sqrt(np.mean(corr**2)) + 1e-300
+    ok = np.abs(got - u_ref) <= 1e-11 * cond + 1e-9 * np.maximum(np.abs(corr_all), scale)
+    assert ok.mean() >= 0.99, ok.mean()
+    far = np.setdiff1d(np.arange(n_int), pos)
+    assert np.all(ok[far])  # out of reach: the clamped gather alone
+    assert int(cl["counters"][5]) == st[1] or abs(int(cl["counters"][5]) - int(st[1])) <= 2
