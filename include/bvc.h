@@ -74,6 +74,8 @@ extern "C" {
  *                  x-param[0]); phi_0 = 1, phi_{2j-1} = cos j theta,
  *                  phi_{2j} = sin j theta
  *   7 POINT_SOURCE 2D A ln|x-x0|, 3D A/|x-x0|, A = param[0], x0 = param[1..]
+ *   8 EXP_PLANE    A exp(a . x), A = param[0], a = param[1..dim] (solves
+ *                  Lap u = |a|^2 u: the screened equation's plane waves)
  */
 typedef struct {
   int32_t kind;

@@ -36,7 +36,8 @@ class _Field(C.Structure):
 
 class _WalkParams(C.Structure):
     _fields_ = [("eps", C.c_double), ("max_steps", C.c_int32), ("n_walks", C.c_int32),
-                ("seed", C.c_uint64), ("batch", C.c_uint32), ("control_variate", C.c_int32)]
+                ("seed", C.c_uint64), ("batch", C.c_uint32), ("control_variate", C.c_int32),
+                ("sigma", C.c_double)]
 
 
 _lib = None
@@ -101,6 +102,16 @@ def lib():
                                        C.c_uint32, C.c_int32, _dp, _ip]
         L.orc_walk_queries.restype = C.c_int32
         L.orc_bvh_visits.argtypes = [C.c_void_p, C.c_int64, _ip, _dp, _ip, C.c_int64, _dp, _ip, _dp, _dp]
+        for nm in ("orc_bessel_i0", "orc_bessel_i1", "orc_bessel_k0", "orc_bessel_k1"):
+            getattr(L, nm).argtypes = [C.c_double]
+            getattr(L, nm).restype = C.c_double
+        L.orc_greens_sigma.argtypes = [C.c_int, C.c_double, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.orc_screen_ball_weight.argtypes = [C.c_int, C.c_double, C.c_double]
+        L.orc_screen_ball_weight.restype = C.c_double
+        L.orc_screen_grad_weight.argtypes = [C.c_int, C.c_double, C.c_double]
+        L.orc_screen_grad_weight.restype = C.c_double
+        L.orc_gather_sigma.argtypes = [C.c_int, C.c_double, C.c_int64, _dp, C.c_int64, _dp, _dp, _dp, _dp,
+                                       C.c_int64, _dp, _dp, _dp, _dp, _dp]
         L.orc_clamp_radius.argtypes = [C.c_int, C.c_double]
         L.orc_clamp_radius.restype = C.c_double
         L.orc_gather_clamped.argtypes = [C.c_int, C.c_int64, _dp, C.c_int64, _dp, _dp, _dp, _dp,
@@ -264,8 +275,9 @@ class Scene:
         return y, sw
 
 
-def walk_params(eps, n_walks, seed, batch=0, max_steps=1024, control_variate=True):
+def walk_params(eps, n_walks, seed, batch=0, max_steps=1024, control_variate=True, sigma=0.0):
     P = _WalkParams()
+    P.sigma = float(sigma)
     P.eps = float(eps)
     P.max_steps = int(max_steps)
     P.n_walks = int(n_walks)
@@ -520,3 +532,54 @@ def clamp_correction(scene: Scene, g, f, params, l, sides, c, n_rays, max_hits, 
                                int(n_rays), int(max_hits), C.byref(Uh) if Uh is not None else None, n, _d(x),
                                _d(corr), st.ctypes.data_as(_lp))
     return corr, st
+
+
+# --- Screened Poisson (sigma > 0; Appendix A.2) -----------------------------
+def bessel(name, x):
+    """Modified Bessel function i0, i1, k0 or k1 of the oracle."""
+    return getattr(lib(), "orc_bessel_" + name)(float(x))
+
+
+def greens_sigma(dim, sigma, x, y, ny=None):
+    x = _f64(x)
+    y = _f64(y)
+    ny = _f64(ny) if ny is not None else np.zeros(dim)
+    G = np.zeros(1)
+    dGdx = np.zeros(dim)
+    dGdn = np.zeros(1)
+    d2 = np.zeros(dim)
+    lib().orc_greens_sigma(dim, float(sigma), _d(x), _d(y), _d(ny), _d(G), _d(dGdx), _d(dGdn), _d(d2))
+    return G[0], dGdx, dGdn[0], d2
+
+
+def screen_ball_weight(dim, sigma, R):
+    return lib().orc_screen_ball_weight(int(dim), float(sigma), float(R))
+
+
+def screen_grad_weight(dim, sigma, R):
+    return lib().orc_screen_grad_weight(int(dim), float(sigma), float(R))
+
+
+def gather_sigma(dim, sigma, ex, cy, cn, a, b, sy=None, sw=None, with_grad=True, with_cond=False):
+    ex = _f64(ex).reshape(-1, dim)
+    cy = _f64(cy).reshape(-1, dim)
+    cn = _f64(cn).reshape(-1, dim)
+    a = _f64(a)
+    b = _f64(b)
+    K, N = ex.shape[0], cy.shape[0]
+    if sy is None:
+        sy = np.zeros((0, dim))
+        sw = np.zeros(0)
+    sy = _f64(sy).reshape(-1, dim)
+    sw = _f64(sw)
+    u = np.zeros(K)
+    g = np.zeros((K, dim)) if with_grad else None
+    c = np.zeros(K) if with_cond else None
+    lib().orc_gather_sigma(dim, float(sigma), K, _d(ex), N, _d(cy), _d(cn), _d(a), _d(b), sy.shape[0], _d(sy),
+                           _d(sw), _d(u), _d(g), _d(c))
+    out = [u]
+    if with_grad:
+        out.append(g)
+    if with_cond:
+        out.append(c)
+    return out[0] if len(out) == 1 else tuple(out)

@@ -639,6 +639,11 @@ double orc_field_eval(const orc_field* F, int dim, const double* x) {
       for (int a = 0; a < dim; ++a) r2 += (x[a] - p[1 + a]) * (x[a] - p[1 + a]);
       return dim == 2 ? p[0] * 0.5 * log(r2) : p[0] / sqrt(r2);
     }
+    case ORC_FIELD_EXP_PLANE: {
+      double e = 0;
+      for (int a = 0; a < dim; ++a) e += p[1 + a] * x[a];
+      return p[0] * exp(e);
+    }
   }
   return 0.0;
 }
@@ -680,6 +685,144 @@ void orc_greens(int dim, const double* x, const double* y, const double* ny, dou
     if (dGdn) *dGdn = c * ndot / r3;
     if (d2Gdxdn)
       for (int a = 0; a < 3; ++a) d2Gdxdn[a] = c * (3 * ndot * yx[a] / (r3 * r2) - ny[a] / r3);
+  }
+}
+
+/* ======================================================================== */
+/* Screened Poisson (Eq. 1 with sigma > 0; Appendix A.2)                     */
+/* ======================================================================== */
+/* I_n(x) = sum_k (x/2)^(2k+n) / (k! (k+n)!) for moderate x; beyond, the
+ * integral (1/pi) int_0^pi e^(x cos t) cos(n t) dt by the trapezoid rule,
+ * which is exponentially accurate for this periodic integrand. */
+static double bessel_i(int n, double x) {
+  x = fabs(x);
+  if (x <= 20.0) {
+    double h = 0.5 * x, term = n ? h : 1.0, sum = term;
+    for (int k = 1; k < 200; ++k) {
+      term *= h * h / ((double)k * (double)(k + n));
+      sum += term;
+      if (term < 1e-18 * sum) break;
+    }
+    return sum;
+  }
+  int N = (int)(2 * x + 40);
+  double sum = 0;
+  for (int j = 0; j <= N; ++j) {
+    double t = ORC_PI * j / N;
+    double f = exp(x * cos(t)) * cos(n * t);
+    sum += (j == 0 || j == N) ? 0.5 * f : f;
+  }
+  return sum / N;
+}
+/* K_n(x) = int_0^inf e^(-x cosh t) cosh(n t) dt by the trapezoid rule, which
+ * is exponentially accurate for this even, analytic integrand; the step
+ * follows the width of its peak at t = 0 (about 1/sqrt(x) for large x). */
+static double bessel_k(int n, double x) {
+  double h = 0.1 / fmax(1.0, sqrt(x) / 3.0);
+  double tmax = acosh(fmax(750.0 / x, 1.0)) + 1.0;
+  double sum = 0.5 * exp(-x);
+  for (int j = 1;; ++j) {
+    double t = h * j;
+    if (t > tmax) break;
+    sum += exp(-x * cosh(t)) * cosh(n * t);
+  }
+  return h * sum;
+}
+double orc_bessel_i0(double x) { return bessel_i(0, x); }
+double orc_bessel_i1(double x) { return bessel_i(1, x); }
+double orc_bessel_k0(double x) { return bessel_k(0, x); }
+double orc_bessel_k1(double x) { return bessel_k(1, x); }
+
+void orc_greens_sigma(int dim, double sigma, const double* x, const double* y, const double* ny,
+                      double* G, double* dGdx, double* dGdn, double* d2Gdxdn) {
+  if (!(sigma > 0)) {
+    orc_greens(dim, x, y, ny, G, dGdx, dGdn, d2Gdxdn);
+    return;
+  }
+  /* G^s = -K0(sr)/(2pi) (2D), -e^(-sr)/(4 pi r) (3D); the derivatives are the
+   * Poisson ones times Q (Appendix A.2): Q = sr K1(sr) (2D),
+   * e^(-sr)(1 + sr) (3D), and dQ/dx = s^2 K0(sr)(y - x) (2D),
+   * s^2 e^(-sr)(y - x) (3D). */
+  double G0, g0[3], n0 = 0, d0[3];
+  orc_greens(dim, x, y, ny, &G0, g0, ny ? &n0 : NULL, ny ? d0 : NULL);
+  double yx[3] = {0, 0, 0}, r2 = 0;
+  for (int a = 0; a < dim; ++a) {
+    yx[a] = y[a] - x[a];
+    r2 += yx[a] * yx[a];
+  }
+  double r = sqrt(r2), s = sqrt(sigma), sr = s * r;
+  double Q, dq; /* dQ/dx = dq (y - x) */
+  if (dim == 2) {
+    double k0 = bessel_k(0, sr), k1 = bessel_k(1, sr);
+    if (G) *G = -k0 / (2 * ORC_PI);
+    Q = sr * k1;
+    dq = sigma * k0;
+  } else {
+    double e = exp(-sr);
+    if (G) *G = -e / (4 * ORC_PI * r);
+    Q = e * (1 + sr);
+    dq = sigma * e;
+  }
+  if (dGdx)
+    for (int a = 0; a < dim; ++a) dGdx[a] = Q * g0[a];
+  if (dGdn) *dGdn = Q * n0;
+  if (d2Gdxdn)
+    for (int a = 0; a < dim; ++a) d2Gdxdn[a] = Q * d0[a] + n0 * dq * yx[a];
+}
+
+/* i1(x) = (x cosh x - sinh x)/x^2, the modified spherical Bessel function of
+ * order 1, by its series sum_k x^(2k+1) / (2^k k! (2k+3)!!) below 1. */
+static double sph_i1(double x) {
+  if (x < 1.0) {
+    double term = x / 3.0, sum = term;
+    for (int k = 1; k < 30; ++k) {
+      term *= x * x / (2.0 * k * (2.0 * k + 3.0));
+      sum += term;
+    }
+    return sum;
+  }
+  return (x * cosh(x) - sinh(x)) / (x * x);
+}
+
+double orc_screen_ball_weight(int dim, double sigma, double R) {
+  if (!(sigma > 0)) return 1.0;
+  double x = sqrt(sigma) * R;
+  if (dim == 2) return 1.0 / bessel_i(0, x);
+  return x < 1e-8 ? 1.0 : x / sinh(x);
+}
+
+double orc_screen_grad_weight(int dim, double sigma, double R) {
+  if (!(sigma > 0)) return dim / R;
+  double s = sqrt(sigma), x = s * R;
+  if (dim == 2) return s / bessel_i(1, x);
+  return s / sph_i1(x);
+}
+
+void orc_gather_sigma(int dim, double sigma, int64_t K, const double* ex, int64_t N, const double* cy,
+                      const double* cn, const double* a, const double* b, int64_t M, const double* sy,
+                      const double* sw, double* u, double* grad, double* cond) {
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t k = 0; k < K; ++k) {
+    const double* x = ex + k * dim;
+    double uk = 0, ck = 0, gk[3] = {0, 0, 0};
+    for (int64_t i = 0; i < N; ++i) {
+      double G, dGdx[3], dGdn, d2[3];
+      orc_greens_sigma(dim, sigma, x, cy + i * dim, cn + i * dim, &G, dGdx, &dGdn, d2);
+      uk += dGdn * a[i] - G * b[i];
+      ck += fabs(dGdn * a[i]) + fabs(G * b[i]);
+      for (int q = 0; q < dim; ++q) gk[q] += d2[q] * a[i] - dGdx[q] * b[i];
+    }
+    for (int64_t j = 0; j < M; ++j) {
+      double G, dGdx[3];
+      orc_greens_sigma(dim, sigma, x, sy + j * dim, NULL, &G, dGdx, NULL, NULL);
+      uk += G * sw[j];
+      ck += fabs(G * sw[j]);
+      for (int q = 0; q < dim; ++q) gk[q] += dGdx[q] * sw[j];
+    }
+    u[k] = uk;
+    if (cond) cond[k] = ck;
+    if (grad)
+      for (int q = 0; q < dim; ++q) grad[k * dim + q] = gk[q];
   }
 }
 
@@ -1020,21 +1163,26 @@ void orc_walk(const orc_scene* s, const orc_field* g, const orc_field* f,
       f_g = orc_field_eval(f, dim, yg);
     }
   }
-  /* Walk on spheres from the first-ball point. */
-  double S = 0, W = 0, pb[3] = {0, 0, 0};
+  /* Walk on spheres from the first-ball point.  With screening every ball
+   * the walk crosses multiplies the estimate by its mean-value factor; the
+   * first ball's factor is applied to U below, not to W (the estimate of u at
+   * the first-ball point that the gradient uses). */
+  const int screened = p->sigma > 0;
+  double S = 0, W = 0, pb[3] = {0, 0, 0}, thr = 1.0;
   int32_t k;
   for (k = 1;; ++k) {
     double d;
     orc_closest(s, pos, 0, &d, pb, NULL);
     if (d < p->eps) {
-      W = orc_field_eval(g, dim, pb) + S;
+      W = screened ? thr * orc_field_eval(g, dim, pb) : orc_field_eval(g, dim, pb) + S;
       break;
     }
     if (k >= p->max_steps) {
-      W = orc_field_eval(g, dim, pb) + S;
+      W = screened ? thr * orc_field_eval(g, dim, pb) : orc_field_eval(g, dim, pb) + S;
       *capped = 1;
       break;
     }
+    if (screened) thr *= orc_screen_ball_weight(dim, p->sigma, d);
     if (has_f) {
       double y[3];
       ball_source_point(p->seed, (uint32_t)k, id, p->batch, tag, dim, pos, d, y);
@@ -1045,16 +1193,23 @@ void orc_walk(const orc_scene* s, const orc_field* g, const orc_field* f,
     for (int a = 0; a < dim; ++a) pos[a] += d * nu[a];
   }
   *steps = k;
-  *U = W - R0 * R0 / (2.0 * dim) * f_u;
+  double gw = dim / R0;
+  if (screened) {
+    /* the screened in-ball source term is not built: a source is refused */
+    *U = has_f ? NAN : orc_screen_ball_weight(dim, p->sigma, R0) * W;
+    gw = orc_screen_grad_weight(dim, p->sigma, R0);
+  } else {
+    *U = W - R0 * R0 / (2.0 * dim) * f_u;
+  }
   double c = p->control_variate ? orc_field_eval(g, dim, xbar) : 0.0;
   double wn = 0;
   for (int a = 0; a < dim; ++a) {
-    grad[a] = dim / R0 * nu0[a] * (W - c);
-    if (has_f && dim == 2) grad[a] -= 2.0 * R0 / 3.0 * yhat_g[a] * f_g;
+    grad[a] = gw * nu0[a] * (W - c);
+    if (has_f && dim == 2 && !screened) grad[a] -= 2.0 * R0 / 3.0 * yhat_g[a] * f_g;
     exit_pt[a] = pb[a];
     if (n) wn += nu0[a] * n[a];
   }
-  *w1 = dim / R0 * wn;
+  *w1 = gw * wn;
 }
 
 int32_t orc_walk_queries(const orc_scene* s, const orc_walk_params* p, int mode, const double* x,

@@ -54,7 +54,8 @@ enum {
   ORC_FIELD_GAUSS_POTENTIAL_2D = 4,
   ORC_FIELD_SOLID_HARMONICS_3D = 5,
   ORC_FIELD_FOURIER_2D = 6,
-  ORC_FIELD_POINT_SOURCE = 7
+  ORC_FIELD_POINT_SOURCE = 7,
+  ORC_FIELD_EXP_PLANE = 8
 };
 
 typedef struct {
@@ -125,10 +126,14 @@ typedef struct {
   uint64_t seed;
   uint32_t batch;
   int32_t control_variate; /* subtract g(xbar) in the gradient estimate */
+  double sigma;            /* screening coefficient of Lap u - sigma u = f (Eq. 1); 0: Poisson */
 } orc_walk_params;
 
 /* One walk.  mode 0: cache walk (tag 1, first ball without termination test);
- * mode 1: pointwise walk (tag 2, returns g(xbar) when R0 < eps).
+ * mode 1: pointwise walk (tag 2, returns g(xbar) when R0 < eps).  With
+ * p->sigma > 0 (screened, source term must be zero) every ball multiplies the
+ * estimate by orc_screen_ball_weight and the gradient uses
+ * orc_screen_grad_weight instead of dim/R0; U is NaN if a source is given.
  * Outputs U (solution sample), grad (dim; gradient sample), exit point,
  * first-step weight (dim/R0)*(nu . n) (cache mode), steps, capped flag. */
 void orc_walk(const orc_scene* s, const orc_field* g, const orc_field* f,
@@ -190,6 +195,28 @@ void orc_gather_backward(int dim, int64_t K, const double* ex, const double* r, 
                          const double* cy, const double* cn, const double* a, const double* b,
                          int64_t M, const double* sy, const double* sw, double* dLda,
                          double* dLdb, double* dLds, double* dLdx);
+
+/* --- Screened Poisson, sigma > 0 (Eq. 1; Appendix A.2) ----------------- */
+/* Modified Bessel functions I0, I1, K0, K1 (x > 0 for K). */
+double orc_bessel_i0(double x);
+double orc_bessel_i1(double x);
+double orc_bessel_k0(double x);
+double orc_bessel_k1(double x);
+/* Free-space Green's function of Lap - sigma with (Lap - sigma) G = delta:
+ * G = -K0(r s)/(2 pi) in 2D, -exp(-r s)/(4 pi r) in 3D (s = sqrt(sigma)), and
+ * its derivatives as orc_greens (which is the sigma = 0 case). */
+void orc_greens_sigma(int dim, double sigma, const double* x, const double* y, const double* ny,
+                      double* G, double* dGdx, double* dGdn, double* d2Gdxdn);
+/* Screened ball weights at radius R: the mean-value factor u(c) = P E[u on the
+ * sphere] (2D 1/I0(sR), 3D sR/sinh(sR)) and the gradient factor
+ * grad u(c) = w E[nu u(c + R nu)] (2D s/I1(sR), 3D s/i1(sR)); sigma = 0 gives
+ * 1 and dim/R. */
+double orc_screen_ball_weight(int dim, double sigma, double R);
+double orc_screen_grad_weight(int dim, double sigma, double R);
+/* orc_gather with the screened kernels (sigma = 0: orc_gather). */
+void orc_gather_sigma(int dim, double sigma, int64_t K, const double* ex, int64_t N, const double* cy,
+                      const double* cn, const double* a, const double* b, int64_t M, const double* sy,
+                      const double* sw, double* u, double* grad, double* cond);
 
 /* --- Clamped double-layer kernel and bias correction (Section 3.4) ------ */
 /* Distance beyond which |dG/dn| cannot exceed c (INFINITY for c <= 0). */

@@ -727,6 +727,11 @@ __device__ inline double field_value(const FieldDev& F, int dim, const double* x
       for (int a = 0; a < dim; ++a) r2 += (x[a] - p[1 + a]) * (x[a] - p[1 + a]);
       return dim == 2 ? p[0] * 0.5 * log(r2) : p[0] * rsqrt(r2);
     }
+    case 8: {
+      double e = 0.0;
+      for (int a = 0; a < dim; ++a) e = fma(p[1 + a], x[a], e);
+      return p[0] * exp(e);
+    }
   }
   return 0.0;
 }

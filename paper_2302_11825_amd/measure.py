@@ -9,6 +9,7 @@
                                      and its bias correction (Section 3.4): time,
                                      and the error near the offset boundary of the
                                      plain, clamped-only and corrected estimates
+    python bench.py --workload c3clamp --clamp-c 1600   the same on the 3D Laplace step
 
 Each prints one JSON line.  Inputs are the seeded synthetic workloads.
 """
@@ -53,7 +54,7 @@ def _log(msg):
 
 
 def run(args):
-    {"c3": c3, "c4a": c4a, "c4b": c4b, "c2clamp": c2clamp}[args.workload](args)
+    {"c3": c3, "c4a": c4a, "c4b": c4b, "c2clamp": c2clamp, "c3clamp": c3clamp}[args.workload](args)
 
 
 def _c3_setup(args):
@@ -222,24 +223,32 @@ def c4b(args):
 
 
 def c2clamp(args):
-    prob = wl.problem_c2()
-    clamp = dict(c=args.clamp_c, n_rays=args.clamp_rays, max_hits=args.clamp_hits, seed=wl.seed(2, 7))
+    _clamp_measure(args, wl.problem_c2(), "c2clamp_star4096_poisson", with_grad=True)
+
+
+def c3clamp(args):
+    _clamp_measure(args, wl.problem_c3(), "c3clamp_dispsphere_laplace", with_grad=False)
+
+
+def _clamp_measure(args, prob, name, with_grad):
+    d = prob.scene.dim
+    clamp = dict(c=args.clamp_c, n_rays=args.clamp_rays, max_hits=args.clamp_hits, seed=wl.seed(d, 7))
     t = time.time()
     plain = pl.Prepared(prob, dtype="f32")
     prep = pl.Prepared(prob, dtype="f32", clamp=clamp)
     cl = prep.clamp
     torch.cuda.synchronize()
-    _log(f"c2clamp setup {time.time() - t:.1f}s: interior {prep.n_int}, near {cl['n_near']} "
+    _log(f"{name} setup {time.time() - t:.1f}s: interior {prep.n_int}, near {cl['n_near']} "
          f"(radius {cl['radius']:.4f})")
     for _ in range(max(1, args.warmup)):
-        pl.solve(prep)
-        pl.solve(plain)
+        pl.solve(prep, with_grad=with_grad)
+        pl.solve(plain, with_grad=with_grad)
     torch.cuda.synchronize()
     watch = pl.Stopwatch()
     e0, e1 = _ev(), _ev()
     e0.record()
     for _ in range(args.steps):
-        sol = pl.solve(prep, watch=watch)
+        sol = pl.solve(prep, with_grad=with_grad, watch=watch)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
@@ -247,7 +256,7 @@ def c2clamp(args):
     watch_p = pl.Stopwatch()
     e0.record()
     for _ in range(args.steps):
-        sol_p = pl.solve(plain, watch=watch_p)
+        sol_p = pl.solve(plain, with_grad=with_grad, watch=watch_p)
     e1.record()
     torch.cuda.synchronize()
     ms_plain = e0.elapsed_time(e1) / args.steps
@@ -255,14 +264,14 @@ def c2clamp(args):
     # errors at the gathered points within reach of the correction: plain,
     # clamped only (the clamped gather over the same cache, no correction) and
     # clamped + corrected; the seeds are shared, so the three use one cache
-    pos = cl["pos"][: cl["n_near"]]
+    n = cl["n_near"]
+    pos = cl["pos"][:n]
     idx_i = prep.idx_int[: prep.n_int].cpu().numpy()
     pts = prob.eval_x[idx_i[pos.cpu().numpy()]]
     truth = wl.field_value(prob.truth, pts)
-    n = cl["n_near"]
     xs = prep.x_int[:, pos].contiguous()
     u_c = torch.empty(max(n, 1), dtype=torch.float32, device="cuda")
-    B.bvc_gather_u(2, sol.extra["cview"], sol.extra["sview"], n, xs, u_c, clamp=cl["c"])
+    B.bvc_gather_u(d, sol.extra["cview"], sol.extra["sview"], n, xs, u_c, clamp=cl["c"])
     torch.cuda.synchronize()
     est = {"plain": sol_p.u_int[pos].double().cpu().numpy(), "clamped_only": u_c[:n].double().cpu().numpy(),
            "clamped_corrected": sol.u_int[pos].double().cpu().numpy()}
@@ -273,7 +282,7 @@ def c2clamp(args):
     far_diff = float(np.max(np.abs(sol.u_int[: prep.n_int].double().cpu().numpy()[far]
                                    - sol_p.u_int[: prep.n_int].double().cpu().numpy()[far]))) if far.size else 0.0
     c = cl["counters"].cpu().numpy()
-    out = {"workload": "c2clamp_star4096_poisson", "clamp_c": cl["c"], "clamp_radius": cl["radius"],
+    out = {"workload": name, "clamp_c": cl["c"], "clamp_radius": cl["radius"],
            "n_rays": args.clamp_rays, "max_hits": args.clamp_hits, "interior_points": prep.n_int,
            "corrected_points": n, "rays": n * args.clamp_rays, "contributing_crossings": int(c[0]),
            "rays_over_capacity": int(c[1]), "correction_walks": int(c[5]), "correction_walk_steps": int(c[3]),

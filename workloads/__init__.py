@@ -33,6 +33,8 @@ kind   name                 value at x
                             phi_{2j}=sin(j theta), last basis cos(J theta) when the
                             count is even
 7      POINT_SOURCE         2D: A ln|x-x0|; 3D: A/|x-x0|; A=param[0], x0=param[1:]
+8      EXP_PLANE            A exp(a.x), A=param[0], a=param[1:1+dim]; solves
+                            Lap u = |a|^2 u (screened Poisson, Eq. 1 with f = 0)
 =====  ===================  =====================================================
 """
 from __future__ import annotations
@@ -51,6 +53,7 @@ FIELD_GAUSS_POTENTIAL_2D = 4
 FIELD_SOLID_HARMONICS_3D = 5
 FIELD_FOURIER_2D = 6
 FIELD_POINT_SOURCE = 7
+FIELD_EXP_PLANE = 8
 
 
 def seed(k: int, p: int) -> int:
@@ -109,6 +112,10 @@ def fourier_2d(coef, center=(0.0, 0.0)) -> Field:
 
 def point_source(amp, x0) -> Field:
     return Field(FIELD_POINT_SOURCE, np.zeros(0), [amp, *x0])
+
+
+def exp_plane(amp, a) -> Field:
+    return Field(FIELD_EXP_PLANE, np.zeros(0), [amp, *a])
 
 
 # --------------------------------------------------------------------------
@@ -198,6 +205,9 @@ def field_value(fld: Field, x: np.ndarray) -> np.ndarray:
         d = x.shape[1]
         r = np.linalg.norm(x - p[1 : 1 + d][None, :], axis=1)
         return p[0] * (np.log(r) if d == 2 else 1.0 / r)
+    if k == FIELD_EXP_PLANE:
+        d = x.shape[1]
+        return p[0] * np.exp(x @ p[1 : 1 + d])
     raise ValueError(f"unknown field kind {k}")
 
 
