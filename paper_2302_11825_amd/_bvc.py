@@ -46,7 +46,7 @@ class bvc_walk_params(C.Structure):
     _fields_ = [("eps", C.c_double), ("max_steps", C.c_int32), ("n_walks", C.c_int32),
                 ("seed", C.c_uint64), ("batch", C.c_uint32), ("control_variate", C.c_int32),
                 ("dtype", C.c_int32), ("blocks", C.c_int32), ("g", bvc_field), ("f", bvc_field),
-                ("ev_begin", C.c_void_p), ("ev_end", C.c_void_p)]
+                ("ev_begin", C.c_void_p), ("ev_end", C.c_void_p), ("sigma", C.c_double)]
 
 
 class bvc_cache_view(C.Structure):
@@ -61,7 +61,7 @@ class bvc_source_view(C.Structure):
 class bvc_gather_params(C.Structure):
     _fields_ = [("accumulate", C.c_int32), ("near_tau", C.c_double), ("near_x", C.c_void_p),
                 ("near_cx", C.c_void_p), ("near_cn", C.c_void_p), ("near_a", C.c_void_p),
-                ("near_b", C.c_void_p), ("clamp_c", C.c_double)]
+                ("near_b", C.c_void_p), ("clamp_c", C.c_double), ("sigma", C.c_double)]
 
 
 class bvc_clamp_params(C.Structure):
@@ -326,13 +326,14 @@ def _views(cache, sources):
     return cv, sv
 
 
-def _gparams(accumulate, near, clamp=0.0):
+def _gparams(accumulate, near, clamp=0.0, sigma=0.0):
     """near: None, or dict(tau, x, cx, cn, a, b) with FP64 device tensors
     (evaluation points [dim][n_eval], cache points and normals [dim][n], a, b).
     clamp: bound c of dG/dn in the potential (Eq. 9), 0 = off."""
     gp = bvc_gather_params()
     gp.accumulate = accumulate
     gp.clamp_c = float(clamp)
+    gp.sigma = float(sigma)
     if near is not None:
         gp.near_tau = float(near["tau"])
         gp.near_x, gp.near_cx, gp.near_cn, gp.near_a, gp.near_b = (
@@ -340,17 +341,18 @@ def _gparams(accumulate, near, clamp=0.0):
     return gp
 
 
-def bvc_gather_u(dim, cache, sources, n_eval, eval_x, u, accumulate=0, stream=None, near=None, clamp=0.0):
+def bvc_gather_u(dim, cache, sources, n_eval, eval_x, u, accumulate=0, stream=None, near=None, clamp=0.0,
+                 sigma=0.0):
     cv, sv = _views(cache, sources)
-    gp = _gparams(accumulate, near, clamp)
+    gp = _gparams(accumulate, near, clamp, sigma)
     _check(_L.bvc_gather_u(dim, C.byref(cv), C.byref(sv) if sv is not None else None, n_eval, ptr(eval_x),
                            ptr(u), C.byref(gp), stream_ptr(stream)), "bvc_gather_u")
 
 
 def bvc_gather_grad(dim, cache, sources, n_eval, eval_x, u, grad, accumulate=0, stream=None, near=None,
-                    clamp=0.0):
+                    clamp=0.0, sigma=0.0):
     cv, sv = _views(cache, sources)
-    gp = _gparams(accumulate, near, clamp)
+    gp = _gparams(accumulate, near, clamp, sigma)
     _check(_L.bvc_gather_grad(dim, C.byref(cv), C.byref(sv) if sv is not None else None, n_eval, ptr(eval_x),
                               ptr(u), ptr(grad), C.byref(gp), stream_ptr(stream)), "bvc_gather_grad")
 

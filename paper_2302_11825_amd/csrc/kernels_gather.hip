@@ -383,6 +383,115 @@ __device__ __forceinline__ void gather_block(const GatherArgs<T>& a, int64_t blo
   }
 }
 
+// Screened gather in 3D (Eqs. 3-6 with the kernels of Appendix A.2):
+// G = -e/(4 pi r), e = exp(-s r), and with Q = e (1 + s r)
+//   a dG/dn - b G = Q t / r^3 + bl e / r,   t = a n.(y-x)/(4 pi), bl = b/(4 pi)
+//   grad = Q [(y-x)(3 t/r^2 + bl)/r^3 - a n/(4 pi r^3)] + s^2 e t (y-x)/r^3
+// (the Poisson terms times Q plus dG/dn times dQ/dx = s^2 e (y - x)); a
+// source term s_j adds G s_j and Q dG0/dx s_j.  One evaluation point per
+// thread; the cache and sources stream through LDS tiles as in k_gather.
+template <typename T, bool GRAD>
+__global__ __launch_bounds__(kGBlock) void k_gather_screened3(GatherArgs<T> a, double sigma) {
+  __shared__ T ent[kTile * 8];
+  const int tid = threadIdx.x;
+  const int64_t k = (int64_t)blockIdx.x * kGBlock + tid;
+  const bool live = k < a.n_eval;
+  T x[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) x[c] = live ? a.ex[c * a.n_eval + k] : T(0);
+  const T s = (T)sqrt(sigma), s2 = (T)sigma;
+  // e^(-s r) by the hardware exp2 in FP32 (s scaled by log2 e)
+  const T sl2 = sizeof(T) == 4 ? (T)(sqrt(sigma) * 1.4426950408889634) : s;
+  auto expo = [&](T r) -> T {
+    if constexpr (sizeof(T) == 4) return __builtin_amdgcn_exp2f(-sl2 * r);
+    else return exp(-sl2 * r);
+  };
+  const T inv4pi = (T)(1.0 / (4.0 * kPi));
+  const T tiny = sizeof(T) == 4 ? (T)1e-18 : (T)1e-200;
+  double tu = 0.0, tg[3] = {0.0, 0.0, 0.0};
+  T au = T(0), ag[3] = {T(0), T(0), T(0)};
+  auto fold = [&]() {
+    tu += (double)au;
+    au = T(0);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      tg[c] += (double)ag[c];
+      ag[c] = T(0);
+    }
+  };
+  for (int64_t t0 = 0; t0 < a.n_cache; t0 += kTile) {
+    const int cnt = (int)std::min<int64_t>(kTile, a.n_cache - t0);
+    if (tid < cnt) {
+      const int64_t i = t0 + tid;
+      T* e = ent + tid * 8;
+      const T av = a.ca[i], bv = a.cb[i];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        e[c] = a.cx[c * a.n_cache + i];
+        e[4 + c] = a.cn[c * a.n_cache + i] * av * inv4pi;
+      }
+      e[3] = bv * inv4pi;
+    }
+    __syncthreads();
+    for (int j = 0; j < cnt; ++j) {
+      const T* e = ent + j * 8;
+      const T dx = e[0] - x[0], dy = e[1] - x[1], dz = e[2] - x[2];
+      const T r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, tiny)));
+      const T ri = rsq(r2);
+      const T r = r2 * ri, ri2 = ri * ri, ri3 = ri2 * ri;
+      const T ev = expo(r);
+      const T Q = ev * fma(s, r, T(1));
+      const T t = fma(e[4], dx, fma(e[5], dy, e[6] * dz));
+      au = fma(Q * t, ri3, fma(e[3] * ev, ri, au));
+      if constexpr (GRAD) {
+        const T q = Q * ri3 * fma(T(3) * t, ri2, e[3]) + s2 * ev * t * ri3;
+        const T m = Q * ri3;
+        ag[0] = fma(q, dx, fma(-m, e[4], ag[0]));
+        ag[1] = fma(q, dy, fma(-m, e[5], ag[1]));
+        ag[2] = fma(q, dz, fma(-m, e[6], ag[2]));
+      }
+    }
+    __syncthreads();
+    fold();
+  }
+  for (int64_t t0 = 0; t0 < a.n_src; t0 += kTile) {
+    const int cnt = (int)std::min<int64_t>(kTile, a.n_src - t0);
+    if (tid < cnt) {
+      const int64_t j = t0 + tid;
+      T* e = ent + tid * 8;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) e[c] = a.sy[c * a.n_src + j];
+      e[3] = -a.ss[j] * inv4pi;  // G s = -s e/(4 pi r); dG/dx s = Q s (x - y)/(4 pi r^3)
+    }
+    __syncthreads();
+    for (int j = 0; j < cnt; ++j) {
+      const T* e = ent + j * 8;
+      const T dx = e[0] - x[0], dy = e[1] - x[1], dz = e[2] - x[2];
+      const T r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, tiny)));
+      const T ri = rsq(r2);
+      const T r = r2 * ri;
+      const T ev = expo(r);
+      au = fma(e[3] * ev, ri, au);
+      if constexpr (GRAD) {
+        const T q = ev * fma(s, r, T(1)) * e[3] * ri * ri * ri;
+        ag[0] = fma(q, dx, ag[0]);
+        ag[1] = fma(q, dy, ag[1]);
+        ag[2] = fma(q, dz, ag[2]);
+      }
+    }
+    __syncthreads();
+    fold();
+  }
+  if (!live) return;
+  const double sc = a.scale ? (double)a.scale[k] : 1.0;
+  if (a.u) a.u[k] = (T)((a.accumulate ? (double)a.u[k] : 0.0) + sc * tu);
+  if (GRAD && a.g) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      a.g[c * a.n_eval + k] = (T)((a.accumulate ? (double)a.g[c * a.n_eval + k] : 0.0) + sc * tg[c]);
+  }
+}
+
 // Transposed gather: cache (or source) points are the parallel dimension and
 // the evaluation points with their residuals r_k stream through LDS.
 template <typename T>
@@ -877,7 +986,7 @@ int tuned_ppt(const GatherClass& k) {
 template <typename T>
 int gather_impl(int dim, const bvc_cache_view* c, const bvc_source_view* s, int64_t n_eval, const void* ex, void* u,
                 void* g, const void* scale, int accumulate, hipStream_t st, const bvc_gather_params* near = nullptr,
-                int ppt = 0, double clamp_c = 0.0) {
+                int ppt = 0, double clamp_c = 0.0, double sigma = 0.0) {
   if (ppt == 0)
     ppt = tuned_ppt(gather_class(dim, sizeof(T) == 4 ? BVC_F32 : BVC_F64, g != nullptr, near != nullptr, n_eval, c->n));
   GatherArgs<T> a{};
@@ -909,6 +1018,12 @@ int gather_impl(int dim, const bvc_cache_view* c, const bvc_source_view* s, int6
   a.clampc = (T)clamp_c;
   a.clamp64 = clamp_c;
   const bool clamp = clamp_c > 0.0;
+  if (sigma > 0.0) {
+    const int blocks = (int)((n_eval + kGBlock - 1) / kGBlock);
+    if (g) hipLaunchKernelGGL((k_gather_screened3<T, true>), dim3(blocks), dim3(kGBlock), 0, st, a, sigma);
+    else hipLaunchKernelGGL((k_gather_screened3<T, false>), dim3(blocks), dim3(kGBlock), 0, st, a, sigma);
+    return check_hip(hipGetLastError(), "screened gather launch");
+  }
   if (dim == 2) launch_gather<T, 2>(a, g != nullptr, near != nullptr, ppt, clamp, st);
   else launch_gather<T, 3>(a, g != nullptr, near != nullptr, ppt, clamp, st);
   return check_hip(hipGetLastError(), "gather launch");
@@ -932,9 +1047,15 @@ int gather_entry(int32_t dim, const bvc_cache_view* c, const bvc_source_view* s,
     return fail(BVC_EINVAL, "near_tau > 0 needs the FP64 copies near_x, near_cx, near_cn, near_a, near_b");
   const double clamp_c = prm ? prm->clamp_c : 0.0;
   if (!(clamp_c >= 0.0) || !std::isfinite(clamp_c)) return fail(BVC_EINVAL, "clamp_c must be finite and >= 0");
+  const double sigma = prm ? prm->sigma : 0.0;
+  if (!(sigma >= 0.0) || !std::isfinite(sigma)) return fail(BVC_EINVAL, "sigma must be finite and >= 0");
+  if (sigma > 0.0 && dim != 3) return fail(BVC_EUNSUPPORTED, "the screened gather is built for 3D");
+  if (sigma > 0.0 && (near || clamp_c > 0.0))
+    return fail(BVC_EUNSUPPORTED, "the screened gather takes no near field or clamp");
   if (c->dtype == BVC_F32)
-    return gather_impl<float>(dim, c, s, n_eval, ex, u, g, nullptr, acc, st, near ? prm : nullptr, ppt, clamp_c);
-  return gather_impl<double>(dim, c, s, n_eval, ex, u, g, nullptr, acc, st, nullptr, ppt, clamp_c);
+    return gather_impl<float>(dim, c, s, n_eval, ex, u, g, nullptr, acc, st, near ? prm : nullptr, ppt, clamp_c,
+                              sigma);
+  return gather_impl<double>(dim, c, s, n_eval, ex, u, g, nullptr, acc, st, nullptr, ppt, clamp_c, sigma);
 }
 
 template <typename T>

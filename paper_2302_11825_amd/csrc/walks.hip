@@ -55,6 +55,7 @@ struct WalkArgs {
   unsigned long long* counters;
   unsigned long long chunk;  // walk ids per claim, 1..kChunkMax
   int open_lanes;            // leave the traversal loop at this many open queries
+  double sigma;              // screening coefficient (3D, no source term), 0 = Poisson
 };
 
 // In-walk source term in the walk's precision (constants and Gaussian sums).
@@ -83,6 +84,25 @@ __device__ __forceinline__ T walk_source(const FieldDev& F, T scale, const T* y)
     else sum = fma(c[0], exp(-r2 * scale), sum);
   }
   return sum;
+}
+
+// Mean-value factor of a screened ball (Lap u = sigma u) in 3D at x = s R:
+// x / sinh x.  Below 0.5 the even series of sinh x / x avoids the
+// cancellation of exp(x) - exp(-x); above, 2 x e^-x / (1 - e^-2x).
+template <typename T>
+__device__ __forceinline__ T screen_ball_weight3(T x) {
+  if (x < T(0.5)) {
+    const T x2 = x * x;
+    T p = T(1.0 / 6227020800.0);
+    p = fma(p, x2, T(1.0 / 39916800.0));
+    p = fma(p, x2, T(1.0 / 362880.0));
+    p = fma(p, x2, T(1.0 / 5040.0));
+    p = fma(p, x2, T(1.0 / 120.0));
+    p = fma(p, x2, T(1.0 / 6.0));
+    return T(1) / fma(p, x2, T(1));
+  }
+  const T e = exp(-x);
+  return T(2) * x * e / (T(1) - e * e);
 }
 
 // Wave-private pool of walk ids [next, end) claimed from a global queue in
@@ -175,6 +195,10 @@ __global__ __launch_bounds__(kBlock) void k_walks(WalkArgs a) {
   const uint32_t tag = MODE == 0 ? 1u : 2u;
   const T eps = (T)a.eps;
   const T src_scale = SRC && a.f.kind == 3 ? source_scale<T>(a.f) : T(0);
+  // screened walks (no source term) carry the product of their balls'
+  // mean-value factors in acc_s, the first ball's excepted
+  const bool scr = !SRC && D == 3 && a.sigma > 0.0;
+  const T s_scr = scr ? (T)sqrt(a.sigma) : T(0);
   const SceneDev& S = a.S;
   T* U = (T*)a.U;
   T* Dof = (T*)a.Dof;
@@ -231,7 +255,7 @@ __global__ __launch_bounds__(kBlock) void k_walks(WalkArgs a) {
                 p[q] = MODE != 1 ? (T)a.x[q * a.n_pts + i] : ((const T*)a.px)[q * a.n_pts + i];
               d = R0;
               k = 0;
-              acc_s = T(0);
+              acc_s = scr ? T(1) : T(0);
               usrc = T(0);
               active = true;
               jump = true;
@@ -294,6 +318,8 @@ __global__ __launch_bounds__(kBlock) void k_walks(WalkArgs a) {
         }
       } else if constexpr (SRC) {
         acc_s = fma(coef, srcv, acc_s);
+      } else if (scr) {
+        acc_s *= screen_ball_weight3<T>(s_scr * d);
       }
 #pragma unroll
       for (int c = 0; c < D; ++c) p[c] = fma(d, nu[c], p[c]);
@@ -341,9 +367,28 @@ __global__ __launch_bounds__(kBlock) void k_walks(WalkArgs a) {
   }
 }
 
+// i1(x) = (x cosh x - sinh x) / x^2, the modified spherical Bessel function
+// of order 1, by its series sum_k x^(2k+1) / (2^k k! (2k+3)!!) below 1.
+__device__ inline double sph_i1(double x) {
+  if (x < 1.0) {
+    double term = x / 3.0, sum = term;
+    for (int k = 1; k < 14; ++k) {
+      term *= x * x / (2.0 * k * (2.0 * k + 3.0));
+      sum += term;
+    }
+    return sum;
+  }
+  return (x * cosh(x) - sinh(x)) / (x * x);
+}
+
 // Boundary data at the exit points, in FP64.  With W = g(exit) + S:
 // U = W + u_src,  mode 0: D = w1 (W - c) + d_src,  mode 1: grad = gw (W - c) + g_src,
-// where c = g(xbar) is the control variate (0 when disabled).
+// where c = g(xbar) is the control variate (0 when disabled).  Screened walks
+// (sigma > 0, 3D, no source) recorded the product of their later balls'
+// mean-value factors in U: W = U g(exit), U = P(R0) W with the first ball's
+// factor P(x) = x / sinh x, x = s R0, and the weights w1, gw (written as
+// dim / R0 times the direction) rescaled to the screened ball gradient weight
+// s / i1(s R0); a pointwise walk that starts in the epsilon shell keeps g.
 // A wave finishes kFinishRun runs of 64 consecutive walks, lane l taking walk
 // l of each run, so that every load and store is coalesced; a lane evaluates
 // the control variate only when its start point changes.
@@ -351,9 +396,12 @@ constexpr int kFinishRun = 8;
 
 template <typename T, int D, int MODE>
 __global__ __launch_bounds__(kBlock) void k_finish(FieldDev g, int cv, uint64_t total, int W, int64_t n_pts,
-                                                    const double* xbar, const T* EX, T* U, T* Dof, const T* W1) {
+                                                    const double* xbar, const T* EX, T* U, T* Dof, const T* W1,
+                                                    double sigma, double eps, const double* R0) {
   const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const uint64_t id0 = wave * (64 * kFinishRun) + (threadIdx.x & 63);
+  const bool scr = D == 3 && sigma > 0.0;
+  const double s = scr ? sqrt(sigma) : 0.0;
   int64_t i_cv = -1;
   double c = 0.0;
   for (int r = 0; r < kFinishRun; ++r) {
@@ -372,14 +420,26 @@ __global__ __launch_bounds__(kBlock) void k_finish(FieldDev g, int cv, uint64_t 
     for (int e = 0; e < D; ++e) q[e] = (double)EX[(size_t)e * total + id];
     const double gq = field_value(g, D, q);
     const double su = (double)U[id];
-    U[id] = (T)(gq + su);
+    double w_est = gq + su, u_est = gq + su, ratio = 1.0;
+    if (scr) {
+      const double r0 = R0[i];
+      if (MODE == 1 && r0 < eps) {
+        w_est = u_est = gq;  // no ball: the walk returned g at the closest point
+      } else {
+        const double x = s * r0;
+        w_est = su * gq;
+        u_est = (x < 1e-8 ? 1.0 : x / sinh(x)) * w_est;
+        ratio = s / sph_i1(x) * r0 / D;
+      }
+    }
+    U[id] = (T)u_est;
     if constexpr (MODE == 0) {
-      Dof[id] = (T)((double)W1[id] * (gq + su - c) + (double)Dof[id]);
+      Dof[id] = (T)((double)W1[id] * ratio * (w_est - c) + (double)Dof[id]);
     } else if (Dof) {
 #pragma unroll
       for (int e = 0; e < D; ++e)
-        Dof[(size_t)e * total + id] =
-            (T)((double)W1[(size_t)e * total + id] * (gq + su - c) + (double)Dof[(size_t)e * total + id]);
+        Dof[(size_t)e * total + id] = (T)((double)W1[(size_t)e * total + id] * ratio * (w_est - c) +
+                                          (double)Dof[(size_t)e * total + id]);
     }
   }
 }
@@ -443,6 +503,10 @@ int check_walk_params(const bvc_walk_params* p, int dim) {
   if (rc) return rc;
   if (p->f.kind != 0 && p->f.kind != 1 && p->f.kind != 3)
     return fail(BVC_EUNSUPPORTED, "walk source terms are constants or Gaussian sums");
+  if (!(p->sigma >= 0.0) || !std::isfinite(p->sigma)) return fail(BVC_EINVAL, "sigma must be finite and >= 0");
+  if (p->sigma > 0.0 && dim != 3) return fail(BVC_EUNSUPPORTED, "screened walks are built for 3D scenes");
+  if (p->sigma > 0.0 && p->f.kind != 0)
+    return fail(BVC_EUNSUPPORTED, "screened walks take no source term (f must be ZERO)");
   return BVC_OK;
 }
 
@@ -467,10 +531,12 @@ void launch_finish(const bvc_walk_params* p, int mode, const WalkArgs& a, hipStr
   FieldDev g = to_dev(p->g);
   if (mode == 0)
     hipLaunchKernelGGL((k_finish<T, D, 0>), dim3(blocks), dim3(kBlock), 0, st, g, p->control_variate, a.total,
-                       a.W, a.n_pts, a.xbar, (const T*)a.exit, (T*)a.U, (T*)a.Dof, (const T*)a.w1);
+                       a.W, a.n_pts, a.xbar, (const T*)a.exit, (T*)a.U, (T*)a.Dof, (const T*)a.w1, a.sigma,
+                       a.eps, a.R0);
   else
     hipLaunchKernelGGL((k_finish<T, D, 1>), dim3(blocks), dim3(kBlock), 0, st, g, p->control_variate, a.total,
-                       a.W, a.n_pts, a.xbar, (const T*)a.exit, (T*)a.U, (T*)a.Dof, (const T*)a.w1);
+                       a.W, a.n_pts, a.xbar, (const T*)a.exit, (T*)a.U, (T*)a.Dof, (const T*)a.w1, a.sigma,
+                       a.eps, a.R0);
 }
 
 size_t stack_bytes(const SceneHost& h) { return (size_t)(h.depth + 1) * kBlock * sizeof(uint32_t); }
@@ -485,6 +551,7 @@ int run_walks(bvc_scene s, const bvc_walk_params* p, int mode, int64_t n, WalkAr
   a.S = h.view();
   a.f = to_dev(p->f);
   a.eps = p->eps;
+  a.sigma = p->sigma;
   a.max_steps = p->max_steps;
   a.W = mode == 2 ? 1 : p->n_walks;
   a.seed = p->seed;
@@ -857,6 +924,7 @@ int bvc_clamp_correction(bvc_scene s, const bvc_walk_params* p, const bvc_clamp_
   rc = check_walk_params(p, dim);
   if (rc) return rc;
   if (!cp) return fail(BVC_EINVAL, "clamp params are null");
+  if (p->sigma > 0.0) return fail(BVC_EUNSUPPORTED, "the clamping correction is built for sigma = 0");
   if (!(cp->l > 0.0) || !std::isfinite(cp->l)) return fail(BVC_EINVAL, "l must be positive");
   if (cp->sides != 1 && !(cp->sides == 2 && dim == 2)) return fail(BVC_EINVAL, "sides must be 1 (or 2 in 2D)");
   if (!(cp->c > 0.0) || !std::isfinite(cp->c)) return fail(BVC_EINVAL, "c must be positive");

@@ -122,8 +122,9 @@ def candidates_for(sc: Scene, n_target, l, sides, seed, pilot=65536):
 
 
 def walk_params(eps, n_walks, seed, g: DeviceField, f: Optional[DeviceField], dtype="f32", batch=0,
-                max_steps=1024, control_variate=True, blocks=0) -> B.bvc_walk_params:
+                max_steps=1024, control_variate=True, blocks=0, sigma=0.0) -> B.bvc_walk_params:
     p = B.bvc_walk_params()
+    p.sigma = float(sigma)
     p.eps = float(eps)
     p.max_steps = int(max_steps)
     p.n_walks = int(n_walks)
@@ -439,7 +440,7 @@ def tune(prep: Prepared, with_grad=True, reps=3) -> dict:
     p, sc, dt = prep.p, prep.sc, prep.dtype
     T, d = DT[dt], sc.dim
     cache = sample_cache(sc, prep.n_cand, p.offset, p.sides, p.seed_cache, 0)
-    wp = walk_params(p.eps, p.n_walks, p.seed_walks, prep.g, prep.f, dt, 0)
+    wp = walk_params(p.eps, p.n_walks, p.seed_walks, prep.g, prep.f, dt, 0, sigma=p.sigma)
     n, W = cache.n, p.n_walks
     U = torch.empty(max(n * W, 1), dtype=T, device=sc.device)
     D = torch.empty_like(U)
@@ -452,7 +453,8 @@ def tune(prep: Prepared, with_grad=True, reps=3) -> dict:
     cview, sview = _gather_views(prep, cache, a, b, 0, _NoWatch())
     u = torch.empty(max(prep.n_int, 1), dtype=T, device=sc.device)
     g = torch.empty(d, max(prep.n_int, 1), dtype=T, device=sc.device) if with_grad else None
-    ppt = B.bvc_tune_gather(d, cview, sview, prep.n_int, prep.x_int, u, g, reps) if prep.n_int else 0
+    ppt = (B.bvc_tune_gather(d, cview, sview, prep.n_int, prep.x_int, u, g, reps)
+           if prep.n_int and p.sigma == 0 else 0)
     return dict(walk_blocks_per_cu=bpc, walk_open_lanes=lanes, gather_points_per_thread=ppt)
 
 
@@ -464,7 +466,7 @@ def solve(prep: Prepared, batch=0, with_grad=True, n_walks_band=None, records=Fa
     watch = watch or _NoWatch()
     with watch.stage("sample_cache"):
         cache = sample_cache(sc, prep.n_cand, p.offset, p.sides, p.seed_cache, batch)
-    wp = walk_params(p.eps, p.n_walks, p.seed_walks, prep.g, prep.f, dt, batch)
+    wp = walk_params(p.eps, p.n_walks, p.seed_walks, prep.g, prep.f, dt, batch, sigma=p.sigma)
     watch.kernel("k_walks_cache", wp)
     with watch.stage("cache_walks"):
         U, D, rec, counters = cache_walks(sc, cache, wp, dt, records)
@@ -478,16 +480,16 @@ def solve(prep: Prepared, batch=0, with_grad=True, n_walks_band=None, records=Fa
     cc = cl["c"] if cl else 0.0
     with watch.stage("gather"):
         if with_grad:
-            B.bvc_gather_grad(d, cview, sview, n_int, prep.x_int, u_int, g_int, clamp=cc)
+            B.bvc_gather_grad(d, cview, sview, n_int, prep.x_int, u_int, g_int, clamp=cc, sigma=p.sigma)
         else:
-            B.bvc_gather_u(d, cview, sview, n_int, prep.x_int, u_int, clamp=cc)
+            B.bvc_gather_u(d, cview, sview, n_int, prep.x_int, u_int, clamp=cc, sigma=p.sigma)
     gathered = None
     if cl:
         gathered = torch.cuda.Event()
         gathered.record()
     Wb = n_walks_band or p.n_walks
     nb = prep.n_band
-    wpb = walk_params(p.eps, Wb, p.seed_walks, prep.g, prep.f, dt, batch)
+    wpb = walk_params(p.eps, Wb, p.seed_walks, prep.g, prep.f, dt, batch, sigma=p.sigma)
     watch.kernel("k_walks_band", wpb)
     with watch.stage("band_walks"):
         u_band, g_band, pwc = pointwise(sc, wpb, prep.x_band[:, :nb] if nb else prep.x_band[:, :0], with_grad)

@@ -382,6 +382,7 @@ class Problem:
     seed_cache: int = 0
     seed_sources: int = 0
     extra: dict = field(default_factory=dict)
+    sigma: float = 0.0     # screening coefficient of Lap u - sigma u = f (Eq. 1)
 
 
 def _harm_c1() -> Field:
@@ -434,6 +435,20 @@ def problem_c3(n_eval_box: int = 2_320_000, slice_n: int = 256, level: int = 6) 
                    np.concatenate([pts, sl3], 0), g, sides=1, precision="f32",
                    seed_walks=seed(3, 4), seed_cache=seed(3, 3), seed_sources=seed(3, 6),
                    extra={"n_box": n_eval_box, "n_slice": sl3.shape[0]})
+
+
+def problem_c3_screened(sigma: float = 4.0, n_eval_box: int = 2_320_000) -> Problem:
+    """The displaced icosphere of the 3D Laplace workload with the screened
+    equation Lap u = sigma u (Eq. 1, f = 0) and the plane wave u = exp(a.x),
+    |a|^2 = sigma, as boundary data and closed-form solution."""
+    p = problem_c3(n_eval_box=n_eval_box)
+    rng = np.random.default_rng(seed(3, 8))
+    a = rng.normal(0, 1, 3)
+    a *= math.sqrt(sigma) / np.linalg.norm(a)
+    g = exp_plane(1.0, a)
+    return Problem("c3s_dispsphere_screened", p.scene, g, Field(), p.n_cache, p.n_walks, p.eps, p.offset, 0,
+                   p.eval_x, g, sides=1, precision="f32", seed_walks=seed(3, 9), seed_cache=p.seed_cache,
+                   seed_sources=p.seed_sources, extra=p.extra, sigma=sigma)
 
 
 def c4_fields(n_fields: int = 64, lmax: int = 8) -> np.ndarray:
