@@ -10,6 +10,7 @@
                                      and the error near the offset boundary of the
                                      plain, clamped-only and corrected estimates
     python bench.py --workload c3clamp --clamp-c 1600   the same on the 3D Laplace step
+    python bench.py --workload c3screen  the 3D step on the screened equation (sigma = 4)
 
 Each prints one JSON line.  Inputs are the seeded synthetic workloads.
 """
@@ -54,11 +55,12 @@ def _log(msg):
 
 
 def run(args):
-    {"c3": c3, "c4a": c4a, "c4b": c4b, "c2clamp": c2clamp, "c3clamp": c3clamp}[args.workload](args)
+    {"c3": c3, "c4a": c4a, "c4b": c4b, "c2clamp": c2clamp, "c3clamp": c3clamp,
+     "c3screen": c3screen}[args.workload](args)
 
 
-def _c3_setup(args):
-    prob = wl.problem_c3()
+def _c3_setup(args, prob=None):
+    prob = prob or wl.problem_c3()
     t = time.time()
     prep = pl.Prepared(prob, dtype="f32")
     tuned = None if getattr(args, "no_tune", False) else pl.tune(prep, with_grad=False, reps=1)
@@ -68,8 +70,14 @@ def _c3_setup(args):
     return prob, prep
 
 
-def c3(args):
-    prob, prep = _c3_setup(args)
+def c3screen(args):
+    """The 3D step on the screened equation Lap u = sigma u (sigma = 4) with the
+    plane wave exp(a.x) as data and solution."""
+    c3(args, wl.problem_c3_screened())
+
+
+def c3(args, prob=None):
+    prob, prep = _c3_setup(args, prob)
     for w in range(args.warmup):
         pl.solve(prep, batch=100 + w, with_grad=False)
     torch.cuda.synchronize()
@@ -102,7 +110,7 @@ def c3(args):
            "gather_pairs_per_s": pairs / (stages["gather"] / 1e3),
            "gather_tflops_u": pairs * FLOPS_3D_BOUNDARY_U / (stages["gather"] / 1e3) / 1e12,
            "stage_ms": stages, "rmse_u_sampled": rmse, "rmse_u_far": rmse_far, "rms_u_true": rms_truth,
-           "capped_walks": int(sol.counters[2])}
+           "capped_walks": int(sol.counters[2]), "sigma": prob.sigma}
     print(json.dumps(out))
 
 
