@@ -112,6 +112,9 @@ def lib():
         L.orc_screen_grad_weight.restype = C.c_double
         L.orc_gather_sigma.argtypes = [C.c_int, C.c_double, C.c_int64, _dp, C.c_int64, _dp, _dp, _dp, _dp,
                                        C.c_int64, _dp, _dp, _dp, _dp, _dp]
+        L.orc_sample_roi.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_uint64, C.c_uint32, _dp, _dp, _dp,
+                                     _dp, _dp, _ip]
+        L.orc_sample_roi.restype = C.c_int64
         L.orc_clamp_radius.argtypes = [C.c_int, C.c_double]
         L.orc_clamp_radius.restype = C.c_double
         L.orc_gather_clamped.argtypes = [C.c_int, C.c_int64, _dp, C.c_int64, _dp, _dp, _dp, _dp,
@@ -583,3 +586,17 @@ def gather_sigma(dim, sigma, ex, cy, cn, a, b, sy=None, sw=None, with_grad=True,
     if with_cond:
         out.append(c)
     return out[0] if len(out) == 1 else tuple(out)
+
+
+# --- Region of interest (Section 3.2, "Boundary Specification") ------------
+def sample_roi(dom: Scene, roi: Scene, n, seed, batch=0):
+    """Cache candidates on the boundary of the region `roi` inside `dom`."""
+    d = roi.dim
+    x = np.zeros((n, d))
+    nrm = np.zeros((n, d))
+    w = np.zeros(n)
+    xb = np.zeros((n, d))
+    R0 = np.zeros(n)
+    acc = np.zeros(n, np.int32)
+    na = lib().orc_sample_roi(dom.h, roi.h, n, int(seed), int(batch), _d(x), _d(nrm), _d(w), _d(xb), _d(R0), _i(acc))
+    return dict(x=x, n=nrm, w=w, xbar=xb, R0=R0, accept=acc.astype(bool), n_accepted=na)

@@ -1033,6 +1033,96 @@ int64_t orc_sample_cache(const orc_scene* s, int64_t n, double l, int sides, uin
   return n_acc;
 }
 
+/* Cache points on the boundary of a region of interest R inside the domain
+ * (Section 3.2, "Boundary Specification"): uniform density 1/|dR| over the
+ * primitives of the closed boundary `roi` (stratified uniforms through the
+ * cumulative primitive measures, Philox tag 6), the unit outward normal of R
+ * (the primitive's own: CCW segments, outward-wound triangles), weight
+ * |dR|/n, and the distance and closest point on the domain boundary `dom`
+ * where the walks run.  A point is accepted when it lies strictly inside the
+ * domain.  Returns the number accepted. */
+int64_t orc_sample_roi(const orc_scene* dom, const orc_scene* roi, int64_t n, uint64_t seed, uint32_t batch,
+                       double* x, double* nrm, double* w, double* xbar, double* R0, int32_t* accept) {
+  int d = roi->dim;
+  int64_t np = roi->np;
+  double* cdf = (double*)malloc((size_t)(np + 1) * sizeof(double));
+  cdf[0] = 0;
+  for (int64_t p = 0; p < np; ++p) {
+    double m;
+    if (d == 2) {
+      const double* a = roi->V + 2 * (int64_t)roi->P[2 * p];
+      const double* b = roi->V + 2 * (int64_t)roi->P[2 * p + 1];
+      m = sqrt((b[0] - a[0]) * (b[0] - a[0]) + (b[1] - a[1]) * (b[1] - a[1]));
+    } else {
+      const double* A = roi->V + 3 * (int64_t)roi->P[3 * p];
+      const double* B = roi->V + 3 * (int64_t)roi->P[3 * p + 1];
+      const double* C = roi->V + 3 * (int64_t)roi->P[3 * p + 2];
+      double ab[3], ac[3], c[3];
+      for (int a = 0; a < 3; ++a) {
+        ab[a] = B[a] - A[a];
+        ac[a] = C[a] - A[a];
+      }
+      cross3(ab, ac, c);
+      m = 0.5 * sqrt(dot3(c, c));
+    }
+    cdf[p + 1] = cdf[p] + m;
+  }
+  double M = cdf[np];
+  int64_t n_acc = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : n_acc)
+  for (int64_t k = 0; k < n; ++k) {
+    double ua, ub;
+    orc_uniform_pair(seed, 0, (uint32_t)k, batch, 6, &ua, &ub);
+    double target = ((double)k + ua) / (double)n * M;
+    int64_t lo = 0, hi = np - 1;
+    while (lo < hi) {
+      int64_t mid = (lo + hi + 1) / 2;
+      if (cdf[mid] <= target) lo = mid;
+      else hi = mid - 1;
+    }
+    double r = (target - cdf[lo]) / (cdf[lo + 1] - cdf[lo]);
+    if (r < 0) r = 0;
+    if (r > 1) r = 1;
+    double* xk = x + k * d;
+    double* nk = nrm + k * d;
+    if (d == 2) {
+      const double* a = roi->V + 2 * (int64_t)roi->P[2 * lo];
+      const double* b = roi->V + 2 * (int64_t)roi->P[2 * lo + 1];
+      double t0 = b[0] - a[0], t1 = b[1] - a[1];
+      double len = sqrt(t0 * t0 + t1 * t1);
+      xk[0] = a[0] + r * t0;
+      xk[1] = a[1] + r * t1;
+      nk[0] = t1 / len;
+      nk[1] = -t0 / len;
+    } else {
+      const double* A = roi->V + 3 * (int64_t)roi->P[3 * lo];
+      const double* B = roi->V + 3 * (int64_t)roi->P[3 * lo + 1];
+      const double* C = roi->V + 3 * (int64_t)roi->P[3 * lo + 2];
+      double su = sqrt(r);
+      double b0 = 1 - su, b1 = su * (1 - ub), b2 = su * ub;
+      double ab[3], ac[3], c[3];
+      for (int a = 0; a < 3; ++a) {
+        ab[a] = B[a] - A[a];
+        ac[a] = C[a] - A[a];
+        xk[a] = b0 * A[a] + b1 * B[a] + b2 * C[a];
+      }
+      cross3(ab, ac, c);
+      double len = sqrt(dot3(c, c));
+      for (int a = 0; a < 3; ++a) nk[a] = c[a] / len;
+    }
+    double dist, xb[3];
+    orc_closest(dom, xk, 0, &dist, xb, NULL);
+    int ok = dist > 0 && orc_inside(dom, xk) != 0;
+    accept[k] = ok;
+    n_acc += ok;
+    R0[k] = dist;
+    w[k] = M / (double)n;
+    for (int a = 0; a < d; ++a) xbar[k * d + a] = xb[a];
+  }
+  free(cdf);
+  return n_acc;
+}
+
 void orc_sample_sources(const orc_scene* s, const orc_field* f, int64_t m, const double* lo,
                         const double* hi, double l, uint64_t seed, uint32_t batch, double* y,
                         double* sw) {

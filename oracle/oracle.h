@@ -35,7 +35,7 @@
  *   Each block yields two uniforms: ua from (w0, w1), ub from (w2, w3).
  *   Walk step k uses blocks 4k + s, s = 0..3 (see orc_walk for the map).
  *   Tags: 1 cache walk, 2 pointwise walk, 3 cache sampling, 4 source sampling,
- *   5 ray directions of the clamping correction.
+ *   5 ray directions of the clamping correction, 6 region-of-interest cache.
  */
 #ifndef BVC_ORACLE_H
 #define BVC_ORACLE_H
@@ -111,6 +111,13 @@ int64_t orc_sample_cache(const orc_scene* s, int64_t n, double l, int sides, uin
                          uint32_t batch, double* x, double* nrm, double* w, double* xbar,
                          double* R0, int32_t* accept);
 double orc_candidate_measure(const orc_scene* s, double l, int sides);
+
+/* Cache points on the closed boundary of a region of interest `roi` inside
+ * the domain `dom` (Section 3.2): uniform 1/|dR| with stratified uniforms
+ * (tag 6), outward normals of R, weight |dR|/n, distance and closest point on
+ * the domain boundary; accepted when strictly inside the domain. */
+int64_t orc_sample_roi(const orc_scene* dom, const orc_scene* roi, int64_t n, uint64_t seed, uint32_t batch,
+                       double* x, double* nrm, double* w, double* xbar, double* R0, int32_t* accept);
 
 /* Source cache: m*m jittered grid over [lo, hi] (2D); s_j = |box|/M f(y)
  * 1[y in R]. */
