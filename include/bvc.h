@@ -147,6 +147,21 @@ int bvc_sample_cache(bvc_scene scene, int64_t n, double l, int32_t sides, uint64
                      uint32_t batch, double* x, double* nrm, double* w, double* xbar, double* R0,
                      int32_t* accept, void* stream);
 
+/* Cache points on the closed boundary of a region of interest R inside the
+ * domain (Section 3.2, "Boundary Specification"; Algorithm 1 with
+ * p^dR = 1/|dR|): candidate k sits at arc length (or area) (k + U_k)/n * |dR|
+ * along the primitives of `roi` (U_k the first uniform of Philox block 0,
+ * id k, tag 6; the second places it inside a triangle), with the primitive's
+ * unit outward normal (CCW segments, outward-wound triangles) and weight
+ * |dR|/n.  R0 and xbar: distance and closest point on the domain boundary
+ * `dom` (where the walks run); accept = 1 when the point lies strictly inside
+ * the domain.  Outputs as bvc_sample_cache.  Evaluation points inside R
+ * (bvc_classify on `roi` with l = 0) are then gathered from this cache; the
+ * estimate vanishes outside R.  The first call for `roi` uploads its sampling
+ * table and synchronises. */
+int bvc_sample_roi(bvc_scene dom, bvc_scene roi, int64_t n, uint64_t seed, uint32_t batch, double* x,
+                   double* nrm, double* w, double* xbar, double* R0, int32_t* accept, void* stream);
+
 /* Source samples (Eq. 4): m^dim jittered cells over the box [lo, hi] (host
  * arrays of dim doubles); s_j = |box|/m^dim * f(y_j) * 1[y_j inside and
  * d(y_j) > l].  y: [dim][m^dim] FP64 device, s: [m^dim] FP64 device. */

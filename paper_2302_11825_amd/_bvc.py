@@ -124,6 +124,7 @@ _SIGS = {
     "bvc_batch_counters": [_vp, _P(_vp)],
     "bvc_batch_destroy": [_vp],
     "bvc_point_winding": [_vp, C.c_int64, _vp, _vp, _vp],
+    "bvc_sample_roi": [_vp, _vp, C.c_int64, C.c_uint64, C.c_uint32, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
     "bvc_clamp_correction": [_vp, _P(bvc_walk_params), _P(bvc_clamp_params), C.c_int64, _vp, _vp, _vp, _vp, _vp,
                              C.c_size_t, _vp, _vp],
 }
@@ -254,6 +255,11 @@ def bvc_cache_measure(scene, l, sides) -> float:
     m = C.c_double()
     _check(_L.bvc_cache_measure(scene, l, sides, C.byref(m)), "bvc_cache_measure")
     return m.value
+
+
+def bvc_sample_roi(dom, roi, n, seed, batch, x, nrm, w, xbar, R0, accept, stream=None):
+    _check(_L.bvc_sample_roi(dom, roi, n, seed, batch, ptr(x), ptr(nrm), ptr(w), ptr(xbar), ptr(R0), ptr(accept),
+                             stream_ptr(stream)), "bvc_sample_roi")
 
 
 def bvc_sample_cache(scene, n, l, sides, seed, batch, x, nrm, w, xbar, R0, accept, stream=None):

@@ -172,6 +172,72 @@ __global__ __launch_bounds__(kBlock) void k_sample_cache(SceneDev S, int64_t n, 
   }
 }
 
+// Cache points on the closed boundary of a region of interest R inside the
+// domain (Section 3.2, "Boundary Specification"): uniform density 1/|dR|,
+// stratified uniforms (k + U_k)/n through the region's primitive measures
+// (its sampling table at l = 0 holds the segments or faces; the zero-measure
+// vertex and edge entries after them are never reached), the primitive's own
+// outward normal, and the distance and closest point on the domain boundary
+// where the walks run.  A point is accepted when it lies strictly inside the
+// domain.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_sample_roi(SceneDev Sd, SceneDev Sr, int64_t n, uint64_t seed,
+                                                        uint32_t batch, double M, double* x, double* nrm, double* w,
+                                                        double* xbar, double* R0, int* acc) {
+  extern __shared__ uint32_t lds[];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double ua, ub;
+  Uniform<double>::pair(seed, 0, (uint32_t)k, batch, 6, ua, ub);
+  const double target = ((double)k + ua) / (double)n * M;
+  int lo = 0, hi = Sr.np - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (Sr.cdf[mid] <= target) lo = mid;
+    else hi = mid - 1;
+  }
+  const double r = fmin(fmax((target - Sr.cdf[lo]) / Sr.meas[lo], 0.0), 1.0);
+  double xc[D], nc[D];
+  if constexpr (D == 2) {
+    const double* a = Sr.V + 2 * (size_t)Sr.P[2 * lo];
+    const double* b = Sr.V + 2 * (size_t)Sr.P[2 * lo + 1];
+    const double t0 = b[0] - a[0], t1 = b[1] - a[1];
+    const double len = sqrt(t0 * t0 + t1 * t1);
+    xc[0] = a[0] + r * t0;
+    xc[1] = a[1] + r * t1;
+    nc[0] = t1 / len;  // outward normal of a CCW loop
+    nc[1] = -t0 / len;
+  } else {
+    const double* A = Sr.V + 3 * (size_t)Sr.P[3 * lo];
+    const double* Bv = Sr.V + 3 * (size_t)Sr.P[3 * lo + 1];
+    const double* C = Sr.V + 3 * (size_t)Sr.P[3 * lo + 2];
+    const double su = sqrt(r);
+    const double b0 = 1 - su, b1 = su * (1 - ub), b2 = su * ub;
+    double ab[3], ac[3];
+    for (int q = 0; q < 3; ++q) {
+      ab[q] = Bv[q] - A[q];
+      ac[q] = C[q] - A[q];
+      xc[q] = b0 * A[q] + b1 * Bv[q] + b2 * C[q];
+    }
+    const double cr[3] = {ab[1] * ac[2] - ab[2] * ac[1], ab[2] * ac[0] - ab[0] * ac[2],
+                          ab[0] * ac[1] - ab[1] * ac[0]};
+    const double len = sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+    for (int q = 0; q < 3; ++q) nc[q] = cr[q] / len;
+  }
+  double q[D];
+  int hint = -1;
+  const double d = sqrt(closest_point<double, D>(Sd, xc, hint, q, lds + threadIdx.x, blockDim.x));
+  acc[k] = (d > 0.0 && inside_point<D>(Sd, xc, hint)) ? 1 : 0;
+  R0[k] = d;
+  w[k] = M / (double)n;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    x[a * n + k] = xc[a];
+    nrm[a * n + k] = nc[a];
+    xbar[a * n + k] = q[a];
+  }
+}
+
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_sample_sources(SceneDev S, FieldDev f, int64_t m, int64_t M, double lo0,
                                                             double lo1, double lo2, double hi0, double hi1,
@@ -369,6 +435,32 @@ int bvc_sample_cache(bvc_scene s, int64_t n, double l, int32_t sides, uint64_t s
     hipLaunchKernelGGL(k_sample_cache<3>, dim3(blocks), dim3(kBlock), lds, st, S, n, l, seed, batch, M, x, nrm, w,
                        xbar, R0, accept);
   return check_hip(hipGetLastError(), "sample_cache launch");
+}
+
+int bvc_sample_roi(bvc_scene dom, bvc_scene roi, int64_t n, uint64_t seed, uint32_t batch, double* x, double* nrm,
+                   double* w, double* xbar, double* R0, int32_t* accept, void* stream) {
+  int rc = check_scene(dom);
+  if (rc) return rc;
+  rc = check_scene(roi);
+  if (rc) return rc;
+  if (dom->h.dim != roi->h.dim) return fail(BVC_EINVAL, "the region and the domain differ in dimension");
+  if (n < 0 || n >= (int64_t)1 << 31) return fail(BVC_EINVAL, "n out of range");
+  if (n == 0) return BVC_OK;
+  if (!x || !nrm || !w || !xbar || !R0 || !accept) return fail(BVC_EINVAL, "null output");
+  hipStream_t st = (hipStream_t)stream;
+  rc = ensure_cdf(roi->h, 0.0, 1, st);
+  if (rc) return rc;
+  const double M = candidate_measure(roi->h, 0.0, 1);
+  const SceneDev Sd = dom->h.view(), Sr = roi->h.view();
+  const int blocks = (int)((n + kBlock - 1) / kBlock);
+  const size_t lds = stack_bytes(dom->h, kBlock);
+  if (Sd.dim == 2)
+    hipLaunchKernelGGL(k_sample_roi<2>, dim3(blocks), dim3(kBlock), lds, st, Sd, Sr, n, seed, batch, M, x, nrm, w,
+                       xbar, R0, accept);
+  else
+    hipLaunchKernelGGL(k_sample_roi<3>, dim3(blocks), dim3(kBlock), lds, st, Sd, Sr, n, seed, batch, M, x, nrm, w,
+                       xbar, R0, accept);
+  return check_hip(hipGetLastError(), "sample_roi launch");
 }
 
 int bvc_sample_sources(bvc_scene s, const bvc_field* f, int64_t m, const double* lo, const double* hi, double l,

@@ -113,6 +113,23 @@ def sample_cache(sc: Scene, n_cand, l, sides, seed, batch=0) -> Cache:
     return c
 
 
+def sample_roi(dom: Scene, roi: Scene, n_cand, seed, batch=0) -> Cache:
+    """Cache points on the boundary of a region of interest inside the domain
+    (Section 3.2), compacted to the accepted ones."""
+    d, dev = dom.dim, dom.device
+    f64 = torch.float64
+    x = torch.empty(d, n_cand, dtype=f64, device=dev)
+    nrm = torch.empty_like(x)
+    xbar = torch.empty_like(x)
+    w = torch.empty(n_cand, dtype=f64, device=dev)
+    R0 = torch.empty_like(w)
+    acc = torch.empty(n_cand, dtype=torch.int32, device=dev)
+    B.bvc_sample_roi(dom.h, roi.h, n_cand, seed, batch, x, nrm, w, xbar, R0, acc)
+    idx, n = dom.compact(acc, 1)
+    return Cache(n, take(x, idx, n, d, n_cand), take(nrm, idx, n, d, n_cand), take(w, idx, n, 1, n_cand),
+                 take(xbar, idx, n, d, n_cand), take(R0, idx, n, 1, n_cand), n_cand)
+
+
 def candidates_for(sc: Scene, n_target, l, sides, seed, pilot=65536):
     """Number of candidates whose expected accepted count is n_target, from a
     pilot draw with an independent batch index."""
@@ -275,6 +292,71 @@ class Prepared:
                           seed=int(clamp.get("seed", p.seed_walks + 1)),
                           ws=torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device),
                           counters=torch.zeros(6, dtype=torch.int64, device=device))
+
+
+class RoiPrepared:
+    """Region-of-interest caching (Section 3.2, "Boundary Specification"):
+    the cache lives on the closed boundary of a region R inside the domain
+    (uniform p^dR = 1/|dR|), its walks run on the domain, and only evaluation
+    points inside R are gathered (the estimate vanishes outside R).  Sources,
+    when the problem has any, are drawn inside R."""
+
+    def __init__(self, problem, roi_scene, dtype=None, n_cand=None, device="cuda", eval_x=None):
+        self.p = problem
+        self.dtype = dtype or problem.precision
+        self.sc = Scene(problem.scene, device)
+        self.roi = Scene(roi_scene, device)
+        self.g = DeviceField(problem.g, device)
+        self.f = DeviceField(problem.f, device) if not problem.f.is_zero else None
+        self.n_cand = int(n_cand or problem.n_cache)
+        ex = problem.eval_x if eval_x is None else eval_x
+        self.eval64 = torch.from_numpy(np.ascontiguousarray(ex.T)).to(device)
+        n = self.eval64.shape[1]
+        self.cls, self.dist = classify(self.roi, self.eval64, 0.0)
+        self.idx_int, self.n_int = self.roi.compact(self.cls, 1)
+        self.x_int = take(self.eval64, self.idx_int, self.n_int, self.sc.dim, n, DT[self.dtype])
+
+
+def solve_roi(prep: RoiPrepared, batch=0, with_grad=True, watch=None) -> Solution:
+    """Algorithm 1 on a region of interest: samples on dR, walks on the
+    domain, then the gather at the evaluation points inside R."""
+    p, sc, roi = prep.p, prep.sc, prep.roi
+    dt, d = prep.dtype, sc.dim
+    T = DT[dt]
+    watch = watch or _NoWatch()
+    with watch.stage("sample_cache"):
+        cache = sample_roi(sc, roi, prep.n_cand, p.seed_cache, batch)
+    wp = walk_params(p.eps, p.n_walks, p.seed_walks, prep.g, prep.f, dt, batch, sigma=p.sigma)
+    with watch.stage("cache_walks"):
+        U, D, rec, counters = cache_walks(sc, cache, wp, dt)
+    with watch.stage("reduce_walks"):
+        uhat, dudn, a, b = reduce_walks(cache, p.n_walks, U, D, dt)
+    if T != torch.float64:
+        cx = take(cache.x, None, cache.n, d, cache.n, T)
+        cn = take(cache.nrm, None, cache.n, d, cache.n, T)
+    else:
+        cx, cn = cache.x, cache.nrm
+    cview = dict(n=cache.n, dtype=CODE[dt], x=cx, nrm=cn, a=a, b=b)
+    sview = None
+    if prep.f is not None and p.n_sources > 0:
+        m = int(round(p.n_sources ** (1.0 / d)))
+        with watch.stage("sample_sources"):
+            y64, s64, M = sample_sources(roi, prep.f, m, 0.0, p.seed_sources, batch)
+            y = take(y64, None, M, d, M, T) if T != torch.float64 else y64
+            s = take(s64, None, M, 1, M, T) if T != torch.float64 else s64
+        sview = dict(n=M, dtype=CODE[dt], y=y, s=s)
+    n_int = prep.n_int
+    u_int = torch.empty(max(n_int, 1), dtype=T, device=sc.device)
+    g_int = torch.empty(d, max(n_int, 1), dtype=T, device=sc.device) if with_grad else None
+    with watch.stage("gather"):
+        if with_grad:
+            B.bvc_gather_grad(d, cview, sview, n_int, prep.x_int, u_int, g_int, sigma=p.sigma)
+        else:
+            B.bvc_gather_u(d, cview, sview, n_int, prep.x_int, u_int, sigma=p.sigma)
+    empty = torch.zeros(1, dtype=T, device=sc.device)
+    return Solution(prep.idx_int, n_int, torch.zeros(1, dtype=torch.int32, device=sc.device), 0, u_int, g_int,
+                    empty, None, cache, uhat, dudn, counters, torch.zeros(4, dtype=torch.int64, device=sc.device),
+                    extra=dict(U=U, D=D, a=a, b=b, cview=cview, sview=sview, rec=rec))
 
 
 class SceneBatch:
