@@ -11,6 +11,8 @@
                                      plain, clamped-only and corrected estimates
     python bench.py --workload c3clamp --clamp-c 1600   the same on the 3D Laplace step
     python bench.py --workload c3screen  the 3D step on the screened equation (sigma = 4)
+    python bench.py --workload c2roi     the 2D Poisson problem cached on the boundary of a
+                                     disk inside the star (region of interest, Section 3.2)
 
 Each prints one JSON line.  Inputs are the seeded synthetic workloads.
 """
@@ -56,7 +58,7 @@ def _log(msg):
 
 def run(args):
     {"c3": c3, "c4a": c4a, "c4b": c4b, "c2clamp": c2clamp, "c3clamp": c3clamp,
-     "c3screen": c3screen}[args.workload](args)
+     "c3screen": c3screen, "c2roi": c2roi}[args.workload](args)
 
 
 def _c3_setup(args, prob=None):
@@ -297,4 +299,50 @@ def _clamp_measure(args, prob, name, with_grad):
            "ms_per_step": ms, "ms_per_step_plain": ms_plain, "stage_ms": stages, "stage_ms_plain": stages_p,
            "error_near_offset_boundary": err, "far_points_max_abs_diff": far_diff,
            "points_per_s": (prep.n_int + prep.n_band) / (ms / 1e3)}
+    print(json.dumps(out))
+
+
+def c2roi(args):
+    """The 2D Poisson problem with its cache on the boundary of a disk inside
+    the star (Section 3.2, region of interest): the same cache size, walks and
+    source count as the full step, spent on the region instead of the jagged
+    boundary.  Compared with the full step on the same evaluation points."""
+    prob = wl.problem_c2()
+    r_in = float(np.min(np.linalg.norm(prob.scene.verts, axis=1)))
+    radius = 0.6 * r_in
+    t = np.linspace(0, 2 * np.pi, 1025)[:-1]
+    roi = wl.Scene(2, np.stack([radius * np.cos(t), radius * np.sin(t)], 1),
+                   np.array([[i, (i + 1) % 1024] for i in range(1024)], dtype=np.int32), "roi_disk")
+    t0 = time.time()
+    prep = pl.RoiPrepared(prob, roi, dtype="f32", n_cand=prob.n_cache)
+    full = pl.Prepared(prob, dtype="f32")
+    torch.cuda.synchronize()
+    _log(f"c2roi setup {time.time() - t0:.1f}s: region radius {radius:.3f}, points inside {prep.n_int}")
+    for _ in range(max(1, args.warmup)):
+        pl.solve_roi(prep)
+    torch.cuda.synchronize()
+    watch = pl.Stopwatch()
+    e0, e1 = _ev(), _ev()
+    e0.record()
+    for _ in range(args.steps):
+        sol = pl.solve_roi(prep, watch=watch)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    stages = {k: sum(v) / len(v) for k, v in watch.totals_ms().items()}
+    sol_full = pl.solve(full)
+    torch.cuda.synchronize()
+    idx = prep.idx_int[: prep.n_int].cpu().numpy()
+    truth = wl.field_value(prob.truth, prob.eval_x[idx])
+    u_roi = sol.u_int[: prep.n_int].double().cpu().numpy()
+    # the same points in the full step (all of them are gathered there: the
+    # region keeps away from the boundary band)
+    pos_full = np.searchsorted(full.idx_int[: full.n_int].cpu().numpy(), idx)
+    u_full = sol_full.u_int.double().cpu().numpy()[pos_full]
+    rmse = lambda u: float(np.sqrt(np.mean((u - truth) ** 2)))
+    out = {"workload": "c2roi_star4096_poisson_disk", "region_radius": radius, "points_inside": prep.n_int,
+           "cache_points": sol.cache.n, "walks_per_point": prob.n_walks, "ms_per_step": ms, "stage_ms": stages,
+           "points_per_s": prep.n_int / (ms / 1e3), "rmse_region_cache": rmse(u_roi),
+           "rmse_full_cache_same_points": rmse(u_full), "rms_truth": float(np.sqrt(np.mean(truth**2))),
+           "walk_steps": int(sol.counters[1])}
     print(json.dumps(out))
