@@ -206,7 +206,7 @@ def main():
     # the gather's template names its evaluation points per thread: the tuned
     # value, else the library's default of 2
     ppt = tuned["gather_points_per_thread"] if tuned else 2
-    gather_kernel = f"k_gather<float,2,true,false,{ppt}>"
+    gather_kernel = f"k_gather<float,2,true,false,{ppt},false>"
     roofline_gather = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                        "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
                        "traffic": measured_traffic(gather_kernel, GATHER_SOURCES),
