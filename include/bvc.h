@@ -76,6 +76,11 @@ extern "C" {
  *   7 POINT_SOURCE 2D A ln|x-x0|, 3D A/|x-x0|, A = param[0], x0 = param[1..]
  *   8 EXP_PLANE    A exp(a . x), A = param[0], a = param[1..dim] (solves
  *                  Lap u = |a|^2 u: the screened equation's plane waves)
+ *   9 WEDGE_2D     A r^p cos(p phi), r, phi = polar coordinates about
+ *                  (param[2], param[3]) with phi in [0, 2 pi); A = param[0],
+ *                  p = param[1] (harmonic off the cut phi = 0; with p = 2/3
+ *                  it has zero normal derivative on both edges of a 270
+ *                  degree corner)
  */
 typedef struct {
   int32_t kind;

@@ -112,6 +112,8 @@ def lib():
         L.orc_screen_grad_weight.restype = C.c_double
         L.orc_gather_sigma.argtypes = [C.c_int, C.c_double, C.c_int64, _dp, C.c_int64, _dp, _dp, _dp, _dp,
                                        C.c_int64, _dp, _dp, _dp, _dp, _dp]
+        L.orc_wost_walks.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(_Field), C.POINTER(_WalkParams), C.c_int,
+                                     C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _ip]
         L.orc_sample_roi.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_uint64, C.c_uint32, _dp, _dp, _dp,
                                      _dp, _dp, _ip]
         L.orc_sample_roi.restype = C.c_int64
@@ -600,3 +602,19 @@ def sample_roi(dom: Scene, roi: Scene, n, seed, batch=0):
     acc = np.zeros(n, np.int32)
     na = lib().orc_sample_roi(dom.h, roi.h, n, int(seed), int(batch), _d(x), _d(nrm), _d(w), _d(xb), _d(R0), _i(acc))
     return dict(x=x, n=nrm, w=w, xbar=xb, R0=R0, accept=acc.astype(bool), n_accepted=na)
+
+
+# --- Walk on stars, mixed Dirichlet / Neumann (2D, h = 0) --------------------
+def wost_walks(dir_scene: Scene, neu_scene: Scene, g, params, mode, x, nrm=None, R0=None, xbar=None):
+    """U (and D in mode 0) per walk, shape (n * W,); see orc_wost_walks."""
+    x = _f64(x).reshape(-1, 2)
+    n, W = x.shape[0], params.n_walks
+    U = np.zeros(n * W)
+    D = np.zeros(n * W)
+    st = np.zeros(n * W, np.int32)
+    G = _field(g)
+    lib().orc_wost_walks(dir_scene.h, neu_scene.h, C.byref(G), C.byref(params), int(mode), n, _d(x),
+                         _d(_f64(nrm).reshape(-1, 2)) if nrm is not None else None,
+                         _d(_f64(R0)) if R0 is not None else None,
+                         _d(_f64(xbar).reshape(-1, 2)) if xbar is not None else None, _d(U), _d(D), _i(st))
+    return U, D, st

@@ -644,6 +644,12 @@ double orc_field_eval(const orc_field* F, int dim, const double* x) {
       for (int a = 0; a < dim; ++a) e += p[1 + a] * x[a];
       return p[0] * exp(e);
     }
+    case ORC_FIELD_WEDGE_2D: {
+      double dx = x[0] - p[2], dy = x[1] - p[3];
+      double phi = atan2(dy, dx);
+      if (phi < 0) phi += 2 * ORC_PI;
+      return p[0] * pow(hypot(dx, dy), p[1]) * cos(p[1] * phi);
+    }
   }
   return 0.0;
 }
@@ -1562,6 +1568,185 @@ void orc_basis_means(const orc_field* basis, int dim, int64_t n_cache, int32_t W
       F[i * nb + m] = sf / W;
     }
   }
+}
+
+/* ======================================================================== */
+/* Walk on stars for mixed Dirichlet / Neumann boundaries (Section 3.1: the  */
+/* WoSt estimator the cache relies on; 2D, Neumann data h = 0, no source)    */
+/* ======================================================================== */
+/* The Dirichlet part `dir` and the Neumann part `neu` are two segment sets
+ * of one counter-clockwise boundary.  Seen from x, a vertex of the Neumann
+ * part is a silhouette point when both Neumann segments at it lie on the same
+ * side of the line through x and the vertex, or when the Neumann part ends
+ * there. */
+typedef struct {
+  int32_t* prev;     /* per Neumann segment: start vertex of the Neumann segment ending at its start, or -1 */
+  int32_t* has_next; /* 1 when a Neumann segment starts at its end vertex */
+} neu_links;
+
+static neu_links make_links(const orc_scene* neu) {
+  neu_links L;
+  int64_t np = neu->np, nv = neu->nv;
+  L.prev = (int32_t*)malloc((size_t)np * sizeof(int32_t));
+  L.has_next = (int32_t*)malloc((size_t)np * sizeof(int32_t));
+  int32_t* ends_at = (int32_t*)malloc((size_t)nv * sizeof(int32_t));
+  int32_t* starts_at = (int32_t*)malloc((size_t)nv * sizeof(int32_t));
+  for (int64_t v = 0; v < nv; ++v) ends_at[v] = starts_at[v] = -1;
+  for (int64_t q = 0; q < np; ++q) {
+    starts_at[neu->P[2 * q]] = (int32_t)q;
+    ends_at[neu->P[2 * q + 1]] = (int32_t)q;
+  }
+  for (int64_t q = 0; q < np; ++q) {
+    int32_t r = ends_at[neu->P[2 * q]];
+    L.prev[q] = r >= 0 ? neu->P[2 * r] : -1;
+    L.has_next[q] = starts_at[neu->P[2 * q + 1]] >= 0;
+  }
+  free(ends_at);
+  free(starts_at);
+  return L;
+}
+
+static double cross2(double ax, double ay, double bx, double by) { return ax * by - ay * bx; }
+
+/* Side of point w relative to the line from x through v: +1, -1, or 0 when
+ * within a relative 1e-9 of it (a walk standing on a Neumann segment lies on
+ * that segment's line only up to rounding). */
+static int line_side(const double* x, const double* v, const double* w) {
+  double vx = v[0] - x[0], vy = v[1] - x[1], wx = w[0] - v[0], wy = w[1] - v[1];
+  double c = cross2(vx, vy, wx, wy);
+  if (fabs(c) <= 1e-9 * hypot(vx, vy) * hypot(wx, wy)) return 0;
+  return c > 0 ? 1 : -1;
+}
+
+/* Distance from x to the closest silhouette vertex of the Neumann part: a
+ * vertex whose two Neumann neighbours lie strictly on one side of the line
+ * from x through it, or one on the line and the other off it (x looks along
+ * one segment past the corner); a vertex on a straight run seen along that
+ * run is none. */
+static double silhouette_distance(const orc_scene* neu, const neu_links* L, const double* x) {
+  double best = INFINITY;
+  for (int64_t q = 0; q < neu->np; ++q) {
+    const double* a = neu->V + 2 * (int64_t)neu->P[2 * q];
+    const double* b = neu->V + 2 * (int64_t)neu->P[2 * q + 1];
+    int sil = 1;
+    if (L->prev[q] >= 0) {
+      const double* u = neu->V + 2 * (int64_t)L->prev[q];
+      int s1 = line_side(x, a, u), s2 = line_side(x, a, b);
+      sil = (s1 * s2 > 0) || ((s1 == 0) != (s2 == 0));
+    }
+    if (sil) best = fmin(best, hypot(a[0] - x[0], a[1] - x[1]));
+    if (!L->has_next[q]) best = fmin(best, hypot(b[0] - x[0], b[1] - x[1]));
+  }
+  return best;
+}
+
+/* Nearest crossing of the ray x + t w, lo < t <= hi, with a Neumann segment:
+ * its t (INFINITY if none), and the segment in *seg (-1 if none). */
+static double neumann_hit(const orc_scene* neu, const double* x, const double* w, double lo, double hi,
+                          int64_t* seg) {
+  double best = INFINITY;
+  *seg = -1;
+  for (int64_t q = 0; q < neu->np; ++q) {
+    const double* a = neu->V + 2 * (int64_t)neu->P[2 * q];
+    const double* b = neu->V + 2 * (int64_t)neu->P[2 * q + 1];
+    double e0 = b[0] - a[0], e1 = b[1] - a[1];
+    double den = cross2(w[0], w[1], e0, e1);
+    if (den == 0) continue;
+    double r0 = a[0] - x[0], r1 = a[1] - x[1];
+    double t = cross2(r0, r1, e0, e1) / den;
+    double u = cross2(r0, r1, w[0], w[1]) / den;
+    if (t > lo && t <= hi && u >= 0 && u <= 1 && t < best) {
+      best = t;
+      *seg = q;
+    }
+  }
+  return best;
+}
+
+/* One walk on stars (modes as orc_wost_walks). */
+static void wost_walk(const orc_scene* dir, const orc_scene* neu, const neu_links* L, const orc_field* g,
+                      const orc_walk_params* p, int mode, const double* x, const double* n, double R0,
+                      const double* xbar, uint32_t id, double* U, double* D, int32_t* steps, int32_t* capped) {
+  uint32_t tag = mode == 0 ? 1u : 2u;
+  double pos[2] = {x[0], x[1]}, nin[2] = {0, 0}, nu0[2] = {0, 0};
+  int onb = 0;
+  int32_t k = 0;
+  *capped = 0;
+  if (mode == 0) {
+    /* first ball, wholly inside the domain: the gradient estimate of Eq. 7 */
+    walk_direction(p->seed, 0, id, p->batch, tag, 2, nu0);
+    pos[0] = x[0] + R0 * nu0[0];
+    pos[1] = x[1] + R0 * nu0[1];
+    k = 1;
+  } else if (mode == 3) {
+    onb = 1;
+    nin[0] = -n[0];
+    nin[1] = -n[1];
+  }
+  double W;
+  for (;; ++k) {
+    double dD, qD[3];
+    orc_closest(dir, pos, 0, &dD, qD, NULL);
+    if (dD < p->eps || k >= p->max_steps) {
+      *capped = !(dD < p->eps);
+      W = orc_field_eval(g, 2, qD);
+      break;
+    }
+    double R = fmax(fmin(dD, silhouette_distance(neu, L, pos)), p->eps);
+    double w[2];
+    walk_direction(p->seed, (uint32_t)k, id, p->batch, tag, 2, w);
+    if (onb && w[0] * nin[0] + w[1] * nin[1] < 0) {
+      w[0] = -w[0];
+      w[1] = -w[1];
+    }
+    int64_t seg;
+    double t = neumann_hit(neu, pos, w, 1e-9 * R, R, &seg);
+    if (seg >= 0) {
+      const double* a = neu->V + 2 * (int64_t)neu->P[2 * seg];
+      const double* b = neu->V + 2 * (int64_t)neu->P[2 * seg + 1];
+      double e0 = b[0] - a[0], e1 = b[1] - a[1], len = hypot(e0, e1);
+      pos[0] += t * w[0];
+      pos[1] += t * w[1];
+      nin[0] = -e1 / len; /* inward normal of a counter-clockwise boundary */
+      nin[1] = e0 / len;
+      onb = 1;
+    } else {
+      pos[0] += R * w[0];
+      pos[1] += R * w[1];
+      onb = 0;
+    }
+  }
+  *steps = k;
+  *U = W;
+  if (D) {
+    *D = 0;
+    if (mode == 0) {
+      double c = p->control_variate ? orc_field_eval(g, 2, xbar) : 0.0;
+      *D = 2.0 / R0 * (nu0[0] * n[0] + nu0[1] * n[1]) * (W - c);
+    }
+  }
+}
+
+void orc_wost_walks(const orc_scene* dir, const orc_scene* neu, const orc_field* g, const orc_walk_params* p,
+                    int mode, int64_t n, const double* x, const double* nrm, const double* R0, const double* xbar,
+                    double* U, double* D, int32_t* steps) {
+  neu_links L = make_links(neu);
+  int64_t W = p->n_walks;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t i = 0; i < n; ++i) {
+    for (int64_t j = 0; j < W; ++j) {
+      int64_t id = i * W + j;
+      int32_t st, cap;
+      double uu, dd;
+      wost_walk(dir, neu, &L, g, p, mode, x + 2 * i, nrm ? nrm + 2 * i : NULL, R0 ? R0[i] : 0.0,
+                xbar ? xbar + 2 * i : NULL, (uint32_t)id, &uu, &dd, &st, &cap);
+      U[id] = uu;
+      if (D) D[id] = dd;
+      if (steps) steps[id] = st;
+    }
+  }
+  free(L.prev);
+  free(L.has_next);
 }
 
 /* ======================================================================== */

@@ -55,7 +55,8 @@ enum {
   ORC_FIELD_SOLID_HARMONICS_3D = 5,
   ORC_FIELD_FOURIER_2D = 6,
   ORC_FIELD_POINT_SOURCE = 7,
-  ORC_FIELD_EXP_PLANE = 8
+  ORC_FIELD_EXP_PLANE = 8,
+  ORC_FIELD_WEDGE_2D = 9
 };
 
 typedef struct {
@@ -224,6 +225,23 @@ double orc_screen_grad_weight(int dim, double sigma, double R);
 void orc_gather_sigma(int dim, double sigma, int64_t K, const double* ex, int64_t N, const double* cy,
                       const double* cn, const double* a, const double* b, int64_t M, const double* sy,
                       const double* sw, double* u, double* grad, double* cond);
+
+/* --- Walk on stars, mixed Dirichlet / Neumann boundaries (2D, h = 0) ---- */
+/* `dir` and `neu` hold the Dirichlet and the Neumann segments of one
+ * counter-clockwise boundary.  Walk j of start point i has id i*W + j.
+ * mode 0: from an offset Dirichlet cache point (normal nrm, R0 = distance to
+ * the whole boundary, xbar = closest Dirichlet point): first ball of radius
+ * R0 with the gradient estimate D = n . (2/R0) nu (W - g(xbar)) (Eq. 7), tag
+ * 1; mode 1: from an interior point, tag 2; mode 3: from a point on the
+ * Neumann boundary (nrm = outward normal), tag 2.  Star radius
+ * max(eps, min(d_Dirichlet, d_silhouette)); direction uniform (block 4k),
+ * turned into the inward half circle on the Neumann boundary; the next point
+ * is the nearest Neumann crossing within the radius, else the sphere point.
+ * Stops when d_Dirichlet < eps (or max_steps) with U = g at the closest
+ * Dirichlet point.  D may be NULL. */
+void orc_wost_walks(const orc_scene* dir, const orc_scene* neu, const orc_field* g, const orc_walk_params* p,
+                    int mode, int64_t n, const double* x, const double* nrm, const double* R0, const double* xbar,
+                    double* U, double* D, int32_t* steps);
 
 /* --- Clamped double-layer kernel and bias correction (Section 3.4) ------ */
 /* Distance beyond which |dG/dn| cannot exceed c (INFINITY for c <= 0). */

@@ -732,6 +732,12 @@ __device__ inline double field_value(const FieldDev& F, int dim, const double* x
       for (int a = 0; a < dim; ++a) e = fma(p[1 + a], x[a], e);
       return p[0] * exp(e);
     }
+    case 9: {
+      const double dx = x[0] - p[2], dy = x[1] - p[3];
+      double phi = atan2(dy, dx);
+      if (phi < 0.0) phi += 2.0 * kPi;
+      return p[0] * pow(hypot(dx, dy), p[1]) * cos(p[1] * phi);
+    }
   }
   return 0.0;
 }

@@ -35,6 +35,8 @@ kind   name                 value at x
 7      POINT_SOURCE         2D: A ln|x-x0|; 3D: A/|x-x0|; A=param[0], x0=param[1:]
 8      EXP_PLANE            A exp(a.x), A=param[0], a=param[1:1+dim]; solves
                             Lap u = |a|^2 u (screened Poisson, Eq. 1 with f = 0)
+9      WEDGE_2D             A r^p cos(p phi), polar (r, phi in [0, 2 pi)) about
+                            (param[2], param[3]); A=param[0], p=param[1]
 =====  ===================  =====================================================
 """
 from __future__ import annotations
@@ -54,6 +56,7 @@ FIELD_SOLID_HARMONICS_3D = 5
 FIELD_FOURIER_2D = 6
 FIELD_POINT_SOURCE = 7
 FIELD_EXP_PLANE = 8
+FIELD_WEDGE_2D = 9
 
 
 def seed(k: int, p: int) -> int:
@@ -116,6 +119,10 @@ def point_source(amp, x0) -> Field:
 
 def exp_plane(amp, a) -> Field:
     return Field(FIELD_EXP_PLANE, np.zeros(0), [amp, *a])
+
+
+def wedge_2d(amp, p, center=(0.0, 0.0)) -> Field:
+    return Field(FIELD_WEDGE_2D, np.zeros(0), [amp, p, center[0], center[1]])
 
 
 # --------------------------------------------------------------------------
@@ -208,6 +215,10 @@ def field_value(fld: Field, x: np.ndarray) -> np.ndarray:
     if k == FIELD_EXP_PLANE:
         d = x.shape[1]
         return p[0] * np.exp(x @ p[1 : 1 + d])
+    if k == FIELD_WEDGE_2D:
+        dx, dy = x[:, 0] - p[2], x[:, 1] - p[3]
+        phi = np.mod(np.arctan2(dy, dx), 2 * np.pi)
+        return p[0] * np.hypot(dx, dy) ** p[1] * np.cos(p[1] * phi)
     raise ValueError(f"unknown field kind {k}")
 
 
