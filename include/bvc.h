@@ -314,6 +314,38 @@ int bvc_gather_grad(int32_t dim, const bvc_cache_view* cache, const bvc_source_v
                     const bvc_gather_params* params, void* stream);
 
 /* ---------------------------------------------------------------------- */
+/* Walk on stars: mixed Dirichlet / Neumann boundaries (Section 3.1)       */
+/* ---------------------------------------------------------------------- */
+/* The estimator the cache uses when part of the boundary is Neumann (walk on
+ * stars; 2D, Neumann data h = 0, no source, no screening).  `dir` and `neu`
+ * hold the Dirichlet and the Neumann segments of one counter-clockwise
+ * boundary (two scenes over the same vertices).  Walk j of start point i has
+ * id i*W + j (n*W < 2^32).  Each step: star radius R = max(eps, min(d_D,
+ * d_S)), d_D the distance to the Dirichlet part and d_S to the closest
+ * silhouette vertex of the Neumann part seen from the walk (both Neumann
+ * neighbours strictly on one side of the line of sight, or one on it and the
+ * other off it, within 1e-9 relative in FP64 and 1e-5 in FP32; ends of
+ * Neumann runs included); a direction uniform on the circle (Philox block 4k
+ * as walk on spheres), turned into the inward half circle on the Neumann
+ * part; the walk moves to the nearest Neumann crossing within R, else to the
+ * sphere; it stops when d_D < eps (or after max_steps, counted as capped)
+ * with U = g(closest Dirichlet point), evaluated in FP64.
+ * mode 0: from offset Dirichlet cache points x with normals nrm, R0 = the
+ *   distance to the whole boundary and xbar = the closest Dirichlet point:
+ *   a first ball of radius R0 (no test at x), tag 1, and
+ *   D = n . (2/R0) nu (W - c) (Eq. 7, c = g(xbar) with the control variate);
+ * mode 1: from interior points, tag 2 (D = 0);
+ * mode 3: from points on the Neumann part with outward normals nrm, tag 2.
+ * x, nrm, xbar: [2][n] FP64; R0 [n]; U, D (optional): [n*W] of dtype;
+ * steps (optional) int32 [n*W].  workspace: caller-owned, at least
+ * bvc_wost_workspace_bytes(neu) bytes (the Neumann run links, uploaded by
+ * the call, which synchronises once).  counters: uint64[4] as the walks. */
+size_t bvc_wost_workspace_bytes(bvc_scene neu);
+int bvc_wost_walks(bvc_scene dir, bvc_scene neu, const bvc_walk_params* params, int32_t mode, int64_t n,
+                   const double* x, const double* nrm, const double* R0, const double* xbar, void* U, void* D,
+                   int32_t* steps, void* workspace, size_t workspace_bytes, uint64_t* counters, void* stream);
+
+/* ---------------------------------------------------------------------- */
 /* Bias correction of the clamped gather (Section 3.4, Eq. 8)              */
 /* ---------------------------------------------------------------------- */
 /* Clamping dG/dn at c (bvc_gather_params.clamp_c) removes the near-boundary

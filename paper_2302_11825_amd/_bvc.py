@@ -124,6 +124,8 @@ _SIGS = {
     "bvc_batch_counters": [_vp, _P(_vp)],
     "bvc_batch_destroy": [_vp],
     "bvc_point_winding": [_vp, C.c_int64, _vp, _vp, _vp],
+    "bvc_wost_walks": [_vp, _vp, _P(bvc_walk_params), C.c_int32, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                       _vp, C.c_size_t, _vp, _vp],
     "bvc_sample_roi": [_vp, _vp, C.c_int64, C.c_uint64, C.c_uint32, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
     "bvc_clamp_correction": [_vp, _P(bvc_walk_params), _P(bvc_clamp_params), C.c_int64, _vp, _vp, _vp, _vp, _vp,
                              C.c_size_t, _vp, _vp],
@@ -144,6 +146,8 @@ _L.bvc_gather_multi_workspace_bytes.argtypes = [C.c_int64, C.c_int32]
 _L.bvc_gather_multi_workspace_bytes.restype = C.c_size_t
 _L.bvc_batch_workspace_bytes.argtypes = [_P(bvc_batch_item), C.c_int32]
 _L.bvc_batch_workspace_bytes.restype = C.c_size_t
+_L.bvc_wost_workspace_bytes.argtypes = [_vp]
+_L.bvc_wost_workspace_bytes.restype = C.c_size_t
 _L.bvc_clamp_radius.argtypes = [C.c_int32, C.c_double]
 _L.bvc_clamp_radius.restype = C.c_double
 _L.bvc_clamp_workspace_bytes.argtypes = [C.c_int32, C.c_int32, C.c_int64, C.c_int32, C.c_int32]
@@ -152,7 +156,7 @@ _L.bvc_clamp_workspace_bytes.restype = C.c_size_t
 EXPORTED = sorted(list(_SIGS) + ["bvc_last_error", "bvc_version", "bvc_compact_scratch_ints",
                                  "bvc_cache_backward_scratch_doubles", "bvc_pointwise_workspace_bytes",
                                  "bvc_gather_multi_workspace_bytes", "bvc_batch_workspace_bytes",
-                                 "bvc_clamp_radius", "bvc_clamp_workspace_bytes"])
+                                 "bvc_clamp_radius", "bvc_clamp_workspace_bytes", "bvc_wost_workspace_bytes"])
 
 
 def _check(rc, name):
@@ -468,3 +472,15 @@ def bvc_clamp_correction(scene, params: bvc_walk_params, cp: bvc_clamp_params, n
     nbytes = 0 if work is None else work.numel() * work.element_size()
     _check(_L.bvc_clamp_correction(scene, C.byref(params), C.byref(cp), n, ptr(x), ptr(wind), ptr(out_index), ptr(u),
                                    ptr(work), nbytes, ptr(counters), stream_ptr(stream)), "bvc_clamp_correction")
+
+
+def bvc_wost_workspace_bytes(neu):
+    return _L.bvc_wost_workspace_bytes(neu)
+
+
+def bvc_wost_walks(dir_scene, neu_scene, params: bvc_walk_params, mode, n, x, nrm, R0, xbar, U, D, steps, work,
+                   counters, stream=None):
+    nbytes = 0 if work is None else work.numel() * work.element_size()
+    _check(_L.bvc_wost_walks(dir_scene, neu_scene, C.byref(params), mode, n, ptr(x), ptr(nrm), ptr(R0), ptr(xbar),
+                             ptr(U), ptr(D), ptr(steps), ptr(work), nbytes, ptr(counters), stream_ptr(stream)),
+           "bvc_wost_walks")

@@ -20,7 +20,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libbvc.so")
 
 SOURCES = ["scene.cpp", "kernels_walk.hip", "walks.hip", "kernels_gather.hip", "kernels_multi.hip",
-           "kernels_mfma.hip", "batch.hip", "kernels_clamp.hip"]
+           "kernels_mfma.hip", "batch.hip", "kernels_clamp.hip",
+           "kernels_wost.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
