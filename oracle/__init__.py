@@ -114,6 +114,9 @@ def lib():
                                        C.c_int64, _dp, _dp, _dp, _dp, _dp]
         L.orc_wost_walks.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(_Field), C.POINTER(_WalkParams), C.c_int,
                                      C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _ip]
+        L.orc_sample_mixed.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_uint64,
+                                       C.c_uint32, _dp, _dp, _dp, _dp, _dp, _ip, _ip]
+        L.orc_sample_mixed.restype = C.c_int64
         L.orc_sample_roi.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_uint64, C.c_uint32, _dp, _dp, _dp,
                                      _dp, _dp, _ip]
         L.orc_sample_roi.restype = C.c_int64
@@ -618,3 +621,17 @@ def wost_walks(dir_scene: Scene, neu_scene: Scene, g, params, mode, x, nrm=None,
                          _d(_f64(R0)) if R0 is not None else None,
                          _d(_f64(xbar).reshape(-1, 2)) if xbar is not None else None, _d(U), _d(D), _i(st))
     return U, D, st
+
+
+def sample_mixed(full: Scene, dir_scene: Scene, neu_scene: Scene, n, l, seed, batch=0):
+    """Cache candidates on the offset Dirichlet boundary and the Neumann part."""
+    x = np.zeros((n, 2))
+    nrm = np.zeros((n, 2))
+    w = np.zeros(n)
+    xb = np.zeros((n, 2))
+    R0 = np.zeros(n)
+    ty = np.zeros(n, np.int32)
+    acc = np.zeros(n, np.int32)
+    na = lib().orc_sample_mixed(full.h, dir_scene.h, neu_scene.h, n, float(l), int(seed), int(batch), _d(x), _d(nrm),
+                                _d(w), _d(xb), _d(R0), _i(ty), _i(acc))
+    return dict(x=x, n=nrm, w=w, xbar=xb, R0=R0, type=ty, accept=acc.astype(bool), n_accepted=na)

@@ -1749,6 +1749,91 @@ void orc_wost_walks(const orc_scene* dir, const orc_scene* neu, const orc_field*
   free(L.has_next);
 }
 
+/* Cache candidates for a boundary with a Neumann part (Section 3.2, "Boundary
+ * Specification": samples on the Neumann part and on the offset Dirichlet
+ * boundary at distance l > eps).  One stratified draw (Philox tag 7) over the
+ * concatenated measures of the offset Dirichlet elements (as
+ * orc_sample_cache with sides 1, on the Dirichlet segments `dir`) followed
+ * by the Neumann segments `neu`.  An offset candidate is kept when its
+ * distance to the Dirichlet part is l (1e-9 relative) and it lies inside the
+ * domain `full`; a Neumann candidate when its distance to the Dirichlet part
+ * exceeds l.  Outputs: x, nrm (offset points: towards the closest Dirichlet
+ * point; Neumann points: the segment's outward normal), w = total measure /
+ * n, xbar = closest Dirichlet point, R0 = distance to the whole boundary,
+ * type (0 offset, 1 Neumann), accept.  Returns the number accepted. */
+int64_t orc_sample_mixed(const orc_scene* full, const orc_scene* dir, const orc_scene* neu, int64_t n, double l,
+                         uint64_t seed, uint32_t batch, double* x, double* nrm, double* w, double* xbar, double* R0,
+                         int32_t* type, int32_t* accept) {
+  elem_table T;
+  make_elements(dir, l, 1, &T);
+  double MD = T.cdf[T.n_el];
+  double* cn = (double*)malloc((size_t)(neu->np + 1) * sizeof(double));
+  cn[0] = 0;
+  for (int64_t q = 0; q < neu->np; ++q) {
+    const double* a = neu->V + 2 * (int64_t)neu->P[2 * q];
+    const double* b = neu->V + 2 * (int64_t)neu->P[2 * q + 1];
+    cn[q + 1] = cn[q] + hypot(b[0] - a[0], b[1] - a[1]);
+  }
+  double M = MD + cn[neu->np];
+  int64_t n_acc = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : n_acc)
+  for (int64_t k = 0; k < n; ++k) {
+    double ua, ub;
+    orc_uniform_pair(seed, 0, (uint32_t)k, batch, 7, &ua, &ub);
+    double target = ((double)k + ua) / (double)n * M;
+    double* xk = x + 2 * k;
+    double* nk = nrm + 2 * k;
+    double dD, xb[3];
+    int ok;
+    if (target < MD) {
+      int64_t lo = 0, hi = T.n_el - 1;
+      while (lo < hi) {
+        int64_t mid = (lo + hi + 1) / 2;
+        if (T.cdf[mid] <= target) lo = mid;
+        else hi = mid - 1;
+      }
+      double r = (target - T.cdf[lo]) / T.meas[lo];
+      r = r < 0 ? 0 : (r > 1 ? 1 : r);
+      candidate_point(dir, &T, lo, r, ub, l, xk);
+      orc_closest(dir, xk, 0, &dD, xb, NULL);
+      ok = fabs(dD - l) <= 1e-9 * l && orc_inside(full, xk) != 0;
+      for (int a = 0; a < 2; ++a) nk[a] = (xb[a] - xk[a]) / dD;
+      type[k] = 0;
+    } else {
+      double t2 = target - MD;
+      int64_t lo = 0, hi = neu->np - 1;
+      while (lo < hi) {
+        int64_t mid = (lo + hi + 1) / 2;
+        if (cn[mid] <= t2) lo = mid;
+        else hi = mid - 1;
+      }
+      const double* a = neu->V + 2 * (int64_t)neu->P[2 * lo];
+      const double* b = neu->V + 2 * (int64_t)neu->P[2 * lo + 1];
+      double e0 = b[0] - a[0], e1 = b[1] - a[1], len = hypot(e0, e1);
+      double r = (t2 - cn[lo]) / len;
+      r = r < 0 ? 0 : (r > 1 ? 1 : r);
+      xk[0] = a[0] + r * e0;
+      xk[1] = a[1] + r * e1;
+      nk[0] = e1 / len;
+      nk[1] = -e0 / len;
+      orc_closest(dir, xk, 0, &dD, xb, NULL);
+      ok = dD > l;
+      type[k] = 1;
+    }
+    double dF, xf[3];
+    orc_closest(full, xk, 0, &dF, xf, NULL);
+    R0[k] = dF;
+    xbar[2 * k] = xb[0];
+    xbar[2 * k + 1] = xb[1];
+    w[k] = M / (double)n;
+    accept[k] = ok;
+    n_acc += ok;
+  }
+  free(cn);
+  free_elements(&T);
+  return n_acc;
+}
+
 /* ======================================================================== */
 /* Clamped double-layer kernel and its bias correction (Section 3.4,         */
 /* Eqs. 8-9)                                                                 */

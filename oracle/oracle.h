@@ -35,7 +35,8 @@
  *   Each block yields two uniforms: ua from (w0, w1), ub from (w2, w3).
  *   Walk step k uses blocks 4k + s, s = 0..3 (see orc_walk for the map).
  *   Tags: 1 cache walk, 2 pointwise walk, 3 cache sampling, 4 source sampling,
- *   5 ray directions of the clamping correction, 6 region-of-interest cache.
+ *   5 ray directions of the clamping correction, 6 region-of-interest cache,
+ *   7 cache on a boundary with a Neumann part.
  */
 #ifndef BVC_ORACLE_H
 #define BVC_ORACLE_H
@@ -242,6 +243,15 @@ void orc_gather_sigma(int dim, double sigma, int64_t K, const double* ex, int64_
 void orc_wost_walks(const orc_scene* dir, const orc_scene* neu, const orc_field* g, const orc_walk_params* p,
                     int mode, int64_t n, const double* x, const double* nrm, const double* R0, const double* xbar,
                     double* U, double* D, int32_t* steps);
+
+/* Cache candidates for a boundary with a Neumann part (2D): the offset
+ * Dirichlet boundary (distance l to the Dirichlet part, inside `full`) and
+ * the Neumann part beyond distance l, one stratified draw (tag 7); type 0
+ * offset / 1 Neumann; R0 = distance to the whole boundary, xbar = closest
+ * Dirichlet point.  Returns the number accepted. */
+int64_t orc_sample_mixed(const orc_scene* full, const orc_scene* dir, const orc_scene* neu, int64_t n, double l,
+                         uint64_t seed, uint32_t batch, double* x, double* nrm, double* w, double* xbar, double* R0,
+                         int32_t* type, int32_t* accept);
 
 /* --- Clamped double-layer kernel and bias correction (Section 3.4) ------ */
 /* Distance beyond which |dG/dn| cannot exceed c (INFINITY for c <= 0). */
