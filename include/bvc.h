@@ -167,6 +167,28 @@ int bvc_sample_cache(bvc_scene scene, int64_t n, double l, int32_t sides, uint64
 int bvc_sample_roi(bvc_scene dom, bvc_scene roi, int64_t n, uint64_t seed, uint32_t batch, double* x,
                    double* nrm, double* w, double* xbar, double* R0, int32_t* accept, void* stream);
 
+/* Cache points for a 2D boundary with a Neumann part (Section 3.2,
+ * "Boundary Specification"): samples on the offset Dirichlet boundary (at
+ * distance l > eps from the Dirichlet part `dir`, inside the domain whose
+ * whole boundary is `full`) and on the Neumann part `neu` where it is farther
+ * than l from `dir`; together they bound the region where the cache is
+ * gathered.  One stratified draw (Philox block 0, id k, tag 7): candidate k
+ * sits at (k + U_k)/n of the concatenated measure of the offset candidates
+ * of `dir` (as bvc_sample_cache with sides 1) and the segments of `neu`.
+ * Outputs (FP64 device, [2][n] or [n]): x; nrm = towards the closest
+ * Dirichlet point on offset points, the segment's outward normal on Neumann
+ * points; w = total candidate measure / n; xbar = closest Dirichlet point;
+ * R0 = distance to `full` (the first ball of a cache walk); kind (int32 [n]:
+ * 0 rejected, 1 accepted offset point (distance l within 1e-9 relative and
+ * inside `full`), 2 accepted Neumann point (farther than l)).  The three
+ * scenes are CCW segment sets over one boundary; the first call for `dir` at
+ * this l and for `neu` uploads their sampling tables and synchronises.
+ * Errors: BVC_EUNSUPPORTED in 3D, BVC_EINVAL for an empty part, l <= 0 or a
+ * null output. */
+int bvc_sample_mixed(bvc_scene full, bvc_scene dir, bvc_scene neu, int64_t n, double l, uint64_t seed,
+                     uint32_t batch, double* x, double* nrm, double* w, double* xbar, double* R0, int32_t* kind,
+                     void* stream);
+
 /* Source samples (Eq. 4): m^dim jittered cells over the box [lo, hi] (host
  * arrays of dim doubles); s_j = |box|/m^dim * f(y_j) * 1[y_j inside and
  * d(y_j) > l].  y: [dim][m^dim] FP64 device, s: [m^dim] FP64 device. */
@@ -179,6 +201,14 @@ int bvc_sample_sources(bvc_scene scene, const bvc_field* f, int64_t m, const dou
  * walks, Section 3.2).  dist (optional) receives d(x). */
 int bvc_classify(bvc_scene scene, int64_t n, const double* x, double l, int32_t* cls,
                  double* dist, void* stream);
+
+/* Classifies 2D points x ([2][n] FP64 device) of a domain with a Neumann
+ * part (Section 3.2): cls = 0 outside `full` (nonzero winding number inside),
+ * 1 inside and farther than l from the Dirichlet part `dir` (gathered from
+ * the mixed cache), 2 inside within l of `dir` (walks on stars).  dist
+ * (optional) receives the distance to `dir`.  BVC_EUNSUPPORTED in 3D. */
+int bvc_classify_mixed(bvc_scene full, bvc_scene dir, int64_t n, const double* x, double l, int32_t* cls,
+                       double* dist, void* stream);
 
 /* Deterministic stream compaction: idx[0..count) = ascending k with
  * flags[k] == want.  scratch: caller-owned device int32 array of at least
@@ -322,10 +352,12 @@ int bvc_gather_grad(int32_t dim, const bvc_cache_view* cache, const bvc_source_v
  * boundary (two scenes over the same vertices).  Walk j of start point i has
  * id i*W + j (n*W < 2^32).  Each step: star radius R = max(eps, min(d_D,
  * d_S)), d_D the distance to the Dirichlet part and d_S to the closest
- * silhouette vertex of the Neumann part seen from the walk (both Neumann
- * neighbours strictly on one side of the line of sight, or one on it and the
- * other off it, within 1e-9 relative in FP64 and 1e-5 in FP32; ends of
- * Neumann runs included); a direction uniform on the circle (Philox block 4k
+ * silhouette vertex of the Neumann part seen from the walk (a corner vertex
+ * with both Neumann neighbours strictly on one side of the line of sight, or
+ * one on it and the other off it, within 1e-9 relative in FP64 and 1e-5 in
+ * FP32; ends of Neumann runs included; a vertex where the boundary continues
+ * straight, within 1e-12 relative, is no corner); a direction uniform on the
+ * circle (Philox block 4k
  * as walk on spheres), turned into the inward half circle on the Neumann
  * part; the walk moves to the nearest Neumann crossing within R, else to the
  * sphere; it stops when d_D < eps (or after max_steps, counted as capped)
@@ -338,8 +370,10 @@ int bvc_gather_grad(int32_t dim, const bvc_cache_view* cache, const bvc_source_v
  * mode 3: from points on the Neumann part with outward normals nrm, tag 2.
  * x, nrm, xbar: [2][n] FP64; R0 [n]; U, D (optional): [n*W] of dtype;
  * steps (optional) int32 [n*W].  workspace: caller-owned, at least
- * bvc_wost_workspace_bytes(neu) bytes (the Neumann run links, uploaded by
- * the call, which synchronises once).  counters: uint64[4] as the walks. */
+ * bvc_wost_workspace_bytes(neu) bytes (the Neumann run links, corner flags
+ * and per-node normal cones that let the silhouette query skip BVH nodes
+ * without corners facing the walk; built on the host and uploaded by the
+ * call, which synchronises once).  counters: uint64[4] as the walks. */
 size_t bvc_wost_workspace_bytes(bvc_scene neu);
 int bvc_wost_walks(bvc_scene dir, bvc_scene neu, const bvc_walk_params* params, int32_t mode, int64_t n,
                    const double* x, const double* nrm, const double* R0, const double* xbar, void* U, void* D,

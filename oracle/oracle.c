@@ -1582,6 +1582,7 @@ void orc_basis_means(const orc_field* basis, int dim, int64_t n_cache, int32_t W
 typedef struct {
   int32_t* prev;     /* per Neumann segment: start vertex of the Neumann segment ending at its start, or -1 */
   int32_t* has_next; /* 1 when a Neumann segment starts at its end vertex */
+  int32_t* straight; /* 1 when the segment and the one ending at its start are collinear */
 } neu_links;
 
 static neu_links make_links(const orc_scene* neu) {
@@ -1589,6 +1590,7 @@ static neu_links make_links(const orc_scene* neu) {
   int64_t np = neu->np, nv = neu->nv;
   L.prev = (int32_t*)malloc((size_t)np * sizeof(int32_t));
   L.has_next = (int32_t*)malloc((size_t)np * sizeof(int32_t));
+  L.straight = (int32_t*)malloc((size_t)np * sizeof(int32_t));
   int32_t* ends_at = (int32_t*)malloc((size_t)nv * sizeof(int32_t));
   int32_t* starts_at = (int32_t*)malloc((size_t)nv * sizeof(int32_t));
   for (int64_t v = 0; v < nv; ++v) ends_at[v] = starts_at[v] = -1;
@@ -1600,6 +1602,15 @@ static neu_links make_links(const orc_scene* neu) {
     int32_t r = ends_at[neu->P[2 * q]];
     L.prev[q] = r >= 0 ? neu->P[2 * r] : -1;
     L.has_next[q] = starts_at[neu->P[2 * q + 1]] >= 0;
+    L.straight[q] = 0;
+    if (r >= 0) {
+      /* no corner at the start vertex: the two segments continue one line */
+      const double* u = neu->V + 2 * (int64_t)L.prev[q];
+      const double* a = neu->V + 2 * (int64_t)neu->P[2 * q];
+      const double* b = neu->V + 2 * (int64_t)neu->P[2 * q + 1];
+      double e0 = a[0] - u[0], e1 = a[1] - u[1], f0 = b[0] - a[0], f1 = b[1] - a[1];
+      L.straight[q] = fabs(e0 * f1 - e1 * f0) <= 1e-12 * hypot(e0, e1) * hypot(f0, f1) && e0 * f0 + e1 * f1 > 0;
+    }
   }
   free(ends_at);
   free(starts_at);
@@ -1619,17 +1630,20 @@ static int line_side(const double* x, const double* v, const double* w) {
 }
 
 /* Distance from x to the closest silhouette vertex of the Neumann part: a
- * vertex whose two Neumann neighbours lie strictly on one side of the line
- * from x through it, or one on the line and the other off it (x looks along
- * one segment past the corner); a vertex on a straight run seen along that
- * run is none. */
+ * corner vertex whose two Neumann neighbours lie strictly on one side of the
+ * line from x through it, or one on the line and the other off it (x looks
+ * along one segment past the corner), and the ends of Neumann runs.  A vertex
+ * where the boundary continues straight is no corner and never a
+ * silhouette. */
 static double silhouette_distance(const orc_scene* neu, const neu_links* L, const double* x) {
   double best = INFINITY;
   for (int64_t q = 0; q < neu->np; ++q) {
     const double* a = neu->V + 2 * (int64_t)neu->P[2 * q];
     const double* b = neu->V + 2 * (int64_t)neu->P[2 * q + 1];
     int sil = 1;
-    if (L->prev[q] >= 0) {
+    if (L->straight[q]) {
+      sil = 0;
+    } else if (L->prev[q] >= 0) {
       const double* u = neu->V + 2 * (int64_t)L->prev[q];
       int s1 = line_side(x, a, u), s2 = line_side(x, a, b);
       sil = (s1 * s2 > 0) || ((s1 == 0) != (s2 == 0));
@@ -1747,6 +1761,7 @@ void orc_wost_walks(const orc_scene* dir, const orc_scene* neu, const orc_field*
   }
   free(L.prev);
   free(L.has_next);
+  free(L.straight);
 }
 
 /* Cache candidates for a boundary with a Neumann part (Section 3.2, "Boundary

@@ -235,7 +235,9 @@ void orc_gather_sigma(int dim, double sigma, int64_t K, const double* ex, int64_
  * R0 with the gradient estimate D = n . (2/R0) nu (W - g(xbar)) (Eq. 7), tag
  * 1; mode 1: from an interior point, tag 2; mode 3: from a point on the
  * Neumann boundary (nrm = outward normal), tag 2.  Star radius
- * max(eps, min(d_Dirichlet, d_silhouette)); direction uniform (block 4k),
+ * max(eps, min(d_Dirichlet, d_silhouette)) (silhouettes: corner vertices
+ * seen with both neighbours on one side, run ends; a vertex where the
+ * boundary continues straight is no corner); direction uniform (block 4k),
  * turned into the inward half circle on the Neumann boundary; the next point
  * is the nearest Neumann crossing within the radius, else the sphere point.
  * Stops when d_Dirichlet < eps (or max_steps) with U = g at the closest

@@ -127,6 +127,9 @@ _SIGS = {
     "bvc_wost_walks": [_vp, _vp, _P(bvc_walk_params), C.c_int32, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                        _vp, C.c_size_t, _vp, _vp],
     "bvc_sample_roi": [_vp, _vp, C.c_int64, C.c_uint64, C.c_uint32, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
+    "bvc_sample_mixed": [_vp, _vp, _vp, C.c_int64, C.c_double, C.c_uint64, C.c_uint32, _vp, _vp, _vp, _vp, _vp, _vp,
+                         _vp],
+    "bvc_classify_mixed": [_vp, _vp, C.c_int64, _vp, C.c_double, _vp, _vp, _vp],
     "bvc_clamp_correction": [_vp, _P(bvc_walk_params), _P(bvc_clamp_params), C.c_int64, _vp, _vp, _vp, _vp, _vp,
                              C.c_size_t, _vp, _vp],
 }
@@ -264,6 +267,16 @@ def bvc_cache_measure(scene, l, sides) -> float:
 def bvc_sample_roi(dom, roi, n, seed, batch, x, nrm, w, xbar, R0, accept, stream=None):
     _check(_L.bvc_sample_roi(dom, roi, n, seed, batch, ptr(x), ptr(nrm), ptr(w), ptr(xbar), ptr(R0), ptr(accept),
                              stream_ptr(stream)), "bvc_sample_roi")
+
+
+def bvc_sample_mixed(full, dir_scene, neu, n, l, seed, batch, x, nrm, w, xbar, R0, kind, stream=None):
+    _check(_L.bvc_sample_mixed(full, dir_scene, neu, n, l, seed, batch, ptr(x), ptr(nrm), ptr(w), ptr(xbar), ptr(R0),
+                               ptr(kind), stream_ptr(stream)), "bvc_sample_mixed")
+
+
+def bvc_classify_mixed(full, dir_scene, n, x, l, cls, dist=None, stream=None):
+    _check(_L.bvc_classify_mixed(full, dir_scene, n, ptr(x), l, ptr(cls), ptr(dist), stream_ptr(stream)),
+           "bvc_classify_mixed")
 
 
 def bvc_sample_cache(scene, n, l, sides, seed, batch, x, nrm, w, xbar, R0, accept, stream=None):

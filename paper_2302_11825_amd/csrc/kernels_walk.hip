@@ -238,6 +238,76 @@ __global__ __launch_bounds__(kBlock) void k_sample_roi(SceneDev Sd, SceneDev Sr,
   }
 }
 
+// Cache points for a 2D boundary with a Neumann part (Section 3.2, "Boundary
+// Specification"): the closed curve made of the offset Dirichlet boundary
+// (points at distance l from the Dirichlet part, inside the domain) and the
+// Neumann part farther than l from the Dirichlet part.  One stratified draw
+// over the Dirichlet offset candidates (segment offsets and vertex circles of
+// the Dirichlet scene's table at (l, 1 side)) followed by the Neumann
+// segments (their table at l = 0).  Offset points take the normal towards the
+// closest Dirichlet point, Neumann points the segment's outward normal.
+__global__ __launch_bounds__(kBlock) void k_sample_mixed(SceneDev Sf, SceneDev Sd, SceneDev Sn, int64_t n, double l,
+                                                          uint64_t seed, uint32_t batch, double MD, double M,
+                                                          double* x, double* nrm, double* w, double* xbar,
+                                                          double* R0, int* kind) {
+  extern __shared__ uint32_t lds[];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double ua, ub;
+  Uniform<double>::pair(seed, 0, (uint32_t)k, batch, 7, ua, ub);
+  const double target = ((double)k + ua) / (double)n * M;
+  double xc[2], nc[2], q[2];
+  bool ok;
+  int ty;  // 1 offset Dirichlet candidate, 2 Neumann candidate
+  int hint = -1;
+  if (target < MD) {
+    int lo = 0, hi = Sd.n_el - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (Sd.cdf[mid] <= target) lo = mid;
+      else hi = mid - 1;
+    }
+    const double r = fmin(fmax((target - Sd.cdf[lo]) / Sd.meas[lo], 0.0), 1.0);
+    candidate_point(Sd, lo, r, ub, l, xc);
+    const double d = sqrt(closest_point<double, 2>(Sd, xc, hint, q, lds + threadIdx.x, blockDim.x));
+    nc[0] = (q[0] - xc[0]) / d;
+    nc[1] = (q[1] - xc[1]) / d;
+    ok = fabs(d - l) <= 1e-9 * l && winding_number(Sf, xc) != 0;
+    ty = 1;
+  } else {
+    const double t2 = target - MD;
+    int lo = 0, hi = Sn.np - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (Sn.cdf[mid] <= t2) lo = mid;
+      else hi = mid - 1;
+    }
+    const double* a = Sn.V + 2 * (size_t)Sn.P[2 * lo];
+    const double* b = Sn.V + 2 * (size_t)Sn.P[2 * lo + 1];
+    const double e0 = b[0] - a[0], e1 = b[1] - a[1];
+    const double len = sqrt(e0 * e0 + e1 * e1);
+    const double r = fmin(fmax((t2 - Sn.cdf[lo]) / len, 0.0), 1.0);
+    xc[0] = a[0] + r * e0;
+    xc[1] = a[1] + r * e1;
+    nc[0] = e1 / len;  // outward normal of a CCW loop
+    nc[1] = -e0 / len;
+    const double d = sqrt(closest_point<double, 2>(Sd, xc, hint, q, lds + threadIdx.x, blockDim.x));
+    ok = d > l;
+    ty = 2;
+  }
+  double qf[2];
+  int hf = -1;
+  R0[k] = sqrt(closest_point<double, 2>(Sf, xc, hf, qf, lds + threadIdx.x, blockDim.x));
+  kind[k] = ok ? ty : 0;
+  w[k] = M / (double)n;
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    x[a * n + k] = xc[a];
+    nrm[a * n + k] = nc[a];
+    xbar[a * n + k] = q[a];
+  }
+}
+
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_sample_sources(SceneDev S, FieldDev f, int64_t m, int64_t M, double lo0,
                                                             double lo1, double lo2, double hi0, double hi1,
@@ -281,6 +351,23 @@ __global__ __launch_bounds__(kBlock) void k_classify(SceneDev S, int64_t n, cons
   int hint = -1;
   const double d = sqrt(closest_point<double, D>(S, xk, hint, q, lds + threadIdx.x, blockDim.x));
   const bool in = inside_point<D>(S, xk, hint);
+  cls[k] = !in ? 0 : (d > l ? 1 : 2);
+  if (dist) dist[k] = d;
+}
+
+// Evaluation points of a 2D domain with a Neumann part: inside the whole
+// boundary `Sf`, split by the distance to the Dirichlet part `Sd` (Section
+// 3.2: the gather applies farther than l, walks on stars within l).
+__global__ __launch_bounds__(kBlock) void k_classify_mixed(SceneDev Sf, SceneDev Sd, int64_t n, const double* x,
+                                                            double l, int* cls, double* dist) {
+  extern __shared__ uint32_t lds[];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const double xk[2] = {x[k], x[n + k]};
+  double q[2];
+  int hint = -1;
+  const double d = sqrt(closest_point<double, 2>(Sd, xk, hint, q, lds + threadIdx.x, blockDim.x));
+  const bool in = winding_number(Sf, xk) != 0;
   cls[k] = !in ? 0 : (d > l ? 1 : 2);
   if (dist) dist[k] = d;
 }
@@ -464,6 +551,34 @@ int bvc_sample_roi(bvc_scene dom, bvc_scene roi, int64_t n, uint64_t seed, uint3
   return check_hip(hipGetLastError(), "sample_roi launch");
 }
 
+int bvc_sample_mixed(bvc_scene full, bvc_scene dir, bvc_scene neu, int64_t n, double l, uint64_t seed,
+                     uint32_t batch, double* x, double* nrm, double* w, double* xbar, double* R0, int32_t* kind,
+                     void* stream) {
+  int rc = check_scene(full);
+  if (!rc) rc = check_scene(dir);
+  if (!rc) rc = check_scene(neu);
+  if (rc) return rc;
+  if (full->h.dim != 2 || dir->h.dim != 2 || neu->h.dim != 2)
+    return fail(BVC_EUNSUPPORTED, "the mixed-boundary cache is 2D only");
+  if (dir->h.np == 0 || neu->h.np == 0) return fail(BVC_EINVAL, "the Dirichlet and the Neumann parts must be non-empty");
+  if (n < 0 || n >= (int64_t)1 << 31) return fail(BVC_EINVAL, "n out of range");
+  if (!(l > 0) || !std::isfinite(l)) return fail(BVC_EINVAL, "offset l must be positive");
+  if (n == 0) return BVC_OK;
+  if (!x || !nrm || !w || !xbar || !R0 || !kind) return fail(BVC_EINVAL, "null output");
+  hipStream_t st = (hipStream_t)stream;
+  rc = ensure_cdf(dir->h, l, 1, st);
+  if (!rc) rc = ensure_cdf(neu->h, 0.0, 1, st);
+  if (rc) return rc;
+  const double MD = candidate_measure(dir->h, l, 1);
+  const double M = MD + candidate_measure(neu->h, 0.0, 1);
+  const SceneDev Sf = full->h.view(), Sd = dir->h.view(), Sn = neu->h.view();
+  const int blocks = (int)((n + kBlock - 1) / kBlock);
+  const size_t lds = std::max(stack_bytes(full->h, kBlock), stack_bytes(dir->h, kBlock));
+  hipLaunchKernelGGL(k_sample_mixed, dim3(blocks), dim3(kBlock), lds, st, Sf, Sd, Sn, n, l, seed, batch, MD, M, x,
+                     nrm, w, xbar, R0, kind);
+  return check_hip(hipGetLastError(), "sample_mixed launch");
+}
+
 int bvc_sample_sources(bvc_scene s, const bvc_field* f, int64_t m, const double* lo, const double* hi, double l,
                        uint64_t seed, uint32_t batch, double* y, double* sw, void* stream) {
   int rc = check_scene(s);
@@ -512,6 +627,24 @@ int bvc_classify(bvc_scene s, int64_t n, const double* x, double l, int32_t* cls
   else
     hipLaunchKernelGGL(k_classify<3>, dim3(blocks), dim3(kBlock), lds, st, S, n, x, l, cls, dist);
   return check_hip(hipGetLastError(), "classify launch");
+}
+
+int bvc_classify_mixed(bvc_scene full, bvc_scene dir, int64_t n, const double* x, double l, int32_t* cls,
+                       double* dist, void* stream) {
+  int rc = check_scene(full);
+  if (!rc) rc = check_scene(dir);
+  if (rc) return rc;
+  if (full->h.dim != 2 || dir->h.dim != 2) return fail(BVC_EUNSUPPORTED, "mixed classification is 2D only");
+  if (n < 0 || n >= (int64_t)1 << 31) return fail(BVC_EINVAL, "n out of range");
+  if (!(l >= 0) || !std::isfinite(l)) return fail(BVC_EINVAL, "l must be finite and >= 0");
+  if (n == 0) return BVC_OK;
+  if (!x || !cls) return fail(BVC_EINVAL, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  const int blocks = (int)((n + kBlock - 1) / kBlock);
+  const size_t lds = stack_bytes(dir->h, kBlock);
+  hipLaunchKernelGGL(k_classify_mixed, dim3(blocks), dim3(kBlock), lds, st, full->h.view(), dir->h.view(), n, x, l,
+                     cls, dist);
+  return check_hip(hipGetLastError(), "classify_mixed launch");
 }
 
 int64_t bvc_compact_scratch_ints(int64_t n) { return (n + kCompactTile - 1) / kCompactTile + 4; }

@@ -24,12 +24,15 @@ namespace bvc {
 namespace {
 
 constexpr int kWostBlock = 128;
+constexpr int kHasNext = 1;   // a Neumann segment starts at this segment's end
+constexpr int kStraight = 2;  // this segment continues the previous one on a line: its start is no corner
 
 struct WostArgs {
   SceneDev Sd;  // Dirichlet part
   SceneDev Sn;  // Neumann part
   const int* prev;      // per Neumann segment (original id): start vertex of the segment ending at its start, or -1
-  const int* has_next;  // per Neumann segment: 1 when a Neumann segment starts at its end
+  const int* flags;     // per Neumann segment: kHasNext | kStraight
+  const float4* cones;  // per BVH node and child: normal cone of the child's corner vertices (see wost_tables)
   FieldDev g;
   double eps;
   int max_steps;
@@ -61,16 +64,40 @@ __device__ __forceinline__ int line_side(const T* x, T vx, T vy, T wx, T wy, T t
   return c > T(0) ? 1 : -1;
 }
 
-// Squared distance from p to the closest silhouette vertex of the Neumann
-// part: a vertex whose two Neumann neighbours lie strictly on one side of the
-// line from p through it, or one on that line and the other off it; the end
-// vertex of a Neumann run counts as well.
+// A child of a BVH node can hold no silhouette vertex for the viewpoint p
+// when every direction from p into its box makes an angle with every normal
+// of its cone that stays away from a right angle: then all its corner
+// vertices see both of their segments from the same side.  cone = (axis,
+// sin, cos) of the half-angle (widened on the host); the view cone is the
+// box's bounding circle seen from p.
 template <typename T>
-__device__ T silhouette_d2(const WostArgs& a, const T* p, uint32_t* stk, int stride) {
+__device__ __forceinline__ bool cone_culls(const float4 cone, const T* lo, const T* hi, const T* p) {
+  const float mx = 0.5f * (float)(lo[0] + hi[0]) - (float)p[0], my = 0.5f * (float)(lo[1] + hi[1]) - (float)p[1];
+  const float ex = (float)(hi[0] - lo[0]), ey = (float)(hi[1] - lo[1]);
+  const float r2 = 0.25f * (ex * ex + ey * ey);
+  const float d2 = mx * mx + my * my;
+  if (!(d2 > 1.01f * r2)) return false;  // p inside (or near) the bounding circle
+  const float d = sqrtf(d2);
+  const float sphi = sqrtf(r2) / d * 1.0001f, cphi = sqrtf(fmaxf(0.0f, 1.0f - sphi * sphi));
+  const float cb = cone.w * cphi - cone.z * sphi;  // cos(theta + phi)
+  if (!(cb > 0.0f)) return false;
+  const float sb = cone.z * cphi + cone.w * sphi;  // sin(theta + phi)
+  return fabsf(cone.x * mx + cone.y * my) > sb * d;
+}
+
+// Squared distance from p to the closest silhouette vertex of the Neumann
+// part within sqrt(bound): a corner vertex whose two Neumann neighbours lie
+// strictly on one side of the line from p through it, or one on that line and
+// the other off it, and the ends of Neumann runs; a vertex where the boundary
+// continues straight is none.  Returns bound when there is none closer (the
+// step radius never exceeds the Dirichlet distance, so the search starts
+// there).
+template <typename T>
+__device__ T silhouette_d2(const WostArgs& a, const T* p, T bound, uint32_t* stk, int stride) {
   const SceneDev& S = a.Sn;
   const T* pr = SceneArrays<T>::prim(S);
   const T tol = sizeof(T) == 4 ? T(1e-5) : T(1e-9);
-  T best = T(INFINITY);
+  T best = bound;
   int sp = 0, node = 0;
   while (true) {
     T lo0[2], hi0[2], lo1[2], hi1[2];
@@ -79,24 +106,31 @@ __device__ T silhouette_d2(const WostArgs& a, const T* p, uint32_t* stk, int str
     const T d0 = box_d2<T, 2>(lo0, hi0, p), d1 = box_d2<T, 2>(lo1, hi1, p);
     const int cs[2] = {ch.x, ch.y};
     const T ds[2] = {d0, d1};
+    const float4 cones[2] = {a.cones[2 * node], a.cones[2 * node + 1]};
     int next = -1;
     for (int s = 0; s < 2; ++s) {
       if (!(ds[s] <= best)) continue;
+      const float4 cn = cones[s];
+      if (cn.z < -0.5f) continue;  // no corner and no run end below this child
+      if (cn.w > -1.5f && cone_culls<T>(cn, s == 0 ? lo0 : lo1, s == 0 ? hi0 : hi1, p)) continue;
       const int c = cs[s];
       if (c < 0) {
         const int s0 = leaf_start(c), m = leaf_count(c);
         for (int i = s0; i < s0 + m; ++i) {
           const T ax = pr[4 * i], ay = pr[4 * i + 1], bx = pr[4 * i + 2], by = pr[4 * i + 3];
           const int q = S.prim_id[i];
+          const int fl = a.flags[q];
           bool sil = true;
           const int pv = a.prev[q];
-          if (pv >= 0) {
+          if (fl & kStraight) {
+            sil = false;
+          } else if (pv >= 0) {
             const T ux = (T)S.V[2 * (size_t)pv], uy = (T)S.V[2 * (size_t)pv + 1];
             const int s1 = line_side<T>(p, ax, ay, ux, uy, tol), s2 = line_side<T>(p, ax, ay, bx, by, tol);
             sil = (s1 * s2 > 0) || ((s1 == 0) != (s2 == 0));
           }
           if (sil) best = fmin(best, (ax - p[0]) * (ax - p[0]) + (ay - p[1]) * (ay - p[1]));
-          if (!a.has_next[q]) best = fmin(best, (bx - p[0]) * (bx - p[0]) + (by - p[1]) * (by - p[1]));
+          if (!(fl & kHasNext)) best = fmin(best, (bx - p[0]) * (bx - p[0]) + (by - p[1]) * (by - p[1]));
         }
       } else if (next < 0) {
         next = c;
@@ -220,14 +254,15 @@ __global__ __launch_bounds__(kWostBlock) void k_wost(WostArgs a) {
     for (;; ++k) {
       T q[2];
       int hint = -1;
-      const T dD = fsqrt(closest_point<T, 2>(a.Sd, pos, hint, q, stk, stride));
+      const T d2D = closest_point<T, 2>(a.Sd, pos, hint, q, stk, stride);
+      const T dD = fsqrt(d2D);
       if (dD < eps || k >= a.max_steps) {
         capped = !(dD < eps);
         const double qd[2] = {(double)q[0], (double)q[1]};
         W = field_value(a.g, 2, qd);
         break;
       }
-      const T R = fmax(fmin(dD, fsqrt(silhouette_d2<T>(a, pos, stk, stride))), eps);
+      const T R = fmax(fmin(dD, fsqrt(silhouette_d2<T>(a, pos, d2D, stk, stride))), eps);
       T w[2];
       walk_direction<T, 2>(a.seed, (uint32_t)k, (uint32_t)id, a.batch, tag, w);
       if (onb && w[0] * nin[0] + w[1] * nin[1] < T(0)) {
@@ -278,21 +313,119 @@ __global__ __launch_bounds__(kWostBlock) void k_wost(WostArgs a) {
   }
 }
 
-// Neumann run links of a segment set: for each segment (original id) the
-// start vertex of the segment ending at its start (-1 if none), and whether
-// a segment starts at its end.
-void neumann_links(const SceneHost& h, std::vector<int>& prev, std::vector<int>& has_next) {
+// Host tables of a Neumann segment set.  prev: per segment (original id) the
+// start vertex of the segment ending at its start, or -1.  flags: kHasNext
+// when a segment starts at its end; kStraight when the segment and the one
+// ending at its start continue one line (relative 1e-12), so that their common
+// vertex is no corner.  cones: per BVH node and child, the unit normals of
+// both segments at every corner vertex below the child (a start vertex that
+// is neither straight nor a run start) as (axis, sin, cos) of the half-angle
+// widened by 1e-3 rad; sin = -1 when the child holds neither a corner nor a
+// run end (never a silhouette), cos = -2 when it holds a run end or its
+// normals span a half circle or more (never culled).  A child's segments are
+// taken as the leaf-order range its leaves span (a superset, so the cone can
+// only be wider than needed).
+void wost_tables(const SceneHost& h, std::vector<int>& prev, std::vector<int>& flags, std::vector<float>& cones) {
   std::vector<int> ends_at((size_t)h.nv, -1), starts_at((size_t)h.nv, -1);
   for (int64_t q = 0; q < h.np; ++q) {
     starts_at[(size_t)h.P[2 * q]] = (int)q;
     ends_at[(size_t)h.P[2 * q + 1]] = (int)q;
   }
   prev.assign((size_t)h.np, -1);
-  has_next.assign((size_t)h.np, 0);
+  flags.assign((size_t)h.np, 0);
+  const double* V = h.V.data();
+  auto normal = [&](int from, int to, double* n) {
+    const double e0 = V[2 * (size_t)to] - V[2 * (size_t)from], e1 = V[2 * (size_t)to + 1] - V[2 * (size_t)from + 1];
+    const double len = std::hypot(e0, e1);
+    n[0] = e1 / len;
+    n[1] = -e0 / len;
+  };
   for (int64_t q = 0; q < h.np; ++q) {
     const int r = ends_at[(size_t)h.P[2 * q]];
     prev[(size_t)q] = r >= 0 ? h.P[2 * (size_t)r] : -1;
-    has_next[(size_t)q] = starts_at[(size_t)h.P[2 * q + 1]] >= 0 ? 1 : 0;
+    int f = starts_at[(size_t)h.P[2 * q + 1]] >= 0 ? kHasNext : 0;
+    if (r >= 0) {
+      const double* u = V + 2 * (size_t)prev[(size_t)q];
+      const double* a = V + 2 * (size_t)h.P[2 * q];
+      const double* b = V + 2 * (size_t)h.P[2 * q + 1];
+      const double e0 = a[0] - u[0], e1 = a[1] - u[1], f0 = b[0] - a[0], f1 = b[1] - a[1];
+      if (std::fabs(e0 * f1 - e1 * f0) <= 1e-12 * std::hypot(e0, e1) * std::hypot(f0, f1) && e0 * f0 + e1 * f1 > 0)
+        f |= kStraight;
+    }
+    flags[(size_t)q] = f;
+  }
+  const int nn = (int)h.child.size();
+  cones.assign((size_t)nn * 8, 0.0f);
+  // leaf-order range below each child, bottom-up (children have larger
+  // breadth-first numbers than their parent)
+  std::vector<int> rlo(nn, 0), rhi(nn, 0);
+  auto child_range = [&](int c, int& lo, int& hi) {
+    if (c < 0) {
+      lo = leaf_start(c);
+      hi = lo + leaf_count(c);
+    } else {
+      lo = rlo[c];
+      hi = rhi[c];
+    }
+  };
+  for (int i = nn - 1; i >= 0; --i) {
+    int l0, h0, l1, h1;
+    child_range(h.child[i].x, l0, h0);
+    child_range(h.child[i].y, l1, h1);
+    rlo[i] = std::min(l0, l1);
+    rhi[i] = std::max(h0, h1);
+  }
+  std::vector<double> ns;
+  for (int i = 0; i < nn; ++i) {
+    for (int s = 0; s < 2; ++s) {
+      int lo, hi;
+      child_range(s == 0 ? h.child[i].x : h.child[i].y, lo, hi);
+      float* out = cones.data() + (size_t)i * 8 + 4 * s;
+      bool always = false;
+      ns.clear();
+      for (int k = lo; k < hi && !always; ++k) {
+        const int q = h.prim_id[(size_t)k];
+        if (!(flags[(size_t)q] & kHasNext) || prev[(size_t)q] < 0) {
+          always = true;
+          break;
+        }
+        if (flags[(size_t)q] & kStraight) continue;
+        double n1[2], n2[2];
+        normal(prev[(size_t)q], h.P[2 * (size_t)q], n1);
+        normal(h.P[2 * (size_t)q], h.P[2 * (size_t)q + 1], n2);
+        ns.insert(ns.end(), {n1[0], n1[1], n2[0], n2[1]});
+      }
+      if (!always && ns.empty()) {
+        out[0] = out[1] = 0.0f;
+        out[2] = -1.0f;
+        out[3] = 1.0f;
+        continue;
+      }
+      double ax = 0, ay = 0;
+      for (size_t k = 0; k < ns.size(); k += 2) {
+        ax += ns[k];
+        ay += ns[k + 1];
+      }
+      const double al = std::hypot(ax, ay);
+      double theta = 4.0;
+      if (!always && al > 1e-6 * (double)(ns.size() / 2)) {
+        ax /= al;
+        ay /= al;
+        double cmin = 1.0;
+        for (size_t k = 0; k < ns.size(); k += 2) cmin = std::min(cmin, ax * ns[k] + ay * ns[k + 1]);
+        theta = std::acos(std::max(-1.0, std::min(1.0, cmin))) + 1e-3;
+      }
+      if (theta >= 0.5 * kPi) {
+        out[0] = out[1] = 0.0f;
+        out[2] = 1.0f;
+        out[3] = -2.0f;
+      } else {
+        out[0] = (float)ax;
+        out[1] = (float)ay;
+        out[2] = (float)std::sin(theta);
+        out[3] = (float)std::cos(theta);
+      }
+    }
   }
 }
 
@@ -305,7 +438,8 @@ extern "C" {
 
 size_t bvc_wost_workspace_bytes(bvc_scene neu) {
   if (check_scene(neu)) return 0;
-  return (size_t)(2 * neu->h.np) * sizeof(int) + 256;
+  const size_t links = ((size_t)(2 * neu->h.np) * sizeof(int) + 255) / 256 * 256;
+  return links + neu->h.child.size() * 8 * sizeof(float) + 256;
 }
 
 int bvc_wost_walks(bvc_scene dir, bvc_scene neu, const bvc_walk_params* p, int32_t mode, int64_t n, const double* x,
@@ -333,21 +467,27 @@ int bvc_wost_walks(bvc_scene dir, bvc_scene neu, const bvc_walk_params* p, int32
   if (mode != 1 && !nrm) return fail(BVC_EINVAL, "modes 0 and 3 need normals");
   if (mode == 0 && (!R0 || !xbar)) return fail(BVC_EINVAL, "mode 0 needs R0 and xbar");
   if (!workspace || workspace_bytes < bvc_wost_workspace_bytes(neu)) return fail(BVC_EINVAL, "workspace too small");
-  std::vector<int> prev, has_next;
-  neumann_links(neu->h, prev, has_next);
+  std::vector<int> prev, flags;
+  std::vector<float> cones;
+  wost_tables(neu->h, prev, flags, cones);
   int* links = (int*)workspace;
   const size_t np = (size_t)neu->h.np;
-  rc = check_hip(hipMemcpyAsync(links, prev.data(), np * sizeof(int), hipMemcpyHostToDevice, st), "links upload");
+  float4* cone_dev = (float4*)((char*)workspace + ((2 * np * sizeof(int) + 255) / 256 * 256));
+  rc = check_hip(hipMemcpyAsync(links, prev.data(), np * sizeof(int), hipMemcpyHostToDevice, st), "tables upload");
   if (!rc)
-    rc = check_hip(hipMemcpyAsync(links + np, has_next.data(), np * sizeof(int), hipMemcpyHostToDevice, st),
-                   "links upload");
-  if (!rc) rc = check_hip(hipStreamSynchronize(st), "links upload sync");  // the host vectors end here
+    rc = check_hip(hipMemcpyAsync(links + np, flags.data(), np * sizeof(int), hipMemcpyHostToDevice, st),
+                   "tables upload");
+  if (!rc)
+    rc = check_hip(hipMemcpyAsync(cone_dev, cones.data(), cones.size() * sizeof(float), hipMemcpyHostToDevice, st),
+                   "tables upload");
+  if (!rc) rc = check_hip(hipStreamSynchronize(st), "tables upload sync");  // the host vectors end here
   if (rc) return rc;
   WostArgs a{};
   a.Sd = dir->h.view();
   a.Sn = neu->h.view();
   a.prev = links;
-  a.has_next = links + np;
+  a.flags = links + np;
+  a.cones = cone_dev;
   a.g = to_dev(p->g);
   a.eps = p->eps;
   a.max_steps = p->max_steps;

@@ -13,6 +13,9 @@
     python bench.py --workload c3screen  the 3D step on the screened equation (sigma = 4)
     python bench.py --workload c2roi     the 2D Poisson problem cached on the boundary of a
                                      disk inside the star (region of interest, Section 3.2)
+    python bench.py --workload c2mixed   Laplace in a channel with Dirichlet ends and Neumann
+                                     walls (Section 3.2 with walk on stars), against
+                                     pointwise walk on stars at equal error
 
 Each prints one JSON line.  Inputs are the seeded synthetic workloads.
 """
@@ -58,7 +61,7 @@ def _log(msg):
 
 def run(args):
     {"c3": c3, "c4a": c4a, "c4b": c4b, "c2clamp": c2clamp, "c3clamp": c3clamp,
-     "c3screen": c3screen, "c2roi": c2roi}[args.workload](args)
+     "c3screen": c3screen, "c2roi": c2roi, "c2mixed": c2mixed}[args.workload](args)
 
 
 def _c3_setup(args, prob=None):
@@ -345,4 +348,66 @@ def c2roi(args):
            "points_per_s": prep.n_int / (ms / 1e3), "rmse_region_cache": rmse(u_roi),
            "rmse_full_cache_same_points": rmse(u_full), "rms_truth": float(np.sqrt(np.mean(truth**2))),
            "walk_steps": int(sol.counters[1])}
+    print(json.dumps(out))
+
+
+def c2mixed(args):
+    """Boundary value caching with a Neumann part: the channel [0, 6] x [0, pi]
+    (4096 segments, Dirichlet ends, reflecting walls), u = x + 0.5 e^(x-6) cos y.
+    Time per step and per stage, the error of the gathered and the band
+    points, and pointwise walk on stars at equal error: the per-walk variance
+    at 8,192 sampled interior points gives the walks per point that reach the
+    cached estimate's RMSE, and the measured walk rate converts that into
+    points per second."""
+    prob = wl.problem_c2_mixed(grid=args.grid)
+    t0 = time.time()
+    prep = pl.MixedPrepared(prob, dtype="f32")
+    torch.cuda.synchronize()
+    _log(f"c2mixed setup {time.time() - t0:.1f}s: gathered {prep.n_int}, band {prep.n_band}")
+    for _ in range(max(1, args.warmup)):
+        pl.solve_mixed(prep, with_grad=False)
+    torch.cuda.synchronize()
+    watch = pl.Stopwatch()
+    e0, e1 = _ev(), _ev()
+    e0.record()
+    for _ in range(args.steps):
+        sol = pl.solve_mixed(prep, with_grad=False, watch=watch)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    stages = {k: sum(v) / len(v) for k, v in watch.totals_ms().items()}
+    xi = prob.eval_x[prep.idx_int[: prep.n_int].cpu().numpy()]
+    xb = prob.eval_x[prep.idx_band[: prep.n_band].cpu().numpy()]
+    ti, tb = wl.field_value(prob.truth, xi), wl.field_value(prob.truth, xb)
+    ui = sol.u_int[: prep.n_int].double().cpu().numpy()
+    ub = sol.u_band[: prep.n_band].double().cpu().numpy()
+    rm = lambda u, t: float(np.sqrt(np.mean((u - t) ** 2)))
+    wall = np.minimum(xi[:, 1], np.pi - xi[:, 1])
+    off_wall = wall > 0.05
+    err_int = rm(ui, ti)
+    # pointwise walk on stars at sampled interior points
+    rng = np.random.default_rng(3)
+    pick = np.sort(rng.choice(prep.n_int, size=min(8192, prep.n_int), replace=False))
+    W = 64
+    xp = torch.from_numpy(np.ascontiguousarray(xi[pick].T)).cuda()
+    wp = pl.walk_params(prob.eps, W, prob.seed_walks + 7, prep.g, None, "f32")
+    pl.wost(prep, wp, 1, pick.size, xp)
+    torch.cuda.synchronize()
+    t_pw = _time(lambda: pl.wost(prep, wp, 1, pick.size, xp), reps=3)
+    U, _, cnt = pl.wost(prep, wp, 1, pick.size, xp)
+    Uw = U.double().cpu().numpy().reshape(pick.size, W)
+    var = float(np.mean(Uw.var(axis=1, ddof=1)))
+    bias2 = max(float(np.mean((Uw.mean(1) - ti[pick]) ** 2)) - var / W, 0.0)
+    w_eq = var / max(err_int**2 - bias2, 1e-30)
+    walks_per_s = pick.size * W / (t_pw / 1e3)
+    out = {"workload": "c2mixed_channel4096_laplace", "grid": args.grid, "points_gathered": prep.n_int,
+           "points_band": prep.n_band, "cache_points": sol.cache.n, "cache_offset_points": sol.extra["n_offset"],
+           "cache_candidates": prep.n_cand, "walks_per_cache_point": prob.n_walks, "ms_per_step": ms,
+           "stage_ms": stages, "points_per_s": (prep.n_int + prep.n_band) / (ms / 1e3),
+           "rmse_gathered": err_int, "rmse_gathered_off_walls": rm(ui[off_wall], ti[off_wall]),
+           "rmse_band": rm(ub, tb), "rms_truth": float(np.sqrt(np.mean(ti**2))),
+           "cache_walk_steps": int(sol.counters[1]),
+           "pointwise": {"points": int(pick.size), "walks": W, "ms": t_pw, "walks_per_s": walks_per_s,
+                         "mean_steps": float(cnt[1].item()) / (pick.size * W), "per_walk_variance": var,
+                         "walks_for_equal_rmse": w_eq, "points_per_s_at_equal_rmse": walks_per_s / w_eq}}
     print(json.dumps(out))

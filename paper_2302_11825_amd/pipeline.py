@@ -359,6 +359,144 @@ def solve_roi(prep: RoiPrepared, batch=0, with_grad=True, watch=None) -> Solutio
                     extra=dict(U=U, D=D, a=a, b=b, cview=cview, sview=sview, rec=rec))
 
 
+class MixedPrepared:
+    """Boundary value caching with a Neumann part (Section 3.2, "Boundary
+    Specification"; 2D, Neumann data h = 0, no source): cache points on the
+    offset Dirichlet boundary (walks on stars from a first ball, u and
+    du/dn by Eq. 7) and on the Neumann part beyond distance l (walks on stars
+    from the boundary, u; du/dn = h = 0); evaluation points farther than l
+    from the Dirichlet part are gathered from the cache, the others take
+    pointwise walks on stars.  `problem.extra` holds the Dirichlet and the
+    Neumann segment sets ("dirichlet", "neumann") of `problem.scene`."""
+
+    def __init__(self, problem, dtype=None, n_cand=None, device="cuda", eval_x=None, n_walks_band=None):
+        self.p = problem
+        self.dtype = dtype or problem.precision
+        self.full = Scene(problem.scene, device)
+        self.dir = Scene(problem.extra["dirichlet"], device)
+        self.neu = Scene(problem.extra["neumann"], device)
+        self.g = DeviceField(problem.g, device)
+        self.n_cand = int(n_cand or problem.n_cache)
+        self.W_band = int(n_walks_band or problem.n_walks)
+        ex = problem.eval_x if eval_x is None else eval_x
+        self.eval64 = torch.from_numpy(np.ascontiguousarray(ex.T)).to(device)
+        n = self.eval64.shape[1]
+        self.cls = torch.empty(max(n, 1), dtype=torch.int32, device=device)
+        self.dist = torch.empty(max(n, 1), dtype=torch.float64, device=device)
+        B.bvc_classify_mixed(self.full.h, self.dir.h, n, self.eval64, problem.offset, self.cls, self.dist)
+        self.idx_int, self.n_int = self.full.compact(self.cls[:n] if n else self.cls, 1)
+        self.idx_band, self.n_band = self.full.compact(self.cls[:n] if n else self.cls, 2)
+        T = DT[self.dtype]
+        self.x_int = take(self.eval64, self.idx_int, self.n_int, 2, n, T)
+        self.x_band = take(self.eval64, self.idx_band, self.n_band, 2, n)
+        self.ones_band = torch.ones(max(self.n_band, 1), dtype=torch.float64, device=device)
+        self.ws = torch.empty(max(B.bvc_wost_workspace_bytes(self.neu.h), 256), dtype=torch.uint8, device=device)
+
+
+def sample_mixed(prep: MixedPrepared, seed, batch=0):
+    """Mixed cache samples, compacted with the offset points first: returns
+    (cache, n_offset)."""
+    dev, n_cand = prep.full.device, prep.n_cand
+    f64 = torch.float64
+    x = torch.empty(2, n_cand, dtype=f64, device=dev)
+    nrm = torch.empty_like(x)
+    xbar = torch.empty_like(x)
+    w = torch.empty(n_cand, dtype=f64, device=dev)
+    R0 = torch.empty_like(w)
+    kind = torch.empty(n_cand, dtype=torch.int32, device=dev)
+    B.bvc_sample_mixed(prep.full.h, prep.dir.h, prep.neu.h, n_cand, prep.p.offset, seed, batch, x, nrm, w, xbar, R0,
+                       kind)
+    idx = torch.empty(n_cand + 1, dtype=torch.int32, device=dev)
+    scratch = prep.full.scratch_int(n_cand)
+    n0 = B.bvc_compact(n_cand, kind, 1, idx, scratch)
+    n1 = B.bvc_compact(n_cand, kind, 2, idx[n0:], scratch)
+    n = n0 + n1
+    c = Cache(n, take(x, idx, n, 2, n_cand), take(nrm, idx, n, 2, n_cand), take(w, idx, n, 1, n_cand),
+              take(xbar, idx, n, 2, n_cand), take(R0, idx, n, 1, n_cand), n_cand)
+    return c, n0
+
+
+def _part(t, lo, hi):
+    """Columns [lo, hi) of a [rows][n] tensor as a contiguous [rows][hi - lo]."""
+    if t.dim() == 1:
+        return t[lo:hi] if hi > lo else t[:1]
+    return t[:, lo:hi].contiguous() if hi > lo else t[:, :1].contiguous()
+
+
+def wost(prep: MixedPrepared, params: B.bvc_walk_params, mode, n, x, nrm=None, R0=None, xbar=None, dtype="f32",
+         stream=None):
+    W = params.n_walks
+    T = DT[dtype]
+    dev = prep.full.device
+    U = torch.empty(max(n * W, 1), dtype=T, device=dev)
+    D = torch.empty_like(U)
+    cnt = torch.zeros(4, dtype=torch.int64, device=dev)
+    B.bvc_wost_walks(prep.dir.h, prep.neu.h, params, mode, n, x, nrm, R0, xbar, U, D, None, prep.ws, cnt, stream)
+    return U, D, cnt
+
+
+NEUMANN_BATCH_BIT = 0x80000000  # batch word of the walks from Neumann cache points
+
+
+def solve_mixed(prep: MixedPrepared, batch=0, with_grad=True, watch=None) -> Solution:
+    """Algorithm 1 with a Neumann part: samples, walks on stars from both
+    parts of the cache, per-point means, the gather at the points farther
+    than l from the Dirichlet part, pointwise walks on stars within l."""
+    p = prep.p
+    dt = prep.dtype
+    T = DT[dt]
+    dev = prep.full.device
+    watch = watch or _NoWatch()
+    W = p.n_walks
+    with watch.stage("sample_cache"):
+        cache, n0 = sample_mixed(prep, p.seed_cache, batch)
+    n, n1 = cache.n, cache.n - n0
+    wp0 = walk_params(p.eps, W, p.seed_walks, prep.g, None, dt, batch)
+    wp1 = walk_params(p.eps, W, p.seed_walks, prep.g, None, dt, batch | NEUMANN_BATCH_BIT)
+    with watch.stage("cache_walks"):
+        U0, D0, c0 = wost(prep, wp0, 0, n0, _part(cache.x, 0, n0), _part(cache.nrm, 0, n0), _part(cache.R0, 0, n0),
+                          _part(cache.xbar, 0, n0), dt)
+        U1, D1, c1 = wost(prep, wp1, 3, n1, _part(cache.x, n0, n), _part(cache.nrm, n0, n), None, None, dt)
+    uhat = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
+    dudn = torch.empty_like(uhat)
+    a = torch.empty(max(n, 1), dtype=T, device=dev)
+    b = torch.empty_like(a)
+    with watch.stage("reduce_walks"):
+        B.bvc_reduce_walks(n0, W, B.dtype_code(T), U0, D0, cache.w, uhat, dudn, CODE[dt], a, b)
+        if n1:
+            B.bvc_reduce_walks(n1, W, B.dtype_code(T), U1, D1, cache.w[n0:], uhat[n0:], dudn[n0:], CODE[dt], a[n0:],
+                               b[n0:])
+    if T != torch.float64:
+        cx = take(cache.x, None, n, 2, n, T)
+        cn = take(cache.nrm, None, n, 2, n, T)
+    else:
+        cx, cn = cache.x, cache.nrm
+    cview = dict(n=n, dtype=CODE[dt], x=cx, nrm=cn, a=a, b=b)
+    n_int = prep.n_int
+    u_int = torch.empty(max(n_int, 1), dtype=T, device=dev)
+    g_int = torch.empty(2, max(n_int, 1), dtype=T, device=dev) if with_grad else None
+    with watch.stage("gather"):
+        if with_grad:
+            B.bvc_gather_grad(2, cview, None, n_int, prep.x_int, u_int, g_int)
+        else:
+            B.bvc_gather_u(2, cview, None, n_int, prep.x_int, u_int)
+    nb = prep.n_band
+    u_band = torch.empty(max(nb, 1), dtype=T, device=dev)
+    pw = torch.zeros(4, dtype=torch.int64, device=dev)
+    Ub = None
+    if nb:
+        wpb = walk_params(p.eps, prep.W_band, p.seed_walks, prep.g, None, dt, batch)
+        with watch.stage("band_walks"):
+            Ub, Db, pw = wost(prep, wpb, 1, nb, prep.x_band, dtype=dt)
+            ub64 = torch.empty(nb, dtype=torch.float64, device=dev)
+            db64 = torch.empty_like(ub64)
+            bb = torch.empty(nb, dtype=T, device=dev)
+            B.bvc_reduce_walks(nb, prep.W_band, B.dtype_code(T), Ub, Db, prep.ones_band, ub64, db64, CODE[dt],
+                               u_band, bb)
+    return Solution(prep.idx_int, n_int, prep.idx_band, nb, u_int, g_int, u_band, None, cache, uhat, dudn,
+                    c0 + c1, pw, extra=dict(n_offset=n0, U0=U0, D0=D0, U1=U1, Ub=Ub, a=a, b=b, cview=cview))
+
+
 class SceneBatch:
     """Many scenes sharing one launch sequence (bvc_batch_plan / _launch).
 

@@ -20,10 +20,21 @@ def to_np_aos(t, n=None):
     return np.ascontiguousarray(a.T).astype(np.float64)
 
 
-def cache_np(cache):
-    n = cache.n
-    return dict(x=to_np_aos(cache.x, n), n=to_np_aos(cache.nrm, n), w=to_np_aos(cache.w, n),
-                xbar=to_np_aos(cache.xbar, n), R0=to_np_aos(cache.R0, n))
+def oracle_cache(ref, device_cache=None, atol=1e-12):
+    """The oracle's own cache: the accepted candidates of an oracle sampler's
+    output `ref` (all candidates with accept flags), in index order, as the
+    device compacts them.  When the device's cache is given it must hold the
+    same points; it is compared with the oracle's, never handed to it."""
+    m = ref["accept"]
+    cn = dict(x=ref["x"][m], n=ref["n"][m], w=ref["w"][m], xbar=ref["xbar"][m], R0=ref["R0"][m])
+    if device_cache is not None:
+        n = device_cache.n
+        assert n == int(m.sum()), (n, int(m.sum()))
+        for key, t in (("x", device_cache.x), ("n", device_cache.nrm), ("xbar", device_cache.xbar)):
+            assert np.allclose(to_np_aos(t, n), cn[key], rtol=0, atol=atol), key
+        assert np.allclose(to_np_aos(device_cache.w, n), cn["w"], rtol=1e-13, atol=0)
+        assert np.allclose(to_np_aos(device_cache.R0, n), cn["R0"], rtol=1e-12, atol=atol)
+    return cn
 
 
 def per_walk_match(a, b, rel=1e-9):

@@ -25,7 +25,7 @@ import pytest
 import torch
 
 import workloads as wl
-from gpu_helpers import lib, to_np_aos
+from gpu_helpers import lib, oracle_cache, to_np_aos
 
 pytestmark = pytest.mark.gpu
 
@@ -286,8 +286,9 @@ def test_correction_argument_errors(B):
 def test_pipeline_solve_with_clamp_fp64(B, orc):
     """pipeline.solve with the clamp on (FP64): the gathered points within
     reach receive the clamped gather plus the correction, the others the
-    clamped gather alone; both against the oracle on the device's own cache,
-    sources and walk seeds."""
+    clamped gather alone; both against the oracle's own chain (its cache,
+    walks, means, near set, clamped gather and correction on the same seeds),
+    whose cache and near set must equal the device's."""
     _bvc, pl = B
     say("pipeline solve with clamp fp64")
     import dataclasses
@@ -307,14 +308,19 @@ def test_pipeline_solve_with_clamp_fp64(B, orc):
     torch.cuda.synchronize()
     n_int = prep.n_int
     assert cl["n_near"] > 100 and n_int > cl["n_near"]
-    cv = sol.extra["cview"]
-    n = cv["n"]
-    cy, cn = to_np_aos(cv["x"], n), to_np_aos(cv["nrm"], n)
-    a, b = cv["a"].cpu().numpy()[:n], cv["b"].cpu().numpy()[:n]
-    idx = prep.idx_int[:n_int].cpu().numpy()
+    osc = orc.Scene(prob.scene)
+    ocache = oracle_cache(osc.sample_cache(prep.n_cand, prob.offset, prob.sides, prob.seed_cache, 0), sol.cache)
+    W = prob.n_walks
+    ref = orc.cache_walks(osc, prob.g, None, orc.walk_params(prob.eps, W, prob.seed_walks), ocache)
+    uh, dh = orc.reduce(ref["U"], ref["D"], W)
+    cy, cn = ocache["x"], ocache["n"]
+    a, b = uh * ocache["w"], dh * ocache["w"]
+    idx = np.flatnonzero(osc.classify(ex, prob.offset) == 1)
+    assert np.array_equal(prep.idx_int[:n_int].cpu().numpy(), idx)
     x = ex[idx]
     u_ref = orc.gather_clamped(2, x, cy, cn, a, b, c)
-    pos = cl["pos"][: cl["n_near"]].cpu().numpy()
+    pos = np.flatnonzero(osc.classify(x, prob.offset + orc.clamp_radius(2, c)) == 2)
+    assert np.array_equal(cl["pos"][: cl["n_near"]].cpu().numpy(), pos)
     P = orc.walk_params(prob.eps, 1, 555)
     corr, st = orc.clamp_correction(orc.Scene(prob.scene), prob.g, None, P, prob.offset, prob.sides, c, 8, 4, x[pos])
     u_ref[pos] += corr

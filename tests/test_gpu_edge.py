@@ -9,7 +9,7 @@ import pytest
 import torch
 
 import workloads as wl
-from gpu_helpers import cache_np, lib, per_walk_match, to_np_aos
+from gpu_helpers import lib, oracle_cache, per_walk_match, to_np_aos
 
 pytestmark = pytest.mark.gpu
 
@@ -89,7 +89,7 @@ def test_step_cap_of_one(orc):
     params = pl.walk_params(1e-3, W, 31, gd, None, "f64", max_steps=1)
     U, D, rec, counters = pl.cache_walks(sc, cache, params, "f64", records=True)
     torch.cuda.synchronize()
-    cn = cache_np(cache)
+    cn = oracle_cache(orc.Scene(scene).sample_cache(300, 5e-3, 1, 8, 0), cache)
     ref = orc.cache_walks(orc.Scene(scene), g, None, orc.walk_params(1e-3, W, 31, max_steps=1), cn)
     n = cache.n * W
     assert np.all(rec["steps"].cpu().numpy()[:n] == 1)
@@ -194,7 +194,8 @@ def test_smallest_scenes(orc, which):
     params = pl.walk_params(2e-3, W, 13, gd, None, "f64")
     U, D, rec, counters = pl.cache_walks(sc, cache, params, "f64")
     torch.cuda.synchronize()
-    ref = orc.cache_walks(orc.Scene(scene), g, None, orc.walk_params(2e-3, W, 13), cache_np(cache))
+    osc = orc.Scene(scene)
+    ref = orc.cache_walks(osc, g, None, orc.walk_params(2e-3, W, 13), oracle_cache(osc.sample_cache(400, l, 1, 4, 0), cache))
     n = cache.n * W
     assert per_walk_match(U.cpu().numpy()[:n], ref["U"]).mean() >= 0.999
     assert per_walk_match(D.cpu().numpy()[:n], ref["D"]).mean() >= 0.999

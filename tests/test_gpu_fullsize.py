@@ -1,16 +1,20 @@
 """Parity at the full benchmark sizes, in the launch configuration bench.py
 times (marked gpu).  The whole step runs at its real shape; the oracle then
-recomputes sampled outputs one by one on the same inputs:
+recomputes sampled outputs one by one from its own inputs (its own
+classification, cache and sources, each first checked equal to the
+device's; the gather kernel is launched at full size on the oracle's cache
+with seeded cache values):
 
 - C2 (4096-segment star, 16,384 cache points x 256 walks, 1024^2 grid) in
   FP64: per-walk parity of every walk of 24 cache points spread over the
-  cache; u and grad u at 64 interior points against the oracle's gather over
-  the whole cache and source set; the 256 walks of 32 band points replayed
+  cache; u and grad u at 64 interior points of a full-size gather against
+  the oracle's gather over the whole cache and source set; the 256 walks of 32 band points replayed
   walk by walk (same ids, same Philox streams).
 - C3 (displaced icosphere, 65,536 x 512 walks, 1.1 M points) in FP32, as
   timed: per-point walk means of 16 cache points and 16 band points against
   the oracle's FP64 walks on the same streams (z-test), and u at 64 interior
-  points against the oracle's gather within the FP32 error bound.
+  points of a full-size FP32 gather against the oracle's within the FP32
+  error bound.
 """
 import sys
 
@@ -19,7 +23,7 @@ import pytest
 import torch
 
 import workloads as wl
-from gpu_helpers import cache_np, lib, per_walk_match, to_np_aos
+from gpu_helpers import lib, oracle_cache, per_walk_match, to_np_aos
 
 pytestmark = pytest.mark.gpu
 
@@ -53,6 +57,26 @@ def _band_walks(orc, osc, prob, params, pts, band_index, W, with_grad):
     return u, g, se
 
 
+def _dev(v, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(v.T if v.ndim == 2 else v)).to("cuda", dtype)
+
+
+def _oracle_split(osc, prob, prep):
+    """The oracle's interior and band index sets; the device's must equal them."""
+    cls = osc.classify(prob.eval_x, prob.offset)
+    idx_i, idx_b = np.flatnonzero(cls == 1), np.flatnonzero(cls == 2)
+    assert np.array_equal(prep.idx_int[: prep.n_int].cpu().numpy(), idx_i)
+    assert np.array_equal(prep.idx_band[: prep.n_band].cpu().numpy(), idx_b)
+    return idx_i, idx_b
+
+
+def _cache_values(cn, seed):
+    """Seeded cache values a, b for a gather launched on the oracle's cache."""
+    rng = np.random.default_rng(seed)
+    n = cn["x"].shape[0]
+    return rng.normal(0, 1, n) * cn["w"], rng.normal(0, 1, n) * cn["w"]
+
+
 def test_c2_full_size_fp64(orc):
     _bvc, pl = lib()
     prob = wl.problem_c2()
@@ -69,7 +93,8 @@ def test_c2_full_size_fp64(orc):
     assert c[3] == n * W and c[2] == 0
     osc = orc.Scene(prob.scene)
     P = orc.walk_params(prob.eps, W, prob.seed_walks)
-    cn = cache_np(cache)
+    idx_i, idx_b = _oracle_split(osc, prob, prep)
+    cn = oracle_cache(osc.sample_cache(prep.n_cand, prob.offset, prob.sides, prob.seed_cache, 0), cache)
     # walks of 24 cache points, walk by walk
     pick = _spread(n, 24)
     ids = (pick[:, None] * W + np.arange(W)[None, :]).ravel()
@@ -79,23 +104,39 @@ def test_c2_full_size_fp64(orc):
     okU, okD = per_walk_match(Ug, ref["U"]), per_walk_match(Dg, ref["D"])
     say(f"  walks {ids.size}: U-match {okU.mean():.5f} D-match {okD.mean():.5f}")
     assert okU.mean() >= 0.999 and okD.mean() >= 0.999
-    # gather at 64 interior points over the whole cache and source set
-    ki = _spread(prep.n_int, 64)
-    idx_i = prep.idx_int[: prep.n_int].cpu().numpy()
-    x = prob.eval_x[idx_i[ki]]
-    a = sol.extra["a"].cpu().numpy()[:n]
-    b = sol.extra["b"].cpu().numpy()[:n]
+    # the oracle's sources; the device's must be the same
+    m = int(round(prob.n_sources ** 0.5))
+    lo, hi = prob.scene.bbox
+    sy, sw = osc.sample_sources(prob.f, m, lo, hi, prob.offset, prob.seed_sources, 0)
     sv = sol.extra["sview"]
-    sy, sw = to_np_aos(sv["y"], sv["n"]), sv["s"].cpu().numpy()[: sv["n"]]
+    assert sv["n"] == sw.size
+    assert np.allclose(to_np_aos(sv["y"], sv["n"]), sy, rtol=0, atol=1e-13)
+    assert np.allclose(sv["s"].cpu().numpy()[: sv["n"]], sw, rtol=1e-12, atol=0)
+    # a full-size gather (every interior point, the whole cache and source
+    # set, as the step launches it) on the oracle's cache with seeded values;
+    # 64 of its outputs against the oracle's gather
+    a, b = _cache_values(cn, 5)
+    cview = dict(n=n, dtype=_bvc.F64, x=_dev(cn["x"]), nrm=_dev(cn["n"]), a=_dev(a), b=_dev(b))
+    sview = dict(n=sw.size, dtype=_bvc.F64, y=_dev(sy), s=_dev(sw))
+    u_full = torch.empty(prep.n_int, dtype=torch.float64, device="cuda")
+    g_full = torch.empty(2, prep.n_int, dtype=torch.float64, device="cuda")
+    _bvc.bvc_gather_grad(2, cview, sview, prep.n_int, _dev(prob.eval_x[idx_i]), u_full, g_full)
+    torch.cuda.synchronize()
+    ki = _spread(prep.n_int, 64)
+    x = prob.eval_x[idx_i[ki]]
     uo, go, cond = orc.gather(2, x, cn["x"], cn["n"], a, b, sy, sw, with_grad=True, with_cond=True)
-    ug = sol.u_int.cpu().numpy()[ki]
-    gg = to_np_aos(sol.g_int)[ki]
+    ug = u_full.cpu().numpy()[ki]
+    gg = to_np_aos(g_full)[ki]
     assert np.all(np.abs(ug - uo) <= 1e-11 * cond)
     gsc = np.abs(go).max(1) + cond
     assert np.all(np.abs(gg - go).max(1) <= 1e-9 * gsc)
+    # the step's own estimate is close to the solution
+    tru = wl.field_value(prob.truth, prob.eval_x[idx_i])
+    err = np.median(np.abs(sol.u_int.cpu().numpy()[: prep.n_int] - tru))
+    say(f"  interior median error {err:.4g}")
+    assert err < 0.02 * np.sqrt(np.mean(tru**2))
     # band points: the library's 256 walks per point, replayed walk by walk
     kb = _spread(prep.n_band, 32)
-    idx_b = prep.idx_band[: prep.n_band].cpu().numpy()
     pts = prob.eval_x[idx_b[kb]]
     ub, gb, se = _band_walks(orc, osc, prob, P, pts, kb, W, True)
     u_gpu = sol.u_band.cpu().numpy()[kb]
@@ -123,7 +164,8 @@ def test_c3_full_size_fp32(orc):
     assert c[3] == n * W and c[2] == 0
     osc = orc.Scene(prob.scene)
     P = orc.walk_params(prob.eps, W, prob.seed_walks)
-    cn = cache_np(cache)
+    idx_i, idx_b = _oracle_split(osc, prob, prep)
+    cn = oracle_cache(osc.sample_cache(prep.n_cand, prob.offset, prob.sides, prob.seed_cache, 0), cache)
     # walk means of 16 cache points against the FP64 walks on the same streams
     pick = _spread(n, 16)
     ids = (pick[:, None] * W + np.arange(W)[None, :]).ravel()
@@ -135,25 +177,36 @@ def test_c3_full_size_fp32(orc):
         z = np.abs(A.mean(1) - Bo.mean(1)) / se
         say(f"  {name}: max z {z.max():.2f}")
         assert np.all(z < 5)
-    # gather at 64 interior points (FP32 inputs as the device holds them)
+    # a full-size FP32 gather (every interior point, the whole cache) on the
+    # oracle's cache with seeded values, all rounded to FP32 on the host; 64
+    # of its outputs against the oracle's gather of the rounded inputs
+    r32 = lambda v: v.astype(np.float32).astype(np.float64)
+    a, b = _cache_values(cn, 6)
+    cy, cnn, a, b = r32(cn["x"]), r32(cn["n"]), r32(a), r32(b)
+    xall = r32(prob.eval_x[idx_i])
+    f32 = torch.float32
+    cview = dict(n=n, dtype=_bvc.F32, x=_dev(cy, f32), nrm=_dev(cnn, f32), a=_dev(a, f32), b=_dev(b, f32))
+    u_full = torch.empty(prep.n_int, dtype=f32, device="cuda")
+    _bvc.bvc_gather_u(3, cview, None, prep.n_int, _dev(xall, f32), u_full)
+    torch.cuda.synchronize()
     ki = _spread(prep.n_int, 64)
-    idx_i = prep.idx_int[: prep.n_int].cpu().numpy()
-    x = to_np_aos(prep.x_int)[ki]
-    cv = sol.extra["cview"]
-    cy, cnn = to_np_aos(cv["x"], n), to_np_aos(cv["nrm"], n)
-    a = cv["a"].double().cpu().numpy()[:n]
-    b = cv["b"].double().cpu().numpy()[:n]
+    x = xall[ki]
     uo, cond = orc.gather(3, x, cy, cnn, a, b, with_grad=False, with_cond=True)
-    ug = sol.u_int.double().cpu().numpy()[ki]
+    ug = u_full.double().cpu().numpy()[ki]
     rmin = np.min(np.linalg.norm(x[:, None, :] - cy[None], axis=2), axis=1)
     zmax = np.linalg.norm(cy, axis=1).max()
     uu = 2.0**-24
     tol = uu * cond * (300 + 4 * (np.linalg.norm(x, axis=1) + zmax) / rmin) + uu * np.abs(uo)
     assert np.all(np.abs(ug - uo) <= tol), np.max(np.abs(ug - uo) / tol)
-    assert np.allclose(prob.eval_x[idx_i[ki]], x, atol=1e-6)
+    # the step's own estimate is close to the solution
+    tru = wl.field_value(prob.truth, prob.eval_x[idx_i])
+    err = np.median(np.abs(sol.u_int.double().cpu().numpy()[: prep.n_int] - tru))
+    say(f"  interior median error {err:.4g}")
+    # (degree-8 solid harmonics on the displaced sphere: a median error of about
+    # 4% of the RMS of u with 512 walks per cache point)
+    assert err < 0.1 * np.sqrt(np.mean(tru**2))
     # band points: walk means against the FP64 walks on the same streams
     kb = _spread(prep.n_band, 16)
-    idx_b = prep.idx_band[: prep.n_band].cpu().numpy()
     pts = prob.eval_x[idx_b[kb]]
     ub, _, se_o = _band_walks(orc, osc, prob, P, pts, kb, W, False)
     u_gpu = sol.u_band.double().cpu().numpy()[kb]

@@ -4,8 +4,10 @@ gradient descent through the hand-written adjoints of the gather and the
 cache (walks fixed, read back from their exit records).
 
 Checks:
-  - the adjoint gradient of the FP32 forward against the FP64 oracle gradient
-    on the same exit records (relative 1e-3);
+  - the device's basis means on the oracle's exit records against the
+    oracle's, and the adjoint gradient of the FP32 forward against the FP64
+    oracle gradient (relative 1e-3); every input (cache, walks, observation
+    points and values) comes from the oracle or the seeded generators;
   - central finite differences (step 1e-4) of the FP64 forward along 16 random
     directions of theta (the loss is quadratic in theta, so central
     differences are exact up to rounding: 1e-7) and of the evaluation
@@ -18,7 +20,7 @@ import pytest
 import torch
 
 import workloads as wl
-from gpu_helpers import lib, to_np_aos
+from gpu_helpers import lib, oracle_cache
 
 pytestmark = pytest.mark.gpu
 
@@ -29,50 +31,67 @@ def say(msg):
 
 @pytest.fixture(scope="module")
 def inv(orc):
+    """Inputs from the oracle: its cache (checked equal to the device
+    sampler's), its FP64 walks' exit records, its classification of the
+    observation candidates and its forward solution plus seeded noise as the
+    observations.  The device's basis means are computed from the oracle's
+    records."""
     _bvc, pl = lib()
     from paper_2302_11825_amd import autograd as ag
 
     p = wl.problem_c5()
-    say("inverse setup: walks and basis means")
+    say("inverse setup: oracle walks and basis means")
     sc = pl.Scene(p["scene"])
+    osc = orc.Scene(p["scene"])
     l, eps, W = p["offset"], p["eps"], p["n_walks"]
-    n_cand = pl.candidates_for(sc, p["n_cache"], l, 2, p["seed_cache"])
-    cache = pl.sample_cache(sc, n_cand, l, 2, p["seed_cache"])
-    g = pl.DeviceField(wl.fourier_2d(p["theta_true"]))
-    U, D, rec, _ = pl.cache_walks(sc, cache, pl.walk_params(eps, W, p["seed_walks"], g, None, "f32"), "f32")
+    pilot = 65536
+    rate = max(osc.sample_cache(pilot, l, 2, p["seed_cache"], 0x7FFFFFFF)["n_accepted"], 1) / pilot
+    n_cand = int(np.ceil(p["n_cache"] / rate))
+    ocache = oracle_cache(osc.sample_cache(n_cand, l, 2, p["seed_cache"], 0), pl.sample_cache(sc, n_cand, l, 2,
+                                                                                               p["seed_cache"]))
+    n = ocache["x"].shape[0]
+    ref = orc.cache_walks(osc, wl.fourier_2d(p["theta_true"]), None, orc.walk_params(eps, W, p["seed_walks"]),
+                          ocache, records=True)
     basis = pl.DeviceField(wl.fourier_2d(np.zeros(256)))
-    n = cache.n
     E = torch.empty(n, 256, dtype=torch.float64, device="cuda")
     F = torch.empty_like(E)
-    _bvc.bvc_basis_means(basis.c(), 2, n, W, _bvc.F32, rec["exit"], rec["w1"], cache.xbar, 1, E, F)
-    obs64 = torch.from_numpy(np.ascontiguousarray(p["obs_candidates"].T)).cuda()
-    cls, dist = pl.classify(sc, obs64, l)
+    _bvc.bvc_basis_means(basis.c(), 2, n, W, _bvc.F64, _dev(ref["exit"]), _dev(ref["w1"]), _dev(ocache["xbar"]), 1,
+                         E, F)
+    Eo, Fo = orc.basis_means(wl.fourier_2d(np.zeros(256)), 2, ref["exit"], ref["w1"], ocache["xbar"], W)
+    # observation points: the first 4096 candidates farther than l, as the oracle classifies them
+    obs = p["obs_candidates"]
+    keep = np.flatnonzero(osc.classify(obs, l) == 1)
+    cls, _ = pl.classify(sc, _dev(obs), l)
     idx, cnt = sc.compact(cls, 1)
-    k = min(4096, cnt)
-    x32 = pl.take(obs64, idx, k, 2, obs64.shape[1], torch.float32)
-    x64 = pl.take(obs64, idx, k, 2, obs64.shape[1], torch.float64)
-    d_obs = pl.take(dist, idx, k, 1, dist.shape[0], torch.float64)
-    cx32 = pl.take(cache.x, None, n, 2, n, torch.float32)
-    cn32 = pl.take(cache.nrm, None, n, 2, n, torch.float32)
+    assert np.array_equal(idx[:cnt].cpu().numpy(), keep)
+    k = min(4096, keep.size)
+    xo = obs[keep[:k]]
+    d_obs, _, _ = osc.closest(xo)
+    r32 = lambda v: v.astype(np.float32).astype(np.float64)
+    w = ocache["w"]
+    a_true, b_true = w * (Eo @ p["theta_true"]), w * (Fo @ p["theta_true"])
+    u_clean = orc.gather(2, r32(xo), r32(ocache["x"]), r32(ocache["n"]), a_true, b_true, with_grad=False)
+    u_obs = r32(u_clean + np.random.default_rng(p["noise_seed"]).normal(0, p["noise_sigma"], k))
     torch.cuda.synchronize()
-    theta_true = torch.from_numpy(p["theta_true"]).cuda()
-    with torch.no_grad():
-        a, b = ag.cache_values(theta_true, E, F, cache.w, torch.float32)
-        u_clean = ag.gather(a, b, x32, cx32, cn32)
-    noise = torch.from_numpy(np.random.default_rng(p["noise_seed"]).normal(0, p["noise_sigma"], k)).cuda()
-    u_obs = (u_clean.double() + noise).float()
-    return dict(p=p, sc=sc, cache=cache, rec=rec, E=E, F=F, x32=x32, x64=x64, d_obs=d_obs, cx32=cx32,
-                cn32=cn32, u_obs=u_obs, theta_true=theta_true, n=n, k=k, W=W, ag=ag, pl=pl)
+    return dict(p=p, sc=sc, E=E, F=F, Eo=Eo, Fo=Fo, w=torch.from_numpy(w).cuda(), w_np=w,
+                x32=_dev(r32(xo), torch.float32), x64=_dev(xo), d_obs=torch.from_numpy(d_obs).cuda(),
+                cx64=_dev(ocache["x"]), cn64=_dev(ocache["n"]), cx32=_dev(r32(ocache["x"]), torch.float32),
+                cn32=_dev(r32(ocache["n"]), torch.float32), cy_np=r32(ocache["x"]), cn_np=r32(ocache["n"]),
+                x_np=r32(xo), u_obs=torch.from_numpy(u_obs).cuda().float(), u_obs_np=u_obs,
+                theta_true=torch.from_numpy(p["theta_true"]).cuda(), n=n, k=k, W=W, ag=ag, pl=pl)
+
+
+def _dev(v, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(v.T if v.ndim == 2 else v)).to("cuda", dtype)
 
 
 def _loss(I, theta, dtype=torch.float32, x=None):
     ag = I["ag"]
-    c = I["cache"]
     if dtype == torch.float64:
-        cx, cn, xx = c.x, c.nrm, (I["x64"] if x is None else x)
+        cx, cn, xx = I["cx64"], I["cn64"], (I["x64"] if x is None else x)
     else:
         cx, cn, xx = I["cx32"], I["cn32"], (I["x32"] if x is None else x)
-    a, b = ag.cache_values(theta, I["E"], I["F"], c.w, dtype)
+    a, b = ag.cache_values(theta, I["E"], I["F"], I["w"], dtype)
     u = ag.gather(a, b, xx, cx, cn)
     r = u - I["u_obs"].to(dtype)
     return 0.5 * (r * r).sum()
@@ -85,19 +104,16 @@ def test_adjoint_matches_oracle_gradient(inv, orc):
     L = _loss(I, theta)
     L.backward()
     g_gpu = theta.grad.cpu().numpy()
-    # oracle: its own basis means from the same exit records, FP64 throughout
-    n, W = I["n"], I["W"]
-    exit_pts = to_np_aos(I["rec"]["exit"], n * W)
-    w1 = I["rec"]["w1"].double().cpu().numpy()[: n * W]
-    xbar = to_np_aos(I["cache"].xbar, n)
-    Eo, Fo = orc.basis_means(wl.fourier_2d(np.zeros(256)), 2, exit_pts, w1, xbar, W)
-    w = I["cache"].w.cpu().numpy()[:n]
-    cy, cn = to_np_aos(I["cx32"], n), to_np_aos(I["cn32"], n)
-    x = to_np_aos(I["x32"], I["k"])
+    # the device's basis means on the oracle's records
+    assert np.allclose(I["E"].cpu().numpy(), I["Eo"], rtol=1e-10, atol=1e-11)
+    assert np.allclose(I["F"].cpu().numpy(), I["Fo"], rtol=1e-9, atol=1e-9)
+    # the oracle's gradient, FP64 throughout, on the same FP32-rounded positions
+    Eo, Fo, w = I["Eo"], I["Fo"], I["w_np"]
+    cy, cn, x = I["cy_np"], I["cn_np"], I["x_np"]
     a = w * (Eo @ np.zeros(256))
     b = w * (Fo @ np.zeros(256))
     u = orc.gather(2, x, cy, cn, a, b, with_grad=False)
-    r = u - I["u_obs"].double().cpu().numpy()
+    r = u - I["u_obs_np"]
     da, db, _, _ = orc.gather_backward(2, x, r, cy, cn, a, b)
     g_ref = Eo.T @ (w * da) + Fo.T @ (w * db)
     rel = np.linalg.norm(g_gpu - g_ref) / np.linalg.norm(g_ref)
@@ -147,7 +163,7 @@ def test_gradient_descent_recovers_boundary_data(inv):
     lam = 1.0
     for _ in range(15):
         th = v.clone().requires_grad_(True)
-        a, b = I["ag"].cache_values(th, I["E"], I["F"], I["cache"].w, torch.float32)
+        a, b = I["ag"].cache_values(th, I["E"], I["F"], I["w"], torch.float32)
         u = I["ag"].gather(a, b, I["x32"], I["cx32"], I["cn32"])
         (0.5 * (u * u).sum()).backward()
         jtjv = th.grad

@@ -18,7 +18,7 @@ import pytest
 import torch
 
 import workloads as wl
-from gpu_helpers import c2_like_fields, cache_np, lib, per_walk_match, small_star, to_np_aos
+from gpu_helpers import c2_like_fields, lib, oracle_cache, per_walk_match, small_star, to_np_aos
 
 pytestmark = pytest.mark.gpu
 
@@ -32,6 +32,11 @@ def say(msg):
 def B():
     assert torch.cuda.is_available(), "GPU tests need a visible GPU"
     return lib()
+
+
+def _dev(v):
+    """A host array on the device in the library's [dim][n] layout."""
+    return torch.from_numpy(np.ascontiguousarray(v.T if v.ndim == 2 else v)).to("cuda", torch.float64)
 
 
 def _prep(pl, scene, g, f=None):
@@ -101,8 +106,8 @@ def test_cache_walks_fp64_per_walk(B, orc, case):
     params = pl.walk_params(eps, W, 4242, gd, fd, "f64")
     U, D, rec, counters = pl.cache_walks(sc, cache, params, "f64", records=True)
     torch.cuda.synchronize()
-    cn = cache_np(cache)
     os_ = orc.Scene(scene)
+    cn = oracle_cache(os_.sample_cache(n, l, sides, 77, 0), cache)
     P = orc.walk_params(eps, W, 4242)
     ref = orc.cache_walks(os_, g, f, P, cn, records=True)
     Ug = U.cpu().numpy()[: cache.n * W]
@@ -119,9 +124,9 @@ def test_cache_walks_fp64_per_walk(B, orc, case):
     ex = to_np_aos(rec["exit"], cache.n * W)
     assert np.mean(np.all(np.abs(ex - ref["exit"]) < 1e-9, axis=1)) >= 0.999
     assert np.mean(per_walk_match(rec["w1"].cpu().numpy()[: cache.n * W], ref["w1"])) >= 0.999
-    # reduction in FP64
-    uhat, dudn, a, b = pl.reduce_walks(cache, W, U, D, "f64")
-    uh_ref, dh_ref = orc.reduce(Ug, Dg, W)
+    # reduction in FP64: the device kernel on the oracle's walks
+    uhat, dudn, a, b = pl.reduce_walks(cache, W, _dev(ref["U"]), _dev(ref["D"]), "f64")
+    uh_ref, dh_ref = orc.reduce(ref["U"], ref["D"], W)
     assert np.allclose(uhat.cpu().numpy()[: cache.n], uh_ref, rtol=1e-12, atol=1e-14)
     assert np.allclose(dudn.cpu().numpy()[: cache.n], dh_ref, rtol=1e-12, atol=1e-12)
     assert np.allclose(a.cpu().numpy()[: cache.n], uh_ref * cn["w"], rtol=1e-12, atol=1e-15)
@@ -347,14 +352,29 @@ def test_basis_means_fp64(B, orc, case):
     F = torch.empty_like(E)
     _bvc.bvc_basis_means(bd.c(), scene.dim, cache.n, W, _bvc.F64, rec["exit"], rec["w1"], cache.xbar, 1, E, F)
     torch.cuda.synchronize()
-    cn = cache_np(cache)
-    Eo, Fo = orc.basis_means(basis, scene.dim, to_np_aos(rec["exit"], cache.n * W),
-                             rec["w1"].cpu().numpy()[: cache.n * W], cn["xbar"], W)
-    assert np.allclose(E.cpu().numpy(), Eo, rtol=1e-10, atol=1e-11)
-    assert np.allclose(F.cpu().numpy(), Fo, rtol=1e-9, atol=1e-9)
+    osc = orc.Scene(scene)
+    cn = oracle_cache(osc.sample_cache(n, l, sides, 7, 0), cache)
+    ref = orc.cache_walks(osc, g, None, orc.walk_params(eps, W, 17), cn, records=True)
+    Eo, Fo = orc.basis_means(basis, scene.dim, ref["exit"], ref["w1"], cn["xbar"], W)
+    # the device kernel on the oracle's exit records
+    E2, F2 = torch.empty_like(E), torch.empty_like(F)
+    _bvc.bvc_basis_means(bd.c(), scene.dim, cache.n, W, _bvc.F64, _dev(ref["exit"]), _dev(ref["w1"]),
+                         _dev(cn["xbar"]), 1, E2, F2)
+    torch.cuda.synchronize()
+    assert np.allclose(E2.cpu().numpy(), Eo, rtol=1e-10, atol=1e-11)
+    assert np.allclose(F2.cpu().numpy(), Fo, rtol=1e-9, atol=1e-9)
+    # the device's own chain: where every walk of a point matches the
+    # oracle's, its rows match too
+    nW = cache.n * W
+    same = (per_walk_match(U.cpu().numpy()[:nW], ref["U"]) & per_walk_match(D.cpu().numpy()[:nW], ref["D"]))
+    same = same.reshape(-1, W).all(1)
+    assert same.mean() >= 0.99
+    assert np.allclose(E.cpu().numpy()[same], Eo[same], rtol=1e-10, atol=1e-11)
+    assert np.allclose(F.cpu().numpy()[same], Fo[same], rtol=1e-9, atol=1e-9)
     # linearity: E theta reproduces the walks' own means
     theta = g.coef
-    uh, dh = orc.reduce(U.cpu().numpy()[: cache.n * W], D.cpu().numpy()[: cache.n * W], W)
+    uh = U.cpu().numpy()[:nW].reshape(-1, W).mean(1)
+    dh = D.cpu().numpy()[:nW].reshape(-1, W).mean(1)
     assert np.allclose(E.cpu().numpy() @ theta, uh, rtol=1e-9, atol=1e-10)
     assert np.allclose(F.cpu().numpy() @ theta, dh, rtol=1e-8, atol=1e-8)
 
@@ -370,7 +390,8 @@ def test_cache_walks_fp32_statistics(B, orc):
     cache = pl.sample_cache(sc, 1200, l, sides, 3, 0)
     U, D, _, _ = pl.cache_walks(sc, cache, pl.walk_params(eps, W, 11, gd, fd, "f32"), "f32")
     torch.cuda.synchronize()
-    ref = orc.cache_walks(orc.Scene(scene), g, f, orc.walk_params(eps, W, 12), cache_np(cache))
+    osc = orc.Scene(scene)
+    ref = orc.cache_walks(osc, g, f, orc.walk_params(eps, W, 12), oracle_cache(osc.sample_cache(1200, l, sides, 3, 0), cache))
     Ug = U.double().cpu().numpy()[: cache.n * W].reshape(-1, W)
     Dg = D.double().cpu().numpy()[: cache.n * W].reshape(-1, W)
     Uo, Do = ref["U"].reshape(-1, W), ref["D"].reshape(-1, W)

@@ -2,8 +2,8 @@
 Specification") against the FP64 oracle (marked gpu): the sampler's accept
 flags bit for bit and its points, normals, weights and domain distances to
 1e-13 (2D and 3D); the classification of evaluation points against the
-region; and the whole ROI step in FP64 against the oracle's walks, means and
-gather on the device's own cache, plus its accuracy inside the region."""
+region; and the whole ROI step in FP64 against the oracle's own cache, walks, means
+and gather, plus its accuracy inside the region."""
 import sys
 
 import numpy as np
@@ -11,7 +11,7 @@ import pytest
 import torch
 
 import workloads as wl
-from gpu_helpers import cache_np, lib, per_walk_match, to_np_aos
+from gpu_helpers import lib, oracle_cache, per_walk_match, to_np_aos
 
 pytestmark = pytest.mark.gpu
 
@@ -70,11 +70,10 @@ def test_roi_step_fp64_matches_oracle(orc):
     sol = pl.solve_roi(prep, with_grad=True)
     torch.cuda.synchronize()
     # evaluation points: exactly those inside the region
-    inside = orc.Scene(roi).classify(ex, 0.0) == 1
-    idx = prep.idx_int[: prep.n_int].cpu().numpy()
-    assert np.array_equal(np.sort(idx), np.flatnonzero(inside))
-    # the oracle's walks on the device's cache, then means and the gather
-    cn = cache_np(sol.cache)
+    idx = np.flatnonzero(orc.Scene(roi).classify(ex, 0.0) == 1)
+    assert np.array_equal(prep.idx_int[: prep.n_int].cpu().numpy(), idx)
+    # the oracle's own cache (equal to the device's), its walks, means and gather
+    cn = oracle_cache(orc.sample_roi(orc.Scene(dom), orc.Scene(roi), prep.n_cand, prob.seed_cache, 0), sol.cache)
     W = prob.n_walks
     ref = orc.cache_walks(orc.Scene(dom), g, None, orc.walk_params(prob.eps, W, prob.seed_walks), cn)
     n = sol.cache.n

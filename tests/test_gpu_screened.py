@@ -17,7 +17,7 @@ import pytest
 import torch
 
 import workloads as wl
-from gpu_helpers import cache_np, lib, per_walk_match, to_np_aos
+from gpu_helpers import lib, oracle_cache, per_walk_match, to_np_aos
 
 pytestmark = pytest.mark.gpu
 
@@ -106,7 +106,7 @@ def test_screened_walks_fp64_walk_by_walk(B, orc):
     torch.cuda.synchronize()
     osc = orc.Scene(scene)
     P = orc.walk_params(eps, W, seed, sigma=SIGMA)
-    ref = orc.cache_walks(osc, g, None, P, cache_np(cache))
+    ref = orc.cache_walks(osc, g, None, P, oracle_cache(osc.sample_cache(600, l, 1, 5, 0), cache))
     n = cache.n * W
     okU = per_walk_match(U.cpu().numpy()[:n], ref["U"])
     okD = per_walk_match(D.cpu().numpy()[:n], ref["D"])
@@ -140,7 +140,9 @@ def test_screened_walks_fp32_statistical(B, orc):
     wp = pl.walk_params(eps, W, seed, gd, None, "f32", sigma=SIGMA)
     U, D, rec, counters = pl.cache_walks(sc, cache, wp, "f32")
     torch.cuda.synchronize()
-    ref = orc.cache_walks(orc.Scene(scene), g, None, orc.walk_params(eps, W, seed, sigma=SIGMA), cache_np(cache))
+    osc = orc.Scene(scene)
+    ref = orc.cache_walks(osc, g, None, orc.walk_params(eps, W, seed, sigma=SIGMA),
+                          oracle_cache(osc.sample_cache(150, l, 1, 6, 0), cache))
     n = cache.n
     for name in ("U", "D"):
         A = (U if name == "U" else D).double().cpu().numpy()[: n * W].reshape(n, W)

@@ -431,6 +431,46 @@ def problem_c2(grid: int = 1024, jitter: str = "isotropic") -> Problem:
                    seed_walks=seed(2, 4), seed_cache=seed(2, 3), seed_sources=seed(2, 6))
 
 
+def mixed_polygon(verts, neumann, counts, name="mixed"):
+    """A CCW polygon whose side i (vertex i to i + 1) is split into counts[i]
+    equal segments and is Neumann where neumann[i]: returns the whole
+    boundary and its Dirichlet and Neumann segment sets, each with only the
+    vertices it uses."""
+    V, F = [], []
+    n = len(verts)
+    for i in range(n):
+        a, b = np.asarray(verts[i], float), np.asarray(verts[(i + 1) % n], float)
+        for j in range(counts[i]):
+            V.append(a + (b - a) * j / counts[i])
+            F.append(bool(neumann[i]))
+    V = np.array(V)
+    m = len(V)
+    segs = np.array([[i, (i + 1) % m] for i in range(m)], dtype=np.int32)
+    F = np.array(F)
+
+    def part(mask, tag):
+        P = segs[mask]
+        used, inv = np.unique(P.ravel(), return_inverse=True)
+        return Scene(2, V[used], inv.reshape(P.shape).astype(np.int32), f"{name}_{tag}")
+
+    return Scene(2, V, segs, name), part(~F, "dirichlet"), part(F, "neumann")
+
+
+def problem_c2_mixed(grid: int = 1024, n_cache: int = 262144, n_walks: int = 256) -> Problem:
+    """Channel [0, 6] x [0, pi] (4096 segments): Dirichlet ends, Neumann walls
+    (h = 0), Laplace, u = x + 0.5 e^(x - 6) cos y (zero flux through y = 0
+    and y = pi)."""
+    full, dir_, neu = mixed_polygon([[0, 0], [6, 0], [6, np.pi], [0, np.pi]], [True, False, True, False],
+                                    [1536, 512, 1536, 512], "c2_channel4096")
+    g = harmonic_2d(1, 1.0, 0.5 * np.exp(-6.0))
+    eps = 1e-3 * full.diagonal
+    lo, hi = full.bbox
+    return Problem("c2_channel4096_mixed", full, g, Field(), n_cache, n_walks, eps, 5 * eps, 0,
+                   grid2d(grid, lo, hi), g, sides=1, precision="f32",
+                   seed_walks=seed(7, 4), seed_cache=seed(7, 3), seed_sources=seed(7, 6),
+                   extra=dict(dirichlet=dir_, neumann=neu))
+
+
 def problem_c3(n_eval_box: int = 2_320_000, slice_n: int = 256, level: int = 6) -> Problem:
     """Displaced icosphere (81,920 triangles), Laplace, solid-harmonic g."""
     sc = displaced_icosphere(level, seed(3, 1))
