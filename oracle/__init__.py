@@ -114,6 +114,8 @@ def lib():
                                        C.c_int64, _dp, _dp, _dp, _dp, _dp]
         L.orc_wost_walks.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(_Field), C.POINTER(_WalkParams), C.c_int,
                                      C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _ip]
+        L.orc_silhouette_distances.argtypes = [C.c_void_p, C.c_int64, _dp, _dp]
+        L.orc_silhouette_distances.restype = None
         L.orc_sample_mixed.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_uint64,
                                        C.c_uint32, _dp, _dp, _dp, _dp, _dp, _ip, _ip]
         L.orc_sample_mixed.restype = C.c_int64
@@ -635,3 +637,11 @@ def sample_mixed(full: Scene, dir_scene: Scene, neu_scene: Scene, n, l, seed, ba
     na = lib().orc_sample_mixed(full.h, dir_scene.h, neu_scene.h, n, float(l), int(seed), int(batch), _d(x), _d(nrm),
                                 _d(w), _d(xb), _d(R0), _i(ty), _i(acc))
     return dict(x=x, n=nrm, w=w, xbar=xb, R0=R0, type=ty, accept=acc.astype(bool), n_accepted=na)
+
+
+def silhouette_distances(neu_scene: Scene, x):
+    """Distance to the closest Neumann silhouette vertex, per point."""
+    x = _f64(x).reshape(-1, 2)
+    d = np.zeros(x.shape[0])
+    lib().orc_silhouette_distances(neu_scene.h, x.shape[0], _d(x), _d(d))
+    return d

@@ -1741,6 +1741,14 @@ static void wost_walk(const orc_scene* dir, const orc_scene* neu, const neu_link
   }
 }
 
+void orc_silhouette_distances(const orc_scene* neu, int64_t n, const double* x, double* d) {
+  neu_links L = make_links(neu);
+  for (int64_t i = 0; i < n; ++i) d[i] = silhouette_distance(neu, &L, x + 2 * i);
+  free(L.prev);
+  free(L.has_next);
+  free(L.straight);
+}
+
 void orc_wost_walks(const orc_scene* dir, const orc_scene* neu, const orc_field* g, const orc_walk_params* p,
                     int mode, int64_t n, const double* x, const double* nrm, const double* R0, const double* xbar,
                     double* U, double* D, int32_t* steps) {

@@ -242,6 +242,9 @@ void orc_gather_sigma(int dim, double sigma, int64_t K, const double* ex, int64_
  * is the nearest Neumann crossing within the radius, else the sphere point.
  * Stops when d_Dirichlet < eps (or max_steps) with U = g at the closest
  * Dirichlet point.  D may be NULL. */
+/* Distance from each x (n x 2) to the closest silhouette vertex of the
+ * Neumann segments `neu` as the walk on stars uses it (INFINITY if none). */
+void orc_silhouette_distances(const orc_scene* neu, int64_t n, const double* x, double* d);
 void orc_wost_walks(const orc_scene* dir, const orc_scene* neu, const orc_field* g, const orc_walk_params* p,
                     int mode, int64_t n, const double* x, const double* nrm, const double* R0, const double* xbar,
                     double* U, double* D, int32_t* steps);

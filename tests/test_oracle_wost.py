@@ -169,3 +169,52 @@ def test_wost_reflex_neumann_corner(k):
     exact = wl.field_value(g, pts)
     for i in range(len(pts)):
         assert abs(U[i].mean() - exact[i]) < 5 * _se(U[i]) + 2e-3, (pts[i], U[i].mean(), exact[i], _se(U[i]))
+
+
+def _inside_points(full, n, seed, margin=1e-3):
+    of = orc.Scene(full)
+    rng = np.random.default_rng(seed)
+    lo, hi = full.bbox
+    out = []
+    while len(out) < n:
+        x = rng.uniform(lo, hi, (4 * n, 2))
+        d, _, _ = of.closest(x)
+        out.extend(x[(of.inside(x) != 0) & (d > margin)])
+    return np.array(out[:n])
+
+
+def _nearest(x, verts):
+    v = np.asarray(verts, float)
+    return np.min(np.hypot(x[:, None, 0] - v[None, :, 0], x[:, None, 1] - v[None, :, 1]), axis=1)
+
+
+def test_silhouette_distance_closed_forms():
+    """The star radius's silhouette term by hand: straight wall vertices and
+    convex corners are never silhouettes, run ends always are, and a reflex
+    corner is one exactly for the viewpoints that see one of its edges hidden
+    behind the other."""
+    # rectangle, Neumann bottom and top: only the four run ends count, also
+    # for walks standing on a wall
+    full, _, neu = polygon_parts(*subdivide([[0, 0], [2, 0], [2, 1], [0, 1]], [True, False, True, False], 8))
+    on = orc.Scene(neu)
+    x = _inside_points(full, 300, 1)
+    corners = [[0, 0], [2, 0], [2, 1], [0, 1]]
+    assert np.allclose(orc.silhouette_distances(on, x), _nearest(x, corners), rtol=1e-15, atol=0)
+    xw = np.stack([np.random.default_rng(2).uniform(0.05, 1.95, 40), np.repeat([0.0, 1.0], 20)], 1)
+    assert np.allclose(orc.silhouette_distances(on, xw), _nearest(xw, corners), rtol=1e-15, atol=0)
+    # a convex Neumann corner (2, 0) between the bottom and the right side
+    full, _, neu = polygon_parts(*subdivide([[0, 0], [2, 0], [2, 1], [0, 1]], [True, True, False, False], 4))
+    x = _inside_points(full, 300, 3)
+    assert np.allclose(orc.silhouette_distances(orc.Scene(neu), x), _nearest(x, [[0, 0], [2, 1]]), rtol=1e-15,
+                       atol=0)
+    # the 270 degree corner at the origin between Neumann edges
+    for k in (1, 8):
+        full, _, neu = polygon_parts(*subdivide([[0, 0], [1, 0], [1, 1], [-1, 1], [-1, -1], [0, -1]],
+                                                [True, False, False, False, False, True], k))
+        x = _inside_points(full, 600, 4 + k)
+        ends = _nearest(x, [[1, 0], [0, -1]])
+        q1 = (x[:, 0] > 0) & (x[:, 1] > 0)
+        q3 = (x[:, 0] < 0) & (x[:, 1] < 0)
+        want = np.where(q1 | q3, np.minimum(ends, np.hypot(x[:, 0], x[:, 1])), ends)
+        assert q1.sum() > 50 and q3.sum() > 50
+        assert np.allclose(orc.silhouette_distances(orc.Scene(neu), x), want, rtol=1e-15, atol=0)
