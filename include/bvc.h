@@ -244,12 +244,13 @@ typedef struct {
   void* ev_end;            /* and right after the walk kernel (NULL = none), to time
                               the traversal alone; ignored by the batch calls */
   double sigma;            /* screening coefficient of Lap u - sigma u = f (Eq. 1),
-                              >= 0.  sigma > 0 (3D scenes, f = ZERO; Appendix A.2):
-                              every ball of radius R multiplies the estimate by
-                              sR/sinh(sR) (s = sqrt(sigma)) and the ball gradient
-                              weight dim/R0 becomes s/i1(sR0), i1(x) =
-                              (x cosh x - sinh x)/x^2.  Not taken by the batch and
-                              clamping calls. */
+                              >= 0.  sigma > 0 (f = ZERO; Appendix A.2): every
+                              ball of radius R multiplies the estimate by its
+                              mean-value factor, 1/I0(sR) in 2D and sR/sinh(sR)
+                              in 3D (s = sqrt(sigma)), and the ball gradient
+                              weight dim/R0 becomes s/I1(sR0) in 2D and
+                              s/i1(sR0) in 3D, i1(x) = (x cosh x - sinh x)/x^2.
+                              Not taken by the batch and clamping calls. */
 } bvc_walk_params;
 
 /* Walk j of cache point i has id i*W + j (n_cache*W < 2^32).  Each walk takes
@@ -325,9 +326,11 @@ typedef struct {
                             potential's boundary term (Eq. 9 in the first
                             integral of Eq. 8); the gradient is not clamped.
                             0 = off */
-  double sigma;          /* > 0: screened kernels G = -exp(-sr)/(4 pi r) and
-                            their derivatives (Appendix A.2; s = sqrt(sigma));
-                            3D only, without near field or clamp.  0 = off */
+  double sigma;          /* > 0: screened kernels G = -K0(sr)/(2 pi) in 2D and
+                            -exp(-sr)/(4 pi r) in 3D with their derivatives
+                            (Appendix A.2; s = sqrt(sigma)); without near field
+                            or clamp.  FP32 evaluates K0, K1 to about 5e-7
+                            relative, FP64 to about 1e-14.  0 = off */
 } bvc_gather_params;
 
 /* u_k = sum_i [dG/dn(x_k,z_i) a_i - G(x_k,z_i) b_i] + sum_j G(x_k,y_j) s_j

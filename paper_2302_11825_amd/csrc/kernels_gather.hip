@@ -17,6 +17,7 @@
 #include <string>
 #include <tuple>
 
+#include "bessel.hpp"
 #include "bvc_device.hpp"
 
 namespace bvc {
@@ -488,6 +489,110 @@ __global__ __launch_bounds__(kGBlock) void k_gather_screened3(GatherArgs<T> a, d
   if (GRAD && a.g) {
 #pragma unroll
     for (int c = 0; c < 3; ++c)
+      a.g[c * a.n_eval + k] = (T)((a.accumulate ? (double)a.g[c * a.n_eval + k] : 0.0) + sc * tg[c]);
+  }
+}
+
+// Screened gather in 2D (Eqs. 3-6 with the kernels of Appendix A.2):
+// G = -K0(z)/(2 pi), z = s r, and with Q = z K1(z), A = a n/(2 pi),
+// B = b/(2 pi), t = A.(y-x):
+//   a dG/dn - b G = Q t / r^2 + B K0
+//   grad = (y-x) [Q (2 t / r^4 + B / r^2) + s^2 K0 t / r^2] - A Q / r^2
+// (the Poisson terms times Q plus dG/dn times dQ/dx = s^2 K0 (y - x)); a
+// source term s_j adds G s_j and Q dG0/dx s_j = -Q (y-x) s_j/(2 pi r^2).
+// One evaluation point per thread; the cache and sources stream through LDS
+// tiles as in k_gather.
+template <typename T, bool GRAD>
+__global__ __launch_bounds__(kGBlock) void k_gather_screened2(GatherArgs<T> a, double sigma) {
+  __shared__ T ent[kTile * 8];
+  const int tid = threadIdx.x;
+  const int64_t k = (int64_t)blockIdx.x * kGBlock + tid;
+  const bool live = k < a.n_eval;
+  T x[2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) x[c] = live ? a.ex[c * a.n_eval + k] : T(0);
+  const T s = (T)sqrt(sigma), s2 = (T)sigma;
+  const T inv2pi = (T)(1.0 / (2.0 * kPi));
+  const T tiny = sizeof(T) == 4 ? (T)1e-18 : (T)1e-200;
+  double tu = 0.0, tg[2] = {0.0, 0.0};
+  T au = T(0), ag[2] = {T(0), T(0)};
+  auto fold = [&]() {
+    tu += (double)au;
+    au = T(0);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      tg[c] += (double)ag[c];
+      ag[c] = T(0);
+    }
+  };
+  for (int64_t t0 = 0; t0 < a.n_cache; t0 += kTile) {
+    const int cnt = (int)std::min<int64_t>(kTile, a.n_cache - t0);
+    if (tid < cnt) {
+      const int64_t i = t0 + tid;
+      T* e = ent + tid * 8;
+      const T av = a.ca[i];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        e[c] = a.cx[c * a.n_cache + i];
+        e[3 + c] = a.cn[c * a.n_cache + i] * av * inv2pi;
+      }
+      e[2] = a.cb[i] * inv2pi;
+    }
+    __syncthreads();
+    for (int j = 0; j < cnt; ++j) {
+      const T* e = ent + j * 8;
+      const T dx = e[0] - x[0], dy = e[1] - x[1];
+      const T r2 = fma(dx, dx, fma(dy, dy, tiny));
+      const T ri2 = T(1) / r2;
+      const T r = sqrt(r2);
+      T k0, k1;
+      bessel_k01t<T>(s * r, k0, k1);
+      const T Q = s * r * k1;
+      const T t = fma(e[3], dx, e[4] * dy);
+      au = fma(Q * t, ri2, fma(e[2], k0, au));
+      if constexpr (GRAD) {
+        const T q = Q * ri2 * fma(T(2) * t, ri2, e[2]) + s2 * k0 * t * ri2;
+        const T m = Q * ri2;
+        ag[0] = fma(q, dx, fma(-m, e[3], ag[0]));
+        ag[1] = fma(q, dy, fma(-m, e[4], ag[1]));
+      }
+    }
+    __syncthreads();
+    fold();
+  }
+  for (int64_t t0 = 0; t0 < a.n_src; t0 += kTile) {
+    const int cnt = (int)std::min<int64_t>(kTile, a.n_src - t0);
+    if (tid < cnt) {
+      const int64_t j = t0 + tid;
+      T* e = ent + tid * 8;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) e[c] = a.sy[c * a.n_src + j];
+      e[2] = -a.ss[j] * inv2pi;
+    }
+    __syncthreads();
+    for (int j = 0; j < cnt; ++j) {
+      const T* e = ent + j * 8;
+      const T dx = e[0] - x[0], dy = e[1] - x[1];
+      const T r2 = fma(dx, dx, fma(dy, dy, tiny));
+      const T r = sqrt(r2);
+      T k0, k1;
+      bessel_k01t<T>(s * r, k0, k1);
+      au = fma(e[2], k0, au);
+      if constexpr (GRAD) {
+        const T q = e[2] * s * r * k1 / r2;
+        ag[0] = fma(q, dx, ag[0]);
+        ag[1] = fma(q, dy, ag[1]);
+      }
+    }
+    __syncthreads();
+    fold();
+  }
+  if (!live) return;
+  const double sc = a.scale ? (double)a.scale[k] : 1.0;
+  if (a.u) a.u[k] = (T)((a.accumulate ? (double)a.u[k] : 0.0) + sc * tu);
+  if (GRAD && a.g) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
       a.g[c * a.n_eval + k] = (T)((a.accumulate ? (double)a.g[c * a.n_eval + k] : 0.0) + sc * tg[c]);
   }
 }
@@ -1020,8 +1125,13 @@ int gather_impl(int dim, const bvc_cache_view* c, const bvc_source_view* s, int6
   const bool clamp = clamp_c > 0.0;
   if (sigma > 0.0) {
     const int blocks = (int)((n_eval + kGBlock - 1) / kGBlock);
-    if (g) hipLaunchKernelGGL((k_gather_screened3<T, true>), dim3(blocks), dim3(kGBlock), 0, st, a, sigma);
-    else hipLaunchKernelGGL((k_gather_screened3<T, false>), dim3(blocks), dim3(kGBlock), 0, st, a, sigma);
+    if (dim == 2) {
+      if (g) hipLaunchKernelGGL((k_gather_screened2<T, true>), dim3(blocks), dim3(kGBlock), 0, st, a, sigma);
+      else hipLaunchKernelGGL((k_gather_screened2<T, false>), dim3(blocks), dim3(kGBlock), 0, st, a, sigma);
+    } else {
+      if (g) hipLaunchKernelGGL((k_gather_screened3<T, true>), dim3(blocks), dim3(kGBlock), 0, st, a, sigma);
+      else hipLaunchKernelGGL((k_gather_screened3<T, false>), dim3(blocks), dim3(kGBlock), 0, st, a, sigma);
+    }
     return check_hip(hipGetLastError(), "screened gather launch");
   }
   if (dim == 2) launch_gather<T, 2>(a, g != nullptr, near != nullptr, ppt, clamp, st);
@@ -1049,7 +1159,6 @@ int gather_entry(int32_t dim, const bvc_cache_view* c, const bvc_source_view* s,
   if (!(clamp_c >= 0.0) || !std::isfinite(clamp_c)) return fail(BVC_EINVAL, "clamp_c must be finite and >= 0");
   const double sigma = prm ? prm->sigma : 0.0;
   if (!(sigma >= 0.0) || !std::isfinite(sigma)) return fail(BVC_EINVAL, "sigma must be finite and >= 0");
-  if (sigma > 0.0 && dim != 3) return fail(BVC_EUNSUPPORTED, "the screened gather is built for 3D");
   if (sigma > 0.0 && (near || clamp_c > 0.0))
     return fail(BVC_EUNSUPPORTED, "the screened gather takes no near field or clamp");
   if (c->dtype == BVC_F32)

@@ -18,6 +18,7 @@
 #include <mutex>
 #include <string>
 
+#include "bessel.hpp"
 #include "bvc_device.hpp"
 
 namespace bvc {
@@ -55,7 +56,7 @@ struct WalkArgs {
   unsigned long long* counters;
   unsigned long long chunk;  // walk ids per claim, 1..kChunkMax
   int open_lanes;            // leave the traversal loop at this many open queries
-  double sigma;              // screening coefficient (3D, no source term), 0 = Poisson
+  double sigma;              // screening coefficient (no source term), 0 = Poisson
 };
 
 // In-walk source term in the walk's precision (constants and Gaussian sums).
@@ -103,6 +104,13 @@ __device__ __forceinline__ T screen_ball_weight3(T x) {
   }
   const T e = exp(-x);
   return T(2) * x * e / (T(1) - e * e);
+}
+
+// Mean-value factor of a screened ball at x = s R: 1/I0(x) in 2D, x/sinh x in 3D.
+template <typename T, int D>
+__device__ __forceinline__ T screen_ball_weight(T x) {
+  if constexpr (D == 3) return screen_ball_weight3<T>(x);
+  else return T(1) / bessel_i0<T>(x);
 }
 
 // Wave-private pool of walk ids [next, end) claimed from a global queue in
@@ -197,7 +205,7 @@ __global__ __launch_bounds__(kBlock) void k_walks(WalkArgs a) {
   const T src_scale = SRC && a.f.kind == 3 ? source_scale<T>(a.f) : T(0);
   // screened walks (no source term) carry the product of their balls'
   // mean-value factors in acc_s, the first ball's excepted
-  const bool scr = !SRC && D == 3 && a.sigma > 0.0;
+  const bool scr = !SRC && a.sigma > 0.0;
   const T s_scr = scr ? (T)sqrt(a.sigma) : T(0);
   const SceneDev& S = a.S;
   T* U = (T*)a.U;
@@ -319,7 +327,7 @@ __global__ __launch_bounds__(kBlock) void k_walks(WalkArgs a) {
       } else if constexpr (SRC) {
         acc_s = fma(coef, srcv, acc_s);
       } else if (scr) {
-        acc_s *= screen_ball_weight3<T>(s_scr * d);
+        acc_s *= screen_ball_weight<T, D>(s_scr * d);
       }
 #pragma unroll
       for (int c = 0; c < D; ++c) p[c] = fma(d, nu[c], p[c]);
@@ -384,11 +392,12 @@ __device__ inline double sph_i1(double x) {
 // Boundary data at the exit points, in FP64.  With W = g(exit) + S:
 // U = W + u_src,  mode 0: D = w1 (W - c) + d_src,  mode 1: grad = gw (W - c) + g_src,
 // where c = g(xbar) is the control variate (0 when disabled).  Screened walks
-// (sigma > 0, 3D, no source) recorded the product of their later balls'
+// (sigma > 0, no source) recorded the product of their later balls'
 // mean-value factors in U: W = U g(exit), U = P(R0) W with the first ball's
-// factor P(x) = x / sinh x, x = s R0, and the weights w1, gw (written as
-// dim / R0 times the direction) rescaled to the screened ball gradient weight
-// s / i1(s R0); a pointwise walk that starts in the epsilon shell keeps g.
+// factor P(x) (1/I0(x) in 2D, x / sinh x in 3D, x = s R0), and the weights
+// w1, gw (written as dim / R0 times the direction) rescaled to the screened
+// ball gradient weight (s / I1(s R0) in 2D, s / i1(s R0) in 3D); a pointwise
+// walk that starts in the epsilon shell keeps g.
 // A wave finishes kFinishRun runs of 64 consecutive walks, lane l taking walk
 // l of each run, so that every load and store is coalesced; a lane evaluates
 // the control variate only when its start point changes.
@@ -400,7 +409,7 @@ __global__ __launch_bounds__(kBlock) void k_finish(FieldDev g, int cv, uint64_t 
                                                     double sigma, double eps, const double* R0) {
   const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const uint64_t id0 = wave * (64 * kFinishRun) + (threadIdx.x & 63);
-  const bool scr = D == 3 && sigma > 0.0;
+  const bool scr = sigma > 0.0;
   const double s = scr ? sqrt(sigma) : 0.0;
   int64_t i_cv = -1;
   double c = 0.0;
@@ -428,8 +437,15 @@ __global__ __launch_bounds__(kBlock) void k_finish(FieldDev g, int cv, uint64_t 
       } else {
         const double x = s * r0;
         w_est = su * gq;
-        u_est = (x < 1e-8 ? 1.0 : x / sinh(x)) * w_est;
-        ratio = s / sph_i1(x) * r0 / D;
+        if constexpr (D == 3) {
+          u_est = (x < 1e-8 ? 1.0 : x / sinh(x)) * w_est;
+          ratio = s / sph_i1(x) * r0 / D;
+        } else {
+          double i0, i1;
+          bessel_i01(x, i0, i1);
+          u_est = w_est / i0;
+          ratio = s / i1 * r0 / D;
+        }
       }
     }
     U[id] = (T)u_est;
@@ -504,7 +520,6 @@ int check_walk_params(const bvc_walk_params* p, int dim) {
   if (p->f.kind != 0 && p->f.kind != 1 && p->f.kind != 3)
     return fail(BVC_EUNSUPPORTED, "walk source terms are constants or Gaussian sums");
   if (!(p->sigma >= 0.0) || !std::isfinite(p->sigma)) return fail(BVC_EINVAL, "sigma must be finite and >= 0");
-  if (p->sigma > 0.0 && dim != 3) return fail(BVC_EUNSUPPORTED, "screened walks are built for 3D scenes");
   if (p->sigma > 0.0 && p->f.kind != 0)
     return fail(BVC_EUNSUPPORTED, "screened walks take no source term (f must be ZERO)");
   return BVC_OK;

@@ -1,4 +1,4 @@
-"""GPU parity of the screened Poisson path (Eq. 1 with sigma > 0, 3D;
+"""GPU parity of the screened Poisson path (Eq. 1 with sigma > 0, 2D and 3D;
 Appendix A.2) against the FP64 oracle, through the C-ABI (marked gpu).
 
 - Screened gather (u, grad u, sources): FP64 to 1e-11 of the sum of |terms|,
@@ -6,9 +6,9 @@ Appendix A.2) against the FP64 oracle, through the C-ABI (marked gpu).
 - Screened walks, FP64: cache walks (U, D) and pointwise walks (U, grad)
   walk by walk on the oracle's Philox streams (at least 99.9% within 1e-9);
   FP32: walk means against the FP64 walks on the same streams (z-test).
-- The pipeline on the screened sphere problem recovers exp(a.x).
-- Unsupported combinations (2D, a walk source, near field, clamp, batch,
-  clamping correction) are refused with an error.
+- The pipeline on the screened sphere and star problems recovers exp(a.x).
+- Unsupported combinations (a walk source, near field, clamp, clamping
+  correction) are refused with an error.
 """
 import sys
 
@@ -35,40 +35,42 @@ def B():
     return lib()
 
 
-def _plane():
-    a = np.array([1.0, 0.5, -0.7])
+def _plane(dim=3):
+    a = np.array([1.0, 0.5, -0.7])[:dim]
     return wl.exp_plane(1.0, a / np.linalg.norm(a) * np.sqrt(SIGMA))
 
 
+@pytest.mark.parametrize("dim", [2, 3])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_screened_gather_matches_oracle(B, orc, dtype):
+def test_screened_gather_matches_oracle(B, orc, dtype, dim):
     _bvc, pl = B
-    say(f"screened gather {dtype}")
-    rng = np.random.default_rng(21)
+    say(f"screened gather {dim}d {dtype}")
+    rng = np.random.default_rng(21 + dim)
     N, M, K = 1300, 700, 1537
-    th = rng.normal(0, 1, (N, 3))
+    th = rng.normal(0, 1, (N, dim))
     cy = th / np.linalg.norm(th, axis=1, keepdims=True) * 1.01
     cn = cy / np.linalg.norm(cy, axis=1, keepdims=True)
     a, b = rng.normal(0, 1, N) / N, rng.normal(0, 1, N) / N
-    sy, sw = rng.uniform(-0.7, 0.7, (M, 3)), rng.normal(0, 1, M) / M
-    v = rng.normal(0, 1, (K, 3))
-    ex = v / np.linalg.norm(v, axis=1, keepdims=True) * (0.95 * rng.random(K) ** (1 / 3))[:, None]
+    sy, sw = rng.uniform(-0.7, 0.7, (M, dim)), rng.normal(0, 1, M) / M
+    v = rng.normal(0, 1, (K, dim))
+    ex = v / np.linalg.norm(v, axis=1, keepdims=True) * (0.95 * rng.random(K) ** (1 / dim))[:, None]
     T = torch.float64 if dtype == "f64" else torch.float32
     code = _bvc.F64 if dtype == "f64" else _bvc.F32
     dev = lambda x: torch.from_numpy(np.ascontiguousarray(x.T if x.ndim == 2 else x)).to("cuda", T)
     cache = dict(n=N, dtype=code, x=dev(cy), nrm=dev(cn), a=dev(a), b=dev(b))
     src = dict(n=M, dtype=code, y=dev(sy), s=dev(sw))
     u = torch.empty(K, dtype=T, device="cuda")
-    g = torch.empty(3, K, dtype=T, device="cuda")
+    g = torch.empty(dim, K, dtype=T, device="cuda")
     u2 = torch.empty(K, dtype=T, device="cuda")
-    _bvc.bvc_gather_grad(3, cache, src, K, dev(ex), u, g, sigma=SIGMA)
-    _bvc.bvc_gather_u(3, cache, src, K, dev(ex), u2, sigma=SIGMA)
+    _bvc.bvc_gather_grad(dim, cache, src, K, dev(ex), u, g, sigma=SIGMA)
+    _bvc.bvc_gather_u(dim, cache, src, K, dev(ex), u2, sigma=SIGMA)
     torch.cuda.synchronize()
     r64 = lambda t: t.double().cpu().numpy()
     cy_r, cn_r, a_r, b_r = to_np_aos(cache["x"]), to_np_aos(cache["nrm"]), r64(cache["a"]), r64(cache["b"])
     ex_r, sy_r, sw_r = to_np_aos(dev(ex)), to_np_aos(src["y"]), r64(src["s"])
-    uo, go, cond = orc.gather_sigma(3, SIGMA, ex_r, cy_r, cn_r, a_r, b_r, sy_r, sw_r, with_grad=True, with_cond=True)
-    up = orc.gather(3, ex_r, cy_r, cn_r, a_r, b_r, sy_r, sw_r, with_grad=False)
+    uo, go, cond = orc.gather_sigma(dim, SIGMA, ex_r, cy_r, cn_r, a_r, b_r, sy_r, sw_r, with_grad=True,
+                                    with_cond=True)
+    up = orc.gather(dim, ex_r, cy_r, cn_r, a_r, b_r, sy_r, sw_r, with_grad=False)
     assert np.mean(np.abs(uo - up)) > 1e-3 * np.mean(cond)  # screening changes the result
     ug, gg = u.double().cpu().numpy(), to_np_aos(g)
     if dtype == "f64":
@@ -82,22 +84,28 @@ def test_screened_gather_matches_oracle(B, orc, dtype):
         zmax = np.linalg.norm(zall, axis=1).max()
         tol = uu * cond * (300 + 4 * (np.linalg.norm(ex_r, axis=1) + zmax) / rmin) + uu * np.abs(uo)
         assert np.all(np.abs(ug - uo) <= tol), np.max(np.abs(ug - uo) / tol)
-        gsum = (4 * np.abs(a_r).sum() / rmin**3 + (np.abs(b_r).sum() + np.abs(sw_r).sum()) / rmin**2) / (4 * np.pi)
+        if dim == 3:
+            gsum = (4 * np.abs(a_r).sum() / rmin**3 + (np.abs(b_r).sum() + np.abs(sw_r).sum()) / rmin**2) / (4 * np.pi)
+        else:
+            lg = np.abs(np.log(np.sqrt(SIGMA) * rmin)) + 1
+            gsum = (3 * np.abs(a_r).sum() / rmin**2 + SIGMA * lg * np.abs(a_r).sum() / rmin
+                    + (np.abs(b_r).sum() + np.abs(sw_r).sum()) / rmin) / (2 * np.pi)
         gtol = uu * gsum * (300 + 4 * (np.linalg.norm(ex_r, axis=1) + zmax) / rmin) + uu * np.abs(go).max(1)
         assert np.all(np.abs(gg - go).max(1) <= gtol)
 
 
-def _sphere_case(pl):
-    scene = wl.displaced_icosphere(3, 31)
+def _sphere_case(pl, dim=3):
+    scene = wl.displaced_icosphere(3, 31) if dim == 3 else wl.star_polygon(512, 11, jitter="radial", sigma=0.01)
     sc = pl.Scene(scene)
-    g = _plane()
+    g = _plane(dim)
     return scene, sc, g
 
 
-def test_screened_walks_fp64_walk_by_walk(B, orc):
+@pytest.mark.parametrize("dim", [2, 3])
+def test_screened_walks_fp64_walk_by_walk(B, orc, dim):
     _bvc, pl = B
-    say("screened walks fp64")
-    scene, sc, g = _sphere_case(pl)
+    say(f"screened walks fp64 {dim}d")
+    scene, sc, g = _sphere_case(pl, dim)
     gd = pl.DeviceField(g)
     eps, l, W, seed = 4e-3, 2e-2, 8, 77
     cache = pl.sample_cache(sc, 600, l, 1, 5, 0)
@@ -114,7 +122,7 @@ def test_screened_walks_fp64_walk_by_walk(B, orc):
     assert okU.mean() >= 0.999 and okD.mean() >= 0.999
     # pointwise walks (u and grad), some starting inside the epsilon shell
     rng = np.random.default_rng(3)
-    v = rng.normal(0, 1, (150, 3))
+    v = rng.normal(0, 1, (150, dim))
     x = v / np.linalg.norm(v, axis=1, keepdims=True) * rng.uniform(0.2, 0.97, 150)[:, None]
     d0, _, _ = osc.closest(x)
     x = x[osc.inside(x) != 0]
@@ -130,10 +138,11 @@ def test_screened_walks_fp64_walk_by_walk(B, orc):
     assert oku.mean() >= 0.99 and okg.mean() >= 0.99
 
 
-def test_screened_walks_fp32_statistical(B, orc):
+@pytest.mark.parametrize("dim", [2, 3])
+def test_screened_walks_fp32_statistical(B, orc, dim):
     _bvc, pl = B
-    say("screened walks fp32")
-    scene, sc, g = _sphere_case(pl)
+    say(f"screened walks fp32 {dim}d")
+    scene, sc, g = _sphere_case(pl, dim)
     gd = pl.DeviceField(g)
     eps, l, W, seed = 4e-3, 2e-2, 64, 78
     cache = pl.sample_cache(sc, 150, l, 1, 6, 0)
@@ -184,14 +193,39 @@ def test_pipeline_screened_sphere(B):
     assert np.sqrt(np.mean(gerr[m] ** 2)) < 0.04 * gn
 
 
+def test_pipeline_screened_star(B):
+    """The whole 2D step on the screened star problem (FP32) recovers the
+    plane wave exp(a.x) at interior points to a few percent of its RMS."""
+    _bvc, pl = B
+    say("pipeline screened star")
+    prob = wl.problem_c2_screened(grid=256)
+    prep = pl.Prepared(prob, dtype="f32")
+    sol = pl.solve(prep, with_grad=True)
+    torch.cuda.synchronize()
+    idx = prep.idx_int[: prep.n_int].cpu().numpy()
+    pts = prob.eval_x[idx]
+    truth = wl.field_value(prob.truth, pts)
+    u = sol.u_int[: prep.n_int].double().cpu().numpy()
+    d = prep.dist[prep.idx_int[: prep.n_int].long()].cpu().numpy()
+    far = d > 0.05
+    rms = np.sqrt(np.mean(truth**2))
+    err = np.sqrt(np.mean((u[far] - truth[far]) ** 2))
+    say(f"  interior {prep.n_int}: rmse {err:.4g} vs rms {rms:.4g}")
+    assert err < 0.02 * rms
+    gt = np.array(prob.truth.param[1:3])[None] * truth[:, None]
+    gerr = np.sqrt(np.sum((to_np_aos(sol.g_int, prep.n_int) - gt) ** 2, 1))
+    gn = np.sqrt(np.mean(np.sum(gt**2, 1)))
+    m = d > 0.2
+    say(f"  grad rmse (d > 0.2): {np.sqrt(np.mean(gerr[m] ** 2)) / gn:.4f} of rms, {m.sum()} points")
+    assert np.sqrt(np.mean(gerr[m] ** 2)) < 0.04 * gn
+    ub = sol.u_band[: prep.n_band].double().cpu().numpy()
+    tb = wl.field_value(prob.truth, prob.eval_x[prep.idx_band[: prep.n_band].cpu().numpy()])
+    assert np.sqrt(np.mean((ub - tb) ** 2)) < 0.02 * rms
+
+
 def test_screened_unsupported_combinations(B):
     _bvc, pl = B
     say("screened unsupported combinations")
-    sc2 = pl.Scene(wl.circle_polygon(64))
-    g2 = pl.DeviceField(wl.exp_plane(1.0, [2.0, 0.0]))
-    cache2 = pl.sample_cache(sc2, 100, 0.02, 1, 1, 0)
-    with pytest.raises(_bvc.BVCError):
-        pl.cache_walks(sc2, cache2, pl.walk_params(1e-3, 4, 1, g2, None, "f64", sigma=1.0), "f64")
     scene, sc, g = _sphere_case(pl)
     gd = pl.DeviceField(g)
     cache = pl.sample_cache(sc, 100, 2e-2, 1, 1, 0)
@@ -205,9 +239,6 @@ def test_screened_unsupported_combinations(B):
     u = torch.empty(4, dtype=T, device="cuda")
     with pytest.raises(_bvc.BVCError):
         _bvc.bvc_gather_u(3, cv, None, 4, torch.zeros(3, 4, dtype=T, device="cuda"), u, sigma=1.0, clamp=2.0)
-    cv2 = dict(cv, x=torch.ones(2, 4, dtype=T, device="cuda"), nrm=torch.ones(2, 4, dtype=T, device="cuda"))
-    with pytest.raises(_bvc.BVCError):
-        _bvc.bvc_gather_u(2, cv2, None, 4, torch.zeros(2, 4, dtype=T, device="cuda"), u, sigma=1.0)
     wp = pl.walk_params(4e-3, 1, 1, gd, None, "f64", sigma=1.0)
     ws = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
     cnt = torch.zeros(6, dtype=torch.int64, device="cuda")

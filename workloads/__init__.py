@@ -502,6 +502,20 @@ def problem_c3_screened(sigma: float = 4.0, n_eval_box: int = 2_320_000) -> Prob
                    seed_sources=p.seed_sources, extra=p.extra, sigma=sigma)
 
 
+def problem_c2_screened(sigma: float = 4.0, grid: int = 1024) -> Problem:
+    """The 4096-segment star of the 2D Poisson workload with the screened
+    equation Lap u = sigma u (Eq. 1, f = 0) and the plane wave u = exp(a.x),
+    |a|^2 = sigma, as boundary data and closed-form solution."""
+    p = problem_c2(grid=grid)
+    rng = np.random.default_rng(seed(2, 8))
+    a = rng.normal(0, 1, 2)
+    a *= math.sqrt(sigma) / np.linalg.norm(a)
+    g = exp_plane(1.0, a)
+    return Problem("c2s_star4096_screened", p.scene, g, Field(), p.n_cache, p.n_walks, p.eps, p.offset, 0,
+                   p.eval_x, g, sides=p.sides, precision="f32", seed_walks=seed(2, 9), seed_cache=p.seed_cache,
+                   seed_sources=p.seed_sources, extra=p.extra, sigma=sigma)
+
+
 def c4_fields(n_fields: int = 64, lmax: int = 8) -> np.ndarray:
     """Coefficient matrix (n_fields, (lmax+1)^2) of the batched 3D workload."""
     rng = np.random.default_rng(seed(4, 2))
