@@ -564,6 +564,52 @@ __device__ inline int winding_number(const SceneDev& S, const double* x) {
   return wn;
 }
 
+// The same winding number with the BVH: a segment can change it only when
+// its y-range holds x[1] (the two comparisons above are exact on the same
+// doubles), so children whose FP64 box misses the line y = x[1] are skipped
+// and the result equals the full sum.  stk: LDS stack of depth + 1 entries
+// at stride `stride`.
+__device__ inline int winding_number_bvh(const SceneDev& S, const double* x, uint32_t* stk, int stride) {
+  const double* pr = S.prim64;
+  const double y = x[1];
+  int wn = 0, sp = 0, node = 0;
+  while (true) {
+    const double* b = S.box64 + (size_t)node * 8;  // child 0: lo(2) hi(2), child 1: lo(2) hi(2)
+    const int2 ch = S.child[node];
+    const int cs[2] = {ch.x, ch.y};
+    int next = -1;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      if (!(b[4 * s + 1] <= y && b[4 * s + 3] >= y)) continue;
+      const int c = cs[s];
+      if (c < 0) {
+        const int s0 = leaf_start(c), m = leaf_count(c);
+        for (int i = s0; i < s0 + m; ++i) {
+          const double ax = pr[4 * i], ay = pr[4 * i + 1], bx = pr[4 * i + 2], by = pr[4 * i + 3];
+          const double cr = (bx - ax) * (y - ay) - (x[0] - ax) * (by - ay);
+          if (ay <= y) {
+            if (by > y && cr > 0) ++wn;
+          } else if (by <= y && cr < 0) {
+            --wn;
+          }
+        }
+      } else if (next < 0) {
+        next = c;
+      } else {
+        stk[sp * stride] = (uint32_t)c;
+        ++sp;
+      }
+    }
+    if (next < 0 && sp > 0) {
+      --sp;
+      next = (int)stk[sp * stride];
+    }
+    if (next < 0) break;
+    node = next;
+  }
+  return wn;
+}
+
 // 3D: x is inside when (x - q) . N < 0 for the pseudonormal N of the feature
 // of original triangle t that holds the closest point q.
 __device__ inline bool inside_3d(const SceneDev& S, const double* x, int t) {
@@ -585,6 +631,40 @@ __device__ inline bool inside_3d(const SceneDev& S, const double* x, int t) {
 // ---------------------------------------------------------------------------
 // Ein(z) = int_0^z (1 - e^-t)/t dt: alternating power series below 4, else
 // E1(z) + ln z + gamma with E1 from its continued fraction (modified Lentz).
+// Compile-time tables for the boundary-data fields: reciprocals 1/k and the
+// normalisations sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!) (times sqrt 2 for m > 0) of
+// the real solid harmonics up to degree 16, so that the per-walk evaluation
+// needs no FP64 division or square root.
+constexpr double cx_sqrt(double a) {
+  if (!(a > 0.0)) return 0.0;
+  double x = a > 1.0 ? a : 1.0;
+  for (int i = 0; i < 200; ++i) {
+    const double y = 0.5 * (x + a / x);
+    if (y >= x) break;  // Newton from above decreases until it stalls
+    x = y;
+  }
+  return x;
+}
+
+struct FieldTables {
+  static constexpr int kMaxL = 16;
+  double inv[81];
+  double sh_norm[(kMaxL + 1) * (kMaxL + 1)];
+  constexpr FieldTables() : inv(), sh_norm() {
+    inv[0] = 0.0;
+    for (int k = 1; k < 81; ++k) inv[k] = 1.0 / k;
+    for (int l = 0; l <= kMaxL; ++l)
+      for (int m = 0; m <= l; ++m) {
+        double ratio = 1.0;  // (l-m)!/(l+m)!
+        for (int i = l - m + 1; i <= l + m; ++i) ratio /= i;
+        double nrm = cx_sqrt((2 * l + 1) / (4.0 * kPi) * ratio);
+        if (m > 0) nrm *= 1.4142135623730950488;
+        sh_norm[l * l + l + m] = nrm;
+      }
+  }
+};
+__device__ constexpr FieldTables kFieldTables{};
+
 __device__ inline double ein(double z) {
   if (z <= 0.0) return 0.0;
   // beyond 40, E1(z) < e^-40/40 is below half an ulp of ln z + gamma
@@ -592,8 +672,9 @@ __device__ inline double ein(double z) {
   if (z < 4.0) {
     double term = z, sum = z;  // term_k = (-1)^{k+1} z^k / k!
     for (int k = 2; k < 80; ++k) {
-      term *= -z / k;
-      const double add = term / k;
+      const double ik = kFieldTables.inv[k];
+      term *= -z * ik;
+      const double add = term * ik;
       sum += add;
       if (fabs(add) < 1e-17 * fabs(sum)) break;
     }
@@ -644,13 +725,10 @@ __device__ inline double solid_harmonics(const double* coef, int L, const double
       double q;
       if (l == m) q = dfact;
       else if (l == m + 1) q = (2 * m + 1) * x[2] * dfact;
-      else q = ((2 * l - 1) * x[2] * qm1 - (l + m - 1) * r2 * qm2) / (l - m);
+      else q = ((2 * l - 1) * x[2] * qm1 - (l + m - 1) * r2 * qm2) * kFieldTables.inv[l - m];
       qm2 = qm1;
       qm1 = q;
-      double ratio = 1.0;  // (l-m)!/(l+m)!
-      for (int i = l - m + 1; i <= l + m; ++i) ratio /= i;
-      double nrm = sqrt((2 * l + 1) / (4.0 * kPi) * ratio);
-      if (m > 0) nrm *= 1.4142135623730950488;
+      const double nrm = kFieldTables.sh_norm[l * l + l + m];
       const int ic = l * l + l + m, is = l * l + l - m;
       if (only >= 0) {
         if (only == ic) return nrm * q * cm;
@@ -740,6 +818,103 @@ __device__ inline double field_value(const FieldDev& F, int dim, const double* x
     }
   }
   return 0.0;
+}
+
+// FP32 evaluation of the closed-form kinds (0-4, 7, 8) for FP32 walks, whose
+// Monte Carlo error is orders of magnitude above FP32 rounding; the other
+// kinds, and every FP64 walk, use the FP64 field_value.
+__device__ inline float ein_f32(float z) {
+  if (z <= 0.0f) return 0.0f;
+  if (z > 16.0f) return logf(z) + 0.5772156649f;  // E1(z) < e^-16/16, below the FP32 ulp of the rest
+  if (z < 4.0f) {
+    float term = z, sum = z;
+    for (int k = 2; k < 40; ++k) {
+      const float ik = (float)kFieldTables.inv[k];
+      term *= -z * ik;
+      const float add = term * ik;
+      sum += add;
+      if (fabsf(add) < 1e-8f * fabsf(sum)) break;
+    }
+    return sum;
+  }
+  float b = z + 1.0f, c = 1e30f, d = 1.0f / b, h = d;
+  for (int i = 1; i < 100; ++i) {
+    const float an = -(float)i * (float)i;
+    b += 2.0f;
+    d = 1.0f / fmaf(an, d, b);
+    c = b + an / c;
+    const float del = c * d;
+    h *= del;
+    if (fabsf(del - 1.0f) < 1e-7f) break;
+  }
+  return h * expf(-z) + logf(z) + 0.5772156649f;
+}
+
+__device__ inline float harmonic2d_f32(float k, float alpha, float beta, const float* x) {
+  float re = 1.0f, im = 0.0f;
+  const int kk = (int)k;
+  for (int i = 0; i < kk; ++i) {
+    const float r2 = re * x[0] - im * x[1];
+    im = re * x[1] + im * x[0];
+    re = r2;
+  }
+  return alpha * re + beta * expf(x[0]) * cosf(x[1]);
+}
+
+__device__ inline double field_value_f32(const FieldDev& F, int dim, const float* x) {
+  const double* p = F.param;
+  switch (F.kind) {
+    case 0:
+      return 0.0;
+    case 1:
+      return p[0];
+    case 2:
+      return (double)harmonic2d_f32((float)p[0], (float)p[1], (float)p[2], x);
+    case 3: {
+      const int ng = F.n_coef / (1 + dim);
+      const float inv = (float)(1.0 / (2.0 * p[0] * p[0]));
+      float sum = 0.0f;
+      for (int k = 0; k < ng; ++k) {
+        const double* c = F.coef + k * (1 + dim);
+        float r2 = 0.0f;
+        for (int a = 0; a < dim; ++a) {
+          const float t = x[a] - (float)c[1 + a];
+          r2 = fmaf(t, t, r2);
+        }
+        sum = fmaf((float)c[0], expf(-r2 * inv), sum);
+      }
+      return (double)sum;
+    }
+    case 4: {
+      const int ng = F.n_coef / 3;
+      const float s2 = (float)(p[0] * p[0]), inv = (float)(1.0 / (2.0 * p[0] * p[0]));
+      float sum = 0.0f;
+      for (int k = 0; k < ng; ++k) {
+        const double* c = F.coef + 3 * k;
+        const float dx = x[0] - (float)c[1], dy = x[1] - (float)c[2];
+        sum = fmaf((float)c[0] * s2 * 0.5f, ein_f32(fmaf(dx, dx, dy * dy) * inv), sum);
+      }
+      return (double)(sum + harmonic2d_f32((float)p[1], (float)p[2], (float)p[3], x));
+    }
+    case 7: {
+      float r2 = 0.0f;
+      for (int a = 0; a < dim; ++a) {
+        const float t = x[a] - (float)p[1 + a];
+        r2 = fmaf(t, t, r2);
+      }
+      return dim == 2 ? p[0] * 0.5 * (double)logf(r2) : p[0] * (double)rsqrtf(r2);
+    }
+    case 8: {
+      float e = 0.0f;
+      for (int a = 0; a < dim; ++a) e = fmaf((float)p[1 + a], x[a], e);
+      return p[0] * (double)expf(e);
+    }
+    default: {
+      double xd[3] = {0.0, 0.0, 0.0};
+      for (int a = 0; a < dim; ++a) xd[a] = (double)x[a];
+      return field_value(F, dim, xd);
+    }
+  }
 }
 
 __device__ inline double basis_value(const FieldDev& F, int dim, int m, const double* x) {

@@ -132,8 +132,8 @@ __device__ void candidate_point(const SceneDev& S, int e, double r, double v, do
 }
 
 template <int D>
-__device__ bool inside_point(const SceneDev& S, const double* x, int leaf_prim) {
-  if constexpr (D == 2) return winding_number(S, x) != 0;
+__device__ bool inside_point(const SceneDev& S, const double* x, int leaf_prim, uint32_t* stk, int stride) {
+  if constexpr (D == 2) return winding_number_bvh(S, x, stk, stride) != 0;
   else return inside_3d(S, x, S.prim_id[leaf_prim]);
 }
 
@@ -160,7 +160,7 @@ __global__ __launch_bounds__(kBlock) void k_sample_cache(SceneDev S, int64_t n, 
   double q[D];
   int hint = -1;
   const double d = sqrt(closest_point<double, D>(S, xc, hint, q, lds + threadIdx.x, blockDim.x));
-  const bool ok = d >= l * (1 - 1e-9) && inside_point<D>(S, xc, hint);
+  const bool ok = d >= l * (1 - 1e-9) && inside_point<D>(S, xc, hint, lds + threadIdx.x, blockDim.x);
   acc[k] = ok ? 1 : 0;
   R0[k] = d;
   w[k] = M / (double)n;
@@ -227,7 +227,7 @@ __global__ __launch_bounds__(kBlock) void k_sample_roi(SceneDev Sd, SceneDev Sr,
   double q[D];
   int hint = -1;
   const double d = sqrt(closest_point<double, D>(Sd, xc, hint, q, lds + threadIdx.x, blockDim.x));
-  acc[k] = (d > 0.0 && inside_point<D>(Sd, xc, hint)) ? 1 : 0;
+  acc[k] = (d > 0.0 && inside_point<D>(Sd, xc, hint, lds + threadIdx.x, blockDim.x)) ? 1 : 0;
   R0[k] = d;
   w[k] = M / (double)n;
 #pragma unroll
@@ -272,7 +272,7 @@ __global__ __launch_bounds__(kBlock) void k_sample_mixed(SceneDev Sf, SceneDev S
     const double d = sqrt(closest_point<double, 2>(Sd, xc, hint, q, lds + threadIdx.x, blockDim.x));
     nc[0] = (q[0] - xc[0]) / d;
     nc[1] = (q[1] - xc[1]) / d;
-    ok = fabs(d - l) <= 1e-9 * l && winding_number(Sf, xc) != 0;
+    ok = fabs(d - l) <= 1e-9 * l && winding_number_bvh(Sf, xc, lds + threadIdx.x, blockDim.x) != 0;
     ty = 1;
   } else {
     const double t2 = target - MD;
@@ -334,7 +334,7 @@ __global__ __launch_bounds__(kBlock) void k_sample_sources(SceneDev S, FieldDev 
   double q[D];
   int hint = -1;
   const double d = sqrt(closest_point<double, D>(S, yj, hint, q, lds + threadIdx.x, blockDim.x));
-  const bool in = inside_point<D>(S, yj, hint) && d > l;
+  const bool in = inside_point<D>(S, yj, hint, lds + threadIdx.x, blockDim.x) && d > l;
   s[j] = in ? vol / (double)M * field_value(f, D, yj) : 0.0;
 }
 
@@ -350,7 +350,7 @@ __global__ __launch_bounds__(kBlock) void k_classify(SceneDev S, int64_t n, cons
   double q[D];
   int hint = -1;
   const double d = sqrt(closest_point<double, D>(S, xk, hint, q, lds + threadIdx.x, blockDim.x));
-  const bool in = inside_point<D>(S, xk, hint);
+  const bool in = inside_point<D>(S, xk, hint, lds + threadIdx.x, blockDim.x);
   cls[k] = !in ? 0 : (d > l ? 1 : 2);
   if (dist) dist[k] = d;
 }
@@ -367,7 +367,7 @@ __global__ __launch_bounds__(kBlock) void k_classify_mixed(SceneDev Sf, SceneDev
   double q[2];
   int hint = -1;
   const double d = sqrt(closest_point<double, 2>(Sd, xk, hint, q, lds + threadIdx.x, blockDim.x));
-  const bool in = winding_number(Sf, xk) != 0;
+  const bool in = winding_number_bvh(Sf, xk, lds + threadIdx.x, blockDim.x) != 0;
   cls[k] = !in ? 0 : (d > l ? 1 : 2);
   if (dist) dist[k] = d;
 }
@@ -641,7 +641,7 @@ int bvc_classify_mixed(bvc_scene full, bvc_scene dir, int64_t n, const double* x
   if (!x || !cls) return fail(BVC_EINVAL, "null argument");
   hipStream_t st = (hipStream_t)stream;
   const int blocks = (int)((n + kBlock - 1) / kBlock);
-  const size_t lds = stack_bytes(dir->h, kBlock);
+  const size_t lds = std::max(stack_bytes(full->h, kBlock), stack_bytes(dir->h, kBlock));
   hipLaunchKernelGGL(k_classify_mixed, dim3(blocks), dim3(kBlock), lds, st, full->h.view(), dir->h.view(), n, x, l,
                      cls, dist);
   return check_hip(hipGetLastError(), "classify_mixed launch");

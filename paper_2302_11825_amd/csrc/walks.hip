@@ -389,7 +389,9 @@ __device__ inline double sph_i1(double x) {
   return (x * cosh(x) - sinh(x)) / (x * x);
 }
 
-// Boundary data at the exit points, in FP64.  With W = g(exit) + S:
+// Boundary data at the exit points (FP32 walks evaluate the closed-form
+// kinds of g in FP32, FP64 walks every kind in FP64), combined in FP64.
+// With W = g(exit) + S:
 // U = W + u_src,  mode 0: D = w1 (W - c) + d_src,  mode 1: grad = gw (W - c) + g_src,
 // where c = g(xbar) is the control variate (0 when disabled).  Screened walks
 // (sigma > 0, no source) recorded the product of their later balls'
@@ -424,10 +426,18 @@ __global__ __launch_bounds__(kBlock) void k_finish(FieldDev g, int cv, uint64_t 
       c = field_value(g, D, xb);
       i_cv = i;
     }
-    double q[D];
+    double gq;
+    if constexpr (sizeof(T) == 4) {
+      float q[D];
 #pragma unroll
-    for (int e = 0; e < D; ++e) q[e] = (double)EX[(size_t)e * total + id];
-    const double gq = field_value(g, D, q);
+      for (int e = 0; e < D; ++e) q[e] = EX[(size_t)e * total + id];
+      gq = field_value_f32(g, D, q);
+    } else {
+      double q[D];
+#pragma unroll
+      for (int e = 0; e < D; ++e) q[e] = (double)EX[(size_t)e * total + id];
+      gq = field_value(g, D, q);
+    }
     const double su = (double)U[id];
     double w_est = gq + su, u_est = gq + su, ratio = 1.0;
     if (scr) {
