@@ -147,7 +147,10 @@ int bvc_cache_measure(bvc_scene scene, double l, int32_t sides, double* measure)
  * and it lies inside (2D: nonzero winding number; 3D: pseudonormal sign).
  * Outputs (FP64 device, [dim][n] or [n]): x, unit outward normal of the
  * region {d > l} (towards the closest boundary point), weight w = measure/n,
- * closest boundary point xbar, distance R0, accept flag (int32 0/1). */
+ * xbar, distance R0, accept flag (int32 0/1).  xbar is the closest boundary
+ * point q seen from the candidate, q + 1e-3 (x - q): the control variate
+ * c = g(xbar) of its walks reads the data on the candidate's own side of a
+ * boundary with double-sided conditions (Appendix B). */
 int bvc_sample_cache(bvc_scene scene, int64_t n, double l, int32_t sides, uint64_t seed,
                      uint32_t batch, double* x, double* nrm, double* w, double* xbar, double* R0,
                      int32_t* accept, void* stream);
@@ -159,6 +162,7 @@ int bvc_sample_cache(bvc_scene scene, int64_t n, double l, int32_t sides, uint64
  * id k, tag 6; the second places it inside a triangle), with the primitive's
  * unit outward normal (CCW segments, outward-wound triangles) and weight
  * |dR|/n.  R0 and xbar: distance and closest point on the domain boundary
+ * (xbar seen from the sample, as in bvc_sample_cache)
  * `dom` (where the walks run); accept = 1 when the point lies strictly inside
  * the domain.  Outputs as bvc_sample_cache.  Evaluation points inside R
  * (bvc_classify on `roi` with l = 0) are then gathered from this cache; the
@@ -177,7 +181,8 @@ int bvc_sample_roi(bvc_scene dom, bvc_scene roi, int64_t n, uint64_t seed, uint3
  * of `dir` (as bvc_sample_cache with sides 1) and the segments of `neu`.
  * Outputs (FP64 device, [2][n] or [n]): x; nrm = towards the closest
  * Dirichlet point on offset points, the segment's outward normal on Neumann
- * points; w = total candidate measure / n; xbar = closest Dirichlet point;
+ * points; w = total candidate measure / n; xbar = closest Dirichlet point q
+ * seen from the sample, q + 1e-3 (x - q);
  * R0 = distance to `full` (the first ball of a cache walk); kind (int32 [n]:
  * 0 rejected, 1 accepted offset point (distance l within 1e-9 relative and
  * inside `full`), 2 accepted Neumann point (farther than l)).  The three

@@ -67,6 +67,14 @@ void orc_uniform_pair(uint64_t seed, uint32_t block, uint32_t id, uint32_t batch
 /* ======================================================================== */
 /* Scene, BVH and closest points                                             */
 /* ======================================================================== */
+/* The samplers report, as a cache point's xbar, its closest boundary point
+ * seen from the point: xbar = closest + XBAR_SIDE (x - closest).  The control
+ * variate of its walks, c = g(xbar), then reads the data on the point's own
+ * side of a boundary with double-sided conditions (Appendix B); for
+ * continuous data it moves c by about 1e-3 l |grad g|, which a control
+ * variate may take (any constant keeps the estimate unbiased). */
+#define XBAR_SIDE 1e-3
+
 typedef struct {
   double lo[3], hi[3];
   int64_t left, right; /* children (internal) or -1 */
@@ -1031,7 +1039,7 @@ int64_t orc_sample_cache(const orc_scene* s, int64_t n, double l, int sides, uin
     R0[k] = dist;
     w[k] = M / (double)n;
     for (int a = 0; a < d; ++a) {
-      xbar[k * d + a] = xb[a];
+      xbar[k * d + a] = xb[a] + XBAR_SIDE * (xk[a] - xb[a]);
       nrm[k * d + a] = (xb[a] - xk[a]) / dist;
     }
   }
@@ -1123,7 +1131,7 @@ int64_t orc_sample_roi(const orc_scene* dom, const orc_scene* roi, int64_t n, ui
     n_acc += ok;
     R0[k] = dist;
     w[k] = M / (double)n;
-    for (int a = 0; a < d; ++a) xbar[k * d + a] = xb[a];
+    for (int a = 0; a < d; ++a) xbar[k * d + a] = xb[a] + XBAR_SIDE * (xk[a] - xb[a]);
   }
   free(cdf);
   return n_acc;
@@ -1218,6 +1226,16 @@ void orc_sample_ball_source(uint64_t seed, uint32_t k, uint32_t id, uint32_t bat
 /* Radius fraction of the 2D gradient source sample: density (3/2)(1 - s^2). */
 double orc_grad_radius(double u) { return 2 * sin(asin(u) / 3); }
 
+/* Where a walk that stops at pos, at distance d from its closest boundary
+ * point pb, reads the boundary data: pb approached from the walk's side by
+ * 1e-3 eps.  Data that differ on the two sides of a boundary curve
+ * (double-sided conditions, Appendix B) are thus read on the side the walk
+ * reached; continuous data change by about 1e-3 eps |grad g|. */
+static void read_point(int dim, const double* pos, const double* pb, double d, double eps, double* e) {
+  const double t = d > 0 ? 1e-3 * eps / d : 0.0;
+  for (int a = 0; a < dim; ++a) e[a] = pb[a] + t * (pos[a] - pb[a]);
+}
+
 void orc_walk(const orc_scene* s, const orc_field* g, const orc_field* f,
               const orc_walk_params* p, int mode, const double* x, const double* n, double R0,
               const double* xbar, uint32_t id, double* U, double* grad, double* exit_pt,
@@ -1228,10 +1246,12 @@ void orc_walk(const orc_scene* s, const orc_field* g, const orc_field* f,
   *capped = 0;
   if (mode == 1 && R0 < p->eps) {
     /* the evaluation point already lies in the epsilon shell */
-    *U = orc_field_eval(g, dim, xbar);
+    double e[3] = {0, 0, 0};
+    read_point(dim, x, xbar, R0, p->eps, e);
+    *U = orc_field_eval(g, dim, e);
     for (int a = 0; a < dim; ++a) {
       grad[a] = 0;
-      exit_pt[a] = xbar[a];
+      exit_pt[a] = e[a];
     }
     *w1 = 0;
     *steps = 0;
@@ -1269,13 +1289,12 @@ void orc_walk(const orc_scene* s, const orc_field* g, const orc_field* f,
   for (k = 1;; ++k) {
     double d;
     orc_closest(s, pos, 0, &d, pb, NULL);
-    if (d < p->eps) {
+    if (d < p->eps || k >= p->max_steps) {
+      *capped = !(d < p->eps);
+      double e[3] = {0, 0, 0};
+      read_point(dim, pos, pb, d, p->eps, e);
+      for (int a = 0; a < dim; ++a) pb[a] = e[a];
       W = screened ? thr * orc_field_eval(g, dim, pb) : orc_field_eval(g, dim, pb) + S;
-      break;
-    }
-    if (k >= p->max_steps) {
-      W = screened ? thr * orc_field_eval(g, dim, pb) : orc_field_eval(g, dim, pb) + S;
-      *capped = 1;
       break;
     }
     if (screened) thr *= orc_screen_ball_weight(dim, p->sigma, d);
@@ -1703,7 +1722,9 @@ static void wost_walk(const orc_scene* dir, const orc_scene* neu, const neu_link
     orc_closest(dir, pos, 0, &dD, qD, NULL);
     if (dD < p->eps || k >= p->max_steps) {
       *capped = !(dD < p->eps);
-      W = orc_field_eval(g, 2, qD);
+      double e[2];
+      read_point(2, pos, qD, dD, p->eps, e);
+      W = orc_field_eval(g, 2, e);
       break;
     }
     double R = fmax(fmin(dD, silhouette_distance(neu, L, pos)), p->eps);
@@ -1846,8 +1867,8 @@ int64_t orc_sample_mixed(const orc_scene* full, const orc_scene* dir, const orc_
     double dF, xf[3];
     orc_closest(full, xk, 0, &dF, xf, NULL);
     R0[k] = dF;
-    xbar[2 * k] = xb[0];
-    xbar[2 * k + 1] = xb[1];
+    xbar[2 * k] = xb[0] + XBAR_SIDE * (xk[0] - xb[0]);
+    xbar[2 * k + 1] = xb[1] + XBAR_SIDE * (xk[1] - xb[1]);
     w[k] = M / (double)n;
     accept[k] = ok;
     n_acc += ok;

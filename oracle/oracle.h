@@ -106,8 +106,11 @@ void orc_greens(int dim, const double* x, const double* y, const double* ny, dou
 /* --- Cache sampling (Section 3.2 offset boundary, Section 4 CDF sampling) -- */
 /* Draws n candidates on the offset boundary at distance l; writes per
  * candidate the point, unit outward normal of the region {d > l}, weight
- * (total candidate measure / n), closest boundary point, distance and an
- * accept flag.  sides: 1 = inward offsets only, 2 = both sides (2D).
+ * (total candidate measure / n), closest boundary point q seen from the
+ * candidate (xbar = q + 1e-3 (x - q), where the control variate reads g),
+ * distance and an accept flag.  sides: 1 = inward offsets only, 2 = both
+ * sides (2D).  The region-of-interest and mixed samplers report xbar the
+ * same way.
  * Returns the number accepted. */
 int64_t orc_sample_cache(const orc_scene* s, int64_t n, double l, int sides, uint64_t seed,
                          uint32_t batch, double* x, double* nrm, double* w, double* xbar,

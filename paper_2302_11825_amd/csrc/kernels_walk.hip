@@ -62,6 +62,12 @@ namespace {
 // ---------------------------------------------------------------------------
 // Cache sampling
 // ---------------------------------------------------------------------------
+// A cache point's xbar is its closest boundary point seen from the point,
+// closest + kXbarSide (x - closest): the control variate c = g(xbar) of its
+// walks then reads the data on the point's own side of a boundary with
+// double-sided conditions (Appendix B); for continuous data c moves by about
+// 1e-3 l |grad g|, which a control variate may take.
+constexpr double kXbarSide = 1e-3;
 __device__ void candidate_point(const SceneDev& S, int e, double r, double v, double l, double* x) {
   if (S.dim == 2) {
     const int ns = S.np * S.sides;
@@ -167,7 +173,7 @@ __global__ __launch_bounds__(kBlock) void k_sample_cache(SceneDev S, int64_t n, 
 #pragma unroll
   for (int a = 0; a < D; ++a) {
     x[a * n + k] = xc[a];
-    xbar[a * n + k] = q[a];
+    xbar[a * n + k] = fma(kXbarSide, xc[a] - q[a], q[a]);
     nrm[a * n + k] = (q[a] - xc[a]) / d;
   }
 }
@@ -234,7 +240,7 @@ __global__ __launch_bounds__(kBlock) void k_sample_roi(SceneDev Sd, SceneDev Sr,
   for (int a = 0; a < D; ++a) {
     x[a * n + k] = xc[a];
     nrm[a * n + k] = nc[a];
-    xbar[a * n + k] = q[a];
+    xbar[a * n + k] = fma(kXbarSide, xc[a] - q[a], q[a]);
   }
 }
 
@@ -304,7 +310,7 @@ __global__ __launch_bounds__(kBlock) void k_sample_mixed(SceneDev Sf, SceneDev S
   for (int a = 0; a < 2; ++a) {
     x[a * n + k] = xc[a];
     nrm[a * n + k] = nc[a];
-    xbar[a * n + k] = q[a];
+    xbar[a * n + k] = fma(kXbarSide, xc[a] - q[a], q[a]);
   }
 }
 

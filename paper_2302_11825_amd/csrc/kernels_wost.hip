@@ -258,7 +258,9 @@ __global__ __launch_bounds__(kWostBlock) void k_wost(WostArgs a) {
       const T dD = fsqrt(d2D);
       if (dD < eps || k >= a.max_steps) {
         capped = !(dD < eps);
-        const double qd[2] = {(double)q[0], (double)q[1]};
+        // read g at the closest Dirichlet point approached from the walk's side
+        const T t = dD > T(0) ? T(1e-3) * eps / dD : T(0);
+        const double qd[2] = {(double)fma(t, pos[0] - q[0], q[0]), (double)fma(t, pos[1] - q[1], q[1])};
         W = field_value(a.g, 2, qd);
         break;
       }

@@ -244,9 +244,14 @@ __global__ __launch_bounds__(kBlock) void k_walks(WalkArgs a) {
             const T R0 = (T)a.R0[i];
             if (MODE != 0 && R0 < eps) {
               // the start point already lies in the epsilon shell: its walk
-              // returns g at the closest boundary point
+              // returns g at the closest boundary point, read from its side
+              const double t = R0 > T(0) ? 1e-3 * a.eps / (double)R0 : 0.0;
 #pragma unroll
-              for (int q = 0; q < D; ++q) EX[(size_t)q * a.ld + id] = (T)a.xbar[q * a.n_pts + i];
+              for (int q = 0; q < D; ++q) {
+                const double xq = MODE != 1 ? a.x[q * a.n_pts + i] : (double)((const T*)a.px)[q * a.n_pts + i];
+                const double bq = a.xbar[q * a.n_pts + i];
+                EX[(size_t)q * a.ld + id] = (T)fma(t, xq - bq, bq);
+              }
               U[id] = T(0);
               if (MODE == 1 && Dof) {
 #pragma unroll
@@ -350,8 +355,12 @@ __global__ __launch_bounds__(kBlock) void k_walks(WalkArgs a) {
       const bool stop = d < eps;
       const bool cap = !stop && k >= a.max_steps;
       if (stop || cap) {
+        // g is read at the closest point approached from the walk's side by
+        // 1e-3 eps, so that data that differ on the two sides of a boundary
+        // curve (double-sided conditions, Appendix B) are read on this side
+        const T t = d > T(0) ? T(1e-3) * eps / d : T(0);
 #pragma unroll
-        for (int c = 0; c < D; ++c) EX[(size_t)c * a.ld + id] = qs.bq[c];
+        for (int c = 0; c < D; ++c) EX[(size_t)c * a.ld + id] = fma(t, p[c] - qs.bq[c], qs.bq[c]);
         U[id] = acc_s + usrc;
         if (a.steps) a.steps[id] = k;
         steps_acc += (unsigned long long)k;
@@ -730,8 +739,9 @@ __global__ __launch_bounds__(kBlock) void k_batch_walks(BatchDev b) {
       const bool stop = d < eps;
       const bool cap = !stop && k >= s.max_steps;
       if (stop || cap) {
+        const float t = d > 0.f ? 1e-3f * eps / d : 0.f;  // read g from the walk's side
 #pragma unroll
-        for (int c = 0; c < D; ++c) b.exit[(size_t)c * b.total_walks + gid] = q[c];
+        for (int c = 0; c < D; ++c) b.exit[(size_t)c * b.total_walks + gid] = fmaf(t, p[c] - q[c], q[c]);
         b.U[gid] = acc_s + usrc;
         steps_acc += (unsigned long long)k;
         capped_acc += cap ? 1ull : 0ull;
@@ -786,10 +796,10 @@ __global__ __launch_bounds__(kBlock) void k_batch_finish(BatchDev b) {
       sc_cv = sc;
     }
     if (!s.cv) c = 0.0;
-    double q[D];
+    float q[D];
 #pragma unroll
-    for (int a = 0; a < D; ++a) q[a] = (double)b.exit[(size_t)a * b.total_walks + gid];
-    const double gq = field_value(s.g, D, q);
+    for (int a = 0; a < D; ++a) q[a] = b.exit[(size_t)a * b.total_walks + gid];
+    const double gq = field_value_f32(s.g, D, q);
     const double su = (double)b.U[gid];
     b.U[gid] = (float)(gq + su);
     b.D[gid] = (float)((double)b.w1[gid] * (gq + su - c) + (double)b.D[gid]);

@@ -55,9 +55,9 @@ def test_mixed_samples_rectangle():
     # distances: R0 to the whole boundary, xbar on the nearest Dirichlet side
     d_full = np.minimum.reduce([x[:, 0], 2 - x[:, 0], x[:, 1], 1 - x[:, 1]])
     assert np.allclose(s["R0"][acc], d_full[acc], atol=1e-12)
-    xb_x = np.where(x[:, 0] < 1, 0.0, 2.0)
-    assert np.allclose(s["xbar"][acc, 0], xb_x[acc], atol=1e-12)
-    assert np.allclose(s["xbar"][acc, 1], np.clip(x[acc, 1], 0, 1), atol=1e-12)
+    # xbar: the closest Dirichlet point seen from the sample, 1e-3 of the way back
+    xb = np.stack([np.where(x[:, 0] < 1, 0.0, 2.0), np.clip(x[:, 1], 0, 1)], 1)
+    assert np.allclose(s["xbar"][acc], (xb + 1e-3 * (x - xb))[acc], atol=1e-12)
 
 
 def _strip():

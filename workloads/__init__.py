@@ -431,6 +431,39 @@ def problem_c2(grid: int = 1024, jitter: str = "isotropic") -> Problem:
                    seed_walks=seed(2, 4), seed_cache=seed(2, 3), seed_sources=seed(2, 6))
 
 
+def slit_disk(n_circle: int = 256, n_slit: int = 64) -> Scene:
+    """The unit disk cut along the segment [0, 1] x {0} (a double-sided
+    boundary, Appendix B): one counter-clockwise polygon that runs round the
+    circle from (1, 0), back along the lower side of the cut to the origin and
+    out again along its upper side; the two sides are separate segments on
+    the same line, so the cut adds nothing to winding numbers off it."""
+    t = 2 * np.pi * np.arange(n_circle) / n_circle
+    V = [np.stack([np.cos(t), np.sin(t)], 1)]
+    back = np.stack([1 - np.arange(1, n_slit + 1) / n_slit, np.zeros(n_slit)], 1)  # to the origin
+    out = np.stack([np.arange(1, n_slit) / n_slit, np.zeros(n_slit - 1)], 1)  # out again
+    V = np.concatenate([V[0], back, out])
+    m = V.shape[0]
+    P = np.array([[i, (i + 1) % m] for i in range(m)], dtype=np.int32)
+    return Scene(2, V, P, f"slit_disk{n_circle}_{n_slit}")
+
+
+def slit_field() -> Field:
+    """u = r^(1/2) cos(phi/2), phi in [0, 2 pi): harmonic in the slit disk,
+    sqrt(r) on the upper side of the cut and -sqrt(r) on the lower one."""
+    return wedge_2d(1.0, 0.5)
+
+
+def problem_slit_disk(grid: int = 256, n_cache: int = 16384, n_walks: int = 128) -> Problem:
+    """Laplace in the slit disk with double-sided Dirichlet data on the cut."""
+    sc = slit_disk()
+    g = slit_field()
+    eps = 1e-3 * sc.diagonal
+    lo, hi = sc.bbox
+    return Problem("slit_disk_double_sided", sc, g, Field(), n_cache, n_walks, eps, 5 * eps, 0,
+                   grid2d(grid, lo, hi), g, sides=1, precision="f32",
+                   seed_walks=seed(8, 4), seed_cache=seed(8, 3), seed_sources=seed(8, 6))
+
+
 def mixed_polygon(verts, neumann, counts, name="mixed"):
     """A CCW polygon whose side i (vertex i to i + 1) is split into counts[i]
     equal segments and is Neumann where neumann[i]: returns the whole
