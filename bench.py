@@ -18,6 +18,7 @@ oracle timed on the host cores.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import math
 import os
@@ -52,7 +53,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4a", "c4b", "c2clamp", "c3clamp", "c3screen", "c2roi",
-                                                    "c2mixed", "c2screen"],
+                                                    "c2mixed", "c2screen", "c2slit"],
                     help="c2 prints the benchmark line; the others print their own measurement lines")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes (no autotuning)")
     ap.add_argument("--clamp-c", type=float, default=20.0, help="c2clamp: bound c of dG/dn (Eq. 9)")
@@ -147,17 +148,26 @@ def main():
     print("[bench] warmup done", file=sys.stderr, flush=True)
 
     watch = pl.Stopwatch()
-    sols = []
+    counts = []  # per step: (cache-walk counters, band-walk counters), device tensors
+    sol = None
     torch.cuda.synchronize()
+    # the host's cyclic garbage collector stays out of the timed region, and
+    # each step's buffers are released before the next one so that the
+    # caching allocator reuses them instead of growing the pool mid-run
+    gc.collect()
+    gc.disable()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     e0.record()
     for s in range(args.steps):
-        sols.append(pl.solve(prep, batch=s, watch=watch))
+        sol = None
+        sol = pl.solve(prep, batch=s, watch=watch)
+        counts.append((sol.counters, sol.pw_counters))
     e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    gc.enable()
     ms_step = e0.elapsed_time(e1) / args.steps
     timers = {k: float(np.mean(v)) for k, v in watch.totals_ms().items()}
     kernels = {k: v for k, v in timers.items() if k.startswith("k_")}
@@ -165,14 +175,13 @@ def main():
     print(f"[bench] timed {args.steps} steps: {ms_step:.2f} ms/step (wall {wall:.2f}s) {stages}",
           file=sys.stderr, flush=True)
 
-    sol = sols[-1]
     n_pts = prep.n_int + prep.n_band
     value = n_pts / (ms_step / 1e3)
-    steps_total = sum(int(s.counters[1]) + int(s.pw_counters[1]) for s in sols)
-    walks_total = sum(int(s.counters[3]) + int(s.pw_counters[3]) for s in sols)
-    capped = sum(int(s.counters[2]) + int(s.pw_counters[2]) for s in sols)
+    steps_total = sum(int(c[1]) + int(p[1]) for c, p in counts)
+    walks_total = sum(int(c[3]) + int(p[3]) for c, p in counts)
+    capped = sum(int(c[2]) + int(p[2]) for c, p in counts)
     walk_ms = kernels.get("k_walks_cache", stages.get("cache_walks", 0.0))
-    cache_steps = sum(int(s.counters[1]) for s in sols) / args.steps
+    cache_steps = sum(int(c[1]) for c, _ in counts) / args.steps
     cache_walk_rate = cache_steps / (walk_ms / 1e3) if walk_ms > 0 else 0.0
 
     # error of the last step against the manufactured closed form

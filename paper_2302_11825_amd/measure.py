@@ -12,6 +12,7 @@
     python bench.py --workload c3clamp --clamp-c 1600   the same on the 3D Laplace step
     python bench.py --workload c3screen  the 3D step on the screened equation (sigma = 4)
     python bench.py --workload c2screen  the 2D step on the screened equation (sigma = 4)
+    python bench.py --workload c2slit    double-sided Dirichlet data on a cut disk (Appendix B)
     python bench.py --workload c2roi     the 2D Poisson problem cached on the boundary of a
                                      disk inside the star (region of interest, Section 3.2)
     python bench.py --workload c2mixed   Laplace in a channel with Dirichlet ends and Neumann
@@ -62,7 +63,8 @@ def _log(msg):
 
 def run(args):
     {"c3": c3, "c4a": c4a, "c4b": c4b, "c2clamp": c2clamp, "c3clamp": c3clamp,
-     "c3screen": c3screen, "c2roi": c2roi, "c2mixed": c2mixed, "c2screen": c2screen}[args.workload](args)
+     "c3screen": c3screen, "c2roi": c2roi, "c2mixed": c2mixed, "c2screen": c2screen,
+     "c2slit": c2slit}[args.workload](args)
 
 
 def _c3_setup(args, prob=None):
@@ -80,6 +82,44 @@ def c3screen(args):
     """The 3D step on the screened equation Lap u = sigma u (sigma = 4) with the
     plane wave exp(a.x) as data and solution."""
     c3(args, wl.problem_c3_screened())
+
+
+def c2slit(args):
+    """Double-sided Dirichlet data (Appendix B): the unit disk cut along
+    [0, 1] x {0}, u = r^(1/2) cos(phi/2) (sqrt(r) above the cut, -sqrt(r)
+    below); 65,536 cache points x 128 walks, 1024^2 grid."""
+    prob = wl.problem_slit_disk(grid=args.grid, n_cache=65536, n_walks=128)
+    prep = pl.Prepared(prob, dtype="f32")
+    torch.cuda.synchronize()
+    for _ in range(max(1, args.warmup)):
+        pl.solve(prep, with_grad=False)
+    torch.cuda.synchronize()
+    watch = pl.Stopwatch()
+    e0, e1 = _ev(), _ev()
+    e0.record()
+    for _ in range(args.steps):
+        sol = pl.solve(prep, with_grad=False, watch=watch)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    stages = {k: sum(v) / len(v) for k, v in watch.totals_ms().items()}
+    xi = prob.eval_x[prep.idx_int[: prep.n_int].cpu().numpy()]
+    xb = prob.eval_x[prep.idx_band[: prep.n_band].cpu().numpy()]
+    ti, tb = wl.field_value(prob.truth, xi), wl.field_value(prob.truth, xb)
+    ui = sol.u_int[: prep.n_int].double().cpu().numpy()
+    ub = sol.u_band[: prep.n_band].double().cpu().numpy()
+    d = prep.dist[prep.idx_int[: prep.n_int].long()].cpu().numpy()
+    rm = lambda u, t: float(np.sqrt(np.mean((u - t) ** 2)))
+    far = d >= 0.05
+    near_cut = (xb[:, 0] > 0.1) & (xb[:, 0] < 0.9) & (np.abs(xb[:, 1]) < 0.05)
+    out = {"workload": "slit_disk_double_sided", "ms_per_step": ms, "stage_ms": stages,
+           "points_gathered": prep.n_int, "points_band": prep.n_band, "cache_points": sol.cache.n,
+           "points_per_s": (prep.n_int + prep.n_band) / (ms / 1e3), "rmse_gathered": rm(ui, ti),
+           "rmse_gathered_d_ge_0.05": rm(ui[far], ti[far]), "rmse_band": rm(ub, tb),
+           "band_points_on_the_cut": int(near_cut.sum()),
+           "band_sign_right_on_the_cut": float(np.mean(np.sign(ub[near_cut]) == np.sign(xb[near_cut, 1]))),
+           "rms_truth": float(np.sqrt(np.mean(ti**2)))}
+    print(json.dumps(out))
 
 
 def c2screen(args):
