@@ -208,3 +208,7 @@ def test_mixed_refuses_bad_input():
         _bvc.bvc_sample_mixed(s3.h, sd.h, sn.h, 8, 0.1, 1, 0, x, x, w, x, w, k)
     with pytest.raises(_bvc.BVCError):
         _bvc.bvc_classify_mixed(s3.h, sd.h, 8, x, 0.1, k)
+    # empty inputs are no-ops
+    _bvc.bvc_sample_mixed(sf.h, sd.h, sn.h, 0, 0.1, 1, 0, None, None, None, None, None, None)
+    _bvc.bvc_classify_mixed(sf.h, sd.h, 0, None, 0.1, None)
+    torch.cuda.synchronize()
