@@ -111,8 +111,8 @@ def walk_bytes(dim, es, mode, with_grad):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(sharding is described in DESIGN.md); rerun with --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path; rerun with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
     import torch
 
