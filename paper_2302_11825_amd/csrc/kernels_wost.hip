@@ -260,8 +260,12 @@ __global__ __launch_bounds__(kWostBlock) void k_wost(WostArgs a) {
         capped = !(dD < eps);
         // read g at the closest Dirichlet point approached from the walk's side
         const T t = dD > T(0) ? T(1e-3) * eps / dD : T(0);
-        const double qd[2] = {(double)fma(t, pos[0] - q[0], q[0]), (double)fma(t, pos[1] - q[1], q[1])};
-        W = field_value(a.g, 2, qd);
+        const T qr[2] = {fma(t, pos[0] - q[0], q[0]), fma(t, pos[1] - q[1], q[1])};
+        if constexpr (sizeof(T) == 4) {
+          W = field_value_f32(a.g, 2, qr);
+        } else {
+          W = field_value(a.g, 2, qr);
+        }
         break;
       }
       const T R = fmax(fmin(dD, fsqrt(silhouette_d2<T>(a, pos, d2D, stk, stride))), eps);

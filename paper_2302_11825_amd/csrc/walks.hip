@@ -398,8 +398,9 @@ __device__ inline double sph_i1(double x) {
   return (x * cosh(x) - sinh(x)) / (x * x);
 }
 
-// Boundary data at the exit points (FP32 walks evaluate the closed-form
-// kinds of g in FP32, FP64 walks every kind in FP64), combined in FP64.
+// Boundary data at the exit points and the control variate (FP32 walks
+// evaluate the closed-form kinds of g in FP32, FP64 walks every kind in
+// FP64), combined in FP64.
 // With W = g(exit) + S:
 // U = W + u_src,  mode 0: D = w1 (W - c) + d_src,  mode 1: grad = gw (W - c) + g_src,
 // where c = g(xbar) is the control variate (0 when disabled).  Screened walks
@@ -429,10 +430,19 @@ __global__ __launch_bounds__(kBlock) void k_finish(FieldDev g, int cv, uint64_t 
     if (id >= total) break;
     const int64_t i = (int64_t)(id / (uint64_t)W);
     if (cv && i != i_cv) {
-      double xb[D];
+      // the control variate in the walks' precision: any constant keeps the
+      // gradient estimate unbiased
+      if constexpr (sizeof(T) == 4) {
+        float xb[D];
 #pragma unroll
-      for (int q = 0; q < D; ++q) xb[q] = xbar[q * n_pts + i];
-      c = field_value(g, D, xb);
+        for (int q = 0; q < D; ++q) xb[q] = (float)xbar[q * n_pts + i];
+        c = field_value_f32(g, D, xb);
+      } else {
+        double xb[D];
+#pragma unroll
+        for (int q = 0; q < D; ++q) xb[q] = xbar[q * n_pts + i];
+        c = field_value(g, D, xb);
+      }
       i_cv = i;
     }
     double gq;
@@ -788,10 +798,10 @@ __global__ __launch_bounds__(kBlock) void k_batch_finish(BatchDev b) {
     const BatchSceneDev& s = b.scenes[sc];
     const int64_t i = (int64_t)((gid - s.walk_off) / (uint64_t)s.W);
     if (s.cv && (i != i_cv || sc != sc_cv)) {
-      double xb[D];
+      float xb[D];
 #pragma unroll
-      for (int a = 0; a < D; ++a) xb[a] = s.xbar[a * s.n_cache + i];
-      c = field_value(s.g, D, xb);
+      for (int a = 0; a < D; ++a) xb[a] = (float)s.xbar[a * s.n_cache + i];
+      c = field_value_f32(s.g, D, xb);
       i_cv = i;
       sc_cv = sc;
     }
