@@ -184,8 +184,9 @@ int bvc_sample_roi(bvc_scene dom, bvc_scene roi, int64_t n, uint64_t seed, uint3
  * points; w = total candidate measure / n; xbar = closest Dirichlet point q
  * seen from the sample, q + 1e-3 (x - q);
  * R0 = distance to `full` (the first ball of a cache walk); kind (int32 [n]:
- * 0 rejected, 1 accepted offset point (distance l within 1e-9 relative and
- * inside `full`), 2 accepted Neumann point (farther than l)).  The three
+ * 0 rejected, 1 accepted offset point (distance l within 1e-9 relative,
+ * inside `full` and no closer than l/100 to the Neumann part), 2 accepted
+ * Neumann point (farther than l)).  The three
  * scenes are CCW segment sets over one boundary; the first call for `dir` at
  * this l and for `neu` uploads their sampling tables and synchronises.
  * Errors: BVC_EUNSUPPORTED in 3D, BVC_EINVAL for an empty part, l <= 0 or a
@@ -361,9 +362,10 @@ int bvc_gather_grad(int32_t dim, const bvc_cache_view* cache, const bvc_source_v
  * id i*W + j (n*W < 2^32).  Each step: star radius R = max(eps, min(d_D,
  * d_S)), d_D the distance to the Dirichlet part and d_S to the closest
  * silhouette vertex of the Neumann part seen from the walk (a corner vertex
- * with both Neumann neighbours strictly on one side of the line of sight, or
- * one on it and the other off it, within 1e-9 relative in FP64 and 1e-5 in
- * FP32; ends of Neumann runs included; a vertex where the boundary continues
+ * whose Neumann neighbours are not strictly on opposite sides of the line of
+ * sight, within 1e-9 relative in FP64 and 1e-5 in FP32: both on one side, one
+ * on it, or both on it at the fold of a thin Neumann curve; ends of Neumann
+ * runs included; a vertex where the boundary continues
  * straight, within 1e-12 relative, is no corner); a direction uniform on the
  * circle (Philox block 4k
  * as walk on spheres), turned into the inward half circle on the Neumann

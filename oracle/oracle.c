@@ -1649,11 +1649,11 @@ static int line_side(const double* x, const double* v, const double* w) {
 }
 
 /* Distance from x to the closest silhouette vertex of the Neumann part: a
- * corner vertex whose two Neumann neighbours lie strictly on one side of the
- * line from x through it, or one on the line and the other off it (x looks
- * along one segment past the corner), and the ends of Neumann runs.  A vertex
- * where the boundary continues straight is no corner and never a
- * silhouette. */
+ * corner vertex whose two Neumann neighbours do not lie strictly on opposite
+ * sides of the line from x through it (both on one side; one on the line, x
+ * looking along a segment past the corner; both on it, the fold at the tip
+ * of a thin Neumann curve), and the ends of Neumann runs.  A vertex where the
+ * boundary continues straight is no corner and never a silhouette. */
 static double silhouette_distance(const orc_scene* neu, const neu_links* L, const double* x) {
   double best = INFINITY;
   for (int64_t q = 0; q < neu->np; ++q) {
@@ -1665,7 +1665,10 @@ static double silhouette_distance(const orc_scene* neu, const neu_links* L, cons
     } else if (L->prev[q] >= 0) {
       const double* u = neu->V + 2 * (int64_t)L->prev[q];
       int s1 = line_side(x, a, u), s2 = line_side(x, a, b);
-      sil = (s1 * s2 > 0) || ((s1 == 0) != (s2 == 0));
+      /* a corner hides nothing only when its neighbours lie strictly on
+       * opposite sides of the line of sight; with both on it the boundary
+       * folds back there (the tip of a thin Neumann curve) */
+      sil = !(s1 * s2 < 0);
     }
     if (sil) best = fmin(best, hypot(a[0] - x[0], a[1] - x[1]));
     if (!L->has_next[q]) best = fmin(best, hypot(b[0] - x[0], b[1] - x[1]));
@@ -1683,8 +1686,11 @@ static double neumann_hit(const orc_scene* neu, const double* x, const double* w
     const double* a = neu->V + 2 * (int64_t)neu->P[2 * q];
     const double* b = neu->V + 2 * (int64_t)neu->P[2 * q + 1];
     double e0 = b[0] - a[0], e1 = b[1] - a[1];
+    /* den = |e| w . n_out: only a segment the ray leaves the domain through
+     * counts, so that of the two runs of a double-sided Neumann curve
+     * (Appendix B) the ray meets the one facing its own side */
     double den = cross2(w[0], w[1], e0, e1);
-    if (den == 0) continue;
+    if (!(den > 0)) continue;
     double r0 = a[0] - x[0], r1 = a[1] - x[1];
     double t = cross2(r0, r1, e0, e1) / den;
     double u = cross2(r0, r1, w[0], w[1]) / den;
@@ -1799,9 +1805,9 @@ void orc_wost_walks(const orc_scene* dir, const orc_scene* neu, const orc_field*
  * concatenated measures of the offset Dirichlet elements (as
  * orc_sample_cache with sides 1, on the Dirichlet segments `dir`) followed
  * by the Neumann segments `neu`.  An offset candidate is kept when its
- * distance to the Dirichlet part is l (1e-9 relative) and it lies inside the
- * domain `full`; a Neumann candidate when its distance to the Dirichlet part
- * exceeds l.  Outputs: x, nrm (offset points: towards the closest Dirichlet
+ * distance to the Dirichlet part is l (1e-9 relative), it lies inside the
+ * domain `full` and no closer than l/100 to the Neumann part; a Neumann
+ * candidate when its distance to the Dirichlet part exceeds l.  Outputs: x, nrm (offset points: towards the closest Dirichlet
  * point; Neumann points: the segment's outward normal), w = total measure /
  * n, xbar = closest Dirichlet point, R0 = distance to the whole boundary,
  * type (0 offset, 1 Neumann), accept.  Returns the number accepted. */
@@ -1866,6 +1872,11 @@ int64_t orc_sample_mixed(const orc_scene* full, const orc_scene* dir, const orc_
     }
     double dF, xf[3];
     orc_closest(full, xk, 0, &dF, xf, NULL);
+    /* an offset point within l/100 of the Neumann part is dropped: its first
+     * ball (no larger than that distance) would give the Eq. 7 estimate an
+     * unbounded variance; the boundary integral loses 2 l/100 of length where
+     * the offset curve meets the Neumann part */
+    if (type[k] == 0 && dF < 1e-2 * l) ok = 0;
     R0[k] = dF;
     xbar[2 * k] = xb[0] + XBAR_SIDE * (xk[0] - xb[0]);
     xbar[2 * k + 1] = xb[1] + XBAR_SIDE * (xk[1] - xb[1]);

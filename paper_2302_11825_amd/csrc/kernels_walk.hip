@@ -303,7 +303,11 @@ __global__ __launch_bounds__(kBlock) void k_sample_mixed(SceneDev Sf, SceneDev S
   }
   double qf[2];
   int hf = -1;
-  R0[k] = sqrt(closest_point<double, 2>(Sf, xc, hf, qf, lds + threadIdx.x, blockDim.x));
+  const double dF = sqrt(closest_point<double, 2>(Sf, xc, hf, qf, lds + threadIdx.x, blockDim.x));
+  // an offset point within l/100 of the Neumann part is dropped: its first
+  // ball would give the Eq. 7 estimate an unbounded variance
+  if (ty == 1 && dF < 1e-2 * l) ok = false;
+  R0[k] = dF;
   kind[k] = ok ? ty : 0;
   w[k] = M / (double)n;
 #pragma unroll

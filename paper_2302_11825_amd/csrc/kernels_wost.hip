@@ -86,10 +86,11 @@ __device__ __forceinline__ bool cone_culls(const float4 cone, const T* lo, const
 }
 
 // Squared distance from p to the closest silhouette vertex of the Neumann
-// part within sqrt(bound): a corner vertex whose two Neumann neighbours lie
-// strictly on one side of the line from p through it, or one on that line and
-// the other off it, and the ends of Neumann runs; a vertex where the boundary
-// continues straight is none.  Returns bound when there is none closer (the
+// part within sqrt(bound): a corner vertex whose two Neumann neighbours do
+// not lie strictly on opposite sides of the line from p through it (both on
+// one side; one on it; both on it, the fold at the tip of a thin Neumann
+// curve), and the ends of Neumann runs; a vertex where the boundary continues
+// straight is none.  Returns bound when there is none closer (the
 // step radius never exceeds the Dirichlet distance, so the search starts
 // there).
 template <typename T>
@@ -127,7 +128,7 @@ __device__ T silhouette_d2(const WostArgs& a, const T* p, T bound, uint32_t* stk
           } else if (pv >= 0) {
             const T ux = (T)S.V[2 * (size_t)pv], uy = (T)S.V[2 * (size_t)pv + 1];
             const int s1 = line_side<T>(p, ax, ay, ux, uy, tol), s2 = line_side<T>(p, ax, ay, bx, by, tol);
-            sil = (s1 * s2 > 0) || ((s1 == 0) != (s2 == 0));
+            sil = !(s1 * s2 < 0);  // both on the sight line: a fold (tip of a thin curve)
           }
           if (sil) best = fmin(best, (ax - p[0]) * (ax - p[0]) + (ay - p[1]) * (ay - p[1]));
           if (!(fl & kHasNext)) best = fmin(best, (bx - p[0]) * (bx - p[0]) + (by - p[1]) * (by - p[1]));
@@ -196,8 +197,11 @@ __device__ T neumann_hit(const WostArgs& a, const T* x, const T* w, T lo, T hi, 
         for (int i = s0; i < s0 + m; ++i) {
           const T ax = pr[4 * i], ay = pr[4 * i + 1], bx = pr[4 * i + 2], by = pr[4 * i + 3];
           const T e0 = bx - ax, e1 = by - ay;
+          // den = |e| w . n_out: only a segment the ray leaves the domain
+          // through counts, so that of the two runs of a double-sided
+          // Neumann curve (Appendix B) the ray meets the one facing its side
           const T den = w[0] * e1 - w[1] * e0;
-          if (den == T(0)) continue;
+          if (!(den > T(0))) continue;
           const T r0 = ax - x[0], r1 = ay - x[1];
           const T t = (r0 * e1 - r1 * e0) / den;
           const T u = (r0 * w[1] - r1 * w[0]) / den;
@@ -276,7 +280,10 @@ __global__ __launch_bounds__(kWostBlock) void k_wost(WostArgs a) {
         w[1] = -w[1];
       }
       int seg;
-      const T t = neumann_hit<T>(a, pos, w, T(1e-9) * R, R, seg, stk, stride);
+      // crossings closer than the position's rounding are the walk's own
+      // segment, or the other side of a thin Neumann curve it stands on
+      const T lo = sizeof(T) == 4 ? T(1e-5) * (R + fabs(pos[0]) + fabs(pos[1])) : T(1e-9) * R;
+      const T t = neumann_hit<T>(a, pos, w, lo, R, seg, stk, stride);
       if (seg >= 0) {
         const T* pr = SceneArrays<T>::prim(a.Sn);
         const T e0 = pr[4 * seg + 2] - pr[4 * seg], e1 = pr[4 * seg + 3] - pr[4 * seg + 1];

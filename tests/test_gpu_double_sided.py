@@ -80,3 +80,66 @@ def test_double_sided_step_fp32():
     # on both sides of the cut, within 0.1 of it, the sign follows the side
     near = (xb[:, 0] > 0.2) & (xb[:, 0] < 0.8) & (np.abs(xb[:, 1]) < 0.1)
     assert near.sum() > 20 and np.all(np.sign(ub[near]) == np.sign(xb[near, 1]))
+
+
+def _neumann_cut_problem(n_cand, W, grid, precision):
+    full, dir_, neu = wl.slit_disk_neumann(256, 64)
+    g = wl.slit_field()
+    eps = 1e-3
+    return wl.Problem("slit_disk_neumann_cut", full, g, wl.Field(), n_cand, W, eps, 0.02, 0,
+                      wl.grid2d(grid, (-1, -1), (1, 1)), g, sides=1, precision=precision, seed_walks=71,
+                      seed_cache=72, extra=dict(dirichlet=dir_, neumann=neu))
+
+
+def test_neumann_cut_walk_on_stars_fp64(orc):
+    """Walk on stars with a thin Neumann cut (two runs folding back at the
+    tip, Appendix B): FP64 walks walk by walk from interior points on both
+    sides and from points on either side of the cut."""
+    _bvc, pl = lib()
+    say("neumann cut wost fp64")
+    prob = _neumann_cut_problem(1000, 16, 8, "f64")
+    dir_, neu = prob.extra["dirichlet"], prob.extra["neumann"]
+    prep = pl.MixedPrepared(prob, dtype="f64")
+    od, on = orc.Scene(dir_), orc.Scene(neu)
+    rng = np.random.default_rng(4)
+    xs = rng.uniform(0.05, 0.95, 60)
+    pts = np.stack([xs, rng.choice([-1, 1], 60) * rng.uniform(1e-3, 0.2, 60)], 1)
+    W = 16
+    wp = pl.walk_params(1e-3, W, 71, prep.g, None, "f64")
+    xd = torch.from_numpy(np.ascontiguousarray(pts.T)).to("cuda")
+    U, _, _ = pl.wost(prep, wp, 1, pts.shape[0], xd, dtype="f64")
+    torch.cuda.synchronize()
+    Uo, _, _ = orc.wost_walks(od, on, prob.g, orc.walk_params(1e-3, W, 71), 1, pts)
+    m1 = per_walk_match(U.cpu().numpy()[: pts.shape[0] * W], Uo)
+    bp = np.stack([rng.uniform(0.05, 0.95, 40), np.zeros(40)], 1)
+    nrm = np.stack([np.zeros(40), np.repeat([-1.0, 1.0], 20)], 1)  # into the cut: upper side, lower side
+    U3, _, _ = pl.wost(prep, wp, 3, bp.shape[0], torch.from_numpy(np.ascontiguousarray(bp.T)).to("cuda"),
+                       torch.from_numpy(np.ascontiguousarray(nrm.T)).to("cuda"), dtype="f64")
+    torch.cuda.synchronize()
+    U3o, _, _ = orc.wost_walks(od, on, prob.g, orc.walk_params(1e-3, W, 71), 3, bp, nrm=nrm)
+    m3 = per_walk_match(U3.cpu().numpy()[: bp.shape[0] * W], U3o)
+    say(f"  interior walks {m1.size}: {m1.mean():.5f}; cut walks {m3.size}: {m3.mean():.5f}")
+    assert m1.mean() >= 0.999 and m3.mean() >= 0.999
+
+
+def test_neumann_cut_mixed_step_fp32():
+    """The mixed cache with the cut as a double-sided Neumann boundary (FP32):
+    u = r^(1/2) cos(phi/2) above and below the cut."""
+    _bvc, pl = lib()
+    say("neumann cut mixed step fp32")
+    prob = _neumann_cut_problem(131072, 128, 256, "f32")
+    prep = pl.MixedPrepared(prob)
+    sol = pl.solve_mixed(prep, with_grad=False)
+    torch.cuda.synchronize()
+    xi = prob.eval_x[prep.idx_int[: prep.n_int].cpu().numpy()]
+    ui = sol.u_int.double().cpu().numpy()[: prep.n_int]
+    ti = wl.field_value(prob.g, xi)
+    rms = np.sqrt(np.mean(ti**2))
+    cut = np.abs(xi[:, 1]) < 0.05
+    far = ~cut & (np.hypot(xi[:, 0], xi[:, 1]) < 0.9)
+    e_far = np.sqrt(np.mean((ui[far] - ti[far]) ** 2))
+    say(f"  cache {sol.cache.n} ({sol.extra['n_offset']} offset), gathered {prep.n_int}: rmse {e_far:.4g} "
+        f"(off the cut and the circle), rms {rms:.3g}")
+    assert e_far < 0.03 * rms
+    near = cut & (xi[:, 0] > 0.2) & (xi[:, 0] < 0.8) & (np.abs(xi[:, 1]) > 0.01)
+    assert near.sum() > 20 and np.mean(np.sign(ui[near]) == np.sign(xi[near, 1])) > 0.98

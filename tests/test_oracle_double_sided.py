@@ -114,3 +114,30 @@ def test_double_sided_chain():
     got = orc.gather(2, x, cache["x"], cache["n"], a, b, with_grad=False)
     ex = wl.field_value(g, x)
     assert np.sqrt(np.mean((got - ex) ** 2)) < 0.04 * np.sqrt(np.mean(ex**2))
+
+
+def test_walk_on_stars_with_a_double_sided_neumann_cut():
+    """u = r^(1/2) cos(phi/2) has zero flux through both sides of the cut, so
+    with a reflecting cut and Dirichlet data on the circle it is the solution:
+    walk-on-stars means match it just above and below the cut and from points
+    on either side of the cut itself (a walk that crossed the cut, or reflected
+    to the wrong side, would land near the other side's value)."""
+    full, dir_, neu = wl.slit_disk_neumann(256, 64)
+    od, on = orc.Scene(dir_), orc.Scene(neu)
+    g = wl.slit_field()
+    W = 3000
+    P = orc.walk_params(1e-3, W, 31)
+    pts = np.array([[0.5, 0.03], [0.5, -0.03], [0.2, 0.1], [0.2, -0.1], [-0.3, 0.2], [0.8, -0.02]])
+    U, _, _ = orc.wost_walks(od, on, g, P, 1, pts)
+    U = U.reshape(len(pts), W)
+    ex = wl.field_value(g, pts)
+    for i in range(len(pts)):
+        assert abs(U[i].mean() - ex[i]) < 5 * _se(U[i]) + 2e-3, (pts[i], U[i].mean(), ex[i])
+    # from the cut itself, on each side (outward normals point into the cut)
+    bp = np.array([[0.4, 0.0], [0.4, 0.0], [0.7, 0.0], [0.7, 0.0]])
+    nrm = np.array([[0.0, -1.0], [0.0, 1.0], [0.0, -1.0], [0.0, 1.0]])
+    U3, _, _ = orc.wost_walks(od, on, g, P, 3, bp, nrm=nrm)
+    U3 = U3.reshape(len(bp), W)
+    want = np.array([1, -1, 1, -1]) * np.sqrt(bp[:, 0])
+    for i in range(len(bp)):
+        assert abs(U3[i].mean() - want[i]) < 5 * _se(U3[i]) + 2e-3, (bp[i], nrm[i], U3[i].mean(), want[i])

@@ -49,8 +49,10 @@ def test_mixed_samples_rectangle():
     assert np.all((ty == 1) == np.isin(np.round(x[:, 1], 12), [0.0, 1.0]) | (ty == 1))
     rej_n = (ty == 1) & ~acc
     assert np.all((x[rej_n, 0] <= l + 1e-12) | (x[rej_n, 0] >= 2 - l - 1e-12))
-    # total accepted weight = length of the offset region's boundary
-    exact = 2 * 1.0 + 2 * (2 - 2 * l)
+    # total accepted weight = length of the offset region's boundary, less the
+    # l/100 that each offset line drops at each Neumann wall
+    assert np.all(s["R0"][off] >= 1e-2 * l)
+    exact = 2 * 1.0 + 2 * (2 - 2 * l) - 4 * 1e-2 * l
     assert abs(s["w"][acc].sum() - exact) <= 8 * M / n
     # distances: R0 to the whole boundary, xbar on the nearest Dirichlet side
     d_full = np.minimum.reduce([x[:, 0], 2 - x[:, 0], x[:, 1], 1 - x[:, 1]])
@@ -76,10 +78,28 @@ def test_mixed_representation_with_exact_data():
     gu = np.stack([np.exp(z[:, 0]) * np.cos(z[:, 1]), -np.exp(z[:, 0]) * np.sin(z[:, 1])], 1)
     dudn = np.sum(gu * nz, 1)
     assert np.all(np.abs(dudn[s["type"][acc] == 1]) < 1e-12)  # zero flux on the Neumann sides
+    # the sampler drops the l/100 of each offset line next to a Neumann wall
+    # (four pieces); their exact contribution, by the midpoint rule, closes
+    # the curve again
+    dl, m = 1e-2 * l, 64
+    ys = (np.arange(m) + 0.5) / m * dl
+    gz, gn = [], []
+    for xo, nx in ((l, -1.0), (1 - l, 1.0)):
+        for yy in (ys, np.pi - ys):
+            gz.append(np.stack([np.full(m, xo), yy], 1))
+            gn.append(np.tile([nx, 0.0], (m, 1)))
+    gz, gn = np.concatenate(gz), np.concatenate(gn)
+    gw = np.full(gz.shape[0], dl / m)
+    gu = wl.field_value(g, gz)
+    gd = np.sum(np.stack([np.exp(gz[:, 0]) * np.cos(gz[:, 1]), -np.exp(gz[:, 0]) * np.sin(gz[:, 1])], 1) * gn, 1)
     rng = np.random.default_rng(3)
     xin = np.stack([rng.uniform(l + 0.15, 1 - l - 0.15, 40), rng.uniform(0.3, np.pi - 0.3, 40)], 1)
-    got = orc.gather(2, xin, z, nz, u * w, dudn * w, with_grad=False)
-    assert np.allclose(got, wl.field_value(g, xin), atol=2e-4)
+    zz, nn = np.concatenate([z, gz]), np.concatenate([nz, gn])
+    got = orc.gather(2, xin, zz, nn, np.concatenate([u * w, gu * gw]), np.concatenate([dudn * w, gd * gw]),
+                     with_grad=False)
+    # (each end of a piece cuts a stratum of width M/n = 8e-4: up to about
+    # 4e-4 of quadrature error there)
+    assert np.allclose(got, wl.field_value(g, xin), atol=6e-4)
     # in the Dirichlet band (outside the offset region) the integral vanishes
     xb = np.stack([rng.uniform(0.2 * l, 0.6 * l, 20), rng.uniform(0.5, np.pi - 0.5, 20)], 1)
     out = orc.gather(2, xb, z, nz, u * w, dudn * w, with_grad=False)

@@ -218,3 +218,10 @@ def test_silhouette_distance_closed_forms():
         want = np.where(q1 | q3, np.minimum(ends, np.hypot(x[:, 0], x[:, 1])), ends)
         assert q1.sum() > 50 and q3.sum() > 50
         assert np.allclose(orc.silhouette_distances(orc.Scene(neu), x), want, rtol=1e-15, atol=0)
+    # a thin Neumann cut (two runs folding back at the tip): the tip hides the
+    # other side from every point, also from points on the cut's own line
+    _, _, neu = wl.slit_disk_neumann(64, 16)
+    x = np.array([[0.3, 0.0], [0.6, 0.0], [0.5, 0.2], [0.4, -0.3], [-0.5, 0.0]])
+    ends = _nearest(x, [[1, 0]])
+    want = np.minimum(ends, np.hypot(x[:, 0], x[:, 1]))
+    assert np.allclose(orc.silhouette_distances(orc.Scene(neu), x), want, rtol=1e-15, atol=0)

@@ -438,10 +438,10 @@ def slit_disk(n_circle: int = 256, n_slit: int = 64) -> Scene:
     out again along its upper side; the two sides are separate segments on
     the same line, so the cut adds nothing to winding numbers off it."""
     t = 2 * np.pi * np.arange(n_circle) / n_circle
-    V = [np.stack([np.cos(t), np.sin(t)], 1)]
-    back = np.stack([1 - np.arange(1, n_slit + 1) / n_slit, np.zeros(n_slit)], 1)  # to the origin
-    out = np.stack([np.arange(1, n_slit) / n_slit, np.zeros(n_slit - 1)], 1)  # out again
-    V = np.concatenate([V[0], back, out])
+    circle = np.stack([np.cos(t), np.sin(t)], 1)  # from (1, 0) round to just below it
+    back = np.stack([1 - np.arange(0, n_slit + 1) / n_slit, np.zeros(n_slit + 1)], 1)  # (1, 0) to the origin
+    out = np.stack([np.arange(1, n_slit) / n_slit, np.zeros(n_slit - 1)], 1)  # out again, closing at (1, 0)
+    V = np.concatenate([circle, back, out])
     m = V.shape[0]
     P = np.array([[i, (i + 1) % m] for i in range(m)], dtype=np.int32)
     return Scene(2, V, P, f"slit_disk{n_circle}_{n_slit}")
@@ -451,6 +451,23 @@ def slit_field() -> Field:
     """u = r^(1/2) cos(phi/2), phi in [0, 2 pi): harmonic in the slit disk,
     sqrt(r) on the upper side of the cut and -sqrt(r) on the lower one."""
     return wedge_2d(1.0, 0.5)
+
+
+def slit_disk_neumann(n_circle: int = 256, n_slit: int = 64):
+    """The cut disk of slit_disk with a Neumann cut (both sides reflecting,
+    Appendix B) and a Dirichlet circle: (whole boundary, Dirichlet segments,
+    Neumann segments), each part with only the vertices it uses.  The field
+    of slit_field has zero flux through both sides of the cut."""
+    full = slit_disk(n_circle, n_slit)
+    P = full.prims
+    is_neu = np.arange(P.shape[0]) >= n_circle
+
+    def part(mask, tag):
+        Q = P[mask]
+        used, inv = np.unique(Q.ravel(), return_inverse=True)
+        return Scene(2, full.verts[used], inv.reshape(Q.shape).astype(np.int32), f"{full.name}_{tag}")
+
+    return full, part(~is_neu, "dirichlet"), part(is_neu, "neumann")
 
 
 def problem_slit_disk(grid: int = 256, n_cache: int = 16384, n_walks: int = 128) -> Problem:
