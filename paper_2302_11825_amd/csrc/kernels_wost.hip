@@ -280,9 +280,10 @@ __global__ __launch_bounds__(kWostBlock) void k_wost(WostArgs a) {
         w[1] = -w[1];
       }
       int seg;
-      // crossings closer than the position's rounding are the walk's own
-      // segment, or the other side of a thin Neumann curve it stands on
-      const T lo = sizeof(T) == 4 ? T(1e-5) * (R + fabs(pos[0]) + fabs(pos[1])) : T(1e-9) * R;
+      // a walk standing on a Neumann face ignores crossings closer than its
+      // position's rounding (in FP32 the other face of a thin Neumann curve
+      // lies there); elsewhere every crossing beyond 1e-9 R counts
+      const T lo = (sizeof(T) == 4 && onb) ? T(1e-5) * (R + fabs(pos[0]) + fabs(pos[1])) : T(1e-9) * R;
       const T t = neumann_hit<T>(a, pos, w, lo, R, seg, stk, stride);
       if (seg >= 0) {
         const T* pr = SceneArrays<T>::prim(a.Sn);
