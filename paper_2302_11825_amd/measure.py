@@ -473,8 +473,9 @@ def c2mixed(args):
     U, _, cnt = pl.wost(prep, wp, 1, pick.size, xp)
     Uw = U.double().cpu().numpy().reshape(pick.size, W)
     var = float(np.mean(Uw.var(axis=1, ddof=1)))
-    bias2 = max(float(np.mean((Uw.mean(1) - ti[pick]) ** 2)) - var / W, 0.0)
-    w_eq = var / max(err_int**2 - bias2, 1e-30)
+    # pointwise walk on stars is unbiased up to the epsilon shell: its RMSE
+    # with w walks per point is sqrt(var / w)
+    w_eq = var / err_int**2
     walks_per_s = pick.size * W / (t_pw / 1e3)
     out = {"workload": "c2mixed_channel4096_laplace", "grid": args.grid, "points_gathered": prep.n_int,
            "points_band": prep.n_band, "cache_points": sol.cache.n, "cache_offset_points": sol.extra["n_offset"],
