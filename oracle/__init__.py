@@ -37,7 +37,7 @@ class _Field(C.Structure):
 class _WalkParams(C.Structure):
     _fields_ = [("eps", C.c_double), ("max_steps", C.c_int32), ("n_walks", C.c_int32),
                 ("seed", C.c_uint64), ("batch", C.c_uint32), ("control_variate", C.c_int32),
-                ("sigma", C.c_double)]
+                ("sigma", C.c_double), ("open_center", C.c_double * 3), ("open_radius", C.c_double)]
 
 
 _lib = None
@@ -116,6 +116,8 @@ def lib():
                                      C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _ip]
         L.orc_silhouette_distances.argtypes = [C.c_void_p, C.c_int64, _dp, _dp]
         L.orc_silhouette_distances.restype = None
+        L.orc_sphere_reentry.argtypes = [_dp, C.c_double, _dp, C.c_double, C.c_double, C.c_double, _dp]
+        L.orc_sphere_reentry.restype = C.c_int
         L.orc_sample_mixed.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_uint64,
                                        C.c_uint32, _dp, _dp, _dp, _dp, _dp, _ip, _ip]
         L.orc_sample_mixed.restype = C.c_int64
@@ -285,8 +287,15 @@ class Scene:
         return y, sw
 
 
-def walk_params(eps, n_walks, seed, batch=0, max_steps=1024, control_variate=True, sigma=0.0):
+def walk_params(eps, n_walks, seed, batch=0, max_steps=1024, control_variate=True, sigma=0.0, open_sphere=None):
+    """open_sphere = (center, radius): an open 3D domain whose boundary the
+    sphere encloses (Appendix B); walks outside it escape or re-enter."""
     P = _WalkParams()
+    if open_sphere is not None:
+        c, r = open_sphere
+        for a in range(3):
+            P.open_center[a] = float(c[a])
+        P.open_radius = float(r)
     P.sigma = float(sigma)
     P.eps = float(eps)
     P.max_steps = int(max_steps)
@@ -645,3 +654,22 @@ def silhouette_distances(neu_scene: Scene, x):
     d = np.zeros(x.shape[0])
     lib().orc_silhouette_distances(neu_scene.h, x.shape[0], _d(x), _d(d))
     return d
+
+
+def sphere_reentry(center, radius, x, u, v, w):
+    """orc_sphere_reentry for each row of x (n, 3) with uniforms u, v, w (n):
+    returns (escaped (n,) bool, y (n, 3); NaN rows where escaped)."""
+    L = lib()
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    c = np.ascontiguousarray(center, dtype=np.float64)
+    n = x.shape[0]
+    esc = np.zeros(n, dtype=bool)
+    y = np.full((n, 3), np.nan)
+    yb = np.zeros(3)
+    for i in range(n):
+        e = L.orc_sphere_reentry(c.ctypes.data_as(_dp), float(radius), x[i].ctypes.data_as(_dp), float(u[i]),
+                                 float(v[i]), float(w[i]), yb.ctypes.data_as(_dp))
+        esc[i] = bool(e)
+        if not e:
+            y[i] = yb
+    return esc, y

@@ -1236,6 +1236,58 @@ static void read_point(int dim, const double* pos, const double* pb, double d, d
   for (int a = 0; a < dim; ++a) e[a] = pb[a] + t * (pos[a] - pb[a]);
 }
 
+/* Open (unbounded) 3D domains, Appendix B.  Outside a sphere B(c, Rb) that
+ * encloses the whole boundary, Brownian motion from x (r = |x - c| > Rb) ever
+ * reaches the sphere with probability Rb / r; otherwise it escapes to
+ * infinity, where the solution vanishes.  Given that it reaches the sphere,
+ * its first hit point follows the sphere's exterior harmonic measure from x,
+ * normalised.  By the Kelvin transform that is the interior harmonic measure
+ * from the image point x* = c + (Rb/r)^2 (x - c): the distance s from x* to
+ * the hit point has density proportional to 1/s^2 on [Rb - a, Rb + a],
+ * a = Rb^2 / r.  Inverting its CDF at v and writing rho = Rb / r, m = 1 - 2v,
+ * the polar angle t of the hit point about the direction of x - c is
+ *   cos t = (m + rho (m^2 + 3)/2 + rho^2 m + rho^3 (m^2 - 1)/2) / (1 + rho m)^2,
+ * which keeps its accuracy as rho -> 0 (the hit point seen from infinity is
+ * uniform: cos t = m).  The azimuth is 2 pi w about the orthonormal frame of
+ * Duff et al. 2017 ("Building an orthonormal basis, revisited"). */
+int orc_sphere_reentry(const double* c, double Rb, const double* x, double u, double v, double w, double* y) {
+  double e[3] = {x[0] - c[0], x[1] - c[1], x[2] - c[2]};
+  double r = sqrt(dot3(e, e));
+  double rho = Rb / r;
+  if (u >= rho) return 1;
+  for (int a = 0; a < 3; ++a) e[a] /= r;
+  double m = 1 - 2 * v;
+  double q = 1 + rho * m;
+  double ct = (m + rho * (m * m + 3) / 2 + rho * rho * m + rho * rho * rho * (m * m - 1) / 2) / (q * q);
+  if (ct > 1) ct = 1;
+  if (ct < -1) ct = -1;
+  double st = sqrt(1 - ct * ct);
+  double sg = e[2] >= 0 ? 1.0 : -1.0;
+  double ha = -1 / (sg + e[2]);
+  double hb = e[0] * e[1] * ha;
+  double t1[3] = {1 + sg * e[0] * e[0] * ha, sg * hb, -sg * e[0]};
+  double t2[3] = {hb, sg + e[1] * e[1] * ha, -e[1]};
+  double ph = 2 * ORC_PI * w;
+  double cp = cos(ph), sp = sin(ph);
+  for (int a = 0; a < 3; ++a) y[a] = c[a] + Rb * (ct * e[a] + st * (cp * t1[a] + sp * t2[a]));
+  return 0;
+}
+
+/* A walk that has just jumped (jump index k) into an open domain's far
+ * region: escape (returns 1) or move onto the enclosing sphere. */
+static int open_step(const orc_walk_params* p, uint32_t k, uint32_t id, uint32_t tag, double* pos) {
+  const double* c = p->open_center;
+  double e[3] = {pos[0] - c[0], pos[1] - c[1], pos[2] - c[2]};
+  if (!(dot3(e, e) > p->open_radius * p->open_radius)) return 0;
+  double u, v, w, w2;
+  orc_uniform_pair(p->seed, k, id, p->batch, tag | 8u, &u, &v);
+  orc_uniform_pair(p->seed, k, id, p->batch, tag | 16u, &w, &w2);
+  double y[3];
+  if (orc_sphere_reentry(c, p->open_radius, pos, u, v, w, y)) return 1;
+  for (int a = 0; a < 3; ++a) pos[a] = y[a];
+  return 0;
+}
+
 void orc_walk(const orc_scene* s, const orc_field* g, const orc_field* f,
               const orc_walk_params* p, int mode, const double* x, const double* n, double R0,
               const double* xbar, uint32_t id, double* U, double* grad, double* exit_pt,
@@ -1261,6 +1313,8 @@ void orc_walk(const orc_scene* s, const orc_field* g, const orc_field* f,
   double nu0[3], pos[3];
   walk_direction(p->seed, 0, id, p->batch, tag, dim, nu0);
   for (int a = 0; a < dim; ++a) pos[a] = x[a] + R0 * nu0[a];
+  const int open = dim == 3 && p->open_radius > 0;
+  int escaped = open && open_step(p, 0, id, tag, pos);
   double f_u = 0, f_g = 0, yhat_g[3] = {0, 0, 0};
   if (has_f) {
     double yu[3];
@@ -1287,6 +1341,12 @@ void orc_walk(const orc_scene* s, const orc_field* g, const orc_field* f,
   double S = 0, W = 0, pb[3] = {0, 0, 0}, thr = 1.0;
   int32_t k;
   for (k = 1;; ++k) {
+    if (escaped) {
+      /* u = 0 at infinity */
+      W = S;
+      for (int a = 0; a < dim; ++a) pb[a] = NAN;
+      break;
+    }
     double d;
     orc_closest(s, pos, 0, &d, pb, NULL);
     if (d < p->eps || k >= p->max_steps) {
@@ -1306,6 +1366,7 @@ void orc_walk(const orc_scene* s, const orc_field* g, const orc_field* f,
     double nu[3];
     walk_direction(p->seed, (uint32_t)k, id, p->batch, tag, dim, nu);
     for (int a = 0; a < dim; ++a) pos[a] += d * nu[a];
+    if (open) escaped = open_step(p, (uint32_t)k, id, tag, pos);
   }
   *steps = k;
   double gw = dim / R0;
@@ -1316,6 +1377,8 @@ void orc_walk(const orc_scene* s, const orc_field* g, const orc_field* f,
   } else {
     *U = W - R0 * R0 / (2.0 * dim) * f_u;
   }
+  /* the escape rule holds for the Laplace equation without a source only */
+  if (open && (screened || has_f)) *U = NAN;
   double c = p->control_variate ? orc_field_eval(g, dim, xbar) : 0.0;
   double wn = 0;
   for (int a = 0; a < dim; ++a) {

@@ -139,13 +139,24 @@ typedef struct {
   uint32_t batch;
   int32_t control_variate; /* subtract g(xbar) in the gradient estimate */
   double sigma;            /* screening coefficient of Lap u - sigma u = f (Eq. 1); 0: Poisson */
+  double open_center[3];   /* open (unbounded) 3D domain, Appendix B: a sphere that */
+  double open_radius;      /* encloses the whole boundary; 0 = bounded domain */
 } orc_walk_params;
+
+/* Open 3D domains (Appendix B): from x outside the sphere B(c, Rb), u < Rb/|x-c|
+ * reaches the sphere (returns 0 and writes the first point hit, from the
+ * uniforms v, w); otherwise the path escapes to infinity (returns 1). */
+int orc_sphere_reentry(const double* c, double Rb, const double* x, double u, double v, double w, double* y);
 
 /* One walk.  mode 0: cache walk (tag 1, first ball without termination test);
  * mode 1: pointwise walk (tag 2, returns g(xbar) when R0 < eps).  With
  * p->sigma > 0 (screened, source term must be zero) every ball multiplies the
  * estimate by orc_screen_ball_weight and the gradient uses
  * orc_screen_grad_weight instead of dim/R0; U is NaN if a source is given.
+ * With p->open_radius > 0 (3D, Laplace, no source) a walk that lands outside
+ * the enclosing sphere draws orc_sphere_reentry's uniforms from the Philox
+ * counters (jump index, id, batch, tag | 8) and (..., tag | 16); an escaped walk
+ * takes u = 0 at infinity and reports a NaN exit point.
  * Outputs U (solution sample), grad (dim; gradient sample), exit point,
  * first-step weight (dim/R0)*(nu . n) (cache mode), steps, capped flag. */
 void orc_walk(const orc_scene* s, const orc_field* g, const orc_field* f,

@@ -538,6 +538,38 @@ def problem_c3(n_eval_box: int = 2_320_000, slice_n: int = 256, level: int = 6) 
                    extra={"n_box": n_eval_box, "n_slice": sl3.shape[0]})
 
 
+def exterior_of(sc: Scene, name: str = "") -> Scene:
+    """The open domain outside a closed 3D mesh (Appendix B): the same
+    triangles with their orientation reversed, so that normals point into
+    the solid (out of the domain) and the pseudonormal inside test selects
+    the exterior."""
+    return Scene(sc.dim, sc.verts.copy(), sc.prims[:, [0, 2, 1]].copy(), name or sc.name + "_exterior")
+
+
+def enclosing_sphere(sc: Scene, margin: float = 0.05):
+    """Centre and radius of a sphere about the bounding-box centre that holds
+    every vertex (hence every triangle) with a relative margin."""
+    c = 0.5 * (sc.verts.min(0) + sc.verts.max(0))
+    return c, float(np.linalg.norm(sc.verts - c, axis=1).max() * (1 + margin))
+
+
+def problem_c3_open(n_eval_box: int = 2_320_000, level: int = 6) -> Problem:
+    """The exterior of the displaced icosphere of the 3D Laplace workload: an
+    open domain (Appendix B) with u -> 0 at infinity, Dirichlet data from the
+    decaying potential u = 1/|x - q| of a point q inside the solid (the exact
+    solution), evaluation points drawn uniformly in the box [-2, 2]^3 (those
+    inside the solid are classified out)."""
+    solid = displaced_icosphere(level, seed(3, 1))
+    sc = exterior_of(solid, "c3o_dispsphere_exterior")
+    g = point_source(1.0, (0.1, -0.05, 0.07))
+    eps = 1e-3 * sc.diagonal
+    pts = uniform_box(n_eval_box, (-2.0, -2.0, -2.0), (2.0, 2.0, 2.0), seed(3, 11)) if n_eval_box else np.zeros((0, 3))
+    c, r = enclosing_sphere(sc)
+    return Problem("c3o_dispsphere_exterior", sc, g, Field(), 65536, 512, eps, 5 * eps, 0, pts, g, sides=1,
+                   precision="f32", seed_walks=seed(3, 12), seed_cache=seed(3, 13), seed_sources=seed(3, 14),
+                   extra={"n_box": n_eval_box, "n_slice": 0, "open_sphere": (c, r)})
+
+
 def problem_c3_screened(sigma: float = 4.0, n_eval_box: int = 2_320_000) -> Problem:
     """The displaced icosphere of the 3D Laplace workload with the screened
     equation Lap u = sigma u (Eq. 1, f = 0) and the plane wave u = exp(a.x),
