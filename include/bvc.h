@@ -257,6 +257,28 @@ typedef struct {
                               weight dim/R0 becomes s/I1(sR0) in 2D and
                               s/i1(sR0) in 3D, i1(x) = (x cosh x - sinh x)/x^2.
                               Not taken by the batch and clamping calls. */
+  double open_center[3];   /* open (unbounded) 3D domains (Appendix B): the centre */
+  double open_radius;      /* and radius of a sphere that encloses every vertex of
+                              the scene; 0 = a bounded domain.  The domain is the
+                              side of the mesh its pseudonormals call inside: for
+                              the exterior of a closed solid, give its triangles
+                              reversed.  A walk that jumps (jump index k) to
+                              r = |x - c| > radius draws the Philox uniforms
+                              (u, v) of counter (k, id, batch, tag | 8) and w of
+                              (k, id, batch, tag | 16), tag = 1 for cache walks and
+                              2 for pointwise walks; it escapes to infinity, where
+                              u = 0, when u >= radius / r (the probability that
+                              Brownian motion from x never reaches the sphere is
+                              1 - radius / r), else it moves to the first point
+                              of the sphere it reaches: the sphere's exterior
+                              harmonic measure from x, sampled in closed form
+                              through the Kelvin transform (polar angle from v,
+                              azimuth 2 pi w).  An escaped walk's exit record is
+                              NaN and its boundary value 0.  Laplace only (sigma
+                              = 0, f = ZERO); taken by the cache, pointwise and
+                              tuning walk calls, refused (BVC_EUNSUPPORTED) by
+                              the batch, clamping and walk-on-stars calls;
+                              BVC_EINVAL when the sphere leaves out a vertex. */
 } bvc_walk_params;
 
 /* Walk j of cache point i has id i*W + j (n_cache*W < 2^32).  Each walk takes

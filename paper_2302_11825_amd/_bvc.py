@@ -46,7 +46,8 @@ class bvc_walk_params(C.Structure):
     _fields_ = [("eps", C.c_double), ("max_steps", C.c_int32), ("n_walks", C.c_int32),
                 ("seed", C.c_uint64), ("batch", C.c_uint32), ("control_variate", C.c_int32),
                 ("dtype", C.c_int32), ("blocks", C.c_int32), ("g", bvc_field), ("f", bvc_field),
-                ("ev_begin", C.c_void_p), ("ev_end", C.c_void_p), ("sigma", C.c_double)]
+                ("ev_begin", C.c_void_p), ("ev_end", C.c_void_p), ("sigma", C.c_double),
+                ("open_center", C.c_double * 3), ("open_radius", C.c_double)]
 
 
 class bvc_cache_view(C.Structure):

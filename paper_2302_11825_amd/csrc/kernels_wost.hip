@@ -471,6 +471,7 @@ int bvc_wost_walks(bvc_scene dir, bvc_scene neu, const bvc_walk_params* p, int32
   if (rc) return rc;
   if (p->f.kind != 0 || p->sigma != 0.0)
     return fail(BVC_EUNSUPPORTED, "walk on stars takes no source term and no screening");
+  if (p->open_radius != 0.0) return fail(BVC_EUNSUPPORTED, "walk on stars is built for bounded domains");
   if (mode != 0 && mode != 1 && mode != 3) return fail(BVC_EINVAL, "mode must be 0, 1 or 3");
   if (n < 0 || (uint64_t)n * (uint64_t)p->n_walks >= (1ull << 32)) return fail(BVC_EINVAL, "n * W out of range");
   if (!counters) return fail(BVC_EINVAL, "counters is null");

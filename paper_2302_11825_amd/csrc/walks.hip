@@ -57,7 +57,48 @@ struct WalkArgs {
   unsigned long long chunk;  // walk ids per claim, 1..kChunkMax
   int open_lanes;            // leave the traversal loop at this many open queries
   double sigma;              // screening coefficient (no source term), 0 = Poisson
+  double oc[3];              // open 3D domain: sphere enclosing the boundary,
+  double orad;               // 0 = bounded domain
 };
+
+// Open 3D domains (Appendix B).  A walk that has jumped (jump index k) to
+// r = |p - oc| > orad escapes to infinity, where u = 0, with probability
+// 1 - orad / r, the chance that Brownian motion from p never reaches the
+// sphere (returns true).  Otherwise it moves to the first point of the sphere
+// it reaches, drawn from the sphere's exterior harmonic measure: by the Kelvin
+// transform, the interior harmonic measure from the image point
+// oc + (orad / r)^2 (p - oc), whose distance s to the hit point has density
+// proportional to 1 / s^2.  Its inverse CDF at v, with rho = orad / r and
+// m = 1 - 2 v, gives the cosine of the polar angle about p - oc as
+// (m + rho (m^2 + 3) / 2 + rho^2 m + rho^3 (m^2 - 1) / 2) / (1 + rho m)^2,
+// accurate as rho -> 0; the azimuth 2 pi w turns about the orthonormal frame
+// of Duff et al. (2017).  FP64 whatever the walk's precision: the step is rare.
+template <typename T>
+__device__ bool open_step(const WalkArgs& a, uint32_t k, uint32_t id, uint32_t tag, T* p) {
+  const double e0 = (double)p[0] - a.oc[0], e1 = (double)p[1] - a.oc[1], e2 = (double)p[2] - a.oc[2];
+  const double r2 = e0 * e0 + e1 * e1 + e2 * e2;
+  if (!(r2 > a.orad * a.orad)) return false;
+  double u, v, w, w2;
+  Uniform<double>::pair(a.seed, k, id, a.batch, tag | 8u, u, v);
+  Uniform<double>::pair(a.seed, k, id, a.batch, tag | 16u, w, w2);
+  const double r = sqrt(r2), rho = a.orad / r;
+  if (u >= rho) return true;
+  const double ex = e0 / r, ey = e1 / r, ez = e2 / r;
+  const double m = 1.0 - 2.0 * v, qd = 1.0 + rho * m;
+  double ct = (m + rho * (m * m + 3.0) * 0.5 + rho * rho * m + rho * rho * rho * (m * m - 1.0) * 0.5) / (qd * qd);
+  ct = fmin(fmax(ct, -1.0), 1.0);
+  const double st = sqrt(1.0 - ct * ct);
+  const double sg = ez >= 0.0 ? 1.0 : -1.0;
+  const double ha = -1.0 / (sg + ez), hb = ex * ey * ha;
+  const double t1[3] = {1.0 + sg * ex * ex * ha, sg * hb, -sg * ex};
+  const double t2[3] = {hb, sg + ey * ey * ha, -ey};
+  const double e[3] = {ex, ey, ez};
+  double sp, cp;
+  sincos(2.0 * 3.141592653589793 * w, &sp, &cp);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) p[c] = (T)(a.oc[c] + a.orad * (ct * e[c] + st * (cp * t1[c] + sp * t2[c])));
+  return false;
+}
 
 // In-walk source term in the walk's precision (constants and Gaussian sums).
 // `scale` is 1/(2 sigma^2), times log2(e) in FP32, where the Gaussian factor
@@ -336,9 +377,21 @@ __global__ __launch_bounds__(kBlock) void k_walks(WalkArgs a) {
       }
 #pragma unroll
       for (int c = 0; c < D; ++c) p[c] = fma(d, nu[c], p[c]);
-      query_begin<T, D>(S, p, k == 0 ? -1 : qs.bi, qs);
+      bool esc = false;
+      if constexpr (D == 3) esc = a.orad > 0.0 && open_step<T>(a, (uint32_t)k, id, tag, p);
+      if (!esc) query_begin<T, D>(S, p, k == 0 ? -1 : qs.bi, qs);
       ++k;
       jump = false;
+      if (esc) {
+        // escaped to infinity: a NaN exit record, read as u = 0 by the finish
+#pragma unroll
+        for (int c = 0; c < D; ++c) EX[(size_t)c * a.ld + id] = T(NAN);
+        U[id] = acc_s + usrc;
+        if (a.steps) a.steps[id] = k;
+        steps_acc += (unsigned long long)k;
+        ++walks_acc;
+        active = false;
+      }
     }
     if (!__any(active)) {
       if (exhausted) break;
@@ -450,12 +503,12 @@ __global__ __launch_bounds__(kBlock) void k_finish(FieldDev g, int cv, uint64_t 
       float q[D];
 #pragma unroll
       for (int e = 0; e < D; ++e) q[e] = EX[(size_t)e * total + id];
-      gq = field_value_f32(g, D, q);
+      gq = isnan(q[0]) ? 0.0 : field_value_f32(g, D, q);  // NaN: escaped, u = 0 at infinity
     } else {
       double q[D];
 #pragma unroll
       for (int e = 0; e < D; ++e) q[e] = (double)EX[(size_t)e * total + id];
-      gq = field_value(g, D, q);
+      gq = isnan(q[0]) ? 0.0 : field_value(g, D, q);
     }
     const double su = (double)U[id];
     double w_est = gq + su, u_est = gq + su, ratio = 1.0;
@@ -536,7 +589,9 @@ __global__ __launch_bounds__(kBlock) void k_reduce(int64_t n, int W, int rows, i
   }
 }
 
-int check_walk_params(const bvc_walk_params* p, int dim) {
+// h: the scene of a call that takes open domains (cache, pointwise and
+// tuning walks); null for the calls that refuse them.
+int check_walk_params(const bvc_walk_params* p, int dim, const SceneHost* h = nullptr) {
   if (!p) return fail(BVC_EINVAL, "walk params are null");
   if (!(p->eps > 0) || !std::isfinite(p->eps)) return fail(BVC_EINVAL, "eps must be positive");
   if (p->max_steps < 1) return fail(BVC_EINVAL, "max_steps must be >= 1");
@@ -551,6 +606,21 @@ int check_walk_params(const bvc_walk_params* p, int dim) {
   if (!(p->sigma >= 0.0) || !std::isfinite(p->sigma)) return fail(BVC_EINVAL, "sigma must be finite and >= 0");
   if (p->sigma > 0.0 && p->f.kind != 0)
     return fail(BVC_EUNSUPPORTED, "screened walks take no source term (f must be ZERO)");
+  if (p->open_radius != 0.0) {
+    if (!h) return fail(BVC_EUNSUPPORTED, "open domains are taken by the cache, pointwise and tuning walks only");
+    if (dim != 3) return fail(BVC_EUNSUPPORTED, "open domains are built in 3D");
+    if (p->sigma != 0.0 || p->f.kind != 0)
+      return fail(BVC_EUNSUPPORTED, "open domains take the Laplace equation without a source");
+    const double R = p->open_radius;
+    if (!(R > 0.0) || !std::isfinite(R)) return fail(BVC_EINVAL, "open_radius must be positive and finite");
+    for (int c = 0; c < 3; ++c)
+      if (!std::isfinite(p->open_center[c])) return fail(BVC_EINVAL, "open_center must be finite");
+    for (size_t v = 0; v + 2 < h->V.size(); v += 3) {
+      const double x = h->V[v] - p->open_center[0], y = h->V[v + 1] - p->open_center[1],
+                   z = h->V[v + 2] - p->open_center[2];
+      if (!(x * x + y * y + z * z < R * R)) return fail(BVC_EINVAL, "the open-domain sphere must enclose every vertex");
+    }
+  }
   return BVC_OK;
 }
 
@@ -596,6 +666,8 @@ int run_walks(bvc_scene s, const bvc_walk_params* p, int mode, int64_t n, WalkAr
   a.f = to_dev(p->f);
   a.eps = p->eps;
   a.sigma = p->sigma;
+  for (int c = 0; c < 3; ++c) a.oc[c] = p->open_center[c];
+  a.orad = p->open_radius;
   a.max_steps = p->max_steps;
   a.W = mode == 2 ? 1 : p->n_walks;
   a.seed = p->seed;
@@ -878,7 +950,7 @@ int cache_walks_entry(bvc_scene s, const bvc_walk_params* p, int64_t n_cache, co
                       int32_t* rec_steps, uint64_t* counters, void* stream, const WalkShape* force) {
   int rc = check_scene(s);
   if (rc) return rc;
-  rc = check_walk_params(p, s->h.dim);
+  rc = check_walk_params(p, s->h.dim, &s->h);
   if (rc) return rc;
   if (n_cache < 0) return fail(BVC_EINVAL, "n_cache must be >= 0");
   if ((uint64_t)n_cache * (uint64_t)p->n_walks >= (1ull << 32)) return fail(BVC_EINVAL, "n_cache * W >= 2^32");
@@ -1037,7 +1109,7 @@ int bvc_tune_walks(bvc_scene s, const bvc_walk_params* p, int64_t n_cache, const
                    uint64_t* counters, int32_t reps, int32_t* blocks_per_cu, int32_t* open_lanes, void* stream) {
   int rc = check_scene(s);
   if (rc) return rc;
-  rc = check_walk_params(p, s->h.dim);
+  rc = check_walk_params(p, s->h.dim, &s->h);
   if (rc) return rc;
   if (reps < 1) return fail(BVC_EINVAL, "reps must be >= 1");
   bvc_walk_params q = *p;
@@ -1106,7 +1178,7 @@ int bvc_pointwise_wos(bvc_scene s, const bvc_walk_params* p, int64_t n, const vo
   int rc = check_scene(s);
   if (rc) return rc;
   const int dim = s->h.dim;
-  rc = check_walk_params(p, dim);
+  rc = check_walk_params(p, dim, &s->h);
   if (rc) return rc;
   if (n < 0) return fail(BVC_EINVAL, "n must be >= 0");
   if ((uint64_t)n * (uint64_t)p->n_walks >= (1ull << 32)) return fail(BVC_EINVAL, "n * W >= 2^32");

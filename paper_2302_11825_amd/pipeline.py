@@ -139,9 +139,16 @@ def candidates_for(sc: Scene, n_target, l, sides, seed, pilot=65536):
 
 
 def walk_params(eps, n_walks, seed, g: DeviceField, f: Optional[DeviceField], dtype="f32", batch=0,
-                max_steps=1024, control_variate=True, blocks=0, sigma=0.0) -> B.bvc_walk_params:
+                max_steps=1024, control_variate=True, blocks=0, sigma=0.0, open_sphere=None) -> B.bvc_walk_params:
+    """open_sphere = (centre, radius) of a sphere enclosing the scene: an open
+    3D domain (Appendix B), whose walks escape to infinity or re-enter."""
     p = B.bvc_walk_params()
     p.sigma = float(sigma)
+    if open_sphere is not None:
+        c, r = open_sphere
+        for a in range(3):
+            p.open_center[a] = float(c[a])
+        p.open_radius = float(r)
     p.eps = float(eps)
     p.max_steps = int(max_steps)
     p.n_walks = int(n_walks)
@@ -660,7 +667,8 @@ def tune(prep: Prepared, with_grad=True, reps=3) -> dict:
     p, sc, dt = prep.p, prep.sc, prep.dtype
     T, d = DT[dt], sc.dim
     cache = sample_cache(sc, prep.n_cand, p.offset, p.sides, p.seed_cache, 0)
-    wp = walk_params(p.eps, p.n_walks, p.seed_walks, prep.g, prep.f, dt, 0, sigma=p.sigma)
+    wp = walk_params(p.eps, p.n_walks, p.seed_walks, prep.g, prep.f, dt, 0, sigma=p.sigma,
+                     open_sphere=p.extra.get("open_sphere"))
     n, W = cache.n, p.n_walks
     U = torch.empty(max(n * W, 1), dtype=T, device=sc.device)
     D = torch.empty_like(U)
@@ -686,7 +694,8 @@ def solve(prep: Prepared, batch=0, with_grad=True, n_walks_band=None, records=Fa
     watch = watch or _NoWatch()
     with watch.stage("sample_cache"):
         cache = sample_cache(sc, prep.n_cand, p.offset, p.sides, p.seed_cache, batch)
-    wp = walk_params(p.eps, p.n_walks, p.seed_walks, prep.g, prep.f, dt, batch, sigma=p.sigma)
+    osph = p.extra.get("open_sphere")
+    wp = walk_params(p.eps, p.n_walks, p.seed_walks, prep.g, prep.f, dt, batch, sigma=p.sigma, open_sphere=osph)
     watch.kernel("k_walks_cache", wp)
     with watch.stage("cache_walks"):
         U, D, rec, counters = cache_walks(sc, cache, wp, dt, records)
@@ -709,7 +718,7 @@ def solve(prep: Prepared, batch=0, with_grad=True, n_walks_band=None, records=Fa
         gathered.record()
     Wb = n_walks_band or p.n_walks
     nb = prep.n_band
-    wpb = walk_params(p.eps, Wb, p.seed_walks, prep.g, prep.f, dt, batch, sigma=p.sigma)
+    wpb = walk_params(p.eps, Wb, p.seed_walks, prep.g, prep.f, dt, batch, sigma=p.sigma, open_sphere=osph)
     watch.kernel("k_walks_band", wpb)
     with watch.stage("band_walks"):
         u_band, g_band, pwc = pointwise(sc, wpb, prep.x_band[:, :nb] if nb else prep.x_band[:, :0], with_grad)
