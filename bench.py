@@ -53,7 +53,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4a", "c4b", "c2clamp", "c3clamp", "c3screen", "c2roi",
-                                                    "c2mixed", "c2screen", "c2slit"],
+                                                    "c2mixed", "c2screen", "c2slit", "c3open"],
                     help="c2 prints the benchmark line; the others print their own measurement lines")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes (no autotuning)")
     ap.add_argument("--clamp-c", type=float, default=20.0, help="c2clamp: bound c of dG/dn (Eq. 9)")

@@ -235,9 +235,8 @@ WalkShape tuned_shape(const WalkClass& k) {
   return it == g_walk_shape.end() ? default_shape(k.dim) : it->second;
 }
 
-template <typename T, int D, bool SRC, int MODE>
-__global__ __launch_bounds__(kBlock) void k_walks(WalkArgs a) {
-  extern __shared__ uint32_t lds[];
+template <typename T, int D, bool SRC, int MODE, bool OPEN>
+__device__ __forceinline__ void walks_body(const WalkArgs& a, uint32_t* lds) {
   uint32_t* stk = lds + threadIdx.x;
   const int stride = blockDim.x;
   const int lane = threadIdx.x & 63;
@@ -378,7 +377,7 @@ __global__ __launch_bounds__(kBlock) void k_walks(WalkArgs a) {
 #pragma unroll
       for (int c = 0; c < D; ++c) p[c] = fma(d, nu[c], p[c]);
       bool esc = false;
-      if constexpr (D == 3) esc = a.orad > 0.0 && open_step<T>(a, (uint32_t)k, id, tag, p);
+      if constexpr (OPEN) esc = open_step<T>(a, (uint32_t)k, id, tag, p);
       if (!esc) query_begin<T, D>(S, p, k == 0 ? -1 : qs.bi, qs);
       ++k;
       jump = false;
@@ -435,6 +434,20 @@ __global__ __launch_bounds__(kBlock) void k_walks(WalkArgs a) {
     atomicAdd(&a.counters[2], capped_acc);
     atomicAdd(&a.counters[3], walks_acc);
   }
+}
+
+// Walks in bounded domains, and (3D, Laplace, no source) in open domains,
+// whose extra step stays out of the bounded kernels.
+template <typename T, int D, bool SRC, int MODE>
+__global__ __launch_bounds__(kBlock) void k_walks(WalkArgs a) {
+  extern __shared__ uint32_t lds[];
+  walks_body<T, D, SRC, MODE, false>(a, lds);
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_walks_open(WalkArgs a) {
+  extern __shared__ uint32_t lds[];
+  walks_body<T, 3, false, MODE, true>(a, lds);
 }
 
 // i1(x) = (x cosh x - sinh x) / x^2, the modified spherical Bessel function
@@ -626,6 +639,14 @@ int check_walk_params(const bvc_walk_params* p, int dim, const SceneHost* h = nu
 
 template <typename T, int D>
 void launch_walks(const WalkArgs& args, int mode, bool src, int blocks, size_t lds, hipStream_t st) {
+  if constexpr (D == 3) {
+    // open domains: validated as 3D, source-free, modes 0 and 1
+    if (args.orad > 0.0) {
+      if (mode == 0) hipLaunchKernelGGL((k_walks_open<T, 0>), dim3(blocks), dim3(kBlock), lds, st, args);
+      else hipLaunchKernelGGL((k_walks_open<T, 1>), dim3(blocks), dim3(kBlock), lds, st, args);
+      return;
+    }
+  }
   if (mode == 0) {
     if (src) hipLaunchKernelGGL((k_walks<T, D, true, 0>), dim3(blocks), dim3(kBlock), lds, st, args);
     else hipLaunchKernelGGL((k_walks<T, D, false, 0>), dim3(blocks), dim3(kBlock), lds, st, args);

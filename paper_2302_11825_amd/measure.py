@@ -12,6 +12,8 @@
     python bench.py --workload c3clamp --clamp-c 1600   the same on the 3D Laplace step
     python bench.py --workload c3screen  the 3D step on the screened equation (sigma = 4)
     python bench.py --workload c2screen  the 2D step on the screened equation (sigma = 4)
+    python bench.py --workload c3open    the 3D step outside the displaced icosphere, an open
+                                     domain (Appendix B), u = 1/|x - q|
     python bench.py --workload c2slit    double-sided Dirichlet data on a cut disk (Appendix B)
     python bench.py --workload c2roi     the 2D Poisson problem cached on the boundary of a
                                      disk inside the star (region of interest, Section 3.2)
@@ -64,7 +66,7 @@ def _log(msg):
 def run(args):
     {"c3": c3, "c4a": c4a, "c4b": c4b, "c2clamp": c2clamp, "c3clamp": c3clamp,
      "c3screen": c3screen, "c2roi": c2roi, "c2mixed": c2mixed, "c2screen": c2screen,
-     "c2slit": c2slit}[args.workload](args)
+     "c2slit": c2slit, "c3open": c3open}[args.workload](args)
 
 
 def _c3_setup(args, prob=None):
@@ -82,6 +84,14 @@ def c3screen(args):
     """The 3D step on the screened equation Lap u = sigma u (sigma = 4) with the
     plane wave exp(a.x) as data and solution."""
     c3(args, wl.problem_c3_screened())
+
+
+def c3open(args):
+    """The 3D Laplace step in the exterior of the displaced icosphere, an open
+    domain (Appendix B): walks escape to infinity (u = 0) or re-enter on a
+    sphere enclosing the mesh; data and solution u = 1/|x - q|, q inside the
+    solid; evaluation points uniform in [-2, 2]^3."""
+    c3(args, wl.problem_c3_open())
 
 
 def c2slit(args):
