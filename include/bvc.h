@@ -515,7 +515,9 @@ int bvc_gather_backward(int32_t dim, const bvc_cache_view* cache,
  * E[i*nb+m] = (1/W) sum_j phi_m(exit_ij),
  * F[i*nb+m] = (1/W) sum_j w1_ij (phi_m(exit_ij) - cv phi_m(xbar_i)),
  * so that u-hat = E theta and du/dn-hat = F theta for g = sum theta_m phi_m.
- * rec_exit, rec_w1 as written by bvc_cache_walks (dtype); E, F FP64. */
+ * rec_exit, rec_w1 as written by bvc_cache_walks (dtype); E, F FP64.
+ * A NaN exit record (a walk that escaped an open domain) has phi_m = 0 for
+ * every m: u = 0 at infinity whatever the data. */
 int bvc_basis_means(const bvc_field* basis, int32_t dim, int64_t n_cache, int32_t W,
                     int32_t dtype, const void* rec_exit, const void* rec_w1, const double* xbar,
                     int32_t cv, double* E, double* F, void* stream);

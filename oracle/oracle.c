@@ -1642,7 +1642,10 @@ void orc_basis_means(const orc_field* basis, int dim, int64_t n_cache, int32_t W
       double se = 0, sf = 0;
       for (int32_t j = 0; j < W; ++j) {
         int64_t id = i * W + j;
-        double phi = orc_basis_eval(basis, dim, m, exit_pt + id * dim);
+        /* a walk that escaped an open domain (NaN exit) reads u = 0 at
+         * infinity whatever the data: every basis value is 0 there */
+        const double* e = exit_pt + id * dim;
+        double phi = isnan(e[0]) ? 0.0 : orc_basis_eval(basis, dim, m, e);
         se += phi;
         sf += w1[id] * (phi - base);
       }

@@ -767,7 +767,8 @@ __global__ void k_basis_means(FieldDev F, int nb, int64_t n_cache, int W, const 
     const int64_t id = i * W + j;
     double q[D];
     for (int c = 0; c < D; ++c) q[c] = (double)ex[c * total + id];
-    const double phi = basis_single(F, D, m, q);
+    // NaN: the walk escaped an open domain, where u = 0 for any data
+    const double phi = isnan(q[0]) ? 0.0 : basis_single(F, D, m, q);
     se += phi;
     sf += (double)w1[id] * (phi - base);
   }
@@ -836,7 +837,13 @@ __global__ void k_basis_means_sh(int L, int nb, int64_t n_cache, int W, const T*
   for (int j = 0; j < W; ++j) {
     const int64_t id = i * W + j;
     const double q[3] = {(double)ex[id], (double)ex[total + id], (double)ex[2 * total + id]};
-    sh_chain_values(m, part, L, dfact, q, v);
+    if (isnan(q[0])) {
+      // escaped an open domain: every basis value is 0 at infinity
+#pragma unroll
+      for (int k = 0; k <= kMaxChainL; ++k) v[k] = 0.0;
+    } else {
+      sh_chain_values(m, part, L, dfact, q, v);
+    }
     const double w = (double)w1[id];
 #pragma unroll
     for (int k = 0; k <= kMaxChainL; ++k) {

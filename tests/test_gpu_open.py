@@ -11,6 +11,9 @@ sphere enclosing the mesh, against the FP64 oracle through the C-ABI
 - FP32 cache walks against the FP64 oracle walks on the same streams
   (z-test of the mean difference).
 - The whole step outside the displaced sphere recovers u = 1/|x - q|.
+- Basis means (adjoint and multi-field paths): escaped walks count as u = 0;
+  device on the oracle's records matches the oracle, and E theta, F theta
+  reproduce the walks of g = sum theta_m phi_m.
 - Refusals: a sphere that leaves out a vertex, a source, screening, 2D
   scenes, the batch and walk-on-stars calls.
 """
@@ -172,3 +175,46 @@ def test_open_domain_refusals(B):
     with pytest.raises(RuntimeError, match="3D"):
         pl.cache_walks(sc2, c2, wp, "f32")
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("lmax", [8, 10])
+def test_open_basis_means_fp64(B, orc, lmax):
+    """Basis means of the adjoint and multi-field paths on open-domain walks:
+    an escaped walk contributes 0 to every basis mean (u = 0 at infinity) and
+    its control-variate term to F.  The device kernel on the oracle's records
+    matches the oracle; E theta and F theta reproduce the walks of
+    g = sum theta_m phi_m on the same streams (the escapes do not depend on g)."""
+    _bvc, pl = B
+    say(f"open-domain basis means lmax {lmax}")
+    scene, sc, _, sph = _case(pl)
+    nb = (lmax + 1) ** 2
+    theta = np.random.default_rng(8).normal(0, 1, nb)
+    basis, g = wl.solid_harmonics_3d(np.zeros(nb), lmax), wl.solid_harmonics_3d(theta, lmax)
+    eps, l, W = 1e-3, 2e-2, 8
+    cache = pl.sample_cache(sc, 500, l, 1, 7, 0)
+    gd = pl.DeviceField(g)  # the walk parameters hold only its device pointer
+    U, D, rec, _ = pl.cache_walks(sc, cache, pl.walk_params(eps, W, 17, gd, None, "f64", open_sphere=sph), "f64",
+                                  records=True)
+    bd = pl.DeviceField(basis)
+    E = torch.empty(cache.n, nb, dtype=torch.float64, device="cuda")
+    F = torch.empty_like(E)
+    _bvc.bvc_basis_means(bd.c(), 3, cache.n, W, _bvc.F64, rec["exit"], rec["w1"], cache.xbar, 1, E, F)
+    osc = orc.Scene(scene)
+    cn = oracle_cache(osc.sample_cache(500, l, 1, 7, 0), cache)
+    ref = orc.cache_walks(osc, g, None, orc.walk_params(eps, W, 17, open_sphere=sph), cn, records=True)
+    assert np.isnan(ref["exit"][:, 0]).sum() >= 5
+    Eo, Fo = orc.basis_means(basis, 3, ref["exit"], ref["w1"], cn["xbar"], W)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a.T if a.ndim == 2 else a)).to("cuda")
+    E2, F2 = torch.empty_like(E), torch.empty_like(F)
+    _bvc.bvc_basis_means(bd.c(), 3, cache.n, W, _bvc.F64, dev(ref["exit"]), dev(ref["w1"]), dev(cn["xbar"]), 1,
+                         E2, F2)
+    torch.cuda.synchronize()
+    assert np.all(np.isfinite(E.cpu().numpy())) and np.all(np.isfinite(F.cpu().numpy()))
+    assert np.allclose(E2.cpu().numpy(), Eo, rtol=1e-10, atol=1e-11)
+    assert np.allclose(F2.cpu().numpy(), Fo, rtol=1e-9, atol=1e-9)
+    Um = U.cpu().numpy()[: cache.n * W].reshape(-1, W).mean(1)
+    Dm = D.cpu().numpy()[: cache.n * W].reshape(-1, W).mean(1)
+    s_u, s_d = np.sqrt(np.mean(Um**2)), np.sqrt(np.mean(Dm**2))
+    say(f"  escaped {np.isnan(ref['exit'][:, 0]).mean():.4f}; |E theta - U| {np.abs(E.cpu().numpy() @ theta - Um).max():.3g}")
+    assert np.allclose(E.cpu().numpy() @ theta, Um, rtol=0, atol=1e-9 * s_u)
+    assert np.allclose(F.cpu().numpy() @ theta, Dm, rtol=0, atol=1e-9 * s_d)
