@@ -147,10 +147,8 @@ int bvc_cache_measure(bvc_scene scene, double l, int32_t sides, double* measure)
  * and it lies inside (2D: nonzero winding number; 3D: pseudonormal sign).
  * Outputs (FP64 device, [dim][n] or [n]): x, unit outward normal of the
  * region {d > l} (towards the closest boundary point), weight w = measure/n,
- * xbar, distance R0, accept flag (int32 0/1).  xbar is the closest boundary
- * point q seen from the candidate, q + 1e-3 (x - q): the control variate
- * c = g(xbar) of its walks reads the data on the candidate's own side of a
- * boundary with double-sided conditions (Appendix B). */
+ * xbar (the closest boundary point, where the control variate c = g(xbar) of
+ * the point's walks reads the data), distance R0, accept flag (int32 0/1). */
 int bvc_sample_cache(bvc_scene scene, int64_t n, double l, int32_t sides, uint64_t seed,
                      uint32_t batch, double* x, double* nrm, double* w, double* xbar, double* R0,
                      int32_t* accept, void* stream);
@@ -162,7 +160,6 @@ int bvc_sample_cache(bvc_scene scene, int64_t n, double l, int32_t sides, uint64
  * id k, tag 6; the second places it inside a triangle), with the primitive's
  * unit outward normal (CCW segments, outward-wound triangles) and weight
  * |dR|/n.  R0 and xbar: distance and closest point on the domain boundary
- * (xbar seen from the sample, as in bvc_sample_cache)
  * `dom` (where the walks run); accept = 1 when the point lies strictly inside
  * the domain.  Outputs as bvc_sample_cache.  Evaluation points inside R
  * (bvc_classify on `roi` with l = 0) are then gathered from this cache; the
@@ -181,19 +178,24 @@ int bvc_sample_roi(bvc_scene dom, bvc_scene roi, int64_t n, uint64_t seed, uint3
  * of `dir` (as bvc_sample_cache with sides 1) and the segments of `neu`.
  * Outputs (FP64 device, [2][n] or [n]): x; nrm = towards the closest
  * Dirichlet point on offset points, the segment's outward normal on Neumann
- * points; w = total candidate measure / n; xbar = closest Dirichlet point q
- * seen from the sample, q + 1e-3 (x - q);
+ * points; w = total candidate measure / n; xbar = closest Dirichlet point;
  * R0 = distance to `full` (the first ball of a cache walk); kind (int32 [n]:
- * 0 rejected, 1 accepted offset point (distance l within 1e-9 relative,
- * inside `full` and no closer than l/100 to the Neumann part), 2 accepted
- * Neumann point (farther than l)).  The three
+ * 0 rejected, 1 accepted offset point (distance l within 1e-9 relative and
+ * inside `full`), 2 accepted Neumann point (farther than l)).
+ * junction_drop in [0, 1): offset points closer than junction_drop * l to the
+ * Neumann part are rejected as well.  0 is the plain sampler (the closed
+ * curve of Section 3.2); a positive value removes the pieces of the offset
+ * curve next to each Dirichlet / Neumann junction, whose first balls are as
+ * small as their distance to the Neumann part (the Eq. 7 estimate's
+ * variance grows like (l / R0)^2 there), at the cost of a bias equal to
+ * those pieces' share of Green's representation.  The three
  * scenes are CCW segment sets over one boundary; the first call for `dir` at
  * this l and for `neu` uploads their sampling tables and synchronises.
- * Errors: BVC_EUNSUPPORTED in 3D, BVC_EINVAL for an empty part, l <= 0 or a
- * null output. */
-int bvc_sample_mixed(bvc_scene full, bvc_scene dir, bvc_scene neu, int64_t n, double l, uint64_t seed,
-                     uint32_t batch, double* x, double* nrm, double* w, double* xbar, double* R0, int32_t* kind,
-                     void* stream);
+ * Errors: BVC_EUNSUPPORTED in 3D, BVC_EINVAL for an empty part, l <= 0,
+ * junction_drop outside [0, 1) or a null output. */
+int bvc_sample_mixed(bvc_scene full, bvc_scene dir, bvc_scene neu, int64_t n, double l, double junction_drop,
+                     uint64_t seed, uint32_t batch, double* x, double* nrm, double* w, double* xbar, double* R0,
+                     int32_t* kind, void* stream);
 
 /* Source samples (Eq. 4): m^dim jittered cells over the box [lo, hi] (host
  * arrays of dim doubles); s_j = |box|/m^dim * f(y_j) * 1[y_j inside and
@@ -279,6 +281,16 @@ typedef struct {
                               tuning walk calls, refused (BVC_EUNSUPPORTED) by
                               the batch, clamping and walk-on-stars calls;
                               BVC_EINVAL when the sphere leaves out a vertex. */
+  int32_t side_read;       /* 0: a walk reads g at its closest boundary point and
+                              the control variate c at xbar (Section 3.1).  1:
+                              the side rule for data that differ on the two
+                              sides of a boundary curve (double-sided
+                              conditions, Appendix B): an exit reads g at the
+                              closest point moved 1e-3 eps towards the walk, and
+                              c is read at xbar + 1e-3 (x - xbar), x the start
+                              point, so both read the data on the walk's own
+                              side.  Refused (BVC_EUNSUPPORTED) by the batch
+                              calls. */
 } bvc_walk_params;
 
 /* Walk j of cache point i has id i*W + j (n_cache*W < 2^32).  Each walk takes
@@ -412,7 +424,7 @@ int bvc_wost_walks(bvc_scene dir, bvc_scene neu, const bvc_walk_params* params, 
                    int32_t* steps, void* workspace, size_t workspace_bytes, uint64_t* counters, void* stream);
 
 /* ---------------------------------------------------------------------- */
-/* Bias correction of the clamped gather (Section 3.4, Eq. 8)              */
+/* Bias correction of the clamped gather (Section 3.3, Eq. 8)              */
 /* ---------------------------------------------------------------------- */
 /* Clamping dG/dn at c (bvc_gather_params.clamp_c) removes the near-boundary
  * artefacts of the gather and adds a bias equal to the second integral of
@@ -488,7 +500,8 @@ int bvc_tune_gather(int32_t dim, const bvc_cache_view* cache, const bvc_source_v
  * blocks per compute unit and traversal-loop exit thresholds of 0, 8, 16, 32
  * and 48 open lanes (the default shape first; another is kept only when at
  * least 3% faster) and keeps the choice for every later cache-walk launch of
- * the same class (dim, walk dtype, source term or not) whose params->blocks
+ * the same class (dim, walk dtype, source term or not, open domain or not,
+ * screened or not) whose params->blocks
  * is 0; pointwise walks keep their default shape.  Every shape gives the same
  * walk results (a walk's random numbers depend on its id only).  Arguments as
  * bvc_cache_walks; the outputs hold the walks' results on return.

@@ -37,7 +37,8 @@ class _Field(C.Structure):
 class _WalkParams(C.Structure):
     _fields_ = [("eps", C.c_double), ("max_steps", C.c_int32), ("n_walks", C.c_int32),
                 ("seed", C.c_uint64), ("batch", C.c_uint32), ("control_variate", C.c_int32),
-                ("sigma", C.c_double), ("open_center", C.c_double * 3), ("open_radius", C.c_double)]
+                ("sigma", C.c_double), ("open_center", C.c_double * 3), ("open_radius", C.c_double),
+                ("side_read", C.c_int32)]
 
 
 _lib = None
@@ -118,8 +119,8 @@ def lib():
         L.orc_silhouette_distances.restype = None
         L.orc_sphere_reentry.argtypes = [_dp, C.c_double, _dp, C.c_double, C.c_double, C.c_double, _dp]
         L.orc_sphere_reentry.restype = C.c_int
-        L.orc_sample_mixed.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_uint64,
-                                       C.c_uint32, _dp, _dp, _dp, _dp, _dp, _ip, _ip]
+        L.orc_sample_mixed.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_double,
+                                       C.c_uint64, C.c_uint32, _dp, _dp, _dp, _dp, _dp, _ip, _ip]
         L.orc_sample_mixed.restype = C.c_int64
         L.orc_sample_roi.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_uint64, C.c_uint32, _dp, _dp, _dp,
                                      _dp, _dp, _ip]
@@ -287,10 +288,15 @@ class Scene:
         return y, sw
 
 
-def walk_params(eps, n_walks, seed, batch=0, max_steps=1024, control_variate=True, sigma=0.0, open_sphere=None):
+def walk_params(eps, n_walks, seed, batch=0, max_steps=1024, control_variate=True, sigma=0.0, open_sphere=None,
+                side_read=False):
     """open_sphere = (center, radius): an open 3D domain whose boundary the
-    sphere encloses (Appendix B); walks outside it escape or re-enter."""
+    sphere encloses (Appendix B); walks outside it escape or re-enter.
+    side_read: the side rule of double-sided data (Appendix B): exits and the
+    control variate read g just off the boundary on the walk's side; off,
+    they read it at the closest boundary point (Section 3.1)."""
     P = _WalkParams()
+    P.side_read = int(bool(side_read))
     if open_sphere is not None:
         c, r = open_sphere
         for a in range(3):
@@ -492,7 +498,7 @@ def grad_radius(u):
     return lib().orc_grad_radius(float(u))
 
 
-# --- Clamped double-layer kernel and its bias correction (Section 3.4) ------
+# --- Clamped double-layer kernel and its bias correction (Section 3.3) ------
 def clamp_radius(dim, c):
     """Distance beyond which |dG/dn| cannot exceed c."""
     return lib().orc_clamp_radius(int(dim), float(c))
@@ -634,8 +640,10 @@ def wost_walks(dir_scene: Scene, neu_scene: Scene, g, params, mode, x, nrm=None,
     return U, D, st
 
 
-def sample_mixed(full: Scene, dir_scene: Scene, neu_scene: Scene, n, l, seed, batch=0):
-    """Cache candidates on the offset Dirichlet boundary and the Neumann part."""
+def sample_mixed(full: Scene, dir_scene: Scene, neu_scene: Scene, n, l, seed, batch=0, junction_drop=0.0):
+    """Cache candidates on the offset Dirichlet boundary and the Neumann part.
+    junction_drop > 0 also rejects offset points closer than junction_drop * l
+    to the Neumann part (0: the plain sampler)."""
     x = np.zeros((n, 2))
     nrm = np.zeros((n, 2))
     w = np.zeros(n)
@@ -643,7 +651,8 @@ def sample_mixed(full: Scene, dir_scene: Scene, neu_scene: Scene, n, l, seed, ba
     R0 = np.zeros(n)
     ty = np.zeros(n, np.int32)
     acc = np.zeros(n, np.int32)
-    na = lib().orc_sample_mixed(full.h, dir_scene.h, neu_scene.h, n, float(l), int(seed), int(batch), _d(x), _d(nrm),
+    na = lib().orc_sample_mixed(full.h, dir_scene.h, neu_scene.h, n, float(l), float(junction_drop), int(seed),
+                                int(batch), _d(x), _d(nrm),
                                 _d(w), _d(xb), _d(R0), _i(ty), _i(acc))
     return dict(x=x, n=nrm, w=w, xbar=xb, R0=R0, type=ty, accept=acc.astype(bool), n_accepted=na)
 

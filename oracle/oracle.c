@@ -67,13 +67,6 @@ void orc_uniform_pair(uint64_t seed, uint32_t block, uint32_t id, uint32_t batch
 /* ======================================================================== */
 /* Scene, BVH and closest points                                             */
 /* ======================================================================== */
-/* The samplers report, as a cache point's xbar, its closest boundary point
- * seen from the point: xbar = closest + XBAR_SIDE (x - closest).  The control
- * variate of its walks, c = g(xbar), then reads the data on the point's own
- * side of a boundary with double-sided conditions (Appendix B); for
- * continuous data it moves c by about 1e-3 l |grad g|, which a control
- * variate may take (any constant keeps the estimate unbiased). */
-#define XBAR_SIDE 1e-3
 
 typedef struct {
   double lo[3], hi[3];
@@ -1039,7 +1032,7 @@ int64_t orc_sample_cache(const orc_scene* s, int64_t n, double l, int sides, uin
     R0[k] = dist;
     w[k] = M / (double)n;
     for (int a = 0; a < d; ++a) {
-      xbar[k * d + a] = xb[a] + XBAR_SIDE * (xk[a] - xb[a]);
+      xbar[k * d + a] = xb[a];
       nrm[k * d + a] = (xb[a] - xk[a]) / dist;
     }
   }
@@ -1131,7 +1124,7 @@ int64_t orc_sample_roi(const orc_scene* dom, const orc_scene* roi, int64_t n, ui
     n_acc += ok;
     R0[k] = dist;
     w[k] = M / (double)n;
-    for (int a = 0; a < d; ++a) xbar[k * d + a] = xb[a] + XBAR_SIDE * (xk[a] - xb[a]);
+    for (int a = 0; a < d; ++a) xbar[k * d + a] = xb[a];
   }
   free(cdf);
   return n_acc;
@@ -1227,13 +1220,27 @@ void orc_sample_ball_source(uint64_t seed, uint32_t k, uint32_t id, uint32_t bat
 double orc_grad_radius(double u) { return 2 * sin(asin(u) / 3); }
 
 /* Where a walk that stops at pos, at distance d from its closest boundary
- * point pb, reads the boundary data: pb approached from the walk's side by
- * 1e-3 eps.  Data that differ on the two sides of a boundary curve
- * (double-sided conditions, Appendix B) are thus read on the side the walk
- * reached; continuous data change by about 1e-3 eps |grad g|. */
-static void read_point(int dim, const double* pos, const double* pb, double d, double eps, double* e) {
-  const double t = d > 0 ? 1e-3 * eps / d : 0.0;
+ * point pb, reads the boundary data: at pb itself (Section 3.1), or, with
+ * the side rule of double-sided data (p->side_read, Appendix B), at pb
+ * approached from the walk's side by 1e-3 eps, so that data that differ on
+ * the two sides of a boundary curve are read on the side the walk reached. */
+static void read_point(const orc_walk_params* p, int dim, const double* pos, const double* pb, double d,
+                       double* e) {
+  const double t = p->side_read && d > 0 ? 1e-3 * p->eps / d : 0.0;
   for (int a = 0; a < dim; ++a) e[a] = pb[a] + t * (pos[a] - pb[a]);
+}
+
+/* The control variate c = g at the cache point's closest boundary point
+ * xbar; with the side rule, at xbar moved 1e-3 of the way back to the cache
+ * point x, on the point's own side of a boundary with double-sided data.
+ * Any constant keeps the Eq. 7 estimate unbiased (E[nu] = 0). */
+static double control_value(const orc_walk_params* p, const orc_field* g, int dim, const double* x,
+                            const double* xbar) {
+  if (!p->control_variate) return 0.0;
+  if (!p->side_read) return orc_field_eval(g, dim, xbar);
+  double e[3] = {0, 0, 0};
+  for (int a = 0; a < dim; ++a) e[a] = xbar[a] + 1e-3 * (x[a] - xbar[a]);
+  return orc_field_eval(g, dim, e);
 }
 
 /* Open (unbounded) 3D domains, Appendix B.  Outside a sphere B(c, Rb) that
@@ -1299,7 +1306,7 @@ void orc_walk(const orc_scene* s, const orc_field* g, const orc_field* f,
   if (mode == 1 && R0 < p->eps) {
     /* the evaluation point already lies in the epsilon shell */
     double e[3] = {0, 0, 0};
-    read_point(dim, x, xbar, R0, p->eps, e);
+    read_point(p, dim, x, xbar, R0, e);
     *U = orc_field_eval(g, dim, e);
     for (int a = 0; a < dim; ++a) {
       grad[a] = 0;
@@ -1352,7 +1359,7 @@ void orc_walk(const orc_scene* s, const orc_field* g, const orc_field* f,
     if (d < p->eps || k >= p->max_steps) {
       *capped = !(d < p->eps);
       double e[3] = {0, 0, 0};
-      read_point(dim, pos, pb, d, p->eps, e);
+      read_point(p, dim, pos, pb, d, e);
       for (int a = 0; a < dim; ++a) pb[a] = e[a];
       W = screened ? thr * orc_field_eval(g, dim, pb) : orc_field_eval(g, dim, pb) + S;
       break;
@@ -1379,7 +1386,7 @@ void orc_walk(const orc_scene* s, const orc_field* g, const orc_field* f,
   }
   /* the escape rule holds for the Laplace equation without a source only */
   if (open && (screened || has_f)) *U = NAN;
-  double c = p->control_variate ? orc_field_eval(g, dim, xbar) : 0.0;
+  double c = control_value(p, g, dim, x, xbar);
   double wn = 0;
   for (int a = 0; a < dim; ++a) {
     grad[a] = gw * nu0[a] * (W - c);
@@ -1795,7 +1802,7 @@ static void wost_walk(const orc_scene* dir, const orc_scene* neu, const neu_link
     if (dD < p->eps || k >= p->max_steps) {
       *capped = !(dD < p->eps);
       double e[2];
-      read_point(2, pos, qD, dD, p->eps, e);
+      read_point(p, 2, pos, qD, dD, e);
       W = orc_field_eval(g, 2, e);
       break;
     }
@@ -1828,7 +1835,7 @@ static void wost_walk(const orc_scene* dir, const orc_scene* neu, const neu_link
   if (D) {
     *D = 0;
     if (mode == 0) {
-      double c = p->control_variate ? orc_field_eval(g, 2, xbar) : 0.0;
+      double c = control_value(p, g, 2, x, xbar);
       *D = 2.0 / R0 * (nu0[0] * n[0] + nu0[1] * n[1]) * (W - c);
     }
   }
@@ -1872,14 +1879,15 @@ void orc_wost_walks(const orc_scene* dir, const orc_scene* neu, const orc_field*
  * orc_sample_cache with sides 1, on the Dirichlet segments `dir`) followed
  * by the Neumann segments `neu`.  An offset candidate is kept when its
  * distance to the Dirichlet part is l (1e-9 relative), it lies inside the
- * domain `full` and no closer than l/100 to the Neumann part; a Neumann
- * candidate when its distance to the Dirichlet part exceeds l.  Outputs: x, nrm (offset points: towards the closest Dirichlet
+ * domain `full` and (when junction_drop > 0) no closer than junction_drop * l
+ * to the Neumann part; a Neumann candidate when its distance to the
+ * Dirichlet part exceeds l.  Outputs: x, nrm (offset points: towards the closest Dirichlet
  * point; Neumann points: the segment's outward normal), w = total measure /
  * n, xbar = closest Dirichlet point, R0 = distance to the whole boundary,
  * type (0 offset, 1 Neumann), accept.  Returns the number accepted. */
 int64_t orc_sample_mixed(const orc_scene* full, const orc_scene* dir, const orc_scene* neu, int64_t n, double l,
-                         uint64_t seed, uint32_t batch, double* x, double* nrm, double* w, double* xbar, double* R0,
-                         int32_t* type, int32_t* accept) {
+                         double junction_drop, uint64_t seed, uint32_t batch, double* x, double* nrm, double* w,
+                         double* xbar, double* R0, int32_t* type, int32_t* accept) {
   elem_table T;
   make_elements(dir, l, 1, &T);
   double MD = T.cdf[T.n_el];
@@ -1938,14 +1946,15 @@ int64_t orc_sample_mixed(const orc_scene* full, const orc_scene* dir, const orc_
     }
     double dF, xf[3];
     orc_closest(full, xk, 0, &dF, xf, NULL);
-    /* an offset point within l/100 of the Neumann part is dropped: its first
-     * ball (no larger than that distance) would give the Eq. 7 estimate an
-     * unbounded variance; the boundary integral loses 2 l/100 of length where
-     * the offset curve meets the Neumann part */
-    if (type[k] == 0 && dF < 1e-2 * l) ok = 0;
+    /* optional: an offset point within junction_drop * l of the Neumann part
+     * is dropped (its first ball, no larger than that distance, gives the
+     * Eq. 7 estimate a variance that grows like (l / R0)^2); the boundary
+     * integral then loses that much length where the offset curve meets the
+     * Neumann part.  0 keeps every point of the offset curve. */
+    if (type[k] == 0 && dF < junction_drop * l) ok = 0;
     R0[k] = dF;
-    xbar[2 * k] = xb[0] + XBAR_SIDE * (xk[0] - xb[0]);
-    xbar[2 * k + 1] = xb[1] + XBAR_SIDE * (xk[1] - xb[1]);
+    xbar[2 * k] = xb[0];
+    xbar[2 * k + 1] = xb[1];
     w[k] = M / (double)n;
     accept[k] = ok;
     n_acc += ok;
@@ -1956,7 +1965,7 @@ int64_t orc_sample_mixed(const orc_scene* full, const orc_scene* dir, const orc_
 }
 
 /* ======================================================================== */
-/* Clamped double-layer kernel and its bias correction (Section 3.4,         */
+/* Clamped double-layer kernel and its bias correction (Section 3.3,         */
 /* Eqs. 8-9)                                                                 */
 /* ======================================================================== */
 /* |dG/dn(x, z)| = |n . (z - x)| / (|S| r^dim) <= 1 / (|S| r^(dim-1)), so no

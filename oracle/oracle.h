@@ -20,7 +20,7 @@
  *   - Algorithm 1 (UpdateSolution): cache walks, splat of boundary and source
  *     samples into evaluation points;
  *   - the clamped double-layer kernel and its bias correction by ray-cast
- *     signed-solid-angle sampling with walks at the crossings (Section 3.4,
+ *     signed-solid-angle sampling with walks at the crossings (Section 3.3,
  *     Eqs. 8-9).
  *
  * Conventions (fixed readings of the paper, listed in the design notes):
@@ -106,11 +106,10 @@ void orc_greens(int dim, const double* x, const double* y, const double* ny, dou
 /* --- Cache sampling (Section 3.2 offset boundary, Section 4 CDF sampling) -- */
 /* Draws n candidates on the offset boundary at distance l; writes per
  * candidate the point, unit outward normal of the region {d > l}, weight
- * (total candidate measure / n), closest boundary point q seen from the
- * candidate (xbar = q + 1e-3 (x - q), where the control variate reads g),
- * distance and an accept flag.  sides: 1 = inward offsets only, 2 = both
- * sides (2D).  The region-of-interest and mixed samplers report xbar the
- * same way.
+ * (total candidate measure / n), closest boundary point xbar (where the
+ * control variate reads g), distance and an accept flag.  sides: 1 = inward
+ * offsets only, 2 = both sides (2D).  The region-of-interest and mixed
+ * samplers report xbar the same way.
  * Returns the number accepted. */
 int64_t orc_sample_cache(const orc_scene* s, int64_t n, double l, int sides, uint64_t seed,
                          uint32_t batch, double* x, double* nrm, double* w, double* xbar,
@@ -141,6 +140,14 @@ typedef struct {
   double sigma;            /* screening coefficient of Lap u - sigma u = f (Eq. 1); 0: Poisson */
   double open_center[3];   /* open (unbounded) 3D domain, Appendix B: a sphere that */
   double open_radius;      /* encloses the whole boundary; 0 = bounded domain */
+  int32_t side_read;       /* 0: a walk reads g at its closest boundary point and
+                              the control variate at xbar, as Section 3.1 states.
+                              1 (double-sided data, Appendix B): both read points
+                              are moved off the boundary towards the walk (by
+                              1e-3 eps at an exit, by 1e-3 |x - xbar| for the
+                              control variate), so that data that differ on the
+                              two sides of a boundary curve are read on the
+                              walk's own side */
 } orc_walk_params;
 
 /* Open 3D domains (Appendix B): from x outside the sphere B(c, Rb), u < Rb/|x-c|
@@ -267,12 +274,16 @@ void orc_wost_walks(const orc_scene* dir, const orc_scene* neu, const orc_field*
  * Dirichlet boundary (distance l to the Dirichlet part, inside `full`) and
  * the Neumann part beyond distance l, one stratified draw (tag 7); type 0
  * offset / 1 Neumann; R0 = distance to the whole boundary, xbar = closest
- * Dirichlet point.  Returns the number accepted. */
+ * Dirichlet point.  junction_drop >= 0: offset points closer than
+ * junction_drop * l to the Neumann part are rejected too (0 = the plain
+ * sampler; a positive value removes the pieces of the offset curve next to a
+ * Dirichlet / Neumann junction, a bias traded for the variance of their
+ * small first balls).  Returns the number accepted. */
 int64_t orc_sample_mixed(const orc_scene* full, const orc_scene* dir, const orc_scene* neu, int64_t n, double l,
-                         uint64_t seed, uint32_t batch, double* x, double* nrm, double* w, double* xbar, double* R0,
-                         int32_t* type, int32_t* accept);
+                         double junction_drop, uint64_t seed, uint32_t batch, double* x, double* nrm, double* w,
+                         double* xbar, double* R0, int32_t* type, int32_t* accept);
 
-/* --- Clamped double-layer kernel and bias correction (Section 3.4) ------ */
+/* --- Clamped double-layer kernel and bias correction (Section 3.3) ------ */
 /* Distance beyond which |dG/dn| cannot exceed c (INFINITY for c <= 0). */
 double orc_clamp_radius(int dim, double c);
 /* u only, with dG/dn clamped to [-c, c] (Eq. 9) in the boundary term. */

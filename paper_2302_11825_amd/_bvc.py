@@ -47,7 +47,7 @@ class bvc_walk_params(C.Structure):
                 ("seed", C.c_uint64), ("batch", C.c_uint32), ("control_variate", C.c_int32),
                 ("dtype", C.c_int32), ("blocks", C.c_int32), ("g", bvc_field), ("f", bvc_field),
                 ("ev_begin", C.c_void_p), ("ev_end", C.c_void_p), ("sigma", C.c_double),
-                ("open_center", C.c_double * 3), ("open_radius", C.c_double)]
+                ("open_center", C.c_double * 3), ("open_radius", C.c_double), ("side_read", C.c_int32)]
 
 
 class bvc_cache_view(C.Structure):
@@ -128,8 +128,8 @@ _SIGS = {
     "bvc_wost_walks": [_vp, _vp, _P(bvc_walk_params), C.c_int32, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                        _vp, C.c_size_t, _vp, _vp],
     "bvc_sample_roi": [_vp, _vp, C.c_int64, C.c_uint64, C.c_uint32, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
-    "bvc_sample_mixed": [_vp, _vp, _vp, C.c_int64, C.c_double, C.c_uint64, C.c_uint32, _vp, _vp, _vp, _vp, _vp, _vp,
-                         _vp],
+    "bvc_sample_mixed": [_vp, _vp, _vp, C.c_int64, C.c_double, C.c_double, C.c_uint64, C.c_uint32, _vp, _vp, _vp,
+                         _vp, _vp, _vp, _vp],
     "bvc_classify_mixed": [_vp, _vp, C.c_int64, _vp, C.c_double, _vp, _vp, _vp],
     "bvc_clamp_correction": [_vp, _P(bvc_walk_params), _P(bvc_clamp_params), C.c_int64, _vp, _vp, _vp, _vp, _vp,
                              C.c_size_t, _vp, _vp],
@@ -270,9 +270,10 @@ def bvc_sample_roi(dom, roi, n, seed, batch, x, nrm, w, xbar, R0, accept, stream
                              stream_ptr(stream)), "bvc_sample_roi")
 
 
-def bvc_sample_mixed(full, dir_scene, neu, n, l, seed, batch, x, nrm, w, xbar, R0, kind, stream=None):
-    _check(_L.bvc_sample_mixed(full, dir_scene, neu, n, l, seed, batch, ptr(x), ptr(nrm), ptr(w), ptr(xbar), ptr(R0),
-                               ptr(kind), stream_ptr(stream)), "bvc_sample_mixed")
+def bvc_sample_mixed(full, dir_scene, neu, n, l, seed, batch, x, nrm, w, xbar, R0, kind, stream=None,
+                     junction_drop=0.0):
+    _check(_L.bvc_sample_mixed(full, dir_scene, neu, n, l, float(junction_drop), seed, batch, ptr(x), ptr(nrm), ptr(w),
+                               ptr(xbar), ptr(R0), ptr(kind), stream_ptr(stream)), "bvc_sample_mixed")
 
 
 def bvc_classify_mixed(full, dir_scene, n, x, l, cls, dist=None, stream=None):

@@ -55,6 +55,7 @@ int plan_sizes(const bvc_batch_item* items, int n, int& dim, uint64_t& walks, in
       return fail(BVC_EUNSUPPORTED, "walk source terms are constants or Gaussian sums");
     if (p.sigma != 0.0) return fail(BVC_EUNSUPPORTED, "batched walks are built for sigma = 0");
     if (p.open_radius != 0.0) return fail(BVC_EUNSUPPORTED, "batched walks are built for bounded domains");
+    if (p.side_read != 0) return fail(BVC_EUNSUPPORTED, "batched walks read g at the closest point (no side rule)");
     const int src = p.f.kind != 0;
     if (has_src < 0) has_src = src;
     if (src != has_src) return fail(BVC_EUNSUPPORTED, "mixing scenes with and without sources in one batch");

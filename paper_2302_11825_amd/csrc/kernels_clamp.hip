@@ -1,4 +1,4 @@
-// Bias correction of the clamped gather (Section 3.4, Eq. 8): the crossings
+// Bias correction of the clamped gather (Section 3.3, Eq. 8): the crossings
 // of random rays with the offset boundary dR = {z inside : d(z) = l}, and the
 // weighted sum of the walks started at them.
 //

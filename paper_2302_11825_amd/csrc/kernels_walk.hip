@@ -62,12 +62,9 @@ namespace {
 // ---------------------------------------------------------------------------
 // Cache sampling
 // ---------------------------------------------------------------------------
-// A cache point's xbar is its closest boundary point seen from the point,
-// closest + kXbarSide (x - closest): the control variate c = g(xbar) of its
-// walks then reads the data on the point's own side of a boundary with
-// double-sided conditions (Appendix B); for continuous data c moves by about
-// 1e-3 l |grad g|, which a control variate may take.
-constexpr double kXbarSide = 1e-3;
+// A cache point's xbar is its closest boundary point, where the control
+// variate c = g(xbar) of its walks reads the data (the walks' side rule for
+// double-sided data moves that read point towards the cache point).
 __device__ void candidate_point(const SceneDev& S, int e, double r, double v, double l, double* x) {
   if (S.dim == 2) {
     const int ns = S.np * S.sides;
@@ -173,7 +170,7 @@ __global__ __launch_bounds__(kBlock) void k_sample_cache(SceneDev S, int64_t n, 
 #pragma unroll
   for (int a = 0; a < D; ++a) {
     x[a * n + k] = xc[a];
-    xbar[a * n + k] = fma(kXbarSide, xc[a] - q[a], q[a]);
+    xbar[a * n + k] = q[a];
     nrm[a * n + k] = (q[a] - xc[a]) / d;
   }
 }
@@ -240,7 +237,7 @@ __global__ __launch_bounds__(kBlock) void k_sample_roi(SceneDev Sd, SceneDev Sr,
   for (int a = 0; a < D; ++a) {
     x[a * n + k] = xc[a];
     nrm[a * n + k] = nc[a];
-    xbar[a * n + k] = fma(kXbarSide, xc[a] - q[a], q[a]);
+    xbar[a * n + k] = q[a];
   }
 }
 
@@ -253,7 +250,8 @@ __global__ __launch_bounds__(kBlock) void k_sample_roi(SceneDev Sd, SceneDev Sr,
 // segments (their table at l = 0).  Offset points take the normal towards the
 // closest Dirichlet point, Neumann points the segment's outward normal.
 __global__ __launch_bounds__(kBlock) void k_sample_mixed(SceneDev Sf, SceneDev Sd, SceneDev Sn, int64_t n, double l,
-                                                          uint64_t seed, uint32_t batch, double MD, double M,
+                                                          double jdrop, uint64_t seed, uint32_t batch, double MD,
+                                                          double M,
                                                           double* x, double* nrm, double* w, double* xbar,
                                                           double* R0, int* kind) {
   extern __shared__ uint32_t lds[];
@@ -304,9 +302,10 @@ __global__ __launch_bounds__(kBlock) void k_sample_mixed(SceneDev Sf, SceneDev S
   double qf[2];
   int hf = -1;
   const double dF = sqrt(closest_point<double, 2>(Sf, xc, hf, qf, lds + threadIdx.x, blockDim.x));
-  // an offset point within l/100 of the Neumann part is dropped: its first
-  // ball would give the Eq. 7 estimate an unbounded variance
-  if (ty == 1 && dF < 1e-2 * l) ok = false;
+  // optional junction drop: an offset point closer than jdrop * l to the
+  // Neumann part is rejected (its first ball, no larger than that distance,
+  // gives the Eq. 7 estimate a variance growing like (l / R0)^2)
+  if (ty == 1 && dF < jdrop * l) ok = false;
   R0[k] = dF;
   kind[k] = ok ? ty : 0;
   w[k] = M / (double)n;
@@ -314,7 +313,7 @@ __global__ __launch_bounds__(kBlock) void k_sample_mixed(SceneDev Sf, SceneDev S
   for (int a = 0; a < 2; ++a) {
     x[a * n + k] = xc[a];
     nrm[a * n + k] = nc[a];
-    xbar[a * n + k] = fma(kXbarSide, xc[a] - q[a], q[a]);
+    xbar[a * n + k] = q[a];
   }
 }
 
@@ -561,9 +560,9 @@ int bvc_sample_roi(bvc_scene dom, bvc_scene roi, int64_t n, uint64_t seed, uint3
   return check_hip(hipGetLastError(), "sample_roi launch");
 }
 
-int bvc_sample_mixed(bvc_scene full, bvc_scene dir, bvc_scene neu, int64_t n, double l, uint64_t seed,
-                     uint32_t batch, double* x, double* nrm, double* w, double* xbar, double* R0, int32_t* kind,
-                     void* stream) {
+int bvc_sample_mixed(bvc_scene full, bvc_scene dir, bvc_scene neu, int64_t n, double l, double junction_drop,
+                     uint64_t seed, uint32_t batch, double* x, double* nrm, double* w, double* xbar, double* R0,
+                     int32_t* kind, void* stream) {
   int rc = check_scene(full);
   if (!rc) rc = check_scene(dir);
   if (!rc) rc = check_scene(neu);
@@ -573,6 +572,7 @@ int bvc_sample_mixed(bvc_scene full, bvc_scene dir, bvc_scene neu, int64_t n, do
   if (dir->h.np == 0 || neu->h.np == 0) return fail(BVC_EINVAL, "the Dirichlet and the Neumann parts must be non-empty");
   if (n < 0 || n >= (int64_t)1 << 31) return fail(BVC_EINVAL, "n out of range");
   if (!(l > 0) || !std::isfinite(l)) return fail(BVC_EINVAL, "offset l must be positive");
+  if (!(junction_drop >= 0.0) || !(junction_drop < 1.0)) return fail(BVC_EINVAL, "junction_drop must be in [0, 1)");
   if (n == 0) return BVC_OK;
   if (!x || !nrm || !w || !xbar || !R0 || !kind) return fail(BVC_EINVAL, "null output");
   hipStream_t st = (hipStream_t)stream;
@@ -584,8 +584,8 @@ int bvc_sample_mixed(bvc_scene full, bvc_scene dir, bvc_scene neu, int64_t n, do
   const SceneDev Sf = full->h.view(), Sd = dir->h.view(), Sn = neu->h.view();
   const int blocks = (int)((n + kBlock - 1) / kBlock);
   const size_t lds = std::max(stack_bytes(full->h, kBlock), stack_bytes(dir->h, kBlock));
-  hipLaunchKernelGGL(k_sample_mixed, dim3(blocks), dim3(kBlock), lds, st, Sf, Sd, Sn, n, l, seed, batch, MD, M, x,
-                     nrm, w, xbar, R0, kind);
+  hipLaunchKernelGGL(k_sample_mixed, dim3(blocks), dim3(kBlock), lds, st, Sf, Sd, Sn, n, l, junction_drop, seed,
+                     batch, MD, M, x, nrm, w, xbar, R0, kind);
   return check_hip(hipGetLastError(), "sample_mixed launch");
 }
 

@@ -41,6 +41,7 @@ struct WostArgs {
   uint32_t batch;
   int mode;
   int cv;
+  int side;  // side rule of double-sided data
   int64_t n;
   uint64_t total;
   const double* x;     // [2][n]
@@ -262,8 +263,9 @@ __global__ __launch_bounds__(kWostBlock) void k_wost(WostArgs a) {
       const T dD = fsqrt(d2D);
       if (dD < eps || k >= a.max_steps) {
         capped = !(dD < eps);
-        // read g at the closest Dirichlet point approached from the walk's side
-        const T t = dD > T(0) ? T(1e-3) * eps / dD : T(0);
+        // read g at the closest Dirichlet point (with the side rule,
+        // approached from the walk's side)
+        const T t = a.side && dD > T(0) ? T(1e-3) * eps / dD : T(0);
         const T qr[2] = {fma(t, pos[0] - q[0], q[0]), fma(t, pos[1] - q[1], q[1])};
         if constexpr (sizeof(T) == 4) {
           W = field_value_f32(a.g, 2, qr);
@@ -304,7 +306,11 @@ __global__ __launch_bounds__(kWostBlock) void k_wost(WostArgs a) {
     if (a.D) {
       double dv = 0.0;
       if (a.mode == 0) {
-        const double xb[2] = {a.xbar[i], a.xbar[a.n + i]};
+        double xb[2] = {a.xbar[i], a.xbar[a.n + i]};
+        if (a.side) {
+          xb[0] = fma(1e-3, a.x[i] - xb[0], xb[0]);
+          xb[1] = fma(1e-3, a.x[a.n + i] - xb[1], xb[1]);
+        }
         const double c = a.cv ? field_value(a.g, 2, xb) : 0.0;
         dv = 2.0 / R0 * ((double)nu0[0] * a.nrm[i] + (double)nu0[1] * a.nrm[a.n + i]) * (W - c);
       }
@@ -511,6 +517,7 @@ int bvc_wost_walks(bvc_scene dir, bvc_scene neu, const bvc_walk_params* p, int32
   a.batch = p->batch;
   a.mode = mode;
   a.cv = p->control_variate;
+  a.side = p->side_read != 0;
   a.n = n;
   a.total = (uint64_t)n * (uint64_t)p->n_walks;
   a.x = x;

@@ -2,8 +2,9 @@
 // the upload into a caller-owned device buffer.
 //
 // The BVH is a binary AABB hierarchy (the paper's closest-point structure,
-// Section 4 "Setup") built by median splits of primitive centroids along the
-// widest axis, stored in breadth-first order with both child boxes inside the
+// Section 4 "Setup") built by binned surface-area splits of the primitive
+// centroids (16 bins per axis; a median split along the widest axis where no
+// bin boundary separates them), stored in breadth-first order with both child boxes inside the
 // parent, so one node fetch gives the two boxes a nearest-first traversal
 // compares.  An FP32 copy of the boxes is rounded outward so that it stays
 // conservative for the FP32 walks.

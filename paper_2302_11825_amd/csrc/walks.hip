@@ -59,6 +59,7 @@ struct WalkArgs {
   double sigma;              // screening coefficient (no source term), 0 = Poisson
   double oc[3];              // open 3D domain: sphere enclosing the boundary,
   double orad;               // 0 = bounded domain
+  int side;                  // side rule of double-sided data (reads moved towards the walk)
 };
 
 // Open 3D domains (Appendix B).  A walk that has jumped (jump index k) to
@@ -217,15 +218,23 @@ struct WalkShape {
 };
 WalkShape default_shape(int dim) { return WalkShape{8, dim == 3 ? 32 : 0}; }
 
+// A tuned shape belongs to one kernel instance: dimension, precision, source
+// term, start mode, open domain (its own kernel) and screening (another
+// per-ball cost).
 struct WalkClass {
-  int dim, dtype, src, mode;
+  int dim, dtype, src, mode, open, screened;
   bool operator<(const WalkClass& o) const {
     if (dim != o.dim) return dim < o.dim;
     if (dtype != o.dtype) return dtype < o.dtype;
     if (src != o.src) return src < o.src;
-    return mode < o.mode;
+    if (mode != o.mode) return mode < o.mode;
+    if (open != o.open) return open < o.open;
+    return screened < o.screened;
   }
 };
+WalkClass walk_class(int dim, const bvc_walk_params* p, int mode) {
+  return WalkClass{dim, p->dtype, p->f.kind != 0 ? 1 : 0, mode, p->open_radius > 0.0 ? 1 : 0, p->sigma > 0.0 ? 1 : 0};
+}
 std::mutex g_walk_mu;
 std::map<WalkClass, WalkShape> g_walk_shape;
 
@@ -284,8 +293,9 @@ __device__ __forceinline__ void walks_body(const WalkArgs& a, uint32_t* lds) {
             const T R0 = (T)a.R0[i];
             if (MODE != 0 && R0 < eps) {
               // the start point already lies in the epsilon shell: its walk
-              // returns g at the closest boundary point, read from its side
-              const double t = R0 > T(0) ? 1e-3 * a.eps / (double)R0 : 0.0;
+              // returns g at the closest boundary point (with the side rule,
+              // approached from the start point's side)
+              const double t = a.side && R0 > T(0) ? 1e-3 * a.eps / (double)R0 : 0.0;
 #pragma unroll
               for (int q = 0; q < D; ++q) {
                 const double xq = MODE != 1 ? a.x[q * a.n_pts + i] : (double)((const T*)a.px)[q * a.n_pts + i];
@@ -407,10 +417,11 @@ __device__ __forceinline__ void walks_body(const WalkArgs& a, uint32_t* lds) {
       const bool stop = d < eps;
       const bool cap = !stop && k >= a.max_steps;
       if (stop || cap) {
-        // g is read at the closest point approached from the walk's side by
-        // 1e-3 eps, so that data that differ on the two sides of a boundary
-        // curve (double-sided conditions, Appendix B) are read on this side
-        const T t = d > T(0) ? T(1e-3) * eps / d : T(0);
+        // g is read at the closest point; with the side rule it is
+        // approached from the walk's side by 1e-3 eps, so that data that
+        // differ on the two sides of a boundary curve (double-sided
+        // conditions, Appendix B) are read on this side
+        const T t = a.side && d > T(0) ? T(1e-3) * eps / d : T(0);
 #pragma unroll
         for (int c = 0; c < D; ++c) EX[(size_t)c * a.ld + id] = fma(t, p[c] - qs.bq[c], qs.bq[c]);
         U[id] = acc_s + usrc;
@@ -484,7 +495,8 @@ constexpr int kFinishRun = 8;
 template <typename T, int D, int MODE>
 __global__ __launch_bounds__(kBlock) void k_finish(FieldDev g, int cv, uint64_t total, int W, int64_t n_pts,
                                                     const double* xbar, const T* EX, T* U, T* Dof, const T* W1,
-                                                    double sigma, double eps, const double* R0) {
+                                                    double sigma, double eps, const double* R0, int side,
+                                                    const double* x64, const T* xT) {
   const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const uint64_t id0 = wave * (64 * kFinishRun) + (threadIdx.x & 63);
   const bool scr = sigma > 0.0;
@@ -497,16 +509,23 @@ __global__ __launch_bounds__(kBlock) void k_finish(FieldDev g, int cv, uint64_t 
     const int64_t i = (int64_t)(id / (uint64_t)W);
     if (cv && i != i_cv) {
       // the control variate in the walks' precision: any constant keeps the
-      // gradient estimate unbiased
+      // gradient estimate unbiased; the side rule reads it at xbar moved
+      // 1e-3 of the way back to the start point
+      double xb[D];
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        xb[q] = xbar[q * n_pts + i];
+        if (side) {
+          const double xs = MODE == 0 ? x64[q * n_pts + i] : (double)xT[q * n_pts + i];
+          xb[q] = fma(1e-3, xs - xb[q], xb[q]);
+        }
+      }
       if constexpr (sizeof(T) == 4) {
-        float xb[D];
+        float xf[D];
 #pragma unroll
-        for (int q = 0; q < D; ++q) xb[q] = (float)xbar[q * n_pts + i];
-        c = field_value_f32(g, D, xb);
+        for (int q = 0; q < D; ++q) xf[q] = (float)xb[q];
+        c = field_value_f32(g, D, xf);
       } else {
-        double xb[D];
-#pragma unroll
-        for (int q = 0; q < D; ++q) xb[q] = xbar[q * n_pts + i];
         c = field_value(g, D, xb);
       }
       i_cv = i;
@@ -617,6 +636,7 @@ int check_walk_params(const bvc_walk_params* p, int dim, const SceneHost* h = nu
   if (p->f.kind != 0 && p->f.kind != 1 && p->f.kind != 3)
     return fail(BVC_EUNSUPPORTED, "walk source terms are constants or Gaussian sums");
   if (!(p->sigma >= 0.0) || !std::isfinite(p->sigma)) return fail(BVC_EINVAL, "sigma must be finite and >= 0");
+  if (p->side_read != 0 && p->side_read != 1) return fail(BVC_EINVAL, "side_read must be 0 or 1");
   if (p->sigma > 0.0 && p->f.kind != 0)
     return fail(BVC_EUNSUPPORTED, "screened walks take no source term (f must be ZERO)");
   if (p->open_radius != 0.0) {
@@ -667,11 +687,11 @@ void launch_finish(const bvc_walk_params* p, int mode, const WalkArgs& a, hipStr
   if (mode == 0)
     hipLaunchKernelGGL((k_finish<T, D, 0>), dim3(blocks), dim3(kBlock), 0, st, g, p->control_variate, a.total,
                        a.W, a.n_pts, a.xbar, (const T*)a.exit, (T*)a.U, (T*)a.Dof, (const T*)a.w1, a.sigma,
-                       a.eps, a.R0);
+                       a.eps, a.R0, a.side, a.x, (const T*)a.px);
   else
     hipLaunchKernelGGL((k_finish<T, D, 1>), dim3(blocks), dim3(kBlock), 0, st, g, p->control_variate, a.total,
                        a.W, a.n_pts, a.xbar, (const T*)a.exit, (T*)a.U, (T*)a.Dof, (const T*)a.w1, a.sigma,
-                       a.eps, a.R0);
+                       a.eps, a.R0, a.side, a.x, (const T*)a.px);
 }
 
 size_t stack_bytes(const SceneHost& h) { return (size_t)(h.depth + 1) * kBlock * sizeof(uint32_t); }
@@ -689,6 +709,7 @@ int run_walks(bvc_scene s, const bvc_walk_params* p, int mode, int64_t n, WalkAr
   a.sigma = p->sigma;
   for (int c = 0; c < 3; ++c) a.oc[c] = p->open_center[c];
   a.orad = p->open_radius;
+  a.side = p->side_read != 0;
   a.max_steps = p->max_steps;
   a.W = mode == 2 ? 1 : p->n_walks;
   a.seed = p->seed;
@@ -702,7 +723,7 @@ int run_walks(bvc_scene s, const bvc_walk_params* p, int mode, int64_t n, WalkAr
   }
   int rc = zero_async(a.counters, 4 * sizeof(unsigned long long), st);
   if (rc || total == 0) return rc;
-  const WalkShape shape = force ? *force : tuned_shape(WalkClass{h.dim, p->dtype, p->f.kind != 0 ? 1 : 0, mode});
+  const WalkShape shape = force ? *force : tuned_shape(walk_class(h.dim, p, mode));
   a.open_lanes = shape.open_lanes;
   int blocks = p->blocks > 0 ? p->blocks : num_cus() * shape.blocks_per_cu;
   const int64_t needed = (int64_t)((total + kBlock - 1) / kBlock);
@@ -842,9 +863,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_walks(BatchDev b) {
       const bool stop = d < eps;
       const bool cap = !stop && k >= s.max_steps;
       if (stop || cap) {
-        const float t = d > 0.f ? 1e-3f * eps / d : 0.f;  // read g from the walk's side
 #pragma unroll
-        for (int c = 0; c < D; ++c) b.exit[(size_t)c * b.total_walks + gid] = fmaf(t, p[c] - q[c], q[c]);
+        for (int c = 0; c < D; ++c) b.exit[(size_t)c * b.total_walks + gid] = q[c];
         b.U[gid] = acc_s + usrc;
         steps_acc += (unsigned long long)k;
         capped_acc += cap ? 1ull : 0ull;
@@ -1178,7 +1198,7 @@ int bvc_tune_walks(bvc_scene s, const bvc_walk_params* p, int64_t n_cache, const
   if (rc) return rc;
   {
     std::lock_guard<std::mutex> lock(g_walk_mu);
-    g_walk_shape[WalkClass{s->h.dim, p->dtype, p->f.kind != 0 ? 1 : 0, 0}] = best;
+    g_walk_shape[walk_class(s->h.dim, p, 0)] = best;
   }
   if (blocks_per_cu) *blocks_per_cu = best.blocks_per_cu;
   if (open_lanes) *open_lanes = best.open_lanes;

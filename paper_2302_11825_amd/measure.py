@@ -6,7 +6,7 @@
     python bench.py --workload c4b   32 uneven 2D scenes: one graph-replayed launch
                                      sequence vs per-scene call sequences
     python bench.py --workload c2clamp  the 2D Poisson step with the clamped gather
-                                     and its bias correction (Section 3.4): time,
+                                     and its bias correction (Section 3.3): time,
                                      and the error near the offset boundary of the
                                      plain, clamped-only and corrected estimates
     python bench.py --workload c3clamp --clamp-c 1600   the same on the 3D Laplace step

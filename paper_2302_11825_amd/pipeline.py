@@ -139,10 +139,14 @@ def candidates_for(sc: Scene, n_target, l, sides, seed, pilot=65536):
 
 
 def walk_params(eps, n_walks, seed, g: DeviceField, f: Optional[DeviceField], dtype="f32", batch=0,
-                max_steps=1024, control_variate=True, blocks=0, sigma=0.0, open_sphere=None) -> B.bvc_walk_params:
+                max_steps=1024, control_variate=True, blocks=0, sigma=0.0, open_sphere=None,
+                side_read=False) -> B.bvc_walk_params:
     """open_sphere = (centre, radius) of a sphere enclosing the scene: an open
-    3D domain (Appendix B), whose walks escape to infinity or re-enter."""
+    3D domain (Appendix B), whose walks escape to infinity or re-enter.
+    side_read: the side rule of double-sided data (Appendix B); off, walks
+    read g at the closest boundary point (Section 3.1)."""
     p = B.bvc_walk_params()
+    p.side_read = int(bool(side_read))
     p.sigma = float(sigma)
     if open_sphere is not None:
         c, r = open_sphere
@@ -268,7 +272,7 @@ class Prepared:
             self._prepare_clamp(clamp, device)
 
     def _prepare_clamp(self, clamp, device):
-        """Clamped gather with bias correction (Section 3.4, Eq. 8).  clamp:
+        """Clamped gather with bias correction (Section 3.3, Eq. 8).  clamp:
         dict(c, n_rays, max_hits, seed).  Only gathered points within the
         clamp radius of the offset boundary can receive a correction; they
         are found here once (classification against l + radius) with their
@@ -333,7 +337,7 @@ def solve_roi(prep: RoiPrepared, batch=0, with_grad=True, watch=None) -> Solutio
     watch = watch or _NoWatch()
     with watch.stage("sample_cache"):
         cache = sample_roi(sc, roi, prep.n_cand, p.seed_cache, batch)
-    wp = walk_params(p.eps, p.n_walks, p.seed_walks, prep.g, prep.f, dt, batch, sigma=p.sigma)
+    wp = walk_params(p.eps, p.n_walks, p.seed_walks, prep.g, prep.f, dt, batch, sigma=p.sigma, side_read=p.side_read)
     with watch.stage("cache_walks"):
         U, D, rec, counters = cache_walks(sc, cache, wp, dt)
     with watch.stage("reduce_walks"):
@@ -412,7 +416,7 @@ def sample_mixed(prep: MixedPrepared, seed, batch=0):
     R0 = torch.empty_like(w)
     kind = torch.empty(n_cand, dtype=torch.int32, device=dev)
     B.bvc_sample_mixed(prep.full.h, prep.dir.h, prep.neu.h, n_cand, prep.p.offset, seed, batch, x, nrm, w, xbar, R0,
-                       kind)
+                       kind, junction_drop=prep.p.junction_drop)
     idx = torch.empty(n_cand + 1, dtype=torch.int32, device=dev)
     scratch = prep.full.scratch_int(n_cand)
     n0 = B.bvc_compact(n_cand, kind, 1, idx, scratch)
@@ -458,8 +462,8 @@ def solve_mixed(prep: MixedPrepared, batch=0, with_grad=True, watch=None) -> Sol
     with watch.stage("sample_cache"):
         cache, n0 = sample_mixed(prep, p.seed_cache, batch)
     n, n1 = cache.n, cache.n - n0
-    wp0 = walk_params(p.eps, W, p.seed_walks, prep.g, None, dt, batch)
-    wp1 = walk_params(p.eps, W, p.seed_walks, prep.g, None, dt, batch | NEUMANN_BATCH_BIT)
+    wp0 = walk_params(p.eps, W, p.seed_walks, prep.g, None, dt, batch, side_read=p.side_read)
+    wp1 = walk_params(p.eps, W, p.seed_walks, prep.g, None, dt, batch | NEUMANN_BATCH_BIT, side_read=p.side_read)
     with watch.stage("cache_walks"):
         U0, D0, c0 = wost(prep, wp0, 0, n0, _part(cache.x, 0, n0), _part(cache.nrm, 0, n0), _part(cache.R0, 0, n0),
                           _part(cache.xbar, 0, n0), dt)
@@ -492,7 +496,7 @@ def solve_mixed(prep: MixedPrepared, batch=0, with_grad=True, watch=None) -> Sol
     pw = torch.zeros(4, dtype=torch.int64, device=dev)
     Ub = None
     if nb:
-        wpb = walk_params(p.eps, prep.W_band, p.seed_walks, prep.g, None, dt, batch)
+        wpb = walk_params(p.eps, prep.W_band, p.seed_walks, prep.g, None, dt, batch, side_read=p.side_read)
         with watch.stage("band_walks"):
             Ub, Db, pw = wost(prep, wpb, 1, nb, prep.x_band, dtype=dt)
             ub64 = torch.empty(nb, dtype=torch.float64, device=dev)
@@ -668,7 +672,7 @@ def tune(prep: Prepared, with_grad=True, reps=3) -> dict:
     T, d = DT[dt], sc.dim
     cache = sample_cache(sc, prep.n_cand, p.offset, p.sides, p.seed_cache, 0)
     wp = walk_params(p.eps, p.n_walks, p.seed_walks, prep.g, prep.f, dt, 0, sigma=p.sigma,
-                     open_sphere=p.extra.get("open_sphere"))
+                     open_sphere=p.extra.get("open_sphere"), side_read=p.side_read)
     n, W = cache.n, p.n_walks
     U = torch.empty(max(n * W, 1), dtype=T, device=sc.device)
     D = torch.empty_like(U)
@@ -695,7 +699,8 @@ def solve(prep: Prepared, batch=0, with_grad=True, n_walks_band=None, records=Fa
     with watch.stage("sample_cache"):
         cache = sample_cache(sc, prep.n_cand, p.offset, p.sides, p.seed_cache, batch)
     osph = p.extra.get("open_sphere")
-    wp = walk_params(p.eps, p.n_walks, p.seed_walks, prep.g, prep.f, dt, batch, sigma=p.sigma, open_sphere=osph)
+    wp = walk_params(p.eps, p.n_walks, p.seed_walks, prep.g, prep.f, dt, batch, sigma=p.sigma, open_sphere=osph,
+                     side_read=p.side_read)
     watch.kernel("k_walks_cache", wp)
     with watch.stage("cache_walks"):
         U, D, rec, counters = cache_walks(sc, cache, wp, dt, records)
@@ -718,7 +723,8 @@ def solve(prep: Prepared, batch=0, with_grad=True, n_walks_band=None, records=Fa
         gathered.record()
     Wb = n_walks_band or p.n_walks
     nb = prep.n_band
-    wpb = walk_params(p.eps, Wb, p.seed_walks, prep.g, prep.f, dt, batch, sigma=p.sigma, open_sphere=osph)
+    wpb = walk_params(p.eps, Wb, p.seed_walks, prep.g, prep.f, dt, batch, sigma=p.sigma, open_sphere=osph,
+                      side_read=p.side_read)
     watch.kernel("k_walks_band", wpb)
     with watch.stage("band_walks"):
         u_band, g_band, pwc = pointwise(sc, wpb, prep.x_band[:, :nb] if nb else prep.x_band[:, :0], with_grad)
@@ -729,7 +735,7 @@ def solve(prep: Prepared, batch=0, with_grad=True, n_walks_band=None, records=Fa
         main = torch.cuda.current_stream()
         side = cl.setdefault("stream", torch.cuda.Stream())
         side.wait_event(gathered)
-        wpc = walk_params(p.eps, 1, cl["seed"], prep.g, prep.f, dt, batch)
+        wpc = walk_params(p.eps, 1, cl["seed"], prep.g, prep.f, dt, batch, side_read=p.side_read)
         with torch.cuda.stream(side):
             with watch.stage("clamp_correction"):
                 B.bvc_clamp_correction(sc.h, wpc, cl["cp"], cl["n_near"], cl["x"], cl["wind"], cl["pos"], u_int,

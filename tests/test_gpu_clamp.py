@@ -1,4 +1,4 @@
-"""GPU parity of the clamped gather and its bias correction (Section 3.4,
+"""GPU parity of the clamped gather and its bias correction (Section 3.3,
 Eqs. 8-9) against the FP64 oracle, through the C-ABI (marked gpu).
 
 - Clamped gather: u with dG/dn clamped to [-c, c] matches the oracle's

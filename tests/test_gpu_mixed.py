@@ -58,13 +58,21 @@ def test_mixed_sampler_matches_oracle(orc, name):
     w = torch.empty(n, dtype=f64, device="cuda")
     R0 = torch.empty_like(w)
     kind = torch.empty(n, dtype=torch.int32, device="cuda")
+    # the optional junction drop: same kinds on both sides, fewer offset points
+    _bvc.bvc_sample_mixed(sf.h, sd.h, sn.h, n, l, 43, 2, x, nrm, w, xbar, R0, kind, junction_drop=0.05)
+    torch.cuda.synchronize()
+    ref = orc.sample_mixed(orc.Scene(full), orc.Scene(dir_), orc.Scene(neu), n, l, 43, 2, junction_drop=0.05)
+    got_drop = kind.cpu().numpy()
+    assert np.array_equal(got_drop, np.where(ref["accept"], ref["type"] + 1, 0))
     _bvc.bvc_sample_mixed(sf.h, sd.h, sn.h, n, l, 43, 2, x, nrm, w, xbar, R0, kind)
     torch.cuda.synchronize()
     ref = orc.sample_mixed(orc.Scene(full), orc.Scene(dir_), orc.Scene(neu), n, l, 43, 2)
     want = np.where(ref["accept"], ref["type"] + 1, 0)
     got = kind.cpu().numpy()
-    say(f"  accepted {int((got > 0).sum())} of {n}")
+    say(f"  accepted {int((got > 0).sum())} of {n} ({int((got_drop > 0).sum())} with the junction drop)")
     assert np.array_equal(got, want)
+    assert np.all((got_drop == got) | (got_drop == 0))
+    assert np.allclose(to_np_aos(xbar), ref["xbar"], rtol=0, atol=1e-12)
     assert np.allclose(to_np_aos(x), ref["x"], rtol=0, atol=1e-12)
     assert np.allclose(to_np_aos(nrm), ref["n"], rtol=0, atol=1e-12)
     assert np.allclose(w.cpu().numpy(), ref["w"], rtol=1e-13)
@@ -206,6 +214,10 @@ def test_mixed_refuses_bad_input():
         _bvc.bvc_sample_mixed(sf.h, sd.h, sn.h, 8, 0.0, 1, 0, x, x, w, x, w, k)
     with pytest.raises(_bvc.BVCError):
         _bvc.bvc_sample_mixed(s3.h, sd.h, sn.h, 8, 0.1, 1, 0, x, x, w, x, w, k)
+    with pytest.raises(_bvc.BVCError):
+        _bvc.bvc_sample_mixed(sf.h, sd.h, sn.h, 8, 0.1, 1, 0, x, x, w, x, w, k, junction_drop=-0.1)
+    with pytest.raises(_bvc.BVCError):
+        _bvc.bvc_sample_mixed(sf.h, sd.h, sn.h, 8, 0.1, 1, 0, x, x, w, x, w, k, junction_drop=1.0)
     with pytest.raises(_bvc.BVCError):
         _bvc.bvc_classify_mixed(s3.h, sd.h, 8, x, 0.1, k)
     # empty inputs are no-ops

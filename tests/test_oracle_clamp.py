@@ -1,5 +1,5 @@
 """Pins of the oracle's clamped double-layer kernel and its bias correction
-(Section 3.4, Eqs. 8-9), against facts that do not come from the oracle's
+(Section 3.3, Eqs. 8-9), against facts that do not come from the oracle's
 own arithmetic:
 
 - the clamped gather reduces to the plain gather as c grows without bound,

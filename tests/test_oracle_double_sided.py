@@ -40,7 +40,7 @@ def test_walks_read_the_side_they_reach():
     pts = np.array([[0.5, 0.02], [0.5, -0.02], [0.8, 0.004], [0.8, -0.004], [0.3, 0.3], [-0.4, -0.2],
                     [0.6, 0.0005], [0.6, -0.0005]])
     W = 3000
-    P = orc.walk_params(1e-3, W, 5)
+    P = orc.walk_params(1e-3, W, 5, side_read=True)
     d, xb, _ = osc.closest(pts)
     exact = wl.field_value(g, pts)
     for i, x in enumerate(pts):
@@ -52,6 +52,11 @@ def test_walks_read_the_side_they_reach():
     for i, x in enumerate(sh):
         u = orc.walk(osc, g, None, P, 1, x, None, d[i], xb[i], 0)["U"]
         assert abs(u - np.sign(x[1]) * np.sqrt(0.5)) < 1e-5
+    # without the side rule both read g at the same closest point on the cut
+    # (Section 3.1 as stated), so one of them gets the other side's value
+    P0 = orc.walk_params(1e-3, W, 5)
+    u0 = [orc.walk(osc, g, None, P0, 1, x, None, d[i], xb[i], 0)["U"] for i, x in enumerate(sh)]
+    assert u0[0] == u0[1] and abs(abs(u0[0]) - np.sqrt(0.5)) < 1e-5
 
 
 def test_double_sided_cache_samples():
@@ -104,7 +109,7 @@ def test_double_sided_chain():
     acc = s["accept"]
     cache = {k: s[k][acc] for k in ("x", "n", "w", "xbar", "R0")}
     W = 64
-    ref = orc.cache_walks(osc, g, None, orc.walk_params(1e-3, W, 17), cache)
+    ref = orc.cache_walks(osc, g, None, orc.walk_params(1e-3, W, 17, side_read=True), cache)
     uh, dh = orc.reduce(ref["U"], ref["D"], W)
     a, b = uh * cache["w"], dh * cache["w"]
     rng = np.random.default_rng(6)

@@ -49,17 +49,23 @@ def test_mixed_samples_rectangle():
     assert np.all((ty == 1) == np.isin(np.round(x[:, 1], 12), [0.0, 1.0]) | (ty == 1))
     rej_n = (ty == 1) & ~acc
     assert np.all((x[rej_n, 0] <= l + 1e-12) | (x[rej_n, 0] >= 2 - l - 1e-12))
-    # total accepted weight = length of the offset region's boundary, less the
-    # l/100 that each offset line drops at each Neumann wall
-    assert np.all(s["R0"][off] >= 1e-2 * l)
-    exact = 2 * 1.0 + 2 * (2 - 2 * l) - 4 * 1e-2 * l
+    # total accepted weight = length of the offset region's boundary
+    exact = 2 * 1.0 + 2 * (2 - 2 * l)
     assert abs(s["w"][acc].sum() - exact) <= 8 * M / n
+    # the optional junction drop removes junction_drop * l of each offset
+    # line at each Neumann wall (four pieces), and nothing else
+    s2 = orc.sample_mixed(of, od, on, n, l, 41, 3, junction_drop=0.05)
+    acc2 = s2["accept"]
+    assert np.all(s2["R0"][acc2 & (s2["type"] == 0)] >= 0.05 * l)
+    assert np.array_equal(acc2 & (s2["type"] == 1), acc & (ty == 1))
+    assert np.all(acc2 <= acc)
+    assert abs(s2["w"][acc2].sum() - (exact - 4 * 0.05 * l)) <= 8 * M / n
     # distances: R0 to the whole boundary, xbar on the nearest Dirichlet side
     d_full = np.minimum.reduce([x[:, 0], 2 - x[:, 0], x[:, 1], 1 - x[:, 1]])
     assert np.allclose(s["R0"][acc], d_full[acc], atol=1e-12)
-    # xbar: the closest Dirichlet point seen from the sample, 1e-3 of the way back
+    # xbar: the closest Dirichlet point
     xb = np.stack([np.where(x[:, 0] < 1, 0.0, 2.0), np.clip(x[:, 1], 0, 1)], 1)
-    assert np.allclose(s["xbar"][acc], (xb + 1e-3 * (x - xb))[acc], atol=1e-12)
+    assert np.allclose(s["xbar"][acc], xb[acc], atol=1e-12)
 
 
 def _strip():
@@ -78,10 +84,22 @@ def test_mixed_representation_with_exact_data():
     gu = np.stack([np.exp(z[:, 0]) * np.cos(z[:, 1]), -np.exp(z[:, 0]) * np.sin(z[:, 1])], 1)
     dudn = np.sum(gu * nz, 1)
     assert np.all(np.abs(dudn[s["type"][acc] == 1]) < 1e-12)  # zero flux on the Neumann sides
-    # the sampler drops the l/100 of each offset line next to a Neumann wall
-    # (four pieces); their exact contribution, by the midpoint rule, closes
-    # the curve again
+    rng = np.random.default_rng(3)
+    xin = np.stack([rng.uniform(l + 0.15, 1 - l - 0.15, 40), rng.uniform(0.3, np.pi - 0.3, 40)], 1)
+    got = orc.gather(2, xin, z, nz, u * w, dudn * w, with_grad=False)
+    # the stratified samples are a midpoint-like quadrature of the closed
+    # curve: each end of a piece cuts a stratum of width M/n = 8e-4
+    assert np.allclose(got, wl.field_value(g, xin), atol=2e-4)
+    # with the optional junction drop the curve has four gaps of length
+    # 0.01 l = 8e-4 next to the Neumann walls: the representation then misses
+    # the gaps' share of Green's formula, and adding the gaps back by the
+    # midpoint rule closes the curve again
     dl, m = 1e-2 * l, 64
+    s2 = orc.sample_mixed(of, od, on, n, l, 7, junction_drop=1e-2)
+    acc2 = s2["accept"]
+    z2, n2, w2 = s2["x"][acc2], s2["n"][acc2], s2["w"][acc2]
+    u2 = wl.field_value(g, z2)
+    d2 = np.sum(np.stack([np.exp(z2[:, 0]) * np.cos(z2[:, 1]), -np.exp(z2[:, 0]) * np.sin(z2[:, 1])], 1) * n2, 1)
     ys = (np.arange(m) + 0.5) / m * dl
     gz, gn = [], []
     for xo, nx in ((l, -1.0), (1 - l, 1.0)):
@@ -92,14 +110,13 @@ def test_mixed_representation_with_exact_data():
     gw = np.full(gz.shape[0], dl / m)
     gu = wl.field_value(g, gz)
     gd = np.sum(np.stack([np.exp(gz[:, 0]) * np.cos(gz[:, 1]), -np.exp(gz[:, 0]) * np.sin(gz[:, 1])], 1) * gn, 1)
-    rng = np.random.default_rng(3)
-    xin = np.stack([rng.uniform(l + 0.15, 1 - l - 0.15, 40), rng.uniform(0.3, np.pi - 0.3, 40)], 1)
-    zz, nn = np.concatenate([z, gz]), np.concatenate([nz, gn])
-    got = orc.gather(2, xin, zz, nn, np.concatenate([u * w, gu * gw]), np.concatenate([dudn * w, gd * gw]),
-                     with_grad=False)
-    # (each end of a piece cuts a stratum of width M/n = 8e-4: up to about
-    # 4e-4 of quadrature error there)
-    assert np.allclose(got, wl.field_value(g, xin), atol=6e-4)
+    gap = orc.gather(2, xin, gz, gn, gu * gw, gd * gw, with_grad=False)
+    dropped = orc.gather(2, xin, z2, n2, u2 * w2, d2 * w2, with_grad=False)
+    # (each end of a gap cuts a stratum too: up to about 4e-4 there)
+    assert np.allclose(dropped + gap, wl.field_value(g, xin), atol=6e-4)
+    # the bias the drop adds at these points is of the same order as the
+    # quadrature error of the plain sampler, far below the walks' noise
+    assert 1e-4 < np.max(np.abs(gap)) < 2e-3
     # in the Dirichlet band (outside the offset region) the integral vanishes
     xb = np.stack([rng.uniform(0.2 * l, 0.6 * l, 20), rng.uniform(0.5, np.pi - 0.5, 20)], 1)
     out = orc.gather(2, xb, z, nz, u * w, dudn * w, with_grad=False)

@@ -53,8 +53,8 @@ def test_roi_samples_2d():
     assert np.all(oroi.inside(s["x"] + 1e-6 * s["n"]) == 0) and np.all(oroi.inside(s["x"] - 1e-6 * s["n"]) != 0)
     d_dom, xb, _ = odom.closest(s["x"])
     assert np.allclose(s["R0"], d_dom, rtol=0, atol=1e-15)
-    # xbar: the closest domain point seen from the sample, 1e-3 of the way back
-    assert np.allclose(s["xbar"], xb + 1e-3 * (s["x"] - xb), atol=1e-15)
+    # xbar: the closest domain point
+    assert np.allclose(s["xbar"], xb, atol=1e-15)
     # a region that leaves the domain: its outside samples are rejected
     roi2 = shifted(wl.circle_polygon(64), 0.5, (0.8, 0.0))
     s2 = orc.sample_roi(odom, orc.Scene(roi2), 2000, 3)

@@ -394,6 +394,8 @@ class Problem:
     seed_sources: int = 0
     extra: dict = field(default_factory=dict)
     sigma: float = 0.0     # screening coefficient of Lap u - sigma u = f (Eq. 1)
+    side_read: bool = False      # side rule of double-sided data (Appendix B)
+    junction_drop: float = 0.0   # mixed cache: drop offset points within this * l of the Neumann part
 
 
 def _harm_c1() -> Field:
@@ -478,7 +480,7 @@ def problem_slit_disk(grid: int = 256, n_cache: int = 16384, n_walks: int = 128)
     lo, hi = sc.bbox
     return Problem("slit_disk_double_sided", sc, g, Field(), n_cache, n_walks, eps, 5 * eps, 0,
                    grid2d(grid, lo, hi), g, sides=1, precision="f32",
-                   seed_walks=seed(8, 4), seed_cache=seed(8, 3), seed_sources=seed(8, 6))
+                   seed_walks=seed(8, 4), seed_cache=seed(8, 3), seed_sources=seed(8, 6), side_read=True)
 
 
 def mixed_polygon(verts, neumann, counts, name="mixed"):
@@ -518,7 +520,7 @@ def problem_c2_mixed(grid: int = 1024, n_cache: int = 262144, n_walks: int = 256
     return Problem("c2_channel4096_mixed", full, g, Field(), n_cache, n_walks, eps, 5 * eps, 0,
                    grid2d(grid, lo, hi), g, sides=1, precision="f32",
                    seed_walks=seed(7, 4), seed_cache=seed(7, 3), seed_sources=seed(7, 6),
-                   extra=dict(dirichlet=dir_, neumann=neu))
+                   extra=dict(dirichlet=dir_, neumann=neu), junction_drop=1e-2)
 
 
 def problem_c3(n_eval_box: int = 2_320_000, slice_n: int = 256, level: int = 6) -> Problem:
