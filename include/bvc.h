@@ -335,6 +335,30 @@ int bvc_pointwise_wos(bvc_scene scene, const bvc_walk_params* params, int64_t n,
                       void* U_walk, void* G_walk, void* work, size_t work_bytes, void* u, void* grad,
                       uint64_t* counters, void* stream);
 
+/* Pointwise walk on spheres that allocates nothing, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same walks, same Philox streams and the
+ * same results, bit for bit, as bvc_pointwise_wos; the per-walk values U_walk
+ * and G_walk and the workspace (start radii, closest points, exit records)
+ * live in a library-owned device array of BVC_POINTWISE_STATIC_BYTES (32 MiB)
+ * on each GPU, held from module load until the process ends, instead of in
+ * caller buffers.  The caller still owns x [dim][n], u [n], grad [dim][n]
+ * (optional) and counters (device uint64[4]), as for bvc_pointwise_wos.
+ * A call needs bvc_pointwise_static_bytes(dim, n, W, dtype, grad != NULL) <=
+ * BVC_POINTWISE_STATIC_BYTES: about n W (1 + dim) words of the walk dtype
+ * without grad and n W (1 + 3 dim) with it; a larger call returns BVC_EINVAL
+ * (nothing is launched) and the caller splits its points over several calls.
+ * Every call on one GPU uses that GPU's one array, which keeps the last call's
+ * contents (nothing in it needs to start at zero): calls that overlap on one
+ * GPU (two streams, two host threads) race and must be serialised by the
+ * caller.  The first call on each device resolves the array's device address
+ * (hipGetSymbolAddress, with that device current); no call makes a HIP
+ * allocation or calls a routine that allocates. */
+#define BVC_POINTWISE_STATIC_BYTES ((size_t)32 << 20)
+size_t bvc_pointwise_static_bytes(int32_t dim, int64_t n, int32_t W, int32_t dtype, int32_t with_grad);
+int bvc_pointwise_wos_noalloc(bvc_scene scene, const bvc_walk_params* params, int64_t n, const void* x,
+                              void* u, void* grad, uint64_t* counters, void* stream);
+
 /* ---------------------------------------------------------------------- */
 /* Gather (Eqs. 3-6; Algorithm 1 splat loops)                              */
 /* ---------------------------------------------------------------------- */

@@ -104,6 +104,7 @@ _SIGS = {
     "bvc_reduce_walks": [C.c_int64, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp, _vp, C.c_int32, _vp, _vp, _vp],
     "bvc_pointwise_wos": [_vp, _P(bvc_walk_params), C.c_int64, _vp, _vp, _vp, _vp, C.c_size_t, _vp, _vp, _vp,
                           _vp],
+    "bvc_pointwise_wos_noalloc": [_vp, _P(bvc_walk_params), C.c_int64, _vp, _vp, _vp, _vp, _vp],
     "bvc_gather_u": [C.c_int32, _P(bvc_cache_view), _P(bvc_source_view), C.c_int64, _vp, _vp,
                      _P(bvc_gather_params), _vp],
     "bvc_gather_grad": [C.c_int32, _P(bvc_cache_view), _P(bvc_source_view), C.c_int64, _vp, _vp, _vp,
@@ -156,11 +157,17 @@ _L.bvc_clamp_radius.argtypes = [C.c_int32, C.c_double]
 _L.bvc_clamp_radius.restype = C.c_double
 _L.bvc_clamp_workspace_bytes.argtypes = [C.c_int32, C.c_int32, C.c_int64, C.c_int32, C.c_int32]
 _L.bvc_clamp_workspace_bytes.restype = C.c_size_t
+_L.bvc_pointwise_static_bytes.argtypes = [C.c_int32, C.c_int64, C.c_int32, C.c_int32, C.c_int32]
+_L.bvc_pointwise_static_bytes.restype = C.c_size_t
+
+# size of the library's static scratch of bvc_pointwise_wos_noalloc
+POINTWISE_STATIC_BYTES = 32 << 20
 
 EXPORTED = sorted(list(_SIGS) + ["bvc_last_error", "bvc_version", "bvc_compact_scratch_ints",
                                  "bvc_cache_backward_scratch_doubles", "bvc_pointwise_workspace_bytes",
                                  "bvc_gather_multi_workspace_bytes", "bvc_batch_workspace_bytes",
-                                 "bvc_clamp_radius", "bvc_clamp_workspace_bytes", "bvc_wost_workspace_bytes"])
+                                 "bvc_clamp_radius", "bvc_clamp_workspace_bytes", "bvc_wost_workspace_bytes",
+                                 "bvc_pointwise_static_bytes"])
 
 
 def _check(rc, name):
@@ -335,6 +342,15 @@ def bvc_pointwise_wos(scene, params: bvc_walk_params, n, x, U_walk, G_walk, work
     nbytes = 0 if work is None else work.numel() * work.element_size()
     _check(_L.bvc_pointwise_wos(scene, C.byref(params), n, ptr(x), ptr(U_walk), ptr(G_walk), ptr(work), nbytes,
                                 ptr(u), ptr(grad), ptr(counters), stream_ptr(stream)), "bvc_pointwise_wos")
+
+
+def bvc_pointwise_static_bytes(dim, n, W, dtype, with_grad) -> int:
+    return int(_L.bvc_pointwise_static_bytes(dim, n, W, dtype, int(bool(with_grad))))
+
+
+def bvc_pointwise_wos_noalloc(scene, params: bvc_walk_params, n, x, u, grad, counters, stream=None):
+    _check(_L.bvc_pointwise_wos_noalloc(scene, C.byref(params), n, ptr(x), ptr(u), ptr(grad), ptr(counters),
+                                        stream_ptr(stream)), "bvc_pointwise_wos_noalloc")
 
 
 def _views(cache, sources):

@@ -1048,6 +1048,112 @@ ClampLayout clamp_layout(int dim, int dtype, int64_t n, int n_rays, int max_hits
   return L;
 }
 }  // namespace
+
+// Scratch of bvc_pointwise_wos_noalloc: start radii, closest points, exit
+// records and per-walk values live here instead of in caller buffers.  Each
+// GPU holds its own copy of the array from module load until the process
+// ends.  Host code never passes the array's name to a kernel (on the host it
+// is only a stand-in symbol): static_scratch() resolves each device's own
+// address once, with that device current, and every use goes through it.
+static __device__ __align__(256) unsigned char scratch[BVC_POINTWISE_STATIC_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+int static_scratch(char** out) {
+  int dev = 0;
+  int rc = check_hip(hipGetDevice(&dev), "hipGetDevice");
+  if (rc) return rc;
+  if (dev < 0 || dev >= kMaxDevices) return fail(BVC_EUNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    rc = check_hip(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (rc) return rc;
+    if (!ptr || ((uintptr_t)ptr & 255) != 0) return fail(BVC_EDEVICE, "static scratch address is null or misaligned");
+    g_scratch_ptr[dev] = (char*)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return BVC_OK;
+}
+
+int pointwise_check(bvc_scene s, const bvc_walk_params* p, int64_t n, const void* x, const void* u,
+                    const uint64_t* counters) {
+  int rc = check_scene(s);
+  if (rc) return rc;
+  rc = check_walk_params(p, s->h.dim, &s->h);
+  if (rc) return rc;
+  if (n < 0) return fail(BVC_EINVAL, "n must be >= 0");
+  if ((uint64_t)n * (uint64_t)p->n_walks >= (1ull << 32)) return fail(BVC_EINVAL, "n * W >= 2^32");
+  if (!counters) return fail(BVC_EINVAL, "counters is null");
+  if (n > 0 && (!x || !u)) return fail(BVC_EINVAL, "null input/output");
+  return BVC_OK;
+}
+
+// Closest points of the start points, the walks, and the means.  `work` holds
+// the layout of bvc_pointwise_workspace_bytes: R0 [n] FP64, xbar [dim][n]
+// FP64, exit records [dim][n W], first-ball weights [dim][n W] (grad only).
+int pointwise_run(bvc_scene s, const bvc_walk_params* p, int64_t n, const void* x, void* U_walk, void* G_walk,
+                  char* work, void* u, void* grad, uint64_t* counters, hipStream_t st) {
+  const int dim = s->h.dim;
+  const size_t es = p->dtype == BVC_F64 ? 8 : 4;
+  const size_t nw = (size_t)n * (size_t)p->n_walks;
+  char* w = work;
+  double* R0 = (double*)w;
+  w += align256((size_t)n * 8);
+  double* xbar = (double*)w;
+  w += align256((size_t)dim * n * 8);
+  void* ex = w;
+  w += align256((size_t)dim * nw * es);
+  void* gw = grad ? (void*)w : nullptr;
+  if (n > 0) {
+    const int blocks = (int)((n + kBlock - 1) / kBlock);
+    const size_t lds = stack_bytes(s->h);
+    SceneDev S = s->h.view();
+    if (dim == 2) {
+      if (p->dtype == BVC_F32)
+        hipLaunchKernelGGL((k_closest_points<float, 2>), dim3(blocks), dim3(kBlock), lds, st, S, n, (const float*)x,
+                           R0, xbar);
+      else
+        hipLaunchKernelGGL((k_closest_points<double, 2>), dim3(blocks), dim3(kBlock), lds, st, S, n,
+                           (const double*)x, R0, xbar);
+    } else {
+      if (p->dtype == BVC_F32)
+        hipLaunchKernelGGL((k_closest_points<float, 3>), dim3(blocks), dim3(kBlock), lds, st, S, n, (const float*)x,
+                           R0, xbar);
+      else
+        hipLaunchKernelGGL((k_closest_points<double, 3>), dim3(blocks), dim3(kBlock), lds, st, S, n,
+                           (const double*)x, R0, xbar);
+    }
+  }
+  WalkArgs a{};
+  a.px = x;
+  a.R0 = R0;
+  a.xbar = xbar;
+  a.U = U_walk;
+  a.Dof = grad ? G_walk : nullptr;
+  a.exit = ex;
+  a.w1 = gw;
+  a.counters = (unsigned long long*)counters;
+  int rc = run_walks(s, p, 1, n, a, st);
+  if (rc || n == 0) return rc;
+  const int per = kBlock / 64;
+  const int blocks = (int)((n + per - 1) / per);
+  const int rows = grad ? dim : 0;
+  const int64_t ld = n * (int64_t)p->n_walks;
+  if (p->dtype == BVC_F32)
+    hipLaunchKernelGGL((k_reduce<float, float>), dim3(blocks), dim3(kBlock), 0, st, n, p->n_walks, rows, ld,
+                       (const float*)U_walk, (const float*)G_walk, nullptr, nullptr, nullptr, (float*)u,
+                       (float*)grad, n);
+  else
+    hipLaunchKernelGGL((k_reduce<double, double>), dim3(blocks), dim3(kBlock), 0, st, n, p->n_walks, rows, ld,
+                       (const double*)U_walk, (const double*)G_walk, nullptr, nullptr, nullptr, (double*)u,
+                       (double*)grad, n);
+  return check_hip(hipGetLastError(), "pointwise reduce launch");
+}
+}  // namespace
 }  // namespace bvc
 
 using namespace bvc;
@@ -1216,74 +1322,47 @@ size_t bvc_pointwise_workspace_bytes(int32_t dim, int64_t n, int32_t W, int32_t 
 
 int bvc_pointwise_wos(bvc_scene s, const bvc_walk_params* p, int64_t n, const void* x, void* U_walk, void* G_walk,
                       void* work, size_t work_bytes, void* u, void* grad, uint64_t* counters, void* stream) {
-  int rc = check_scene(s);
+  int rc = pointwise_check(s, p, n, x, u, counters);
   if (rc) return rc;
-  const int dim = s->h.dim;
-  rc = check_walk_params(p, dim, &s->h);
-  if (rc) return rc;
-  if (n < 0) return fail(BVC_EINVAL, "n must be >= 0");
-  if ((uint64_t)n * (uint64_t)p->n_walks >= (1ull << 32)) return fail(BVC_EINVAL, "n * W >= 2^32");
-  if (!counters) return fail(BVC_EINVAL, "counters is null");
-  if (n > 0 && (!x || !U_walk || !u || !work)) return fail(BVC_EINVAL, "null input/output/workspace");
+  if (n > 0 && (!U_walk || !work)) return fail(BVC_EINVAL, "null per-walk scratch or workspace");
   if (grad && !G_walk) return fail(BVC_EINVAL, "grad needs G_walk scratch");
-  const size_t need = bvc_pointwise_workspace_bytes(dim, n, p->n_walks, p->dtype, grad != nullptr);
+  const size_t need = bvc_pointwise_workspace_bytes(s->h.dim, n, p->n_walks, p->dtype, grad != nullptr);
   if (n > 0 && work_bytes < need) return fail(BVC_EINVAL, "pointwise workspace too small");
   if (((uintptr_t)work & 255) != 0) return fail(BVC_EINVAL, "workspace must be 256-byte aligned");
-  hipStream_t st = (hipStream_t)stream;
+  return pointwise_run(s, p, n, x, U_walk, G_walk, (char*)work, u, grad, counters, (hipStream_t)stream);
+}
+
+size_t bvc_pointwise_static_bytes(int32_t dim, int64_t n, int32_t W, int32_t dtype, int32_t with_grad) {
+  if (n < 0 || W < 1 || (dim != 2 && dim != 3)) return 0;
+  const size_t es = dtype == BVC_F64 ? 8 : 4;
+  const size_t nw = (size_t)n * (size_t)W;
+  size_t b = bvc_pointwise_workspace_bytes(dim, n, W, dtype, with_grad) + align256(nw * es);
+  if (with_grad) b += align256((size_t)dim * nw * es);
+  return b;
+}
+
+int bvc_pointwise_wos_noalloc(bvc_scene s, const bvc_walk_params* p, int64_t n, const void* x, void* u, void* grad,
+                              uint64_t* counters, void* stream) {
+  int rc = pointwise_check(s, p, n, x, u, counters);
+  if (rc) return rc;
+  const size_t need = bvc_pointwise_static_bytes(s->h.dim, n, p->n_walks, p->dtype, grad != nullptr);
+  if (need > BVC_POINTWISE_STATIC_BYTES)
+    return fail(BVC_EINVAL, "bvc_pointwise_wos_noalloc: " + std::to_string(n) + " points x " +
+                                std::to_string(p->n_walks) + " walks need " + std::to_string(need) +
+                                " bytes of scratch, more than the library's static " +
+                                std::to_string((size_t)BVC_POINTWISE_STATIC_BYTES) +
+                                " (use fewer points per call, or bvc_pointwise_wos with a workspace)");
+  char* base = nullptr;
+  rc = static_scratch(&base);
+  if (rc) return rc;
+  const int dim = s->h.dim;
   const size_t es = p->dtype == BVC_F64 ? 8 : 4;
   const size_t nw = (size_t)n * (size_t)p->n_walks;
-  char* w = (char*)work;
-  double* R0 = (double*)w;
-  w += align256((size_t)n * 8);
-  double* xbar = (double*)w;
-  w += align256((size_t)dim * n * 8);
-  void* ex = w;
-  w += align256((size_t)dim * nw * es);
-  void* gw = grad ? (void*)w : nullptr;
-  if (n > 0) {
-    const int blocks = (int)((n + kBlock - 1) / kBlock);
-    const size_t lds = stack_bytes(s->h);
-    SceneDev S = s->h.view();
-    if (dim == 2) {
-      if (p->dtype == BVC_F32)
-        hipLaunchKernelGGL((k_closest_points<float, 2>), dim3(blocks), dim3(kBlock), lds, st, S, n, (const float*)x,
-                           R0, xbar);
-      else
-        hipLaunchKernelGGL((k_closest_points<double, 2>), dim3(blocks), dim3(kBlock), lds, st, S, n,
-                           (const double*)x, R0, xbar);
-    } else {
-      if (p->dtype == BVC_F32)
-        hipLaunchKernelGGL((k_closest_points<float, 3>), dim3(blocks), dim3(kBlock), lds, st, S, n, (const float*)x,
-                           R0, xbar);
-      else
-        hipLaunchKernelGGL((k_closest_points<double, 3>), dim3(blocks), dim3(kBlock), lds, st, S, n,
-                           (const double*)x, R0, xbar);
-    }
-  }
-  WalkArgs a{};
-  a.px = x;
-  a.R0 = R0;
-  a.xbar = xbar;
-  a.U = U_walk;
-  a.Dof = grad ? G_walk : nullptr;
-  a.exit = ex;
-  a.w1 = gw;
-  a.counters = (unsigned long long*)counters;
-  rc = run_walks(s, p, 1, n, a, st);
-  if (rc || n == 0) return rc;
-  const int per = kBlock / 64;
-  const int blocks = (int)((n + per - 1) / per);
-  const int rows = grad ? dim : 0;
-  const int64_t ld = n * (int64_t)p->n_walks;
-  if (p->dtype == BVC_F32)
-    hipLaunchKernelGGL((k_reduce<float, float>), dim3(blocks), dim3(kBlock), 0, st, n, p->n_walks, rows, ld,
-                       (const float*)U_walk, (const float*)G_walk, nullptr, nullptr, nullptr, (float*)u,
-                       (float*)grad, n);
-  else
-    hipLaunchKernelGGL((k_reduce<double, double>), dim3(blocks), dim3(kBlock), 0, st, n, p->n_walks, rows, ld,
-                       (const double*)U_walk, (const double*)G_walk, nullptr, nullptr, nullptr, (double*)u,
-                       (double*)grad, n);
-  return check_hip(hipGetLastError(), "pointwise reduce launch");
+  // layout: the bvc_pointwise_wos workspace, then U_walk [n W], then G_walk [dim][n W]
+  char* w = base + bvc_pointwise_workspace_bytes(dim, n, p->n_walks, p->dtype, grad != nullptr);
+  void* U_walk = w;
+  void* G_walk = grad ? (void*)(w + align256(nw * es)) : nullptr;
+  return pointwise_run(s, p, n, x, U_walk, G_walk, base, u, grad, counters, (hipStream_t)stream);
 }
 
 int bvc_reduce_walks(int64_t n_cache, int32_t W, int32_t dti, const void* U, const void* D, const double* w,
