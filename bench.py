@@ -1,19 +1,22 @@
 """Benchmark: Boundary Value Caching on one MI355X.
 
-One step is one pass of the whole hot path over the 2D Poisson workload with
-a self-intersecting 4096-segment star: cache sampling (16,384 cache points
-on the offset boundary), 256 walks per cache point, FP64 cache means, source
-samples (128^2 jittered), gather of u and grad u at the interior points of a
-1024^2 grid, and pointwise walks for the grid points within l of the
-boundary.  Inputs are synthetic and seeded (no dataset exists for this
-method); the scene is built and uploaded once before timing.
+The headline line is the 3D Laplace workload: a displaced icosphere of 81,920
+triangles with solid-harmonic boundary data (degree <= 8).  One step is one
+pass of the whole hot path: 65,536 cache points on the offset boundary, 512
+walks each, FP64 cache means, the gather of u at every interior point of a
+1,048,576-point uniform sample plus a 256^2 slice, and pointwise walks for the
+points within l of the boundary.  The 2D Poisson workload (4096-segment
+self-intersecting star, 16,384 cache points x 256 walks, u and grad u on a
+1024^2 grid, 128^2 Gaussian sources) runs after it and is reported under the
+key "c2" with the same fields.  Inputs are synthetic and seeded (no dataset
+exists for this method); each scene is built and uploaded once before timing.
 
-Prints one JSON line: interior points per second of the BVC step, walk steps
-per second, the error of the BVC result against the manufactured closed form
-next to pointwise walk on spheres at matching error, the roofline of the
-longest kernel of the step (the band-point walks, memory roofline on
-algorithmic traversal bytes) and of the gather (VALU roofline), and the FP64
-oracle timed on the host cores.
+Each workload reports: interior points per second of the BVC step, walk
+steps per second, the error of the BVC result against the closed form next to
+pointwise walk on spheres at matching error, the memory roofline of the
+longest kernel (the walks, on algorithmic traversal bytes) with its VALU
+bound, the VALU roofline of the gather, and the FP64 oracle timed on the host
+cores (all threads and one thread).
 """
 from __future__ import annotations
 
@@ -23,6 +26,7 @@ import json
 import math
 import os
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -33,13 +37,31 @@ if ROOT not in sys.path:
 
 PEAK_FP32_TFLOPS = 157.3   # MI355X published FP32 vector peak
 PEAK_HBM_GBS = 8000.0
+# lane-operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+PEAK_LANE_OPS = 256 * 64 * 2.4e9
 
-# Algorithmic FP operations per gather pair (transcendentals count 1), 2D u and
-# grad u: boundary entry (Eqs. 3 and 5) and source entry (Eqs. 4 and 6).
+# Algorithmic FP operations per gather pair (transcendentals count 1): 2D u
+# and grad u, boundary entry (Eqs. 3 and 5) and source entry (Eqs. 4 and 6);
+# 3D u, boundary entry (Eq. 3): difference (3), r^2 (5), rsqrt (1), r^-2 and
+# r^-3 (2), n.(y - x) (5), the two terms and their accumulation (4).
 FLOPS_2D_BOUNDARY_UG = 26
 FLOPS_2D_SOURCE_UG = 14
-FLOPS_2D_BOUNDARY_U = 14
-FLOPS_2D_SOURCE_U = 8
+FLOPS_3D_BOUNDARY_U = 20
+
+# Minimal VALU lane-operations of one walk step (one closest-point query and
+# the sphere jump that follows it), counted from the arithmetic of each part:
+# a Philox-4x32-10 block is ten rounds of two 32-bit multiplies in high and
+# low halves, four xors and two key additions; a node expansion is two child
+# boxes (per axis: two differences, a three-way max against 0 and a
+# multiply-add) plus the ordering of the two; a segment is the clamped
+# projection and its squared distance; a triangle is the face-region closest
+# point (edge vectors, six dot products, barycentric weights, the point and
+# its squared distance); the step itself draws the direction, jumps and tests
+# the shell.
+OPS_PHILOX_BLOCK = 100
+OPS_NODE = {2: 22, 3: 30}
+OPS_PRIM = {2: 15, 3: 50}
+OPS_STEP = {2: 12, 3: 15}
 
 
 def parse():
@@ -47,14 +69,16 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--grid", type=int, default=1024)
-    ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--grid", type=int, default=1024, help="c2: evaluation grid size")
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f64"], help="c2: walk and gather precision")
     ap.add_argument("--no-pointwise", action="store_true", help="skip the pointwise-WoS comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4a", "c4b", "c2clamp", "c3clamp", "c3screen", "c2roi",
-                                                    "c2mixed", "c2screen", "c2slit", "c3open"],
-                    help="c2 prints the benchmark line; the others print their own measurement lines")
+    ap.add_argument("--no-c2", action="store_true", help="c3 headline without the c2 line")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of each CPU oracle leg")
+    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c4a", "c4b", "c2clamp", "c3clamp", "c3screen",
+                                                    "c2roi", "c2mixed", "c2screen", "c2slit", "c3open"],
+                    help="c3 (headline, with c2 under the key 'c2') and c2 print the benchmark line; the others "
+                         "print their own measurement lines")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes (no autotuning)")
     ap.add_argument("--clamp-c", type=float, default=20.0, help="c2clamp: bound c of dG/dn (Eq. 9)")
     ap.add_argument("--clamp-rays", type=int, default=64, help="c2clamp: rays per corrected point")
@@ -64,23 +88,28 @@ def parse():
     return ap.parse_args()
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def rmse(a, b):
-    return float(np.sqrt(np.mean((a - b) ** 2)))
+    return float(np.sqrt(np.mean((a - b) ** 2))) if len(a) else float("nan")
 
 
-def measured_traffic(kernel, sources):
-    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE /
-    WRITE_SIZE summary, or None when the kernel's sources have changed since
-    those counters were taken (their SHA-256 is recorded beside the figure)."""
+def measured_traffic(kernel, workload, sources):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    FETCH_SIZE / WRITE_SIZE summary, or None when the kernel's sources have
+    changed since those counters were taken (their SHA-256 is recorded beside
+    the figure)."""
     import hashlib
     import re
 
-    path = os.path.join(ROOT, "profiles", "c2_hbm_traffic.md")
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
-    m = re.search(r"kernel: " + re.escape(kernel) + r"\s+source_sha256: ([0-9a-f]{64})\s+"
-                  r"traffic_bytes_per_launch: (\d+)", text)
+    m = re.search(r"kernel: " + re.escape(kernel) + r"\s+workload: " + re.escape(workload) +
+                  r"\s+source_sha256: ([0-9a-f]{64})\s+traffic_bytes_per_launch: (\d+)", text)
     if not m:
         return None
     h = hashlib.sha256()
@@ -95,17 +124,280 @@ WALK_SOURCES = ("walks.hip", "bvc_device.hpp", "bvc_internal.hpp")
 
 
 def walk_bytes(dim, es, mode, with_grad):
-    """Algorithmic bytes of the walk kernel: per BVH node expanded (two child
-    boxes in the walk precision plus the int2 child links), per primitive
-    tested (segment: 4 values; triangle: 3 x 4 values), and per walk (inputs
-    read and records written; mode 0 cache walk, mode 1 pointwise walk)."""
-    node = 2 * 2 * dim * es + 8
-    prim = (4 if dim == 2 else 12) * es
+    """Algorithmic bytes of the walk kernel in the record sizes of FP32 (es =
+    4; FP64 doubles them): per binary BVH node expanded, 48 B in 2D and 64 B
+    in 3D (two child boxes and their links); per primitive tested, a 16 B
+    segment or a 36 B triangle; per walk, its inputs read and records
+    written (mode 0 cache walk, mode 1 pointwise walk)."""
+    s = es // 4
+    node = (48 if dim == 2 else 64) * s
+    prim = (16 if dim == 2 else 36) * s
     if mode == 0:
         io = 8 + 2 * dim * 8 + dim * es + 3 * es          # R0, x, n (FP64); exit, U, D, w1
     else:
         io = 8 + dim * es + dim * es + es + (2 * dim * es if with_grad else 0)  # R0, x; exit, U, grad, w1
     return node, prim, io
+
+
+def philox_blocks_per_step(dim, src):
+    """Philox blocks a walk step evaluates: the direction, plus the in-ball
+    source point of a Poisson walk (two blocks in 2D, three in 3D)."""
+    return 1 + ((2 if dim == 2 else 3) if src else 0)
+
+
+def walk_roofline(kernel, dim, es, mode, with_grad, ms, queries, walks, work_key, work, src, traffic):
+    """Memory roofline of one walk launch on algorithmic traversal bytes (the
+    nodes and primitives a nearest-first query visits, counted by the oracle
+    on this BVH, times their record sizes, plus each walk's inputs and
+    records), and its VALU bound: the minimal lane-operations of those
+    visits, the Philox blocks and the step arithmetic, against the chip's
+    lane-operation peak."""
+    node_b, prim_b, io_b = walk_bytes(dim, es, mode, with_grad)
+    out = {"bound": "hbm", "achieved": None, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": None,
+           "traffic": traffic, "kernel": kernel, "avg_launch_ms": round(ms, 4), "queries_per_launch": queries,
+           "walks_per_launch": walks, "bytes": {"node": node_b, "primitive": prim_b, "walk_io": io_b}}
+    valu = None
+    if work is not None and ms > 0:
+        vn, vp = work[work_key]["nodes_per_query"], work[work_key]["prims_per_query"]
+        per_query = vn * node_b + vp * prim_b
+        alg = queries * per_query + walks * io_b
+        gbs = alg / (ms / 1e3) / 1e9
+        out.update(achieved=round(gbs, 1), frac=round(gbs / PEAK_HBM_GBS, 4), nodes_per_query=vn,
+                   prims_per_query=vp, bytes_per_query=round(per_query, 1), bytes_per_launch=alg)
+        ops = (philox_blocks_per_step(dim, src) * OPS_PHILOX_BLOCK + OPS_STEP[dim] + vn * OPS_NODE[dim] +
+               vp * OPS_PRIM[dim])
+        rate = queries * ops / (ms / 1e3)
+        valu = {"bound": "valu", "achieved": rate / 1e12, "peak": PEAK_LANE_OPS / 1e12, "unit": "Tlane-op/s",
+                "frac": round(rate / PEAK_LANE_OPS, 4), "kernel": kernel, "lane_ops_per_query": round(ops, 1),
+                "ops": {"philox_block": OPS_PHILOX_BLOCK, "philox_blocks_per_step": philox_blocks_per_step(dim, src),
+                        "node": OPS_NODE[dim], "primitive": OPS_PRIM[dim], "step": OPS_STEP[dim]}}
+    return out, valu
+
+
+def pointwise_curve(pl, prob, prep, dtype, pts, truth, rmse_bvc, value):
+    """Pointwise walk on spheres on a subset of interior points at 1 to 256
+    walks per point; the walks per point that match BVC's error come from the
+    fit rmse^2 = a/W + b^2, and the time per walk from the largest run."""
+    import torch
+
+    xs = torch.from_numpy(np.ascontiguousarray(pts.T)).to("cuda", pl.DT[dtype])
+    ks = xs.shape[1]
+    curve = []
+    for Wp in (1, 4, 16, 64, 256):
+        wp = pl.walk_params(prob.eps, Wp, prob.seed_walks + 1, prep.g, prep.f, dtype)
+        pl.pointwise(prep.sc, wp, xs, with_grad=False)  # warm
+        a0 = torch.cuda.Event(enable_timing=True)
+        a1 = torch.cuda.Event(enable_timing=True)
+        a0.record()
+        uo, _, cnt = pl.pointwise(prep.sc, wp, xs, with_grad=False)
+        a1.record()
+        torch.cuda.synchronize()
+        ms = a0.elapsed_time(a1)
+        curve.append({"walks": Wp, "rmse": rmse(uo.double().cpu().numpy()[:ks], truth), "ms": ms,
+                      "points_per_s": ks / (ms / 1e3), "steps": int(cnt[1])})
+    Ws = np.array([c["walks"] for c in curve], float)
+    r2 = np.array([c["rmse"] for c in curve]) ** 2
+    # least squares relative to each point's own size, so that every W counts
+    A = np.stack([1 / Ws, np.ones_like(Ws)], 1) / r2[:, None]
+    (a_fit, b2_fit), *_ = np.linalg.lstsq(A, np.ones_like(r2), rcond=None)
+    b2_fit = max(b2_fit, 0.0)
+    target = rmse_bvc**2
+    w_star = a_fit / (target - b2_fit) if target > b2_fit and a_fit > 0 else float("inf")
+    per_walk_ms = curve[-1]["ms"] / curve[-1]["walks"]
+    pw_pts_s = ks / (max(w_star, 1.0) * per_walk_ms / 1e3) if math.isfinite(w_star) else 0.0
+    return {"subset": ks, "rmse_bvc_subset": rmse_bvc, "curve": curve,
+            "fit": {"a": float(a_fit), "b2": float(b2_fit)},
+            "walks_for_equal_rmse": (float(w_star) if math.isfinite(w_star) else None),
+            "points_per_s_at_equal_rmse": pw_pts_s,
+            "bvc_over_pointwise": (value / pw_pts_s if pw_pts_s > 0 else None)}
+
+
+def timed_steps(pl, prep, args, with_grad):
+    """Warm-up steps, then exactly args.steps steps between two events, with
+    the host garbage collector off and each step's buffers released before
+    the next, so that the caching allocator reuses them."""
+    import torch
+
+    for w in range(args.warmup):
+        pl.solve(prep, batch=1000 + w, with_grad=with_grad)
+    torch.cuda.synchronize()
+    watch = pl.Stopwatch()
+    counts = []
+    sol = None
+    gc.collect()
+    gc.disable()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    for s in range(args.steps):
+        sol = None
+        sol = pl.solve(prep, batch=s, with_grad=with_grad, watch=watch)
+        counts.append((sol.counters, sol.pw_counters))
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gc.enable()
+    ms_step = e0.elapsed_time(e1) / args.steps
+    timers = {k: float(np.mean(v)) for k, v in watch.totals_ms().items()}
+    return sol, counts, ms_step, wall, timers
+
+
+def run_workload(args, which):
+    """One benchmark line (without the process-level keys) for c2 or c3."""
+    import torch
+
+    import workloads as wl
+    from paper_2302_11825_amd import pipeline as pl
+
+    dim = 3 if which == "c3" else 2
+    dtype = "f32" if which == "c3" else args.dtype
+    with_grad = which == "c2"
+    t_setup = time.time()
+    prob = wl.problem_c3() if which == "c3" else wl.problem_c2(grid=args.grid)
+    prep = pl.Prepared(prob, dtype=dtype)
+    tuned = None if args.no_tune else pl.tune(prep, with_grad=with_grad, reps=1 if dim == 3 else 3)
+    torch.cuda.synchronize()
+    setup_s = time.time() - t_setup
+    log(f"{which} setup {setup_s:.1f}s: candidates {prep.n_cand}, interior {prep.n_int}, band {prep.n_band}")
+    if args.calib_copy_mib > 0:
+        # a plain copy of known size: the reference that scales HBM counters
+        src = torch.empty(args.calib_copy_mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    sol, counts, ms_step, wall, timers = timed_steps(pl, prep, args, with_grad)
+    kernels = {k: v for k, v in timers.items() if k.startswith("k_")}
+    stages = {k: v for k, v in timers.items() if not k.startswith("k_")}
+    log(f"{which} timed {args.steps} steps: {ms_step:.2f} ms/step (wall {wall:.2f}s) {stages}")
+
+    n_pts = prep.n_int + prep.n_band
+    value = n_pts / (ms_step / 1e3)
+    steps_total = sum(int(c[1]) + int(p[1]) for c, p in counts)
+    walks_total = sum(int(c[3]) + int(p[3]) for c, p in counts)
+    capped = sum(int(c[2]) + int(p[2]) for c, p in counts)
+    cache_ms = kernels.get("k_walks_cache", stages.get("cache_walks", 0.0))
+    band_ms = kernels.get("k_walks_band", stages.get("band_walks", 0.0))
+    cache_steps = sum(int(c[1]) for c, _ in counts) / args.steps
+
+    # error of the last step against the closed form (3D: an even sample of
+    # about 200k points, the solid harmonics being costly to evaluate)
+    idx_i = prep.idx_int[: prep.n_int].cpu().numpy()
+    idx_b = prep.idx_band[: prep.n_band].cpu().numpy()
+    stride = max(1, idx_i.size // 200000) if dim == 3 else 1
+    sel = np.arange(0, idx_i.size, stride)
+    pts_i = prob.eval_x[idx_i[sel]]
+    pts_b = prob.eval_x[idx_b]
+    truth_i = wl.field_value(prob.truth, pts_i)
+    truth_b = wl.field_value(prob.truth, pts_b)
+    u_i = sol.u_int[: prep.n_int].double().cpu().numpy()[sel]
+    u_b = sol.u_band[: prep.n_band].double().cpu().numpy()
+    dist_i = prep.dist[idx_i[sel]].cpu().numpy() if prep.n_int else np.zeros(0)
+    far = dist_i >= 0.05
+    err = {"all": rmse(np.concatenate([u_i, u_b]), np.concatenate([truth_i, truth_b])),
+           "gathered": rmse(u_i, truth_i), "gathered_d_ge_0.05": rmse(u_i[far], truth_i[far]),
+           "band": rmse(u_b, truth_b), "rms_true": float(np.sqrt(np.mean(truth_i**2)))}
+    if dim == 3:
+        err["sample"] = f"every {stride}th gathered point ({sel.size}) and every band point"
+    if with_grad:
+        grad_true = wl.field_grad_fd(prob.truth, pts_i[::16], 1e-6)
+        g_i = sol.g_int[:, : prep.n_int].double().cpu().numpy().T[sel][::16]
+        gerr = np.sum((g_i - grad_true) ** 2, axis=1)
+        err["grad"] = float(np.sqrt(np.mean(gerr)))
+        err["grad_d_ge_0.05"] = float(np.sqrt(np.mean(gerr[far[::16]]))) if far[::16].any() else float("nan")
+
+    # VALU roofline of the gather (one launch per step)
+    gather_ms = stages["gather"]
+    n_src = int(sol.extra["sview"]["n"]) if sol.extra["sview"] else 0
+    pairs_b = prep.n_int * sol.cache.n
+    pairs_s = prep.n_int * n_src
+    if dim == 2:
+        flops = pairs_b * FLOPS_2D_BOUNDARY_UG + pairs_s * FLOPS_2D_SOURCE_UG
+        fpp = {"boundary": FLOPS_2D_BOUNDARY_UG, "source": FLOPS_2D_SOURCE_UG}
+    else:
+        flops = pairs_b * FLOPS_3D_BOUNDARY_U
+        fpp = {"boundary": FLOPS_3D_BOUNDARY_U}
+    achieved = flops / (gather_ms / 1e3) / 1e12
+    # the gather's template names its evaluation points per thread: the tuned
+    # value, else the library's default of 2
+    ppt = tuned["gather_points_per_thread"] if tuned else 2
+    T = "float" if dtype == "f32" else "double"
+    gather_kernel = f"k_gather<{T},{dim},{'true' if dim == 2 else 'false'},false,{ppt},false>"
+    roofline_gather = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+                       "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                       "traffic": measured_traffic(gather_kernel, which, GATHER_SOURCES),
+                       "kernel": gather_kernel, "pairs_per_launch": pairs_b + pairs_s, "flops_per_pair": fpp,
+                       "avg_launch_ms": round(gather_ms, 4), "pairs_per_s": (pairs_b + pairs_s) / (gather_ms / 1e3)}
+
+    pointwise = None
+    if not args.no_pointwise and prep.n_int > 0:
+        rng = np.random.default_rng(wl.seed(2 if dim == 2 else 3, 5))
+        sub = np.sort(rng.choice(sel.size, size=min(8192, sel.size), replace=False))
+        pointwise = pointwise_curve(pl, prob, prep, dtype, pts_i[sub], truth_i[sub], rmse(u_i[sub], truth_i[sub]),
+                                    value)
+        log(f"{which} pointwise {pointwise['walks_for_equal_rmse']} walks for equal RMSE")
+
+    cpu, work = None, None
+    if not args.no_cpu:
+        cpu, work = oracle_leg(prob, prep, sol, args.cpu_seconds, n_pts, dim, with_grad, pointwise)
+        log(f"{which} cpu baseline {cpu}")
+
+    es = 4 if dtype == "f32" else 8
+    src = prob.f.kind != 0
+    T = "float" if es == 4 else "double"
+    if dim == 3:
+        # the cache walks are the longest launch of the 3D step
+        kname = f"k_walks<{T},3,false,0>"
+        roofline, valu = walk_roofline(kname + " (cache walks)", 3, es, 0, False, cache_ms, int(sol.counters[1]),
+                                       int(sol.counters[3]), "cache", work, src,
+                                       measured_traffic(kname, which, WALK_SOURCES) if es == 4 else None)
+        other, other_valu = walk_roofline(f"k_walks<{T},3,false,1> (band-point walks)", 3, es, 1, False, band_ms,
+                                          int(sol.pw_counters[1]), int(sol.pw_counters[3]), "band", work, src, None)
+    else:
+        # the band-point walks are the longest launch of the 2D step
+        kname = f"k_walks<{T},2,true,1>"
+        roofline, valu = walk_roofline(kname + " (band-point walks)", 2, es, 1, True, band_ms,
+                                       int(sol.pw_counters[1]), int(sol.pw_counters[3]), "band", work, src,
+                                       measured_traffic(kname, which, WALK_SOURCES) if es == 4 else None)
+        other, other_valu = walk_roofline(f"k_walks<{T},2,true,0> (cache walks)", 2, es, 0, False, cache_ms,
+                                          int(sol.counters[1]), int(sol.counters[3]), "cache", work, src, None)
+    if work is not None:
+        roofline["counted_on"] = work["counted_on"]
+
+    config = {"workload": prob.name, "primitives": int(prob.scene.prims.shape[0]),
+              "cache_target": prob.n_cache, "cache_candidates": prep.n_cand, "cache_points": sol.cache.n,
+              "walks_per_point": prob.n_walks, "interior_points": prep.n_int, "band_points": prep.n_band,
+              "eps": prob.eps, "offset_l": prob.offset}
+    if dim == 2:
+        config.update(grid=f"{args.grid}x{args.grid}", sources=n_src)
+    else:
+        config.update(evaluation=f"{prob.extra['n_box']} uniform box candidates + {prob.extra['n_slice']}-point "
+                                 f"z = 0 slice, classified")
+    return {
+        "metric": "interior pts/sec at fixed RMSE (BVC vs pointwise WoS); walk steps/sec",
+        "value": value,
+        "unit": "points/s",
+        "ms_per_step": ms_step,
+        "dtype": dtype,
+        "config": config,
+        "walk_steps_per_s": steps_total / (ms_step * args.steps / 1e3),
+        "cache_walk_steps_per_s": cache_steps / (cache_ms / 1e3) if cache_ms > 0 else 0.0,
+        "walks_per_step": walks_total / args.steps,
+        "capped_walks": capped,
+        "stage_ms": {k: round(v, 4) for k, v in stages.items()},
+        "kernel_ms": {k: round(v, 4) for k, v in kernels.items()},
+        "rmse": err,
+        "pointwise_wos": pointwise,
+        "roofline": roofline,
+        "roofline_valu": valu,
+        "roofline_other_walks": {"hbm": other, "valu": other_valu},
+        "roofline_gather": roofline_gather,
+        "cpu_baseline": cpu,
+        "setup_s": setup_s,
+        "tuned_shapes": tuned,
+    }
 
 
 def main():
@@ -116,297 +408,148 @@ def main():
         sys.exit(2)
     import torch
 
-    import workloads as wl
-    from paper_2302_11825_amd import _bvc as B
-    from paper_2302_11825_amd import pipeline as pl
+    from paper_2302_11825_amd import pipeline as pl  # noqa: F401  (fails loudly without libbvc.so)
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    if args.workload != "c2":
+    if args.workload not in ("c2", "c3"):
         from paper_2302_11825_amd import measure
 
         measure.run(args)
         return
-    t_setup = time.time()
-    prob = wl.problem_c2(grid=args.grid)
-    prep = pl.Prepared(prob, dtype=args.dtype)
-    tuned = None if args.no_tune else pl.tune(prep, with_grad=True)
-    torch.cuda.synchronize()
-    setup_s = time.time() - t_setup
-    print(f"[bench] setup {setup_s:.1f}s: candidates {prep.n_cand}, interior {prep.n_int}, band {prep.n_band}",
-          file=sys.stderr, flush=True)
-
-    if args.calib_copy_mib > 0:
-        # a plain copy of known size: the reference that scales HBM counters
-        src = torch.empty(args.calib_copy_mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-    for w in range(args.warmup):
-        pl.solve(prep, batch=1000 + w)
-    torch.cuda.synchronize()
-    print("[bench] warmup done", file=sys.stderr, flush=True)
-
-    watch = pl.Stopwatch()
-    counts = []  # per step: (cache-walk counters, band-walk counters), device tensors
-    sol = None
-    torch.cuda.synchronize()
-    # the host's cyclic garbage collector stays out of the timed region, and
-    # each step's buffers are released before the next one so that the
-    # caching allocator reuses them instead of growing the pool mid-run
-    gc.collect()
-    gc.disable()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record()
-    for s in range(args.steps):
-        sol = None
-        sol = pl.solve(prep, batch=s, watch=watch)
-        counts.append((sol.counters, sol.pw_counters))
-    e1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gc.enable()
-    ms_step = e0.elapsed_time(e1) / args.steps
-    timers = {k: float(np.mean(v)) for k, v in watch.totals_ms().items()}
-    kernels = {k: v for k, v in timers.items() if k.startswith("k_")}
-    stages = {k: v for k, v in timers.items() if not k.startswith("k_")}
-    print(f"[bench] timed {args.steps} steps: {ms_step:.2f} ms/step (wall {wall:.2f}s) {stages}",
-          file=sys.stderr, flush=True)
-
-    n_pts = prep.n_int + prep.n_band
-    value = n_pts / (ms_step / 1e3)
-    steps_total = sum(int(c[1]) + int(p[1]) for c, p in counts)
-    walks_total = sum(int(c[3]) + int(p[3]) for c, p in counts)
-    capped = sum(int(c[2]) + int(p[2]) for c, p in counts)
-    walk_ms = kernels.get("k_walks_cache", stages.get("cache_walks", 0.0))
-    cache_steps = sum(int(c[1]) for c, _ in counts) / args.steps
-    cache_walk_rate = cache_steps / (walk_ms / 1e3) if walk_ms > 0 else 0.0
-
-    # error of the last step against the manufactured closed form
-    idx_i = prep.idx_int[: prep.n_int].cpu().numpy()
-    idx_b = prep.idx_band[: prep.n_band].cpu().numpy()
-    pts_i = prob.eval_x[idx_i]
-    pts_b = prob.eval_x[idx_b]
-    truth_i = wl.field_value(prob.truth, pts_i)
-    truth_b = wl.field_value(prob.truth, pts_b)
-    u_i = sol.u_int[: prep.n_int].double().cpu().numpy()
-    u_b = sol.u_band[: prep.n_band].double().cpu().numpy()
-    rmse_all = rmse(np.concatenate([u_i, u_b]), np.concatenate([truth_i, truth_b]))
-    rmse_int = rmse(u_i, truth_i)
-    dist_i = prep.dist[idx_i].cpu().numpy() if prep.n_int else np.zeros(0)
-    far = dist_i >= 0.05
-    rmse_far = rmse(u_i[far], truth_i[far]) if far.any() else float("nan")
-    grad_true = wl.field_grad_fd(prob.truth, pts_i[::16], 1e-6)
-    g_i = sol.g_int[:, : prep.n_int].double().cpu().numpy().T[::16]
-    gerr = np.sum((g_i - grad_true) ** 2, axis=1)
-    rmse_grad = float(np.sqrt(np.mean(gerr)))
-    far16 = far[::16]
-    rmse_grad_far = float(np.sqrt(np.mean(gerr[far16]))) if far16.any() else float("nan")
-    band_rmse = rmse(u_b, truth_b) if prep.n_band else float("nan")
-
-    # VALU roofline of the gather (one launch per step)
-    gather_ms = stages["gather"]
-    n_src = int(sol.extra["sview"]["n"]) if sol.extra["sview"] else 0
-    pairs_b = prep.n_int * sol.cache.n
-    pairs_s = prep.n_int * n_src
-    flops = pairs_b * FLOPS_2D_BOUNDARY_UG + pairs_s * FLOPS_2D_SOURCE_UG
-    achieved = flops / (gather_ms / 1e3) / 1e12
-    # the gather's template names its evaluation points per thread: the tuned
-    # value, else the library's default of 2
-    ppt = tuned["gather_points_per_thread"] if tuned else 2
-    gather_kernel = f"k_gather<float,2,true,false,{ppt},false>"
-    roofline_gather = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
-                       "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                       "traffic": measured_traffic(gather_kernel, GATHER_SOURCES),
-                       "kernel": gather_kernel, "pairs_per_launch": pairs_b + pairs_s,
-                       "flops_per_pair": {"boundary": FLOPS_2D_BOUNDARY_UG, "source": FLOPS_2D_SOURCE_UG},
-                       "avg_launch_ms": round(gather_ms, 4),
-                       "pairs_per_s": (pairs_b + pairs_s) / (gather_ms / 1e3)}
-
-    # pointwise walk on spheres at matching error, on a subset of interior points
-    pointwise = None
-    if not args.no_pointwise and prep.n_int > 0:
-        rng = np.random.default_rng(wl.seed(2, 5))
-        sub = np.sort(rng.choice(prep.n_int, size=min(8192, prep.n_int), replace=False))
-        xs = torch.from_numpy(np.ascontiguousarray(pts_i[sub].T)).to("cuda", pl.DT[args.dtype])
-        ks = xs.shape[1]
-        rmse_bvc_sub = rmse(u_i[sub], truth_i[sub])
-        curve = []
-        for Wp in (1, 4, 16, 64, 256):
-            wp = pl.walk_params(prob.eps, Wp, prob.seed_walks + 1, prep.g, prep.f, args.dtype)
-            pl.pointwise(prep.sc, wp, xs, with_grad=False)  # warm
-            a0 = torch.cuda.Event(enable_timing=True)
-            a1 = torch.cuda.Event(enable_timing=True)
-            a0.record()
-            uo, _, cnt = pl.pointwise(prep.sc, wp, xs, with_grad=False)
-            a1.record()
-            torch.cuda.synchronize()
-            ms = a0.elapsed_time(a1)
-            curve.append({"walks": Wp, "rmse": rmse(uo.double().cpu().numpy(), truth_i[sub]), "ms": ms,
-                          "points_per_s": ks / (ms / 1e3), "steps": int(cnt[1])})
-        # smallest W with RMSE <= BVC's, from the fit rmse^2 = a/W + b^2
-        Ws = np.array([c["walks"] for c in curve], float)
-        r2 = np.array([c["rmse"] for c in curve]) ** 2
-        # least squares relative to each point's own size, so that every W counts
-        A = np.stack([1 / Ws, np.ones_like(Ws)], 1) / r2[:, None]
-        (a_fit, b2_fit), *_ = np.linalg.lstsq(A, np.ones_like(r2), rcond=None)
-        b2_fit = max(b2_fit, 0.0)
-        target = rmse_bvc_sub**2
-        w_star = a_fit / (target - b2_fit) if target > b2_fit and a_fit > 0 else float("inf")
-        if math.isfinite(w_star):
-            # time per walk from the largest run
-            per_walk_ms = curve[-1]["ms"] / curve[-1]["walks"]
-            pw_pts_s = ks / (max(w_star, 1.0) * per_walk_ms / 1e3)
-        else:
-            pw_pts_s = 0.0
-        pointwise = {"subset": ks, "rmse_bvc_subset": rmse_bvc_sub, "curve": curve,
-                     "fit": {"a": float(a_fit), "b2": float(b2_fit)},
-                     "walks_for_equal_rmse": (float(w_star) if math.isfinite(w_star) else None),
-                     "points_per_s_at_equal_rmse": pw_pts_s,
-                     "bvc_over_pointwise": (value / pw_pts_s if pw_pts_s > 0 else None)}
-        print(f"[bench] pointwise {pointwise['walks_for_equal_rmse']} walks for equal RMSE", file=sys.stderr,
-              flush=True)
-
-    cpu, work = None, None
-    if not args.no_cpu:
-        cpu, work = oracle_leg(prob, prep, sol, args.cpu_seconds, n_pts)
-        print(f"[bench] cpu baseline {cpu}", file=sys.stderr, flush=True)
-
-    # memory roofline of the band-point walk kernel, the longest launch of the
-    # step, on algorithmic traversal bytes: nodes and primitives a
-    # nearest-first query visits (counted by the oracle on this BVH) times
-    # their record sizes, plus each walk's inputs and records
-    es = 4 if args.dtype == "f32" else 8
-    band_ms = kernels.get("k_walks_band", 0.0)
-    q_band, w_band = int(sol.pw_counters[1]), int(sol.pw_counters[3])
-    node_b, prim_b, io_b = walk_bytes(2, es, 1, True)
-    roofline = {"bound": "hbm", "achieved": None, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": None,
-                "traffic": measured_traffic("k_walks<float,2,true,1>", WALK_SOURCES) if es == 4 else None,
-                "kernel": "k_walks<float,2,true,1> (band-point walks)", "avg_launch_ms": round(band_ms, 4),
-                "queries_per_launch": q_band, "walks_per_launch": w_band,
-                "bytes": {"node": node_b, "primitive": prim_b, "walk_io": io_b}}
-    walk_rates = {}
-    if work is not None and band_ms > 0:
-        vn, vp = work["band"]["nodes_per_query"], work["band"]["prims_per_query"]
-        per_query = vn * node_b + vp * prim_b
-        alg = q_band * per_query + w_band * io_b
-        gbs = alg / (band_ms / 1e3) / 1e9
-        roofline.update(achieved=round(gbs, 1), frac=round(gbs / PEAK_HBM_GBS, 4), nodes_per_query=vn,
-                        prims_per_query=vp, bytes_per_query=round(per_query, 1), bytes_per_launch=alg)
-        vn_c, vp_c = work["cache"]["nodes_per_query"], work["cache"]["prims_per_query"]
-        node_c, prim_c, io_c = walk_bytes(2, es, 0, False)
-        q_c, w_c = int(sol.counters[1]), int(sol.counters[3])
-        cache_ms = kernels.get("k_walks_cache", 0.0)
-        alg_c = q_c * (vn_c * node_c + vp_c * prim_c) + w_c * io_c
-        walk_rates = {"cache_walk_kernel": {"avg_launch_ms": round(cache_ms, 4), "queries": q_c,
-                                            "nodes_per_query": vn_c, "prims_per_query": vp_c,
-                                            "GB_per_s": round(alg_c / (cache_ms / 1e3) / 1e9, 1),
-                                            "frac_hbm": round(alg_c / (cache_ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4)},
-                      "counted_on": work["counted_on"]}
-
-    out = {
-        "metric": "interior pts/sec at fixed RMSE (BVC vs pointwise WoS); walk steps/sec",
-        "value": value,
-        "unit": "points/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": args.dtype,
-        "data": "synthetic",
-        "config": {"workload": prob.name, "segments": int(prob.scene.prims.shape[0]),
-                   "cache_target": prob.n_cache, "cache_candidates": prep.n_cand,
-                   "cache_points": sol.cache.n, "walks_per_point": prob.n_walks, "sources": n_src,
-                   "grid": f"{args.grid}x{args.grid}", "interior_points": prep.n_int,
-                   "band_points": prep.n_band, "eps": prob.eps, "offset_l": prob.offset},
-        "walk_steps_per_s": steps_total / (ms_step * args.steps / 1e3),
-        "cache_walk_steps_per_s": cache_walk_rate,
-        "walks_per_step": walks_total / args.steps,
-        "capped_walks": capped,
-        "stage_ms": {k: round(v, 4) for k, v in stages.items()},
-        "rmse": {"all": rmse_all, "gathered": rmse_int, "gathered_d_ge_0.05": rmse_far, "band": band_rmse,
-                 "grad": rmse_grad, "grad_d_ge_0.05": rmse_grad_far},
-        "pointwise_wos": pointwise,
-        "roofline": roofline,
-        "roofline_gather": roofline_gather,
-        "walk_kernels": walk_rates,
-        "kernel_ms": {k: round(v, 4) for k, v in kernels.items()},
-        "cpu_baseline": cpu,
-        "setup_s": setup_s,
-        "tuned_shapes": tuned,
-    }
+    line = run_workload(args, args.workload)
+    out = {"metric": line.pop("metric"), "value": line.pop("value"), "unit": line.pop("unit"), "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": line.pop("ms_per_step"),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": line.pop("dtype"),
+           "data": "synthetic", "config": line.pop("config")}
+    out.update(line)
+    if args.workload == "c3" and not args.no_c2:
+        gc.collect()
+        torch.cuda.empty_cache()
+        out["c2"] = run_workload(args, "c2")
     print(json.dumps(out))
 
 
-def oracle_leg(prob, prep, sol, budget_s, n_pts):
-    """The host oracle leg.  (1) cpu_baseline: the FP64 oracle on a bounded
-    sample of the same step, extrapolated to the step's full work: walks of
-    the first cache points, the gather at the first interior points,
-    pointwise walks at the first band points.  (2) The traversal work per
+_NATIVE = None
+
+
+def native_oracle():
+    """The oracle built on this host with -O3 -march=native (same arithmetic:
+    no FMA contraction, no reassociation), loaded for the timing legs."""
+    global _NATIVE
+    import oracle
+
+    if _NATIVE is None:
+        path = os.path.join(tempfile.mkdtemp(prefix="bvc_oracle_"), "liboracle_native.so")
+        oracle.build(path=path, native=True)
+        oracle.load(path)
+        _NATIVE = path
+    return oracle
+
+
+def oracle_leg(prob, prep, sol, budget_s, n_pts, dim, with_grad, pointwise):
+    """The host oracle leg.  (1) cpu_baseline: the FP64 oracle, built here
+    with -O3 -march=native -ffp-contract=off, on a bounded sample of the same
+    step, extrapolated to the step's full work: walks of the first cache
+    points, the gather at the first interior points against the whole cache
+    and source set, pointwise walks at the first band points; once on all
+    host threads and once on one thread.  BVC against pointwise walk on
+    spheres on the oracle: the oracle's pointwise walks at interior points,
+    times the walks per point that match BVC's error (the estimator's
+    property, measured on the GPU).  (2) The traversal work per
     closest-point query: the oracle replays walks with the library's walk ids
     and counts the nodes and primitives a nearest-first query visits on the
     library's own BVH (exported through the C-ABI)."""
-    import oracle
-    import workloads as wl
-
+    oracle = native_oracle()
     osc = oracle.Scene(prob.scene)
     W = prob.n_walks
     n_cache = sol.cache.n
     cn = {k: np.ascontiguousarray(v.cpu().numpy()[:, :n_cache].T) if v.dim() == 2 else v.cpu().numpy()[:n_cache]
           for k, v in dict(x=sol.cache.x, n=sol.cache.nrm, w=sol.cache.w, xbar=sol.cache.xbar,
                            R0=sol.cache.R0).items()}
-    share = budget_s / 3
-    # walks
-    nw = 8
-    while True:
-        sub = {k: v[:nw] for k, v in cn.items()}
-        t = time.perf_counter()
-        out = oracle.cache_walks(osc, prob.g, prob.f, oracle.walk_params(prob.eps, W, prob.seed_walks), sub)
-        tw = time.perf_counter() - t
-        if tw > share / 4 or nw >= n_cache:
-            break
-        nw = min(n_cache, nw * 4)
-    walks_per_s = nw * W / tw
-    # gather at interior points against the whole cache and source set
-    uh, dh = oracle.reduce(out["U"], out["D"], W)
-    a = np.resize(uh, n_cache) * cn["w"]
-    b = np.resize(dh, n_cache) * cn["w"]
     sv = sol.extra["sview"]
     sy = np.ascontiguousarray(sv["y"].double().cpu().numpy().T) if sv else None
     sw = sv["s"].double().cpu().numpy() if sv else None
     idx_i = prep.idx_int[: prep.n_int].cpu().numpy()
-    ng = 16
-    while True:
-        pts = prob.eval_x[idx_i[:ng]]
-        t = time.perf_counter()
-        oracle.gather(2, pts, cn["x"], cn["n"], a, b, sy, sw, with_grad=True)
-        tg = time.perf_counter() - t
-        if tg > share / 4 or ng >= prep.n_int:
-            break
-        ng = min(prep.n_int, ng * 4)
-    gather_pts_s = ng / tg
-    # pointwise walks at band points
     idx_b = prep.idx_band[: prep.n_band].cpu().numpy()
-    nbp = min(64, prep.n_band)
-    tb = 0.0
-    if nbp:
-        t = time.perf_counter()
-        oracle.pointwise(osc, prob.g, prob.f, oracle.walk_params(prob.eps, W, prob.seed_walks), prob.eval_x[idx_b[:nbp]])
-        tb = time.perf_counter() - t
-    band_pts_s = nbp / tb if tb > 0 else float("inf")
-    step_s = n_cache * W / walks_per_s + prep.n_int / gather_pts_s + (prep.n_band / band_pts_s if nbp else 0.0)
+    P = oracle.walk_params(prob.eps, W, prob.seed_walks)
+    all_threads = oracle.num_threads()
+
+    def leg(threads, share):
+        oracle.set_threads(threads)
+        nw = 1
+        while True:
+            sub = {k: v[:nw] for k, v in cn.items()}
+            t = time.perf_counter()
+            out = oracle.cache_walks(osc, prob.g, prob.f, P, sub)
+            tw = time.perf_counter() - t
+            if tw > share / 4 or nw >= n_cache:
+                break
+            nw = min(n_cache, nw * 4)
+        walks_per_s = nw * W / tw
+        uh, dh = oracle.reduce(out["U"], out["D"], W)
+        a = np.resize(uh, n_cache) * cn["w"]
+        b = np.resize(dh, n_cache) * cn["w"]
+        ng = 4
+        while True:
+            pts = prob.eval_x[idx_i[:ng]]
+            t = time.perf_counter()
+            oracle.gather(dim, pts, cn["x"], cn["n"], a, b, sy, sw, with_grad=with_grad)
+            tg = time.perf_counter() - t
+            if tg > share / 4 or ng >= prep.n_int:
+                break
+            ng = min(prep.n_int, ng * 4)
+        gather_pts_s = ng / tg
+        nbp = 1
+        tb = 0.0
+        while prep.n_band:
+            t = time.perf_counter()
+            oracle.pointwise(osc, prob.g, prob.f, P, prob.eval_x[idx_b[:nbp]], with_grad=with_grad)
+            tb = time.perf_counter() - t
+            if tb > share / 8 or nbp >= min(prep.n_band, 256):
+                break
+            nbp = min(prep.n_band, 256, nbp * 4)
+        band_pts_s = nbp / tb if tb > 0 else float("inf")
+        step_s = (n_cache * W / walks_per_s + prep.n_int / gather_pts_s +
+                  (prep.n_band / band_pts_s if prep.n_band else 0.0))
+        return {"value": n_pts / step_s, "unit": "points/s", "threads": threads,
+                "step_s_extrapolated": step_s, "walks_per_s": walks_per_s, "gather_points_per_s": gather_pts_s,
+                "band_points_per_s": band_pts_s,
+                "sample": (f"{nw} cache points x {W} walks, gather at {ng} interior points against {n_cache} cache"
+                           f" + {0 if sw is None else sw.size} sources, pointwise walks ({W} each) at {nbp} band "
+                           f"points; extrapolated to the full step ({step_s:.1f} s)")}
+
+    full = leg(all_threads, budget_s)
+    one = leg(1, budget_s / 2)
+    oracle.set_threads(all_threads)
+    # BVC against pointwise WoS on the oracle
+    bvc_vs_pw = None
+    if pointwise and pointwise.get("walks_for_equal_rmse"):
+        wstar = max(pointwise["walks_for_equal_rmse"], 1.0)
+        npw = 1
+        while True:
+            pts = prob.eval_x[idx_i[: 8 * npw : 8]]
+            Pp = oracle.walk_params(prob.eps, 16, prob.seed_walks + 1)
+            t = time.perf_counter()
+            oracle.pointwise(osc, prob.g, prob.f, Pp, pts, with_grad=False)
+            tp = time.perf_counter() - t
+            if tp > budget_s / 8 or 8 * npw >= prep.n_int:
+                break
+            npw *= 4
+        pw_walks_s = pts.shape[0] * 16 / tp
+        pw_pts_s = pw_walks_s / wstar
+        bvc_vs_pw = {"pointwise_walks_per_s": pw_walks_s, "walks_for_equal_rmse": wstar,
+                     "pointwise_points_per_s_at_equal_rmse": pw_pts_s, "bvc_points_per_s": full["value"],
+                     "bvc_over_pointwise": full["value"] / pw_pts_s,
+                     "sample": f"16 pointwise walks at {pts.shape[0]} interior points, all threads"}
     work = traversal_work(oracle, osc, prob, prep, cn, idx_b, W)
-    return {"value": n_pts / step_s, "unit": "points/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": (f"FP64 oracle: {nw} cache points x {W} walks ({walks_per_s:.3g} walks/s), gather at "
-                       f"{ng} interior points against {n_cache} cache + {0 if sw is None else sw.size} sources "
-                       f"({gather_pts_s:.3g} points/s), pointwise walks at {nbp} band points; extrapolated to "
-                       f"the full step ({step_s:.1f} s)"),
-            "step_s_extrapolated": step_s}, work
+    cpu = {"value": full["value"], "unit": "points/s", "cores": all_threads, "kind": "oracle",
+           "sample": "FP64 oracle, all host threads: " + full["sample"],
+           "step_s_extrapolated": full["step_s_extrapolated"], "one_thread": one,
+           "all_threads": {k: full[k] for k in ("walks_per_s", "gather_points_per_s", "band_points_per_s")},
+           "cpu_model": oracle.cpu_model(), "host_cpus": os.cpu_count(),
+           "build": "gcc " + " ".join(oracle.FLAGS + ["-march=native"]),
+           "bvc_vs_pointwise_on_oracle": bvc_vs_pw}
+    return cpu, work
 
 
 def traversal_work(oracle, osc, prob, prep, cn, idx_b, W, n_cache_pts=256, n_band_pts=1024, walks_each=8):

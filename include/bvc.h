@@ -629,6 +629,13 @@ int bvc_batch_plan(const bvc_batch_item* items, int32_t n_items, void* workspace
 int bvc_batch_launch(bvc_batch batch, void* stream);
 /* Device pointer to the batch's uint64[4] counters (as bvc_cache_walks). */
 int bvc_batch_counters(bvc_batch batch, uint64_t** dev_counters);
+/* Device pointers into the batch's workspace, for inspection once a launch
+ * has completed (Eqs. 3 and 7 per scene): the FP32 per-walk samples U and D
+ * ([sum over scenes of n_cache*W]; scene s starts at the sum of the earlier
+ * scenes' n_cache*W, and walk j of its cache point i sits at i*W + j from
+ * there) and the FP32 cache values a = u-hat w and b = du/dn-hat w ([sum of
+ * n_cache], scene s from the sum of the earlier scenes' n_cache). */
+int bvc_batch_results(bvc_batch batch, float** U, float** D, float** a, float** b);
 int bvc_batch_destroy(bvc_batch batch);
 
 const char* bvc_last_error(void);

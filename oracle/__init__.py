@@ -20,13 +20,43 @@ _ip = C.POINTER(C.c_int32)
 _lp = C.POINTER(C.c_int64)
 
 
-def build(force: bool = True) -> str:
-    """Compile liboracle.so with gcc (plain C, FP64, no FMA contraction)."""
-    if force or not os.path.exists(LIB_PATH):
-        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
-               "-Wall", "-o", LIB_PATH, os.path.join(_HERE, "oracle.c"), "-lm"]
+FLAGS = ["-O3", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", "-Wall"]
+
+
+def build(force: bool = True, path: str = LIB_PATH, native: bool = False) -> str:
+    """Compile the oracle with gcc (plain C, FP64, no FMA contraction, no
+    reassociation, so every flag set gives the same results).  The shared
+    copy targets the generic x86-64 baseline, since it may run on another
+    host than the one that built it; native=True adds -march=native for a
+    copy built and timed on the same host (the CPU baseline)."""
+    if force or not os.path.exists(path):
+        flags = FLAGS + (["-march=native"] if native else [])
+        cmd = ["gcc", *flags, "-o", path, os.path.join(_HERE, "oracle.c"), "-lm"]
         subprocess.run(cmd, check=True)
-    return LIB_PATH
+    return path
+
+
+def load(path: str) -> None:
+    """Use the oracle library at `path` from here on (e.g. a native build)."""
+    global _lib, _lib_path
+    _lib_path = path
+    _lib = None
+    lib()
+
+
+def set_threads(n: int) -> None:
+    lib().orc_set_threads(int(n))
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 class _Field(C.Structure):
@@ -42,14 +72,15 @@ class _WalkParams(C.Structure):
 
 
 _lib = None
+_lib_path = LIB_PATH
 
 
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
-            build()
-        L = C.CDLL(LIB_PATH)
+        if not os.path.exists(_lib_path):
+            build(path=_lib_path)
+        L = C.CDLL(_lib_path)
         L.orc_scene_new.restype = C.c_void_p
         L.orc_scene_new.argtypes = [C.c_int, _dp, C.c_int64, _ip, C.c_int64]
         L.orc_scene_free.argtypes = [C.c_void_p]
@@ -93,6 +124,7 @@ def lib():
         L.orc_basis_means.argtypes = [C.POINTER(_Field), C.c_int, C.c_int64, C.c_int32, _dp, _dp,
                                       _dp, C.c_int, _dp, _dp]
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_threads.argtypes = [C.c_int]
         L.orc_sample_direction.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
                                            C.c_uint32, C.c_int, _dp]
         L.orc_sample_ball_source.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,

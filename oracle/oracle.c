@@ -2270,6 +2270,14 @@ void orc_clamp_correction(const orc_scene* s, const orc_field* g, const orc_fiel
   }
 }
 
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 int orc_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

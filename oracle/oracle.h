@@ -317,6 +317,8 @@ void orc_basis_means(const orc_field* basis, int dim, int64_t n_cache, int32_t W
                      double* E, double* F);
 
 int orc_num_threads(void);
+/* Threads of the OpenMP loops from here on (n > 0). */
+void orc_set_threads(int n);
 
 #ifdef __cplusplus
 }

@@ -124,6 +124,7 @@ _SIGS = {
     "bvc_batch_plan": [_P(bvc_batch_item), C.c_int32, _vp, C.c_size_t, _vp, _P(_vp)],
     "bvc_batch_launch": [_vp, _vp],
     "bvc_batch_counters": [_vp, _P(_vp)],
+    "bvc_batch_results": [_vp, _P(_vp), _P(_vp), _P(_vp), _P(_vp)],
     "bvc_batch_destroy": [_vp],
     "bvc_point_winding": [_vp, C.c_int64, _vp, _vp, _vp],
     "bvc_wost_walks": [_vp, _vp, _P(bvc_walk_params), C.c_int32, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
@@ -463,6 +464,13 @@ def bvc_batch_counters(batch) -> int:
     p = C.c_void_p()
     _check(_L.bvc_batch_counters(batch, C.byref(p)), "bvc_batch_counters")
     return p.value
+
+
+def bvc_batch_results(batch):
+    """Device addresses (U, D, a, b) of the batch's per-walk samples and cache values."""
+    ps = [C.c_void_p() for _ in range(4)]
+    _check(_L.bvc_batch_results(batch, *(C.byref(p) for p in ps)), "bvc_batch_results")
+    return tuple(p.value for p in ps)
 
 
 def bvc_batch_destroy(batch):

@@ -199,6 +199,15 @@ int bvc_batch_counters(bvc_batch b, uint64_t** dev_counters) {
   return BVC_OK;
 }
 
+int bvc_batch_results(bvc_batch b, float** U, float** D, float** a, float** bv) {
+  if (!b || !U || !D || !a || !bv) return fail(BVC_EINVAL, "null argument");
+  *U = b->dev.U;
+  *D = b->dev.D;
+  *a = b->dev.a;
+  *bv = b->dev.b;
+  return BVC_OK;
+}
+
 int bvc_batch_destroy(bvc_batch b) {
   delete b;
   return BVC_OK;

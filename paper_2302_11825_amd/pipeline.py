@@ -567,6 +567,26 @@ class SceneBatch:
         off = B.bvc_batch_counters(self.h) - self.ws.data_ptr()
         return self.ws[off:off + 32].view(torch.int64).cpu().numpy()
 
+    def results(self):
+        """Per scene (U, D, a, b) after a launch: FP32 per-walk samples
+        [n_cache*W] and cache values [n_cache], views of the workspace."""
+        ptrs = B.bvc_batch_results(self.h)
+        base = self.ws.data_ptr()
+        total_w = sum(e["cache"].n * e["problem"].n_walks for e in self.entries)
+        total_c = sum(e["cache"].n for e in self.entries)
+        views = []
+        for p, n in zip(ptrs, (total_w, total_w, total_c, total_c)):
+            off = p - base
+            assert off >= 0 and off % 4 == 0 and off + 4 * n <= self.ws.numel()
+            views.append(self.ws[off:off + 4 * n].view(torch.float32))
+        out, wo, co = [], 0, 0
+        for e in self.entries:
+            nw, nc = e["cache"].n * e["problem"].n_walks, e["cache"].n
+            out.append((views[0][wo:wo + nw], views[1][wo:wo + nw], views[2][co:co + nc], views[3][co:co + nc]))
+            wo += nw
+            co += nc
+        return out
+
     def run_sequential(self):
         """The same work with one call sequence per scene (walks, means, gather)."""
         outs = []
