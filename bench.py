@@ -126,11 +126,12 @@ WALK_SOURCES = ("walks.hip", "bvc_device.hpp", "bvc_internal.hpp")
 def walk_bytes(dim, es, mode, with_grad):
     """Algorithmic bytes of the walk kernel in the record sizes of FP32 (es =
     4; FP64 doubles them): per binary BVH node expanded, 48 B in 2D and 64 B
-    in 3D (two child boxes and their links); per primitive tested, a 16 B
-    segment or a 36 B triangle; per walk, its inputs read and records
+    in 3D (two child boxes and their links), plus in 3D the 40 B of the two
+    children's slab bounds (axis and range each); per primitive tested, a
+    16 B segment or a 36 B triangle; per walk, its inputs read and records
     written (mode 0 cache walk, mode 1 pointwise walk)."""
     s = es // 4
-    node = (48 if dim == 2 else 64) * s
+    node = (48 if dim == 2 else 64 + 40) * s
     prim = (16 if dim == 2 else 36) * s
     if mode == 0:
         io = 8 + 2 * dim * 8 + dim * es + 3 * es          # R0, x, n (FP64); exit, U, D, w1
@@ -560,6 +561,7 @@ def traversal_work(oracle, osc, prob, prep, cn, idx_b, W, n_cache_pts=256, n_ban
     from paper_2302_11825_amd import _bvc as B
 
     child, boxes, order = B.bvc_scene_export_bvh(prep.sc.h)
+    slabs = B.bvc_scene_export_slabs(prep.sc.h) if prob.scene.dim == 3 else None
     P = oracle.walk_params(prob.eps, W, prob.seed_walks)
     out = {}
     n_all = cn["x"].shape[0]
@@ -568,7 +570,7 @@ def traversal_work(oracle, osc, prob, prep, cn, idx_b, W, n_cache_pts=256, n_ban
     ids = [int(i) * W + j for i in ci for j in range(walks_each)]
     q, h, _ = oracle.walk_queries(osc, P, 0, np.repeat(cn["x"][ci], walks_each, 0),
                                   np.repeat(cn["R0"][ci], walks_each), ids)
-    vn, vp = oracle.bvh_visits(osc, child, boxes, order, q, h)
+    vn, vp = oracle.bvh_visits(osc, child, boxes, order, q, h, slabs=slabs)
     out["cache"] = {"nodes_per_query": float(vn.mean()), "prims_per_query": float(vp.mean()),
                     "queries_counted": int(q.shape[0])}
     bi = np.linspace(0, idx_b.size - 1, min(n_band_pts, idx_b.size)).astype(np.int64)
@@ -577,7 +579,7 @@ def traversal_work(oracle, osc, prob, prep, cn, idx_b, W, n_cache_pts=256, n_ban
     d, _, _ = osc.closest(pts)
     ids = [int(k) * W + j for k in bi for j in range(walks_each)]
     q, h, _ = oracle.walk_queries(osc, P, 1, np.repeat(pts, walks_each, 0), np.repeat(d, walks_each), ids)
-    vn, vp = oracle.bvh_visits(osc, child, boxes, order, q, h)
+    vn, vp = oracle.bvh_visits(osc, child, boxes, order, q, h, slabs=slabs)
     out["band"] = {"nodes_per_query": float(vn.mean()), "prims_per_query": float(vp.mean()),
                    "queries_counted": int(q.shape[0])}
     out["counted_on"] = (f"{out['cache']['queries_counted']} cache-walk and {out['band']['queries_counted']} "

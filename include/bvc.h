@@ -130,6 +130,14 @@ int bvc_scene_destroy(bvc_scene scene);
  * original primitive id of each leaf-ordered primitive.  Node 0 is the root.
  * Host pointers, caller-owned, sized from bvc_scene_info; any may be NULL. */
 int bvc_scene_export_bvh(bvc_scene scene, int32_t* child, double* boxes, int32_t* order);
+/* 3D only: the second bound of each child, slabs [n_nodes][12] FP64 (host,
+ * caller-owned): for child c, (n_x, n_y, n_z, smin, smax) at 5c, with n the
+ * unit area-weighted mean normal of the child's triangles and [smin, smax]
+ * the range of n.y over their vertices, widened by the rounding of n.p
+ * (entries 10 and 11 are 0).  Closest-point traversals prune a child when
+ * the larger of its box distance and its slab distance exceeds the best
+ * distance so far.  BVC_EUNSUPPORTED for 2D scenes. */
+int bvc_scene_export_slabs(bvc_scene scene, double* slabs);
 
 /* Total measure of the offset-boundary candidate set at offset l: segment
  * lengths (times `sides`) plus vertex circles (2D); face areas plus edge

@@ -134,7 +134,7 @@ def lib():
         L.orc_walk_queries.argtypes = [C.c_void_p, C.POINTER(_WalkParams), C.c_int, _dp, C.c_double,
                                        C.c_uint32, C.c_int32, _dp, _ip]
         L.orc_walk_queries.restype = C.c_int32
-        L.orc_bvh_visits.argtypes = [C.c_void_p, C.c_int64, _ip, _dp, _ip, C.c_int64, _dp, _ip, _dp, _dp]
+        L.orc_bvh_visits.argtypes = [C.c_void_p, C.c_int64, _ip, _dp, _dp, _ip, C.c_int64, _dp, _ip, _dp, _dp]
         for nm in ("orc_bessel_i0", "orc_bessel_i1", "orc_bessel_k0", "orc_bessel_k1"):
             getattr(L, nm).argtypes = [C.c_double]
             getattr(L, nm).restype = C.c_double
@@ -380,19 +380,21 @@ def walk_queries(scene: Scene, params, mode, x, R0, ids, max_q=None):
     return np.concatenate(pts), np.concatenate(hints), np.concatenate(owner)
 
 
-def bvh_visits(scene: Scene, child, boxes, order, q, hints):
+def bvh_visits(scene: Scene, child, boxes, order, q, hints, slabs=None):
     """Nodes expanded and primitive distances evaluated by a nearest-first
     query at each point q on the given BVH (child links, FP64 child boxes in
-    the parent, leaf order), seeded with the hint primitive."""
+    the parent, leaf order, optional 3D slab bounds), seeded with the hint
+    primitive."""
     child = np.ascontiguousarray(child, dtype=np.int32)
     order = np.ascontiguousarray(order, dtype=np.int32)
     boxes = _f64(boxes)
+    slabs = None if slabs is None else _f64(slabs)
     q = _f64(q).reshape(-1, scene.dim)
     hints = np.ascontiguousarray(hints, dtype=np.int32)
     nodes = np.zeros(q.shape[0])
     prims = np.zeros(q.shape[0])
-    lib().orc_bvh_visits(scene.h, child.shape[0], _i(child), _d(boxes), _i(order), q.shape[0], _d(q),
-                         _i(hints), _d(nodes), _d(prims))
+    lib().orc_bvh_visits(scene.h, child.shape[0], _i(child), _d(boxes), _d(slabs), _i(order), q.shape[0],
+                         _d(q), _i(hints), _d(nodes), _d(prims))
     return nodes, prims
 
 

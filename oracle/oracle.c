@@ -1421,8 +1421,8 @@ int32_t orc_walk_queries(const orc_scene* s, const orc_walk_params* p, int mode,
 }
 
 void orc_bvh_visits(const orc_scene* s, int64_t n_nodes, const int32_t* child, const double* boxes,
-                    const int32_t* order, int64_t n_q, const double* q, const int32_t* hint,
-                    double* nodes, double* prims) {
+                    const double* slabs, const int32_t* order, int64_t n_q, const double* q,
+                    const int32_t* hint, double* nodes, double* prims) {
   int dim = s->dim;
   (void)n_nodes;
 #pragma omp parallel for schedule(dynamic, 64)
@@ -1464,6 +1464,15 @@ void orc_bvh_visits(const orc_scene* s, int64_t n_nodes, const int32_t* child, c
           if (x[a] < lo[a]) e = lo[a] - x[a];
           else if (x[a] > hi[a]) e = x[a] - hi[a];
           d2 += e * e;
+        }
+        if (slabs) {
+          /* a second lower bound: the distance from n.x to the child's slab
+             [smin, smax] along its axis n */
+          const double* sl = slabs + (int64_t)link * 12 + ch * 5;
+          double t = sl[0] * x[0] + sl[1] * x[1] + sl[2] * x[2], e = 0;
+          if (t < sl[3]) e = sl[3] - t;
+          else if (t > sl[4]) e = t - sl[4];
+          if (e * e > d2) d2 = e * e;
         }
         db[ch] = d2;
       }

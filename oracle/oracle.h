@@ -190,10 +190,12 @@ int32_t orc_walk_queries(const orc_scene* s, const orc_walk_params* p, int mode,
  * over primitives order[start..]; node 0 is the root): internal nodes expanded
  * and primitive distances evaluated, per query point, with the hint primitive
  * (original id, or -1) evaluated first.  A popped entry whose box is farther
- * than the best distance so far is skipped. */
+ * than the best distance so far is skipped.  slabs (3D, nullable): a second
+ * lower bound per child, (n, smin, smax) at [node][5 c], the distance from n.x
+ * to [smin, smax]; a child's bound is the larger of the two. */
 void orc_bvh_visits(const orc_scene* s, int64_t n_nodes, const int32_t* child, const double* boxes,
-                    const int32_t* order, int64_t n_q, const double* q, const int32_t* hint,
-                    double* nodes, double* prims);
+                    const double* slabs, const int32_t* order, int64_t n_q, const double* q,
+                    const int32_t* hint, double* nodes, double* prims);
 
 /* All walks of n_cache cache points: U[i*W + j], D[i*W + j] = n_i . grad. */
 void orc_cache_walks(const orc_scene* s, const orc_field* g, const orc_field* f,

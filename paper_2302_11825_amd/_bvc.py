@@ -90,6 +90,7 @@ _SIGS = {
     "bvc_scene_upload": [_vp, _vp, C.c_size_t, _vp],
     "bvc_scene_destroy": [_vp],
     "bvc_scene_export_bvh": [_vp, _vp, _vp, _vp],
+    "bvc_scene_export_slabs": [_vp, _vp],
     "bvc_cache_measure": [_vp, C.c_double, C.c_int32, _P(C.c_double)],
     "bvc_sample_cache": [_vp, C.c_int64, C.c_double, C.c_int32, C.c_uint64, C.c_uint32, _vp, _vp, _vp,
                          _vp, _vp, _vp, _vp],
@@ -256,6 +257,16 @@ def bvc_scene_export_bvh(scene):
     _check(_L.bvc_scene_export_bvh(scene, child.ctypes.data, boxes.ctypes.data, order.ctypes.data),
            "bvc_scene_export_bvh")
     return child, boxes, order
+
+
+def bvc_scene_export_slabs(scene):
+    """Host copy of the 3D slab bounds, float64 [n_nodes, 12]."""
+    import numpy as np
+
+    info = bvc_scene_get_info(scene)
+    slabs = np.empty((info.n_nodes, 12), dtype=np.float64)
+    _check(_L.bvc_scene_export_slabs(scene, slabs.ctypes.data), "bvc_scene_export_slabs")
+    return slabs
 
 
 def bvc_scene_upload(scene, buf, stream=None):

@@ -140,7 +140,11 @@ __device__ __forceinline__ T segment_d2(const T* p, T ax, T ay, T bx, T by, T& c
 
 // Closest point of a triangle by Voronoi regions of its vertices, edges and
 // face (Ericson, Real-Time Collision Detection, Sec. 5.1.5).  region: 0 face,
-// 1/2/3 vertex a/b/c, 4/5/6 edge ab/bc/ca.
+// 1/2/3 vertex a/b/c, 4/5/6 edge ab/bc/ca.  Every region's test is evaluated
+// and the first that holds (in the order vertex a, vertex b, edge ab, vertex
+// c, edge ca, edge bc, face) picks the barycentric numerators and their
+// common denominator, so the wave runs one straight-line sequence with one
+// reciprocal whatever region each lane's point lies in.
 template <typename T>
 __device__ __forceinline__ T triangle_d2(const T* p, const T* a, const T* b, const T* c, T* q, int& region) {
   T ab[3], ac[3], ap[3];
@@ -161,48 +165,40 @@ __device__ __forceinline__ T triangle_d2(const T* p, const T* a, const T* b, con
   const T vc = d1 * d4 - d3 * d2;
   const T vb = d5 * d2 - d1 * d6;
   const T va = d3 * d6 - d5 * d4;
-  T u, v;  // q = a + u ab + v ac
-  if (d1 <= T(0) && d2 <= T(0)) {
-    region = 1;
-    u = 0;
-    v = 0;
-  } else if (d3 >= T(0) && d4 <= d3) {
-    region = 2;
-    u = 1;
-    v = 0;
-  } else if (vc <= T(0) && d1 >= T(0) && d3 <= T(0)) {
-    region = 4;
-    u = fdiv(d1, d1 - d3);
-    v = 0;
-  } else if (d6 >= T(0) && d5 <= d6) {
-    region = 3;
-    u = 0;
-    v = 1;
-  } else if (vb <= T(0) && d2 >= T(0) && d6 <= T(0)) {
-    region = 6;
-    u = 0;
-    v = fdiv(d2, d2 - d6);
-  } else if (va <= T(0) && (d4 - d3) >= T(0) && (d5 - d6) >= T(0)) {
-    region = 5;
-    const T w = fdiv(d4 - d3, (d4 - d3) + (d5 - d6));
-    u = T(1) - w;
-    v = w;
-  } else {
-    region = 0;
-    const T den = T(1) / (va + vb + vc);
-    u = vb * den;
-    v = vc * den;
-  }
+  const T e43 = d4 - d3, e56 = d5 - d6;
+  const bool in_a = d1 <= T(0) && d2 <= T(0);
+  const bool in_b = d3 >= T(0) && d4 <= d3;
+  const bool in_ab = vc <= T(0) && d1 >= T(0) && d3 <= T(0);
+  const bool in_c = d6 >= T(0) && d5 <= d6;
+  const bool in_ca = vb <= T(0) && d2 >= T(0) && d6 <= T(0);
+  const bool in_bc = va <= T(0) && e43 >= T(0) && e56 >= T(0);
+  // q = a + (nu ab + nv ac) / den (face and edges ab, ca), q = b + nv (c - b)
+  // / den (edge bc), q = the vertex itself (vertex regions); the assignments
+  // run from the last test to the first so that the first test that holds wins
+  int reg = 0;
+  T nu = vb, nv = vc, den = va + vb + vc;
+  if (in_bc) { reg = 5; nu = T(0); nv = e43; den = e43 + e56; }
+  if (in_ca) { reg = 6; nu = T(0); nv = d2; den = d2 - d6; }
+  if (in_c) reg = 3;
+  if (in_ab) { reg = 4; nu = d1; nv = T(0); den = d1 - d3; }
+  if (in_b) reg = 2;
+  if (in_a) reg = 1;
+  const bool vertex = reg == 1 || reg == 2 || reg == 3;
+  if (vertex) { nu = T(0); nv = T(0); den = T(1); }
+  const T rden = fdiv(T(1), den);
+  const T u = nu * rden, v = nv * rden;
   // vertices are returned exactly when the projection clamps to them
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     T qi = a[i] + u * ab[i] + v * ac[i];
-    if (region == 1) qi = a[i];
-    if (region == 2) qi = b[i];
-    if (region == 3) qi = c[i];
-    if (region == 5) qi = b[i] + v * (c[i] - b[i]);
+    const T qbc = b[i] + v * (c[i] - b[i]);
+    qi = reg == 5 ? qbc : qi;
+    qi = reg == 1 ? a[i] : qi;
+    qi = reg == 2 ? b[i] : qi;
+    qi = reg == 3 ? c[i] : qi;
     q[i] = qi;
   }
+  region = reg;
   const T dx = p[0] - q[0], dy = p[1] - q[1], dz = p[2] - q[2];
   return dx * dx + dy * dy + dz * dz;
 }
@@ -224,12 +220,40 @@ template <>
 struct SceneArrays<float> {
   __device__ static const float* box(const SceneDev& s) { return s.box32; }
   __device__ static const float* prim(const SceneDev& s) { return s.prim32; }
+  __device__ static const float* slab(const SceneDev& s) { return s.slab32; }
 };
 template <>
 struct SceneArrays<double> {
   __device__ static const double* box(const SceneDev& s) { return s.box64; }
   __device__ static const double* prim(const SceneDev& s) { return s.prim64; }
+  __device__ static const double* slab(const SceneDev& s) { return s.slab64; }
 };
+
+// Raises the box bounds d0, d1 of the two children of a 3D node to their slab
+// bounds where those are larger: the squared distance from n.p to the range
+// [smin, smax] of n.y over the child's triangles bounds the squared distance
+// to any of them from below.
+template <typename T>
+__device__ __forceinline__ void slab_bounds(const SceneDev& S, int node, const T* p, T& d0, T& d1) {
+  const T* b = SceneArrays<T>::slab(S) + (size_t)node * 12;
+  T w[10];
+  if constexpr (sizeof(T) == 4) {
+    const float4 u = reinterpret_cast<const float4*>(b)[0];
+    const float4 v = reinterpret_cast<const float4*>(b)[1];
+    const float2 x = reinterpret_cast<const float2*>(b)[4];
+    w[0] = u.x; w[1] = u.y; w[2] = u.z; w[3] = u.w; w[4] = v.x;
+    w[5] = v.y; w[6] = v.z; w[7] = v.w; w[8] = x.x; w[9] = x.y;
+  } else {
+#pragma unroll
+    for (int j = 0; j < 10; ++j) w[j] = b[j];
+  }
+  const T s0 = w[0] * p[0] + w[1] * p[1] + w[2] * p[2];
+  const T s1 = w[5] * p[0] + w[6] * p[1] + w[7] * p[2];
+  const T e0 = fmax(fmax(w[3] - s0, s0 - w[4]), T(0));
+  const T e1 = fmax(fmax(w[8] - s1, s1 - w[9]), T(0));
+  d0 = fmax(d0, e0 * e0);
+  d1 = fmax(d1, e1 * e1);
+}
 
 // Vertices (a, b, c) of leaf-ordered triangle i.
 template <typename T>
@@ -378,6 +402,7 @@ __device__ __forceinline__ void bvh_closest(const SceneDev& S, const T* p, T& be
     const int2 ch = S.child[node];
     T d0 = box_d2<T, D>(lo0, hi0, p);
     T d1 = box_d2<T, D>(lo1, hi1, p);
+    if constexpr (D == 3) slab_bounds<T>(S, node, p, d0, d1);
     int c0 = ch.x, c1 = ch.y;
     if (d1 < d0) {
       const T td = d0;
@@ -413,18 +438,22 @@ __device__ __forceinline__ void bvh_closest(const SceneDev& S, const T* p, T& be
 }
 
 // Resumable form of the same nearest-first query, for wave-interleaved
-// traversal.  A step tests at most one primitive and expands at most one node,
-// so every lane of a wave runs the same instructions per step whatever mix of
-// nodes and leaves its query meets.  Leaves reached by an expansion wait in
-// two pending slots (leaf encodings, 0 = empty) and are consumed one primitive
-// per step; a node is expanded only when no leaf is pending, so the slots
-// never overflow.  The query is finished when no node and no leaf remain.
+// traversal.  A step tests at most one primitive and then expands at most one
+// node, so every lane of a wave runs the same instructions per step whatever
+// mix of nodes and leaves its query meets, and a lane with both a pending
+// primitive and an open node advances both in one step.  Leaves reached by an
+// expansion wait in three pending slots (leaf encodings, 0 = empty, nearest
+// first) and are consumed one primitive per step; a node is expanded only
+// when at most one leaf is pending after the step's primitive, so the two
+// leaves an expansion can add always fit.  The primitive is tested before the
+// node so that the expansion prunes with the updated bound.  The query is
+// finished when no node and no leaf remain.
 template <typename T, int D>
 struct Query {
-  int node;   // next internal node to expand, -1 when the stack is empty
+  int node;       // next internal node to expand, -1 when the stack is empty
   int sp;
   int bi;
-  int pa, pb; // pending leaves (pa first)
+  int pa, pb, pc; // pending leaves (pa first)
   T best;
   T bq[D];
 };
@@ -440,6 +469,7 @@ __device__ __forceinline__ void query_begin(const SceneDev& S, const T* p, int h
   q.sp = 0;
   q.pa = 0;
   q.pb = 0;
+  q.pc = 0;
   q.best = T(INFINITY);
   q.bi = -1;
   if (hint >= 0) {
@@ -447,6 +477,13 @@ __device__ __forceinline__ void query_begin(const SceneDev& S, const T* p, int h
     q.best = prim_d2<T, D>(S, hint, p, q.bq, reg);
     q.bi = hint;
   }
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void query_push_leaf(Query<T, D>& q, int leaf) {
+  if (q.pa == 0) q.pa = leaf;
+  else if (q.pb == 0) q.pb = leaf;
+  else q.pc = leaf;
 }
 
 template <typename T, int D>
@@ -483,10 +520,11 @@ __device__ __forceinline__ void query_step(const SceneDev& S, const T* p, Query<
       q.pa = encode_leaf(i + 1, n - 1);
     } else {
       q.pa = q.pb;
-      q.pb = 0;
+      q.pb = q.pc;
+      q.pc = 0;
     }
   }
-  if (q.pa != 0 || q.node < 0) return;
+  if (q.node < 0 || q.pb != 0) return;
   // ---- expand one node: leaves go to the pending slots, the nearer inner
   // child is expanded next and the farther one is pushed with its bound
   T lo0[D], hi0[D], lo1[D], hi1[D];
@@ -494,6 +532,7 @@ __device__ __forceinline__ void query_step(const SceneDev& S, const T* p, Query<
   const int2 ch = S.child[q.node];
   T d0 = box_d2<T, D>(lo0, hi0, p);
   T d1 = box_d2<T, D>(lo1, hi1, p);
+  if constexpr (D == 3) slab_bounds<T>(S, q.node, p, d0, d1);
   int c0 = ch.x, c1 = ch.y;
   if (d1 < d0) {
     const T td = d0;
@@ -505,13 +544,12 @@ __device__ __forceinline__ void query_step(const SceneDev& S, const T* p, Query<
   }
   int next = -1;
   if (d0 <= q.best) {
-    if (c0 < 0) q.pa = c0;
+    if (c0 < 0) query_push_leaf(q, c0);
     else next = c0;
   }
   if (d1 <= q.best) {
     if (c1 < 0) {
-      if (q.pa == 0) q.pa = c1;
-      else q.pb = c1;
+      query_push_leaf(q, c1);
     } else if (next < 0) {
       next = c1;
     } else {

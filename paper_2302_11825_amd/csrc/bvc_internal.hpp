@@ -30,6 +30,9 @@ struct SceneDev {
   const int2* child;    // [n_nodes] child links
   const double* box64;  // [n_nodes][4*dim]: child0 lo, child0 hi, child1 lo, child1 hi
   const float* box32;   // same, rounded outward
+  const double* slab64; // 3D [n_nodes][12]: per child, a unit axis n and the range [smin, smax]
+                        // of n.y over the child's triangles (n0 smin0 smax0 n1 smin1 smax1 0 0)
+  const float* slab32;  // same with the axis rounded to FP32 and the range widened outward
   const double* prim64; // leaf order: 2D [np][4] (a, b); 3D [np][12] (a, b, c, pad)
   const float* prim32;  // same layout in FP32
   const int* prim_id;   // leaf order -> original primitive id
@@ -69,6 +72,8 @@ struct SceneHost {
   std::vector<int2> child;
   std::vector<double> box64;
   std::vector<float> box32;
+  std::vector<double> slab64;
+  std::vector<float> slab32;
   std::vector<double> prim64;
   std::vector<float> prim32;
   std::vector<int> prim_id;
@@ -80,7 +85,8 @@ struct SceneHost {
   double boundary_measure = 0;
   // device placement
   size_t bytes = 0;
-  size_t off_V = 0, off_P = 0, off_E = 0, off_child = 0, off_box64 = 0, off_box32 = 0,
+  size_t off_V = 0, off_P = 0, off_E = 0, off_child = 0, off_box64 = 0, off_box32 = 0, off_slab64 = 0,
+         off_slab32 = 0,
          off_prim64 = 0, off_prim32 = 0, off_prim_id = 0, off_fn = 0, off_epn = 0, off_vpn = 0,
          off_cdf = 0, off_meas = 0;
   int64_t n_el_max = 0;

@@ -208,6 +208,8 @@ SceneDev SceneHost::view() const {
   s.child = (const int2*)(dev + off_child);
   s.box64 = (const double*)(dev + off_box64);
   s.box32 = (const float*)(dev + off_box32);
+  s.slab64 = dim == 3 ? (const double*)(dev + off_slab64) : nullptr;
+  s.slab32 = dim == 3 ? (const float*)(dev + off_slab32) : nullptr;
   s.prim64 = (const double*)(dev + off_prim64);
   s.prim32 = (const float*)(dev + off_prim32);
   s.prim_id = (const int*)(dev + off_prim_id);
@@ -352,6 +354,108 @@ static int build_scene(SceneHost& S, int dim, const double* verts, int64_t nv, c
     }
     S.child[i] = make_int2(link[0], link[1]);
   }
+  if (dim == 3) {
+    // A second bound per child (3D): the slab of its triangles along their
+    // area-weighted mean normal n.  Every point y of those triangles has
+    // smin <= n.y <= smax, so the distance from p to any of them is at least
+    // the distance from n.p to [smin, smax]; a patch of a smooth surface is
+    // thin along its normal, where its box is not.  The FP64 range is widened
+    // by the rounding of n.p in FP64, the FP32 one by that of n.p in FP32 for
+    // |p| up to four times the scene's extent (and by the FP32 axis's
+    // departure from unit length), so both stay lower bounds.
+    std::vector<int> rs(T.size(), 0), re(T.size(), 0);
+    std::vector<int> post;
+    std::vector<std::pair<int, bool>> st{{root, false}};
+    while (!st.empty()) {
+      auto [t, done] = st.back();
+      st.pop_back();
+      if (T[t].leaf) {
+        rs[t] = T[t].start;
+        re[t] = T[t].start + T[t].count;
+      } else if (!done) {
+        st.push_back({t, true});
+        st.push_back({T[t].left, false});
+        st.push_back({T[t].right, false});
+      } else {
+        rs[t] = std::min(rs[T[t].left], rs[T[t].right]);
+        re[t] = std::max(re[T[t].left], re[T[t].right]);
+      }
+    }
+    double M = 1.0;
+    for (int a = 0; a < 3; ++a) M = std::max(M, 4.0 * std::max(std::fabs(S.lo[a]), std::fabs(S.hi[a])));
+    S.slab64.assign((size_t)nn * 12, 0.0);
+    S.slab32.assign((size_t)nn * 12, 0.0f);
+    for (int i = 0; i < nn; ++i) {
+      const TmpNode& nd = T[order[i]];
+      int kids[2] = {nd.left, nd.right};
+      for (int c = 0; c < 2; ++c) {
+        const TmpNode& k = T[kids[c]];
+        double* o64 = &S.slab64[(size_t)i * 12 + c * 5];
+        float* o32 = &S.slab32[(size_t)i * 12 + c * 5];
+        if (!std::isfinite(k.lo[0])) {  // the empty sibling of a single-leaf root
+          o64[2] = o32[2] = 1;
+          o64[3] = o32[3] = INFINITY;
+          o64[4] = o32[4] = -INFINITY;
+          continue;
+        }
+        double n[3] = {0, 0, 0}, area2 = 0;
+        for (int j = rs[kids[c]]; j < re[kids[c]]; ++j) {
+          const int t = perm[j];
+          const double* A = &S.V[(size_t)S.P[3 * t] * 3];
+          const double* Bv = &S.V[(size_t)S.P[3 * t + 1] * 3];
+          const double* Cv = &S.V[(size_t)S.P[3 * t + 2] * 3];
+          double ab[3], ac[3], x[3];
+          for (int a = 0; a < 3; ++a) {
+            ab[a] = Bv[a] - A[a];
+            ac[a] = Cv[a] - A[a];
+          }
+          cross3(ab, ac, x);
+          for (int a = 0; a < 3; ++a) n[a] += x[a];
+          area2 += std::sqrt(dot3(x, x));
+        }
+        double len = std::sqrt(dot3(n, n));
+        if (!(len > 1e-9 * area2)) {
+          // no dominant normal (a closed or folded patch): the axis of the
+          // box's thinnest side, which then adds nothing but costs nothing
+          int a_min = 0;
+          for (int a = 1; a < 3; ++a)
+            if (k.hi[a] - k.lo[a] < k.hi[a_min] - k.lo[a_min]) a_min = a;
+          n[0] = n[1] = n[2] = 0;
+          n[a_min] = 1;
+          len = 1;
+        }
+        double n64[3], n32d[3];
+        float n32[3];
+        for (int a = 0; a < 3; ++a) {
+          n64[a] = n[a] / len;
+          n32[a] = (float)n64[a];
+          n32d[a] = (double)n32[a];
+        }
+        double lo64 = INFINITY, hi64 = -INFINITY, lo32 = INFINITY, hi32 = -INFINITY;
+        for (int j = rs[kids[c]]; j < re[kids[c]]; ++j)
+          for (int v = 0; v < 3; ++v) {
+            const double* y = &S.V[(size_t)S.P[3 * perm[j] + v] * 3];
+            const double s64 = dot3(n64, y), s32 = dot3(n32d, y);
+            lo64 = std::min(lo64, s64);
+            hi64 = std::max(hi64, s64);
+            lo32 = std::min(lo32, s32);
+            hi32 = std::max(hi32, s32);
+          }
+        const double l1_64 = std::fabs(n64[0]) + std::fabs(n64[1]) + std::fabs(n64[2]);
+        const double l1_32 = std::fabs(n32d[0]) + std::fabs(n32d[1]) + std::fabs(n32d[2]);
+        const double m64 = 16.0 * std::ldexp(1.0, -53) * M * l1_64;
+        const double m32 = 16.0 * std::ldexp(1.0, -24) * M * l1_32;
+        for (int a = 0; a < 3; ++a) {
+          o64[a] = n64[a];
+          o32[a] = n32[a];
+        }
+        o64[3] = lo64 - m64;
+        o64[4] = hi64 + m64;
+        o32[3] = round_down(lo32 - m32);
+        o32[4] = round_up(hi32 + m32);
+      }
+    }
+  }
   // leaf-ordered primitive records
   int pw = dim == 2 ? 4 : 12;
   S.prim64.assign((size_t)np * pw, 0.0);
@@ -445,6 +549,8 @@ static int build_scene(SceneHost& S, int dim, const double* verts, int64_t nv, c
   place(S.off_child, S.child.size() * sizeof(int2));
   place(S.off_box64, S.box64.size() * sizeof(double));
   place(S.off_box32, S.box32.size() * sizeof(float));
+  place(S.off_slab64, S.slab64.size() * sizeof(double));
+  place(S.off_slab32, S.slab32.size() * sizeof(float));
   place(S.off_prim64, S.prim64.size() * sizeof(double));
   place(S.off_prim32, S.prim32.size() * sizeof(float));
   place(S.off_prim_id, S.prim_id.size() * sizeof(int));
@@ -573,6 +679,14 @@ int bvc_scene_export_bvh(bvc_scene s, int32_t* child, double* boxes, int32_t* or
   return BVC_OK;
 }
 
+int bvc_scene_export_slabs(bvc_scene s, double* slabs) {
+  if (!s || !slabs) return fail(BVC_EINVAL, "null argument");
+  const SceneHost& h = s->h;
+  if (h.dim != 3) return fail(BVC_EUNSUPPORTED, "slab bounds exist for 3D scenes only");
+  std::copy(h.slab64.begin(), h.slab64.end(), slabs);
+  return BVC_OK;
+}
+
 int bvc_scene_upload(bvc_scene s, void* buf, size_t bytes, void* stream) {
   if (!s || !buf) return fail(BVC_EINVAL, "null argument");
   SceneHost& h = s->h;
@@ -589,6 +703,8 @@ int bvc_scene_upload(bvc_scene s, void* buf, size_t bytes, void* stream) {
   put(h.off_child, h.child.data(), h.child.size() * sizeof(int2));
   put(h.off_box64, h.box64.data(), h.box64.size() * sizeof(double));
   put(h.off_box32, h.box32.data(), h.box32.size() * sizeof(float));
+  put(h.off_slab64, h.slab64.data(), h.slab64.size() * sizeof(double));
+  put(h.off_slab32, h.slab32.data(), h.slab32.size() * sizeof(float));
   put(h.off_prim64, h.prim64.data(), h.prim64.size() * sizeof(double));
   put(h.off_prim32, h.prim32.data(), h.prim32.size() * sizeof(float));
   put(h.off_prim_id, h.prim_id.data(), h.prim_id.size() * sizeof(int));

@@ -274,7 +274,7 @@ __device__ __forceinline__ void walks_body(const WalkArgs& a, uint32_t* lds) {
   T d = T(0), acc_s = T(0), usrc = T(0);
   Query<T, D> qs;
   qs.node = -1;
-  qs.pa = qs.pb = 0;
+  qs.pa = qs.pb = qs.pc = 0;
   unsigned long long steps_acc = 0, capped_acc = 0, walks_acc = 0;
 #pragma unroll
   for (int q = 0; q < D; ++q) p[q] = T(0);
@@ -330,7 +330,7 @@ __device__ __forceinline__ void walks_body(const WalkArgs& a, uint32_t* lds) {
     // ---- sphere jump: source sample in the ball, direction, next query
     if (jump) {
       T srcv = T(0);
-      const T coef = -d * d / (T)(2 * D);
+      const T coef = -d * d * (T(1) / T(2 * D));
       if constexpr (SRC) {
         T y[D];
         ball_source_point<T, D>(a.seed, (uint32_t)k, id, a.batch, tag, p, d, y);
@@ -343,7 +343,7 @@ __device__ __forceinline__ void walks_body(const WalkArgs& a, uint32_t* lds) {
         // normal-derivative estimators (Eq. 7 with the control variate)
         usrc = SRC ? coef * srcv : T(0);
         const int64_t i = (int64_t)(id / (uint32_t)a.W);
-        const T wgt = (T)D / d;
+        const T wgt = fdiv((T)D, d);
         T gs[D];
 #pragma unroll
         for (int q = 0; q < D; ++q) gs[q] = T(0);
@@ -421,7 +421,7 @@ __device__ __forceinline__ void walks_body(const WalkArgs& a, uint32_t* lds) {
         // approached from the walk's side by 1e-3 eps, so that data that
         // differ on the two sides of a boundary curve (double-sided
         // conditions, Appendix B) are read on this side
-        const T t = a.side && d > T(0) ? T(1e-3) * eps / d : T(0);
+        const T t = a.side && d > T(0) ? fdiv(T(1e-3) * eps, d) : T(0);
 #pragma unroll
         for (int c = 0; c < D; ++c) EX[(size_t)c * a.ld + id] = fma(t, p[c] - qs.bq[c], qs.bq[c]);
         U[id] = acc_s + usrc;

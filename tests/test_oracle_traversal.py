@@ -126,3 +126,78 @@ def test_bvh_visits_bounds(exported):
     assert np.all(vp0 >= 1) and np.all(vp0 <= sc.prims.shape[0])
     # the closest primitive as the hint never adds node work
     assert np.all(vn1 <= vn0)
+
+
+@pytest.fixture(scope="module")
+def exported3():
+    from paper_2302_11825_amd import _bvc as B
+
+    sc = wl.displaced_icosphere(2, 31)
+    h = B.bvc_scene_create(3, sc.verts, sc.prims)
+    try:
+        child, boxes, order = B.bvc_scene_export_bvh(h)
+        slabs = B.bvc_scene_export_slabs(h)
+    finally:
+        B.bvc_scene_destroy(h)
+    return sc, child, boxes, order, slabs
+
+
+def _subtree_prims(child, order, link):
+    out, todo = [], [link]
+    while todo:
+        c = todo.pop()
+        if c < 0:
+            s, k = (~c) >> 3, ((~c) & 7) + 1
+            out.extend(order[s:s + k])
+        else:
+            todo.extend(child[c])
+    return np.array(out)
+
+
+def test_slabs_hold_their_triangles(exported3):
+    """Each child's slab axis is a unit vector and its range contains n.y for
+    every vertex of every triangle below the child."""
+    sc, child, boxes, order, slabs = exported3
+    for node in range(child.shape[0]):
+        for c in range(2):
+            n, lo, hi = slabs[node, 5 * c:5 * c + 3], slabs[node, 5 * c + 3], slabs[node, 5 * c + 4]
+            assert abs(np.linalg.norm(n) - 1.0) < 1e-14
+            tri = _subtree_prims(child, order, child[node, c])
+            s = sc.verts[sc.prims[tri].ravel()] @ n
+            assert lo <= s.min() and s.max() <= hi
+            assert s.min() - lo < 1e-12 and hi - s.max() < 1e-12
+    assert np.all(slabs[:, 10:] == 0)
+
+
+def test_slab_distance_bounds_the_subtree_distance(exported3):
+    """The slab distance of a child never exceeds the distance from the point
+    to the closest triangle below that child (brute force over the subtree)."""
+    sc, child, boxes, order, slabs = exported3
+    rng = np.random.default_rng(5)
+    q = rng.uniform(-1.3, 1.3, (40, 3))
+    for node in list(range(0, child.shape[0], 7)):
+        for c in range(2):
+            tri = _subtree_prims(child, order, child[node, c])
+            sub = oracle.Scene(wl.Scene(3, sc.verts, np.ascontiguousarray(sc.prims[tri]), "sub"))
+            d, _, _ = sub.closest(q, brute=True)
+            n, lo, hi = slabs[node, 5 * c:5 * c + 3], slabs[node, 5 * c + 3], slabs[node, 5 * c + 4]
+            t = q @ n
+            e = np.maximum(np.maximum(lo - t, t - hi), 0.0)
+            assert np.all(e <= d + 1e-12)
+
+
+def test_slab_bounds_cut_work(exported3):
+    """Pruning with the larger of the two bounds visits fewer nodes and
+    primitives in total (not query by query: the nearer child can change, and
+    with it the order in which the best distance falls)."""
+    sc, child, boxes, order, slabs = exported3
+    osc = oracle.Scene(sc)
+    rng = np.random.default_rng(14)
+    r = rng.uniform(0.2, 1.0, 300) ** (1 / 3)
+    dvec = rng.normal(0, 1, (300, 3))
+    q = dvec / np.linalg.norm(dvec, axis=1, keepdims=True) * r[:, None]
+    _, _, prim = osc.closest(q)
+    for hints in (-np.ones(300, np.int32), prim.astype(np.int32)):
+        vn0, vp0 = oracle.bvh_visits(osc, child, boxes, order, q, hints)
+        vn1, vp1 = oracle.bvh_visits(osc, child, boxes, order, q, hints, slabs=slabs)
+        assert vn1.sum() < vn0.sum() and vp1.sum() < vp0.sum()
