@@ -175,6 +175,39 @@ def walk_roofline(kernel, dim, es, mode, with_grad, ms, queries, walks, work_key
     return out, valu
 
 
+def near_field_effect(pl, prep, sol, with_grad, truth_i, sel, dist_i, gather_ms):
+    """Cost and effect of the FP64 near field of the timed FP32 gather: the
+    same gather launched once more without it (same cache, sources and
+    points), its time and the error of both near the boundary."""
+    import torch
+
+    from paper_2302_11825_amd import _bvc as B
+
+    near = sol.extra.get("near")
+    if near is None or prep.n_int == 0:
+        return None
+    d = prep.sc.dim
+    cview, sview = sol.extra["cview"], sol.extra["sview"]
+    u0 = torch.empty_like(sol.u_int)
+    g0 = torch.empty_like(sol.g_int) if with_grad else None
+    fn = ((lambda: B.bvc_gather_grad(d, cview, sview, prep.n_int, prep.x_int, u0, g0)) if with_grad else
+          (lambda: B.bvc_gather_u(d, cview, sview, prep.n_int, prep.x_int, u0)))
+    fn()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    fn()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_off = e0.elapsed_time(e1)
+    u_on = sol.u_int[: prep.n_int].double().cpu().numpy()[sel]
+    u_off = u0[: prep.n_int].double().cpu().numpy()[sel]
+    close = dist_i < 2 * near["tau"] + prep.p.offset
+    return {"tau": near["tau"], "gather_ms_with": round(gather_ms, 4), "gather_ms_without": round(ms_off, 4),
+            "points_within_l_plus_2tau": int(close.sum()),
+            "rmse_there_with": rmse(u_on[close], truth_i[close]), "rmse_there_without": rmse(u_off[close], truth_i[close]),
+            "max_abs_change": float(np.abs(u_on - u_off).max()) if u_on.size else 0.0}
+
+
 def pointwise_curve(pl, prob, prep, dtype, pts, truth, rmse_bvc, value):
     """Pointwise walk on spheres on a subset of interior points at 1 to 256
     walks per point; the walks per point that match BVC's error come from the
@@ -332,6 +365,8 @@ def run_workload(args, which):
                        "kernel": gather_kernel, "pairs_per_launch": pairs_b + pairs_s, "flops_per_pair": fpp,
                        "avg_launch_ms": round(gather_ms, 4), "pairs_per_s": (pairs_b + pairs_s) / (gather_ms / 1e3)}
 
+    near_field = near_field_effect(pl, prep, sol, with_grad, truth_i, sel, dist_i, gather_ms)
+
     pointwise = None
     if not args.no_pointwise and prep.n_int > 0:
         rng = np.random.default_rng(wl.seed(2 if dim == 2 else 3, 5))
@@ -395,6 +430,7 @@ def run_workload(args, which):
         "roofline_valu": valu,
         "roofline_other_walks": {"hbm": other, "valu": other_valu},
         "roofline_gather": roofline_gather,
+        "near_field": near_field,
         "cpu_baseline": cpu,
         "setup_s": setup_s,
         "tuned_shapes": tuned,

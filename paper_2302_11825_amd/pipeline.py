@@ -250,7 +250,7 @@ class Prepared:
     """Per-scene state reused across solves: device scene, fields, classified
     evaluation points and the candidate count of the cache sampler."""
 
-    def __init__(self, problem, dtype=None, n_cand=None, device="cuda", eval_x=None, clamp=None):
+    def __init__(self, problem, dtype=None, n_cand=None, device="cuda", eval_x=None, clamp=None, near_tau=None):
         self.p = problem
         self.dtype = dtype or problem.precision
         self.sc = Scene(problem.scene, device)
@@ -267,6 +267,16 @@ class Prepared:
         T = DT[self.dtype]
         self.x_int = take(self.eval64, self.idx_int, self.n_int, self.sc.dim, n, T)
         self.x_band = take(self.eval64, self.idx_band, self.n_band, self.sc.dim, n, T)
+        # FP32 gathers keep the near-singular boundary pairs in FP64: pairs
+        # closer than tau (default: the offset l; an evaluation point lies at
+        # least l from the boundary and a cache point exactly l from it) are
+        # summed from FP64 copies of both points and of the cache values
+        self.near_tau = 0.0
+        self.x_int64 = None
+        if self.dtype == "f32" and problem.sigma == 0:
+            self.near_tau = float(problem.offset if near_tau is None else near_tau)
+            if self.near_tau > 0:
+                self.x_int64 = take(self.eval64, self.idx_int, self.n_int, self.sc.dim, n, torch.float64)
         self.clamp = None
         if clamp is not None:
             self._prepare_clamp(clamp, device)
@@ -683,6 +693,16 @@ def _gather_views(prep: Prepared, cache: Cache, a, b, batch, watch):
     return cview, sview
 
 
+def _near(prep: Prepared, cache: Cache, U, D):
+    """Near-field argument of an FP32 gather (None when off): FP64 cache
+    values a, b from the walks' FP64 means, and the FP64 cache points,
+    normals and evaluation points."""
+    if not prep.near_tau or cache.n == 0:
+        return None
+    _, _, a64, b64 = reduce_walks(cache, prep.p.n_walks, U, D, "f64")
+    return dict(tau=prep.near_tau, x=prep.x_int64, cx=cache.x, cn=cache.nrm, a=a64, b=b64)
+
+
 def tune(prep: Prepared, with_grad=True, reps=3) -> dict:
     """Picks the launch shapes of this problem's walks and gather with the
     library's tuners (bvc_tune_walks, bvc_tune_gather) on one solve's real
@@ -705,7 +725,7 @@ def tune(prep: Prepared, with_grad=True, reps=3) -> dict:
     cview, sview = _gather_views(prep, cache, a, b, 0, _NoWatch())
     u = torch.empty(max(prep.n_int, 1), dtype=T, device=sc.device)
     g = torch.empty(d, max(prep.n_int, 1), dtype=T, device=sc.device) if with_grad else None
-    ppt = (B.bvc_tune_gather(d, cview, sview, prep.n_int, prep.x_int, u, g, reps)
+    ppt = (B.bvc_tune_gather(d, cview, sview, prep.n_int, prep.x_int, u, g, reps, near=_near(prep, cache, U, D))
            if prep.n_int and p.sigma == 0 else 0)
     return dict(walk_blocks_per_cu=bpc, walk_open_lanes=lanes, gather_points_per_thread=ppt)
 
@@ -726,6 +746,7 @@ def solve(prep: Prepared, batch=0, with_grad=True, n_walks_band=None, records=Fa
         U, D, rec, counters = cache_walks(sc, cache, wp, dt, records)
     with watch.stage("reduce_walks"):
         uhat, dudn, a, b = reduce_walks(cache, p.n_walks, U, D, dt)
+        near = _near(prep, cache, U, D)
     cview, sview = _gather_views(prep, cache, a, b, batch, watch)
     n_int = prep.n_int
     u_int = torch.empty(max(n_int, 1), dtype=T, device=sc.device)
@@ -734,9 +755,9 @@ def solve(prep: Prepared, batch=0, with_grad=True, n_walks_band=None, records=Fa
     cc = cl["c"] if cl else 0.0
     with watch.stage("gather"):
         if with_grad:
-            B.bvc_gather_grad(d, cview, sview, n_int, prep.x_int, u_int, g_int, clamp=cc, sigma=p.sigma)
+            B.bvc_gather_grad(d, cview, sview, n_int, prep.x_int, u_int, g_int, clamp=cc, sigma=p.sigma, near=near)
         else:
-            B.bvc_gather_u(d, cview, sview, n_int, prep.x_int, u_int, clamp=cc, sigma=p.sigma)
+            B.bvc_gather_u(d, cview, sview, n_int, prep.x_int, u_int, clamp=cc, sigma=p.sigma, near=near)
     gathered = None
     if cl:
         gathered = torch.cuda.Event()
@@ -762,4 +783,4 @@ def solve(prep: Prepared, batch=0, with_grad=True, n_walks_band=None, records=Fa
                                        cl["ws"], cl["counters"])
         main.wait_stream(side)
     return Solution(prep.idx_int, n_int, prep.idx_band, nb, u_int, g_int, u_band, g_band, cache, uhat, dudn,
-                    counters, pwc, extra=dict(U=U, D=D, a=a, b=b, cview=cview, sview=sview, rec=rec))
+                    counters, pwc, extra=dict(U=U, D=D, a=a, b=b, cview=cview, sview=sview, rec=rec, near=near))

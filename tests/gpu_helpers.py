@@ -52,3 +52,37 @@ def c2_like_fields():
     f = wl.gauss_sum(amps, centers, sigma)
     g = wl.gauss_potential_2d(amps, centers, sigma, 3, 1.0, 1.0)
     return g, f
+
+
+def z_ok(z, level=3.0):
+    """True when no more |z| exceed `level` than a normal distribution
+    predicts: the expected count n P(|Z| > level) plus three of its Poisson
+    standard deviations and one."""
+    from math import erfc, sqrt
+
+    z = np.asarray(z, dtype=np.float64)
+    mu = z.size * erfc(level / sqrt(2.0))
+    fails = int(np.sum(~(z < level)))
+    allowed = mu + 3.0 * sqrt(mu) + 1.0
+    return fails <= allowed, f"{fails} of {z.size} beyond {level} sigma (expected {mu:.2f}, allowed {allowed:.2f})"
+
+
+def abs_terms(dim, ex, cy, cn, a, b, sy, sw, tau):
+    """Sums of |terms| of u and of grad u per evaluation point, split into the
+    pairs at r >= tau (FP32 in the kernel) and r < tau (FP64 near field)."""
+    d = cy[None, :, :] - ex[:, None, :]
+    r = np.linalg.norm(d, axis=2)
+    nd = np.abs(np.einsum("kid,id->ki", d, cn))
+    c = 2 * np.pi if dim == 2 else 4 * np.pi
+    g_abs = np.abs(np.log(r)) / (2 * np.pi) if dim == 2 else 1 / (4 * np.pi * r)
+    tu = np.abs(a)[None] * nd / (c * r**dim) + np.abs(b)[None] * g_abs
+    tg = (4 * np.abs(a)[None] / r**dim + np.abs(b)[None] / r ** (dim - 1)) / c
+    far = r >= tau * (1 - 1e-4)  # margin for the FP32 test in the kernel
+    ds_ = np.linalg.norm(sy[None] - ex[:, None], axis=2)
+    su = np.abs(sw)[None] * (np.abs(np.log(ds_)) / (2 * np.pi) if dim == 2 else 1 / (4 * np.pi * ds_))
+    sg = np.abs(sw)[None] / (c * ds_ ** (dim - 1))
+    rmin = np.minimum(np.where(far, r, np.inf).min(1), ds_.min(1))
+    return ((tu * far).sum(1) + su.sum(1), (tu * ~far).sum(1), (tg * far).sum(1) + sg.sum(1),
+            (tg * ~far).sum(1), rmin)
+
+

@@ -10,6 +10,11 @@ with seeded cache values):
   cache; u and grad u at 64 interior points of a full-size gather against
   the oracle's gather over the whole cache and source set; the 256 walks of 32 band points replayed
   walk by walk (same ids, same Philox streams).
+- C2 in FP32, as timed (FP64 near field for pairs closer than l): per-point
+  walk means of 16 cache points against the oracle's FP64 walks on the same
+  streams (3 sigma), u and grad u at 64 interior points of a full-size FP32
+  gather with the near field on the oracle's cache and sources within the
+  FP32 bound of the far pairs, band means against the oracle's walks.
 - C3 (displaced icosphere, 65,536 x 512 walks, 1.1 M points) in FP32, as
   timed: per-point walk means of 16 cache points and 16 band points against
   the oracle's FP64 walks on the same streams (z-test), and u at 64 interior
@@ -23,7 +28,7 @@ import pytest
 import torch
 
 import workloads as wl
-from gpu_helpers import lib, oracle_cache, per_walk_match, to_np_aos
+from gpu_helpers import abs_terms, lib, oracle_cache, per_walk_match, to_np_aos, z_ok
 
 pytestmark = pytest.mark.gpu
 
@@ -146,6 +151,94 @@ def test_c2_full_size_fp64(orc):
     assert close.mean() >= 0.9
     assert np.all(np.abs(u_gpu - ub) <= 6 * se + 1e-12)
     assert np.mean(np.all(np.abs(g_gpu - gb) <= 1e-8 * (np.abs(gb) + 1), axis=1)) >= 0.9
+
+
+def test_c2_full_size_fp32(orc):
+    _bvc, pl = lib()
+    prob = wl.problem_c2()
+    say("c2 full size fp32: prepare")
+    prep = pl.Prepared(prob, dtype="f32")
+    assert prep.near_tau == prob.offset
+    W = prob.n_walks
+    sol = pl.solve(prep, batch=0, with_grad=True)
+    torch.cuda.synchronize()
+    cache = sol.cache
+    n = cache.n
+    say(f"c2 full size fp32: cache {n} interior {prep.n_int} band {prep.n_band}")
+    assert 14000 <= n <= 19000 and prep.n_int > 400000 and prep.n_band > 50000
+    c = sol.counters.cpu().numpy()
+    assert c[3] == n * W and c[2] == 0
+    osc = orc.Scene(prob.scene)
+    P = orc.walk_params(prob.eps, W, prob.seed_walks)
+    idx_i, idx_b = _oracle_split(osc, prob, prep)
+    cn = oracle_cache(osc.sample_cache(prep.n_cand, prob.offset, prob.sides, prob.seed_cache, 0), cache)
+    # walk means of 16 cache points against the FP64 walks on the same streams
+    pick = _spread(n, 16)
+    ids = (pick[:, None] * W + np.arange(W)[None, :]).ravel()
+    ref = orc.cache_walks_subset(osc, prob.g, prob.f, P, cn, ids)
+    for name in ("U", "D"):
+        A = sol.extra[name].double().cpu().numpy()[ids].reshape(-1, W)
+        Bo = ref[name].reshape(-1, W)
+        se = np.sqrt(A.var(1, ddof=1) / W + Bo.var(1, ddof=1) / W) + 1e-12
+        z = np.abs(A.mean(1) - Bo.mean(1)) / se
+        ok, msg = z_ok(z)
+        say(f"  {name}: {msg}")
+        assert ok, msg
+    # the oracle's sources; the device's must be the same
+    m = int(round(prob.n_sources ** 0.5))
+    lo, hi = prob.scene.bbox
+    sy, sw = osc.sample_sources(prob.f, m, lo, hi, prob.offset, prob.seed_sources, 0)
+    sv = sol.extra["sview"]
+    assert sv["n"] == sw.size
+    assert np.allclose(to_np_aos(sv["y"], sv["n"]), sy, rtol=0, atol=1e-6)
+    # (FP32 weights: Gaussian tails below the FP32 range round to 0)
+    assert np.allclose(sv["s"].double().cpu().numpy()[: sv["n"]], sw, rtol=1e-6, atol=1e-7 * np.abs(sw).max())
+    # a full-size FP32 gather of u and grad u with the near field, as the
+    # step launches it, on the oracle's cache and sources with seeded values
+    # rounded to FP32 (the near field's FP64 copies hold the same numbers);
+    # 64 outputs against the oracle
+    r32 = lambda v: v.astype(np.float32).astype(np.float64)
+    a, b = _cache_values(cn, 7)
+    cy, cnn, a, b, sy, sw = (r32(v) for v in (cn["x"], cn["n"], a, b, sy, sw))
+    xall = prob.eval_x[idx_i]
+    f32, f64 = torch.float32, torch.float64
+    tau = prep.near_tau
+    cview = dict(n=n, dtype=_bvc.F32, x=_dev(cy, f32), nrm=_dev(cnn, f32), a=_dev(a, f32), b=_dev(b, f32))
+    sview = dict(n=sw.size, dtype=_bvc.F32, y=_dev(sy, f32), s=_dev(sw, f32))
+    near = dict(tau=tau, x=_dev(xall, f64), cx=_dev(cy, f64), cn=_dev(cnn, f64), a=_dev(a, f64), b=_dev(b, f64))
+    u_full = torch.empty(prep.n_int, dtype=f32, device="cuda")
+    g_full = torch.empty(2, prep.n_int, dtype=f32, device="cuda")
+    _bvc.bvc_gather_grad(2, cview, sview, prep.n_int, _dev(xall, f32), u_full, g_full, near=near)
+    torch.cuda.synchronize()
+    ki = _spread(prep.n_int, 64)
+    x = xall[ki]
+    uo, go = orc.gather(2, x, cy, cnn, a, b, sy, sw, with_grad=True)
+    su_far, su_near, sg_far, sg_near, rmin = abs_terms(2, x, cy, cnn, a, b, sy, sw, tau)
+    uu = 2.0**-24
+    zmax = np.linalg.norm(np.concatenate([cy, sy]), axis=1).max()
+    x32 = r32(x)
+    shift = np.linalg.norm(x - x32, axis=1) / rmin
+    rel = uu * (300 + 4 * (np.linalg.norm(x, axis=1) + zmax) / rmin) + 4 * shift
+    tol = su_far * rel + 1e-10 * su_near + uu * np.abs(uo)
+    err = np.abs(u_full.double().cpu().numpy()[ki] - uo)
+    assert np.all(err <= tol), np.max(err / tol)
+    gtol = sg_far * (rel + 2 * shift) + 1e-10 * sg_near + uu * np.abs(go).max(1)
+    gerr = np.abs(to_np_aos(g_full)[ki] - go).max(1)
+    assert np.all(gerr <= gtol + 1e-30), np.max(gerr / gtol)
+    # the step's own estimate is close to the solution
+    tru = wl.field_value(prob.truth, xall)
+    err = np.median(np.abs(sol.u_int.double().cpu().numpy()[: prep.n_int] - tru))
+    say(f"  interior median error {err:.4g}")
+    assert err < 0.02 * np.sqrt(np.mean(tru**2))
+    # band points: walk means against the FP64 walks on the same streams
+    kb = _spread(prep.n_band, 16)
+    pts = prob.eval_x[idx_b[kb]]
+    ub, _, se_o = _band_walks(orc, osc, prob, P, pts, kb, W, True)
+    u_gpu = sol.u_band.double().cpu().numpy()[kb]
+    z = np.abs(u_gpu - ub) / (np.sqrt(2) * se_o + 1e-6 * (1 + np.abs(ub)))
+    ok, msg = z_ok(z)
+    say(f"  band: {msg}")
+    assert ok, msg
 
 
 def test_c3_full_size_fp32(orc):

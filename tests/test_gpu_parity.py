@@ -18,7 +18,8 @@ import pytest
 import torch
 
 import workloads as wl
-from gpu_helpers import c2_like_fields, lib, oracle_cache, per_walk_match, small_star, to_np_aos
+from gpu_helpers import abs_terms as _abs_terms
+from gpu_helpers import c2_like_fields, lib, oracle_cache, per_walk_match, small_star, to_np_aos, z_ok
 
 pytestmark = pytest.mark.gpu
 
@@ -222,25 +223,6 @@ def test_gather_matches_oracle(B, orc, dim, dtype):
         assert np.all(np.abs(gg - go).max(1) <= gtol + 1e-30)
 
 
-def _abs_terms(dim, ex, cy, cn, a, b, sy, sw, tau):
-    """Sums of |terms| of u and of grad u per evaluation point, split into the
-    pairs at r >= tau (FP32 in the kernel) and r < tau (FP64 near field)."""
-    d = cy[None, :, :] - ex[:, None, :]
-    r = np.linalg.norm(d, axis=2)
-    nd = np.abs(np.einsum("kid,id->ki", d, cn))
-    c = 2 * np.pi if dim == 2 else 4 * np.pi
-    g_abs = np.abs(np.log(r)) / (2 * np.pi) if dim == 2 else 1 / (4 * np.pi * r)
-    tu = np.abs(a)[None] * nd / (c * r**dim) + np.abs(b)[None] * g_abs
-    tg = (4 * np.abs(a)[None] / r**dim + np.abs(b)[None] / r ** (dim - 1)) / c
-    far = r >= tau * (1 - 1e-4)  # margin for the FP32 test in the kernel
-    ds_ = np.linalg.norm(sy[None] - ex[:, None], axis=2)
-    su = np.abs(sw)[None] * (np.abs(np.log(ds_)) / (2 * np.pi) if dim == 2 else 1 / (4 * np.pi * ds_))
-    sg = np.abs(sw)[None] / (c * ds_ ** (dim - 1))
-    rmin = np.minimum(np.where(far, r, np.inf).min(1), ds_.min(1))
-    return ((tu * far).sum(1) + su.sum(1), (tu * ~far).sum(1), (tg * far).sum(1) + sg.sum(1),
-            (tg * ~far).sum(1), rmin)
-
-
 @pytest.mark.parametrize("dim", [2, 3])
 def test_gather_fp32_near_field(B, orc, dim):
     """FP32 gather with the FP64 near field (pairs closer than tau evaluated
@@ -381,7 +363,8 @@ def test_basis_means_fp64(B, orc, case):
 
 def test_cache_walks_fp32_statistics(B, orc):
     """FP32 walks follow the FP64 oracle in distribution: per cache point the
-    means agree within 4.5 standard errors for >= 99% of points."""
+    means of independent walk sets (other seeds) agree within 3 standard
+    errors, as often as a normal distribution predicts."""
     _bvc, pl = B
     say("cache walks fp32 statistics star_poisson")
     scene, g, f, eps, l, sides, n, W = CASES["star_poisson"]()
@@ -396,6 +379,8 @@ def test_cache_walks_fp32_statistics(B, orc):
     Dg = D.double().cpu().numpy()[: cache.n * W].reshape(-1, W)
     Uo, Do = ref["U"].reshape(-1, W), ref["D"].reshape(-1, W)
     for A, Bo in ((Ug, Uo), (Dg, Do)):
-        se = np.sqrt(A.var(1) / W + Bo.var(1) / W) + 1e-12
+        se = np.sqrt(A.var(1, ddof=1) / W + Bo.var(1, ddof=1) / W) + 1e-12
         z = np.abs(A.mean(1) - Bo.mean(1)) / se
-        assert np.mean(z < 4.5) >= 0.99
+        ok, msg = z_ok(z)
+        say(msg)
+        assert ok, msg
