@@ -145,8 +145,8 @@ def lib():
         L.orc_screen_grad_weight.restype = C.c_double
         L.orc_gather_sigma.argtypes = [C.c_int, C.c_double, C.c_int64, _dp, C.c_int64, _dp, _dp, _dp, _dp,
                                        C.c_int64, _dp, _dp, _dp, _dp, _dp]
-        L.orc_wost_walks.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(_Field), C.POINTER(_WalkParams), C.c_int,
-                                     C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _ip]
+        L.orc_wost_walks.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(_Field), C.POINTER(_Field),
+                                     C.POINTER(_WalkParams), C.c_int, C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _ip]
         L.orc_silhouette_distances.argtypes = [C.c_void_p, C.c_int64, _dp, _dp]
         L.orc_silhouette_distances.restype = None
         L.orc_sphere_reentry.argtypes = [_dp, C.c_double, _dp, C.c_double, C.c_double, C.c_double, _dp]
@@ -659,18 +659,21 @@ def sample_roi(dom: Scene, roi: Scene, n, seed, batch=0):
 
 
 # --- Walk on stars, mixed Dirichlet / Neumann (2D, h = 0) --------------------
-def wost_walks(dir_scene: Scene, neu_scene: Scene, g, params, mode, x, nrm=None, R0=None, xbar=None):
-    """U (and D in mode 0) per walk, shape (n * W,); see orc_wost_walks."""
-    x = _f64(x).reshape(-1, 2)
+def wost_walks(dir_scene: Scene, neu_scene: Scene, g, params, mode, x, nrm=None, R0=None, xbar=None, h=None):
+    """U (and D in mode 0) per walk, shape (n * W,); see orc_wost_walks.
+    h: Neumann data (None: h = 0)."""
+    d = dir_scene.dim
+    x = _f64(x).reshape(-1, d)
     n, W = x.shape[0], params.n_walks
     U = np.zeros(n * W)
     D = np.zeros(n * W)
     st = np.zeros(n * W, np.int32)
     G = _field(g)
-    lib().orc_wost_walks(dir_scene.h, neu_scene.h, C.byref(G), C.byref(params), int(mode), n, _d(x),
-                         _d(_f64(nrm).reshape(-1, 2)) if nrm is not None else None,
+    H = _field(h)
+    lib().orc_wost_walks(dir_scene.h, neu_scene.h, C.byref(G), C.byref(H), C.byref(params), int(mode), n, _d(x),
+                         _d(_f64(nrm).reshape(-1, d)) if nrm is not None else None,
                          _d(_f64(R0)) if R0 is not None else None,
-                         _d(_f64(xbar).reshape(-1, 2)) if xbar is not None else None, _d(U), _d(D), _i(st))
+                         _d(_f64(xbar).reshape(-1, d)) if xbar is not None else None, _d(U), _d(D), _i(st))
     return U, D, st
 
 
@@ -692,8 +695,8 @@ def sample_mixed(full: Scene, dir_scene: Scene, neu_scene: Scene, n, l, seed, ba
 
 
 def silhouette_distances(neu_scene: Scene, x):
-    """Distance to the closest Neumann silhouette vertex, per point."""
-    x = _f64(x).reshape(-1, 2)
+    """Distance to the closest Neumann silhouette (2D vertex, 3D edge), per point."""
+    x = _f64(x).reshape(-1, neu_scene.dim)
     d = np.zeros(x.shape[0])
     lib().orc_silhouette_distances(neu_scene.h, x.shape[0], _d(x), _d(d))
     return d

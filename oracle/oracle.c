@@ -1673,22 +1673,81 @@ void orc_basis_means(const orc_field* basis, int dim, int64_t n_cache, int32_t W
 
 /* ======================================================================== */
 /* Walk on stars for mixed Dirichlet / Neumann boundaries (Section 3.1: the  */
-/* WoSt estimator the cache relies on; 2D, Neumann data h = 0, no source)    */
+/* WoSt estimator the cache relies on; 2D segments and 3D triangles, Neumann */
+/* data h, no source term)                                                  */
 /* ======================================================================== */
-/* The Dirichlet part `dir` and the Neumann part `neu` are two segment sets
- * of one counter-clockwise boundary.  Seen from x, a vertex of the Neumann
- * part is a silhouette point when both Neumann segments at it lie on the same
- * side of the line through x and the vertex, or when the Neumann part ends
- * there. */
+/* The Dirichlet part `dir` and the Neumann part `neu` are two element sets
+ * of one boundary (2D: counter-clockwise segments; 3D: triangles with
+ * outward normals by the right-hand rule).
+ *
+ * 2D: seen from x, a vertex of the Neumann part is a silhouette point when
+ * both Neumann segments at it lie on the same side of the line through x and
+ * the vertex, or when the Neumann part ends there. */
 typedef struct {
   int32_t* prev;     /* per Neumann segment: start vertex of the Neumann segment ending at its start, or -1 */
   int32_t* has_next; /* 1 when a Neumann segment starts at its end vertex */
   int32_t* straight; /* 1 when the segment and the one ending at its start are collinear */
+  /* 3D: per triangle and edge k (vertex k to vertex k+1 mod 3) */
+  int32_t* nb;       /* the Neumann triangle across the edge, or -1 (the Neumann part ends there) */
+  int32_t* flat;     /* 1 when that triangle is coplanar with this one (no fold at the edge) */
 } neu_links;
 
+static void free_links(neu_links* L) {
+  free(L->prev);
+  free(L->has_next);
+  free(L->straight);
+  free(L->nb);
+  free(L->flat);
+}
+
+typedef struct {
+  int32_t lo, hi, tri, k;
+} edge_rec;
+
+static int edge_cmp(const void* a, const void* b) {
+  const edge_rec* x = (const edge_rec*)a;
+  const edge_rec* y = (const edge_rec*)b;
+  if (x->lo != y->lo) return x->lo < y->lo ? -1 : 1;
+  if (x->hi != y->hi) return x->hi < y->hi ? -1 : 1;
+  if (x->tri != y->tri) return x->tri < y->tri ? -1 : 1;
+  return x->k - y->k;
+}
+
 static neu_links make_links(const orc_scene* neu) {
-  neu_links L;
+  neu_links L = {NULL, NULL, NULL, NULL, NULL};
   int64_t np = neu->np, nv = neu->nv;
+  if (neu->dim == 3) {
+    /* triangles across each edge from the sorted list of edges by vertex pair */
+    L.nb = (int32_t*)malloc((size_t)np * 3 * sizeof(int32_t));
+    L.flat = (int32_t*)malloc((size_t)np * 3 * sizeof(int32_t));
+    edge_rec* E = (edge_rec*)malloc((size_t)np * 3 * sizeof(edge_rec));
+    for (int64_t t = 0; t < np; ++t)
+      for (int k = 0; k < 3; ++k) {
+        int32_t a = neu->P[3 * t + k], b = neu->P[3 * t + (k + 1) % 3];
+        E[3 * t + k].lo = a < b ? a : b;
+        E[3 * t + k].hi = a < b ? b : a;
+        E[3 * t + k].tri = (int32_t)t;
+        E[3 * t + k].k = k;
+        L.nb[3 * t + k] = -1;
+        L.flat[3 * t + k] = 0;
+      }
+    qsort(E, (size_t)np * 3, sizeof(edge_rec), edge_cmp);
+    for (int64_t i = 0; i + 1 < np * 3; ++i) {
+      if (E[i].lo != E[i + 1].lo || E[i].hi != E[i + 1].hi) continue;
+      const edge_rec *e = &E[i], *f = &E[i + 1];
+      L.nb[3 * e->tri + e->k] = f->tri;
+      L.nb[3 * f->tri + f->k] = e->tri;
+      const double* n1 = neu->fnorm + 3 * (int64_t)e->tri;
+      const double* n2 = neu->fnorm + 3 * (int64_t)f->tri;
+      double c[3];
+      cross3(n1, n2, c);
+      int fl = sqrt(dot3(c, c)) <= 1e-12 && dot3(n1, n2) > 0;
+      L.flat[3 * e->tri + e->k] = L.flat[3 * f->tri + f->k] = fl;
+      ++i;
+    }
+    free(E);
+    return L;
+  }
   L.prev = (int32_t*)malloc((size_t)np * sizeof(int32_t));
   L.has_next = (int32_t*)malloc((size_t)np * sizeof(int32_t));
   L.straight = (int32_t*)malloc((size_t)np * sizeof(int32_t));
@@ -1730,14 +1789,54 @@ static int line_side(const double* x, const double* v, const double* w) {
   return c > 0 ? 1 : -1;
 }
 
-/* Distance from x to the closest silhouette vertex of the Neumann part: a
- * corner vertex whose two Neumann neighbours do not lie strictly on opposite
- * sides of the line from x through it (both on one side; one on the line, x
- * looking along a segment past the corner; both on it, the fold at the tip
- * of a thin Neumann curve), and the ends of Neumann runs.  A vertex where the
- * boundary continues straight is no corner and never a silhouette. */
+/* Side of x relative to the plane of a triangle with unit normal n through
+ * the point v: +1 in front (the side the normal points to), -1 behind, 0
+ * within a relative 1e-9 of the plane (a walk standing on a Neumann face lies
+ * in its plane only up to rounding). */
+static int plane_side(const double* x, const double* v, const double* n) {
+  double d[3] = {x[0] - v[0], x[1] - v[1], x[2] - v[2]};
+  double s = dot3(n, d);
+  if (fabs(s) <= 1e-9 * sqrt(dot3(d, d))) return 0;
+  return s > 0 ? 1 : -1;
+}
+
+static double segment_dist3(const double* x, const double* a, const double* b) {
+  double e[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]}, r[3] = {x[0] - a[0], x[1] - a[1], x[2] - a[2]};
+  double t = dot3(r, e) / dot3(e, e);
+  t = t < 0 ? 0 : (t > 1 ? 1 : t);
+  double d[3] = {r[0] - t * e[0], r[1] - t * e[1], r[2] - t * e[2]};
+  return sqrt(dot3(d, d));
+}
+
+/* Distance from x to the closest silhouette of the Neumann part.
+ * 2D: a corner vertex whose two Neumann neighbours do not lie strictly on
+ * opposite sides of the line from x through it (both on one side; one on the
+ * line, x looking along a segment past the corner; both on it, the fold at
+ * the tip of a thin Neumann curve), and the ends of Neumann runs.  A vertex
+ * where the boundary continues straight is no corner and never a silhouette.
+ * 3D: an edge where the Neumann part ends, and an edge between two
+ * non-coplanar Neumann triangles unless x lies strictly in front of both
+ * planes or strictly behind both (one seen from the front and the other
+ * from the back is a fold of the surface as seen from x; x in one of the
+ * planes sees that face edge-on). */
 static double silhouette_distance(const orc_scene* neu, const neu_links* L, const double* x) {
   double best = INFINITY;
+  if (neu->dim == 3) {
+    for (int64_t t = 0; t < neu->np; ++t)
+      for (int k = 0; k < 3; ++k) {
+        int32_t nb = L->nb[3 * t + k];
+        if (nb >= 0 && (nb < t || L->flat[3 * t + k])) continue; /* each interior edge once; flat edges never */
+        const double* a = neu->V + 3 * (int64_t)neu->P[3 * t + k];
+        const double* b = neu->V + 3 * (int64_t)neu->P[3 * t + (k + 1) % 3];
+        int sil = 1;
+        if (nb >= 0) {
+          int s1 = plane_side(x, a, neu->fnorm + 3 * t), s2 = plane_side(x, a, neu->fnorm + 3 * (int64_t)nb);
+          sil = !(s1 * s2 > 0);
+        }
+        if (sil) best = fmin(best, segment_dist3(x, a, b));
+      }
+    return best;
+  }
   for (int64_t q = 0; q < neu->np; ++q) {
     const double* a = neu->V + 2 * (int64_t)neu->P[2 * q];
     const double* b = neu->V + 2 * (int64_t)neu->P[2 * q + 1];
@@ -1758,19 +1857,42 @@ static double silhouette_distance(const orc_scene* neu, const neu_links* L, cons
   return best;
 }
 
-/* Nearest crossing of the ray x + t w, lo < t <= hi, with a Neumann segment:
- * its t (INFINITY if none), and the segment in *seg (-1 if none). */
+/* Nearest crossing of the ray x + t w, lo < t <= hi, with a Neumann element
+ * the ray leaves the domain through (w . n_out > 0), so that of the two
+ * faces of a double-sided Neumann sheet (Appendix B) the ray meets the one
+ * facing its own side: its t (INFINITY if none), and the element in *el (-1
+ * if none).  3D: the ray's parameters on the triangle by Cramer's rule on
+ * x + t w = a + u (b - a) + v (c - a). */
 static double neumann_hit(const orc_scene* neu, const double* x, const double* w, double lo, double hi,
-                          int64_t* seg) {
+                          int64_t* el) {
   double best = INFINITY;
-  *seg = -1;
+  *el = -1;
+  if (neu->dim == 3) {
+    for (int64_t t3 = 0; t3 < neu->np; ++t3) {
+      const double* a = neu->V + 3 * (int64_t)neu->P[3 * t3];
+      const double* b = neu->V + 3 * (int64_t)neu->P[3 * t3 + 1];
+      const double* c = neu->V + 3 * (int64_t)neu->P[3 * t3 + 2];
+      double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]}, e2[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+      double n[3];
+      cross3(e1, e2, n);
+      double den = dot3(w, n);
+      if (!(den > 0)) continue;
+      double r[3] = {x[0] - a[0], x[1] - a[1], x[2] - a[2]}, rw[3];
+      cross3(r, w, rw);
+      double t = -dot3(r, n) / den;
+      double u = -dot3(rw, e2) / den;
+      double v = dot3(rw, e1) / den;
+      if (t > lo && t <= hi && u >= 0 && v >= 0 && u + v <= 1 && t < best) {
+        best = t;
+        *el = t3;
+      }
+    }
+    return best;
+  }
   for (int64_t q = 0; q < neu->np; ++q) {
     const double* a = neu->V + 2 * (int64_t)neu->P[2 * q];
     const double* b = neu->V + 2 * (int64_t)neu->P[2 * q + 1];
     double e0 = b[0] - a[0], e1 = b[1] - a[1];
-    /* den = |e| w . n_out: only a segment the ray leaves the domain through
-     * counts, so that of the two runs of a double-sided Neumann curve
-     * (Appendix B) the ray meets the one facing its own side */
     double den = cross2(w[0], w[1], e0, e1);
     if (!(den > 0)) continue;
     double r0 = a[0] - x[0], r1 = a[1] - x[1];
@@ -1778,31 +1900,105 @@ static double neumann_hit(const orc_scene* neu, const double* x, const double* w
     double u = cross2(r0, r1, w[0], w[1]) / den;
     if (t > lo && t <= hi && u >= 0 && u <= 1 && t < best) {
       best = t;
-      *seg = q;
+      *el = q;
     }
   }
   return best;
 }
 
+/* The Neumann term of one star (Section 3.1; the boundary integral of the
+ * Green's representation on the star St(x, R) with u's normal derivative h
+ * known on the Neumann part): I = int over the Neumann part of the star's
+ * boundary of G^B(x, z) h(z) dz, divided by alpha(x) = 1/2 when x stands on
+ * the Neumann part (the star is then a half ball at x) and 1 inside.  With
+ * R at most the silhouette distance, that part is every point of a Neumann
+ * element within R of x whose element x does not lie strictly behind.  One
+ * sample: the elements within R of x (x not strictly behind) form the set C
+ * of total measure |C|; one element is drawn with probability measure /
+ * |C| by an exponential race (key -ln(1 - U_e) / measure_e, the smallest
+ * wins; U_e from Philox block e, the element's index, tag | 32 | (k << 8)),
+ * which does not depend on the order the elements are visited in; z is
+ * uniform on it (block 4k + 1, tag | 64: 2D a + U1 (b - a); 3D barycentric
+ * (1 - s, s (1 - U2), s U2), s = sqrt(U1)); the estimate is
+ * |C| G^B(x, z) h(z) / alpha when |z - x| < R, else 0.  G^B(x, z) is
+ * ln(R / r) / (2 pi) in 2D and (1 / r - 1 / R) / (4 pi) in 3D. */
+static double neumann_term(const orc_scene* neu, const orc_field* h, const orc_walk_params* p, uint32_t k,
+                           uint32_t id, uint32_t tag, const double* x, double R, int onb) {
+  int dim = neu->dim;
+  double AC = 0, key_best = INFINITY;
+  int64_t pick = -1;
+  for (int64_t e = 0; e < neu->np; ++e) {
+    const double* a = neu->V + dim * (int64_t)neu->P[dim * e];
+    double c[3];
+    int reg;
+    if (!(prim_dist2(neu, e, x, c, &reg) < R * R)) continue;
+    double meas;
+    if (dim == 2) {
+      const double* b = neu->V + 2 * (int64_t)neu->P[2 * e + 1];
+      double n_out[2] = {b[1] - a[1], -(b[0] - a[0])};
+      double len = hypot(n_out[0], n_out[1]);
+      double sd = (n_out[0] * (x[0] - a[0]) + n_out[1] * (x[1] - a[1])) / len;
+      if (sd > 1e-9 * hypot(x[0] - a[0], x[1] - a[1])) continue; /* strictly behind */
+      meas = len;
+    } else {
+      if (plane_side(x, a, neu->fnorm + 3 * e) > 0) continue;
+      const double* b = neu->V + 3 * (int64_t)neu->P[3 * e + 1];
+      const double* cc = neu->V + 3 * (int64_t)neu->P[3 * e + 2];
+      double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]}, e2[3] = {cc[0] - a[0], cc[1] - a[1], cc[2] - a[2]};
+      double nn[3];
+      cross3(e1, e2, nn);
+      meas = 0.5 * sqrt(dot3(nn, nn));
+    }
+    AC += meas;
+    double u, unused;
+    orc_uniform_pair(p->seed, (uint32_t)e, id, p->batch, tag | 32u | (k << 8), &u, &unused);
+    double key = -log(1.0 - u) / meas;
+    if (key < key_best) {
+      key_best = key;
+      pick = e;
+    }
+  }
+  if (pick < 0) return 0.0;
+  double u1, u2, z[3] = {0, 0, 0};
+  orc_uniform_pair(p->seed, 4 * k + 1, id, p->batch, tag | 64u, &u1, &u2);
+  const double* a = neu->V + dim * (int64_t)neu->P[dim * pick];
+  const double* b = neu->V + dim * (int64_t)neu->P[dim * pick + 1];
+  if (dim == 2) {
+    for (int q = 0; q < 2; ++q) z[q] = a[q] + u1 * (b[q] - a[q]);
+  } else {
+    const double* c = neu->V + 3 * (int64_t)neu->P[3 * pick + 2];
+    double s = sqrt(u1);
+    for (int q = 0; q < 3; ++q) z[q] = (1 - s) * a[q] + s * (1 - u2) * b[q] + s * u2 * c[q];
+  }
+  double r2 = 0;
+  for (int q = 0; q < dim; ++q) r2 += (z[q] - x[q]) * (z[q] - x[q]);
+  double r = sqrt(r2);
+  if (!(r < R) || !(r > 0)) return 0.0;
+  double G = dim == 2 ? log(R / r) / (2 * ORC_PI) : (1.0 / r - 1.0 / R) / (4 * ORC_PI);
+  return AC * G * orc_field_eval(h, dim, z) / (onb ? 0.5 : 1.0);
+}
+
 /* One walk on stars (modes as orc_wost_walks). */
 static void wost_walk(const orc_scene* dir, const orc_scene* neu, const neu_links* L, const orc_field* g,
-                      const orc_walk_params* p, int mode, const double* x, const double* n, double R0,
-                      const double* xbar, uint32_t id, double* U, double* D, int32_t* steps, int32_t* capped) {
+                      const orc_field* h, const orc_walk_params* p, int mode, const double* x, const double* n,
+                      double R0, const double* xbar, uint32_t id, double* U, double* D, int32_t* steps,
+                      int32_t* capped) {
+  int dim = dir->dim;
   uint32_t tag = mode == 0 ? 1u : 2u;
-  double pos[2] = {x[0], x[1]}, nin[2] = {0, 0}, nu0[2] = {0, 0};
+  double pos[3] = {0, 0, 0}, nin[3] = {0, 0, 0}, nu0[3] = {0, 0, 0};
+  for (int q = 0; q < dim; ++q) pos[q] = x[q];
   int onb = 0;
   int32_t k = 0;
+  double SN = 0.0;
   *capped = 0;
   if (mode == 0) {
     /* first ball, wholly inside the domain: the gradient estimate of Eq. 7 */
-    walk_direction(p->seed, 0, id, p->batch, tag, 2, nu0);
-    pos[0] = x[0] + R0 * nu0[0];
-    pos[1] = x[1] + R0 * nu0[1];
+    walk_direction(p->seed, 0, id, p->batch, tag, dim, nu0);
+    for (int q = 0; q < dim; ++q) pos[q] = x[q] + R0 * nu0[q];
     k = 1;
   } else if (mode == 3) {
     onb = 1;
-    nin[0] = -n[0];
-    nin[1] = -n[1];
+    for (int q = 0; q < dim; ++q) nin[q] = -n[q];
   }
   double W;
   for (;; ++k) {
@@ -1810,75 +2006,76 @@ static void wost_walk(const orc_scene* dir, const orc_scene* neu, const neu_link
     orc_closest(dir, pos, 0, &dD, qD, NULL);
     if (dD < p->eps || k >= p->max_steps) {
       *capped = !(dD < p->eps);
-      double e[2];
-      read_point(p, 2, pos, qD, dD, e);
-      W = orc_field_eval(g, 2, e);
+      double e[3];
+      read_point(p, dim, pos, qD, dD, e);
+      W = orc_field_eval(g, dim, e);
       break;
     }
     double R = fmax(fmin(dD, silhouette_distance(neu, L, pos)), p->eps);
-    double w[2];
-    walk_direction(p->seed, (uint32_t)k, id, p->batch, tag, 2, w);
-    if (onb && w[0] * nin[0] + w[1] * nin[1] < 0) {
-      w[0] = -w[0];
-      w[1] = -w[1];
-    }
-    int64_t seg;
-    double t = neumann_hit(neu, pos, w, 1e-9 * R, R, &seg);
-    if (seg >= 0) {
-      const double* a = neu->V + 2 * (int64_t)neu->P[2 * seg];
-      const double* b = neu->V + 2 * (int64_t)neu->P[2 * seg + 1];
-      double e0 = b[0] - a[0], e1 = b[1] - a[1], len = hypot(e0, e1);
-      pos[0] += t * w[0];
-      pos[1] += t * w[1];
-      nin[0] = -e1 / len; /* inward normal of a counter-clockwise boundary */
-      nin[1] = e0 / len;
+    if (h && h->kind != 0) SN += neumann_term(neu, h, p, (uint32_t)k, id, tag, pos, R, onb);
+    double w[3];
+    walk_direction(p->seed, (uint32_t)k, id, p->batch, tag, dim, w);
+    double wn = 0;
+    for (int q = 0; q < dim; ++q) wn += w[q] * nin[q];
+    if (onb && wn < 0)
+      for (int q = 0; q < dim; ++q) w[q] = -w[q];
+    int64_t el;
+    double t = neumann_hit(neu, pos, w, 1e-9 * R, R, &el);
+    if (el >= 0) {
+      for (int q = 0; q < dim; ++q) pos[q] += t * w[q];
+      if (dim == 2) {
+        const double* a = neu->V + 2 * (int64_t)neu->P[2 * el];
+        const double* b = neu->V + 2 * (int64_t)neu->P[2 * el + 1];
+        double e0 = b[0] - a[0], e1 = b[1] - a[1], len = hypot(e0, e1);
+        nin[0] = -e1 / len; /* inward normal of a counter-clockwise boundary */
+        nin[1] = e0 / len;
+      } else {
+        for (int q = 0; q < 3; ++q) nin[q] = -neu->fnorm[3 * el + q];
+      }
       onb = 1;
     } else {
-      pos[0] += R * w[0];
-      pos[1] += R * w[1];
+      for (int q = 0; q < dim; ++q) pos[q] += R * w[q];
       onb = 0;
     }
   }
   *steps = k;
-  *U = W;
+  *U = W + SN;
   if (D) {
     *D = 0;
     if (mode == 0) {
-      double c = control_value(p, g, 2, x, xbar);
-      *D = 2.0 / R0 * (nu0[0] * n[0] + nu0[1] * n[1]) * (W - c);
+      double c = control_value(p, g, dim, x, xbar), dn = 0;
+      for (int q = 0; q < dim; ++q) dn += nu0[q] * n[q];
+      *D = (double)dim / R0 * dn * (*U - c);
     }
   }
 }
 
 void orc_silhouette_distances(const orc_scene* neu, int64_t n, const double* x, double* d) {
   neu_links L = make_links(neu);
-  for (int64_t i = 0; i < n; ++i) d[i] = silhouette_distance(neu, &L, x + 2 * i);
-  free(L.prev);
-  free(L.has_next);
-  free(L.straight);
+  for (int64_t i = 0; i < n; ++i) d[i] = silhouette_distance(neu, &L, x + neu->dim * i);
+  free_links(&L);
 }
 
-void orc_wost_walks(const orc_scene* dir, const orc_scene* neu, const orc_field* g, const orc_walk_params* p,
-                    int mode, int64_t n, const double* x, const double* nrm, const double* R0, const double* xbar,
-                    double* U, double* D, int32_t* steps) {
+void orc_wost_walks(const orc_scene* dir, const orc_scene* neu, const orc_field* g, const orc_field* h,
+                    const orc_walk_params* p, int mode, int64_t n, const double* x, const double* nrm,
+                    const double* R0, const double* xbar, double* U, double* D, int32_t* steps) {
   neu_links L = make_links(neu);
   int64_t W = p->n_walks;
+  int dim = dir->dim;
 #pragma omp parallel for schedule(dynamic, 4)
   for (int64_t i = 0; i < n; ++i) {
     for (int64_t j = 0; j < W; ++j) {
       int64_t id = i * W + j;
       int32_t st, cap;
       double uu, dd;
-      wost_walk(dir, neu, &L, g, p, mode, x + 2 * i, nrm ? nrm + 2 * i : NULL, R0 ? R0[i] : 0.0,
-                xbar ? xbar + 2 * i : NULL, (uint32_t)id, &uu, &dd, &st, &cap);
+      wost_walk(dir, neu, &L, g, h, p, mode, x + dim * i, nrm ? nrm + dim * i : NULL, R0 ? R0[i] : 0.0,
+                xbar ? xbar + dim * i : NULL, (uint32_t)id, &uu, &dd, &st, &cap);
       U[id] = uu;
       if (D) D[id] = dd;
       if (steps) steps[id] = st;
     }
   }
-  free(L.prev);
-  free(L.has_next);
-  free(L.straight);
+  free_links(&L);
 }
 
 /* Cache candidates for a boundary with a Neumann part (Section 3.2, "Boundary

@@ -250,27 +250,35 @@ void orc_gather_sigma(int dim, double sigma, int64_t K, const double* ex, int64_
                       const double* cn, const double* a, const double* b, int64_t M, const double* sy,
                       const double* sw, double* u, double* grad, double* cond);
 
-/* --- Walk on stars, mixed Dirichlet / Neumann boundaries (2D, h = 0) ---- */
-/* `dir` and `neu` hold the Dirichlet and the Neumann segments of one
- * counter-clockwise boundary.  Walk j of start point i has id i*W + j.
+/* --- Walk on stars, mixed Dirichlet / Neumann boundaries (2D and 3D) ---- */
+/* `dir` and `neu` hold the Dirichlet and the Neumann elements of one
+ * boundary (2D: counter-clockwise segments; 3D: triangles, outward by the
+ * right-hand rule).  Walk j of start point i has id i*W + j.
  * mode 0: from an offset Dirichlet cache point (normal nrm, R0 = distance to
  * the whole boundary, xbar = closest Dirichlet point): first ball of radius
- * R0 with the gradient estimate D = n . (2/R0) nu (W - g(xbar)) (Eq. 7), tag
- * 1; mode 1: from an interior point, tag 2; mode 3: from a point on the
+ * R0 with the gradient estimate D = n . (dim/R0) nu (U - g(xbar)) (Eq. 7),
+ * tag 1; mode 1: from an interior point, tag 2; mode 3: from a point on the
  * Neumann boundary (nrm = outward normal), tag 2.  Star radius
- * max(eps, min(d_Dirichlet, d_silhouette)) (silhouettes: corner vertices
+ * max(eps, min(d_Dirichlet, d_silhouette)) (2D silhouettes: corner vertices
  * seen with both neighbours on one side, run ends; a vertex where the
- * boundary continues straight is no corner); direction uniform (block 4k),
- * turned into the inward half circle on the Neumann boundary; the next point
- * is the nearest Neumann crossing within the radius, else the sphere point.
- * Stops when d_Dirichlet < eps (or max_steps) with U = g at the closest
- * Dirichlet point.  D may be NULL. */
-/* Distance from each x (n x 2) to the closest silhouette vertex of the
- * Neumann segments `neu` as the walk on stars uses it (INFINITY if none). */
+ * boundary continues straight is no corner; 3D silhouettes: edges where the
+ * Neumann part ends and edges between non-coplanar triangles that x does not
+ * see both from the front or both from the back); direction uniform (block
+ * 4k), turned into the inward half space on the Neumann boundary; the next
+ * point is the nearest Neumann crossing within the radius, else the sphere
+ * point.  Neumann data h (NULL or kind 0: h = 0): every star adds one sample
+ * of its Neumann term (see neumann_term in oracle.c: an element within R
+ * drawn by measure with an exponential race, Philox tag | 32 | (k << 8) and
+ * block = element index; z uniform on it, block 4k + 1, tag | 64;
+ * |C| G^B(x, z) h(z), doubled on the Neumann boundary).  Stops when
+ * d_Dirichlet < eps (or max_steps) with U = g at the closest Dirichlet point
+ * plus the walk's Neumann terms.  D may be NULL. */
+/* Distance from each x (n x dim) to the closest silhouette of the Neumann
+ * elements `neu` as the walk on stars uses it (INFINITY if none). */
 void orc_silhouette_distances(const orc_scene* neu, int64_t n, const double* x, double* d);
-void orc_wost_walks(const orc_scene* dir, const orc_scene* neu, const orc_field* g, const orc_walk_params* p,
-                    int mode, int64_t n, const double* x, const double* nrm, const double* R0, const double* xbar,
-                    double* U, double* D, int32_t* steps);
+void orc_wost_walks(const orc_scene* dir, const orc_scene* neu, const orc_field* g, const orc_field* h,
+                    const orc_walk_params* p, int mode, int64_t n, const double* x, const double* nrm,
+                    const double* R0, const double* xbar, double* U, double* D, int32_t* steps);
 
 /* Cache candidates for a boundary with a Neumann part (2D): the offset
  * Dirichlet boundary (distance l to the Dirichlet part, inside `full`) and

@@ -508,6 +508,52 @@ def mixed_polygon(verts, neumann, counts, name="mixed"):
     return Scene(2, V, segs, name), part(~F, "dirichlet"), part(F, "neumann")
 
 
+def mixed_box(lo, hi, neumann, m, name="box"):
+    """The box [lo, hi] (3D) with each face split into an m x m grid of
+    squares, two triangles each, outward by the right-hand rule; face f in
+    (-x, +x, -y, +y, -z, +z) is Neumann where neumann[f].  Returns the whole
+    boundary and its Dirichlet and Neumann triangle sets, each with only the
+    vertices it uses."""
+    lo = np.asarray(lo, float)
+    hi = np.asarray(hi, float)
+    verts, tris, flags, index = [], [], [], {}
+
+    def vid(p):
+        key = tuple(np.round(p, 12))
+        if key not in index:
+            index[key] = len(verts)
+            verts.append(np.asarray(p, float))
+        return index[key]
+
+    for f in range(6):
+        a, side = f // 2, f % 2       # normal axis, 0 = low face, 1 = high face
+        b, c = (a + 1) % 3, (a + 2) % 3  # (b, c, a) is right-handed
+        for i in range(m):
+            for j in range(m):
+                corners = []
+                for di, dj in ((0, 0), (1, 0), (1, 1), (0, 1)):
+                    p = np.empty(3)
+                    p[a] = hi[a] if side else lo[a]
+                    p[b] = lo[b] + (hi[b] - lo[b]) * (i + di) / m
+                    p[c] = lo[c] + (hi[c] - lo[c]) * (j + dj) / m
+                    corners.append(vid(p))
+                q0, q1, q2, q3 = corners
+                # counter-clockwise in (b, c) has normal +a: reversed on low faces
+                for t in ((q0, q1, q2), (q0, q2, q3)):
+                    tris.append(t if side else (t[0], t[2], t[1]))
+                    flags.append(bool(neumann[f]))
+    V = np.array(verts)
+    P = np.array(tris, dtype=np.int32)
+    F = np.array(flags)
+
+    def part(mask, tag):
+        Q = P[mask]
+        used, inv = np.unique(Q.ravel(), return_inverse=True)
+        return Scene(3, V[used], inv.reshape(Q.shape).astype(np.int32), f"{name}_{tag}")
+
+    return Scene(3, V, P, name), part(~F, "dirichlet"), part(F, "neumann")
+
+
 def problem_c2_mixed(grid: int = 1024, n_cache: int = 262144, n_walks: int = 256) -> Problem:
     """Channel [0, 6] x [0, pi] (4096 segments): Dirichlet ends, Neumann walls
     (h = 0), Laplace, u = x + 0.5 e^(x - 6) cos y (zero flux through y = 0
