@@ -299,6 +299,8 @@ typedef struct {
                               point, so both read the data on the walk's own
                               side.  Refused (BVC_EUNSUPPORTED) by the batch
                               calls. */
+  bvc_field h;             /* Neumann data du/dn = h on the Neumann part (Eq. 1);
+                              read only by bvc_wost_walks (kind 0: h = 0). */
 } bvc_walk_params;
 
 /* Walk j of cache point i has id i*W + j (n_cache*W < 2^32).  Each walk takes
@@ -422,34 +424,51 @@ int bvc_gather_grad(int32_t dim, const bvc_cache_view* cache, const bvc_source_v
 /* Walk on stars: mixed Dirichlet / Neumann boundaries (Section 3.1)       */
 /* ---------------------------------------------------------------------- */
 /* The estimator the cache uses when part of the boundary is Neumann (walk on
- * stars; 2D, Neumann data h = 0, no source, no screening).  `dir` and `neu`
- * hold the Dirichlet and the Neumann segments of one counter-clockwise
- * boundary (two scenes over the same vertices).  Walk j of start point i has
+ * stars; 2D and 3D, Neumann data h, no source, no screening).  `dir` and
+ * `neu` hold the Dirichlet and the Neumann elements of one boundary (2D:
+ * counter-clockwise segments; 3D: triangles with outward normals by the
+ * right-hand rule; two scenes of one dimension).  Walk j of start point i has
  * id i*W + j (n*W < 2^32).  Each step: star radius R = max(eps, min(d_D,
  * d_S)), d_D the distance to the Dirichlet part and d_S to the closest
- * silhouette vertex of the Neumann part seen from the walk (a corner vertex
- * whose Neumann neighbours are not strictly on opposite sides of the line of
- * sight, within 1e-9 relative in FP64 and 1e-5 in FP32: both on one side, one
- * on it, or both on it at the fold of a thin Neumann curve; ends of Neumann
- * runs included; a vertex where the boundary continues
- * straight, within 1e-12 relative, is no corner); a direction uniform on the
- * circle (Philox block 4k
- * as walk on spheres), turned into the inward half circle on the Neumann
- * part; the walk moves to the nearest Neumann crossing within R, else to the
- * sphere; it stops when d_D < eps (or after max_steps, counted as capped)
- * with U = g(closest Dirichlet point), evaluated in FP64.
+ * silhouette of the Neumann part seen from the walk.  2D silhouettes: a
+ * corner vertex whose Neumann neighbours are not strictly on opposite sides
+ * of the line of sight (within 1e-9 relative in FP64 and 1e-5 in FP32: both
+ * on one side, one on it, or both on it at the fold of a thin Neumann curve),
+ * and the ends of Neumann runs; a vertex where the boundary continues
+ * straight, within 1e-12 relative, is no corner.  3D silhouettes: an edge
+ * where the Neumann part ends, and an edge between two triangles that are not
+ * coplanar unless the walk lies strictly in front of both planes or strictly
+ * behind both (same tolerances).  With Neumann data h (kind != 0) the step
+ * adds one sample of its star's Neumann term: every Neumann element within
+ * R (1 + 1e-9) (FP32: R (1 + 1e-5)) that the walk does not lie strictly
+ * behind is a candidate, of total measure |C| (elements beyond R add 0, so
+ * the superset keeps the estimate unbiased and holds the elements that touch
+ * the ball at a silhouette in both precisions); one is drawn with probability measure / |C| by an exponential
+ * race (key -ln(1 - U) / measure with U the FP64 uniform of Philox block =
+ * the element's original id, tag | 32 | (k << 8), k the step; smallest key),
+ * z uniform on it (block 4k + 1, tag | 64: 2D a + U1 (b - a), 3D barycentric
+ * (1 - s, s (1 - U2), s U2) with s = sqrt(U1)), and the sample is
+ * |C| G^B(x, z) h(z), doubled when the walk stands on the Neumann part, when
+ * |z - x| < R (else 0); G^B = ln(R/r)/(2 pi) in 2D, (1/r - 1/R)/(4 pi) in 3D.
+ * A direction uniform on the circle or sphere (Philox block 4k as walk on
+ * spheres), turned into the inward half space on the Neumann part; the walk
+ * moves to the nearest crossing within R of a Neumann element it leaves the
+ * domain through, else to the sphere; it stops when d_D < eps (or after
+ * max_steps, counted as capped) with U = g(closest Dirichlet point) plus its
+ * Neumann terms, g and h evaluated in FP64 (FP32 walks: in FP32).
  * mode 0: from offset Dirichlet cache points x with normals nrm, R0 = the
  *   distance to the whole boundary and xbar = the closest Dirichlet point:
  *   a first ball of radius R0 (no test at x), tag 1, and
- *   D = n . (2/R0) nu (W - c) (Eq. 7, c = g(xbar) with the control variate);
+ *   D = n . (dim/R0) nu (U - c) (Eq. 7, c = g(xbar) with the control variate);
  * mode 1: from interior points, tag 2 (D = 0);
  * mode 3: from points on the Neumann part with outward normals nrm, tag 2.
- * x, nrm, xbar: [2][n] FP64; R0 [n]; U, D (optional): [n*W] of dtype;
+ * x, nrm, xbar: [dim][n] FP64; R0 [n]; U, D (optional): [n*W] of dtype;
  * steps (optional) int32 [n*W].  workspace: caller-owned, at least
- * bvc_wost_workspace_bytes(neu) bytes (the Neumann run links, corner flags
- * and per-node normal cones that let the silhouette query skip BVH nodes
- * without corners facing the walk; built on the host and uploaded by the
- * call, which synchronises once).  counters: uint64[4] as the walks. */
+ * bvc_wost_workspace_bytes(neu) bytes (2D: the Neumann run links, corner
+ * flags and per-node normal cones that let the silhouette query skip BVH
+ * nodes without corners facing the walk; 3D: the triangle across each edge
+ * and the flat-edge bits; built on the host and uploaded by the call, which
+ * synchronises once).  counters: uint64[4] as the walks. */
 size_t bvc_wost_workspace_bytes(bvc_scene neu);
 int bvc_wost_walks(bvc_scene dir, bvc_scene neu, const bvc_walk_params* params, int32_t mode, int64_t n,
                    const double* x, const double* nrm, const double* R0, const double* xbar, void* U, void* D,

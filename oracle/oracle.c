@@ -1913,8 +1913,11 @@ static double neumann_hit(const orc_scene* neu, const double* x, const double* w
  * the Neumann part (the star is then a half ball at x) and 1 inside.  With
  * R at most the silhouette distance, that part is every point of a Neumann
  * element within R of x whose element x does not lie strictly behind.  One
- * sample: the elements within R of x (x not strictly behind) form the set C
- * of total measure |C|; one element is drawn with probability measure /
+ * sample: the elements within R (1 + 1e-9) of x (x not strictly behind) form
+ * the set C of total measure |C| (a superset of the elements that meet the
+ * ball: one beyond R draws a point outside it and adds 0, so the estimate
+ * stays unbiased; the margin keeps in C the elements that touch the ball
+ * where R is set by a silhouette, at distance R up to rounding); one element is drawn with probability measure /
  * |C| by an exponential race (key -ln(1 - U_e) / measure_e, the smallest
  * wins; U_e from Philox block e, the element's index, tag | 32 | (k << 8)),
  * which does not depend on the order the elements are visited in; z is
@@ -1931,7 +1934,7 @@ static double neumann_term(const orc_scene* neu, const orc_field* h, const orc_w
     const double* a = neu->V + dim * (int64_t)neu->P[dim * e];
     double c[3];
     int reg;
-    if (!(prim_dist2(neu, e, x, c, &reg) < R * R)) continue;
+    if (!(prim_dist2(neu, e, x, c, &reg) < R * R * (1 + 2e-9))) continue;
     double meas;
     if (dim == 2) {
       const double* b = neu->V + 2 * (int64_t)neu->P[2 * e + 1];

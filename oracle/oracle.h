@@ -270,7 +270,8 @@ void orc_gather_sigma(int dim, double sigma, int64_t K, const double* ex, int64_
  * of its Neumann term (see neumann_term in oracle.c: an element within R
  * drawn by measure with an exponential race, Philox tag | 32 | (k << 8) and
  * block = element index; z uniform on it, block 4k + 1, tag | 64;
- * |C| G^B(x, z) h(z), doubled on the Neumann boundary).  Stops when
+ * |C| G^B(x, z) h(z), doubled on the Neumann boundary; candidates within
+ * R (1 + 1e-9)).  Stops when
  * d_Dirichlet < eps (or max_steps) with U = g at the closest Dirichlet point
  * plus the walk's Neumann terms.  D may be NULL. */
 /* Distance from each x (n x dim) to the closest silhouette of the Neumann

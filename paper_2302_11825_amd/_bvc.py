@@ -47,7 +47,8 @@ class bvc_walk_params(C.Structure):
                 ("seed", C.c_uint64), ("batch", C.c_uint32), ("control_variate", C.c_int32),
                 ("dtype", C.c_int32), ("blocks", C.c_int32), ("g", bvc_field), ("f", bvc_field),
                 ("ev_begin", C.c_void_p), ("ev_end", C.c_void_p), ("sigma", C.c_double),
-                ("open_center", C.c_double * 3), ("open_radius", C.c_double), ("side_read", C.c_int32)]
+                ("open_center", C.c_double * 3), ("open_radius", C.c_double), ("side_read", C.c_int32),
+                ("h", bvc_field)]
 
 
 class bvc_cache_view(C.Structure):

@@ -140,11 +140,12 @@ def candidates_for(sc: Scene, n_target, l, sides, seed, pilot=65536):
 
 def walk_params(eps, n_walks, seed, g: DeviceField, f: Optional[DeviceField], dtype="f32", batch=0,
                 max_steps=1024, control_variate=True, blocks=0, sigma=0.0, open_sphere=None,
-                side_read=False) -> B.bvc_walk_params:
+                side_read=False, h: Optional[DeviceField] = None) -> B.bvc_walk_params:
     """open_sphere = (centre, radius) of a sphere enclosing the scene: an open
     3D domain (Appendix B), whose walks escape to infinity or re-enter.
     side_read: the side rule of double-sided data (Appendix B); off, walks
-    read g at the closest boundary point (Section 3.1)."""
+    read g at the closest boundary point (Section 3.1).  h: Neumann data of
+    the walk on stars (None: h = 0)."""
     p = B.bvc_walk_params()
     p.side_read = int(bool(side_read))
     p.sigma = float(sigma)
@@ -163,6 +164,10 @@ def walk_params(eps, n_walks, seed, g: DeviceField, f: Optional[DeviceField], dt
     p.blocks = int(blocks)
     p.g = g.c()
     p.f = f.c() if f is not None else B.make_field(0, None, [])
+    p.h = h.c() if h is not None else B.make_field(0, None, [])
+    # the struct holds raw device pointers to the fields' coefficients: keep
+    # the fields alive as long as the struct is
+    p._fields_keep = (g, f, h)
     return p
 
 
