@@ -83,6 +83,12 @@ def parse():
     ap.add_argument("--clamp-c", type=float, default=20.0, help="c2clamp: bound c of dG/dn (Eq. 9)")
     ap.add_argument("--clamp-rays", type=int, default=64, help="c2clamp: rays per corrected point")
     ap.add_argument("--clamp-hits", type=int, default=4, help="c2clamp: contributing crossings kept per ray")
+    ap.add_argument("--grad-band", default="1.5,4",
+                    help="c2: also solve once per width with pointwise grad u within that many offsets l of the "
+                         "boundary (comma-separated; empty: skip)")
+    ap.add_argument("--wide-band", default="1.25,2",
+                    help="also solve once per width with pointwise walks (u, grad u) within that many offsets l "
+                         "(comma-separated; empty: skip)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="copy this many MiB device-to-device before timing (HBM counter calibration)")
     return ap.parse_args()
@@ -94,6 +100,97 @@ def log(msg):
 
 def rmse(a, b):
     return float(np.sqrt(np.mean((a - b) ** 2))) if len(a) else float("nan")
+
+
+# bins of the distance to the boundary, in units of the offset l
+BIN_EDGES = (0.0, 1.0, 1.25, 1.5, 2.0, 3.0, 4.0, 8.0, math.inf)
+
+
+def error_by_distance(l, dist, u, truth, g=None, gtrue=None, pointwise=None):
+    """RMSE of u (and of grad u, as the root of the mean squared vector
+    error) against the closed form in bins of d / l, d the distance to the
+    boundary; `pointwise` marks the points whose value (u in [0, 1), grad u
+    wherever set) came from pointwise walks."""
+    out = []
+    r = dist / l
+    for lo, hi in zip(BIN_EDGES[:-1], BIN_EDGES[1:]):
+        m = (r >= lo) & (r < hi)
+        row = {"d_over_l": [lo, hi if math.isfinite(hi) else None], "points": int(m.sum()),
+               "rmse_u": rmse(u[m], truth[m])}
+        if g is not None:
+            row["rmse_grad"] = float(np.sqrt(np.mean(np.sum((g[m] - gtrue[m]) ** 2, 1)))) if m.any() else float("nan")
+        if pointwise is not None:
+            row["pointwise_points"] = int(pointwise[m].sum())
+        out.append(row)
+    return out
+
+
+def band_options(args, pl, prob, prep, dtype, with_grad, base):
+    """Cost and effect of two wider bands next to the timed configuration,
+    each solved once more (same cache, sources, streams and points): grad u
+    from pointwise walks within args.grad_band l (u still gathered), and
+    pointwise u and grad u within args.wide_band l.  `base` holds the sampled
+    points' truth of the timed run (indices into the evaluation points)."""
+    import torch
+
+    l = prob.offset
+    out = {}
+    opts = []
+    if with_grad:
+        opts += [(f"grad_band_{w:g}l", "grad_band", dict(grad_band=w * l)) for w in widths(args.grad_band)]
+    opts += [(f"wide_band_{w:g}l", "wide_band", dict(band=w * l)) for w in widths(args.wide_band)]
+    for name, key, kw in opts:
+        p2 = pl.Prepared(prob, dtype=dtype, n_cand=prep.n_cand, **kw)
+        pl.solve(p2, batch=args.steps - 1, with_grad=with_grad)
+        torch.cuda.synchronize()
+        watch = pl.Stopwatch()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s2 = pl.solve(p2, batch=args.steps - 1, with_grad=with_grad, watch=watch)
+        e1.record()
+        torch.cuda.synchronize()
+        u, g, pw = gather_values(p2, s2, with_grad)
+        idx = base["idx"]
+        row = {"width_over_l": kw.get("grad_band", kw.get("band")) / l, "step_ms": round(e0.elapsed_time(e1), 4),
+               "stage_ms": {k: round(float(np.mean(v)), 4) for k, v in watch.totals_ms().items()
+                            if not k.startswith("k_")},
+               "pointwise_points": int(p2.n_gb if key == "grad_band" else p2.n_band),
+               "walks_per_point": int(p2.gb_walks if key == "grad_band" else prob.n_walks),
+               "by_distance": error_by_distance(l, base["dist"], u[idx], base["truth"],
+                                                g[idx] if g is not None else None, base.get("gtrue"), pw[idx])}
+        row["rmse_u_all"] = rmse(u[idx], base["truth"])
+        if g is not None:
+            row["rmse_grad_all"] = float(np.sqrt(np.mean(np.sum((g[idx] - base["gtrue"]) ** 2, 1))))
+        out[name] = row
+        log(f"{name}: {row['pointwise_points']} points, step {row['step_ms']} ms")
+        del p2, s2
+    return out
+
+
+def widths(spec):
+    return [float(w) for w in str(spec).split(",") if w.strip() and float(w) > 1]
+
+
+def gather_values(prep, sol, with_grad):
+    """u (and grad u) of one solve at every evaluation point (NaN outside),
+    and a mask of the points whose grad u came from pointwise walks."""
+    n = prep.eval64.shape[1]
+    d = prep.sc.dim
+    idx_i = prep.idx_int[: prep.n_int].cpu().numpy().astype(np.int64)
+    idx_b = prep.idx_band[: prep.n_band].cpu().numpy().astype(np.int64)
+    u = np.full(n, np.nan)
+    u[idx_i] = sol.u_int[: prep.n_int].double().cpu().numpy()
+    u[idx_b] = sol.u_band[: prep.n_band].double().cpu().numpy()
+    g = None
+    pw = np.zeros(n, bool)
+    pw[idx_b] = True
+    if with_grad:
+        g = np.full((n, d), np.nan)
+        g[idx_i] = sol.g_int[:, : prep.n_int].double().cpu().numpy().T
+        g[idx_b] = sol.g_band[:, : prep.n_band].double().cpu().numpy().T
+        if getattr(prep, "n_gb", 0):
+            pw[idx_i[prep.gb_pos[: prep.n_gb].cpu().numpy().astype(np.int64)]] = True
+    return u, g, pw
 
 
 def measured_traffic(kernel, workload, sources):
@@ -335,12 +432,26 @@ def run_workload(args, which):
            "band": rmse(u_b, truth_b), "rms_true": float(np.sqrt(np.mean(truth_i**2)))}
     if dim == 3:
         err["sample"] = f"every {stride}th gathered point ({sel.size}) and every band point"
+    # by distance to the boundary: the sampled gathered points and every band
+    # point (2D: grad u against finite differences of the closed form)
+    base = {"idx": np.concatenate([idx_i[sel], idx_b]).astype(np.int64),
+            "dist": np.concatenate([dist_i, prep.dist[idx_b].cpu().numpy() if prep.n_band else np.zeros(0)]),
+            "truth": np.concatenate([truth_i, truth_b])}
+    u_all, g_all, pw_all = gather_values(prep, sol, with_grad)
     if with_grad:
-        grad_true = wl.field_grad_fd(prob.truth, pts_i[::16], 1e-6)
-        g_i = sol.g_int[:, : prep.n_int].double().cpu().numpy().T[sel][::16]
-        gerr = np.sum((g_i - grad_true) ** 2, axis=1)
-        err["grad"] = float(np.sqrt(np.mean(gerr)))
-        err["grad_d_ge_0.05"] = float(np.sqrt(np.mean(gerr[far[::16]]))) if far[::16].any() else float("nan")
+        base["gtrue"] = wl.field_grad_fd(prob.truth, prob.eval_x[base["idx"]], 1e-6)
+        gerr = np.sum((g_all[base["idx"]] - base["gtrue"]) ** 2, axis=1)
+        gi = gerr[: sel.size]
+        err["grad"] = float(np.sqrt(np.mean(gi)))
+        err["grad_d_ge_0.05"] = float(np.sqrt(np.mean(gi[far]))) if far.any() else float("nan")
+        err["grad_band"] = float(np.sqrt(np.mean(gerr[sel.size:]))) if prep.n_band else float("nan")
+    err["by_distance"] = error_by_distance(prob.offset, base["dist"], u_all[base["idx"]], base["truth"],
+                                           g_all[base["idx"]] if with_grad else None, base.get("gtrue"),
+                                           pw_all[base["idx"]])
+    err["by_distance_note"] = ("d_over_l: bin of the distance to the boundary in offsets l; [0, 1) are the band "
+                               "points (pointwise walks), the rest gathered")
+    if widths(args.grad_band) or widths(args.wide_band):
+        err["band_options"] = band_options(args, pl, prob, prep, dtype, with_grad, base)
 
     # VALU roofline of the gather (one launch per step)
     gather_ms = stages["gather"]

@@ -255,7 +255,14 @@ class Prepared:
     """Per-scene state reused across solves: device scene, fields, classified
     evaluation points and the candidate count of the cache sampler."""
 
-    def __init__(self, problem, dtype=None, n_cand=None, device="cuda", eval_x=None, clamp=None, near_tau=None):
+    def __init__(self, problem, dtype=None, n_cand=None, device="cuda", eval_x=None, clamp=None, near_tau=None,
+                 band=None, grad_band=None, grad_band_walks=None):
+        # points within `band` of the boundary take pointwise walks for u and
+        # grad u (the band of Algorithm 1 is the offset l; a wider band trades
+        # walks for the gather's error next to the cache surface)
+        self.band = float(problem.offset if band is None else band)
+        if self.band < problem.offset:
+            raise ValueError(f"band {self.band} is narrower than the offset {problem.offset}")
         self.p = problem
         self.dtype = dtype or problem.precision
         self.sc = Scene(problem.scene, device)
@@ -266,7 +273,7 @@ class Prepared:
         ex = problem.eval_x if eval_x is None else eval_x
         self.eval64 = torch.from_numpy(np.ascontiguousarray(ex.T)).to(device)
         n = self.eval64.shape[1]
-        self.cls, self.dist = classify(self.sc, self.eval64, problem.offset)
+        self.cls, self.dist = classify(self.sc, self.eval64, self.band)
         self.idx_int, self.n_int = self.sc.compact(self.cls, 1)
         self.idx_band, self.n_band = self.sc.compact(self.cls, 2)
         T = DT[self.dtype]
@@ -285,6 +292,31 @@ class Prepared:
         self.clamp = None
         if clamp is not None:
             self._prepare_clamp(clamp, device)
+        self._prepare_grad_band(grad_band, grad_band_walks, device)
+
+    def _prepare_grad_band(self, width, walks, device):
+        """Gathered points within `width` of the boundary take grad u from
+        pointwise walks (the gradient estimate of Eq. 7 at the point itself)
+        in place of the gathered gradient, whose kernels grow like the inverse
+        distance to the cache surface squared (2D) or cubed (3D); u stays the
+        gathered value.  Found here once: their positions among the gathered
+        points and their coordinates in the walk dtype."""
+        self.grad_band = 0.0
+        self.n_gb = 0
+        self.gb_pos = None
+        self.x_gb = None
+        self.gb_walks = int(walks or self.p.n_walks)
+        if width is None or width <= self.band or self.n_int == 0:
+            return
+        d, n = self.sc.dim, self.eval64.shape[1]
+        self.grad_band = float(width)
+        x64 = take(self.eval64, self.idx_int, self.n_int, d, n, torch.float64)
+        cls, _ = classify(self.sc, x64, self.grad_band)
+        pos, self.n_gb = self.sc.compact(cls[: self.n_int], 2)
+        self.gb_pos = pos
+        if self.n_gb:
+            self.x_gb = take(self.eval64, self.idx_int[pos[: self.n_gb].to(torch.int64)].contiguous(), self.n_gb, d,
+                             n, DT[self.dtype])
 
     def _prepare_clamp(self, clamp, device):
         """Clamped gather with bias correction (Section 3.3, Eq. 8).  clamp:
@@ -462,6 +494,7 @@ def wost(prep: MixedPrepared, params: B.bvc_walk_params, mode, n, x, nrm=None, R
 
 
 NEUMANN_BATCH_BIT = 0x80000000  # batch word of the walks from Neumann cache points
+GRAD_BAND_BATCH_BIT = 0x40000000  # batch word of the pointwise gradient walks near the boundary
 
 
 def solve_mixed(prep: MixedPrepared, batch=0, with_grad=True, watch=None) -> Solution:
@@ -774,6 +807,16 @@ def solve(prep: Prepared, batch=0, with_grad=True, n_walks_band=None, records=Fa
     watch.kernel("k_walks_band", wpb)
     with watch.stage("band_walks"):
         u_band, g_band, pwc = pointwise(sc, wpb, prep.x_band[:, :nb] if nb else prep.x_band[:, :0], with_grad)
+    gb = None
+    if with_grad and prep.n_gb:
+        # pointwise gradients near the boundary replace the gathered ones
+        wpg = walk_params(p.eps, prep.gb_walks, p.seed_walks, prep.g, prep.f, dt, batch | GRAD_BAND_BATCH_BIT,
+                          sigma=p.sigma, open_sphere=osph, side_read=p.side_read)
+        watch.kernel("k_walks_grad_band", wpg)
+        with watch.stage("grad_band_walks"):
+            _, gg, gbc = pointwise(sc, wpg, prep.x_gb, True)
+            B.bvc_scatter(B.dtype_code(T), prep.n_gb, prep.gb_pos, d, gg.shape[1], gg, g_int.shape[1], g_int)
+        gb = dict(n=prep.n_gb, width=prep.grad_band, walks=prep.gb_walks, counters=gbc)
     if cl:
         # the second integral of Eq. 8 at the gathered points near the offset
         # boundary, on a second stream (default priority) so that it overlaps
@@ -788,4 +831,5 @@ def solve(prep: Prepared, batch=0, with_grad=True, n_walks_band=None, records=Fa
                                        cl["ws"], cl["counters"])
         main.wait_stream(side)
     return Solution(prep.idx_int, n_int, prep.idx_band, nb, u_int, g_int, u_band, g_band, cache, uhat, dudn,
-                    counters, pwc, extra=dict(U=U, D=D, a=a, b=b, cview=cview, sview=sview, rec=rec, near=near))
+                    counters, pwc, extra=dict(U=U, D=D, a=a, b=b, cview=cview, sview=sview, rec=rec, near=near,
+                                              grad_band=gb))

@@ -102,3 +102,11 @@ def test_argument_validation_without_gpu():
     assert L.bvc_reduce_walks(1, 0, 0, None, None, None, None, None, 0, None, None, None) == -1
     assert L.bvc_cache_walks(None, None, 0, None, None, None, None, None, None, None, None, None, None,
                              None) == -1
+
+
+def test_band_narrower_than_offset_is_rejected():
+    from paper_2302_11825_amd import pipeline as pl
+
+    prob = wl.problem_c1()
+    with pytest.raises(ValueError, match="narrower than the offset"):
+        pl.Prepared(prob, band=0.5 * prob.offset, device="cpu")
