@@ -80,6 +80,7 @@ def parse():
                     help="c3 (headline, with c2 under the key 'c2') and c2 print the benchmark line; the others "
                          "print their own measurement lines")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes (no autotuning)")
+    ap.add_argument("--no-graph", action="store_true", help="skip the graph-captured replay of the step")
     ap.add_argument("--clamp-c", type=float, default=20.0, help="c2clamp: bound c of dG/dn (Eq. 9)")
     ap.add_argument("--clamp-rays", type=int, default=64, help="c2clamp: rays per corrected point")
     ap.add_argument("--clamp-hits", type=int, default=4, help="c2clamp: contributing crossings kept per ray")
@@ -354,6 +355,7 @@ def timed_steps(pl, prep, args, with_grad):
     torch.cuda.synchronize()
     watch = pl.Stopwatch()
     counts = []
+    cache_counts = []
     sol = None
     gc.collect()
     gc.disable()
@@ -366,13 +368,49 @@ def timed_steps(pl, prep, args, with_grad):
         sol = None
         sol = pl.solve(prep, batch=s, with_grad=with_grad, watch=watch)
         counts.append((sol.counters, sol.pw_counters))
+        cache_counts.append(sol.cache.n_dev)
     e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     gc.enable()
     ms_step = e0.elapsed_time(e1) / args.steps
     timers = {k: float(np.mean(v)) for k, v in watch.totals_ms().items()}
+    # every step's accepted cache count fitted its capacity
+    worst = max(int(c[0]) for c in cache_counts) if cache_counts else 0
+    if worst > prep.n_cap:
+        raise RuntimeError(f"cache overflow in a timed step: {worst} > {prep.n_cap}")
     return sol, counts, ms_step, wall, timers
+
+
+def captured_step(pl, prep, args, with_grad):
+    """The step captured once in a HIP graph (it has no host synchronisation:
+    the cache count stays on the device) and replayed args.steps times
+    between two events.  The graph holds the kernel arguments of one batch,
+    so every replay redoes that batch's work."""
+    import torch
+
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        pl.solve(prep, batch=0, with_grad=with_grad)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph):
+        sol = pl.solve(prep, batch=0, with_grad=with_grad)
+    graph.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    out = {"ms_per_step": round(ms, 4), "replays": args.steps, "cache_points": sol.cache.n}
+    del graph, sol
+    torch.cuda.empty_cache()
+    return out
 
 
 def run_workload(args, which):
@@ -400,6 +438,9 @@ def run_workload(args, which):
         torch.cuda.synchronize()
         del src, dst
     sol, counts, ms_step, wall, timers = timed_steps(pl, prep, args, with_grad)
+    captured = None if args.no_graph else captured_step(pl, prep, args, with_grad)
+    if captured:
+        log(f"{which} captured step {captured['ms_per_step']} ms (eager {ms_step:.3f} ms)")
     kernels = {k: v for k, v in timers.items() if k.startswith("k_")}
     stages = {k: v for k, v in timers.items() if not k.startswith("k_")}
     log(f"{which} timed {args.steps} steps: {ms_step:.2f} ms/step (wall {wall:.2f}s) {stages}")
@@ -515,6 +556,7 @@ def run_workload(args, which):
 
     config = {"workload": prob.name, "primitives": int(prob.scene.prims.shape[0]),
               "cache_target": prob.n_cache, "cache_candidates": prep.n_cand, "cache_points": sol.cache.n,
+              "cache_capacity": prep.n_cap,
               "walks_per_point": prob.n_walks, "interior_points": prep.n_int, "band_points": prep.n_band,
               "eps": prob.eps, "offset_l": prob.offset}
     if dim == 2:
@@ -542,6 +584,7 @@ def run_workload(args, which):
         "roofline_other_walks": {"hbm": other, "valu": other_valu},
         "roofline_gather": roofline_gather,
         "near_field": near_field,
+        "captured_step": captured,
         "cpu_baseline": cpu,
         "setup_s": setup_s,
         "tuned_shapes": tuned,

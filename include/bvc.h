@@ -238,6 +238,17 @@ int bvc_compact(int64_t n, const int32_t* flags, int32_t want, int32_t* idx, int
  * FP64 -> FP32. */
 int bvc_take(int32_t dtype_in, int32_t dtype_out, int64_t n_idx, const int32_t* idx,
              int32_t rows, int64_t ld_in, const void* in, int64_t ld_out, void* out, void* stream);
+/* bvc_compact without the readback: the count is written to the device
+ * int64 *count (zero when n == 0) and nothing synchronises, so that a step
+ * can be enqueued (and captured in a HIP graph) before its cache size is
+ * known; idx holds the ascending k with flags[k] == want in [0, *count) and
+ * is not written beyond. */
+int bvc_compact_count(int64_t n, const int32_t* flags, int32_t want, int32_t* idx, int32_t* scratch,
+                      int64_t* count, void* stream);
+/* bvc_take for the first min(n_cap, *count) entries, count a device int64
+ * (entries beyond it are left untouched, and idx is read only below it). */
+int bvc_take_count(int32_t dtype_in, int32_t dtype_out, int64_t n_cap, const int64_t* count, const int32_t* idx,
+                   int32_t rows, int64_t ld_in, const void* in, int64_t ld_out, void* out, void* stream);
 /* out[idx[q]] = in[q] (scatter back; dtype of in and out equal). */
 int bvc_scatter(int32_t dtype, int64_t n_idx, const int32_t* idx, int32_t rows, int64_t ld_in,
                 const void* in, int64_t ld_out, void* out, void* stream);
@@ -301,6 +312,14 @@ typedef struct {
                               calls. */
   bvc_field h;             /* Neumann data du/dn = h on the Neumann part (Eq. 1);
                               read only by bvc_wost_walks (kind 0: h = 0). */
+  const int64_t* n_dev;    /* bvc_cache_walks and bvc_tune_walks only (NULL
+                              elsewhere, else BVC_EUNSUPPORTED): device int64 count of cache
+                              points, read by the kernels; the call walks the
+                              first min(n_cache, *n_dev) points and n_cache is
+                              the capacity the arrays are laid out for (record
+                              strides n_cache*W).  Lets a step run without
+                              reading its cache size back (see
+                              bvc_compact_count).  NULL: n_cache points. */
 } bvc_walk_params;
 
 /* Walk j of cache point i has id i*W + j (n_cache*W < 2^32).  Each walk takes
@@ -329,6 +348,13 @@ int bvc_cache_walks(bvc_scene scene, const bvc_walk_params* params, int64_t n_ca
 int bvc_reduce_walks(int64_t n_cache, int32_t W, int32_t dtype_in, const void* U, const void* D,
                      const double* w, double* uhat, double* dudn, int32_t dtype_out, void* a,
                      void* b, void* stream);
+/* The same means for the first min(n_cap, *count) points, count a device
+ * int64 (bvc_compact_count); point i's walks are U, D [i*W, i*W + W).
+ * Entries at and beyond the count are left untouched.  No host
+ * synchronisation. */
+int bvc_reduce_walks_count(int64_t n_cap, const int64_t* count, int32_t W, int32_t dtype_in, const void* U,
+                           const void* D, const double* w, double* uhat, double* dudn, int32_t dtype_out,
+                           void* a, void* b, void* stream);
 
 /* Pointwise walk on spheres at n points x ([dim][n] of params->dtype): the
  * estimator the paper uses within l of the boundary (Section 3.2) and the
@@ -379,6 +405,11 @@ typedef struct {
   const void* nrm; /* [dim][n] unit outward normals */
   const void* a;   /* [n] u-hat_i / p(z_i) / N */
   const void* b;   /* [n] du/dn-hat_i / p(z_i) / N */
+  const int64_t* n_dev; /* NULL, or a device int64 count: the gather sums the
+                           first min(n, *n_dev) entries, n being the capacity
+                           (leading dimension) of x and nrm.  Taken by
+                           bvc_gather_u, bvc_gather_grad and bvc_tune_gather;
+                           the adjoint refuses it (BVC_EUNSUPPORTED). */
 } bvc_cache_view;
 
 typedef struct {

@@ -48,12 +48,12 @@ class bvc_walk_params(C.Structure):
                 ("dtype", C.c_int32), ("blocks", C.c_int32), ("g", bvc_field), ("f", bvc_field),
                 ("ev_begin", C.c_void_p), ("ev_end", C.c_void_p), ("sigma", C.c_double),
                 ("open_center", C.c_double * 3), ("open_radius", C.c_double), ("side_read", C.c_int32),
-                ("h", bvc_field)]
+                ("h", bvc_field), ("n_dev", C.c_void_p)]
 
 
 class bvc_cache_view(C.Structure):
     _fields_ = [("n", C.c_int64), ("dtype", C.c_int32), ("x", C.c_void_p), ("nrm", C.c_void_p),
-                ("a", C.c_void_p), ("b", C.c_void_p)]
+                ("a", C.c_void_p), ("b", C.c_void_p), ("n_dev", C.c_void_p)]
 
 
 class bvc_source_view(C.Structure):
@@ -100,10 +100,14 @@ _SIGS = {
     "bvc_classify": [_vp, C.c_int64, _vp, C.c_double, _vp, _vp, _vp],
     "bvc_compact": [C.c_int64, _vp, C.c_int32, _vp, _vp, _P(C.c_int64), _vp],
     "bvc_take": [C.c_int32, C.c_int32, C.c_int64, _vp, C.c_int32, C.c_int64, _vp, C.c_int64, _vp, _vp],
+    "bvc_compact_count": [C.c_int64, _vp, C.c_int32, _vp, _vp, _vp, _vp],
+    "bvc_take_count": [C.c_int32, C.c_int32, C.c_int64, _vp, _vp, C.c_int32, C.c_int64, _vp, C.c_int64, _vp, _vp],
     "bvc_scatter": [C.c_int32, C.c_int64, _vp, C.c_int32, C.c_int64, _vp, C.c_int64, _vp, _vp],
     "bvc_cache_walks": [_vp, _P(bvc_walk_params), C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                         _vp, _vp],
     "bvc_reduce_walks": [C.c_int64, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp, _vp, C.c_int32, _vp, _vp, _vp],
+    "bvc_reduce_walks_count": [C.c_int64, _vp, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp, _vp, C.c_int32, _vp, _vp,
+                               _vp],
     "bvc_pointwise_wos": [_vp, _P(bvc_walk_params), C.c_int64, _vp, _vp, _vp, _vp, C.c_size_t, _vp, _vp, _vp,
                           _vp],
     "bvc_pointwise_wos_noalloc": [_vp, _P(bvc_walk_params), C.c_int64, _vp, _vp, _vp, _vp, _vp],
@@ -324,6 +328,17 @@ def bvc_compact(n, flags, want, idx, scratch, stream=None) -> int:
     return cnt.value
 
 
+def bvc_compact_count(n, flags, want, idx, scratch, count, stream=None):
+    """Compaction with the count left on the device (int64 tensor `count`)."""
+    _check(_L.bvc_compact_count(n, ptr(flags), want, ptr(idx), ptr(scratch), ptr(count), stream_ptr(stream)),
+           "bvc_compact_count")
+
+
+def bvc_take_count(dtype_in, dtype_out, n_cap, count, idx, rows, ld_in, src, ld_out, out, stream=None):
+    _check(_L.bvc_take_count(dtype_in, dtype_out, n_cap, ptr(count), ptr(idx), rows, ld_in, ptr(src), ld_out,
+                             ptr(out), stream_ptr(stream)), "bvc_take_count")
+
+
 def bvc_take(dtype_in, dtype_out, n_idx, idx, rows, ld_in, src, ld_out, out, stream=None):
     _check(_L.bvc_take(dtype_in, dtype_out, n_idx, ptr(idx), rows, ld_in, ptr(src), ld_out, ptr(out),
                        stream_ptr(stream)), "bvc_take")
@@ -344,6 +359,11 @@ def bvc_cache_walks(scene, params: bvc_walk_params, n_cache, x, nrm, R0, xbar, U
 def bvc_reduce_walks(n_cache, W, dtype_in, U, D, w, uhat, dudn, dtype_out, a, b, stream=None):
     _check(_L.bvc_reduce_walks(n_cache, W, dtype_in, ptr(U), ptr(D), ptr(w), ptr(uhat), ptr(dudn), dtype_out,
                                ptr(a), ptr(b), stream_ptr(stream)), "bvc_reduce_walks")
+
+
+def bvc_reduce_walks_count(n_cap, count, W, dtype_in, U, D, w, uhat, dudn, dtype_out, a, b, stream=None):
+    _check(_L.bvc_reduce_walks_count(n_cap, ptr(count), W, dtype_in, ptr(U), ptr(D), ptr(w), ptr(uhat), ptr(dudn),
+                                     dtype_out, ptr(a), ptr(b), stream_ptr(stream)), "bvc_reduce_walks_count")
 
 
 def bvc_pointwise_workspace_bytes(dim, n, W, dtype, with_grad) -> int:
@@ -371,6 +391,8 @@ def _views(cache, sources):
     cv.n, cv.dtype = cache["n"], cache["dtype"]
     cv.x, cv.nrm, cv.a, cv.b = (t.data_ptr() if t is not None else None
                                 for t in (cache["x"], cache["nrm"], cache["a"], cache["b"]))
+    n_dev = cache.get("n_dev")
+    cv.n_dev = n_dev.data_ptr() if n_dev is not None else None
     sv = None
     if sources is not None:
         sv = bvc_source_view()

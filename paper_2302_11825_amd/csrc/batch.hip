@@ -46,6 +46,7 @@ int plan_sizes(const bvc_batch_item* items, int n, int& dim, uint64_t& walks, in
     if (d != dim) return fail(BVC_EINVAL, "all scenes of a batch must have the same dimension");
     const bvc_walk_params& p = it.walk;
     if (p.dtype != BVC_F32) return fail(BVC_EUNSUPPORTED, "batched walks run in FP32");
+    if (p.n_dev) return fail(BVC_EUNSUPPORTED, "batched walks take host counts");
     if (!(p.eps > 0) || p.max_steps < 1 || p.n_walks < 1) return fail(BVC_EINVAL, "bad walk parameters");
     rc = check_field(p.g, d, "g");
     if (rc) return rc;

@@ -70,7 +70,15 @@ struct GatherArgs {
   // field.
   T clampc;
   double clamp64;
+  // device count of cache entries (<= n_cache, the arrays' leading
+  // dimension), or null for n_cache
+  const int64_t* n_dev;
 };
+
+template <typename T>
+__device__ __forceinline__ int64_t cache_count(const GatherArgs<T>& a) {
+  return a.n_dev ? std::min<int64_t>(a.n_cache, *a.n_dev) : a.n_cache;
+}
 
 // Entry layout in LDS (8 values): 2D boundary {y0, y1, 2 na0, 2 na1, 2 bl, bg,
 // na0, na1}, 3D boundary {y0, y1, y2, bl, na0, na1, na2, -}; sources
@@ -177,8 +185,9 @@ __device__ __forceinline__ void gather_block(const GatherArgs<T>& a, int64_t blo
   };
 
   // ---- boundary samples (Eqs. 3 and 5) ----
-  for (int64_t t0 = 0; t0 < a.n_cache; t0 += kTile) {
-    const int cnt = (int)std::min<int64_t>(kTile, a.n_cache - t0);
+  const int64_t nc = cache_count(a);
+  for (int64_t t0 = 0; t0 < nc; t0 += kTile) {
+    const int cnt = (int)std::min<int64_t>(kTile, nc - t0);
     if (tid < cnt) {
       const int64_t i = t0 + tid;
       T y[D], nn[D];
@@ -420,8 +429,9 @@ __global__ __launch_bounds__(kGBlock) void k_gather_screened3(GatherArgs<T> a, d
       ag[c] = T(0);
     }
   };
-  for (int64_t t0 = 0; t0 < a.n_cache; t0 += kTile) {
-    const int cnt = (int)std::min<int64_t>(kTile, a.n_cache - t0);
+  const int64_t nc = cache_count(a);
+  for (int64_t t0 = 0; t0 < nc; t0 += kTile) {
+    const int cnt = (int)std::min<int64_t>(kTile, nc - t0);
     if (tid < cnt) {
       const int64_t i = t0 + tid;
       T* e = ent + tid * 8;
@@ -525,8 +535,9 @@ __global__ __launch_bounds__(kGBlock) void k_gather_screened2(GatherArgs<T> a, d
       ag[c] = T(0);
     }
   };
-  for (int64_t t0 = 0; t0 < a.n_cache; t0 += kTile) {
-    const int cnt = (int)std::min<int64_t>(kTile, a.n_cache - t0);
+  const int64_t nc = cache_count(a);
+  for (int64_t t0 = 0; t0 < nc; t0 += kTile) {
+    const int cnt = (int)std::min<int64_t>(kTile, nc - t0);
     if (tid < cnt) {
       const int64_t i = t0 + tid;
       T* e = ent + tid * 8;
@@ -1129,6 +1140,7 @@ int gather_impl(int dim, const bvc_cache_view* c, const bvc_source_view* s, int6
   }
   a.clampc = (T)clamp_c;
   a.clamp64 = clamp_c;
+  a.n_dev = c->n_dev;
   const bool clamp = clamp_c > 0.0;
   if (sigma > 0.0) {
     const int blocks = (int)((n_eval + kGBlock - 1) / kGBlock);
@@ -1302,6 +1314,7 @@ int bvc_gather_backward(int32_t dim, const bvc_cache_view* cache, const bvc_sour
   if (dim != 2 && dim != 3) return fail(BVC_EINVAL, "dim must be 2 or 3");
   int rc = check_view(cache, dim);
   if (rc) return rc;
+  if (cache->n_dev) return fail(BVC_EUNSUPPORTED, "the gather adjoint takes a host cache count");
   rc = check_sources(sources, cache->dtype);
   if (rc) return rc;
   if (n_eval < 0) return fail(BVC_EINVAL, "n_eval must be >= 0");

@@ -453,10 +453,12 @@ __global__ __launch_bounds__(kBlock) void k_compact_scatter(int64_t n, const int
 }
 
 template <typename Ti, typename To>
-__global__ void k_take(int64_t n_idx, const int* idx, int rows, int64_t ld_in, const Ti* in, int64_t ld_out,
-                       To* out) {
+__global__ void k_take(int64_t n_idx, const int64_t* count, const int* idx, int rows, int64_t ld_in, const Ti* in,
+                       int64_t ld_out, To* out) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= n_idx) return;
+  // a device-resident count bounds the entries (the rest stay untouched)
+  const int64_t n = count ? std::min<int64_t>(n_idx, *count) : n_idx;
+  if (q >= n) return;
   const int64_t src = idx ? idx[q] : q;
   for (int r = 0; r < rows; ++r) out[r * ld_out + q] = (To)in[r * ld_in + src];
 }
@@ -500,6 +502,32 @@ int check_field(const bvc_field& f, int dim, const char* name) {
   if (f.kind == 6 && f.n_coef < 1) return fail(BVC_EINVAL, std::string(name) + ": Fourier series is empty");
   return BVC_OK;
 }
+
+namespace {
+int take_impl(int32_t dti, int32_t dto, int64_t n_idx, const int64_t* count, const int32_t* idx, int32_t rows,
+              int64_t ld_in, const void* in, int64_t ld_out, void* out, void* stream) {
+  if ((dti != BVC_F32 && dti != BVC_F64) || (dto != BVC_F32 && dto != BVC_F64))
+    return fail(BVC_EINVAL, "dtype must be F32 or F64");
+  if (n_idx < 0 || rows < 0 || ld_in < 0 || ld_out < n_idx) return fail(BVC_EINVAL, "bad sizes");
+  if (n_idx == 0 || rows == 0) return BVC_OK;
+  if (!in || !out) return fail(BVC_EINVAL, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  const int blocks = (int)((n_idx + kBlock - 1) / kBlock);
+  if (dti == BVC_F64 && dto == BVC_F64)
+    hipLaunchKernelGGL((k_take<double, double>), dim3(blocks), dim3(kBlock), 0, st, n_idx, count, idx, rows, ld_in,
+                       (const double*)in, ld_out, (double*)out);
+  else if (dti == BVC_F64 && dto == BVC_F32)
+    hipLaunchKernelGGL((k_take<double, float>), dim3(blocks), dim3(kBlock), 0, st, n_idx, count, idx, rows, ld_in,
+                       (const double*)in, ld_out, (float*)out);
+  else if (dti == BVC_F32 && dto == BVC_F64)
+    hipLaunchKernelGGL((k_take<float, double>), dim3(blocks), dim3(kBlock), 0, st, n_idx, count, idx, rows, ld_in,
+                       (const float*)in, ld_out, (double*)out);
+  else
+    hipLaunchKernelGGL((k_take<float, float>), dim3(blocks), dim3(kBlock), 0, st, n_idx, count, idx, rows, ld_in,
+                       (const float*)in, ld_out, (float*)out);
+  return check_hip(hipGetLastError(), "take launch");
+}
+}  // namespace
 
 }  // namespace bvc
 
@@ -683,28 +711,32 @@ int bvc_compact(int64_t n, const int32_t* flags, int32_t want, int32_t* idx, int
   return rc;
 }
 
+int bvc_compact_count(int64_t n, const int32_t* flags, int32_t want, int32_t* idx, int32_t* scratch, int64_t* count,
+                      void* stream) {
+  if (n < 0 || n >= (int64_t)1 << 31) return fail(BVC_EINVAL, "n out of range");
+  if (!count) return fail(BVC_EINVAL, "count is null");
+  hipStream_t st = (hipStream_t)stream;
+  if (n == 0) return zero_async(count, sizeof(int64_t), st);
+  if (!flags || !idx || !scratch) return fail(BVC_EINVAL, "null argument");
+  if (((uintptr_t)scratch & 7) != 0) return fail(BVC_EINVAL, "scratch must be 8-byte aligned");
+  const int nb = (int)((n + kCompactTile - 1) / kCompactTile);
+  int* offs = scratch + 2;
+  hipLaunchKernelGGL(k_compact_count, dim3(nb), dim3(kBlock), 0, st, n, flags, want, offs);
+  hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, st, nb, offs, count);
+  hipLaunchKernelGGL(k_compact_scatter, dim3(nb), dim3(kBlock), 0, st, n, flags, want, offs, idx);
+  return check_hip(hipGetLastError(), "compact launch");
+}
+
+
 int bvc_take(int32_t dti, int32_t dto, int64_t n_idx, const int32_t* idx, int32_t rows, int64_t ld_in,
              const void* in, int64_t ld_out, void* out, void* stream) {
-  if ((dti != BVC_F32 && dti != BVC_F64) || (dto != BVC_F32 && dto != BVC_F64))
-    return fail(BVC_EINVAL, "dtype must be F32 or F64");
-  if (n_idx < 0 || rows < 0 || ld_in < 0 || ld_out < n_idx) return fail(BVC_EINVAL, "bad sizes");
-  if (n_idx == 0 || rows == 0) return BVC_OK;
-  if (!in || !out) return fail(BVC_EINVAL, "null argument");
-  hipStream_t st = (hipStream_t)stream;
-  const int blocks = (int)((n_idx + kBlock - 1) / kBlock);
-  if (dti == BVC_F64 && dto == BVC_F64)
-    hipLaunchKernelGGL((k_take<double, double>), dim3(blocks), dim3(kBlock), 0, st, n_idx, idx, rows, ld_in,
-                       (const double*)in, ld_out, (double*)out);
-  else if (dti == BVC_F64 && dto == BVC_F32)
-    hipLaunchKernelGGL((k_take<double, float>), dim3(blocks), dim3(kBlock), 0, st, n_idx, idx, rows, ld_in,
-                       (const double*)in, ld_out, (float*)out);
-  else if (dti == BVC_F32 && dto == BVC_F64)
-    hipLaunchKernelGGL((k_take<float, double>), dim3(blocks), dim3(kBlock), 0, st, n_idx, idx, rows, ld_in,
-                       (const float*)in, ld_out, (double*)out);
-  else
-    hipLaunchKernelGGL((k_take<float, float>), dim3(blocks), dim3(kBlock), 0, st, n_idx, idx, rows, ld_in,
-                       (const float*)in, ld_out, (float*)out);
-  return check_hip(hipGetLastError(), "take launch");
+  return take_impl(dti, dto, n_idx, nullptr, idx, rows, ld_in, in, ld_out, out, stream);
+}
+
+int bvc_take_count(int32_t dti, int32_t dto, int64_t n_cap, const int64_t* count, const int32_t* idx, int32_t rows,
+                   int64_t ld_in, const void* in, int64_t ld_out, void* out, void* stream) {
+  if (!count) return fail(BVC_EINVAL, "count is null");
+  return take_impl(dti, dto, n_cap, count, idx, rows, ld_in, in, ld_out, out, stream);
 }
 
 int bvc_scatter(int32_t dtype, int64_t n_idx, const int32_t* idx, int32_t rows, int64_t ld_in, const void* in,

@@ -60,6 +60,7 @@ struct WalkArgs {
   double oc[3];              // open 3D domain: sphere enclosing the boundary,
   double orad;               // 0 = bounded domain
   int side;                  // side rule of double-sided data (reads moved towards the walk)
+  const int64_t* n_dev;      // modes 0, 1: device count of start points (<= n_pts), or null
 };
 
 // Open 3D domains (Appendix B).  A walk that has jumped (jump index k) to
@@ -268,6 +269,16 @@ __device__ __forceinline__ void walks_body(const WalkArgs& a, uint32_t* lds) {
   // same jump code as every later ball).
   bool active = false, jump = false, exhausted = false;
   IdPool pool;
+  // a device-resident start-point count bounds the ids and sets the claim
+  // size (the host sized the grid and records for the capacity n_pts)
+  uint64_t live = a.total;
+  unsigned long long chunk = a.chunk;
+  if (MODE != 2 && a.n_dev) {
+    const int64_t c = *a.n_dev;
+    const uint64_t t = (uint64_t)(c > 0 ? c : 0) * (uint64_t)a.W;
+    if (t < live) live = t;
+    chunk = chunk_for(live, (int)gridDim.x);
+  }
   uint32_t id = 0;
   int k = 0;
   T p[D];
@@ -284,7 +295,7 @@ __device__ __forceinline__ void walks_body(const WalkArgs& a, uint32_t* lds) {
     if (!exhausted) {
       const uint64_t need = __ballot(!active);
       if (need) {
-        const unsigned long long my = pool.take(need, lane, &a.counters[0], a.chunk, a.total, exhausted);
+        const unsigned long long my = pool.take(need, lane, &a.counters[0], chunk, live, exhausted);
         if (!active) {
           if (my != ~0ull) {
             // mode 2 walks start from the points their ids index (one walk each)
@@ -496,7 +507,14 @@ template <typename T, int D, int MODE>
 __global__ __launch_bounds__(kBlock) void k_finish(FieldDev g, int cv, uint64_t total, int W, int64_t n_pts,
                                                     const double* xbar, const T* EX, T* U, T* Dof, const T* W1,
                                                     double sigma, double eps, const double* R0, int side,
-                                                    const double* x64, const T* xT) {
+                                                    const double* x64, const T* xT, const int64_t* n_dev) {
+  // ids below `live` are finished; `total` stays the records' stride
+  uint64_t live = total;
+  if (n_dev) {
+    const int64_t c = *n_dev;
+    const uint64_t t = (uint64_t)(c > 0 ? c : 0) * (uint64_t)W;
+    if (t < live) live = t;
+  }
   const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const uint64_t id0 = wave * (64 * kFinishRun) + (threadIdx.x & 63);
   const bool scr = sigma > 0.0;
@@ -505,7 +523,7 @@ __global__ __launch_bounds__(kBlock) void k_finish(FieldDev g, int cv, uint64_t 
   double c = 0.0;
   for (int r = 0; r < kFinishRun; ++r) {
     const uint64_t id = id0 + (uint64_t)r * 64;
-    if (id >= total) break;
+    if (id >= live) break;
     const int64_t i = (int64_t)(id / (uint64_t)W);
     if (cv && i != i_cv) {
       // the control variate in the walks' precision: any constant keeps the
@@ -595,10 +613,10 @@ __global__ __launch_bounds__(kBlock) void k_closest_points(SceneDev S, int64_t n
 template <typename Ti, typename To>
 __global__ __launch_bounds__(kBlock) void k_reduce(int64_t n, int W, int rows, int64_t ld, const Ti* U,
                                                     const Ti* G, const double* w, double* uhat, double* ghat,
-                                                    To* a, To* b, int64_t ld_g) {
+                                                    To* a, To* b, int64_t ld_g, const int64_t* count) {
   const int lane = threadIdx.x & 63;
   const int64_t i = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-  if (i >= n) return;
+  if (i >= (count ? std::min<int64_t>(n, *count) : n)) return;
   double su = 0.0;
   double sg[3] = {0.0, 0.0, 0.0};
   for (int j = lane; j < W; j += 64) {
@@ -623,8 +641,9 @@ __global__ __launch_bounds__(kBlock) void k_reduce(int64_t n, int W, int rows, i
 
 // h: the scene of a call that takes open domains (cache, pointwise and
 // tuning walks); null for the calls that refuse them.
-int check_walk_params(const bvc_walk_params* p, int dim, const SceneHost* h = nullptr) {
+int check_walk_params(const bvc_walk_params* p, int dim, const SceneHost* h = nullptr, bool count_ok = false) {
   if (!p) return fail(BVC_EINVAL, "walk params are null");
+  if (p->n_dev && !count_ok) return fail(BVC_EUNSUPPORTED, "a device point count is taken by the cache walks only");
   if (!(p->eps > 0) || !std::isfinite(p->eps)) return fail(BVC_EINVAL, "eps must be positive");
   if (p->max_steps < 1) return fail(BVC_EINVAL, "max_steps must be >= 1");
   if (p->n_walks < 1) return fail(BVC_EINVAL, "n_walks must be >= 1");
@@ -687,11 +706,11 @@ void launch_finish(const bvc_walk_params* p, int mode, const WalkArgs& a, hipStr
   if (mode == 0)
     hipLaunchKernelGGL((k_finish<T, D, 0>), dim3(blocks), dim3(kBlock), 0, st, g, p->control_variate, a.total,
                        a.W, a.n_pts, a.xbar, (const T*)a.exit, (T*)a.U, (T*)a.Dof, (const T*)a.w1, a.sigma,
-                       a.eps, a.R0, a.side, a.x, (const T*)a.px);
+                       a.eps, a.R0, a.side, a.x, (const T*)a.px, a.n_dev);
   else
     hipLaunchKernelGGL((k_finish<T, D, 1>), dim3(blocks), dim3(kBlock), 0, st, g, p->control_variate, a.total,
                        a.W, a.n_pts, a.xbar, (const T*)a.exit, (T*)a.U, (T*)a.Dof, (const T*)a.w1, a.sigma,
-                       a.eps, a.R0, a.side, a.x, (const T*)a.px);
+                       a.eps, a.R0, a.side, a.x, (const T*)a.px, a.n_dev);
 }
 
 size_t stack_bytes(const SceneHost& h) { return (size_t)(h.depth + 1) * kBlock * sizeof(uint32_t); }
@@ -991,7 +1010,7 @@ int cache_walks_entry(bvc_scene s, const bvc_walk_params* p, int64_t n_cache, co
                       int32_t* rec_steps, uint64_t* counters, void* stream, const WalkShape* force) {
   int rc = check_scene(s);
   if (rc) return rc;
-  rc = check_walk_params(p, s->h.dim, &s->h);
+  rc = check_walk_params(p, s->h.dim, &s->h, true);
   if (rc) return rc;
   if (n_cache < 0) return fail(BVC_EINVAL, "n_cache must be >= 0");
   if ((uint64_t)n_cache * (uint64_t)p->n_walks >= (1ull << 32)) return fail(BVC_EINVAL, "n_cache * W >= 2^32");
@@ -1009,6 +1028,7 @@ int cache_walks_entry(bvc_scene s, const bvc_walk_params* p, int64_t n_cache, co
   a.w1 = rec_w1;
   a.steps = rec_steps;
   a.counters = (unsigned long long*)counters;
+  a.n_dev = p->n_dev;
   return run_walks(s, p, 0, n_cache, a, (hipStream_t)stream, force);
 }
 }  // namespace
@@ -1146,12 +1166,39 @@ int pointwise_run(bvc_scene s, const bvc_walk_params* p, int64_t n, const void* 
   if (p->dtype == BVC_F32)
     hipLaunchKernelGGL((k_reduce<float, float>), dim3(blocks), dim3(kBlock), 0, st, n, p->n_walks, rows, ld,
                        (const float*)U_walk, (const float*)G_walk, nullptr, nullptr, nullptr, (float*)u,
-                       (float*)grad, n);
+                       (float*)grad, n, nullptr);
   else
     hipLaunchKernelGGL((k_reduce<double, double>), dim3(blocks), dim3(kBlock), 0, st, n, p->n_walks, rows, ld,
                        (const double*)U_walk, (const double*)G_walk, nullptr, nullptr, nullptr, (double*)u,
-                       (double*)grad, n);
+                       (double*)grad, n, nullptr);
   return check_hip(hipGetLastError(), "pointwise reduce launch");
+}
+
+int reduce_impl(int64_t n_cache, const int64_t* count, int32_t W, int32_t dti, const void* U, const void* D,
+                const double* w, double* uhat, double* dudn, int32_t dto, void* a, void* b, void* stream) {
+  if (n_cache < 0 || W < 1) return fail(BVC_EINVAL, "bad sizes");
+  if ((dti != BVC_F32 && dti != BVC_F64) || (dto != BVC_F32 && dto != BVC_F64))
+    return fail(BVC_EINVAL, "dtype must be F32 or F64");
+  if (n_cache == 0) return BVC_OK;
+  if (!U || !D) return fail(BVC_EINVAL, "null input");
+  if ((a || b) && !w) return fail(BVC_EINVAL, "weights are null");
+  hipStream_t st = (hipStream_t)stream;
+  const int per = kBlock / 64;
+  const int blocks = (int)((n_cache + per - 1) / per);
+  const int64_t ld = n_cache * (int64_t)W;
+  if (dti == BVC_F32 && dto == BVC_F32)
+    hipLaunchKernelGGL((k_reduce<float, float>), dim3(blocks), dim3(kBlock), 0, st, n_cache, W, 1, ld,
+                       (const float*)U, (const float*)D, w, uhat, dudn, (float*)a, (float*)b, n_cache, count);
+  else if (dti == BVC_F32)
+    hipLaunchKernelGGL((k_reduce<float, double>), dim3(blocks), dim3(kBlock), 0, st, n_cache, W, 1, ld,
+                       (const float*)U, (const float*)D, w, uhat, dudn, (double*)a, (double*)b, n_cache, count);
+  else if (dto == BVC_F32)
+    hipLaunchKernelGGL((k_reduce<double, float>), dim3(blocks), dim3(kBlock), 0, st, n_cache, W, 1, ld,
+                       (const double*)U, (const double*)D, w, uhat, dudn, (float*)a, (float*)b, n_cache, count);
+  else
+    hipLaunchKernelGGL((k_reduce<double, double>), dim3(blocks), dim3(kBlock), 0, st, n_cache, W, 1, ld,
+                       (const double*)U, (const double*)D, w, uhat, dudn, (double*)a, (double*)b, n_cache, count);
+  return check_hip(hipGetLastError(), "reduce launch");
 }
 }  // namespace
 }  // namespace bvc
@@ -1256,7 +1303,7 @@ int bvc_tune_walks(bvc_scene s, const bvc_walk_params* p, int64_t n_cache, const
                    uint64_t* counters, int32_t reps, int32_t* blocks_per_cu, int32_t* open_lanes, void* stream) {
   int rc = check_scene(s);
   if (rc) return rc;
-  rc = check_walk_params(p, s->h.dim, &s->h);
+  rc = check_walk_params(p, s->h.dim, &s->h, true);
   if (rc) return rc;
   if (reps < 1) return fail(BVC_EINVAL, "reps must be >= 1");
   bvc_walk_params q = *p;
@@ -1367,29 +1414,14 @@ int bvc_pointwise_wos_noalloc(bvc_scene s, const bvc_walk_params* p, int64_t n, 
 
 int bvc_reduce_walks(int64_t n_cache, int32_t W, int32_t dti, const void* U, const void* D, const double* w,
                      double* uhat, double* dudn, int32_t dto, void* a, void* b, void* stream) {
-  if (n_cache < 0 || W < 1) return fail(BVC_EINVAL, "bad sizes");
-  if ((dti != BVC_F32 && dti != BVC_F64) || (dto != BVC_F32 && dto != BVC_F64))
-    return fail(BVC_EINVAL, "dtype must be F32 or F64");
-  if (n_cache == 0) return BVC_OK;
-  if (!U || !D) return fail(BVC_EINVAL, "null input");
-  if ((a || b) && !w) return fail(BVC_EINVAL, "weights are null");
-  hipStream_t st = (hipStream_t)stream;
-  const int per = kBlock / 64;
-  const int blocks = (int)((n_cache + per - 1) / per);
-  const int64_t ld = n_cache * (int64_t)W;
-  if (dti == BVC_F32 && dto == BVC_F32)
-    hipLaunchKernelGGL((k_reduce<float, float>), dim3(blocks), dim3(kBlock), 0, st, n_cache, W, 1, ld,
-                       (const float*)U, (const float*)D, w, uhat, dudn, (float*)a, (float*)b, n_cache);
-  else if (dti == BVC_F32)
-    hipLaunchKernelGGL((k_reduce<float, double>), dim3(blocks), dim3(kBlock), 0, st, n_cache, W, 1, ld,
-                       (const float*)U, (const float*)D, w, uhat, dudn, (double*)a, (double*)b, n_cache);
-  else if (dto == BVC_F32)
-    hipLaunchKernelGGL((k_reduce<double, float>), dim3(blocks), dim3(kBlock), 0, st, n_cache, W, 1, ld,
-                       (const double*)U, (const double*)D, w, uhat, dudn, (float*)a, (float*)b, n_cache);
-  else
-    hipLaunchKernelGGL((k_reduce<double, double>), dim3(blocks), dim3(kBlock), 0, st, n_cache, W, 1, ld,
-                       (const double*)U, (const double*)D, w, uhat, dudn, (double*)a, (double*)b, n_cache);
-  return check_hip(hipGetLastError(), "reduce launch");
+  return reduce_impl(n_cache, nullptr, W, dti, U, D, w, uhat, dudn, dto, a, b, stream);
+}
+
+int bvc_reduce_walks_count(int64_t n_cap, const int64_t* count, int32_t W, int32_t dti, const void* U,
+                           const void* D, const double* w, double* uhat, double* dudn, int32_t dto, void* a,
+                           void* b, void* stream) {
+  if (!count) return fail(BVC_EINVAL, "count is null");
+  return reduce_impl(n_cap, count, W, dti, U, D, w, uhat, dudn, dto, a, b, stream);
 }
 
 }  // extern "C"

@@ -80,20 +80,41 @@ class Scene:
         return idx, cnt
 
 
-@dataclass
 class Cache:
-    n: int
-    x: torch.Tensor      # [d][n] FP64
-    nrm: torch.Tensor
-    w: torch.Tensor      # [n]
-    xbar: torch.Tensor
-    R0: torch.Tensor
-    n_candidates: int = 0
+    """Accepted cache samples, FP64: x, nrm, xbar [d][cap], w, R0 [cap].
+
+    A cache compacted with its count read back holds n = cap points.  One
+    sampled without the readback (sample_cache_device) keeps the count on the
+    device (n_dev, int64 [1]) and cap entries of room; the calls that consume
+    it read the count there, and reading `n` on the host synchronises."""
+
+    def __init__(self, n, x, nrm, w, xbar, R0, n_candidates=0, n_dev=None, cap=None):
+        self._n = n
+        self.x, self.nrm, self.w, self.xbar, self.R0 = x, nrm, w, xbar, R0
+        self.n_candidates = n_candidates
+        self.n_dev = n_dev
+        self.cap = n if cap is None else cap
+
+    @property
+    def n(self) -> int:
+        if self._n is None:
+            raw = int(self.n_dev[0].item())
+            if raw > self.cap:
+                raise RuntimeError(f"cache overflow: {raw} accepted candidates for a capacity of {self.cap}; the "
+                                   f"step used the first {self.cap} (raise cache_cap)")
+            self._n = raw
+        return self._n
 
 
-def take(src, idx, n, rows, ld_in, dtype_out=torch.float64):
+def take(src, idx, n, rows, ld_in, dtype_out=torch.float64, count=None):
+    """Columns idx[0..n) of src (all columns when idx is None) as [rows][n];
+    with a device count, the first min(n, count) only (n is the capacity)."""
     out = torch.empty((rows, max(n, 1)) if rows > 1 else (max(n, 1),), dtype=dtype_out, device=src.device)
-    B.bvc_take(B.dtype_code(src.dtype), B.dtype_code(dtype_out), n, idx, rows, ld_in, src, max(n, 1), out)
+    if count is None:
+        B.bvc_take(B.dtype_code(src.dtype), B.dtype_code(dtype_out), n, idx, rows, ld_in, src, max(n, 1), out)
+    else:
+        B.bvc_take_count(B.dtype_code(src.dtype), B.dtype_code(dtype_out), n, count, idx, rows, ld_in, src,
+                         max(n, 1), out)
     return out
 
 
@@ -111,6 +132,27 @@ def sample_cache(sc: Scene, n_cand, l, sides, seed, batch=0) -> Cache:
     c = Cache(n, take(x, idx, n, d, n_cand), take(nrm, idx, n, d, n_cand), take(w, idx, n, 1, n_cand),
               take(xbar, idx, n, d, n_cand), take(R0, idx, n, 1, n_cand), n_cand)
     return c
+
+
+def sample_cache_device(sc: Scene, n_cand, cap, l, sides, seed, batch=0) -> Cache:
+    """sample_cache without the count readback: the accepted count stays on
+    the device and the compacted arrays have room for `cap` points (the
+    first cap accepted candidates are kept; Cache.n reports an overflow)."""
+    d, dev = sc.dim, sc.device
+    f64 = torch.float64
+    x = torch.empty(d, n_cand, dtype=f64, device=dev)
+    nrm = torch.empty_like(x)
+    xbar = torch.empty_like(x)
+    w = torch.empty(n_cand, dtype=f64, device=dev)
+    R0 = torch.empty_like(w)
+    acc = torch.empty(n_cand, dtype=torch.int32, device=dev)
+    B.bvc_sample_cache(sc.h, n_cand, l, sides, seed, batch, x, nrm, w, xbar, R0, acc)
+    idx = torch.empty(max(n_cand, 1), dtype=torch.int32, device=dev)
+    count = torch.empty(1, dtype=torch.int64, device=dev)
+    B.bvc_compact_count(n_cand, acc, 1, idx, sc.scratch_int(n_cand), count)
+    return Cache(None, take(x, idx, cap, d, n_cand, count=count), take(nrm, idx, cap, d, n_cand, count=count),
+                 take(w, idx, cap, 1, n_cand, count=count), take(xbar, idx, cap, d, n_cand, count=count),
+                 take(R0, idx, cap, 1, n_cand, count=count), n_cand, n_dev=count, cap=cap)
 
 
 def sample_roi(dom: Scene, roi: Scene, n_cand, seed, batch=0) -> Cache:
@@ -172,8 +214,12 @@ def walk_params(eps, n_walks, seed, g: DeviceField, f: Optional[DeviceField], dt
 
 
 def cache_walks(sc: Scene, cache: Cache, params: B.bvc_walk_params, dtype="f32", records=False):
+    """Walks from every cache point; a cache with a device count is walked up
+    to that count (outputs laid out for its capacity)."""
     dev = sc.device
-    n, W = cache.n, params.n_walks
+    n, W = cache.cap, params.n_walks
+    if cache.n_dev is not None:
+        params.n_dev = cache.n_dev.data_ptr()
     T = DT[dtype]
     U = torch.empty(max(n * W, 1), dtype=T, device=dev)
     D = torch.empty_like(U)
@@ -206,12 +252,16 @@ def pointwise(sc: Scene, params: B.bvc_walk_params, x, with_grad=True):
 
 def reduce_walks(cache: Cache, W, U, D, dtype_out="f32"):
     dev = U.device
-    n = cache.n
+    n = cache.cap
     uhat = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
     dudn = torch.empty_like(uhat)
     a = torch.empty(max(n, 1), dtype=DT[dtype_out], device=dev)
     b = torch.empty_like(a)
-    B.bvc_reduce_walks(n, W, B.dtype_code(U.dtype), U, D, cache.w, uhat, dudn, CODE[dtype_out], a, b)
+    if cache.n_dev is None:
+        B.bvc_reduce_walks(n, W, B.dtype_code(U.dtype), U, D, cache.w, uhat, dudn, CODE[dtype_out], a, b)
+    else:
+        B.bvc_reduce_walks_count(n, cache.n_dev, W, B.dtype_code(U.dtype), U, D, cache.w, uhat, dudn,
+                                 CODE[dtype_out], a, b)
     return uhat, dudn, a, b
 
 
@@ -256,7 +306,7 @@ class Prepared:
     evaluation points and the candidate count of the cache sampler."""
 
     def __init__(self, problem, dtype=None, n_cand=None, device="cuda", eval_x=None, clamp=None, near_tau=None,
-                 band=None, grad_band=None, grad_band_walks=None):
+                 band=None, grad_band=None, grad_band_walks=None, cache_cap=None):
         # points within `band` of the boundary take pointwise walks for u and
         # grad u (the band of Algorithm 1 is the offset l; a wider band trades
         # walks for the gather's error next to the cache surface)
@@ -270,6 +320,14 @@ class Prepared:
         self.f = DeviceField(problem.f, device) if not problem.f.is_zero else None
         self.n_cand = n_cand or candidates_for(self.sc, problem.n_cache, problem.offset, problem.sides,
                                                problem.seed_cache)
+        # a solve keeps its accepted cache count on the device: the arrays
+        # have room for n_cap points.  With the candidate count drawn for an
+        # expected n_cache accepted points, twice that (plus 1024) lies beyond
+        # any plausible draw; a given candidate count may all be accepted.
+        if cache_cap is None:
+            cache_cap = min(self.n_cand, 2 * problem.n_cache + 1024) if n_cand is None else self.n_cand
+        self.n_cap = int(cache_cap)
+        self.sc.scratch_int(self.n_cand)
         ex = problem.eval_x if eval_x is None else eval_x
         self.eval64 = torch.from_numpy(np.ascontiguousarray(ex.T)).to(device)
         n = self.eval64.shape[1]
@@ -389,12 +447,13 @@ def solve_roi(prep: RoiPrepared, batch=0, with_grad=True, watch=None) -> Solutio
         U, D, rec, counters = cache_walks(sc, cache, wp, dt)
     with watch.stage("reduce_walks"):
         uhat, dudn, a, b = reduce_walks(cache, p.n_walks, U, D, dt)
+    n = cache.cap
     if T != torch.float64:
-        cx = take(cache.x, None, cache.n, d, cache.n, T)
-        cn = take(cache.nrm, None, cache.n, d, cache.n, T)
+        cx = take(cache.x, None, n, d, n, T, count=cache.n_dev)
+        cn = take(cache.nrm, None, n, d, n, T, count=cache.n_dev)
     else:
         cx, cn = cache.x, cache.nrm
-    cview = dict(n=cache.n, dtype=CODE[dt], x=cx, nrm=cn, a=a, b=b)
+    cview = dict(n=n, dtype=CODE[dt], x=cx, nrm=cn, a=a, b=b, n_dev=cache.n_dev)
     sview = None
     if prep.f is not None and p.n_sources > 0:
         m = int(round(p.n_sources ** (1.0 / d)))
@@ -711,12 +770,13 @@ def _gather_views(prep: Prepared, cache: Cache, a, b, batch, watch):
     source view (jittered source samples, Eq. 4) of one solve."""
     p, sc, dt = prep.p, prep.sc, prep.dtype
     T, d = DT[dt], sc.dim
+    n = cache.cap
     if T != torch.float64:
-        cx = take(cache.x, None, cache.n, d, cache.n, T)
-        cn = take(cache.nrm, None, cache.n, d, cache.n, T)
+        cx = take(cache.x, None, n, d, n, T, count=cache.n_dev)
+        cn = take(cache.nrm, None, n, d, n, T, count=cache.n_dev)
     else:
         cx, cn = cache.x, cache.nrm
-    cview = dict(n=cache.n, dtype=CODE[dt], x=cx, nrm=cn, a=a, b=b)
+    cview = dict(n=n, dtype=CODE[dt], x=cx, nrm=cn, a=a, b=b, n_dev=cache.n_dev)
     sview = None
     if prep.f is not None and p.n_sources > 0:
         m = int(round(p.n_sources ** (1.0 / d)))
@@ -735,7 +795,7 @@ def _near(prep: Prepared, cache: Cache, U, D):
     """Near-field argument of an FP32 gather (None when off): FP64 cache
     values a, b from the walks' FP64 means, and the FP64 cache points,
     normals and evaluation points."""
-    if not prep.near_tau or cache.n == 0:
+    if not prep.near_tau or cache.cap == 0:
         return None
     _, _, a64, b64 = reduce_walks(cache, prep.p.n_walks, U, D, "f64")
     return dict(tau=prep.near_tau, x=prep.x_int64, cx=cache.x, cn=cache.nrm, a=a64, b=b64)
@@ -748,10 +808,11 @@ def tune(prep: Prepared, with_grad=True, reps=3) -> dict:
     depend on the shapes."""
     p, sc, dt = prep.p, prep.sc, prep.dtype
     T, d = DT[dt], sc.dim
-    cache = sample_cache(sc, prep.n_cand, p.offset, p.sides, p.seed_cache, 0)
+    cache = sample_cache_device(sc, prep.n_cand, prep.n_cap, p.offset, p.sides, p.seed_cache, 0)
     wp = walk_params(p.eps, p.n_walks, p.seed_walks, prep.g, prep.f, dt, 0, sigma=p.sigma,
                      open_sphere=p.extra.get("open_sphere"), side_read=p.side_read)
-    n, W = cache.n, p.n_walks
+    wp.n_dev = cache.n_dev.data_ptr()
+    n, W = cache.cap, p.n_walks
     U = torch.empty(max(n * W, 1), dtype=T, device=sc.device)
     D = torch.empty_like(U)
     ex = torch.empty(d, max(n * W, 1), dtype=T, device=sc.device)
@@ -775,7 +836,7 @@ def solve(prep: Prepared, batch=0, with_grad=True, n_walks_band=None, records=Fa
     d = sc.dim
     watch = watch or _NoWatch()
     with watch.stage("sample_cache"):
-        cache = sample_cache(sc, prep.n_cand, p.offset, p.sides, p.seed_cache, batch)
+        cache = sample_cache_device(sc, prep.n_cand, prep.n_cap, p.offset, p.sides, p.seed_cache, batch)
     osph = p.extra.get("open_sphere")
     wp = walk_params(p.eps, p.n_walks, p.seed_walks, prep.g, prep.f, dt, batch, sigma=p.sigma, open_sphere=osph,
                      side_read=p.side_read)
