@@ -62,6 +62,10 @@ OPS_PHILOX_BLOCK = 100
 OPS_NODE = {2: 22, 3: 30}
 OPS_PRIM = {2: 15, 3: 50}
 OPS_STEP = {2: 12, 3: 15}
+# a 3D node's two slab bounds when the traversal uses them: per child the
+# dot product n.p (5), the distance to the range (3) and the comparison with
+# the box bound (1), twice
+OPS_SLAB = 18
 
 
 def parse():
@@ -221,15 +225,16 @@ GATHER_SOURCES = ("kernels_gather.hip", "bvc_device.hpp", "bvc_internal.hpp")
 WALK_SOURCES = ("walks.hip", "bvc_device.hpp", "bvc_internal.hpp")
 
 
-def walk_bytes(dim, es, mode, with_grad):
+def walk_bytes(dim, es, mode, with_grad, slabs=True):
     """Algorithmic bytes of the walk kernel in the record sizes of FP32 (es =
     4; FP64 doubles them): per binary BVH node expanded, 48 B in 2D and 64 B
-    in 3D (two child boxes and their links), plus in 3D the 40 B of the two
-    children's slab bounds (axis and range each); per primitive tested, a
-    16 B segment or a 36 B triangle; per walk, its inputs read and records
-    written (mode 0 cache walk, mode 1 pointwise walk)."""
+    in 3D (two child boxes and their links), plus in 3D, when the traversal
+    uses them, the 40 B of the two children's slab bounds (axis and range
+    each); per primitive tested, a 16 B segment or a 36 B triangle; per walk,
+    its inputs read and records written (mode 0 cache walk, mode 1 pointwise
+    walk)."""
     s = es // 4
-    node = (48 if dim == 2 else 64 + 40) * s
+    node = (48 if dim == 2 else 64 + (40 if slabs else 0)) * s
     prim = (16 if dim == 2 else 36) * s
     if mode == 0:
         io = 8 + 2 * dim * 8 + dim * es + 3 * es          # R0, x, n (FP64); exit, U, D, w1
@@ -244,14 +249,16 @@ def philox_blocks_per_step(dim, src):
     return 1 + ((2 if dim == 2 else 3) if src else 0)
 
 
-def walk_roofline(kernel, dim, es, mode, with_grad, ms, queries, walks, work_key, work, src, traffic):
+def walk_roofline(kernel, dim, es, mode, with_grad, ms, queries, walks, work_key, work, src, traffic, slabs=True):
     """Memory roofline of one walk launch on algorithmic traversal bytes (the
     nodes and primitives a nearest-first query visits, counted by the oracle
     on this BVH, times their record sizes, plus each walk's inputs and
     records), and its VALU bound: the minimal lane-operations of those
     visits, the Philox blocks and the step arithmetic, against the chip's
     lane-operation peak."""
-    node_b, prim_b, io_b = walk_bytes(dim, es, mode, with_grad)
+    slabs = bool(slabs) and dim == 3
+    node_b, prim_b, io_b = walk_bytes(dim, es, mode, with_grad, slabs)
+    ops_node = OPS_NODE[dim] + (OPS_SLAB if slabs else 0)
     out = {"bound": "hbm", "achieved": None, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": None,
            "traffic": traffic, "kernel": kernel, "avg_launch_ms": round(ms, 4), "queries_per_launch": queries,
            "walks_per_launch": walks, "bytes": {"node": node_b, "primitive": prim_b, "walk_io": io_b}}
@@ -263,13 +270,14 @@ def walk_roofline(kernel, dim, es, mode, with_grad, ms, queries, walks, work_key
         gbs = alg / (ms / 1e3) / 1e9
         out.update(achieved=round(gbs, 1), frac=round(gbs / PEAK_HBM_GBS, 4), nodes_per_query=vn,
                    prims_per_query=vp, bytes_per_query=round(per_query, 1), bytes_per_launch=alg)
-        ops = (philox_blocks_per_step(dim, src) * OPS_PHILOX_BLOCK + OPS_STEP[dim] + vn * OPS_NODE[dim] +
+        ops = (philox_blocks_per_step(dim, src) * OPS_PHILOX_BLOCK + OPS_STEP[dim] + vn * ops_node +
                vp * OPS_PRIM[dim])
         rate = queries * ops / (ms / 1e3)
         valu = {"bound": "valu", "achieved": rate / 1e12, "peak": PEAK_LANE_OPS / 1e12, "unit": "Tlane-op/s",
                 "frac": round(rate / PEAK_LANE_OPS, 4), "kernel": kernel, "lane_ops_per_query": round(ops, 1),
                 "ops": {"philox_block": OPS_PHILOX_BLOCK, "philox_blocks_per_step": philox_blocks_per_step(dim, src),
-                        "node": OPS_NODE[dim], "primitive": OPS_PRIM[dim], "step": OPS_STEP[dim]}}
+                        "node": ops_node, "primitive": OPS_PRIM[dim], "step": OPS_STEP[dim]}}
+        out["slab_bounds"] = slabs
     return out, valu
 
 
@@ -510,7 +518,8 @@ def run_workload(args, which):
     # value, else the library's default of 2
     ppt = tuned["gather_points_per_thread"] if tuned else 2
     T = "float" if dtype == "f32" else "double"
-    gather_kernel = f"k_gather<{T},{dim},{'true' if dim == 2 else 'false'},false,{ppt},false>"
+    near_on = "true" if sol.extra.get("near") is not None else "false"
+    gather_kernel = f"k_gather<{T},{dim},{'true' if with_grad else 'false'},{near_on},{ppt},false>"
     roofline_gather = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                        "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
                        "traffic": measured_traffic(gather_kernel, which, GATHER_SOURCES),
@@ -527,9 +536,14 @@ def run_workload(args, which):
                                     value)
         log(f"{which} pointwise {pointwise['walks_for_equal_rmse']} walks for equal RMSE")
 
+    # the traversal's slab bounds (3D): the tuned choice for the cache walks,
+    # the default of a bounded domain (on) for the band walks
+    cache_slabs = bool((tuned or {}).get("walk_slabs", 1)) and dim == 3
+    band_slabs = dim == 3
     cpu, work = None, None
     if not args.no_cpu:
-        cpu, work = oracle_leg(prob, prep, sol, args.cpu_seconds, n_pts, dim, with_grad, pointwise)
+        cpu, work = oracle_leg(prob, prep, sol, args.cpu_seconds, n_pts, dim, with_grad, pointwise,
+                               (cache_slabs, band_slabs))
         log(f"{which} cpu baseline {cpu}")
 
     es = 4 if dtype == "f32" else 8
@@ -540,7 +554,8 @@ def run_workload(args, which):
         kname = f"k_walks<{T},3,false,0>"
         roofline, valu = walk_roofline(kname + " (cache walks)", 3, es, 0, False, cache_ms, int(sol.counters[1]),
                                        int(sol.counters[3]), "cache", work, src,
-                                       measured_traffic(kname, which, WALK_SOURCES) if es == 4 else None)
+                                       measured_traffic(kname, which, WALK_SOURCES) if es == 4 else None,
+                                       cache_slabs)
         other, other_valu = walk_roofline(f"k_walks<{T},3,false,1> (band-point walks)", 3, es, 1, False, band_ms,
                                           int(sol.pw_counters[1]), int(sol.pw_counters[3]), "band", work, src, None)
     else:
@@ -637,7 +652,7 @@ def native_oracle():
     return oracle
 
 
-def oracle_leg(prob, prep, sol, budget_s, n_pts, dim, with_grad, pointwise):
+def oracle_leg(prob, prep, sol, budget_s, n_pts, dim, with_grad, pointwise, slabs=(True, True)):
     """The host oracle leg.  (1) cpu_baseline: the FP64 oracle, built here
     with -O3 -march=native -ffp-contract=off, on a bounded sample of the same
     step, extrapolated to the step's full work: walks of the first cache
@@ -732,7 +747,7 @@ def oracle_leg(prob, prep, sol, budget_s, n_pts, dim, with_grad, pointwise):
                      "pointwise_points_per_s_at_equal_rmse": pw_pts_s, "bvc_points_per_s": full["value"],
                      "bvc_over_pointwise": full["value"] / pw_pts_s,
                      "sample": f"16 pointwise walks at {pts.shape[0]} interior points, all threads"}
-    work = traversal_work(oracle, osc, prob, prep, cn, idx_b, W)
+    work = traversal_work(oracle, osc, prob, prep, cn, idx_b, W, slabs=slabs)
     cpu = {"value": full["value"], "unit": "points/s", "cores": all_threads, "kind": "oracle",
            "sample": "FP64 oracle, all host threads: " + full["sample"],
            "step_s_extrapolated": full["step_s_extrapolated"], "one_thread": one,
@@ -743,15 +758,19 @@ def oracle_leg(prob, prep, sol, budget_s, n_pts, dim, with_grad, pointwise):
     return cpu, work
 
 
-def traversal_work(oracle, osc, prob, prep, cn, idx_b, W, n_cache_pts=256, n_band_pts=1024, walks_each=8):
+def traversal_work(oracle, osc, prob, prep, cn, idx_b, W, n_cache_pts=256, n_band_pts=1024, walks_each=8,
+                   slabs=(True, True)):
     """Mean nodes expanded and primitives tested per query, counted by the
-    oracle on the library's exported BVH, over the queries of `walks_each`
+    oracle on the library's exported BVH (with its slab bounds where the
+    cache or band walks use them, `slabs`), over the queries of `walks_each`
     walks (ids i*W + j, as the library numbers them) of cache points and band
     points taken evenly across their sets (cache walks and pointwise walks)."""
     from paper_2302_11825_amd import _bvc as B
 
     child, boxes, order = B.bvc_scene_export_bvh(prep.sc.h)
-    slabs = B.bvc_scene_export_slabs(prep.sc.h) if prob.scene.dim == 3 else None
+    sl = B.bvc_scene_export_slabs(prep.sc.h) if prob.scene.dim == 3 else None
+    slabs_cache = sl if slabs[0] else None
+    slabs_band = sl if slabs[1] else None
     P = oracle.walk_params(prob.eps, W, prob.seed_walks)
     out = {}
     n_all = cn["x"].shape[0]
@@ -760,7 +779,7 @@ def traversal_work(oracle, osc, prob, prep, cn, idx_b, W, n_cache_pts=256, n_ban
     ids = [int(i) * W + j for i in ci for j in range(walks_each)]
     q, h, _ = oracle.walk_queries(osc, P, 0, np.repeat(cn["x"][ci], walks_each, 0),
                                   np.repeat(cn["R0"][ci], walks_each), ids)
-    vn, vp = oracle.bvh_visits(osc, child, boxes, order, q, h, slabs=slabs)
+    vn, vp = oracle.bvh_visits(osc, child, boxes, order, q, h, slabs=slabs_cache)
     out["cache"] = {"nodes_per_query": float(vn.mean()), "prims_per_query": float(vp.mean()),
                     "queries_counted": int(q.shape[0])}
     bi = np.linspace(0, idx_b.size - 1, min(n_band_pts, idx_b.size)).astype(np.int64)
@@ -769,7 +788,7 @@ def traversal_work(oracle, osc, prob, prep, cn, idx_b, W, n_cache_pts=256, n_ban
     d, _, _ = osc.closest(pts)
     ids = [int(k) * W + j for k in bi for j in range(walks_each)]
     q, h, _ = oracle.walk_queries(osc, P, 1, np.repeat(pts, walks_each, 0), np.repeat(d, walks_each), ids)
-    vn, vp = oracle.bvh_visits(osc, child, boxes, order, q, h, slabs=slabs)
+    vn, vp = oracle.bvh_visits(osc, child, boxes, order, q, h, slabs=slabs_band)
     out["band"] = {"nodes_per_query": float(vn.mean()), "prims_per_query": float(vp.mean()),
                    "queries_counted": int(q.shape[0])}
     out["counted_on"] = (f"{out['cache']['queries_counted']} cache-walk and {out['band']['queries_counted']} "

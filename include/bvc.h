@@ -580,18 +580,23 @@ int bvc_tune_gather(int32_t dim, const bvc_cache_view* cache, const bvc_source_v
 
 /* Times the cache walks of this problem over persistent grids of 4, 8 and 16
  * blocks per compute unit and traversal-loop exit thresholds of 0, 8, 16, 32
- * and 48 open lanes (the default shape first; another is kept only when at
+ * and 48 open lanes, and in 3D with and without the slab bounds in the
+ * traversal (default shape: 8 blocks per CU, 32 open lanes in 3D and 0 in 2D,
+ * slab bounds on for bounded 3D domains and off for open ones; the other slab
+ * setting is tried at the default grid and threshold first, then grids and
+ * thresholds with the setting kept; a shape replaces the default only when at
  * least 3% faster) and keeps the choice for every later cache-walk launch of
  * the same class (dim, walk dtype, source term or not, open domain or not,
- * screened or not) whose params->blocks
- * is 0; pointwise walks keep their default shape.  Every shape gives the same
- * walk results (a walk's random numbers depend on its id only).  Arguments as
- * bvc_cache_walks; the outputs hold the walks' results on return.
- * Synchronises the stream. */
+ * screened or not) whose params->blocks is 0; pointwise walks keep their
+ * default shape.  Every shape gives the same walk results (a walk's random
+ * numbers depend on its id only, and the slab bounds only prune subtrees that
+ * cannot hold a closer primitive).  Arguments as bvc_cache_walks; the outputs
+ * hold the walks' results on return; *slabs (optional) receives 1 when the
+ * slab bounds are kept.  Synchronises the stream. */
 int bvc_tune_walks(bvc_scene scene, const bvc_walk_params* params, int64_t n_cache, const double* x,
                    const double* nrm, const double* R0, const double* xbar, void* U, void* D,
                    void* rec_exit, void* rec_w1, uint64_t* counters, int32_t reps,
-                   int32_t* blocks_per_cu, int32_t* open_lanes, void* stream);
+                   int32_t* blocks_per_cu, int32_t* open_lanes, int32_t* slabs, void* stream);
 
 /* Adjoint of the gather for dL/du = r [n_eval]:
  * dL/da_i = sum_k r_k dG/dn(x_k,z_i), dL/db_i = -sum_k r_k G(x_k,z_i),

@@ -118,7 +118,7 @@ _SIGS = {
     "bvc_tune_gather": [C.c_int32, _P(bvc_cache_view), _P(bvc_source_view), C.c_int64, _vp, _vp, _vp,
                         _P(bvc_gather_params), C.c_int32, _P(C.c_int32), _vp],
     "bvc_tune_walks": [_vp, _P(bvc_walk_params), C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
-                       C.c_int32, _P(C.c_int32), _P(C.c_int32), _vp],
+                       C.c_int32, _P(C.c_int32), _P(C.c_int32), _P(C.c_int32), _vp],
     "bvc_gather_backward": [C.c_int32, _P(bvc_cache_view), _P(bvc_source_view), C.c_int64, _vp, _vp, _vp,
                             _vp, _vp, _vp, _vp],
     "bvc_basis_means": [_P(bvc_field), C.c_int32, C.c_int64, C.c_int32, C.c_int32, _vp, _vp, _vp, C.c_int32,
@@ -446,12 +446,13 @@ def bvc_tune_gather(dim, cache, sources, n_eval, eval_x, u, grad=None, reps=3, s
 
 def bvc_tune_walks(scene, params: bvc_walk_params, n_cache, x, nrm, R0, xbar, U, D, rec_exit, rec_w1, counters,
                    reps=2, stream=None):
-    """Returns (blocks per compute unit, open lanes) the library keeps for this walk class."""
-    bpc, lanes = C.c_int32(), C.c_int32()
+    """Returns (blocks per compute unit, open lanes, slab bounds on) the library
+    keeps for this walk class."""
+    bpc, lanes, slabs = C.c_int32(), C.c_int32(), C.c_int32()
     _check(_L.bvc_tune_walks(scene, C.byref(params), n_cache, ptr(x), ptr(nrm), ptr(R0), ptr(xbar), ptr(U), ptr(D),
                              ptr(rec_exit), ptr(rec_w1), ptr(counters), reps, C.byref(bpc), C.byref(lanes),
-                             stream_ptr(stream)), "bvc_tune_walks")
-    return bpc.value, lanes.value
+                             C.byref(slabs), stream_ptr(stream)), "bvc_tune_walks")
+    return bpc.value, lanes.value, slabs.value
 
 
 def bvc_gather_backward(dim, cache, sources, n_eval, eval_x, dL_du, dL_da, dL_db, dL_ds=None, dL_dx=None,

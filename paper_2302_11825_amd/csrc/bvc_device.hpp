@@ -488,7 +488,7 @@ __device__ __forceinline__ void query_push_leaf(Query<T, D>& q, int leaf) {
 
 template <typename T, int D>
 __device__ __forceinline__ void query_step(const SceneDev& S, const T* p, Query<T, D>& q, uint32_t* stk,
-                                           int stride) {
+                                           int stride, bool slab = true) {
   // ---- one primitive of the first pending leaf
   if (q.pa != 0) {
     const int i = leaf_start(q.pa), n = leaf_count(q.pa);
@@ -532,7 +532,9 @@ __device__ __forceinline__ void query_step(const SceneDev& S, const T* p, Query<
   const int2 ch = S.child[q.node];
   T d0 = box_d2<T, D>(lo0, hi0, p);
   T d1 = box_d2<T, D>(lo1, hi1, p);
-  if constexpr (D == 3) slab_bounds<T>(S, q.node, p, d0, d1);
+  if constexpr (D == 3) {
+    if (slab) slab_bounds<T>(S, q.node, p, d0, d1);
+  }
   int c0 = ch.x, c1 = ch.y;
   if (d1 < d0) {
     const T td = d0;

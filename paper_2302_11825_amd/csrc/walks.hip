@@ -56,6 +56,7 @@ struct WalkArgs {
   unsigned long long* counters;
   unsigned long long chunk;  // walk ids per claim, 1..kChunkMax
   int open_lanes;            // leave the traversal loop at this many open queries
+  int slab;                  // 3D: prune the traversal with the slab bounds as well
   double sigma;              // screening coefficient (no source term), 0 = Poisson
   double oc[3];              // open 3D domain: sphere enclosing the boundary,
   double orad;               // 0 = bounded domain
@@ -213,11 +214,21 @@ __host__ __device__ inline unsigned long long chunk_for(uint64_t total, int bloc
 // all 64); 2D polylines, whose queries are short and even, run best when the
 // wave finishes every query first.  bvc_tune_walks can pick another threshold
 // and grid size for a problem class.
+//
+// The slab bounds of a 3D tree pay where the walks see the surface from its
+// concave side (inside a closed surface: C3's cache walks 1.65x faster) and
+// cost where they see it from the convex side (outside a closed solid: they
+// prune little there, and the exterior walks ran 1.7x slower with them), so
+// they are a shape choice too: on for bounded domains, off for open ones,
+// and the tuner tries the other setting.
 struct WalkShape {
   int blocks_per_cu;
   int open_lanes;
+  int slabs;
 };
-WalkShape default_shape(int dim) { return WalkShape{8, dim == 3 ? 32 : 0}; }
+WalkShape default_shape(int dim, bool open = false) {
+  return WalkShape{8, dim == 3 ? 32 : 0, dim == 3 && !open ? 1 : 0};
+}
 
 // A tuned shape belongs to one kernel instance: dimension, precision, source
 // term, start mode, open domain (its own kernel) and screening (another
@@ -242,7 +253,7 @@ std::map<WalkClass, WalkShape> g_walk_shape;
 WalkShape tuned_shape(const WalkClass& k) {
   std::lock_guard<std::mutex> lock(g_walk_mu);
   auto it = g_walk_shape.find(k);
-  return it == g_walk_shape.end() ? default_shape(k.dim) : it->second;
+  return it == g_walk_shape.end() ? default_shape(k.dim, k.open != 0) : it->second;
 }
 
 template <typename T, int D, bool SRC, int MODE, bool OPEN>
@@ -419,7 +430,7 @@ __device__ __forceinline__ void walks_body(const WalkArgs& a, uint32_t* lds) {
     }
     // ---- expand one node per open query until few queries remain open
     while (true) {
-      if (active && query_open(qs)) query_step<T, D>(S, p, qs, stk, stride);
+      if (active && query_open(qs)) query_step<T, D>(S, p, qs, stk, stride, a.slab != 0);
       if (__popcll(__ballot(active && query_open(qs))) <= a.open_lanes) break;
     }
     // ---- lanes whose query closed: stop in the shell, or jump next
@@ -744,6 +755,7 @@ int run_walks(bvc_scene s, const bvc_walk_params* p, int mode, int64_t n, WalkAr
   if (rc || total == 0) return rc;
   const WalkShape shape = force ? *force : tuned_shape(walk_class(h.dim, p, mode));
   a.open_lanes = shape.open_lanes;
+  a.slab = shape.slabs;
   int blocks = p->blocks > 0 ? p->blocks : num_cus() * shape.blocks_per_cu;
   const int64_t needed = (int64_t)((total + kBlock - 1) / kBlock);
   blocks = (int)std::max<int64_t>(1, std::min<int64_t>(blocks, needed));
@@ -1300,7 +1312,8 @@ int bvc_cache_walks(bvc_scene s, const bvc_walk_params* p, int64_t n_cache, cons
 
 int bvc_tune_walks(bvc_scene s, const bvc_walk_params* p, int64_t n_cache, const double* x, const double* nrm,
                    const double* R0, const double* xbar, void* U, void* D, void* rec_exit, void* rec_w1,
-                   uint64_t* counters, int32_t reps, int32_t* blocks_per_cu, int32_t* open_lanes, void* stream) {
+                   uint64_t* counters, int32_t reps, int32_t* blocks_per_cu, int32_t* open_lanes, int32_t* slabs,
+                   void* stream) {
   int rc = check_scene(s);
   if (rc) return rc;
   rc = check_walk_params(p, s->h.dim, &s->h, true);
@@ -1315,37 +1328,51 @@ int bvc_tune_walks(bvc_scene s, const bvc_walk_params* p, int64_t n_cache, const
   rc = check_hip(hipEventCreate(&e0), "tune event");
   if (!rc) rc = check_hip(hipEventCreate(&e1), "tune event");
   // the default shape first: another is kept only when it is at least 3%
-  // faster, so that timing noise does not move the choice
-  const WalkShape def = default_shape(s->h.dim);
-  WalkShape cand[16];
-  int nc = 0;
-  cand[nc++] = def;
-  const int bpc[3] = {4, 8, 16};
-  const int lanes[5] = {0, 8, 16, 32, 48};
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 5; ++j)
-      if (bpc[i] != def.blocks_per_cu || lanes[j] != def.open_lanes) cand[nc++] = WalkShape{bpc[i], lanes[j]};
+  // faster, so that timing noise does not move the choice.  In 3D the other
+  // slab setting is tried first at the default grid and threshold; the grid
+  // and threshold are then searched with the setting kept.
+  auto time_shape = [&](const WalkShape& sh, float& ms) -> int {
+    int r = cache_walks_entry(s, &q, n_cache, x, nrm, R0, xbar, U, D, rec_exit, rec_w1, nullptr, counters, stream,
+                              &sh);  // warm-up
+    if (!r) r = check_hip(hipEventRecord(e0, st), "tune event");
+    for (int k = 0; k < reps && !r; ++k)
+      r = cache_walks_entry(s, &q, n_cache, x, nrm, R0, xbar, U, D, rec_exit, rec_w1, nullptr, counters, stream,
+                            &sh);
+    if (!r) r = check_hip(hipEventRecord(e1, st), "tune event");
+    if (!r) r = check_hip(hipEventSynchronize(e1), "tune sync");
+    ms = 0;
+    if (!r) r = check_hip(hipEventElapsedTime(&ms, e0, e1), "tune time");
+    return r;
+  };
+  const WalkShape def = default_shape(s->h.dim, p->open_radius > 0.0);
   WalkShape best = def;
-  float best_ms = INFINITY, def_ms = INFINITY;
-  for (int c = 0; c < nc && !rc; ++c) {
-    const WalkShape sh = cand[c];
-    rc = cache_walks_entry(s, &q, n_cache, x, nrm, R0, xbar, U, D, rec_exit, rec_w1, nullptr, counters, stream,
-                           &sh);  // warm-up
-    if (!rc) rc = check_hip(hipEventRecord(e0, st), "tune event");
-    for (int r = 0; r < reps && !rc; ++r)
-      rc = cache_walks_entry(s, &q, n_cache, x, nrm, R0, xbar, U, D, rec_exit, rec_w1, nullptr, counters, stream,
-                             &sh);
-    if (!rc) rc = check_hip(hipEventRecord(e1, st), "tune event");
-    if (!rc) rc = check_hip(hipEventSynchronize(e1), "tune sync");
+  float best_ms = INFINITY;
+  if (!rc) rc = time_shape(def, best_ms);
+  if (!rc && s->h.dim == 3) {
+    WalkShape flip = def;
+    flip.slabs = 1 - def.slabs;
     float ms = 0;
-    if (!rc) rc = check_hip(hipEventElapsedTime(&ms, e0, e1), "tune time");
-    if (rc) break;
-    if (c == 0) def_ms = ms;
-    if (ms < best_ms && (c == 0 || ms < 0.97f * def_ms)) {
+    rc = time_shape(flip, ms);
+    if (!rc && ms < 0.97f * best_ms) {
+      best = flip;
       best_ms = ms;
-      best = sh;
     }
   }
+  const WalkShape base = best;
+  const float base_ms = best_ms;
+  const int bpc[3] = {4, 8, 16};
+  const int lanes[5] = {0, 8, 16, 32, 48};
+  for (int i = 0; i < 3 && !rc; ++i)
+    for (int j = 0; j < 5 && !rc; ++j) {
+      if (bpc[i] == base.blocks_per_cu && lanes[j] == base.open_lanes) continue;
+      const WalkShape sh{bpc[i], lanes[j], base.slabs};
+      float ms = 0;
+      rc = time_shape(sh, ms);
+      if (!rc && ms < best_ms && ms < 0.97f * base_ms) {
+        best_ms = ms;
+        best = sh;
+      }
+    }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   if (rc) return rc;
@@ -1355,6 +1382,7 @@ int bvc_tune_walks(bvc_scene s, const bvc_walk_params* p, int64_t n_cache, const
   }
   if (blocks_per_cu) *blocks_per_cu = best.blocks_per_cu;
   if (open_lanes) *open_lanes = best.open_lanes;
+  if (slabs) *slabs = best.slabs;
   return BVC_OK;
 }
 

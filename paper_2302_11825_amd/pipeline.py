@@ -818,7 +818,7 @@ def tune(prep: Prepared, with_grad=True, reps=3) -> dict:
     ex = torch.empty(d, max(n * W, 1), dtype=T, device=sc.device)
     w1 = torch.empty_like(U)
     counters = torch.zeros(4, dtype=torch.int64, device=sc.device)
-    bpc, lanes = B.bvc_tune_walks(sc.h, wp, n, cache.x, cache.nrm, cache.R0, cache.xbar, U, D, ex, w1, counters,
+    bpc, lanes, slabs = B.bvc_tune_walks(sc.h, wp, n, cache.x, cache.nrm, cache.R0, cache.xbar, U, D, ex, w1, counters,
                                   reps)
     _, _, a, b = reduce_walks(cache, W, U, D, dt)
     cview, sview = _gather_views(prep, cache, a, b, 0, _NoWatch())
@@ -826,7 +826,7 @@ def tune(prep: Prepared, with_grad=True, reps=3) -> dict:
     g = torch.empty(d, max(prep.n_int, 1), dtype=T, device=sc.device) if with_grad else None
     ppt = (B.bvc_tune_gather(d, cview, sview, prep.n_int, prep.x_int, u, g, reps, near=_near(prep, cache, U, D))
            if prep.n_int and p.sigma == 0 else 0)
-    return dict(walk_blocks_per_cu=bpc, walk_open_lanes=lanes, gather_points_per_thread=ppt)
+    return dict(walk_blocks_per_cu=bpc, walk_open_lanes=lanes, walk_slabs=slabs, gather_points_per_thread=ppt)
 
 
 def solve(prep: Prepared, batch=0, with_grad=True, n_walks_band=None, records=False, watch=None) -> Solution:

@@ -1,7 +1,8 @@
 """Autotuned launch shapes (marked gpu): the tuners pick among shapes that
 compute the same results, so every tuned launch must reproduce the default
 launch bit for bit, for the gather (points per thread) and for the walks
-(persistent grid size, traversal-loop exit threshold)."""
+(persistent grid size, traversal-loop exit threshold, and in 3D whether the
+slab bounds prune the traversal)."""
 import sys
 
 import numpy as np
@@ -59,12 +60,39 @@ def test_tuned_walks_are_bit_identical():
     U1, D1 = torch.empty_like(U0), torch.empty_like(D0)
     ex, w1 = torch.empty_like(rec0["exit"]), torch.empty_like(rec0["w1"])
     c1 = torch.zeros(4, dtype=torch.int64, device="cuda")
-    bpc, lanes = _bvc.bvc_tune_walks(sc.h, params, n, cache.x, cache.nrm, cache.R0, cache.xbar, U1, D1, ex, w1, c1,
-                                     reps=1)
+    bpc, lanes, slabs = _bvc.bvc_tune_walks(sc.h, params, n, cache.x, cache.nrm, cache.R0, cache.xbar, U1, D1, ex, w1,
+                                            c1, reps=1)
     U2, D2, rec2, c2 = pl.cache_walks(sc, cache, params, "f32")
     torch.cuda.synchronize()
     say(f"  chosen blocks per CU {bpc}, open lanes {lanes}")
-    assert bpc in (4, 8, 16) and lanes in (0, 8, 16, 32, 48)
+    assert bpc in (4, 8, 16) and lanes in (0, 8, 16, 32, 48) and slabs == 0
+    k = n * W
+    for U, D in ((U1, D1), (U2, D2)):
+        assert torch.equal(U[:k], U0[:k]) and torch.equal(D[:k], D0[:k])
+    assert torch.equal(rec2["exit"][:, :k], rec0["exit"][:, :k])
+    assert torch.equal(c2[1:], c0[1:]) and torch.equal(c1[1:], c0[1:])
+
+
+def test_tuned_walks_3d_are_bit_identical():
+    _bvc, pl = lib()
+    say("tune walks 3D")
+    scene = wl.displaced_icosphere(3, 31)
+    g = wl.solid_harmonics_3d(np.random.default_rng(1).normal(0, 1, 16), 3)
+    sc = pl.Scene(scene)
+    gd = pl.DeviceField(g)
+    cache = pl.sample_cache(sc, 6000, 2e-2, 1, 5, 0)
+    params = pl.walk_params(4e-3, 16, 78, gd, None, "f32")
+    U0, D0, rec0, c0 = pl.cache_walks(sc, cache, params, "f32")
+    n, W = cache.n, 16
+    U1, D1 = torch.empty_like(U0), torch.empty_like(D0)
+    ex, w1 = torch.empty_like(rec0["exit"]), torch.empty_like(rec0["w1"])
+    c1 = torch.zeros(4, dtype=torch.int64, device="cuda")
+    bpc, lanes, slabs = _bvc.bvc_tune_walks(sc.h, params, n, cache.x, cache.nrm, cache.R0, cache.xbar, U1, D1, ex, w1,
+                                            c1, reps=1)
+    U2, D2, rec2, c2 = pl.cache_walks(sc, cache, params, "f32")
+    torch.cuda.synchronize()
+    say(f"  chosen blocks per CU {bpc}, open lanes {lanes}, slabs {slabs}")
+    assert bpc in (4, 8, 16) and lanes in (0, 8, 16, 32, 48) and slabs in (0, 1)
     k = n * W
     for U, D in ((U1, D1), (U2, D2)):
         assert torch.equal(U[:k], U0[:k]) and torch.equal(D[:k], D0[:k])
