@@ -536,10 +536,10 @@ def run_workload(args, which):
                                     value)
         log(f"{which} pointwise {pointwise['walks_for_equal_rmse']} walks for equal RMSE")
 
-    # the traversal's slab bounds (3D): the tuned choice for the cache walks,
-    # the default of a bounded domain (on) for the band walks
+    # the traversal's slab bounds (3D): the tuned choices (default of a
+    # bounded domain: on)
     cache_slabs = bool((tuned or {}).get("walk_slabs", 1)) and dim == 3
-    band_slabs = dim == 3
+    band_slabs = bool((tuned or {}).get("band_slabs", 1)) and dim == 3
     cpu, work = None, None
     if not args.no_cpu:
         cpu, work = oracle_leg(prob, prep, sol, args.cpu_seconds, n_pts, dim, with_grad, pointwise,
@@ -557,7 +557,8 @@ def run_workload(args, which):
                                        measured_traffic(kname, which, WALK_SOURCES) if es == 4 else None,
                                        cache_slabs)
         other, other_valu = walk_roofline(f"k_walks<{T},3,false,1> (band-point walks)", 3, es, 1, False, band_ms,
-                                          int(sol.pw_counters[1]), int(sol.pw_counters[3]), "band", work, src, None)
+                                          int(sol.pw_counters[1]), int(sol.pw_counters[3]), "band", work, src, None,
+                                          band_slabs)
     else:
         # the band-point walks are the longest launch of the 2D step
         kname = f"k_walks<{T},2,true,1>"

@@ -597,6 +597,16 @@ int bvc_tune_walks(bvc_scene scene, const bvc_walk_params* params, int64_t n_cac
                    const double* nrm, const double* R0, const double* xbar, void* U, void* D,
                    void* rec_exit, void* rec_w1, uint64_t* counters, int32_t reps,
                    int32_t* blocks_per_cu, int32_t* open_lanes, int32_t* slabs, void* stream);
+/* The same search for the pointwise walks of bvc_pointwise_wos (arguments as
+ * there, plus reps and the outputs of bvc_tune_walks): the choice is kept for
+ * every later pointwise-walk launch of the class (band points, whose walks
+ * start within l of the boundary and take a few steps, favour other shapes
+ * than the cache walks).  u and grad hold the means on return.  Synchronises
+ * the stream. */
+int bvc_tune_pointwise(bvc_scene scene, const bvc_walk_params* params, int64_t n, const void* x, void* U_walk,
+                       void* G_walk, void* workspace, size_t workspace_bytes, void* u, void* grad,
+                       uint64_t* counters, int32_t reps, int32_t* blocks_per_cu, int32_t* open_lanes,
+                       int32_t* slabs, void* stream);
 
 /* Adjoint of the gather for dL/du = r [n_eval]:
  * dL/da_i = sum_k r_k dG/dn(x_k,z_i), dL/db_i = -sum_k r_k G(x_k,z_i),

@@ -119,6 +119,8 @@ _SIGS = {
                         _P(bvc_gather_params), C.c_int32, _P(C.c_int32), _vp],
     "bvc_tune_walks": [_vp, _P(bvc_walk_params), C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                        C.c_int32, _P(C.c_int32), _P(C.c_int32), _P(C.c_int32), _vp],
+    "bvc_tune_pointwise": [_vp, _P(bvc_walk_params), C.c_int64, _vp, _vp, _vp, _vp, C.c_size_t, _vp, _vp, _vp,
+                           C.c_int32, _P(C.c_int32), _P(C.c_int32), _P(C.c_int32), _vp],
     "bvc_gather_backward": [C.c_int32, _P(bvc_cache_view), _P(bvc_source_view), C.c_int64, _vp, _vp, _vp,
                             _vp, _vp, _vp, _vp],
     "bvc_basis_means": [_P(bvc_field), C.c_int32, C.c_int64, C.c_int32, C.c_int32, _vp, _vp, _vp, C.c_int32,
@@ -364,6 +366,18 @@ def bvc_reduce_walks(n_cache, W, dtype_in, U, D, w, uhat, dudn, dtype_out, a, b,
 def bvc_reduce_walks_count(n_cap, count, W, dtype_in, U, D, w, uhat, dudn, dtype_out, a, b, stream=None):
     _check(_L.bvc_reduce_walks_count(n_cap, ptr(count), W, dtype_in, ptr(U), ptr(D), ptr(w), ptr(uhat), ptr(dudn),
                                      dtype_out, ptr(a), ptr(b), stream_ptr(stream)), "bvc_reduce_walks_count")
+
+
+def bvc_tune_pointwise(scene, params: bvc_walk_params, n, x, U_walk, G_walk, work, u, grad, counters, reps=2,
+                       stream=None):
+    """Returns (blocks per compute unit, open lanes, slab bounds on) the library
+    keeps for this class of pointwise walks."""
+    bpc, lanes, slabs = C.c_int32(), C.c_int32(), C.c_int32()
+    nbytes = work.numel() * work.element_size() if work is not None else 0
+    _check(_L.bvc_tune_pointwise(scene, C.byref(params), n, ptr(x), ptr(U_walk), ptr(G_walk), ptr(work), nbytes,
+                                 ptr(u), ptr(grad), ptr(counters), reps, C.byref(bpc), C.byref(lanes),
+                                 C.byref(slabs), stream_ptr(stream)), "bvc_tune_pointwise")
+    return bpc.value, lanes.value, slabs.value
 
 
 def bvc_pointwise_workspace_bytes(dim, n, W, dtype, with_grad) -> int:

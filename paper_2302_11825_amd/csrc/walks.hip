@@ -1111,6 +1111,61 @@ int static_scratch(char** out) {
   return BVC_OK;
 }
 
+// Times one walk class over its launch shapes with `run` (one launch at a
+// forced shape, on `st`): the default shape first, in 3D then the other slab
+// setting at the default grid and threshold, then the grids of 4, 8 and 16
+// blocks per CU and thresholds of 0, 8, 16, 32 and 48 open lanes with the
+// slab setting kept.  A shape replaces the default only when at least 3%
+// faster, so that timing noise does not move the choice.
+template <typename Run>
+int search_shapes(int dim, bool open, int reps, hipStream_t st, const Run& run, WalkShape& best) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = check_hip(hipEventCreate(&e0), "tune event");
+  if (!rc) rc = check_hip(hipEventCreate(&e1), "tune event");
+  auto time_shape = [&](const WalkShape& sh, float& ms) -> int {
+    int r = run(sh);  // warm-up
+    if (!r) r = check_hip(hipEventRecord(e0, st), "tune event");
+    for (int k = 0; k < reps && !r; ++k) r = run(sh);
+    if (!r) r = check_hip(hipEventRecord(e1, st), "tune event");
+    if (!r) r = check_hip(hipEventSynchronize(e1), "tune sync");
+    ms = 0;
+    if (!r) r = check_hip(hipEventElapsedTime(&ms, e0, e1), "tune time");
+    return r;
+  };
+  const WalkShape def = default_shape(dim, open);
+  best = def;
+  float best_ms = INFINITY;
+  if (!rc) rc = time_shape(def, best_ms);
+  if (!rc && dim == 3) {
+    WalkShape flip = def;
+    flip.slabs = 1 - def.slabs;
+    float ms = 0;
+    rc = time_shape(flip, ms);
+    if (!rc && ms < 0.97f * best_ms) {
+      best = flip;
+      best_ms = ms;
+    }
+  }
+  const WalkShape base = best;
+  const float base_ms = best_ms;
+  const int bpc[3] = {4, 8, 16};
+  const int lanes[5] = {0, 8, 16, 32, 48};
+  for (int i = 0; i < 3 && !rc; ++i)
+    for (int j = 0; j < 5 && !rc; ++j) {
+      if (bpc[i] == base.blocks_per_cu && lanes[j] == base.open_lanes) continue;
+      const WalkShape sh{bpc[i], lanes[j], base.slabs};
+      float ms = 0;
+      rc = time_shape(sh, ms);
+      if (!rc && ms < best_ms && ms < 0.97f * base_ms) {
+        best_ms = ms;
+        best = sh;
+      }
+    }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  return rc;
+}
+
 int pointwise_check(bvc_scene s, const bvc_walk_params* p, int64_t n, const void* x, const void* u,
                     const uint64_t* counters) {
   int rc = check_scene(s);
@@ -1128,7 +1183,8 @@ int pointwise_check(bvc_scene s, const bvc_walk_params* p, int64_t n, const void
 // the layout of bvc_pointwise_workspace_bytes: R0 [n] FP64, xbar [dim][n]
 // FP64, exit records [dim][n W], first-ball weights [dim][n W] (grad only).
 int pointwise_run(bvc_scene s, const bvc_walk_params* p, int64_t n, const void* x, void* U_walk, void* G_walk,
-                  char* work, void* u, void* grad, uint64_t* counters, hipStream_t st) {
+                  char* work, void* u, void* grad, uint64_t* counters, hipStream_t st,
+                  const WalkShape* force = nullptr) {
   const int dim = s->h.dim;
   const size_t es = p->dtype == BVC_F64 ? 8 : 4;
   const size_t nw = (size_t)n * (size_t)p->n_walks;
@@ -1169,7 +1225,7 @@ int pointwise_run(bvc_scene s, const bvc_walk_params* p, int64_t n, const void* 
   a.exit = ex;
   a.w1 = gw;
   a.counters = (unsigned long long*)counters;
-  int rc = run_walks(s, p, 1, n, a, st);
+  int rc = run_walks(s, p, 1, n, a, st, force);
   if (rc || n == 0) return rc;
   const int per = kBlock / 64;
   const int blocks = (int)((n + per - 1) / per);
@@ -1323,62 +1379,50 @@ int bvc_tune_walks(bvc_scene s, const bvc_walk_params* p, int64_t n_cache, const
   q.blocks = 0;
   q.ev_begin = nullptr;
   q.ev_end = nullptr;
-  hipStream_t st = (hipStream_t)stream;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  rc = check_hip(hipEventCreate(&e0), "tune event");
-  if (!rc) rc = check_hip(hipEventCreate(&e1), "tune event");
-  // the default shape first: another is kept only when it is at least 3%
-  // faster, so that timing noise does not move the choice.  In 3D the other
-  // slab setting is tried first at the default grid and threshold; the grid
-  // and threshold are then searched with the setting kept.
-  auto time_shape = [&](const WalkShape& sh, float& ms) -> int {
-    int r = cache_walks_entry(s, &q, n_cache, x, nrm, R0, xbar, U, D, rec_exit, rec_w1, nullptr, counters, stream,
-                              &sh);  // warm-up
-    if (!r) r = check_hip(hipEventRecord(e0, st), "tune event");
-    for (int k = 0; k < reps && !r; ++k)
-      r = cache_walks_entry(s, &q, n_cache, x, nrm, R0, xbar, U, D, rec_exit, rec_w1, nullptr, counters, stream,
-                            &sh);
-    if (!r) r = check_hip(hipEventRecord(e1, st), "tune event");
-    if (!r) r = check_hip(hipEventSynchronize(e1), "tune sync");
-    ms = 0;
-    if (!r) r = check_hip(hipEventElapsedTime(&ms, e0, e1), "tune time");
-    return r;
-  };
-  const WalkShape def = default_shape(s->h.dim, p->open_radius > 0.0);
-  WalkShape best = def;
-  float best_ms = INFINITY;
-  if (!rc) rc = time_shape(def, best_ms);
-  if (!rc && s->h.dim == 3) {
-    WalkShape flip = def;
-    flip.slabs = 1 - def.slabs;
-    float ms = 0;
-    rc = time_shape(flip, ms);
-    if (!rc && ms < 0.97f * best_ms) {
-      best = flip;
-      best_ms = ms;
-    }
-  }
-  const WalkShape base = best;
-  const float base_ms = best_ms;
-  const int bpc[3] = {4, 8, 16};
-  const int lanes[5] = {0, 8, 16, 32, 48};
-  for (int i = 0; i < 3 && !rc; ++i)
-    for (int j = 0; j < 5 && !rc; ++j) {
-      if (bpc[i] == base.blocks_per_cu && lanes[j] == base.open_lanes) continue;
-      const WalkShape sh{bpc[i], lanes[j], base.slabs};
-      float ms = 0;
-      rc = time_shape(sh, ms);
-      if (!rc && ms < best_ms && ms < 0.97f * base_ms) {
-        best_ms = ms;
-        best = sh;
-      }
-    }
-  if (e0) (void)hipEventDestroy(e0);
-  if (e1) (void)hipEventDestroy(e1);
+  WalkShape best{};
+  rc = search_shapes(s->h.dim, p->open_radius > 0.0, reps, (hipStream_t)stream,
+                     [&](const WalkShape& sh) {
+                       return cache_walks_entry(s, &q, n_cache, x, nrm, R0, xbar, U, D, rec_exit, rec_w1, nullptr,
+                                                counters, stream, &sh);
+                     },
+                     best);
   if (rc) return rc;
   {
     std::lock_guard<std::mutex> lock(g_walk_mu);
     g_walk_shape[walk_class(s->h.dim, p, 0)] = best;
+  }
+  if (blocks_per_cu) *blocks_per_cu = best.blocks_per_cu;
+  if (open_lanes) *open_lanes = best.open_lanes;
+  if (slabs) *slabs = best.slabs;
+  return BVC_OK;
+}
+
+int bvc_tune_pointwise(bvc_scene s, const bvc_walk_params* p, int64_t n, const void* x, void* U_walk, void* G_walk,
+                       void* work, size_t work_bytes, void* u, void* grad, uint64_t* counters, int32_t reps,
+                       int32_t* blocks_per_cu, int32_t* open_lanes, int32_t* slabs, void* stream) {
+  int rc = pointwise_check(s, p, n, x, u, counters);
+  if (rc) return rc;
+  if (reps < 1) return fail(BVC_EINVAL, "reps must be >= 1");
+  if (n > 0 && (!U_walk || !work)) return fail(BVC_EINVAL, "null per-walk scratch or workspace");
+  if (grad && !G_walk) return fail(BVC_EINVAL, "grad needs G_walk scratch");
+  const size_t need = bvc_pointwise_workspace_bytes(s->h.dim, n, p->n_walks, p->dtype, grad != nullptr);
+  if (n > 0 && work_bytes < need) return fail(BVC_EINVAL, "pointwise workspace too small");
+  if (((uintptr_t)work & 255) != 0) return fail(BVC_EINVAL, "workspace must be 256-byte aligned");
+  bvc_walk_params q = *p;
+  q.blocks = 0;
+  q.ev_begin = nullptr;
+  q.ev_end = nullptr;
+  WalkShape best{};
+  rc = search_shapes(s->h.dim, p->open_radius > 0.0, reps, (hipStream_t)stream,
+                     [&](const WalkShape& sh) {
+                       return pointwise_run(s, &q, n, x, U_walk, G_walk, (char*)work, u, grad, counters,
+                                            (hipStream_t)stream, &sh);
+                     },
+                     best);
+  if (rc) return rc;
+  {
+    std::lock_guard<std::mutex> lock(g_walk_mu);
+    g_walk_shape[walk_class(s->h.dim, p, 1)] = best;
   }
   if (blocks_per_cu) *blocks_per_cu = best.blocks_per_cu;
   if (open_lanes) *open_lanes = best.open_lanes;

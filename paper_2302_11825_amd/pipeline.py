@@ -826,7 +826,23 @@ def tune(prep: Prepared, with_grad=True, reps=3) -> dict:
     g = torch.empty(d, max(prep.n_int, 1), dtype=T, device=sc.device) if with_grad else None
     ppt = (B.bvc_tune_gather(d, cview, sview, prep.n_int, prep.x_int, u, g, reps, near=_near(prep, cache, U, D))
            if prep.n_int and p.sigma == 0 else 0)
-    return dict(walk_blocks_per_cu=bpc, walk_open_lanes=lanes, walk_slabs=slabs, gather_points_per_thread=ppt)
+    out = dict(walk_blocks_per_cu=bpc, walk_open_lanes=lanes, walk_slabs=slabs, gather_points_per_thread=ppt)
+    nb = prep.n_band
+    if nb:
+        # the band points' pointwise walks: another class with its own shape
+        wpb = walk_params(p.eps, p.n_walks, p.seed_walks, prep.g, prep.f, dt, 0, sigma=p.sigma,
+                          open_sphere=p.extra.get("open_sphere"), side_read=p.side_read)
+        xb = prep.x_band[:, :nb].contiguous()
+        Uw = torch.empty(nb * p.n_walks, dtype=T, device=sc.device)
+        Gw = torch.empty(d, nb * p.n_walks, dtype=T, device=sc.device) if with_grad else None
+        work = torch.empty(B.bvc_pointwise_workspace_bytes(d, nb, p.n_walks, B.dtype_code(T), with_grad),
+                           dtype=torch.uint8, device=sc.device)
+        ub = torch.empty(nb, dtype=T, device=sc.device)
+        gb = torch.empty(d, nb, dtype=T, device=sc.device) if with_grad else None
+        cnt = torch.zeros(4, dtype=torch.int64, device=sc.device)
+        bpb, lb, sb = B.bvc_tune_pointwise(sc.h, wpb, nb, xb, Uw, Gw, work, ub, gb, cnt, reps)
+        out.update(band_blocks_per_cu=bpb, band_open_lanes=lb, band_slabs=sb)
+    return out
 
 
 def solve(prep: Prepared, batch=0, with_grad=True, n_walks_band=None, records=False, watch=None) -> Solution:

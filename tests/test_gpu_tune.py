@@ -98,3 +98,37 @@ def test_tuned_walks_3d_are_bit_identical():
         assert torch.equal(U[:k], U0[:k]) and torch.equal(D[:k], D0[:k])
     assert torch.equal(rec2["exit"][:, :k], rec0["exit"][:, :k])
     assert torch.equal(c2[1:], c0[1:]) and torch.equal(c1[1:], c0[1:])
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_tuned_pointwise_walks_are_bit_identical(dim):
+    _bvc, pl = lib()
+    say(f"tune pointwise walks dim={dim}")
+    if dim == 2:
+        scene = small_star()
+        g, f = c2_like_fields()
+        fd = pl.DeviceField(f)
+    else:
+        scene = wl.displaced_icosphere(3, 31)
+        g = wl.solid_harmonics_3d(np.random.default_rng(1).normal(0, 1, 16), 3)
+        fd = None
+    sc = pl.Scene(scene)
+    gd = pl.DeviceField(g)
+    osc_pts = wl.uniform_box(3000, np.array(scene.bbox[0]) * 0.5, np.array(scene.bbox[1]) * 0.5, 5)
+    x = torch.from_numpy(np.ascontiguousarray(osc_pts.T)).to("cuda", torch.float32)
+    n, W = x.shape[1], 16
+    params = pl.walk_params(3e-3, W, 79, gd, fd, "f32")
+    u0, g0, c0 = pl.pointwise(sc, params, x, with_grad=True)
+    Uw = torch.empty(n * W, dtype=torch.float32, device="cuda")
+    Gw = torch.empty(dim, n * W, dtype=torch.float32, device="cuda")
+    work = torch.empty(_bvc.bvc_pointwise_workspace_bytes(dim, n, W, _bvc.F32, True), dtype=torch.uint8, device="cuda")
+    u1, g1 = torch.empty_like(u0), torch.empty_like(g0)
+    c1 = torch.zeros(4, dtype=torch.int64, device="cuda")
+    bpc, lanes, slabs = _bvc.bvc_tune_pointwise(sc.h, params, n, x, Uw, Gw, work, u1, g1, c1, reps=1)
+    u2, g2, c2 = pl.pointwise(sc, params, x, with_grad=True)
+    torch.cuda.synchronize()
+    say(f"  chosen blocks per CU {bpc}, open lanes {lanes}, slabs {slabs}")
+    assert bpc in (4, 8, 16) and lanes in (0, 8, 16, 32, 48) and slabs in ((0,) if dim == 2 else (0, 1))
+    for u, gr in ((u1, g1), (u2, g2)):
+        assert torch.equal(u, u0) and torch.equal(gr, g0)
+    assert torch.equal(c2[1:], c0[1:]) and torch.equal(c1[1:], c0[1:])
