@@ -141,8 +141,14 @@ def lib():
         L.orc_greens_sigma.argtypes = [C.c_int, C.c_double, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
         L.orc_screen_ball_weight.argtypes = [C.c_int, C.c_double, C.c_double]
         L.orc_screen_ball_weight.restype = C.c_double
+        L.orc_sample_grad_source.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int, _dp,
+                                             C.c_double, _dp, _dp, C.POINTER(C.c_double)]
+        L.orc_sample_grad_source.restype = C.c_double
         L.orc_screen_grad_weight.argtypes = [C.c_int, C.c_double, C.c_double]
         L.orc_screen_grad_weight.restype = C.c_double
+        for nm in ("orc_screen_source_ratio", "orc_screen_grad_source_ratio"):
+            getattr(L, nm).argtypes = [C.c_int, C.c_double, C.c_double, C.c_double]
+            getattr(L, nm).restype = C.c_double
         L.orc_gather_sigma.argtypes = [C.c_int, C.c_double, C.c_int64, _dp, C.c_int64, _dp, _dp, _dp, _dp,
                                        C.c_int64, _dp, _dp, _dp, _dp, _dp]
         L.orc_wost_walks.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(_Field), C.POINTER(_Field),
@@ -522,6 +528,16 @@ def sample_direction(seed, k, id_, batch, tag, dim):
     return nu
 
 
+def sample_grad_source(seed, id_, batch, tag, dim, c, R):
+    """(t, yhat, y, m) of the first ball's gradient source sample."""
+    yhat = np.zeros(dim)
+    y = np.zeros(dim)
+    m = C.c_double()
+    t = lib().orc_sample_grad_source(seed, id_, batch, tag, dim, _d(_f64(c)), float(R), _d(yhat), _d(y),
+                                     C.byref(m))
+    return t, yhat, y, m.value
+
+
 def sample_ball_source(seed, k, id_, batch, tag, dim, c, R):
     y = np.zeros(dim)
     lib().orc_sample_ball_source(seed, k, id_, batch, tag, dim, _d(_f64(c)), float(R), _d(y))
@@ -617,6 +633,14 @@ def screen_ball_weight(dim, sigma, R):
 
 def screen_grad_weight(dim, sigma, R):
     return lib().orc_screen_grad_weight(int(dim), float(sigma), float(R))
+
+
+def screen_source_ratio(dim, sigma, R, t):
+    return lib().orc_screen_source_ratio(int(dim), float(sigma), float(R), float(t))
+
+
+def screen_grad_source_ratio(dim, sigma, R, t):
+    return lib().orc_screen_grad_source_ratio(int(dim), float(sigma), float(R), float(t))
 
 
 def gather_sigma(dim, sigma, ex, cy, cn, a, b, sy=None, sw=None, with_grad=True, with_cond=False):

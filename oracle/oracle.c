@@ -651,6 +651,11 @@ double orc_field_eval(const orc_field* F, int dim, const double* x) {
       if (phi < 0) phi += 2 * ORC_PI;
       return p[0] * pow(hypot(dx, dy), p[1]) * cos(p[1] * phi);
     }
+    case ORC_FIELD_QUADRATIC: {
+      double r2 = 0;
+      for (int a = 0; a < dim; ++a) r2 += (x[a] - p[2 + a]) * (x[a] - p[2 + a]);
+      return p[0] * r2 + p[1];
+    }
   }
   return 0.0;
 }
@@ -803,6 +808,45 @@ double orc_screen_grad_weight(int dim, double sigma, double R) {
   double s = sqrt(sigma), x = s * R;
   if (dim == 2) return s / bessel_i(1, x);
   return s / sph_i1(x);
+}
+
+/* The in-ball source term of the screened equation (Eq. 1 with sigma > 0 and
+ * f != 0).  Ball B(c, R), point y at r = t R from c.  The screened ball
+ * Green's function (zero on the sphere, for -Lap + sigma) is
+ *   2D  [K0(s r) - K0(s R) I0(s r) / I0(s R)] / (2 pi),
+ *   3D  sinh(s (R - r)) / (4 pi r sinh(s R)),           s = sqrt(sigma),
+ * and the walks sample y from the Laplace one, ln(R/r)/(2 pi) or
+ * (1/r - 1/R)/(4 pi); this is the ratio of the two, in (0, 1].  It tends to 1
+ * as sigma -> 0. */
+double orc_screen_source_ratio(int dim, double sigma, double R, double t) {
+  if (!(sigma > 0)) return 1.0;
+  double s = sqrt(sigma), r = t * R;
+  if (dim == 2) {
+    double num = orc_bessel_k0(s * r) - orc_bessel_k0(s * R) * bessel_i(0, s * r) / bessel_i(0, s * R);
+    return num / -log(t);
+  }
+  double z = s * R * (1 - t);
+  double shz = z < 1e-8 ? 1.0 : sinh(z) / z; /* sinh(z)/z */
+  return s * R * shz / sinh(s * R);
+}
+
+/* The same ratio for the gradient of the in-ball source term at the centre
+ * (the first ball of Eq. 7): the centre gradient of the screened ball
+ * Green's function points along y - c with magnitude
+ *   2D  s [K1(s r) - I1(s r) K1(s R) / I1(s R)] / (2 pi),
+ *   3D  [e^(-s r)(1 + s r)/r^2 - e^(-s R)(1 + s R)/R^2 i1(s r)/i1(s R)] / (4 pi)
+ * (the free-space kernel's radial derivative minus the order-1 mode of the
+ * part that cancels it on the sphere), against the Laplace magnitudes
+ * (1/r - r/R^2)/(2 pi) and (1/r^2 - r/R^3)/(4 pi). */
+double orc_screen_grad_source_ratio(int dim, double sigma, double R, double t) {
+  if (!(sigma > 0)) return 1.0;
+  double s = sqrt(sigma), r = t * R;
+  if (dim == 2) {
+    double num = s * (orc_bessel_k1(s * r) - bessel_i(1, s * r) * orc_bessel_k1(s * R) / bessel_i(1, s * R));
+    return num / (1 / r - r / (R * R));
+  }
+  double num = exp(-s * r) * (1 + s * r) - exp(-s * R) * (1 + s * R) * t * t * sph_i1(s * r) / sph_i1(s * R);
+  return num / (1 - t * t * t);
 }
 
 void orc_gather_sigma(int dim, double sigma, int64_t K, const double* ex, int64_t N, const double* cy,
@@ -1184,8 +1228,8 @@ static void walk_direction(uint64_t seed, uint32_t k, uint32_t id, uint32_t batc
 /* Point of a ball B(c, R) drawn with density proportional to |G^B(c, .)|:
  * radius fraction sqrt(U1 U2) in 2D (density 4 s ln(1/s)), median of three
  * uniforms in 3D (density 6 s (1-s)); direction uniform.  Blocks 4k+1..4k+3. */
-static void ball_source_point(uint64_t seed, uint32_t k, uint32_t id, uint32_t batch,
-                              uint32_t tag, int dim, const double* c, double R, double* y) {
+static double ball_source_point(uint64_t seed, uint32_t k, uint32_t id, uint32_t batch,
+                                uint32_t tag, int dim, const double* c, double R, double* y) {
   double u1, u2, u3, u4, u5, u6;
   orc_uniform_pair(seed, 4 * k + 1, id, batch, tag, &u1, &u2);
   orc_uniform_pair(seed, 4 * k + 2, id, batch, tag, &u3, &u4);
@@ -1194,23 +1238,67 @@ static void ball_source_point(uint64_t seed, uint32_t k, uint32_t id, uint32_t b
     double th = 2 * ORC_PI * u3;
     y[0] = c[0] + R * s * cos(th);
     y[1] = c[1] + R * s * sin(th);
-  } else {
-    double lo = u1 < u2 ? u1 : u2, hi = u1 < u2 ? u2 : u1;
-    double s = u3 < lo ? lo : (u3 > hi ? hi : u3);
-    orc_uniform_pair(seed, 4 * k + 3, id, batch, tag, &u5, &u6);
-    double z = 1 - 2 * u5;
-    double rho = sqrt(fmax(0.0, 1 - z * z));
-    double ph = 2 * ORC_PI * u6;
-    y[0] = c[0] + R * s * rho * cos(ph);
-    y[1] = c[1] + R * s * rho * sin(ph);
-    y[2] = c[2] + R * s * z;
+    return s;
   }
+  double lo = u1 < u2 ? u1 : u2, hi = u1 < u2 ? u2 : u1;
+  double s = u3 < lo ? lo : (u3 > hi ? hi : u3);
+  orc_uniform_pair(seed, 4 * k + 3, id, batch, tag, &u5, &u6);
+  double z = 1 - 2 * u5;
+  double rho = sqrt(fmax(0.0, 1 - z * z));
+  double ph = 2 * ORC_PI * u6;
+  y[0] = c[0] + R * s * rho * cos(ph);
+  y[1] = c[1] + R * s * rho * sin(ph);
+  y[2] = c[2] + R * s * z;
+  return s;
+}
+
+/* The gradient source sample of the first ball (Eq. 7 with a source): the
+ * centre gradient of the in-ball source term, minus the integral of
+ * grad_x G^B(c, y) f(y), is E[-m(t) R y_hat f(y)] with y = c + t R y_hat:
+ *   2D  t from the density (3/2)(1 - t^2), m = 2/3 (the Laplace magnitude
+ *       integrates to 2R/3 over the disk), y_hat at angle 2 pi U3;
+ *   3D  t uniform, m = 1 - t^3 (the magnitude's radial density (4/3)(1 - t^3)
+ *       times its integral 3R/4), y_hat uniform on the sphere.
+ * Uniforms: 2D the second of block 2 and the first of block 3 (tag); 3D
+ * block 0 (direction) and the first of block 1 under tag | 128.  Returns t;
+ * *m receives the weight. */
+static double grad_source_point(uint64_t seed, uint32_t id, uint32_t batch, uint32_t tag, int dim,
+                                const double* c, double R, double* yhat, double* y, double* m) {
+  if (dim == 2) {
+    double u1, u2, u3, u4;
+    orc_uniform_pair(seed, 2, id, batch, tag, &u1, &u2);
+    orc_uniform_pair(seed, 3, id, batch, tag, &u3, &u4);
+    double t = 2 * sin(asin(u2) / 3);
+    double th = 2 * ORC_PI * u3;
+    yhat[0] = cos(th);
+    yhat[1] = sin(th);
+    y[0] = c[0] + R * t * yhat[0];
+    y[1] = c[1] + R * t * yhat[1];
+    *m = 2.0 / 3.0;
+    return t;
+  }
+  double a, b, t, w;
+  orc_uniform_pair(seed, 0, id, batch, tag | 128u, &a, &b);
+  orc_uniform_pair(seed, 1, id, batch, tag | 128u, &t, &w);
+  double z = 1 - 2 * a;
+  double rho = sqrt(fmax(0.0, 1 - z * z));
+  double ph = 2 * ORC_PI * b;
+  yhat[0] = rho * cos(ph);
+  yhat[1] = rho * sin(ph);
+  yhat[2] = z;
+  for (int q = 0; q < 3; ++q) y[q] = c[q] + R * t * yhat[q];
+  *m = 1 - t * t * t;
+  return t;
 }
 
 /* Exported views of the two samplers above, for the density tests. */
 void orc_sample_direction(uint64_t seed, uint32_t k, uint32_t id, uint32_t batch, uint32_t tag,
                           int dim, double* nu) {
   walk_direction(seed, k, id, batch, tag, dim, nu);
+}
+double orc_sample_grad_source(uint64_t seed, uint32_t id, uint32_t batch, uint32_t tag, int dim,
+                              const double* c, double R, double* yhat, double* y, double* m) {
+  return grad_source_point(seed, id, batch, tag, dim, c, R, yhat, y, m);
 }
 void orc_sample_ball_source(uint64_t seed, uint32_t k, uint32_t id, uint32_t batch, uint32_t tag,
                             int dim, const double* c, double R, double* y) {
@@ -1322,29 +1410,22 @@ void orc_walk(const orc_scene* s, const orc_field* g, const orc_field* f,
   for (int a = 0; a < dim; ++a) pos[a] = x[a] + R0 * nu0[a];
   const int open = dim == 3 && p->open_radius > 0;
   int escaped = open && open_step(p, 0, id, tag, pos);
-  double f_u = 0, f_g = 0, yhat_g[3] = {0, 0, 0};
+  const int screened = p->sigma > 0;
+  /* the first ball's source terms: u (weight R0^2/(2 dim) times the screened
+   * ratio) and the gradient (weight m(t) R0 times its screened ratio) */
+  double src_u = 0, src_g = 0, yhat_g[3] = {0, 0, 0};
   if (has_f) {
-    double yu[3];
-    ball_source_point(p->seed, 0, id, p->batch, tag, dim, x, R0, yu);
-    f_u = orc_field_eval(f, dim, yu);
-    if (dim == 2) {
-      /* gradient source sample: radius density (3/2)(1 - s^2) */
-      double u1, u2, u3, u4;
-      orc_uniform_pair(p->seed, 2, id, p->batch, tag, &u1, &u2);
-      orc_uniform_pair(p->seed, 3, id, p->batch, tag, &u3, &u4);
-      double sg = 2 * sin(asin(u2) / 3);
-      double th = 2 * ORC_PI * u3;
-      yhat_g[0] = cos(th);
-      yhat_g[1] = sin(th);
-      double yg[2] = {x[0] + R0 * sg * yhat_g[0], x[1] + R0 * sg * yhat_g[1]};
-      f_g = orc_field_eval(f, dim, yg);
-    }
+    double yu[3], yg[3], m;
+    double tu = ball_source_point(p->seed, 0, id, p->batch, tag, dim, x, R0, yu);
+    src_u = R0 * R0 / (2.0 * dim) * orc_screen_source_ratio(dim, p->sigma, R0, tu) * orc_field_eval(f, dim, yu);
+    double tg = grad_source_point(p->seed, id, p->batch, tag, dim, x, R0, yhat_g, yg, &m);
+    src_g = m * R0 * orc_screen_grad_source_ratio(dim, p->sigma, R0, tg) * orc_field_eval(f, dim, yg);
   }
   /* Walk on spheres from the first-ball point.  With screening every ball
-   * the walk crosses multiplies the estimate by its mean-value factor; the
+   * the walk crosses multiplies the estimate by its mean-value factor, and a
+   * ball's source term counts with the factors of the balls before it; the
    * first ball's factor is applied to U below, not to W (the estimate of u at
    * the first-ball point that the gradient uses). */
-  const int screened = p->sigma > 0;
   double S = 0, W = 0, pb[3] = {0, 0, 0}, thr = 1.0;
   int32_t k;
   for (k = 1;; ++k) {
@@ -1361,15 +1442,15 @@ void orc_walk(const orc_scene* s, const orc_field* g, const orc_field* f,
       double e[3] = {0, 0, 0};
       read_point(p, dim, pos, pb, d, e);
       for (int a = 0; a < dim; ++a) pb[a] = e[a];
-      W = screened ? thr * orc_field_eval(g, dim, pb) : orc_field_eval(g, dim, pb) + S;
+      W = thr * orc_field_eval(g, dim, pb) + S;
       break;
     }
-    if (screened) thr *= orc_screen_ball_weight(dim, p->sigma, d);
     if (has_f) {
       double y[3];
-      ball_source_point(p->seed, (uint32_t)k, id, p->batch, tag, dim, pos, d, y);
-      S -= d * d / (2.0 * dim) * orc_field_eval(f, dim, y);
+      double t = ball_source_point(p->seed, (uint32_t)k, id, p->batch, tag, dim, pos, d, y);
+      S -= thr * d * d / (2.0 * dim) * orc_screen_source_ratio(dim, p->sigma, d, t) * orc_field_eval(f, dim, y);
     }
+    if (screened) thr *= orc_screen_ball_weight(dim, p->sigma, d);
     double nu[3];
     walk_direction(p->seed, (uint32_t)k, id, p->batch, tag, dim, nu);
     for (int a = 0; a < dim; ++a) pos[a] += d * nu[a];
@@ -1378,19 +1459,17 @@ void orc_walk(const orc_scene* s, const orc_field* g, const orc_field* f,
   *steps = k;
   double gw = dim / R0;
   if (screened) {
-    /* the screened in-ball source term is not built: a source is refused */
-    *U = has_f ? NAN : orc_screen_ball_weight(dim, p->sigma, R0) * W;
+    *U = orc_screen_ball_weight(dim, p->sigma, R0) * W - src_u;
     gw = orc_screen_grad_weight(dim, p->sigma, R0);
   } else {
-    *U = W - R0 * R0 / (2.0 * dim) * f_u;
+    *U = W - src_u;
   }
   /* the escape rule holds for the Laplace equation without a source only */
   if (open && (screened || has_f)) *U = NAN;
   double c = control_value(p, g, dim, x, xbar);
   double wn = 0;
   for (int a = 0; a < dim; ++a) {
-    grad[a] = gw * nu0[a] * (W - c);
-    if (has_f && dim == 2 && !screened) grad[a] -= 2.0 * R0 / 3.0 * yhat_g[a] * f_g;
+    grad[a] = gw * nu0[a] * (W - c) - yhat_g[a] * src_g;
     exit_pt[a] = pb[a];
     if (n) wn += nu0[a] * n[a];
   }

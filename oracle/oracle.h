@@ -57,7 +57,8 @@ enum {
   ORC_FIELD_FOURIER_2D = 6,
   ORC_FIELD_POINT_SOURCE = 7,
   ORC_FIELD_EXP_PLANE = 8,
-  ORC_FIELD_WEDGE_2D = 9
+  ORC_FIELD_WEDGE_2D = 9,
+  ORC_FIELD_QUADRATIC = 10 /* A |x - x0|^2 + B: A = param[0], B = param[1], x0 = param[2..] */
 };
 
 typedef struct {
@@ -157,9 +158,12 @@ int orc_sphere_reentry(const double* c, double Rb, const double* x, double u, do
 
 /* One walk.  mode 0: cache walk (tag 1, first ball without termination test);
  * mode 1: pointwise walk (tag 2, returns g(xbar) when R0 < eps).  With
- * p->sigma > 0 (screened, source term must be zero) every ball multiplies the
- * estimate by orc_screen_ball_weight and the gradient uses
- * orc_screen_grad_weight instead of dim/R0; U is NaN if a source is given.
+ * p->sigma > 0 (screened) every ball multiplies the estimate by
+ * orc_screen_ball_weight and the gradient uses orc_screen_grad_weight instead
+ * of dim/R0.  With a source f every ball adds -R^2/(2 dim) f(y) times
+ * orc_screen_source_ratio (1 without screening), y from the Laplace ball
+ * density, weighted by the factors of the balls before it; the first ball's
+ * gradient adds its centre-gradient source sample (see grad_source_point).
  * With p->open_radius > 0 (3D, Laplace, no source) a walk that lands outside
  * the enclosing sphere draws orc_sphere_reentry's uniforms from the Philox
  * counters (jump index, id, batch, tag | 8) and (..., tag | 16); an escaped walk
@@ -173,6 +177,10 @@ void orc_walk(const orc_scene* s, const orc_field* g, const orc_field* f,
 
 void orc_sample_direction(uint64_t seed, uint32_t k, uint32_t id, uint32_t batch, uint32_t tag,
                           int dim, double* nu);
+/* The first ball's gradient source sample (returns t; yhat, y and the weight
+ * m(t) as described at grad_source_point). */
+double orc_sample_grad_source(uint64_t seed, uint32_t id, uint32_t batch, uint32_t tag, int dim,
+                              const double* c, double R, double* yhat, double* y, double* m);
 void orc_sample_ball_source(uint64_t seed, uint32_t k, uint32_t id, uint32_t batch, uint32_t tag,
                             int dim, const double* c, double R, double* y);
 double orc_grad_radius(double u);
@@ -245,6 +253,11 @@ void orc_greens_sigma(int dim, double sigma, const double* x, const double* y, c
  * 1 and dim/R. */
 double orc_screen_ball_weight(int dim, double sigma, double R);
 double orc_screen_grad_weight(int dim, double sigma, double R);
+/* Screened over Laplace ball Green's function at r = t R (in-ball source term)
+ * and the same ratio for the centre gradient of the in-ball source term; 1 at
+ * sigma = 0. */
+double orc_screen_source_ratio(int dim, double sigma, double R, double t);
+double orc_screen_grad_source_ratio(int dim, double sigma, double R, double t);
 /* orc_gather with the screened kernels (sigma = 0: orc_gather). */
 void orc_gather_sigma(int dim, double sigma, int64_t K, const double* ex, int64_t N, const double* cy,
                       const double* cn, const double* a, const double* b, int64_t M, const double* sy,

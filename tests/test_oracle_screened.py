@@ -192,12 +192,3 @@ def test_screened_walks_converge(dim):
         assert abs(ds.mean() - n @ a * ux) < 5 * se(ds) + 2e-3 * ux
         assert us.std() > 0  # the weights vary walk to walk
 
-
-def test_screened_walk_refuses_a_source():
-    scene = wl.circle_polygon(64)
-    osc = orc.Scene(scene)
-    P = orc.walk_params(1e-3, 1, 1, sigma=1.0)
-    x = np.array([0.1, 0.2])
-    d, xb, _ = osc.closest(x)
-    w = orc.walk(osc, wl.exp_plane(1.0, [1.0, 0.0]), wl.Field(1, np.zeros(0), (1.0,)), P, 1, x, None, d[0], xb[0], 3)
-    assert np.isnan(w["U"])

@@ -57,6 +57,7 @@ FIELD_FOURIER_2D = 6
 FIELD_POINT_SOURCE = 7
 FIELD_EXP_PLANE = 8
 FIELD_WEDGE_2D = 9
+FIELD_QUADRATIC = 10
 
 
 def seed(k: int, p: int) -> int:
@@ -119,6 +120,11 @@ def point_source(amp, x0) -> Field:
 
 def exp_plane(amp, a) -> Field:
     return Field(FIELD_EXP_PLANE, np.zeros(0), [amp, *a])
+
+
+def quadratic(A: float, B: float = 0.0, center=(0.0, 0.0, 0.0)) -> Field:
+    """A |x - center|^2 + B (Lap = 2 dim A)."""
+    return Field(FIELD_QUADRATIC, np.zeros(0), [A, B, *center])
 
 
 def wedge_2d(amp, p, center=(0.0, 0.0)) -> Field:
@@ -215,6 +221,9 @@ def field_value(fld: Field, x: np.ndarray) -> np.ndarray:
     if k == FIELD_EXP_PLANE:
         d = x.shape[1]
         return p[0] * np.exp(x @ p[1 : 1 + d])
+    if k == FIELD_QUADRATIC:
+        d = x.shape[1]
+        return p[0] * ((x - np.asarray(p[2 : 2 + d])[None, :]) ** 2).sum(1) + p[1]
     if k == FIELD_WEDGE_2D:
         dx, dy = x[:, 0] - p[2], x[:, 1] - p[3]
         phi = np.mod(np.arctan2(dy, dx), 2 * np.pi)
