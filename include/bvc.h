@@ -81,6 +81,9 @@ extern "C" {
  *                  p = param[1] (harmonic off the cut phi = 0; with p = 2/3
  *                  it has zero normal derivative on both edges of a 270
  *                  degree corner)
+ *  10 QUADRATIC    A |x - x0|^2 + B, A = param[0], B = param[1], x0 =
+ *                  param[2..] (Lap = 2 dim A; with a constant source it gives
+ *                  closed-form Poisson solutions)
  */
 typedef struct {
   int32_t kind;
@@ -271,13 +274,22 @@ typedef struct {
   void* ev_end;            /* and right after the walk kernel (NULL = none), to time
                               the traversal alone; ignored by the batch calls */
   double sigma;            /* screening coefficient of Lap u - sigma u = f (Eq. 1),
-                              >= 0.  sigma > 0 (f = ZERO; Appendix A.2): every
-                              ball of radius R multiplies the estimate by its
-                              mean-value factor, 1/I0(sR) in 2D and sR/sinh(sR)
-                              in 3D (s = sqrt(sigma)), and the ball gradient
-                              weight dim/R0 becomes s/I1(sR0) in 2D and
-                              s/i1(sR0) in 3D, i1(x) = (x cosh x - sinh x)/x^2.
-                              Not taken by the batch and clamping calls. */
+                              >= 0.  sigma > 0 (Appendix A.2): every ball of
+                              radius R multiplies the estimate by its mean-value
+                              factor, 1/I0(sR) in 2D and sR/sinh(sR) in 3D
+                              (s = sqrt(sigma)), and the ball gradient weight
+                              dim/R0 becomes s/I1(sR0) in 2D and s/i1(sR0) in
+                              3D, i1(x) = (x cosh x - sinh x)/x^2.  With a
+                              source f each ball's source sample (drawn from
+                              the Laplace ball density) is weighted by the
+                              ratio of the screened to the Laplace ball
+                              Green's function at its radius, and by the
+                              factors of the balls before it; the first
+                              ball's gradient source sample by the ratio of
+                              the centre gradients; these ratios are
+                              evaluated in FP64.  Such walks evaluate g at
+                              their exit themselves.  Not taken by the batch
+                              and clamping calls. */
   double open_center[3];   /* open (unbounded) 3D domains (Appendix B): the centre */
   double open_radius;      /* and radius of a sphere that encloses every vertex of
                               the scene; 0 = a bounded domain.  The domain is the
@@ -327,15 +339,19 @@ typedef struct {
  * source sample with density |G^B|), then walk on spheres until d < eps (or
  * max_steps queries, counted as capped), reading g at the closest point.
  * U[id]  = g(exit) + in-walk source sums - R0^2/(2 dim) f(y_u)
- * D[id]  = n_i . [(dim/R0) nu (W - c_i) - (2 R0/3) y_g f(y_g)]  (2D source term)
+ * D[id]  = n_i . [(dim/R0) nu (W - c_i) - m(t) R0 yhat f(y_g)]
+ * with the first ball's gradient source sample y_g = x_i + t R0 yhat: 2D t
+ * from the density (3/2)(1 - t^2), m = 2/3 (the second uniform of Philox
+ * block 2 and the first of block 3); 3D t uniform, m = 1 - t^3, yhat uniform
+ * on the sphere (blocks 0 and 1 under tag | 128).
  * Inputs x, nrm, xbar: [dim][n_cache] FP64; R0: [n_cache] FP64 (from
  * bvc_sample_cache after compaction).  U, D: [n_cache*W] of params->dtype.
  * Exit records (required; they are also the checkpoint the cache adjoint
  * reads instead of re-walking): rec_exit [dim][n_cache*W] of dtype (the
  * closest boundary point where the walk stopped), rec_w1 [n_cache*W]
  * ((dim/R0)(nu . n_i)); rec_steps int32 [n_cache*W] is optional.  The source
- * term f must be ZERO, CONST or GAUSS_SUM; g is evaluated in FP64 at the
- * exit points.  counters: device uint64[4], zeroed by the call: [0] work
+ * term f must be ZERO, CONST, GAUSS_SUM or EXP_PLANE; g is evaluated in FP64
+ * at the exit points (FP32 for the closed-form kinds when the walks are FP32).  counters: device uint64[4], zeroed by the call: [0] work
  * queue, [1] total closest-point queries, [2] capped walks, [3] walks. */
 int bvc_cache_walks(bvc_scene scene, const bvc_walk_params* params, int64_t n_cache,
                     const double* x, const double* nrm, const double* R0, const double* xbar,

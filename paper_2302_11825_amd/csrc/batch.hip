@@ -52,8 +52,8 @@ int plan_sizes(const bvc_batch_item* items, int n, int& dim, uint64_t& walks, in
     if (rc) return rc;
     rc = check_field(p.f, d, "f");
     if (rc) return rc;
-    if (p.f.kind != 0 && p.f.kind != 1 && p.f.kind != 3)
-      return fail(BVC_EUNSUPPORTED, "walk source terms are constants or Gaussian sums");
+    if (p.f.kind != 0 && p.f.kind != 1 && p.f.kind != 3 && p.f.kind != 8)
+      return fail(BVC_EUNSUPPORTED, "walk source terms are constants, Gaussian sums or exponential planes");
     if (p.sigma != 0.0) return fail(BVC_EUNSUPPORTED, "batched walks are built for sigma = 0");
     if (p.open_radius != 0.0) return fail(BVC_EUNSUPPORTED, "batched walks are built for bounded domains");
     if (p.side_read != 0) return fail(BVC_EUNSUPPORTED, "batched walks read g at the closest point (no side rule)");

@@ -90,10 +90,11 @@ __device__ __forceinline__ void walk_direction(uint64_t seed, uint32_t k, uint32
 }
 
 // Point of B(c, R) with density proportional to |G^B(c, .)| (blocks 4k+1..3):
-// radius fraction sqrt(U1 U2) in 2D, median of three uniforms in 3D.
+// radius fraction sqrt(U1 U2) in 2D, median of three uniforms in 3D.  Returns
+// the radius fraction.
 template <typename T, int D>
-__device__ __forceinline__ void ball_source_point(uint64_t seed, uint32_t k, uint32_t id, uint32_t batch,
-                                                  uint32_t tag, const T* c, T R, T* y) {
+__device__ __forceinline__ T ball_source_point(uint64_t seed, uint32_t k, uint32_t id, uint32_t batch,
+                                               uint32_t tag, const T* c, T R, T* y) {
   T u1, u2, u3, u4;
   Uniform<T>::pair(seed, 4u * k + 1u, id, batch, tag, u1, u2);
   Uniform<T>::pair(seed, 4u * k + 2u, id, batch, tag, u3, u4);
@@ -103,6 +104,7 @@ __device__ __forceinline__ void ball_source_point(uint64_t seed, uint32_t k, uin
     sincos_turns(u3, &sn, &cs);
     y[0] = c[0] + R * s * cs;
     y[1] = c[1] + R * s * sn;
+    return s;
   } else {
     T s = fmax(fmin(u1, u2), fmin(fmax(u1, u2), u3));
     T u5, u6;
@@ -114,6 +116,44 @@ __device__ __forceinline__ void ball_source_point(uint64_t seed, uint32_t k, uin
     y[0] = c[0] + R * s * rho * cs;
     y[1] = c[1] + R * s * rho * sn;
     y[2] = c[2] + R * s * z;
+    return s;
+  }
+}
+
+// The first ball's gradient source sample (Eq. 7 with a source): the centre
+// gradient of the in-ball source term is the mean of -m(t) R yhat f(y), with
+// y = c + t R yhat.  2D: t = 2 sin(asin(U)/3) (density (3/2)(1 - t^2)),
+// m = 2/3, U the second uniform of block 2 and the angle of yhat the first of
+// block 3 (tag); 3D: t uniform (the first uniform of block 1), m = 1 - t^3,
+// yhat uniform on the sphere from block 0, both under tag | 128.  Returns t.
+template <typename T, int D>
+__device__ __forceinline__ T grad_source_point(uint64_t seed, uint32_t id, uint32_t batch, uint32_t tag,
+                                               const T* c, T R, T* yhat, T* y, T& m) {
+  if constexpr (D == 2) {
+    T u1, u2, u3, u4;
+    Uniform<T>::pair(seed, 2, id, batch, tag, u1, u2);
+    Uniform<T>::pair(seed, 3, id, batch, tag, u3, u4);
+    const T t = T(2) * sin(asin(u2) / T(3));
+    sincos_turns(u3, &yhat[1], &yhat[0]);
+    y[0] = fma(R * t, yhat[0], c[0]);
+    y[1] = fma(R * t, yhat[1], c[1]);
+    m = T(2) / T(3);
+    return t;
+  } else {
+    T a, b, t, w;
+    Uniform<T>::pair(seed, 0, id, batch, tag | 128u, a, b);
+    Uniform<T>::pair(seed, 1, id, batch, tag | 128u, t, w);
+    const T z = T(1) - T(2) * a;
+    const T rho = fsqrt(fmax(T(0), T(1) - z * z));
+    T sn, cs;
+    sincos_turns(b, &sn, &cs);
+    yhat[0] = rho * cs;
+    yhat[1] = rho * sn;
+    yhat[2] = z;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) y[q] = fma(R * t, yhat[q], c[q]);
+    m = T(1) - t * t * t;
+    return t;
   }
 }
 
@@ -855,6 +895,11 @@ __device__ inline double field_value(const FieldDev& F, int dim, const double* x
       double phi = atan2(dy, dx);
       if (phi < 0.0) phi += 2.0 * kPi;
       return p[0] * pow(hypot(dx, dy), p[1]) * cos(p[1] * phi);
+    }
+    case 10: {
+      double r2 = 0.0;
+      for (int a = 0; a < dim; ++a) r2 += (x[a] - p[2 + a]) * (x[a] - p[2 + a]);
+      return p[0] * r2 + p[1];
     }
   }
   return 0.0;

@@ -483,7 +483,7 @@ int check_scene(bvc_scene s) {
 }
 
 int check_field(const bvc_field& f, int dim, const char* name) {
-  if (f.kind < 0 || f.kind > 9) return fail(BVC_EINVAL, std::string(name) + ": unknown field kind");
+  if (f.kind < 0 || f.kind > 10) return fail(BVC_EINVAL, std::string(name) + ": unknown field kind");
   if (f.kind == 9 && dim != 2) return fail(BVC_EINVAL, std::string(name) + ": 2D field used in 3D");
   if (f.n_coef < 0) return fail(BVC_EINVAL, std::string(name) + ": negative coefficient count");
   if (f.n_coef > 0 && !f.coef) return fail(BVC_EINVAL, std::string(name) + ": coefficients are null");

@@ -33,7 +33,8 @@ constexpr int kChunkMax = 256;
 
 struct WalkArgs {
   SceneDev S;
-  FieldDev f;      // source term: kinds 0, 1, 3
+  FieldDev f;      // source term: kinds 0, 1, 3, 8
+  FieldDev g;      // boundary data (read by the screened source walks at their exit)
   double eps;
   int max_steps;
   int W;
@@ -103,7 +104,8 @@ __device__ bool open_step(const WalkArgs& a, uint32_t k, uint32_t id, uint32_t t
   return false;
 }
 
-// In-walk source term in the walk's precision (constants and Gaussian sums).
+// In-walk source term in the walk's precision (constants, Gaussian sums and
+// exponential planes).
 // `scale` is 1/(2 sigma^2), times log2(e) in FP32, where the Gaussian factor
 // is taken as a power of two on the hardware exp2.
 template <typename T>
@@ -115,6 +117,13 @@ __device__ __forceinline__ T source_scale(const FieldDev& F) {
 template <typename T, int D>
 __device__ __forceinline__ T walk_source(const FieldDev& F, T scale, const T* y) {
   if (F.kind == 1) return (T)F.param[0];
+  if (F.kind == 8) {
+    // A e^(a.y)
+    T e = T(0);
+#pragma unroll
+    for (int q = 0; q < D; ++q) e = fma((T)F.param[1 + q], y[q], e);
+    return (T)F.param[0] * exp(e);
+  }
   const int ng = F.n_coef / (1 + D);
   T sum = T(0);
   for (int k = 0; k < ng; ++k) {
@@ -155,6 +164,84 @@ template <typename T, int D>
 __device__ __forceinline__ T screen_ball_weight(T x) {
   if constexpr (D == 3) return screen_ball_weight3<T>(x);
   else return T(1) / bessel_i0<T>(x);
+}
+
+// i1(x) = (x cosh x - sinh x) / x^2, the modified spherical Bessel function
+// of order 1, by its series sum_k x^(2k+1) / (2^k k! (2k+3)!!) below 1.
+__device__ inline double sph_i1(double x) {
+  if (x < 1.0) {
+    double term = x / 3.0, sum = term;
+    for (int k = 1; k < 14; ++k) {
+      term *= x * x / (2.0 * k * (2.0 * k + 3.0));
+      sum += term;
+    }
+    return sum;
+  }
+  return (x * cosh(x) - sinh(x)) / (x * x);
+}
+
+// In-ball source terms of the screened equation (sigma > 0 with a source), in
+// FP64 for both walk precisions.  Ball B(c, R), sample at r = t R, s =
+// sqrt(sigma).  The walks draw the point from the Laplace ball density and
+// weight the sample by the ratio of the screened to the Laplace ball Green's
+// function,
+//   2D [K0(s r) - K0(s R) I0(s r)/I0(s R)] / ln(R/r),
+//   3D R sinh(s (R - r)) / ((R - r) sinh(s R)),
+// and the first ball's gradient source sample by the ratio of the centre
+// gradients,
+//   2D s [K1(s r) - I1(s r) K1(s R)/I1(s R)] / (1/r - r/R^2),
+//   3D [e^(-s r)(1 + s r) - e^(-s R)(1 + s R) t^2 i1(s r)/i1(s R)] / (1 - t^3)
+// (the free-space kernel's radial derivative minus the order-1 mode of the
+// part that cancels it on the sphere).
+template <int D>
+__device__ inline double screen_source_ratio(double s, double R, double t) {
+  const double r = t * R;
+  if constexpr (D == 2) {
+    double k0r, k1r, k0R, k1R, i0r, i1r, i0R, i1R;
+    bessel_k01(s * r, k0r, k1r);
+    bessel_k01(s * R, k0R, k1R);
+    bessel_i01(s * r, i0r, i1r);
+    bessel_i01(s * R, i0R, i1R);
+    return (k0r - k0R * i0r / i0R) / -log(t);
+  } else {
+    const double z = s * R * (1.0 - t);
+    const double shz = z < 1e-8 ? 1.0 : sinh(z) / z;
+    return s * R * shz / sinh(s * R);
+  }
+}
+
+template <int D>
+__device__ inline double screen_grad_source_ratio(double s, double R, double t) {
+  const double r = t * R;
+  if constexpr (D == 2) {
+    double k0r, k1r, k0R, k1R, i0r, i1r, i0R, i1R;
+    bessel_k01(s * r, k0r, k1r);
+    bessel_k01(s * R, k0R, k1R);
+    bessel_i01(s * r, i0r, i1r);
+    bessel_i01(s * R, i0R, i1R);
+    return s * (k1r - i1r * k1R / i1R) / (1.0 / r - r / (R * R));
+  } else {
+    const double num = exp(-s * r) * (1.0 + s * r) - exp(-s * R) * (1.0 + s * R) * t * t * sph_i1(s * r) / sph_i1(s * R);
+    return num / (1.0 - t * t * t);
+  }
+}
+
+// The first ball's factors of a screened walk at x = s R0: the mean-value
+// factor P (2D 1/I0(x), 3D x/sinh x) and the ratio of the gradient weight to
+// dim/R0 (2D s/I1(x), 3D s/i1(x), times R0/dim).  k_finish applies the same
+// expressions.
+template <int D>
+__device__ inline void screen_first_ball(double s, double r0, double& P, double& ratio) {
+  const double x = s * r0;
+  if constexpr (D == 3) {
+    P = x < 1e-8 ? 1.0 : x / sinh(x);
+    ratio = s / sph_i1(x) * r0 / D;
+  } else {
+    double i0, i1;
+    bessel_i01(x, i0, i1);
+    P = 1.0 / i0;
+    ratio = s / i1 * r0 / D;
+  }
 }
 
 // Wave-private pool of walk ids [next, end) claimed from a global queue in
@@ -256,18 +343,28 @@ WalkShape tuned_shape(const WalkClass& k) {
   return it == g_walk_shape.end() ? default_shape(k.dim, k.open != 0) : it->second;
 }
 
-template <typename T, int D, bool SRC, int MODE, bool OPEN>
+// SS: screened walks with a source term (sigma > 0, f != 0), a kernel of their
+// own.  They carry the product of their balls' mean-value factors in thr and
+// the source terms (each weighted by the factors of the balls before it) in
+// acc_s, evaluate g at their exit themselves, and write U = W + usrc / P0
+// (W = acc_s + thr g(exit), usrc the first ball's source term, P0 its
+// factor), so that the finish's screened formulas (u = P0 U, D from U with
+// the first-ball source term moved into the D offset) apply unchanged.
+template <typename T, int D, bool SRC, int MODE, bool OPEN, bool SS = false>
 __device__ __forceinline__ void walks_body(const WalkArgs& a, uint32_t* lds) {
+  static_assert(!SS || SRC, "a screened source walk has a source");
   uint32_t* stk = lds + threadIdx.x;
   const int stride = blockDim.x;
   const int lane = threadIdx.x & 63;
   const uint32_t tag = MODE == 0 ? 1u : 2u;
   const T eps = (T)a.eps;
   const T src_scale = SRC && a.f.kind == 3 ? source_scale<T>(a.f) : T(0);
-  // screened walks (no source term) carry the product of their balls'
+  // screened walks without a source term carry the product of their balls'
   // mean-value factors in acc_s, the first ball's excepted
-  const bool scr = !SRC && a.sigma > 0.0;
+  const bool scr = (!SRC || SS) && a.sigma > 0.0;
   const T s_scr = scr ? (T)sqrt(a.sigma) : T(0);
+  const double s64 = SS ? sqrt(a.sigma) : 0.0;
+  T thr = T(1);
   const SceneDev& S = a.S;
   T* U = (T*)a.U;
   T* Dof = (T*)a.Dof;
@@ -340,7 +437,8 @@ __device__ __forceinline__ void walks_body(const WalkArgs& a, uint32_t* lds) {
                 p[q] = MODE != 1 ? (T)a.x[q * a.n_pts + i] : ((const T*)a.px)[q * a.n_pts + i];
               d = R0;
               k = 0;
-              acc_s = scr ? T(1) : T(0);
+              acc_s = scr && !SS ? T(1) : T(0);
+              thr = T(1);
               usrc = T(0);
               active = true;
               jump = true;
@@ -355,8 +453,9 @@ __device__ __forceinline__ void walks_body(const WalkArgs& a, uint32_t* lds) {
       const T coef = -d * d * (T(1) / T(2 * D));
       if constexpr (SRC) {
         T y[D];
-        ball_source_point<T, D>(a.seed, (uint32_t)k, id, a.batch, tag, p, d, y);
+        const T t = ball_source_point<T, D>(a.seed, (uint32_t)k, id, a.batch, tag, p, d, y);
         srcv = walk_source<T, D>(a.f, src_scale, y);
+        if constexpr (SS) srcv *= (T)screen_source_ratio<D>(s64, (double)d, (double)t);
       }
       T nu[D];
       walk_direction<T, D>(a.seed, (uint32_t)k, id, a.batch, tag, nu);
@@ -369,18 +468,24 @@ __device__ __forceinline__ void walks_body(const WalkArgs& a, uint32_t* lds) {
         T gs[D];
 #pragma unroll
         for (int q = 0; q < D; ++q) gs[q] = T(0);
-        if constexpr (SRC && D == 2) {
-          // gradient source sample, radius density (3/2)(1 - s^2)
-          T u1, u2, u3, u4;
-          Uniform<T>::pair(a.seed, 2, id, a.batch, tag, u1, u2);
-          Uniform<T>::pair(a.seed, 3, id, a.batch, tag, u3, u4);
-          const T sg = T(2) * sin(asin(u2) / T(3));
-          T sn, cs;
-          sincos_turns(u3, &sn, &cs);
-          const T yg[2] = {fma(d * sg, cs, p[0]), fma(d * sg, sn, p[1])};
-          const T c = -T(2) * d / T(3) * walk_source<T, D>(a.f, src_scale, yg);
-          gs[0] = c * cs;
-          gs[1] = c * sn;
+        if constexpr (SRC) {
+          // gradient source sample (the centre gradient of the in-ball source term)
+          T yhat[D], yg[D], m;
+          const T tg = grad_source_point<T, D>(a.seed, id, a.batch, tag, p, d, yhat, yg, m);
+          T c = -m * d * walk_source<T, D>(a.f, src_scale, yg);
+          if constexpr (SS) c *= (T)screen_grad_source_ratio<D>(s64, (double)d, (double)tg);
+#pragma unroll
+          for (int q = 0; q < D; ++q) gs[q] = c * yhat[q];
+        }
+        // a screened source walk moves its first-ball source term into U / P0
+        // and the D offset (the finish multiplies U by P0 and the gradient
+        // weight by the screening ratio)
+        T du = usrc;
+        if constexpr (SS) {
+          double P0, ratio;
+          screen_first_ball<D>(s64, (double)d, P0, ratio);
+          usrc = (T)((double)usrc / P0);
+          du = (T)((double)usrc * ratio);
         }
         if constexpr (MODE == 0) {
           T dn = T(0), ds = T(0);
@@ -392,15 +497,18 @@ __device__ __forceinline__ void walks_body(const WalkArgs& a, uint32_t* lds) {
           }
           const T w1 = wgt * dn;
           W1[id] = w1;
-          Dof[id] = ds - w1 * usrc;
+          Dof[id] = ds - w1 * du;
         } else if (MODE == 1 && Dof) {
 #pragma unroll
           for (int q = 0; q < D; ++q) {
             const T gw = wgt * nu[q];
             W1[(size_t)q * a.ld + id] = gw;
-            Dof[(size_t)q * a.ld + id] = gs[q] - gw * usrc;
+            Dof[(size_t)q * a.ld + id] = gs[q] - gw * du;
           }
         }
+      } else if constexpr (SS) {
+        acc_s = fma(thr * coef, srcv, acc_s);
+        thr *= screen_ball_weight<T, D>(s_scr * d);
       } else if constexpr (SRC) {
         acc_s = fma(coef, srcv, acc_s);
       } else if (scr) {
@@ -444,9 +552,30 @@ __device__ __forceinline__ void walks_body(const WalkArgs& a, uint32_t* lds) {
         // differ on the two sides of a boundary curve (double-sided
         // conditions, Appendix B) are read on this side
         const T t = a.side && d > T(0) ? fdiv(T(1e-3) * eps, d) : T(0);
+        T ex[D];
 #pragma unroll
-        for (int c = 0; c < D; ++c) EX[(size_t)c * a.ld + id] = fma(t, p[c] - qs.bq[c], qs.bq[c]);
-        U[id] = acc_s + usrc;
+        for (int c = 0; c < D; ++c) {
+          ex[c] = fma(t, p[c] - qs.bq[c], qs.bq[c]);
+          EX[(size_t)c * a.ld + id] = ex[c];
+        }
+        if constexpr (SS) {
+          // g at the exit, as the finish would read it for this precision
+          double gq;
+          if constexpr (sizeof(T) == 4) {
+            float q[D];
+#pragma unroll
+            for (int c = 0; c < D; ++c) q[c] = ex[c];
+            gq = field_value_f32(a.g, D, q);
+          } else {
+            double q[D];
+#pragma unroll
+            for (int c = 0; c < D; ++c) q[c] = (double)ex[c];
+            gq = field_value(a.g, D, q);
+          }
+          U[id] = fma(thr, (T)gq, acc_s) + usrc;
+        } else {
+          U[id] = acc_s + usrc;
+        }
         if (a.steps) a.steps[id] = k;
         steps_acc += (unsigned long long)k;
         capped_acc += cap ? 1ull : 0ull;
@@ -483,18 +612,11 @@ __global__ __launch_bounds__(kBlock) void k_walks_open(WalkArgs a) {
   walks_body<T, 3, false, MODE, true>(a, lds);
 }
 
-// i1(x) = (x cosh x - sinh x) / x^2, the modified spherical Bessel function
-// of order 1, by its series sum_k x^(2k+1) / (2^k k! (2k+3)!!) below 1.
-__device__ inline double sph_i1(double x) {
-  if (x < 1.0) {
-    double term = x / 3.0, sum = term;
-    for (int k = 1; k < 14; ++k) {
-      term *= x * x / (2.0 * k * (2.0 * k + 3.0));
-      sum += term;
-    }
-    return sum;
-  }
-  return (x * cosh(x) - sinh(x)) / (x * x);
+// Screened walks with a source term (sigma > 0, f != 0).
+template <typename T, int D, int MODE>
+__global__ __launch_bounds__(kBlock) void k_walks_ss(WalkArgs a) {
+  extern __shared__ uint32_t lds[];
+  walks_body<T, D, true, MODE, false, true>(a, lds);
 }
 
 // Boundary data at the exit points and the control variate (FP32 walks
@@ -518,7 +640,8 @@ template <typename T, int D, int MODE>
 __global__ __launch_bounds__(kBlock) void k_finish(FieldDev g, int cv, uint64_t total, int W, int64_t n_pts,
                                                     const double* xbar, const T* EX, T* U, T* Dof, const T* W1,
                                                     double sigma, double eps, const double* R0, int side,
-                                                    const double* x64, const T* xT, const int64_t* n_dev) {
+                                                    const double* x64, const T* xT, const int64_t* n_dev,
+                                                    int ss) {
   // ids below `live` are finished; `total` stays the records' stride
   uint64_t live = total;
   if (n_dev) {
@@ -579,7 +702,8 @@ __global__ __launch_bounds__(kBlock) void k_finish(FieldDev g, int cv, uint64_t 
         w_est = u_est = gq;  // no ball: the walk returned g at the closest point
       } else {
         const double x = s * r0;
-        w_est = su * gq;
+        // a screened source walk wrote W + usrc / P0 with g already in it
+        w_est = ss ? su : su * gq;
         if constexpr (D == 3) {
           u_est = (x < 1e-8 ? 1.0 : x / sinh(x)) * w_est;
           ratio = s / sph_i1(x) * r0 / D;
@@ -663,12 +787,10 @@ int check_walk_params(const bvc_walk_params* p, int dim, const SceneHost* h = nu
   if (rc) return rc;
   rc = check_field(p->f, dim, "f");
   if (rc) return rc;
-  if (p->f.kind != 0 && p->f.kind != 1 && p->f.kind != 3)
-    return fail(BVC_EUNSUPPORTED, "walk source terms are constants or Gaussian sums");
+  if (p->f.kind != 0 && p->f.kind != 1 && p->f.kind != 3 && p->f.kind != 8)
+    return fail(BVC_EUNSUPPORTED, "walk source terms are constants, Gaussian sums or exponential planes");
   if (!(p->sigma >= 0.0) || !std::isfinite(p->sigma)) return fail(BVC_EINVAL, "sigma must be finite and >= 0");
   if (p->side_read != 0 && p->side_read != 1) return fail(BVC_EINVAL, "side_read must be 0 or 1");
-  if (p->sigma > 0.0 && p->f.kind != 0)
-    return fail(BVC_EUNSUPPORTED, "screened walks take no source term (f must be ZERO)");
   if (p->open_radius != 0.0) {
     if (!h) return fail(BVC_EUNSUPPORTED, "open domains are taken by the cache, pointwise and tuning walks only");
     if (dim != 3) return fail(BVC_EUNSUPPORTED, "open domains are built in 3D");
@@ -697,6 +819,13 @@ void launch_walks(const WalkArgs& args, int mode, bool src, int blocks, size_t l
       return;
     }
   }
+  if (src && args.sigma > 0.0) {
+    // screened with a source: modes 0 and 1 (the batch and clamping calls
+    // refuse screening)
+    if (mode == 0) hipLaunchKernelGGL((k_walks_ss<T, D, 0>), dim3(blocks), dim3(kBlock), lds, st, args);
+    else hipLaunchKernelGGL((k_walks_ss<T, D, 1>), dim3(blocks), dim3(kBlock), lds, st, args);
+    return;
+  }
   if (mode == 0) {
     if (src) hipLaunchKernelGGL((k_walks<T, D, true, 0>), dim3(blocks), dim3(kBlock), lds, st, args);
     else hipLaunchKernelGGL((k_walks<T, D, false, 0>), dim3(blocks), dim3(kBlock), lds, st, args);
@@ -717,11 +846,11 @@ void launch_finish(const bvc_walk_params* p, int mode, const WalkArgs& a, hipStr
   if (mode == 0)
     hipLaunchKernelGGL((k_finish<T, D, 0>), dim3(blocks), dim3(kBlock), 0, st, g, p->control_variate, a.total,
                        a.W, a.n_pts, a.xbar, (const T*)a.exit, (T*)a.U, (T*)a.Dof, (const T*)a.w1, a.sigma,
-                       a.eps, a.R0, a.side, a.x, (const T*)a.px, a.n_dev);
+                       a.eps, a.R0, a.side, a.x, (const T*)a.px, a.n_dev, (p->f.kind != 0 && a.sigma > 0.0) ? 1 : 0);
   else
     hipLaunchKernelGGL((k_finish<T, D, 1>), dim3(blocks), dim3(kBlock), 0, st, g, p->control_variate, a.total,
                        a.W, a.n_pts, a.xbar, (const T*)a.exit, (T*)a.U, (T*)a.Dof, (const T*)a.w1, a.sigma,
-                       a.eps, a.R0, a.side, a.x, (const T*)a.px, a.n_dev);
+                       a.eps, a.R0, a.side, a.x, (const T*)a.px, a.n_dev, (p->f.kind != 0 && a.sigma > 0.0) ? 1 : 0);
 }
 
 size_t stack_bytes(const SceneHost& h) { return (size_t)(h.depth + 1) * kBlock * sizeof(uint32_t); }
@@ -735,6 +864,7 @@ int run_walks(bvc_scene s, const bvc_walk_params* p, int mode, int64_t n, WalkAr
   const uint64_t total = (uint64_t)n * (uint64_t)(mode == 2 ? 1 : p->n_walks);
   a.S = h.view();
   a.f = to_dev(p->f);
+  a.g = to_dev(p->g);
   a.eps = p->eps;
   a.sigma = p->sigma;
   for (int c = 0; c < 3; ++c) a.oc[c] = p->open_center[c];
@@ -861,17 +991,11 @@ __global__ __launch_bounds__(kBlock) void k_batch_walks(BatchDev b) {
               float yu[D];
               ball_source_point<float, D>(s.seed, 0, id, s.batch, 1u, x0, R0, yu);
               usrc = -R0 * R0 / (float)(2 * D) * walk_source<float, D>(s.f, sscale, yu);
-              if constexpr (D == 2) {
-                float u1, u2, u3, u4;
-                Uniform<float>::pair(s.seed, 2, id, s.batch, 1u, u1, u2);
-                Uniform<float>::pair(s.seed, 3, id, s.batch, 1u, u3, u4);
-                const float sg = 2.f * sinf(asinf(u2) / 3.f);
-                float sn, cs;
-                sincos_turns(u3, &sn, &cs);
-                const float yg[2] = {fmaf(R0 * sg, cs, x0[0]), fmaf(R0 * sg, sn, x0[1])};
-                const float c = -2.f * R0 / 3.f * walk_source<float, D>(s.f, sscale, yg);
-                ds = c * (cs * (float)s.nrm[i] + sn * (float)s.nrm[s.n_cache + i]);
-              }
+              float yhat[D], yg[D], m;
+              grad_source_point<float, D>(s.seed, id, s.batch, 1u, x0, R0, yhat, yg, m);
+              const float c = -m * R0 * walk_source<float, D>(s.f, sscale, yg);
+#pragma unroll
+              for (int q = 0; q < D; ++q) ds = fmaf(c * yhat[q], (float)s.nrm[q * s.n_cache + i], ds);
             }
             b.w1[gid] = w1;
             b.D[gid] = ds - w1 * usrc;

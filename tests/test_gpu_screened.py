@@ -228,10 +228,7 @@ def test_screened_unsupported_combinations(B):
     say("screened unsupported combinations")
     scene, sc, g = _sphere_case(pl)
     gd = pl.DeviceField(g)
-    cache = pl.sample_cache(sc, 100, 2e-2, 1, 1, 0)
-    f = pl.DeviceField(wl.Field(1, np.zeros(0), (1.0,)))
-    with pytest.raises(_bvc.BVCError):
-        pl.cache_walks(sc, cache, pl.walk_params(4e-3, 4, 1, gd, f, "f64", sigma=1.0), "f64")
+    # (a source with screening is built: tests/test_gpu_sources.py)
     T = torch.float64
     cv = dict(n=4, dtype=_bvc.F64, x=torch.ones(3, 4, dtype=T, device="cuda"),
               nrm=torch.ones(3, 4, dtype=T, device="cuda"), a=torch.ones(4, dtype=T, device="cuda"),
