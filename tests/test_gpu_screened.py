@@ -7,8 +7,9 @@ Appendix A.2) against the FP64 oracle, through the C-ABI (marked gpu).
   walk by walk on the oracle's Philox streams (at least 99.9% within 1e-9);
   FP32: walk means against the FP64 walks on the same streams (z-test).
 - The pipeline on the screened sphere and star problems recovers exp(a.x).
-- Unsupported combinations (a walk source, near field, clamp, clamping
-  correction) are refused with an error.
+- Unsupported combinations (near field or clamp with screening, the
+  clamping correction) are refused with an error; a walk source with
+  screening is built and tested in test_gpu_sources.py.
 """
 import sys
 
