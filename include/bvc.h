@@ -452,6 +452,11 @@ typedef struct {
                             (Appendix A.2; s = sqrt(sigma)); without near field
                             or clamp.  FP32 evaluates K0, K1 to about 5e-7
                             relative, FP64 to about 1e-14.  0 = off */
+  int64_t near_lead;     /* near field: > 0 when only the first near_lead
+                            evaluation points can have a pair closer than tau
+                            (the caller orders them first); the blocks past
+                            them skip the near test.  0 = every point;
+                            BVC_EINVAL outside [0, n_eval] */
 } bvc_gather_params;
 
 /* u_k = sum_i [dG/dn(x_k,z_i) a_i - G(x_k,z_i) b_i] + sum_j G(x_k,y_j) s_j

@@ -63,7 +63,7 @@ class bvc_source_view(C.Structure):
 class bvc_gather_params(C.Structure):
     _fields_ = [("accumulate", C.c_int32), ("near_tau", C.c_double), ("near_x", C.c_void_p),
                 ("near_cx", C.c_void_p), ("near_cn", C.c_void_p), ("near_a", C.c_void_p),
-                ("near_b", C.c_void_p), ("clamp_c", C.c_double), ("sigma", C.c_double)]
+                ("near_b", C.c_void_p), ("clamp_c", C.c_double), ("sigma", C.c_double), ("near_lead", C.c_int64)]
 
 
 class bvc_clamp_params(C.Structure):
@@ -417,8 +417,10 @@ def _views(cache, sources):
 
 
 def _gparams(accumulate, near, clamp=0.0, sigma=0.0):
-    """near: None, or dict(tau, x, cx, cn, a, b) with FP64 device tensors
-    (evaluation points [dim][n_eval], cache points and normals [dim][n], a, b).
+    """near: None, or dict(tau, x, cx, cn, a, b[, lead]) with FP64 device
+    tensors (evaluation points [dim][n_eval], cache points and normals
+    [dim][n], a, b); lead: the number of leading evaluation points that can
+    need the near field (0 = all).
     clamp: bound c of dG/dn in the potential (Eq. 9), 0 = off."""
     gp = bvc_gather_params()
     gp.accumulate = accumulate
@@ -428,6 +430,7 @@ def _gparams(accumulate, near, clamp=0.0, sigma=0.0):
         gp.near_tau = float(near["tau"])
         gp.near_x, gp.near_cx, gp.near_cn, gp.near_a, gp.near_b = (
             ptr(near[k]) for k in ("x", "cx", "cn", "a", "b"))
+        gp.near_lead = int(near.get("lead", 0))
     return gp
 
 

@@ -73,6 +73,8 @@ struct GatherArgs {
   // device count of cache entries (<= n_cache, the arrays' leading
   // dimension), or null for n_cache
   const int64_t* n_dev;
+  // near field: the evaluation points that may need it come first (0 = any)
+  int64_t near_lead;
 };
 
 template <typename T>
@@ -88,9 +90,19 @@ __device__ __forceinline__ int64_t cache_count(const GatherArgs<T>& a) {
 template <typename T, int D, bool GRAD, bool NEAR = false, int PPT = kPPT, bool CLAMP = false>
 __device__ __forceinline__ void gather_block(const GatherArgs<T>& a, int64_t block, T* ent);
 
+// With the near field and near_lead > 0 only the blocks holding one of the
+// first near_lead evaluation points run the near test (the caller orders the
+// points that can meet a cache point closer than tau first); the others take
+// the plain FP32 loop.
 template <typename T, int D, bool GRAD, bool NEAR, int PPT, bool CLAMP = false>
 __global__ __launch_bounds__(kGBlock) void k_gather(GatherArgs<T> a) {
   __shared__ T ent[kTile * (CLAMP ? 9 : 8)];
+  if constexpr (NEAR) {
+    if (a.near_lead > 0 && (int64_t)blockIdx.x * (kGBlock * PPT) >= a.near_lead) {
+      gather_block<T, D, GRAD, false, PPT, CLAMP>(a, blockIdx.x, ent);
+      return;
+    }
+  }
   gather_block<T, D, GRAD, NEAR, PPT, CLAMP>(a, blockIdx.x, ent);
 }
 
@@ -1137,6 +1149,7 @@ int gather_impl(int dim, const bvc_cache_view* c, const bvc_source_view* s, int6
     a.ncn = near->near_cn;
     a.na = near->near_a;
     a.nb = near->near_b;
+    a.near_lead = near->near_lead;
   }
   a.clampc = (T)clamp_c;
   a.clamp64 = clamp_c;
@@ -1166,6 +1179,8 @@ int gather_entry(int32_t dim, const bvc_cache_view* c, const bvc_source_view* s,
   rc = check_sources(s, c->dtype);
   if (rc) return rc;
   if (n_eval < 0) return fail(BVC_EINVAL, "n_eval must be >= 0");
+  if (prm && (prm->near_lead < 0 || prm->near_lead > n_eval))
+    return fail(BVC_EINVAL, "near_lead must lie in [0, n_eval]");
   if (n_eval == 0) return BVC_OK;
   if (!ex || (!u && !g)) return fail(BVC_EINVAL, "null evaluation points or outputs");
   const int acc = prm ? prm->accumulate : 0;

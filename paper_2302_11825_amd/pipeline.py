@@ -343,14 +343,37 @@ class Prepared:
         # summed from FP64 copies of both points and of the cache values
         self.near_tau = 0.0
         self.x_int64 = None
+        self.split = None
         if self.dtype == "f32" and problem.sigma == 0:
             self.near_tau = float(problem.offset if near_tau is None else near_tau)
             if self.near_tau > 0:
                 self.x_int64 = take(self.eval64, self.idx_int, self.n_int, self.sc.dim, n, torch.float64)
+                self._prepare_split(device)
         self.clamp = None
         if clamp is not None:
             self._prepare_clamp(clamp, device)
         self._prepare_grad_band(grad_band, grad_band_walks, device)
+
+    def _prepare_split(self, device):
+        """Only gathered points within l + tau of the boundary can meet a cache
+        point closer than tau (every cache point lies l from the boundary).
+        The gathered points are reordered once with those first (their count
+        is the gather's near_lead, so that the blocks past them skip the near
+        test) and the gather's outputs are scattered back to the gathered
+        order: the permutation, the permuted coordinates in the gather dtype
+        and in FP64."""
+        d, n, n_int = self.sc.dim, self.eval64.shape[1], self.n_int
+        if n_int == 0:
+            return
+        cls, _ = classify(self.sc, self.x_int64, self.p.offset + self.near_tau)
+        pos_near, n_near = self.sc.compact(cls[:n_int], 2)
+        pos_far, n_far = self.sc.compact(cls[:n_int], 1)
+        if n_far + n_near != n_int:
+            raise RuntimeError("near-field split lost gathered points")
+        perm = torch.cat([pos_near[:n_near], pos_far[:n_far]]).contiguous()
+        idx = self.idx_int[perm.to(torch.int64)].contiguous()
+        self.split = dict(n_near=n_near, perm=perm, x=take(self.eval64, idx, n_int, d, n, DT[self.dtype]),
+                          x64=take(self.eval64, idx, n_int, d, n, torch.float64))
 
     def _prepare_grad_band(self, width, walks, device):
         """Gathered points within `width` of the boundary take grad u from
@@ -794,12 +817,37 @@ def _gather_views(prep: Prepared, cache: Cache, a, b, batch, watch):
 def _near(prep: Prepared, cache: Cache, U, D):
     """Near-field argument of an FP32 gather (None when off): FP64 cache
     values a, b from the walks' FP64 means, and the FP64 cache points,
-    normals and evaluation points."""
+    normals and evaluation points (the near set's when the gather is split)."""
     if not prep.near_tau or cache.cap == 0:
         return None
     _, _, a64, b64 = reduce_walks(cache, prep.p.n_walks, U, D, "f64")
+    sp = prep.split
+    if sp is not None:
+        return dict(tau=prep.near_tau, x=sp["x64"], cx=cache.x, cn=cache.nrm, a=a64, b=b64, lead=sp["n_near"])
     return dict(tau=prep.near_tau, x=prep.x_int64, cx=cache.x, cn=cache.nrm, a=a64, b=b64)
 
+
+def gather_all(prep: Prepared, cview, sview, u_int, g_int, near, clamp=0.0, sigma=0.0):
+    """The gather at every gathered point; with the near-field split, over the
+    reordered points (those that can need the near field first) and scattered
+    back into u_int (and g_int)."""
+    d = prep.sc.dim
+    sp = prep.split
+    if sp is None or near is None:
+        x, u, g = prep.x_int, u_int, g_int
+    else:
+        x = sp["x"]
+        u = torch.empty_like(u_int)
+        g = torch.empty_like(g_int) if g_int is not None else None
+    if g is not None:
+        B.bvc_gather_grad(d, cview, sview, prep.n_int, x, u, g, clamp=clamp, sigma=sigma, near=near)
+    else:
+        B.bvc_gather_u(d, cview, sview, prep.n_int, x, u, clamp=clamp, sigma=sigma, near=near)
+    if u is not u_int:
+        code = B.dtype_code(u.dtype)
+        B.bvc_scatter(code, prep.n_int, sp["perm"], 1, u.shape[0], u, u_int.shape[0], u_int)
+        if g is not None:
+            B.bvc_scatter(code, prep.n_int, sp["perm"], d, g.shape[1], g, g_int.shape[1], g_int)
 
 def tune(prep: Prepared, with_grad=True, reps=3) -> dict:
     """Picks the launch shapes of this problem's walks and gather with the
@@ -824,7 +872,9 @@ def tune(prep: Prepared, with_grad=True, reps=3) -> dict:
     cview, sview = _gather_views(prep, cache, a, b, 0, _NoWatch())
     u = torch.empty(max(prep.n_int, 1), dtype=T, device=sc.device)
     g = torch.empty(d, max(prep.n_int, 1), dtype=T, device=sc.device) if with_grad else None
-    ppt = (B.bvc_tune_gather(d, cview, sview, prep.n_int, prep.x_int, u, g, reps, near=_near(prep, cache, U, D))
+    near = _near(prep, cache, U, D)
+    x = prep.split["x"] if prep.split is not None and near is not None else prep.x_int
+    ppt = (B.bvc_tune_gather(d, cview, sview, prep.n_int, x, u, g, reps, near=near)
            if prep.n_int and p.sigma == 0 else 0)
     out = dict(walk_blocks_per_cu=bpc, walk_open_lanes=lanes, walk_slabs=slabs, gather_points_per_thread=ppt)
     nb = prep.n_band
@@ -869,10 +919,7 @@ def solve(prep: Prepared, batch=0, with_grad=True, n_walks_band=None, records=Fa
     cl = prep.clamp
     cc = cl["c"] if cl else 0.0
     with watch.stage("gather"):
-        if with_grad:
-            B.bvc_gather_grad(d, cview, sview, n_int, prep.x_int, u_int, g_int, clamp=cc, sigma=p.sigma, near=near)
-        else:
-            B.bvc_gather_u(d, cview, sview, n_int, prep.x_int, u_int, clamp=cc, sigma=p.sigma, near=near)
+        gather_all(prep, cview, sview, u_int, g_int, near, clamp=cc, sigma=p.sigma)
     gathered = None
     if cl:
         gathered = torch.cuda.Event()

@@ -9,7 +9,7 @@ import pytest
 import torch
 
 import workloads as wl
-from gpu_helpers import lib, oracle_cache, per_walk_match, to_np_aos
+from gpu_helpers import abs_terms, lib, oracle_cache, per_walk_match, to_np_aos
 
 pytestmark = pytest.mark.gpu
 
@@ -147,6 +147,53 @@ def test_near_field_covering_the_scene_is_the_fp64_sum(orc, dim):
     assert np.all(np.abs(u.double().cpu().numpy() - uo) <= uu * np.abs(uo) + 1e-12 * cond)
     gd = to_np_aos(g)
     assert np.all(np.abs(gd - go) <= uu * np.abs(go) + 1e-11 * (np.abs(go).max() + cond.max()))
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_near_field_lead(orc, dim):
+    """Evaluation points that can meet a cache point closer than tau ordered
+    first, their count passed as near_lead: the blocks past them skip the
+    near test.  The leading points (near path in both launches) agree bit for
+    bit with a launch that tests every point, the trailing ones (no pair
+    closer than tau) to FP32 rounding of the sum of |terms|; a lead outside
+    [0, n_eval] is refused."""
+    _bvc, pl = lib()
+    say(f"near field lead dim={dim}")
+    rng = np.random.default_rng(31 + dim)
+    N, n_near, n_far = 700, 1301, 3790
+    d = rng.normal(0, 1, (N, dim))
+    cy = (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32).astype(np.float64)
+    a = (rng.normal(0, 1, N) / N).astype(np.float32).astype(np.float64)
+    b = (rng.normal(0, 1, N) / N).astype(np.float32).astype(np.float64)
+    tau = 0.05
+    # leading points 0.02 inside a cache point, trailing ones at radius <= 0.8
+    xn = cy[np.arange(n_near) % N] * 0.98
+    xf = rng.normal(0, 1, (n_far, dim))
+    xf *= rng.uniform(0, 0.8, (n_far, 1)) / np.linalg.norm(xf, axis=1, keepdims=True)
+    x = np.concatenate([xn, xf])
+    K = x.shape[0]
+    cache, _, dev = _views(_bvc, torch.float32, _bvc.F32, cy, cy, a, b)
+    d64 = lambda v: torch.from_numpy(np.ascontiguousarray(v.T if v.ndim == 2 else v)).to("cuda", torch.float64)
+    near = dict(tau=tau, x=d64(x), cx=d64(cy), cn=d64(cy), a=d64(a), b=d64(b))
+    out = []
+    for lead in (0, n_near):
+        u = torch.empty(K, dtype=torch.float32, device="cuda")
+        g = torch.empty(dim, K, dtype=torch.float32, device="cuda")
+        _bvc.bvc_gather_grad(dim, cache, None, K, dev(x), u, g, near=dict(near, lead=lead))
+        torch.cuda.synchronize()
+        out.append((u.double().cpu().numpy(), to_np_aos(g)))
+    (u0, g0), (u1, g1) = out
+    assert np.array_equal(u1[:n_near], u0[:n_near]) and np.array_equal(g1[:n_near], g0[:n_near])
+    # (one source of weight 0 far away: abs_terms wants a source)
+    su, sun, sg, sgn, _ = abs_terms(dim, xf, cy, cy, a, b, np.full((1, dim), 10.0), np.zeros(1), tau)
+    assert np.all(sun == 0) and np.all(sgn == 0)
+    uu = 2.0**-24
+    assert np.all(np.abs(u1[n_near:] - u0[n_near:]) <= 64 * uu * su)
+    assert np.all(np.abs(g1[n_near:] - g0[n_near:]) <= 64 * uu * sg[:, None])
+    u = torch.empty(K, dtype=torch.float32, device="cuda")
+    for lead in (-1, K + 1):
+        with pytest.raises(_bvc.BVCError):
+            _bvc.bvc_gather_u(dim, cache, None, K, dev(x), u, near=dict(near, lead=lead))
 
 
 @pytest.mark.parametrize("n_cand", [1, 7, 4097])
