@@ -243,6 +243,59 @@ __device__ __forceinline__ T triangle_d2(const T* p, const T* a, const T* b, con
   return dx * dx + dy * dy + dz * dz;
 }
 
+// The same closest point for a triangle record v = (a, b, c, |b-a|^2,
+// (b-a).(c-a), |c-a|^2) whose last three entries the scene builder stored:
+// the region tests are those of triangle_d2, and every region's point is
+// written as a + U (b - a) + V (c - a) (U, V in {0, 1} at the vertices, U =
+// 1 - V on edge bc), so that p - q comes from ap with two FMAs per axis and
+// no per-axis selects.  Vertices are then reached through one rounding more
+// than the stored coordinates.
+template <typename T>
+__device__ __forceinline__ T triangle_d2_pre(const T* p, const T* v, T* q, int& region) {
+  T ab[3], ac[3], ap[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    ab[i] = v[3 + i] - v[i];
+    ac[i] = v[6 + i] - v[i];
+    ap[i] = p[i] - v[i];
+  }
+  const T abab = v[9], abac = v[10], acac = v[11];
+  const T d1 = ab[0] * ap[0] + ab[1] * ap[1] + ab[2] * ap[2];
+  const T d2 = ac[0] * ap[0] + ac[1] * ap[1] + ac[2] * ap[2];
+  const T d3 = d1 - abab, d4 = d2 - abac;  // (p-b).ab, (p-b).ac
+  const T d5 = d1 - abac, d6 = d2 - acac;  // (p-c).ab, (p-c).ac
+  const T vc = d1 * d4 - d3 * d2;
+  const T vb = d5 * d2 - d1 * d6;
+  const T va = d3 * d6 - d5 * d4;
+  const T e43 = d4 - d3, e56 = d5 - d6;
+  const bool in_a = d1 <= T(0) && d2 <= T(0);
+  const bool in_b = d3 >= T(0) && d4 <= d3;
+  const bool in_ab = vc <= T(0) && d1 >= T(0) && d3 <= T(0);
+  const bool in_c = d6 >= T(0) && d5 <= d6;
+  const bool in_ca = vb <= T(0) && d2 >= T(0) && d6 <= T(0);
+  const bool in_bc = va <= T(0) && e43 >= T(0) && e56 >= T(0);
+  // U = nu / den, V = nv / den; the first test that holds wins
+  int reg = 0;
+  T nu = vb, nv = vc, den = va + vb + vc;
+  if (in_bc) { reg = 5; nu = e56; nv = e43; den = e43 + e56; }
+  if (in_ca) { reg = 6; nu = T(0); nv = d2; den = d2 - d6; }
+  if (in_c) { reg = 3; nu = T(0); nv = T(1); den = T(1); }
+  if (in_ab) { reg = 4; nu = d1; nv = T(0); den = d1 - d3; }
+  if (in_b) { reg = 2; nu = T(1); nv = T(0); den = T(1); }
+  if (in_a) { reg = 1; nu = T(0); nv = T(0); den = T(1); }
+  const T rden = fdiv(T(1), den);
+  const T U = nu * rden, V = nv * rden;
+  region = reg;
+  T d2s = T(0);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const T e = fma(-V, ac[i], fma(-U, ab[i], ap[i]));  // p - q
+    q[i] = p[i] - e;
+    d2s = fma(e, e, d2s);
+  }
+  return d2s;
+}
+
 template <typename T, int D>
 __device__ __forceinline__ T box_d2(const T* lo, const T* hi, const T* p) {
   T d2 = T(0);
@@ -317,6 +370,27 @@ __device__ __forceinline__ void load_triangle(const SceneDev& S, int i, T* v) {
   }
 }
 
+// Triangle record with the three stored dot products of triangle_d2_pre.
+template <typename T>
+__device__ __forceinline__ void load_triangle_pre(const SceneDev& S, int i, T* v) {
+  const T* pr = SceneArrays<T>::prim(S);
+  if constexpr (sizeof(T) == 4) {
+    const float4* r = reinterpret_cast<const float4*>(pr) + 3 * i;
+    const float4 r0 = r[0], r1 = r[1], r2 = r[2];
+    v[0] = r0.x; v[1] = r0.y; v[2] = r0.z; v[3] = r0.w;
+    v[4] = r1.x; v[5] = r1.y; v[6] = r1.z; v[7] = r1.w;
+    v[8] = r2.x; v[9] = r2.y; v[10] = r2.z; v[11] = r2.w;
+  } else {
+    const double2* r = reinterpret_cast<const double2*>(pr) + 6 * i;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const double2 w = r[j];
+      v[2 * j] = w.x;
+      v[2 * j + 1] = w.y;
+    }
+  }
+}
+
 // Distance^2 and closest point of leaf-ordered primitive i.
 template <typename T, int D>
 __device__ __forceinline__ T prim_d2(const SceneDev& S, int i, const T* p, T* q, int& region) {
@@ -332,9 +406,9 @@ __device__ __forceinline__ T prim_d2(const SceneDev& S, int i, const T* p, T* q,
       return segment_d2<T>(p, r0.x, r0.y, r1.x, r1.y, q[0], q[1]);
     }
   } else {
-    T v[9];
-    load_triangle<T>(S, i, v);
-    return triangle_d2<T>(p, v, v + 3, v + 6, q, region);
+    T v[12];
+    load_triangle_pre<T>(S, i, v);
+    return triangle_d2_pre<T>(p, v, q, region);
   }
 }
 
@@ -417,10 +491,10 @@ __device__ __forceinline__ void bvh_closest(const SceneDev& S, const T* p, T& be
       T d2;
       if constexpr (D == 3) {
         // skip the exact test when the triangle's box is already farther
-        T v[9];
-        load_triangle<T>(S, i, v);
+        T v[12];
+        load_triangle_pre<T>(S, i, v);
         if (triangle_box_d2<T>(p, v) > best) continue;
-        d2 = triangle_d2<T>(p, v, v + 3, v + 6, q, reg);
+        d2 = triangle_d2_pre<T>(p, v, q, reg);
       } else {
         d2 = prim_d2<T, D>(S, i, p, q, reg);
       }
@@ -537,12 +611,12 @@ __device__ __forceinline__ void query_step(const SceneDev& S, const T* p, Query<
     int reg;
     T d2 = T(INFINITY);
     if constexpr (D == 3) {
-      T v[9];
-      load_triangle<T>(S, i, v);
+      T v[12];
+      load_triangle_pre<T>(S, i, v);
       // a single-primitive leaf already passed its own box; in longer
       // leaves the triangle's box is a cheap lower bound
       if (n > 1 && triangle_box_d2<T>(p, v) > q.best) test = false;
-      if (test) d2 = triangle_d2<T>(p, v, v + 3, v + 6, qq, reg);
+      if (test) d2 = triangle_d2_pre<T>(p, v, qq, reg);
     } else {
       d2 = prim_d2<T, D>(S, i, p, qq, reg);
     }

@@ -33,7 +33,7 @@ struct SceneDev {
   const double* slab64; // 3D [n_nodes][12]: per child, a unit axis n and the range [smin, smax]
                         // of n.y over the child's triangles (n0 smin0 smax0 n1 smin1 smax1 0 0)
   const float* slab32;  // same with the axis rounded to FP32 and the range widened outward
-  const double* prim64; // leaf order: 2D [np][4] (a, b); 3D [np][12] (a, b, c, pad)
+  const double* prim64; // leaf order: 2D [np][4] (a, b); 3D [np][12] (a, b, c, |b-a|^2, (b-a).(c-a), |c-a|^2)
   const float* prim32;  // same layout in FP32
   const int* prim_id;   // leaf order -> original primitive id
   const double* fn;     // 3D [np][3] unit face normals (original order)

@@ -470,6 +470,29 @@ static int build_scene(SceneHost& S, int dim, const double* verts, int64_t nv, c
         S.prim64[(size_t)i * pw + c * dim + a] = v;
         S.prim32[(size_t)i * pw + c * dim + a] = (float)v;
       }
+    if (dim == 3) {
+      // the closest-point test's |b-a|^2, (b-a).(c-a), |c-a|^2, from the edge
+      // vectors each precision's test forms itself (FP32 differences of the
+      // FP32 vertices), summed in FP64
+      double* r64 = &S.prim64[(size_t)i * pw];
+      float* r32 = &S.prim32[(size_t)i * pw];
+      double e64[2][3], e32[2][3];
+      for (int e = 0; e < 2; ++e)
+        for (int a = 0; a < 3; ++a) {
+          e64[e][a] = r64[3 * (e + 1) + a] - r64[a];
+          e32[e][a] = (double)(r32[3 * (e + 1) + a] - r32[a]);
+        }
+      const int pairs[3][2] = {{0, 0}, {0, 1}, {1, 1}};
+      for (int k = 0; k < 3; ++k) {
+        double s64 = 0.0, s32 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+          s64 += e64[pairs[k][0]][a] * e64[pairs[k][1]][a];
+          s32 += e32[pairs[k][0]][a] * e32[pairs[k][1]][a];
+        }
+        r64[9 + k] = s64;
+        r32[9 + k] = (float)s32;
+      }
+    }
   }
   if (dim == 3) {
     // face normals, angle-weighted vertex pseudonormals, edge pseudonormals
