@@ -332,7 +332,36 @@ typedef struct {
                               strides n_cache*W).  Lets a step run without
                               reading its cache size back (see
                               bvc_compact_count).  NULL: n_cache points. */
+  const int32_t* order;    /* bvc_cache_walks, bvc_pointwise_wos(_noalloc),
+                              bvc_tune_walks and bvc_tune_pointwise only (NULL
+                              elsewhere, else BVC_EUNSUPPORTED): device int32
+                              launch order of the start points, a permutation
+                              of [0, count) (count: the n_dev value when given,
+                              else the point count), e.g. from
+                              bvc_spatial_order.  The walks of point order[0]
+                              are started first, then those of order[1], and so
+                              on, so that the walks in flight together query
+                              nearby parts of the tree and share the caches.
+                              Every walk keeps its id, random stream and record
+                              slot: the results do not depend on the order.
+                              Entries outside [0, count) are skipped (their
+                              walks do not run).  NULL: point order. */
 } bvc_walk_params;
+
+/* Launch order by position, for the walk params' `order` (a scheduling
+ * choice of this library, not part of the method: results do not depend on
+ * it).  order[0..count) lists the points 0..count-1 (count = min(n, *n_dev)
+ * with a device count, else n) by the Morton index of their cell in a grid of
+ * 32^3 (3D) or 256^2 (2D) cells over the scene's bounding box (points outside
+ * it, or not finite, fall in the nearest edge cell); the order inside a cell is
+ * unspecified (device atomics).  x: device [dim][ld] (ld >= n) of dtype
+ * BVC_F32 or BVC_F64; order: device int32 [n] (entries from count on are left
+ * unwritten); work: device workspace of at least
+ * bvc_spatial_order_workspace_bytes() bytes, 256-byte aligned, overwritten.
+ * Allocates nothing; no host synchronisation. */
+size_t bvc_spatial_order_workspace_bytes(void);
+int bvc_spatial_order(bvc_scene scene, int32_t dtype, int64_t n, const void* x, int64_t ld, const int64_t* n_dev,
+                      int32_t* order, void* work, size_t work_bytes, void* stream);
 
 /* Walk j of cache point i has id i*W + j (n_cache*W < 2^32).  Each walk takes
  * a first ball B(x_i, R0_i) with no termination test (uniform direction nu;

@@ -48,7 +48,7 @@ class bvc_walk_params(C.Structure):
                 ("dtype", C.c_int32), ("blocks", C.c_int32), ("g", bvc_field), ("f", bvc_field),
                 ("ev_begin", C.c_void_p), ("ev_end", C.c_void_p), ("sigma", C.c_double),
                 ("open_center", C.c_double * 3), ("open_radius", C.c_double), ("side_read", C.c_int32),
-                ("h", bvc_field), ("n_dev", C.c_void_p)]
+                ("h", bvc_field), ("n_dev", C.c_void_p), ("order", C.c_void_p)]
 
 
 class bvc_cache_view(C.Structure):
@@ -103,6 +103,7 @@ _SIGS = {
     "bvc_compact_count": [C.c_int64, _vp, C.c_int32, _vp, _vp, _vp, _vp],
     "bvc_take_count": [C.c_int32, C.c_int32, C.c_int64, _vp, _vp, C.c_int32, C.c_int64, _vp, C.c_int64, _vp, _vp],
     "bvc_scatter": [C.c_int32, C.c_int64, _vp, C.c_int32, C.c_int64, _vp, C.c_int64, _vp, _vp],
+    "bvc_spatial_order": [_vp, C.c_int32, C.c_int64, _vp, C.c_int64, _vp, _vp, _vp, C.c_size_t, _vp],
     "bvc_cache_walks": [_vp, _P(bvc_walk_params), C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                         _vp, _vp],
     "bvc_reduce_walks": [C.c_int64, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp, _vp, C.c_int32, _vp, _vp, _vp],
@@ -168,6 +169,8 @@ _L.bvc_clamp_workspace_bytes.argtypes = [C.c_int32, C.c_int32, C.c_int64, C.c_in
 _L.bvc_clamp_workspace_bytes.restype = C.c_size_t
 _L.bvc_pointwise_static_bytes.argtypes = [C.c_int32, C.c_int64, C.c_int32, C.c_int32, C.c_int32]
 _L.bvc_pointwise_static_bytes.restype = C.c_size_t
+_L.bvc_spatial_order_workspace_bytes.argtypes = []
+_L.bvc_spatial_order_workspace_bytes.restype = C.c_size_t
 
 # size of the library's static scratch of bvc_pointwise_wos_noalloc
 POINTWISE_STATIC_BYTES = 32 << 20
@@ -176,7 +179,7 @@ EXPORTED = sorted(list(_SIGS) + ["bvc_last_error", "bvc_version", "bvc_compact_s
                                  "bvc_cache_backward_scratch_doubles", "bvc_pointwise_workspace_bytes",
                                  "bvc_gather_multi_workspace_bytes", "bvc_batch_workspace_bytes",
                                  "bvc_clamp_radius", "bvc_clamp_workspace_bytes", "bvc_wost_workspace_bytes",
-                                 "bvc_pointwise_static_bytes"])
+                                 "bvc_pointwise_static_bytes", "bvc_spatial_order_workspace_bytes"])
 
 
 def _check(rc, name):
@@ -349,6 +352,17 @@ def bvc_take(dtype_in, dtype_out, n_idx, idx, rows, ld_in, src, ld_out, out, str
 def bvc_scatter(dtype, n_idx, idx, rows, ld_in, src, ld_out, out, stream=None):
     _check(_L.bvc_scatter(dtype, n_idx, ptr(idx), rows, ld_in, ptr(src), ld_out, ptr(out), stream_ptr(stream)),
            "bvc_scatter")
+
+
+def bvc_spatial_order_workspace_bytes():
+    return int(_L.bvc_spatial_order_workspace_bytes())
+
+
+def bvc_spatial_order(scene, n, x, order, work, n_dev=None, stream=None):
+    """x: [dim][ld] FP32 or FP64 device points; order: int32 [n] device."""
+    _check(_L.bvc_spatial_order(scene, dtype_code(x.dtype), n, ptr(x), x.shape[1] if x.dim() == 2 else 0,
+                                ptr(n_dev), ptr(order), ptr(work), work.numel() * work.element_size(),
+                                stream_ptr(stream)), "bvc_spatial_order")
 
 
 def bvc_cache_walks(scene, params: bvc_walk_params, n_cache, x, nrm, R0, xbar, U, D, rec_exit=None,

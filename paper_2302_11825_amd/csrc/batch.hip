@@ -47,6 +47,7 @@ int plan_sizes(const bvc_batch_item* items, int n, int& dim, uint64_t& walks, in
     const bvc_walk_params& p = it.walk;
     if (p.dtype != BVC_F32) return fail(BVC_EUNSUPPORTED, "batched walks run in FP32");
     if (p.n_dev) return fail(BVC_EUNSUPPORTED, "batched walks take host counts");
+    if (p.order) return fail(BVC_EUNSUPPORTED, "batched walks take no launch order");
     if (!(p.eps > 0) || p.max_steps < 1 || p.n_walks < 1) return fail(BVC_EINVAL, "bad walk parameters");
     rc = check_field(p.g, d, "g");
     if (rc) return rc;

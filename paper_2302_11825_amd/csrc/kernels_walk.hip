@@ -471,6 +471,82 @@ __global__ void k_scatter(int64_t n_idx, const int* idx, int rows, int64_t ld_in
   for (int r = 0; r < rows; ++r) out[r * ld_out + idx[q]] = in[r * ld_in + q];
 }
 
+// ---------------------------------------------------------------------------
+// Launch order by position: a counting sort of the points by the Morton index
+// of their grid cell (32^3 cells in 3D, 256^2 in 2D, 2^15 or 2^16 buckets)
+// ---------------------------------------------------------------------------
+constexpr int kOrderBuckets = 1 << 16;
+
+struct OrderGrid {
+  double lo[3], scale[3];  // cell coordinate = (x - lo) * scale
+  int bits;                // per axis
+};
+
+template <typename T>
+__device__ __forceinline__ uint32_t order_key(const OrderGrid& g, int dim, const T* x, int64_t ld, int64_t i) {
+  const double top = (double)((1 << g.bits) - 1);
+  uint32_t c[3] = {0u, 0u, 0u};
+  for (int a = 0; a < dim; ++a) {
+    double t = ((double)x[a * ld + i] - g.lo[a]) * g.scale[a];
+    t = t >= 0.0 ? (t <= top ? t : top) : 0.0;  // NaN lands in cell 0
+    c[a] = (uint32_t)t;
+  }
+  uint32_t key = 0u;
+  for (int b = 0; b < g.bits; ++b)
+    for (int a = 0; a < dim; ++a) key |= ((c[a] >> b) & 1u) << (b * dim + a);
+  return key;
+}
+
+__device__ __forceinline__ int64_t order_live(int64_t n, const int64_t* n_dev) {
+  if (!n_dev) return n;
+  const int64_t c = *n_dev;
+  return c < 0 ? 0 : (c < n ? c : n);
+}
+
+template <typename T>
+__global__ void k_order_count(OrderGrid g, int dim, int64_t n, const T* x, int64_t ld, const int64_t* n_dev,
+                              uint32_t* hist) {
+  const int64_t live = order_live(n, n_dev);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < live; i += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd(&hist[order_key(g, dim, x, ld, i)], 1u);
+}
+
+// Exclusive prefix sum of the kOrderBuckets counts in place, one block of
+// kBlock threads, each owning a contiguous run of buckets.
+__global__ __launch_bounds__(kBlock) void k_order_scan(uint32_t* hist) {
+  constexpr int kRun = kOrderBuckets / kBlock;
+  __shared__ uint32_t part[kBlock];
+  const int t = threadIdx.x;
+  uint32_t* h = hist + (size_t)t * kRun;
+  uint32_t sum = 0u;
+  for (int k = 0; k < kRun; ++k) sum += h[k];
+  part[t] = sum;
+  __syncthreads();
+  // Hillis-Steele inclusive scan of the run sums
+  for (int off = 1; off < kBlock; off <<= 1) {
+    const uint32_t add = t >= off ? part[t - off] : 0u;
+    __syncthreads();
+    part[t] += add;
+    __syncthreads();
+  }
+  uint32_t run = part[t] - sum;
+  for (int k = 0; k < kRun; ++k) {
+    const uint32_t v = h[k];
+    h[k] = run;
+    run += v;
+  }
+}
+
+template <typename T>
+__global__ void k_order_place(OrderGrid g, int dim, int64_t n, const T* x, int64_t ld, const int64_t* n_dev,
+                              uint32_t* next, int32_t* order) {
+  const int64_t live = order_live(n, n_dev);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < live; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t pos = atomicAdd(&next[order_key(g, dim, x, ld, i)], 1u);
+    order[pos] = (int32_t)i;
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -754,6 +830,49 @@ int bvc_scatter(int32_t dtype, int64_t n_idx, const int32_t* idx, int32_t rows, 
     hipLaunchKernelGGL(k_scatter<float>, dim3(blocks), dim3(kBlock), 0, st, n_idx, idx, rows, ld_in,
                        (const float*)in, ld_out, (float*)out);
   return check_hip(hipGetLastError(), "scatter launch");
+}
+
+size_t bvc_spatial_order_workspace_bytes(void) { return (size_t)kOrderBuckets * sizeof(uint32_t); }
+
+int bvc_spatial_order(bvc_scene s, int32_t dtype, int64_t n, const void* x, int64_t ld, const int64_t* n_dev,
+                      int32_t* order, void* work, size_t work_bytes, void* stream) {
+  int rc = check_scene(s);
+  if (rc) return rc;
+  if (dtype != BVC_F32 && dtype != BVC_F64) return fail(BVC_EINVAL, "dtype must be F32 or F64");
+  if (n < 0 || ld < n) return fail(BVC_EINVAL, "need 0 <= n <= ld");
+  if (n > INT32_MAX) return fail(BVC_EINVAL, "n must fit int32 (order entries)");
+  if (n == 0) return BVC_OK;
+  if (!x || !order || !work) return fail(BVC_EINVAL, "null argument");
+  if (work_bytes < bvc_spatial_order_workspace_bytes()) return fail(BVC_EINVAL, "spatial order workspace too small");
+  if (((uintptr_t)work & 255) != 0) return fail(BVC_EINVAL, "spatial order workspace must be 256-byte aligned");
+  const SceneHost& h = s->h;
+  const int dim = h.dim;
+  OrderGrid g{};
+  g.bits = dim == 3 ? 5 : 8;
+  for (int a = 0; a < dim; ++a) {
+    const double ext = h.hi[a] - h.lo[a];
+    g.lo[a] = h.lo[a];
+    g.scale[a] = ext > 0.0 ? (double)(1 << g.bits) / ext : 0.0;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  uint32_t* hist = (uint32_t*)work;
+  rc = zero_async(hist, bvc_spatial_order_workspace_bytes(), st);
+  if (rc) return rc;
+  const int blocks = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, 4096);
+  if (dtype == BVC_F64)
+    hipLaunchKernelGGL(k_order_count<double>, dim3(blocks), dim3(kBlock), 0, st, g, dim, n, (const double*)x, ld,
+                       n_dev, hist);
+  else
+    hipLaunchKernelGGL(k_order_count<float>, dim3(blocks), dim3(kBlock), 0, st, g, dim, n, (const float*)x, ld,
+                       n_dev, hist);
+  hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(kBlock), 0, st, hist);
+  if (dtype == BVC_F64)
+    hipLaunchKernelGGL(k_order_place<double>, dim3(blocks), dim3(kBlock), 0, st, g, dim, n, (const double*)x, ld,
+                       n_dev, hist, order);
+  else
+    hipLaunchKernelGGL(k_order_place<float>, dim3(blocks), dim3(kBlock), 0, st, g, dim, n, (const float*)x, ld,
+                       n_dev, hist, order);
+  return check_hip(hipGetLastError(), "spatial order launch");
 }
 
 }  // extern "C"

@@ -817,6 +817,7 @@ int bvc_wost_walks(bvc_scene dir, bvc_scene neu, const bvc_walk_params* p, int32
   if (neu->h.dim != dim) return fail(BVC_EINVAL, "the Dirichlet and Neumann parts must have the same dimension");
   if (!p) return fail(BVC_EINVAL, "walk params are null");
   if (p->n_dev) return fail(BVC_EUNSUPPORTED, "a device point count is taken by the cache walks only");
+  if (p->order) return fail(BVC_EUNSUPPORTED, "walks on stars take no launch order");
   if (!(p->eps > 0) || p->max_steps < 1 || p->n_walks < 1) return fail(BVC_EINVAL, "bad walk parameters");
   if (p->dtype != BVC_F32 && p->dtype != BVC_F64) return fail(BVC_EINVAL, "walk dtype must be F32 or F64");
   rc = check_field(p->g, dim, "g");

@@ -63,6 +63,7 @@ struct WalkArgs {
   double orad;               // 0 = bounded domain
   int side;                  // side rule of double-sided data (reads moved towards the walk)
   const int64_t* n_dev;      // modes 0, 1: device count of start points (<= n_pts), or null
+  const int32_t* order;      // modes 0, 1: launch order of the start points, or null
 };
 
 // Open 3D domains (Appendix B).  A walk that has jumped (jump index k) to
@@ -403,8 +404,17 @@ __device__ __forceinline__ void walks_body(const WalkArgs& a, uint32_t* lds) {
     if (!exhausted) {
       const uint64_t need = __ballot(!active);
       if (need) {
-        const unsigned long long my = pool.take(need, lane, &a.counters[0], chunk, live, exhausted);
+        unsigned long long my = pool.take(need, lane, &a.counters[0], chunk, live, exhausted);
         if (!active) {
+          if (my != ~0ull && MODE != 2 && a.order) {
+            // launch slot -> walk: slot s runs walk s mod W of point
+            // order[s / W]; an entry outside the live points skips the walk
+            const uint32_t slot = (uint32_t)my, ps = slot / (uint32_t)a.W;
+            const int32_t pi = a.order[ps];
+            my = (pi >= 0 && (uint64_t)pi * (uint64_t)a.W < live)
+                     ? (unsigned long long)pi * (unsigned long long)a.W + (slot - ps * (uint32_t)a.W)
+                     : ~0ull;
+          }
           if (my != ~0ull) {
             // mode 2 walks start from the points their ids index (one walk each)
             id = MODE == 2 ? a.ids[my] : (uint32_t)my;
@@ -776,9 +786,12 @@ __global__ __launch_bounds__(kBlock) void k_reduce(int64_t n, int W, int rows, i
 
 // h: the scene of a call that takes open domains (cache, pointwise and
 // tuning walks); null for the calls that refuse them.
-int check_walk_params(const bvc_walk_params* p, int dim, const SceneHost* h = nullptr, bool count_ok = false) {
+int check_walk_params(const bvc_walk_params* p, int dim, const SceneHost* h = nullptr, bool count_ok = false,
+                      bool order_ok = false) {
   if (!p) return fail(BVC_EINVAL, "walk params are null");
   if (p->n_dev && !count_ok) return fail(BVC_EUNSUPPORTED, "a device point count is taken by the cache walks only");
+  if (p->order && !order_ok)
+    return fail(BVC_EUNSUPPORTED, "a launch order is taken by the cache, pointwise and tuning walks only");
   if (!(p->eps > 0) || !std::isfinite(p->eps)) return fail(BVC_EINVAL, "eps must be positive");
   if (p->max_steps < 1) return fail(BVC_EINVAL, "max_steps must be >= 1");
   if (p->n_walks < 1) return fail(BVC_EINVAL, "n_walks must be >= 1");
@@ -1146,7 +1159,7 @@ int cache_walks_entry(bvc_scene s, const bvc_walk_params* p, int64_t n_cache, co
                       int32_t* rec_steps, uint64_t* counters, void* stream, const WalkShape* force) {
   int rc = check_scene(s);
   if (rc) return rc;
-  rc = check_walk_params(p, s->h.dim, &s->h, true);
+  rc = check_walk_params(p, s->h.dim, &s->h, true, true);
   if (rc) return rc;
   if (n_cache < 0) return fail(BVC_EINVAL, "n_cache must be >= 0");
   if ((uint64_t)n_cache * (uint64_t)p->n_walks >= (1ull << 32)) return fail(BVC_EINVAL, "n_cache * W >= 2^32");
@@ -1165,6 +1178,7 @@ int cache_walks_entry(bvc_scene s, const bvc_walk_params* p, int64_t n_cache, co
   a.steps = rec_steps;
   a.counters = (unsigned long long*)counters;
   a.n_dev = p->n_dev;
+  a.order = p->order;
   return run_walks(s, p, 0, n_cache, a, (hipStream_t)stream, force);
 }
 }  // namespace
@@ -1294,7 +1308,7 @@ int pointwise_check(bvc_scene s, const bvc_walk_params* p, int64_t n, const void
                     const uint64_t* counters) {
   int rc = check_scene(s);
   if (rc) return rc;
-  rc = check_walk_params(p, s->h.dim, &s->h);
+  rc = check_walk_params(p, s->h.dim, &s->h, false, true);
   if (rc) return rc;
   if (n < 0) return fail(BVC_EINVAL, "n must be >= 0");
   if ((uint64_t)n * (uint64_t)p->n_walks >= (1ull << 32)) return fail(BVC_EINVAL, "n * W >= 2^32");
@@ -1349,6 +1363,7 @@ int pointwise_run(bvc_scene s, const bvc_walk_params* p, int64_t n, const void* 
   a.exit = ex;
   a.w1 = gw;
   a.counters = (unsigned long long*)counters;
+  a.order = p->order;
   int rc = run_walks(s, p, 1, n, a, st, force);
   if (rc || n == 0) return rc;
   const int per = kBlock / 64;
@@ -1496,7 +1511,7 @@ int bvc_tune_walks(bvc_scene s, const bvc_walk_params* p, int64_t n_cache, const
                    void* stream) {
   int rc = check_scene(s);
   if (rc) return rc;
-  rc = check_walk_params(p, s->h.dim, &s->h, true);
+  rc = check_walk_params(p, s->h.dim, &s->h, true, true);
   if (rc) return rc;
   if (reps < 1) return fail(BVC_EINVAL, "reps must be >= 1");
   bvc_walk_params q = *p;

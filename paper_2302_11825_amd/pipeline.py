@@ -73,6 +73,32 @@ class Scene:
             self._scratch[k] = torch.empty(B.bvc_compact_scratch_ints(n), dtype=torch.int32, device=self.device)
         return self._scratch[k]
 
+    def order_work(self):
+        k = ("order",)
+        if k not in self._scratch:
+            self._scratch[k] = torch.empty(B.bvc_spatial_order_workspace_bytes(), dtype=torch.uint8,
+                                           device=self.device)
+        return self._scratch[k]
+
+    @property
+    def ordered_walks(self) -> bool:
+        """Whether walks start in spatial order: when the FP32 traversal data
+        (nodes with their slab bounds, primitives) exceed one XCD's 4 MiB L2,
+        walks in flight together should query one part of the tree.  Smaller
+        trees stay in L2 whatever the order, and there the order's
+        indirection only costs."""
+        i = self.info
+        node, prim = (48, 16) if self.dim == 2 else (104, 48)
+        return i.n_nodes * node + i.n_prims * prim > (4 << 20)
+
+    def spatial_order(self, x, n, n_dev=None):
+        """Launch order of the points x ([dim][ld], ld >= n) by position, for
+        the walks' `order` (bvc_spatial_order): walks started together then
+        query nearby parts of the tree.  Results do not depend on it."""
+        order = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
+        B.bvc_spatial_order(self.h, n, x, order, self.order_work(), n_dev=n_dev)
+        return order
+
     def compact(self, flags, want):
         n = flags.numel()
         idx = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
@@ -94,6 +120,7 @@ class Cache:
         self.n_candidates = n_candidates
         self.n_dev = n_dev
         self.cap = n if cap is None else cap
+        self.order = None  # launch order of the walks, made by cache_walks
 
     @property
     def n(self) -> int:
@@ -220,6 +247,7 @@ def cache_walks(sc: Scene, cache: Cache, params: B.bvc_walk_params, dtype="f32",
     n, W = cache.cap, params.n_walks
     if cache.n_dev is not None:
         params.n_dev = cache.n_dev.data_ptr()
+    _set_cache_order(sc, cache, params)
     T = DT[dtype]
     U = torch.empty(max(n * W, 1), dtype=T, device=dev)
     D = torch.empty_like(U)
@@ -232,11 +260,23 @@ def cache_walks(sc: Scene, cache: Cache, params: B.bvc_walk_params, dtype="f32",
     return U, D, rec, counters
 
 
-def pointwise(sc: Scene, params: B.bvc_walk_params, x, with_grad=True):
+def _set_cache_order(sc: Scene, cache: Cache, params: B.bvc_walk_params):
+    """The cache walks start in the cache points' spatial order (once per
+    cache; up to the device count when there is one)."""
+    if cache.cap and cache.order is None and sc.ordered_walks:
+        cache.order = sc.spatial_order(cache.x, cache.cap, cache.n_dev)
+    if cache.order is not None:
+        params.order = cache.order.data_ptr()
+
+
+def pointwise(sc: Scene, params: B.bvc_walk_params, x, with_grad=True, order=None):
     """Pointwise walk on spheres at points x ([dim][n] of the walk dtype):
-    returns (u [n], grad [dim][n] or None, counters)."""
+    returns (u [n], grad [dim][n] or None, counters).  order: the points'
+    launch order (Scene.spatial_order), or None."""
     dev, d = sc.device, sc.dim
     n = x.shape[1] if x.dim() == 2 else 0
+    if order is not None and n:
+        params.order = order.data_ptr()
     W = params.n_walks
     T = x.dtype
     Uw = torch.empty(max(n * W, 1), dtype=T, device=dev)
@@ -337,6 +377,8 @@ class Prepared:
         T = DT[self.dtype]
         self.x_int = take(self.eval64, self.idx_int, self.n_int, self.sc.dim, n, T)
         self.x_band = take(self.eval64, self.idx_band, self.n_band, self.sc.dim, n, T)
+        self.band_order = (self.sc.spatial_order(self.x_band, self.n_band) if self.n_band and self.sc.ordered_walks
+                           else None)
         # FP32 gathers keep the near-singular boundary pairs in FP64: pairs
         # closer than tau (default: the offset l; an evaluation point lies at
         # least l from the boundary and a cache point exactly l from it) are
@@ -386,6 +428,7 @@ class Prepared:
         self.n_gb = 0
         self.gb_pos = None
         self.x_gb = None
+        self.gb_order = None
         self.gb_walks = int(walks or self.p.n_walks)
         if width is None or width <= self.band or self.n_int == 0:
             return
@@ -398,6 +441,7 @@ class Prepared:
         if self.n_gb:
             self.x_gb = take(self.eval64, self.idx_int[pos[: self.n_gb].to(torch.int64)].contiguous(), self.n_gb, d,
                              n, DT[self.dtype])
+            self.gb_order = self.sc.spatial_order(self.x_gb, self.n_gb) if self.sc.ordered_walks else None
 
     def _prepare_clamp(self, clamp, device):
         """Clamped gather with bias correction (Section 3.3, Eq. 8).  clamp:
@@ -860,6 +904,7 @@ def tune(prep: Prepared, with_grad=True, reps=3) -> dict:
     wp = walk_params(p.eps, p.n_walks, p.seed_walks, prep.g, prep.f, dt, 0, sigma=p.sigma,
                      open_sphere=p.extra.get("open_sphere"), side_read=p.side_read)
     wp.n_dev = cache.n_dev.data_ptr()
+    _set_cache_order(sc, cache, wp)
     n, W = cache.cap, p.n_walks
     U = torch.empty(max(n * W, 1), dtype=T, device=sc.device)
     D = torch.empty_like(U)
@@ -890,6 +935,8 @@ def tune(prep: Prepared, with_grad=True, reps=3) -> dict:
         ub = torch.empty(nb, dtype=T, device=sc.device)
         gb = torch.empty(d, nb, dtype=T, device=sc.device) if with_grad else None
         cnt = torch.zeros(4, dtype=torch.int64, device=sc.device)
+        if prep.band_order is not None:
+            wpb.order = prep.band_order.data_ptr()
         bpb, lb, sb = B.bvc_tune_pointwise(sc.h, wpb, nb, xb, Uw, Gw, work, ub, gb, cnt, reps)
         out.update(band_blocks_per_cu=bpb, band_open_lanes=lb, band_slabs=sb)
     return out
@@ -930,7 +977,8 @@ def solve(prep: Prepared, batch=0, with_grad=True, n_walks_band=None, records=Fa
                       side_read=p.side_read)
     watch.kernel("k_walks_band", wpb)
     with watch.stage("band_walks"):
-        u_band, g_band, pwc = pointwise(sc, wpb, prep.x_band[:, :nb] if nb else prep.x_band[:, :0], with_grad)
+        u_band, g_band, pwc = pointwise(sc, wpb, prep.x_band[:, :nb] if nb else prep.x_band[:, :0], with_grad,
+                                        order=prep.band_order)
     gb = None
     if with_grad and prep.n_gb:
         # pointwise gradients near the boundary replace the gathered ones
@@ -938,7 +986,7 @@ def solve(prep: Prepared, batch=0, with_grad=True, n_walks_band=None, records=Fa
                           sigma=p.sigma, open_sphere=osph, side_read=p.side_read)
         watch.kernel("k_walks_grad_band", wpg)
         with watch.stage("grad_band_walks"):
-            _, gg, gbc = pointwise(sc, wpg, prep.x_gb, True)
+            _, gg, gbc = pointwise(sc, wpg, prep.x_gb, True, order=prep.gb_order)
             B.bvc_scatter(B.dtype_code(T), prep.n_gb, prep.gb_pos, d, gg.shape[1], gg, g_int.shape[1], g_int)
         gb = dict(n=prep.n_gb, width=prep.grad_band, walks=prep.gb_walks, counters=gbc)
     if cl:
