@@ -896,6 +896,52 @@ __device__ inline double solid_harmonics(const double* coef, int L, const double
   return only >= 0 ? 0.0 : total;
 }
 
+// The same series in FP32 for FP32 walks: tab[l*l + l + m] holds coef times
+// the normalisation (rounded once to FP32, see solid_harmonics_table), and the
+// recurrences run in FP32 (relative error a few ulp per degree).
+__device__ inline float solid_harmonics_f32(const float* tab, int L, const float* x) {
+  const float* inv = tab + (L + 1) * (L + 1);
+  const float r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+  float cm = 1.0f, sm = 0.0f;
+  float dfact = 1.0f;
+  float total = 0.0f;
+  for (int m = 0; m <= L; ++m) {
+    if (m > 0) {
+      const float c2 = cm * x[0] - sm * x[1];
+      sm = cm * x[1] + sm * x[0];
+      cm = c2;
+      dfact *= (float)(2 * m - 1);
+    }
+    float qm2 = 0.0f, qm1 = 0.0f;
+    for (int l = m; l <= L; ++l) {
+      float q;
+      if (l == m) q = dfact;
+      else if (l == m + 1) q = (float)(2 * m + 1) * x[2] * dfact;
+      else q = ((float)(2 * l - 1) * x[2] * qm1 - (float)(l + m - 1) * r2 * qm2) * inv[l - m];
+      qm2 = qm1;
+      qm1 = q;
+      const float cq = tab[l * l + l + m] * cm;
+      total = fmaf(cq, q, total);
+      if (m > 0) total = fmaf(tab[l * l + l - m] * sm, q, total);
+    }
+  }
+  return total;
+}
+
+// Fills tab[0 .. (L+1)^2 + L] for solid_harmonics_f32 (coefficient times
+// normalisation, in FP64, rounded to FP32) and after them the reciprocals
+// 1/j, j = 0..L, the threads of the block sharing the entries.
+__device__ inline void solid_harmonics_table(const double* coef, int L, float* tab) {
+  for (int j = threadIdx.x; j <= L; j += blockDim.x) tab[(L + 1) * (L + 1) + j] = (float)kFieldTables.inv[j];
+  for (int k = threadIdx.x; k < (L + 1) * (L + 1); k += blockDim.x) {
+    // entry l*l + l + m for |m| <= l; the normalisation depends on |m|
+    int l = 0;
+    while ((l + 1) * (l + 1) <= k) ++l;
+    const int m = k - l * l - l;
+    tab[k] = (float)(coef[k] * kFieldTables.sh_norm[l * l + l + (m < 0 ? -m : m)]);
+  }
+}
+
 __device__ inline double fourier_basis(int b, double th) {
   if (b == 0) return 1.0;
   const int j = (b + 1) / 2;

@@ -645,6 +645,7 @@ __global__ __launch_bounds__(kBlock) void k_walks_ss(WalkArgs a) {
 // l of each run, so that every load and store is coalesced; a lane evaluates
 // the control variate only when its start point changes.
 constexpr int kFinishRun = 8;
+constexpr int kShTab = (FieldTables::kMaxL + 1) * (FieldTables::kMaxL + 1) + FieldTables::kMaxL + 1;
 
 template <typename T, int D, int MODE>
 __global__ __launch_bounds__(kBlock) void k_finish(FieldDev g, int cv, uint64_t total, int W, int64_t n_pts,
@@ -659,6 +660,15 @@ __global__ __launch_bounds__(kBlock) void k_finish(FieldDev g, int cv, uint64_t 
     const uint64_t t = (uint64_t)(c > 0 ? c : 0) * (uint64_t)W;
     if (t < live) live = t;
   }
+  // FP32 walks evaluate solid-harmonic data from an FP32 table of
+  // coefficient times normalisation kept in LDS
+  __shared__ float sh_tab[kShTab];
+  const bool sh32 = sizeof(T) == 4 && g.kind == 5 && (int)g.param[0] <= FieldTables::kMaxL;
+  if (sh32) {
+    solid_harmonics_table(g.coef, (int)g.param[0], sh_tab);
+    __syncthreads();
+  }
+  const int sh_L = (int)g.param[0];
   const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const uint64_t id0 = wave * (64 * kFinishRun) + (threadIdx.x & 63);
   const bool scr = sigma > 0.0;
@@ -686,7 +696,8 @@ __global__ __launch_bounds__(kBlock) void k_finish(FieldDev g, int cv, uint64_t 
         float xf[D];
 #pragma unroll
         for (int q = 0; q < D; ++q) xf[q] = (float)xb[q];
-        c = field_value_f32(g, D, xf);
+        if constexpr (D == 3) c = sh32 ? (double)solid_harmonics_f32(sh_tab, sh_L, xf) : field_value_f32(g, D, xf);
+        else c = field_value_f32(g, D, xf);
       } else {
         c = field_value(g, D, xb);
       }
@@ -697,7 +708,11 @@ __global__ __launch_bounds__(kBlock) void k_finish(FieldDev g, int cv, uint64_t 
       float q[D];
 #pragma unroll
       for (int e = 0; e < D; ++e) q[e] = EX[(size_t)e * total + id];
-      gq = isnan(q[0]) ? 0.0 : field_value_f32(g, D, q);  // NaN: escaped, u = 0 at infinity
+      // NaN: escaped, u = 0 at infinity
+      if constexpr (D == 3)
+        gq = isnan(q[0]) ? 0.0 : sh32 ? (double)solid_harmonics_f32(sh_tab, sh_L, q) : field_value_f32(g, D, q);
+      else
+        gq = isnan(q[0]) ? 0.0 : field_value_f32(g, D, q);
     } else {
       double q[D];
 #pragma unroll

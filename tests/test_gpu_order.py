@@ -152,3 +152,4 @@ def test_order_refused_where_not_taken():
     cnt = torch.zeros(6, dtype=torch.int64, device="cuda")
     with pytest.raises(_bvc.BVCError):
         _bvc.bvc_clamp_correction(sc.h, p, cp, 1, x, wind, pos, u, ws, cnt)
+
