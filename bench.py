@@ -270,6 +270,10 @@ def walk_roofline(kernel, dim, es, mode, with_grad, ms, queries, walks, work_key
         gbs = alg / (ms / 1e3) / 1e9
         out.update(achieved=round(gbs, 1), frac=round(gbs / PEAK_HBM_GBS, 4), nodes_per_query=vn,
                    prims_per_query=vp, bytes_per_query=round(per_query, 1), bytes_per_launch=alg)
+        if gbs > PEAK_HBM_GBS:
+            out["note"] = ("the algorithmic bytes outrun the HBM peak: L2 and the MALL serve the traversal data "
+                           "(traffic counts only what missed L2), so HBM does not bind; the kernel's limit is "
+                           "VALU issue (roofline_valu)")
         ops = (philox_blocks_per_step(dim, src) * OPS_PHILOX_BLOCK + OPS_STEP[dim] + vn * ops_node +
                vp * OPS_PRIM[dim])
         rate = queries * ops / (ms / 1e3)
