@@ -948,9 +948,24 @@ def solve(prep: Prepared, batch=0, with_grad=True, n_walks_band=None, records=Fa
     T = DT[dt]
     d = sc.dim
     watch = watch or _NoWatch()
+    osph = p.extra.get("open_sphere")
+    Wb = n_walks_band or p.n_walks
+    nb = prep.n_band
+    wpb = walk_params(p.eps, Wb, p.seed_walks, prep.g, prep.f, dt, batch, sigma=p.sigma, open_sphere=osph,
+                      side_read=p.side_read)
+    band = None
+    main = torch.cuda.current_stream()
+    if nb and not sc.ordered_walks and prep.clamp is None:
+        # trees that fit L2 make short kernels: the band walks, which need
+        # nothing from the cache, run on a second stream (default priority)
+        # beside the cache walks and the gather, filling their tails
+        side = prep.__dict__.setdefault("_band_stream", torch.cuda.Stream())
+        side.wait_stream(main)
+        watch.kernel("k_walks_band", wpb)
+        with torch.cuda.stream(side):
+            band = pointwise(sc, wpb, prep.x_band[:, :nb], with_grad, order=prep.band_order)
     with watch.stage("sample_cache"):
         cache = sample_cache_device(sc, prep.n_cand, prep.n_cap, p.offset, p.sides, p.seed_cache, batch)
-    osph = p.extra.get("open_sphere")
     wp = walk_params(p.eps, p.n_walks, p.seed_walks, prep.g, prep.f, dt, batch, sigma=p.sigma, open_sphere=osph,
                      side_read=p.side_read)
     watch.kernel("k_walks_cache", wp)
@@ -971,14 +986,14 @@ def solve(prep: Prepared, batch=0, with_grad=True, n_walks_band=None, records=Fa
     if cl:
         gathered = torch.cuda.Event()
         gathered.record()
-    Wb = n_walks_band or p.n_walks
-    nb = prep.n_band
-    wpb = walk_params(p.eps, Wb, p.seed_walks, prep.g, prep.f, dt, batch, sigma=p.sigma, open_sphere=osph,
-                      side_read=p.side_read)
-    watch.kernel("k_walks_band", wpb)
-    with watch.stage("band_walks"):
-        u_band, g_band, pwc = pointwise(sc, wpb, prep.x_band[:, :nb] if nb else prep.x_band[:, :0], with_grad,
-                                        order=prep.band_order)
+    if band is None:
+        watch.kernel("k_walks_band", wpb)
+        with watch.stage("band_walks"):
+            u_band, g_band, pwc = pointwise(sc, wpb, prep.x_band[:, :nb] if nb else prep.x_band[:, :0], with_grad,
+                                            order=prep.band_order)
+    else:
+        main.wait_stream(side)
+        u_band, g_band, pwc = band
     gb = None
     if with_grad and prep.n_gb:
         # pointwise gradients near the boundary replace the gathered ones
