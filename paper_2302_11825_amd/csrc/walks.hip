@@ -609,9 +609,11 @@ __device__ __forceinline__ void walks_body(const WalkArgs& a, uint32_t* lds) {
 }
 
 // Walks in bounded domains, and (3D, Laplace, no source) in open domains,
-// whose extra step stays out of the bounded kernels.
+// whose extra step stays out of the bounded kernels.  2D kernels are held to
+// 64 VGPRs (a few values spill), so that eight waves per SIMD hide more of
+// their short queries' latency; 3D kernels keep their registers.
 template <typename T, int D, bool SRC, int MODE>
-__global__ __launch_bounds__(kBlock) void k_walks(WalkArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(D == 2 ? 8 : 1))) void k_walks(WalkArgs a) {
   extern __shared__ uint32_t lds[];
   walks_body<T, D, SRC, MODE, false>(a, lds);
 }
