@@ -928,6 +928,51 @@ __device__ inline float solid_harmonics_f32(const float* tab, int L, const float
   return total;
 }
 
+// solid_harmonics_f32 at N points at once: each table entry, read once, serves
+// the N evaluations, whose recurrences run side by side.
+template <int N>
+__device__ inline void solid_harmonics_f32_n(const float* tab, int L, const float (*x)[3], float* out) {
+  const float* inv = tab + (L + 1) * (L + 1);
+  float r2[N], cm[N], sm[N], tot[N], qm1[N], qm2[N];
+#pragma unroll
+  for (int n = 0; n < N; ++n) {
+    r2[n] = x[n][0] * x[n][0] + x[n][1] * x[n][1] + x[n][2] * x[n][2];
+    cm[n] = 1.0f;
+    sm[n] = 0.0f;
+    tot[n] = 0.0f;
+  }
+  float dfact = 1.0f;
+  for (int m = 0; m <= L; ++m) {
+    if (m > 0) {
+#pragma unroll
+      for (int n = 0; n < N; ++n) {
+        const float c2 = cm[n] * x[n][0] - sm[n] * x[n][1];
+        sm[n] = cm[n] * x[n][1] + sm[n] * x[n][0];
+        cm[n] = c2;
+      }
+      dfact *= (float)(2 * m - 1);
+    }
+    for (int l = m; l <= L; ++l) {
+      const float tc = tab[l * l + l + m], ts = tab[l * l + l - m];
+      const float a1 = (float)(2 * l - 1), a2 = (float)(l + m - 1), il = inv[l - m];
+      const float b1 = (float)(2 * m + 1);
+#pragma unroll
+      for (int n = 0; n < N; ++n) {
+        float q;
+        if (l == m) q = dfact;
+        else if (l == m + 1) q = b1 * x[n][2] * dfact;
+        else q = (a1 * x[n][2] * qm1[n] - a2 * r2[n] * qm2[n]) * il;
+        qm2[n] = qm1[n];
+        qm1[n] = q;
+        tot[n] = fmaf(tc * cm[n], q, tot[n]);
+        if (m > 0) tot[n] = fmaf(ts * sm[n], q, tot[n]);
+      }
+    }
+  }
+#pragma unroll
+  for (int n = 0; n < N; ++n) out[n] = tot[n];
+}
+
 // Fills tab[0 .. (L+1)^2 + L] for solid_harmonics_f32 (coefficient times
 // normalisation, in FP64, rounded to FP32) and after them the reciprocals
 // 1/j, j = 0..L, the threads of the block sharing the entries.

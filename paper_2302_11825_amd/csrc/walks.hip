@@ -649,12 +649,14 @@ __global__ __launch_bounds__(kBlock) void k_walks_ss(WalkArgs a) {
 constexpr int kFinishRun = 8;
 constexpr int kShTab = (FieldTables::kMaxL + 1) * (FieldTables::kMaxL + 1) + FieldTables::kMaxL + 1;
 
+// The field evaluators of every kind inline here and would take about 170
+// VGPRs (two waves per SIMD); four waves hide the streaming loads better, the
+// few spilled values sit on the rarely taken kinds' paths.
 template <typename T, int D, int MODE>
-__global__ __launch_bounds__(kBlock) void k_finish(FieldDev g, int cv, uint64_t total, int W, int64_t n_pts,
-                                                    const double* xbar, const T* EX, T* U, T* Dof, const T* W1,
-                                                    double sigma, double eps, const double* R0, int side,
-                                                    const double* x64, const T* xT, const int64_t* n_dev,
-                                                    int ss) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_finish(
+    FieldDev g, int cv, uint64_t total, int W, int64_t n_pts, const double* xbar, const T* EX, T* U, T* Dof,
+    const T* W1, double sigma, double eps, const double* R0, int side, const double* x64, const T* xT,
+    const int64_t* n_dev, int ss) {
   // ids below `live` are finished; `total` stays the records' stride
   uint64_t live = total;
   if (n_dev) {
@@ -673,6 +675,24 @@ __global__ __launch_bounds__(kBlock) void k_finish(FieldDev g, int cv, uint64_t 
   const int sh_L = (int)g.param[0];
   const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const uint64_t id0 = wave * (64 * kFinishRun) + (threadIdx.x & 63);
+  // the lane's exits of all runs evaluated together (solid harmonics, FP32),
+  // parked in LDS for the run loop
+  __shared__ float g8s[kFinishRun * kBlock];
+  if constexpr (sizeof(T) == 4 && D == 3) {
+    if (sh32) {
+      float q8[kFinishRun][3], g8[kFinishRun];
+#pragma unroll
+      for (int r = 0; r < kFinishRun; ++r) {
+        const uint64_t id = id0 + (uint64_t)r * 64;
+#pragma unroll
+        for (int e = 0; e < 3; ++e) q8[r][e] = id < live ? (float)EX[(size_t)e * total + id] : 0.0f;
+      }
+      solid_harmonics_f32_n<kFinishRun>(sh_tab, sh_L, q8, g8);
+#pragma unroll
+      for (int r = 0; r < kFinishRun; ++r)
+        g8s[r * kBlock + threadIdx.x] = isnan(q8[r][0]) ? 0.0f : g8[r];  // NaN: escaped, u = 0
+    }
+  }
   const bool scr = sigma > 0.0;
   const double s = scr ? sqrt(sigma) : 0.0;
   int64_t i_cv = -1;
@@ -707,14 +727,14 @@ __global__ __launch_bounds__(kBlock) void k_finish(FieldDev g, int cv, uint64_t 
     }
     double gq;
     if constexpr (sizeof(T) == 4) {
-      float q[D];
+      if (D == 3 && sh32) {
+        gq = (double)g8s[r * kBlock + threadIdx.x];
+      } else {
+        float q[D];
 #pragma unroll
-      for (int e = 0; e < D; ++e) q[e] = EX[(size_t)e * total + id];
-      // NaN: escaped, u = 0 at infinity
-      if constexpr (D == 3)
-        gq = isnan(q[0]) ? 0.0 : sh32 ? (double)solid_harmonics_f32(sh_tab, sh_L, q) : field_value_f32(g, D, q);
-      else
-        gq = isnan(q[0]) ? 0.0 : field_value_f32(g, D, q);
+        for (int e = 0; e < D; ++e) q[e] = EX[(size_t)e * total + id];
+        gq = isnan(q[0]) ? 0.0 : field_value_f32(g, D, q);  // NaN: escaped, u = 0 at infinity
+      }
     } else {
       double q[D];
 #pragma unroll
