@@ -222,7 +222,7 @@ def measured_traffic(kernel, workload, sources):
 
 
 GATHER_SOURCES = ("kernels_gather.hip", "bvc_device.hpp", "bvc_internal.hpp")
-WALK_SOURCES = ("walks.hip", "bvc_device.hpp", "bvc_internal.hpp")
+WALK_SOURCES = ("walks.hip", "bvc_device.hpp", "bvc_internal.hpp", "scene.cpp")  # the tree the walks read
 
 
 def walk_bytes(dim, es, mode, with_grad, slabs=True):

@@ -285,11 +285,11 @@ static int build_scene(SceneHost& S, int dim, const double* verts, int64_t nv, c
     }
   std::vector<int> perm(np);
   std::iota(perm.begin(), perm.end(), 0);
-  // One primitive per leaf while the node indices fit: a node expansion then
-  // tests at most two primitives, which keeps the 64 lanes of a wave doing
-  // the same amount of work per traversal step.  Larger scenes use leaves of
-  // up to kLeafMax primitives.
-  const int leaf_max = np < (1 << 17) ? 1 : kLeafMax;
+  // Up to three primitives per leaf while the node indices fit (measured
+  // best for the walks' closest-point queries among 1 to 8: shallower trees
+  // trade node expansions for primitive tests, which the traversal takes one
+  // per step); larger scenes use leaves of up to kLeafMax primitives.
+  const int leaf_max = np < (1 << 17) ? 3 : kLeafMax;
   Builder B{dim, plo, phi, cen, perm, {}, leaf_max};
   B.nodes.reserve(2 * np + 2);
   int root = B.build(0, (int)np, 1);
