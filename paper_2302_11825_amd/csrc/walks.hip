@@ -609,11 +609,13 @@ __device__ __forceinline__ void walks_body(const WalkArgs& a, uint32_t* lds) {
 }
 
 // Walks in bounded domains, and (3D, Laplace, no source) in open domains,
-// whose extra step stays out of the bounded kernels.  2D kernels are held to
-// 64 VGPRs (a few values spill), so that eight waves per SIMD hide more of
-// their short queries' latency; 3D kernels keep their registers.
+// whose extra step stays out of the bounded kernels.  Register budgets of the
+// FP32 kernels, set for latency hiding: 2D held to 64 VGPRs (eight waves per
+// SIMD, a few values spill), 3D to 72 (seven waves; eight spill too much).
+// FP64 kernels keep their registers.
 template <typename T, int D, bool SRC, int MODE>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(D == 2 ? 8 : 1))) void k_walks(WalkArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? (D == 2 ? 8 : 7) : 1)))
+void k_walks(WalkArgs a) {
   extern __shared__ uint32_t lds[];
   walks_body<T, D, SRC, MODE, false>(a, lds);
 }
