@@ -861,7 +861,8 @@ def _gather_views(prep: Prepared, cache: Cache, a, b, batch, watch):
 def _near(prep: Prepared, cache: Cache, U, D):
     """Near-field argument of an FP32 gather (None when off): FP64 cache
     values a, b from the walks' FP64 means, and the FP64 cache points,
-    normals and evaluation points (the near set's when the gather is split)."""
+    normals and evaluation points (reordered, with the near-field points
+    leading, when the gathered points were reordered)."""
     if not prep.near_tau or cache.cap == 0:
         return None
     _, _, a64, b64 = reduce_walks(cache, prep.p.n_walks, U, D, "f64")
