@@ -358,7 +358,9 @@ typedef struct {
  * BVC_F32 or BVC_F64; order: device int32 [n] (entries from count on are left
  * unwritten); work: device workspace of at least
  * bvc_spatial_order_workspace_bytes() bytes, 256-byte aligned, overwritten.
- * Allocates nothing; no host synchronisation. */
+ * Allocates nothing; no host synchronisation.  BVC_EINVAL for another dtype,
+ * n < 0, n > INT32_MAX, ld < n, a null argument (n > 0) or a short or
+ * misaligned workspace; BVC_ESTATE for a scene not uploaded. */
 size_t bvc_spatial_order_workspace_bytes(void);
 int bvc_spatial_order(bvc_scene scene, int32_t dtype, int64_t n, const void* x, int64_t ld, const int64_t* n_dev,
                       int32_t* order, void* work, size_t work_bytes, void* stream);
