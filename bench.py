@@ -573,6 +573,11 @@ def run_workload(args, which):
                                           int(sol.counters[1]), int(sol.counters[3]), "cache", work, src, None)
     if work is not None:
         roofline["counted_on"] = work["counted_on"]
+    if prep.n_band and prep.clamp is None:
+        # the two walk launches of a step overlap on two streams
+        first = prep.band_first == (dim == 2)
+        roofline["overlap"] = ("the other walk launch runs beside this one on a second stream; this one "
+                               + ("starts first" if first else "starts second and its duration includes the wait"))
 
     config = {"workload": prob.name, "primitives": int(prob.scene.prims.shape[0]),
               "cache_target": prob.n_cache, "cache_candidates": prep.n_cand, "cache_points": sol.cache.n,

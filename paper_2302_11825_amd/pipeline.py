@@ -240,9 +240,10 @@ def walk_params(eps, n_walks, seed, g: DeviceField, f: Optional[DeviceField], dt
     return p
 
 
-def cache_walks(sc: Scene, cache: Cache, params: B.bvc_walk_params, dtype="f32", records=False):
+def cache_walks(sc: Scene, cache: Cache, params: B.bvc_walk_params, dtype="f32", records=False, started=None):
     """Walks from every cache point; a cache with a device count is walked up
-    to that count (outputs laid out for its capacity)."""
+    to that count (outputs laid out for its capacity).  started: an event
+    recorded on the stream right before the walk launch, or None."""
     dev = sc.device
     n, W = cache.cap, params.n_walks
     if cache.n_dev is not None:
@@ -255,6 +256,8 @@ def cache_walks(sc: Scene, cache: Cache, params: B.bvc_walk_params, dtype="f32",
                w1=torch.empty(max(n * W, 1), dtype=T, device=dev),
                steps=torch.empty(max(n * W, 1), dtype=torch.int32, device=dev) if records else None)
     counters = torch.zeros(4, dtype=torch.int64, device=dev)
+    if started is not None:
+        started.record()
     B.bvc_cache_walks(sc.h, params, n, cache.x, cache.nrm, cache.R0, cache.xbar, U, D, rec["exit"], rec["w1"],
                       rec["steps"], counters)
     return U, D, rec, counters
@@ -379,6 +382,9 @@ class Prepared:
         self.x_band = take(self.eval64, self.idx_band, self.n_band, self.sc.dim, n, T)
         self.band_order = (self.sc.spatial_order(self.x_band, self.n_band) if self.n_band and self.sc.ordered_walks
                            else None)
+        # which walk launch of a solve starts first when the two overlap (the
+        # longer one; tune() measures them): by launch size until then
+        self.band_first = self.n_band > self.n_cap
         # FP32 gathers keep the near-singular boundary pairs in FP64: pairs
         # closer than tau (default: the offset l; an evaluation point lies at
         # least l from the boundary and a cache point exactly l from it) are
@@ -914,6 +920,8 @@ def tune(prep: Prepared, with_grad=True, reps=3) -> dict:
     counters = torch.zeros(4, dtype=torch.int64, device=sc.device)
     bpc, lanes, slabs = B.bvc_tune_walks(sc.h, wp, n, cache.x, cache.nrm, cache.R0, cache.xbar, U, D, ex, w1, counters,
                                   reps)
+    cache_ms = _launch_ms(wp, lambda: B.bvc_cache_walks(sc.h, wp, n, cache.x, cache.nrm, cache.R0, cache.xbar, U, D,
+                                                        ex, w1, None, counters))
     _, _, a, b = reduce_walks(cache, W, U, D, dt)
     cview, sview = _gather_views(prep, cache, a, b, 0, _NoWatch())
     u = torch.empty(max(prep.n_int, 1), dtype=T, device=sc.device)
@@ -939,8 +947,24 @@ def tune(prep: Prepared, with_grad=True, reps=3) -> dict:
         if prep.band_order is not None:
             wpb.order = prep.band_order.data_ptr()
         bpb, lb, sb = B.bvc_tune_pointwise(sc.h, wpb, nb, xb, Uw, Gw, work, ub, gb, cnt, reps)
-        out.update(band_blocks_per_cu=bpb, band_open_lanes=lb, band_slabs=sb)
+        band_ms = _launch_ms(wpb, lambda: B.bvc_pointwise_wos(sc.h, wpb, nb, xb, Uw, Gw, work, ub, gb, cnt))
+        prep.band_first = band_ms > cache_ms
+        out.update(band_blocks_per_cu=bpb, band_open_lanes=lb, band_slabs=sb, band_first=prep.band_first)
     return out
+
+
+def _launch_ms(params: B.bvc_walk_params, launch) -> float:
+    """Duration of one walk launch in ms (events the library records right
+    around its kernel)."""
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    e1.record()
+    params.ev_begin, params.ev_end = e0.cuda_event, e1.cuda_event
+    launch()
+    params.ev_begin = params.ev_end = None
+    e1.synchronize()
+    return e0.elapsed_time(e1)
 
 
 def solve(prep: Prepared, batch=0, with_grad=True, n_walks_band=None, records=False, watch=None) -> Solution:
@@ -956,22 +980,31 @@ def solve(prep: Prepared, batch=0, with_grad=True, n_walks_band=None, records=Fa
                       side_read=p.side_read)
     band = None
     main = torch.cuda.current_stream()
-    if nb and not sc.ordered_walks and prep.clamp is None:
-        # trees that fit L2 make short kernels: the band walks, which need
-        # nothing from the cache, run on a second stream (default priority)
-        # beside the cache walks and the gather, filling their tails
-        side = prep.__dict__.setdefault("_band_stream", torch.cuda.Stream())
-        side.wait_stream(main)
+    # the band walks need nothing from the cache: once it is sampled they run
+    # on a second stream (default priority) beside the cache walks and the
+    # gather.  The longer of the two walk launches starts first and holds the
+    # GPU at its own speed; the shorter fills the CUs its blocks leave.
+    side = prep.__dict__.setdefault("_band_stream", torch.cuda.Stream()) if nb and prep.clamp is None else None
+
+    def launch_band():
         watch.kernel("k_walks_band", wpb)
         with torch.cuda.stream(side):
-            band = pointwise(sc, wpb, prep.x_band[:, :nb], with_grad, order=prep.band_order)
+            return pointwise(sc, wpb, prep.x_band[:, :nb], with_grad, order=prep.band_order)
+
     with watch.stage("sample_cache"):
         cache = sample_cache_device(sc, prep.n_cand, prep.n_cap, p.offset, p.sides, p.seed_cache, batch)
+    if side is not None and prep.band_first:
+        side.wait_stream(main)
+        band = launch_band()
     wp = walk_params(p.eps, p.n_walks, p.seed_walks, prep.g, prep.f, dt, batch, sigma=p.sigma, open_sphere=osph,
                      side_read=p.side_read)
     watch.kernel("k_walks_cache", wp)
+    started = torch.cuda.Event() if side is not None and band is None else None
     with watch.stage("cache_walks"):
-        U, D, rec, counters = cache_walks(sc, cache, wp, dt, records)
+        U, D, rec, counters = cache_walks(sc, cache, wp, dt, records, started=started)
+    if started is not None:
+        side.wait_event(started)
+        band = launch_band()
     with watch.stage("reduce_walks"):
         uhat, dudn, a, b = reduce_walks(cache, p.n_walks, U, D, dt)
         near = _near(prep, cache, U, D)
