@@ -573,7 +573,7 @@ def run_workload(args, which):
                                           int(sol.counters[1]), int(sol.counters[3]), "cache", work, src, None)
     if work is not None:
         roofline["counted_on"] = work["counted_on"]
-    if prep.n_band and prep.clamp is None:
+    if prep.n_band:
         # the two walk launches of a step overlap on two streams
         first = prep.band_first == (dim == 2)
         roofline["overlap"] = ("the other walk launch runs beside this one on a second stream; this one "

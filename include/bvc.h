@@ -608,7 +608,8 @@ size_t bvc_clamp_workspace_bytes(int32_t dim, int32_t dtype, int64_t n, int32_t 
  * crossings, [1] rays with more than max_hits of them or more candidates than
  * the ray kernel holds (their extra crossings are dropped), [2] walk queue,
  * [3] closest-point queries of the walks, [4] capped walks, [5] walks.
- * Synchronises the stream once (the number of walks sizes their launch). */
+ * No host synchronisation: the number of contributing crossings stays on the
+ * device (in the workspace) and bounds the walk queue there. */
 int bvc_clamp_correction(bvc_scene scene, const bvc_walk_params* params, const bvc_clamp_params* cp,
                          int64_t n, const double* x, const int32_t* wind, const int64_t* out_index,
                          void* u, void* workspace, size_t workspace_bytes, uint64_t* counters,

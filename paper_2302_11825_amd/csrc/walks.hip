@@ -62,7 +62,8 @@ struct WalkArgs {
   double oc[3];              // open 3D domain: sphere enclosing the boundary,
   double orad;               // 0 = bounded domain
   int side;                  // side rule of double-sided data (reads moved towards the walk)
-  const int64_t* n_dev;      // modes 0, 1: device count of start points (<= n_pts), or null
+  const int64_t* n_dev;      // device count of start points (modes 0, 1; <= n_pts) or of queued ids
+                             // (mode 2; <= total), or null
   const int32_t* order;      // modes 0, 1: launch order of the start points, or null
 };
 
@@ -378,11 +379,12 @@ __device__ __forceinline__ void walks_body(const WalkArgs& a, uint32_t* lds) {
   // same jump code as every later ball).
   bool active = false, jump = false, exhausted = false;
   IdPool pool;
-  // a device-resident start-point count bounds the ids and sets the claim
-  // size (the host sized the grid and records for the capacity n_pts)
+  // a device-resident count (start points, or queued ids in mode 2, where W
+  // is 1) bounds the ids and sets the claim size (the host sized the grid and
+  // records for the capacity)
   uint64_t live = a.total;
   unsigned long long chunk = a.chunk;
-  if (MODE != 2 && a.n_dev) {
+  if (a.n_dev) {
     const int64_t c = *a.n_dev;
     const uint64_t t = (uint64_t)(c > 0 ? c : 0) * (uint64_t)a.W;
     if (t < live) live = t;
@@ -1518,22 +1520,24 @@ int bvc_clamp_correction(bvc_scene s, const bvc_walk_params* p, const bvc_clamp_
                        cp->max_hits, p->seed, p->batch, slot_x, slot_R0, slot_xbar, slot_w, flags,
                        (unsigned long long*)counters, st);
   if (rc) return rc;
-  int64_t count = 0;
-  rc = bvc_compact((int64_t)slots, flags, 1, ids, scratch, &count, stream);
+  // the contributing crossings stay counted on the device (the first 8 bytes
+  // of the compaction scratch): the walk launch is sized for every slot and
+  // its kernel reads the count, so the call never waits for the GPU
+  int64_t* count = (int64_t*)scratch;
+  rc = bvc_compact_count((int64_t)slots, flags, 1, ids, scratch, count, stream);
   if (rc) return rc;
-  if (count > 0) {
-    WalkArgs a{};
-    a.x = slot_x;
-    a.R0 = slot_R0;
-    a.xbar = slot_xbar;
-    a.ids = (const uint32_t*)ids;
-    a.ld = slots;
-    a.U = U;
-    a.exit = EX;
-    a.counters = (unsigned long long*)(counters + 2);
-    rc = run_walks(s, p, 2, count, a, st);
-    if (rc) return rc;
-  }
+  WalkArgs a{};
+  a.x = slot_x;
+  a.R0 = slot_R0;
+  a.xbar = slot_xbar;
+  a.ids = (const uint32_t*)ids;
+  a.ld = slots;
+  a.U = U;
+  a.exit = EX;
+  a.n_dev = count;
+  a.counters = (unsigned long long*)(counters + 2);
+  rc = run_walks(s, p, 2, (int64_t)slots, a, st);
+  if (rc) return rc;
   return launch_corr_sum(p->g, dim, p->dtype, n, cp->n_rays, cp->max_hits, slot_w, EX, U, out_index, u, st);
 }
 

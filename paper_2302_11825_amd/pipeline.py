@@ -984,7 +984,7 @@ def solve(prep: Prepared, batch=0, with_grad=True, n_walks_band=None, records=Fa
     # on a second stream (default priority) beside the cache walks and the
     # gather.  The longer of the two walk launches starts first and holds the
     # GPU at its own speed; the shorter fills the CUs its blocks leave.
-    side = prep.__dict__.setdefault("_band_stream", torch.cuda.Stream()) if nb and prep.clamp is None else None
+    side = prep.__dict__.setdefault("_band_stream", torch.cuda.Stream()) if nb else None
 
     def launch_band():
         watch.kernel("k_walks_band", wpb)
@@ -1040,8 +1040,9 @@ def solve(prep: Prepared, batch=0, with_grad=True, n_walks_band=None, records=Fa
         gb = dict(n=prep.n_gb, width=prep.grad_band, walks=prep.gb_walks, counters=gbc)
     if cl:
         # the second integral of Eq. 8 at the gathered points near the offset
-        # boundary, on a second stream (default priority) so that it overlaps
-        # the band walks it does not depend on; it reads the gather's output
+        # boundary, on a third stream (default priority) as soon as the gather
+        # is done, beside what remains of the band walks; it reads the
+        # gather's output
         main = torch.cuda.current_stream()
         side = cl.setdefault("stream", torch.cuda.Stream())
         side.wait_event(gathered)
