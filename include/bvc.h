@@ -550,8 +550,10 @@ int bvc_gather_grad(int32_t dim, const bvc_cache_view* cache, const bvc_source_v
  * bvc_wost_workspace_bytes(neu) bytes (2D: the Neumann run links, corner
  * flags and per-node normal cones that let the silhouette query skip BVH
  * nodes without corners facing the walk; 3D: the triangle across each edge
- * and the flat-edge bits; built on the host and uploaded by the call, which
- * synchronises once).  counters: uint64[4] as the walks. */
+ * and the flat-edge bits; built on the host at the first call for this
+ * Neumann scene, kept with it in pinned host memory, and uploaded by every
+ * call on its stream without synchronising).  Calls that overlap on several
+ * streams need a workspace each.  counters: uint64[4] as the walks. */
 size_t bvc_wost_workspace_bytes(bvc_scene neu);
 int bvc_wost_walks(bvc_scene dir, bvc_scene neu, const bvc_walk_params* params, int32_t mode, int64_t n,
                    const double* x, const double* nrm, const double* R0, const double* xbar, void* U, void* D,

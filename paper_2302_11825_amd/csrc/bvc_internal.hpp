@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -169,4 +170,14 @@ int zero_async(void* p, size_t bytes, hipStream_t st);
 
 struct bvc_scene_s {
   bvc::SceneHost h;
+  // walk-on-stars tables of this scene as a Neumann part, built at its first
+  // bvc_wost_walks into pinned host memory, so that every call uploads them
+  // without waiting: [links | cones], wost_bytes = {links, cones} in bytes
+  void* wost_tab = nullptr;
+  size_t wost_bytes[2] = {0, 0};
+  std::mutex wost_mu;
+  bvc_scene_s() = default;
+  bvc_scene_s(const bvc_scene_s&) = delete;
+  bvc_scene_s& operator=(const bvc_scene_s&) = delete;
+  ~bvc_scene_s();
 };

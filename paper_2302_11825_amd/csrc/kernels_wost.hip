@@ -21,6 +21,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "bvc_device.hpp"
@@ -791,6 +792,28 @@ void wost_tables(const SceneHost& h, std::vector<int>& prev, std::vector<int>& f
   }
 }
 
+// The walk-on-stars tables of a Neumann scene in its pinned host buffer
+// (built once; later calls find them there).
+int wost_host_tables(bvc_scene neu, int dim) {
+  std::lock_guard<std::mutex> lock(neu->wost_mu);
+  if (neu->wost_tab) return BVC_OK;
+  std::vector<int> t0, t1;
+  std::vector<float> cones;
+  if (dim == 2) wost_tables(neu->h, t0, t1, cones);
+  else wost_tables3(neu->h, t0, t1);
+  const size_t b0 = (t0.size() + t1.size()) * sizeof(int), b1 = cones.size() * sizeof(float);
+  void* tab = nullptr;
+  int rc = check_hip(hipHostMalloc(&tab, std::max<size_t>(b0 + b1, 4), hipHostMallocDefault), "pinned tables");
+  if (rc) return rc;
+  std::memcpy(tab, t0.data(), t0.size() * sizeof(int));
+  std::memcpy((int*)tab + t0.size(), t1.data(), t1.size() * sizeof(int));
+  if (b1) std::memcpy((char*)tab + b0, cones.data(), b1);
+  neu->wost_bytes[0] = b0;
+  neu->wost_bytes[1] = b1;
+  neu->wost_tab = tab;
+  return BVC_OK;
+}
+
 }  // namespace
 }  // namespace bvc
 
@@ -840,18 +863,13 @@ int bvc_wost_walks(bvc_scene dir, bvc_scene neu, const bvc_walk_params* p, int32
   const size_t np = (size_t)neu->h.np;
   int* links = (int*)workspace;
   float4* cone_dev = (float4*)((char*)workspace + ((4 * np * sizeof(int) + 255) / 256 * 256));
-  std::vector<int> t0, t1;
-  std::vector<float> cones;
-  if (dim == 2) wost_tables(neu->h, t0, t1, cones);
-  else wost_tables3(neu->h, t0, t1);
-  rc = check_hip(hipMemcpyAsync(links, t0.data(), t0.size() * sizeof(int), hipMemcpyHostToDevice, st), "tables upload");
-  if (!rc)
-    rc = check_hip(hipMemcpyAsync(links + t0.size(), t1.data(), t1.size() * sizeof(int), hipMemcpyHostToDevice, st),
+  rc = wost_host_tables(neu, dim);
+  if (rc) return rc;
+  rc = check_hip(hipMemcpyAsync(links, neu->wost_tab, neu->wost_bytes[0], hipMemcpyHostToDevice, st), "tables upload");
+  if (!rc && neu->wost_bytes[1])
+    rc = check_hip(hipMemcpyAsync(cone_dev, (const char*)neu->wost_tab + neu->wost_bytes[0], neu->wost_bytes[1],
+                                  hipMemcpyHostToDevice, st),
                    "tables upload");
-  if (!rc && dim == 2)
-    rc = check_hip(hipMemcpyAsync(cone_dev, cones.data(), cones.size() * sizeof(float), hipMemcpyHostToDevice, st),
-                   "tables upload");
-  if (!rc) rc = check_hip(hipStreamSynchronize(st), "tables upload sync");  // the host vectors end here
   if (rc) return rc;
   WostArgs a{};
   a.Sd = dir->h.view();

@@ -745,6 +745,14 @@ int bvc_scene_upload(bvc_scene s, void* buf, size_t bytes, void* stream) {
   return BVC_OK;
 }
 
+bvc_scene_s::~bvc_scene_s() {
+  if (wost_tab) {
+    // uploads from the pinned tables may still be in flight
+    (void)hipDeviceSynchronize();
+    (void)hipHostFree(wost_tab);
+  }
+}
+
 int bvc_scene_destroy(bvc_scene s) {
   delete s;
   return BVC_OK;

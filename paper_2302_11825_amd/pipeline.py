@@ -581,6 +581,8 @@ class MixedPrepared:
         self.x_band = take(self.eval64, self.idx_band, self.n_band, 2, n)
         self.ones_band = torch.ones(max(self.n_band, 1), dtype=torch.float64, device=device)
         self.ws = torch.empty(max(B.bvc_wost_workspace_bytes(self.neu.h), 256), dtype=torch.uint8, device=device)
+        # the band walks run beside the cache walks: a workspace of their own
+        self.ws_band = torch.empty_like(self.ws)
 
 
 def sample_mixed(prep: MixedPrepared, seed, batch=0):
@@ -614,14 +616,15 @@ def _part(t, lo, hi):
 
 
 def wost(prep: MixedPrepared, params: B.bvc_walk_params, mode, n, x, nrm=None, R0=None, xbar=None, dtype="f32",
-         stream=None):
+         stream=None, ws=None):
     W = params.n_walks
     T = DT[dtype]
     dev = prep.full.device
     U = torch.empty(max(n * W, 1), dtype=T, device=dev)
     D = torch.empty_like(U)
     cnt = torch.zeros(4, dtype=torch.int64, device=dev)
-    B.bvc_wost_walks(prep.dir.h, prep.neu.h, params, mode, n, x, nrm, R0, xbar, U, D, None, prep.ws, cnt, stream)
+    B.bvc_wost_walks(prep.dir.h, prep.neu.h, params, mode, n, x, nrm, R0, xbar, U, D, None,
+                     prep.ws if ws is None else ws, cnt, stream)
     return U, D, cnt
 
 
@@ -644,10 +647,36 @@ def solve_mixed(prep: MixedPrepared, batch=0, with_grad=True, watch=None) -> Sol
     n, n1 = cache.n, cache.n - n0
     wp0 = walk_params(p.eps, W, p.seed_walks, prep.g, None, dt, batch, side_read=p.side_read)
     wp1 = walk_params(p.eps, W, p.seed_walks, prep.g, None, dt, batch | NEUMANN_BATCH_BIT, side_read=p.side_read)
+    nb = prep.n_band
+    main = torch.cuda.current_stream()
+    started = torch.cuda.Event() if nb else None
     with watch.stage("cache_walks"):
+        if started is not None:
+            started.record()
         U0, D0, c0 = wost(prep, wp0, 0, n0, _part(cache.x, 0, n0), _part(cache.nrm, 0, n0), _part(cache.R0, 0, n0),
                           _part(cache.xbar, 0, n0), dt)
         U1, D1, c1 = wost(prep, wp1, 3, n1, _part(cache.x, n0, n), _part(cache.nrm, n0, n), None, None, dt)
+    Ub = None
+    side = None
+    if not nb:
+        u_band = torch.empty(1, dtype=T, device=dev)
+        pw = torch.zeros(4, dtype=torch.int64, device=dev)
+    else:
+        # the band walks need nothing from the cache: they run on a second
+        # stream (default priority) once the longer cache walks are queued,
+        # and fill the CUs those leave
+        side = prep.__dict__.setdefault("_band_stream", torch.cuda.Stream())
+        side.wait_event(started)
+        wpb = walk_params(p.eps, prep.W_band, p.seed_walks, prep.g, None, dt, batch, side_read=p.side_read)
+        with torch.cuda.stream(side):
+            with watch.stage("band_walks"):
+                Ub, Db, pw = wost(prep, wpb, 1, nb, prep.x_band, dtype=dt, ws=prep.ws_band)
+                u_band = torch.empty(nb, dtype=T, device=dev)
+                ub64 = torch.empty(nb, dtype=torch.float64, device=dev)
+                db64 = torch.empty_like(ub64)
+                bb = torch.empty(nb, dtype=T, device=dev)
+                B.bvc_reduce_walks(nb, prep.W_band, B.dtype_code(T), Ub, Db, prep.ones_band, ub64, db64, CODE[dt],
+                                   u_band, bb)
     uhat = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
     dudn = torch.empty_like(uhat)
     a = torch.empty(max(n, 1), dtype=T, device=dev)
@@ -671,19 +700,8 @@ def solve_mixed(prep: MixedPrepared, batch=0, with_grad=True, watch=None) -> Sol
             B.bvc_gather_grad(2, cview, None, n_int, prep.x_int, u_int, g_int)
         else:
             B.bvc_gather_u(2, cview, None, n_int, prep.x_int, u_int)
-    nb = prep.n_band
-    u_band = torch.empty(max(nb, 1), dtype=T, device=dev)
-    pw = torch.zeros(4, dtype=torch.int64, device=dev)
-    Ub = None
-    if nb:
-        wpb = walk_params(p.eps, prep.W_band, p.seed_walks, prep.g, None, dt, batch, side_read=p.side_read)
-        with watch.stage("band_walks"):
-            Ub, Db, pw = wost(prep, wpb, 1, nb, prep.x_band, dtype=dt)
-            ub64 = torch.empty(nb, dtype=torch.float64, device=dev)
-            db64 = torch.empty_like(ub64)
-            bb = torch.empty(nb, dtype=T, device=dev)
-            B.bvc_reduce_walks(nb, prep.W_band, B.dtype_code(T), Ub, Db, prep.ones_band, ub64, db64, CODE[dt],
-                               u_band, bb)
+    if side is not None:
+        main.wait_stream(side)
     return Solution(prep.idx_int, n_int, prep.idx_band, nb, u_int, g_int, u_band, None, cache, uhat, dudn,
                     c0 + c1, pw, extra=dict(n_offset=n0, U0=U0, D0=D0, U1=U1, Ub=Ub, a=a, b=b, cview=cview))
 
